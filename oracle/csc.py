@@ -1,0 +1,377 @@
+"""Plain FP64 CPU oracle for stochastic convolutional sparse coding.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this module.  It shares no code
+with the HIP path.
+
+Paper: Xiong, Richtarik, Heidrich, "Stochastic Convolutional Sparse Coding"
+(VMV 2019).  Conventions (readings of the paper where it is silent; each one
+is listed with its reason in the design notes):
+
+* Images x_n are H_n x W_n; codes z_{n,k} have the image's size (Sec. 2); the
+  convolution of eq. (1) is linear, "same"-sized, zero outside the image, with
+  the m x m filter anchored at its centre c = m // 2 (the spatial domain is
+  used precisely to avoid circular boundaries, Sec. 1).
+* Synthesis (the stacked operator D of Sec. 3.1):
+      (D z)[p] = sum_k sum_{s in [-c,c]^2} d_k[s] z_k[p - s],
+  with d_k[s] = d[k, s_y + c, s_x + c].
+* Its adjoint: (D^T r)_k[q] = sum_s d_k[s] r[q + s].
+* Code-side operator Z of eq. (5) (Z d == D z):  (Z^T r)_k[s] = sum_q z_k[q] r[q + s].
+* Bernoulli(p) subsampling (eq. 2): i.i.d. per coordinate, from Philox4x32-10
+  keyed by the seed, with counter (l >> 2, n, draw) and word l & 3 for the
+  pixel-major coordinate index l = (y W + x) K + k of image n; sampled iff the
+  word is < floor(p 2^32).
+* Code solver: proximal gradient (ISTA) on the subsampled LASSO of eq. (3),
+  step 1/L_z, unselected coordinates held at zero (the upsampling of eq. (4)).
+* Filter solver: projected gradient on eq. (5) (batch) or on the surrogate
+  problem eq. (8) with surrogates accumulated per eq. (7) (online).
+
+Every array is float64 unless noted.  Batches are Python lists (images may have
+different sizes).
+"""
+
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from .philox import philox4x32_10
+
+# ---------------------------------------------------------------------------
+# Convolution operators (Sec. 3.1: D z = sum_k d_k * z_k; eq. (5): Z d = D z)
+# ---------------------------------------------------------------------------
+
+
+def _taps(m: int):
+    c = m // 2
+    for sy in range(-c, c + 1):
+        for sx in range(-c, c + 1):
+            yield sy, sx
+
+
+def _check_filters(d: np.ndarray) -> int:
+    K, mh, mw = d.shape
+    if mh != mw or mh % 2 != 1:
+        raise ValueError("filters must be square with odd side")
+    return K
+
+
+def synthesize(d: np.ndarray, z: np.ndarray) -> np.ndarray:
+    """Reconstruction D z = sum_k d_k * z_k of eq. (1) for one image.
+
+    d: [K, m, m]; z: [K, H, W]  ->  [H, W].  Tap by tap, the shifted code maps
+    z_k[p - s] are weighted by d_k[s] and summed over k (a tensordot).
+    """
+    K = _check_filters(d)
+    m = d.shape[1]
+    c = m // 2
+    _, H, W = z.shape
+    zp = np.zeros((K, H + 2 * c, W + 2 * c))
+    zp[:, c : c + H, c : c + W] = z
+    y = np.zeros((H, W))
+    for sy, sx in _taps(m):
+        # z_k[p - s] for p in the image: padded rows (p_y - s_y + c)
+        shifted = zp[:, c - sy : c - sy + H, c - sx : c - sx + W]
+        y += np.tensordot(d[:, sy + c, sx + c], shifted, axes=(0, 0))
+    return y
+
+
+def adjoint(d: np.ndarray, r: np.ndarray) -> np.ndarray:
+    """D^T r: correlation of the residual with every filter.  [H, W] -> [K, H, W]."""
+    K = _check_filters(d)
+    m = d.shape[1]
+    c = m // 2
+    H, W = r.shape
+    rp = np.zeros((H + 2 * c, W + 2 * c))
+    rp[c : c + H, c : c + W] = r
+    g = np.zeros((K, H, W))
+    for sy, sx in _taps(m):
+        shifted = rp[c + sy : c + sy + H, c + sx : c + sx + W]  # r[q + s]
+        g += d[:, sy + c, sx + c][:, None, None] * shifted[None, :, :]
+    return g
+
+
+def filter_corr(z: np.ndarray, r: np.ndarray, m: int) -> np.ndarray:
+    """Z^T r for one image: G_k[s] = sum_q z_k[q] r[q + s].  [K,H,W],[H,W] -> [K,m,m]."""
+    K, H, W = z.shape
+    c = m // 2
+    rp = np.zeros((H + 2 * c, W + 2 * c))
+    rp[c : c + H, c : c + W] = r
+    G = np.zeros((K, m, m))
+    for sy, sx in _taps(m):
+        shifted = rp[c + sy : c + sy + H, c + sx : c + sx + W]
+        G[:, sy + c, sx + c] = np.tensordot(z, shifted, axes=([1, 2], [0, 1]))
+    return G
+
+
+def code_matrix(z: np.ndarray, m: int) -> np.ndarray:
+    """Explicit Z of eq. (5) for one image: [H*W, K*m*m], column (k, s) holds z_k[p - s].
+
+    Column index k*m*m + (s_y + c)*m + (s_x + c) matches a row-major flattening
+    of d, so Z @ d.ravel() == synthesize(d, z).ravel().
+    """
+    K, H, W = z.shape
+    c = m // 2
+    M = m * m
+    zp = np.zeros((K, H + 2 * c, W + 2 * c))
+    zp[:, c : c + H, c : c + W] = z
+    Z = np.zeros((H * W, K * M))
+    for sy, sx in _taps(m):
+        si = (sy + c) * m + (sx + c)
+        shifted = zp[:, c - sy : c - sy + H, c - sx : c - sx + W]
+        for k in range(K):
+            Z[:, k * M + si] = shifted[k].ravel()
+    return Z
+
+
+# ---------------------------------------------------------------------------
+# Bernoulli subsampling M^t (eq. 2)
+# ---------------------------------------------------------------------------
+
+
+def sample_threshold(p: float) -> int:
+    """floor(p * 2^32), exact in binary64; p = 1 gives 2^32 (every word passes)."""
+    if not (0.0 < p <= 1.0):
+        raise ValueError("p must lie in (0, 1]")
+    return int(math.floor(math.ldexp(p, 32)))
+
+
+def bernoulli_mask(K: int, H: int, W: int, p: float, seed: int, draw: int, image_index: int) -> np.ndarray:
+    """Selection of eq. (2) for one image as a bool array [K, H, W].
+
+    Coordinate (k, y, x) has index l = (y*W + x)*K + k; its uniform word is
+    word (l & 3) of Philox4x32-10 at counter (lo32(l>>2), hi32(l>>2),
+    image_index, draw) under key (lo32(seed), hi32(seed)).
+    """
+    thr = sample_threshold(p)
+    y, x, k = np.meshgrid(np.arange(H), np.arange(W), np.arange(K), indexing="ij")
+    l = ((y.astype(np.uint64) * np.uint64(W) + x.astype(np.uint64)) * np.uint64(K) + k.astype(np.uint64))
+    q = l >> np.uint64(2)
+    seed = int(seed) & ((1 << 64) - 1)
+    w0, w1, w2, w3 = philox4x32_10(
+        q & np.uint64(0xFFFFFFFF),
+        q >> np.uint64(32),
+        np.uint64(image_index & 0xFFFFFFFF),
+        np.uint64(draw & 0xFFFFFFFF),
+        np.uint64(seed & 0xFFFFFFFF),
+        np.uint64(seed >> 32),
+    )
+    sel = (l & np.uint64(3)).astype(np.int64)
+    words = np.choose(sel, [w0, w1, w2, w3])
+    sampled = words < np.uint64(thr) if thr < (1 << 32) else np.ones(words.shape, dtype=bool)
+    # [H, W, K] -> [K, H, W]
+    return np.ascontiguousarray(np.transpose(sampled, (2, 0, 1)))
+
+
+# ---------------------------------------------------------------------------
+# Step sizes
+# ---------------------------------------------------------------------------
+
+
+def dft_size(max_side: int, m: int) -> int:
+    """Smallest power of two >= max_side + m - 1 (no wrap-around of the full convolution)."""
+    need = max_side + m - 1
+    P = 1
+    while P < need:
+        P *= 2
+    return P
+
+
+def lipschitz_code(d: np.ndarray, max_side: int) -> float:
+    """Upper bound on ||D||^2 (Lipschitz constant of the data-term gradient in z).
+
+    "Same" convolution with zero boundary is a crop of a P x P circular
+    convolution when P >= H + m - 1, so ||D||^2 <= max over the P x P DFT grid
+    of sum_k |DFT_P(d_k)(w)|^2.
+    """
+    m = d.shape[1]
+    P = dft_size(max_side, m)
+    F = np.fft.fft2(d, s=(P, P), axes=(1, 2))
+    return float(np.max(np.sum(np.abs(F) ** 2, axis=0)))
+
+
+def soft_threshold(u: np.ndarray, t: float) -> np.ndarray:
+    """Pointwise shrinkage sign(u) * max(|u| - t, 0) (the L1 proximal map)."""
+    return np.sign(u) * np.maximum(np.abs(u) - t, 0.0)
+
+
+# ---------------------------------------------------------------------------
+# Code update: subsampled LASSO eq. (3) by ISTA, upsampled per eq. (4)
+# ---------------------------------------------------------------------------
+
+
+def code_step(
+    x: np.ndarray,
+    d: np.ndarray,
+    z_prev: np.ndarray,
+    lam: float,
+    p: float,
+    seed: int,
+    draw: int,
+    n_iter: int,
+    step: float | None = None,
+    W: np.ndarray | None = None,
+    image_index: int = 0,
+    max_side: int | None = None,
+):
+    """One code update for one image.  Returns (z_new [K,H,W], sampled mask [K,H,W]).
+
+    The selected coordinates S (eq. 2) are drawn once and kept for all n_iter
+    proximal-gradient iterations.  z starts from z_prev restricted to S; each
+    iteration forms the masked residual r = W (x - D z), the gradient D^T r,
+    and applies the soft-threshold on S; coordinates off S are zero (eq. 4).
+    """
+    K = d.shape[0]
+    H, Wd = x.shape
+    S = bernoulli_mask(K, H, Wd, p, seed, draw, image_index)
+    if step is None:
+        step = 1.0 / lipschitz_code(d, max(H, Wd) if max_side is None else max_side)
+    Wm = np.ones_like(x) if W is None else W.astype(np.float64)
+    z = np.where(S, z_prev, 0.0)
+    for _ in range(n_iter):
+        r = Wm * (x - synthesize(d, z))
+        u = z + step * adjoint(d, r)
+        z = np.where(S, soft_threshold(u, step * lam), 0.0)
+    return z, S
+
+
+# ---------------------------------------------------------------------------
+# Objective (eq. 1, summed over the images)
+# ---------------------------------------------------------------------------
+
+
+def objective(xs, d, zs, lam: float, Ws=None):
+    """(F, data term, L1 term) with F = sum_n 1/2 ||W_n (x_n - D z_n)||^2 + lam sum |z|."""
+    data = 0.0
+    l1 = 0.0
+    for i, (x, z) in enumerate(zip(xs, zs)):
+        Wm = 1.0 if Ws is None or Ws[i] is None else Ws[i].astype(np.float64)
+        e = Wm * (x - synthesize(d, z))
+        data += 0.5 * float(np.sum(e * e))
+        l1 += float(np.sum(np.abs(z)))
+    return data + lam * l1, data, l1
+
+
+# ---------------------------------------------------------------------------
+# Filter update: eq. (5) (batch) and eqs. (7)-(8) (online)
+# ---------------------------------------------------------------------------
+
+
+def project_ball(v: np.ndarray) -> np.ndarray:
+    """Euclidean projection of each filter onto ||d_k||_2 <= 1 (constraint of eq. 1)."""
+    nrm = np.sqrt(np.sum(v * v, axis=(1, 2), keepdims=True))
+    return v / np.maximum(1.0, nrm)
+
+
+def _weight(Ws, i):
+    return None if Ws is None or Ws[i] is None else Ws[i].astype(np.float64)
+
+
+def normal_matvec(zs, Ws, v: np.ndarray) -> np.ndarray:
+    """sum_n Z_n^T W_n Z_n v (v filter-shaped [K, m, m])."""
+    m = v.shape[1]
+    out = np.zeros_like(v)
+    for i, z in enumerate(zs):
+        y = synthesize(v, z)
+        Wm = _weight(Ws, i)
+        if Wm is not None:
+            y = Wm * y
+        out += filter_corr(z, y, m)
+    return out
+
+
+def lipschitz_filter(zs, Ws, K: int, m: int, n_power: int = 20) -> float:
+    """Power-iteration estimate of lambda_max(sum_n Z_n^T W_n Z_n).
+
+    Starts from the normalised all-ones vector; each iteration takes
+    w = A v, the Rayleigh quotient v^T w, and v <- w / ||w||.  Returns the
+    last Rayleigh quotient (0 when A v vanishes).
+    """
+    v = np.ones((K, m, m)) / math.sqrt(K * m * m)
+    lam = 0.0
+    for _ in range(n_power):
+        w = normal_matvec(zs, Ws, v)
+        lam = float(np.sum(v * w))
+        nw = math.sqrt(float(np.sum(w * w)))
+        if nw == 0.0:
+            return 0.0
+        v = w / nw
+    return lam
+
+
+def dict_step_batch(xs, Ws, zs, d: np.ndarray, n_iter: int = 1, step: float | None = None, n_power: int = 20):
+    """Projected-gradient update of eq. (5): d <- P(d + step * sum_n Z_n^T W_n (x_n - Z_n d)).
+
+    step defaults to 1 / L_d with L_d from ``lipschitz_filter``; when L_d is 0
+    (all codes zero) the gradient vanishes and d is only projected.
+    Returns (d_new, L_d).
+    """
+    K, m, _ = d.shape
+    Ld = lipschitz_filter(zs, Ws, K, m, n_power)
+    if step is None:
+        step = 0.0 if Ld <= 0.0 else 1.0 / Ld
+    for _ in range(n_iter):
+        G = np.zeros_like(d)
+        for i, (x, z) in enumerate(zip(xs, zs)):
+            r = x - synthesize(d, z)
+            Wm = _weight(Ws, i)
+            if Wm is not None:
+                r = Wm * r
+            G += filter_corr(z, r, m)
+        d = project_ball(d + step * G)
+    return d, Ld
+
+
+def surrogate_increment(xs, Ws, zs, K: int, m: int):
+    """(sum_n Z_n^T W_n Z_n, sum_n Z_n^T W_n x_n): the batch terms of eq. (7).
+
+    Returned dense: C_inc [K*m*m, K*m*m], B_inc [K*m*m] (row-major flattening of d).
+    """
+    KM = K * m * m
+    C = np.zeros((KM, KM))
+    B = np.zeros(KM)
+    for i, (x, z) in enumerate(zip(xs, zs)):
+        Z = code_matrix(z, m)
+        Wm = _weight(Ws, i)
+        w = np.ones(x.size) if Wm is None else Wm.ravel()
+        C += Z.T @ (w[:, None] * Z)
+        B += Z.T @ (w * x.ravel())
+    return C, B
+
+
+class OnlineState:
+    """State of the online learner: unscaled sums C_bar, B_bar, the count t and the
+    running sum of per-batch L_d estimates.  C^t = C_bar / t and B^t = B_bar / t
+    equal the recursion of eq. (7) started from zero."""
+
+    def __init__(self, K: int, m: int):
+        KM = K * m * m
+        self.C = np.zeros((KM, KM))
+        self.B = np.zeros(KM)
+        self.t = 0
+        self.Ld_sum = 0.0
+
+
+def dict_step_online(xs, Ws, zs, d: np.ndarray, state: OnlineState, n_iter: int = 1, n_power: int = 20):
+    """Online filter update (eqs. 7-8) for one mini-batch; mutates ``state``.
+
+    C_bar += sum Z^T W Z, B_bar += sum Z^T W x, t += 1, Ld_sum += L_d(batch);
+    then n_iter steps d <- P(d - (C^t d - B^t) / L^t) with L^t = Ld_sum / t, an
+    upper bound on lambda_max(C^t) by subadditivity.  Returns d_new.
+    """
+    K, m, _ = d.shape
+    Cinc, Binc = surrogate_increment(xs, Ws, zs, K, m)
+    state.C += Cinc
+    state.B += Binc
+    state.t += 1
+    state.Ld_sum += lipschitz_filter(zs, Ws, K, m, n_power)
+    if state.Ld_sum <= 0.0:
+        return project_ball(d)
+    Ct = state.C / state.t
+    Bt = state.B / state.t
+    Lt = state.Ld_sum / state.t
+    for _ in range(n_iter):
+        g = Ct @ d.ravel() - Bt
+        d = project_ball(d - (g / Lt).reshape(d.shape))
+    return d

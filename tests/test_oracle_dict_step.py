@@ -1,0 +1,123 @@
+"""Pins for the oracle's filter updates: batch eq. (5) and online eqs. (7)-(8).
+
+* one delta code (K = 1, z = e_q inside the image): Z^T Z = I, L_d = 1 and one
+  projected step from any d lands on P(patch_q(x)) -- exactly;
+* L_d from power iteration against eigvalsh of the explicit normal matrix;
+* surrogates: symmetric PSD, diag(C)_(k,s) = sum_p z_k[p - s]^2 (written from
+  the definition with loops), C d - B = -Z^T W (x - Z d), and the running
+  sums divided by t equal the eq. (7) recursion;
+* the online step at t = 1 equals the batch projected-gradient step with the
+  same step size.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+
+
+def test_single_delta_code_closed_form(rng):
+    H, W, m = 12, 13, 5
+    c = m // 2
+    x = rng.standard_normal((H, W))
+    z = np.zeros((1, H, W))
+    qy, qx = 6, 5
+    z[0, qy, qx] = 1.0
+    d0 = oracle.project_ball(rng.standard_normal((1, m, m)))
+    d1, Ld = oracle.dict_step_batch([x], None, [z], d0)
+    assert Ld == pytest.approx(1.0, rel=1e-12)
+    patch = x[qy - c : qy + c + 1, qx - c : qx + c + 1][None]
+    np.testing.assert_allclose(d1, oracle.project_ball(patch), rtol=1e-12, atol=1e-14)
+    C, B = oracle.surrogate_increment([x], None, [z], 1, m)
+    np.testing.assert_allclose(C, np.eye(m * m), atol=0)
+    np.testing.assert_allclose(B, patch.ravel(), atol=0)
+
+
+def test_lipschitz_filter_vs_eigvalsh(rng):
+    K, m = 3, 3
+    zs = [rng.standard_normal((K, 8, 9)) * (rng.random((K, 8, 9)) < 0.3), rng.standard_normal((K, 6, 7))]
+    Ws = [None, (rng.random((6, 7)) < 0.7).astype(np.uint8)]
+    A = sum(oracle.code_matrix(z, m).T @ ((1.0 if w is None else w.ravel()[:, None]) * oracle.code_matrix(z, m))
+            for z, w in zip(zs, Ws))
+    top = np.linalg.eigvalsh(A)[-1]
+    est = oracle.lipschitz_filter(zs, Ws, K, m, n_power=200)
+    assert 0.99 * top <= est <= top * (1 + 1e-12)
+
+
+def test_zero_codes_leave_filters(rng):
+    d = oracle.project_ball(rng.standard_normal((2, 3, 3)))
+    x = rng.standard_normal((6, 6))
+    d1, Ld = oracle.dict_step_batch([x], None, [np.zeros((2, 6, 6))], d)
+    assert Ld == 0.0
+    np.testing.assert_array_equal(d1, d)
+
+
+def test_surrogate_structure(rng):
+    K, m, H, W = 2, 3, 7, 6
+    c = m // 2
+    z = rng.standard_normal((K, H, W)) * (rng.random((K, H, W)) < 0.4)
+    x = rng.standard_normal((H, W))
+    Wm = (rng.random((H, W)) < 0.6).astype(np.uint8)
+    C, B = oracle.surrogate_increment([x], [Wm], [z], K, m)
+    np.testing.assert_allclose(C, C.T, atol=0)
+    assert np.linalg.eigvalsh(C)[0] >= -1e-10
+    M = m * m
+    for k in range(K):
+        for sy in range(-c, c + 1):
+            for sx in range(-c, c + 1):
+                acc = 0.0
+                for py in range(H):
+                    for px in range(W):
+                        qy, qx = py - sy, px - sx
+                        if 0 <= qy < H and 0 <= qx < W and Wm[py, px]:
+                            acc += z[k, qy, qx] ** 2
+                i = k * M + (sy + c) * m + (sx + c)
+                assert C[i, i] == pytest.approx(acc, rel=1e-12, abs=1e-14)
+    # C d - B = -Z^T W (x - Z d)
+    d = rng.standard_normal((K, m, m))
+    r = Wm * (x - oracle.synthesize(d, z))
+    np.testing.assert_allclose(C @ d.ravel() - B, -oracle.filter_corr(z, r, m).ravel(), rtol=1e-11, atol=1e-11)
+
+
+def test_online_running_mean_equals_recursion(rng):
+    K, m = 2, 3
+    st = oracle.OnlineState(K, m)
+    Crec = np.zeros((K * m * m,) * 2)
+    Brec = np.zeros(K * m * m)
+    d = oracle.project_ball(rng.standard_normal((K, m, m)))
+    for t in range(1, 5):
+        x = rng.standard_normal((6, 7))
+        z = rng.standard_normal((K, 6, 7)) * (rng.random((K, 6, 7)) < 0.3)
+        Ci, Bi = oracle.surrogate_increment([x], None, [z], K, m)
+        Crec = (t - 1) / t * Crec + Ci / t
+        Brec = (t - 1) / t * Brec + Bi / t
+        d = oracle.dict_step_online([x], None, [z], d, st)
+        assert st.t == t
+        np.testing.assert_allclose(st.C / st.t, Crec, rtol=1e-13, atol=1e-14)
+        np.testing.assert_allclose(st.B / st.t, Brec, rtol=1e-13, atol=1e-14)
+
+
+def test_online_first_step_equals_batch(rng):
+    K, m = 3, 5
+    xs = [rng.standard_normal((10, 9)), rng.standard_normal((8, 11))]
+    zs = [rng.standard_normal((K,) + x.shape) * (rng.random((K,) + x.shape) < 0.2) for x in xs]
+    d = oracle.project_ball(rng.standard_normal((K, m, m)))
+    d_batch, Ld = oracle.dict_step_batch(xs, None, zs, d)
+    st = oracle.OnlineState(K, m)
+    d_online = oracle.dict_step_online(xs, None, zs, d, st)
+    assert st.Ld_sum == pytest.approx(Ld, rel=1e-14)
+    np.testing.assert_allclose(d_online, d_batch, rtol=1e-11, atol=1e-12)
+
+
+def test_batch_dict_step_decreases_objective(rng):
+    K, m, H, W = 4, 5, 16, 16
+    x = rng.standard_normal((H, W))
+    d = oracle.project_ball(rng.standard_normal((K, m, m)))
+    z, _ = oracle.code_step(x, d, np.zeros((K, H, W)), 0.2, 1.0, 1, 1, n_iter=30)
+    f0 = oracle.objective([x], d, [z], 0.2)[0]
+    for _ in range(5):
+        d, _ = oracle.dict_step_batch([x], None, [z], d)
+        f1 = oracle.objective([x], d, [z], 0.2)[0]
+        assert f1 <= f0 + 1e-12 * f0
+        f0 = f1
+    assert np.all(np.sqrt((d ** 2).sum(axis=(1, 2))) <= 1 + 1e-14)
