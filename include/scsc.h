@@ -1,0 +1,186 @@
+/*
+ * scsc.h -- C ABI of the MI355X (gfx950) stochastic convolutional sparse coding library.
+ *
+ * Method: Xiong, Richtarik, Heidrich, "Stochastic Convolutional Sparse Coding"
+ * (VMV 2019).  The library computes the data-parallel hot path of that method:
+ * the Bernoulli-subsampled code update (Sec. 3.1, eqs. 2-4, solved here by
+ * proximal gradient), the filter update of eq. (5), the online surrogates of
+ * eqs. (7)-(8), and the objective of eq. (1).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Memory.  Every array argument is a DEVICE pointer owned by the caller unless
+ *   the comment says "host".  The library never frees caller memory.  It owns
+ *   device workspaces inside the handle and grows them on demand.
+ * Stream.  Work is enqueued on the handle's HIP stream.  Calls that return
+ *   host values (objective, statistics, L_d, the surrogate count) synchronise
+ *   that stream before returning; the others are asynchronous.
+ * Errors.  Every int-returning function returns CSC_OK (0) or a negative
+ *   csc_status.  Arguments are validated before any work is enqueued: on
+ *   CSC_EINVAL / CSC_EUNSUPPORTED no output has been written.  The message of
+ *   the last failure is available from csc_last_error().
+ * Images.  A call processes a batch of n images of sizes H_i x W_i (they may
+ *   differ).  Packed layouts:
+ *     x, r, y, W (observation mask) : image i at offset off_i = sum_{j<i} H_j W_j,
+ *                                     row-major [H_i][W_i];
+ *     z (codes), g                  : image i at offset K * off_i, as [K][H_i][W_i];
+ *     d (filters), G                : [K][m][m], row-major; m odd, anchor at the centre.
+ * Operators (Sec. 3.1 and eq. 5; zero outside each image, "same" size, c = m / 2):
+ *     (D z)[p]     = sum_k sum_{s in [-c,c]^2} d_k[s] z_k[p - s]        (synthesis)
+ *     (D^T r)_k[q] = sum_s d_k[s] r[q + s]                              (adjoint)
+ *     (Z^T r)_k[s] = sum_q z_k[q] r[q + s]                              (filter correlation)
+ *   with d_k[s] = d[k][s_y + c][s_x + c].
+ * Subsampling (eq. 2).  Coordinate (k, y, x) of image i is selected iff
+ *   word (l & 3) of Philox4x32-10(counter = (lo32(l >> 2), hi32(l >> 2),
+ *   index_base + i, draw), key = (lo32(seed), hi32(seed))) is below
+ *   floor(p * 2^32), where l = (y * W_i + x) * K + k.  (Philox: Salmon et al.,
+ *   SC'11.)  The selection depends only on (seed, draw, image index, k, y, x).
+ * Supported sizes: 1 <= K <= 1024, m in {3, 5, 7, 9, 11}, 1 <= H, W,
+ *   total pixels < 2^31, total selected coordinates < 2^32.
+ */
+#ifndef SCSC_H
+#define SCSC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CSC_VERSION 100 /* 1.00 */
+
+typedef struct csc_ctx *csc_handle;
+
+typedef enum {
+    CSC_OK = 0,
+    CSC_EINVAL = -1,       /* invalid argument (nothing written)              */
+    CSC_ENOMEM = -2,       /* device workspace allocation failed              */
+    CSC_EHIP = -3,         /* a HIP runtime call or kernel launch failed      */
+    CSC_EUNSUPPORTED = -4  /* valid but unsupported size / option             */
+} csc_status;
+
+typedef enum {
+    CSC_FP32 = 0, /* FP32 operands and accumulation                                        */
+    CSC_BF16 = 1  /* adjoint / filter-gradient contractions with BF16 operands on MFMA and
+                     FP32 accumulation; codes, filters and residual stay FP32             */
+} csc_precision;
+
+/* A batch of images (host struct). */
+typedef struct {
+    int32_t n;          /* number of images, >= 1                                  */
+    const int32_t *hw;  /* host array of 2n ints: H_0, W_0, H_1, W_1, ...           */
+    int32_t index_base; /* image i uses image index index_base + i in the sampler   */
+} csc_images;
+
+/* Statistics of one code step (host struct, filled when non-NULL). */
+typedef struct {
+    int64_t sampled; /* |S|: selected coordinates, summed over images              */
+    int64_t nnz;     /* non-zero codes after the step                               */
+    double L_z;      /* Lipschitz bound used (0 when the caller passed a step)      */
+    double step;     /* step size used                                              */
+} csc_code_stats;
+
+/* Online surrogates of eq. (7), kept as unscaled sums:
+ *   C_bar = sum_t sum_{i in batch t} Z_i^T W_i Z_i,  B_bar = sum_t sum_i Z_i^T W_i x_i,
+ * so that C^t = C_bar / t and B^t = B_bar / t equal the recursion of eq. (7).
+ * C is stored in the lag layout (csc_surrogate_index gives the position of any
+ * dense entry); B is [K][m][m].  t and Ld_sum live on the host and are updated
+ * by csc_dict_step.  Start from C = 0, B = 0, t = 0, Ld_sum = 0. */
+typedef struct {
+    double *C;     /* device, csc_surrogate_size(K, m) doubles                       */
+    double *B;     /* device, K*m*m doubles                                          */
+    int64_t t;     /* mini-batches accumulated so far                                */
+    double Ld_sum; /* sum over batches of the power-iteration estimate of L_d        */
+} csc_surrogate;
+
+/* ---- handle ---------------------------------------------------------------- */
+
+/* Create a handle bound to HIP device `device` and stream `stream` (a
+ * hipStream_t; NULL = the default stream).  *out receives the handle. */
+int csc_create(csc_handle *out, int device, void *stream);
+/* Release the handle and its workspaces (synchronises its stream). */
+int csc_destroy(csc_handle h);
+/* Rebind the handle to another stream of the same device. */
+int csc_set_stream(csc_handle h, void *stream);
+/* Message of the last failure on this handle ("" if none).  Owned by the handle. */
+const char *csc_last_error(csc_handle h);
+/* CSC_VERSION of the built library. */
+int csc_version(void);
+
+/* ---- hot path ---------------------------------------------------------------- */
+
+/* Code update for every image of the batch: eqs. (2)-(4).
+ * Draws the selection S (see "Subsampling"), starts from z restricted to S,
+ * runs n_iter proximal-gradient iterations on the subsampled LASSO of eq. (3)
+ *     r = W (x - D z);  u = z + step * D^T r;  z = sign(u) max(|u| - step*lambda, 0) on S,
+ * with every coordinate off S held at zero, and writes the upsampled codes
+ * (eq. 4) back to z (dense [K][H][W] per image; in/out).
+ *   x      : images, packed, FP32.                W : observation mask (0/1 bytes), or NULL = all ones.
+ *   d      : filters [K][m][m], FP32.             z : codes, packed, FP32, in/out.
+ *   lambda : L1 weight, >= 0.                     p : sampling rate in (0, 1].
+ *   seed, draw : sampler key and counter word (the outer iteration or mini-batch index).
+ *   n_iter : proximal-gradient iterations, >= 0.
+ *   step   : > 0 to force a step; <= 0 selects 1 / L_z with L_z from csc_lipschitz_code
+ *            (max_side = the largest image side of the batch).
+ *   precision : csc_precision.   stats : host, may be NULL (filling it synchronises). */
+int csc_code_step(csc_handle h, const csc_images *im, const float *x, const uint8_t *W,
+                  const float *d, int K, int m, float *z, double lambda, double p,
+                  uint64_t seed, uint32_t draw, int n_iter, double step, int precision,
+                  csc_code_stats *stats);
+
+/* Filter update.
+ * sur == NULL: batch problem eq. (5), n_iter projected-gradient steps
+ *     d <- P(d + step * sum_i Z_i^T W_i (x_i - Z_i d)),   P = projection onto ||d_k|| <= 1,
+ *   step <= 0 selects 1 / L_d, L_d = power-iteration estimate (n_power iterations from
+ *   the normalised all-ones vector, last Rayleigh quotient) of
+ *   lambda_max(sum_i Z_i^T W_i Z_i); when L_d = 0 the codes are all zero and d is only projected.
+ * sur != NULL: online problem, eqs. (7)-(8): C_bar += sum_i Z_i^T W_i Z_i,
+ *   B_bar += sum_i Z_i^T W_i x_i, t += 1, Ld_sum += L_d(this batch); then n_iter steps
+ *     d <- P(d - (C_bar d - B_bar) / Ld_sum)      (= P(d - (C^t d - B^t) / (Ld_sum / t))).
+ *   step is ignored in this mode.
+ *   z : codes, packed, FP32 (read only).   d : filters, in/out.
+ *   L_d_out : host, may be NULL; receives this batch's L_d (synchronises). */
+int csc_dict_step(csc_handle h, const csc_images *im, const float *x, const uint8_t *W,
+                  const float *z, float *d, int K, int m, csc_surrogate *sur, int n_iter,
+                  double step, int n_power, int precision, double *L_d_out);
+
+/* Objective of eq. (1) summed over the batch, in FP64:
+ *   F = sum_i 1/2 ||W_i (x_i - D z_i)||^2 + lambda sum_i ||z_i||_1.
+ * f_out (host) receives F; terms_out (host, may be NULL) receives {data term, L1 norm}.
+ * Synchronises. */
+int csc_objective(csc_handle h, const csc_images *im, const float *x, const uint8_t *W,
+                  const float *d, int K, int m, const float *z, double lambda,
+                  double *f_out, double *terms_out);
+
+/* ---- operators and helpers --------------------------------------------------- */
+
+/* y = D z for every image (y packed like x). */
+int csc_synthesize(csc_handle h, const csc_images *im, const float *d, int K, int m,
+                   const float *z, float *y, int precision);
+/* g = D^T r at every coordinate (g packed like z). */
+int csc_adjoint(csc_handle h, const csc_images *im, const float *d, int K, int m,
+                const float *r, float *g, int precision);
+/* G = sum_i Z_i^T r_i  ([K][m][m]). */
+int csc_filter_corr(csc_handle h, const csc_images *im, const float *z, int K, int m,
+                    const float *r, float *G, int precision);
+/* The selection of eq. (2) as bytes (1 = selected), packed like z. */
+int csc_mask(csc_handle h, const csc_images *im, int K, double p, uint64_t seed,
+             uint32_t draw, uint8_t *mask);
+/* Upper bound on ||D||^2: max over the P x P DFT grid of sum_k |DFT_P(d_k)|^2, with P the
+ * smallest power of two >= max_side + m - 1.  FP64.  L_out is host.  Synchronises. */
+int csc_lipschitz_code(csc_handle h, const float *d, int K, int m, int max_side, double *L_out);
+
+/* Number of doubles of the lag-layout surrogate C for K filters of side m (= (K m^2)^2). */
+int64_t csc_surrogate_size(int K, int m);
+/* Position in the lag layout of the dense entry C[(k, s), (k2, s2)], where s = (sy, sx)
+ * and s2 = (sy2, sx2) are tap offsets in [-c, c].  Layout: blocks (k, k2) row-major, each
+ * of m^4 doubles; inside a block, lags delta = s - s2 in [-(m-1), m-1]^2 row-major, each
+ * holding the (m-|delta_y|) x (m-|delta_x|) valid s, row-major.  Returns -1 when an
+ * argument is out of range.  Host only. */
+int64_t csc_surrogate_index(int K, int m, int k, int sy, int sx, int k2, int sy2, int sx2);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SCSC_H */

@@ -1,0 +1,537 @@
+// C ABI of the gfx950 stochastic-CSC library: handle, workspaces, argument
+// validation, batch geometry, and the entry points declared in scsc.h.
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "scsc_internal.h"
+
+using namespace scsc;
+
+namespace {
+
+enum Slot {
+    WS_IMG,
+    WS_TILES,
+    WS_MASK,
+    WS_CNT32,
+    WS_OFF,
+    WS_SCANTMP,
+    WS_SCAL,
+    WS_PAIRS0,
+    WS_PAIRS1,
+    WS_NZC0,
+    WS_NZC1,
+    WS_R,
+    WS_PART,
+    WS_V,
+    WS_W,
+    WS_G,
+    WS_Y,
+    WS_LIP,
+    WS_COUNT
+};
+
+// Device scalars (doubles / u64) inside WS_SCAL.
+enum Scalar { SC_TOTAL = 0, SC_NNZ = 1, SC_LAM = 2, SC_LZ = 3, SC_OBJ = 4 /* 2 */, SC_COUNT = 8 };
+
+struct Buffer {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace
+
+struct csc_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    Buffer ws[WS_COUNT];
+    Geometry geo;
+    std::vector<int32_t> geo_key;
+    bool geo_valid = false;
+    double *h_pinned = nullptr;  // host readback staging (SC_COUNT doubles)
+};
+
+namespace {
+
+int fail(csc_ctx *h, int code, const std::string &msg) {
+    if (h) h->err = msg;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                              \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess) return fail(h, CSC_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// Device workspace of at least `bytes` (contents undefined).  Growing frees the
+// old buffer after the stream has drained.
+void *ws(csc_ctx *h, Slot s, size_t bytes, int *status) {
+    Buffer &b = h->ws[s];
+    if (bytes == 0) bytes = 256;
+    if (b.bytes >= bytes) return b.p;
+    if (b.p) {
+        hipStreamSynchronize(h->stream);
+        hipFree(b.p);
+        b.p = nullptr;
+        b.bytes = 0;
+    }
+    size_t want = bytes + bytes / 8;
+    if (hipMalloc(&b.p, want) != hipSuccess) {
+        hipGetLastError();
+        b.p = nullptr;
+        *status = fail(h, CSC_ENOMEM, "device workspace allocation of " + std::to_string(want) + " bytes failed");
+        return nullptr;
+    }
+    b.bytes = want;
+    return b.p;
+}
+
+#define WS(ptr, type, slot, count)                                                    \
+    type *ptr = nullptr;                                                              \
+    do {                                                                              \
+        int st_ = CSC_OK;                                                             \
+        ptr = static_cast<type *>(ws(h, slot, sizeof(type) * (size_t)(count), &st_)); \
+        if (!ptr) return st_;                                                         \
+    } while (0)
+
+bool supported_m(int m) { return m == 3 || m == 5 || m == 7 || m == 9 || m == 11; }
+
+int check_filters(csc_ctx *h, int K, int m) {
+    if (K < 1 || K > MAX_K) return fail(h, CSC_EINVAL, "K must lie in [1, 1024]");
+    if (m < 1 || (m & 1) == 0) return fail(h, CSC_EINVAL, "filter side m must be odd and positive");
+    if (!supported_m(m)) return fail(h, CSC_EUNSUPPORTED, "filter side m must be one of 3, 5, 7, 9, 11");
+    return CSC_OK;
+}
+
+int check_images(csc_ctx *h, const csc_images *im) {
+    if (!im || !im->hw || im->n < 1) return fail(h, CSC_EINVAL, "images: need n >= 1 and a host hw array");
+    if (im->index_base < 0) return fail(h, CSC_EINVAL, "images: index_base must be >= 0");
+    long long pix = 0;
+    for (int i = 0; i < im->n; ++i) {
+        const long long H = im->hw[2 * i], W = im->hw[2 * i + 1];
+        if (H < 1 || W < 1) return fail(h, CSC_EINVAL, "images: every H and W must be >= 1");
+        pix += H * W;
+    }
+    if (pix >= (1LL << 31)) return fail(h, CSC_EUNSUPPORTED, "images: total pixel count must be < 2^31");
+    return CSC_OK;
+}
+
+int check_precision(csc_ctx *h, int precision) {
+    if (precision != CSC_FP32 && precision != CSC_BF16) return fail(h, CSC_EINVAL, "unknown precision");
+    return CSC_OK;
+}
+
+// Upload (or reuse) the geometry of a batch.
+int geometry(csc_ctx *h, const csc_images *im) {
+    std::vector<int32_t> key(im->hw, im->hw + 2 * im->n);
+    key.push_back(im->index_base);
+    if (h->geo_valid && key == h->geo_key) return CSC_OK;
+    Geometry &g = h->geo;
+    g.h_img.assign(im->n, ImgInfo{});
+    g.h_tiles.clear();
+    long long pix = 0;
+    int tiles = 0, max_side = 0;
+    for (int i = 0; i < im->n; ++i) {
+        ImgInfo &ii = g.h_img[i];
+        ii.H = im->hw[2 * i];
+        ii.W = im->hw[2 * i + 1];
+        ii.pix_off = pix;
+        ii.tiles_y = (ii.H + TS - 1) / TS;
+        ii.tiles_x = (ii.W + TS - 1) / TS;
+        ii.tile_off = tiles;
+        ii.index = im->index_base + i;
+        for (int ty = 0; ty < ii.tiles_y; ++ty)
+            for (int tx = 0; tx < ii.tiles_x; ++tx) g.h_tiles.push_back(TileInfo{i, ty, tx, 0});
+        tiles += ii.tiles_y * ii.tiles_x;
+        pix += (long long)ii.H * ii.W;
+        max_side = std::max(max_side, std::max(ii.H, ii.W));
+    }
+    g.n_img = im->n;
+    g.n_tiles = tiles;
+    g.n_pix = pix;
+    g.max_side = max_side;
+    h->geo_valid = false;
+    WS(dimg, ImgInfo, WS_IMG, g.n_img);
+    WS(dtiles, TileInfo, WS_TILES, g.n_tiles);
+    HIPCHK(hipMemcpyAsync(dimg, g.h_img.data(), sizeof(ImgInfo) * g.n_img, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipMemcpyAsync(dtiles, g.h_tiles.data(), sizeof(TileInfo) * g.n_tiles, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    g.d_img = dimg;
+    g.d_tiles = dtiles;
+    h->geo_key = key;
+    h->geo_valid = true;
+    return CSC_OK;
+}
+
+int read_scalars(csc_ctx *h, const void *dev, int count) {
+    HIPCHK(hipMemcpyAsync(h->h_pinned, dev, sizeof(double) * count, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return CSC_OK;
+}
+
+int dft_size(int max_side, int m) {
+    int P = 1;
+    while (P < max_side + m - 1) P *= 2;
+    return P;
+}
+
+int lipschitz(csc_ctx *h, const float *d, int K, int m, int max_side, double *out) {
+    const int P = dft_size(max_side, m);
+    WS(tmp, double, WS_LIP, lipschitz_tmp_elems(K, m, P));
+    WS(sc, double, WS_SCAL, SC_COUNT);
+    HIPCHK(launch_lipschitz_code(d, K, m, P, tmp, sc + SC_LZ, h->stream));
+    int st = read_scalars(h, sc, SC_COUNT);
+    if (st) return st;
+    *out = h->h_pinned[SC_LZ];
+    return CSC_OK;
+}
+
+// Lists of the non-zero codes of a dense z (capacity = exact count).
+int build_nonzero_lists(csc_ctx *h, int K, const float *z, Lists *out) {
+    const Geometry &g = h->geo;
+    WS(cnt32, unsigned, WS_CNT32, g.n_pix);
+    WS(off, unsigned, WS_OFF, g.n_pix + 1);
+    WS(tmp, unsigned long long, WS_SCANTMP, scan_tmp_elems(g.n_pix));
+    WS(sc, double, WS_SCAL, SC_COUNT);
+    unsigned long long *total = reinterpret_cast<unsigned long long *>(sc + SC_TOTAL);
+    HIPCHK(launch_count_nonzero(g, K, z, cnt32, h->stream));
+    HIPCHK(launch_scan(cnt32, off, g.n_pix, tmp, total, h->stream));
+    int st = read_scalars(h, sc, SC_COUNT);
+    if (st) return st;
+    unsigned long long nz;
+    std::memcpy(&nz, &h->h_pinned[SC_TOTAL], sizeof(nz));
+    if (nz >= (1ULL << 32)) return fail(h, CSC_EUNSUPPORTED, "more than 2^32 non-zero codes");
+    WS(pairs, Pair, WS_PAIRS0, nz + 1);
+    WS(nzc, unsigned short, WS_NZC0, g.n_pix);
+    HIPCHK(launch_fill_nonzero(g, K, z, off, pairs, nzc, h->stream));
+    *out = Lists{off, nzc, pairs};
+    return CSC_OK;
+}
+
+// G = sum_i Z_i^T r_i into `G` (FP32, [K][M]) from lists.
+int filter_corr_lists(csc_ctx *h, int K, int m, Lists L, const float *r, float *G) {
+    const Geometry &g = h->geo;
+    const int M = m * m;
+    const int nb = corr_blocks(g);
+    WS(part, float, WS_PART, (size_t)nb * K * M);
+    HIPCHK(launch_filter_corr_f32(g, K, m, L, r, part, nb, h->stream));
+    HIPCHK(launch_reduce_partials_f32(part, nb, K * M, G, h->stream));
+    return CSC_OK;
+}
+
+// Power iteration on sum_i Z_i^T W_i Z_i; leaves the estimate in the device scalar SC_LAM.
+int power_iteration(csc_ctx *h, int K, int m, Lists L, const unsigned char *W, int n_power) {
+    const Geometry &g = h->geo;
+    const int M = m * m;
+    WS(v, float, WS_V, K * M);
+    WS(w, float, WS_W, K * M);
+    WS(R, float, WS_R, g.n_pix);
+    WS(sc, double, WS_SCAL, SC_COUNT);
+    HIPCHK(launch_fill(v, K * M, (float)(1.0 / std::sqrt((double)K * M)), h->stream));
+    HIPCHK(hipMemsetAsync(sc + SC_LAM, 0, sizeof(double), h->stream));
+    for (int it = 0; it < n_power; ++it) {
+        HIPCHK(launch_synth(g, K, m, L, v, nullptr, W, R, SYNTH_WEIGHTED, h->stream));
+        int st = filter_corr_lists(h, K, m, L, R, w);
+        if (st) return st;
+        HIPCHK(launch_power_update(v, w, K * M, sc + SC_LAM, h->stream));
+    }
+    return CSC_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// Entry points
+// ===========================================================================
+
+extern "C" int csc_version(void) { return CSC_VERSION; }
+
+extern "C" int csc_create(csc_handle *out, int device, void *stream) {
+    if (!out) return CSC_EINVAL;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) {
+        hipGetLastError();
+        return CSC_EINVAL;
+    }
+    if (hipSetDevice(device) != hipSuccess) return CSC_EHIP;
+    csc_ctx *h = new csc_ctx();
+    h->device = device;
+    h->stream = static_cast<hipStream_t>(stream);
+    if (hipHostMalloc(reinterpret_cast<void **>(&h->h_pinned), sizeof(double) * SC_COUNT, hipHostMallocDefault) !=
+        hipSuccess) {
+        delete h;
+        return CSC_ENOMEM;
+    }
+    *out = h;
+    return CSC_OK;
+}
+
+extern "C" int csc_destroy(csc_handle h) {
+    if (!h) return CSC_EINVAL;
+    hipSetDevice(h->device);
+    hipStreamSynchronize(h->stream);
+    for (auto &b : h->ws)
+        if (b.p) hipFree(b.p);
+    if (h->h_pinned) hipHostFree(h->h_pinned);
+    delete h;
+    return CSC_OK;
+}
+
+extern "C" int csc_set_stream(csc_handle h, void *stream) {
+    if (!h) return CSC_EINVAL;
+    hipSetDevice(h->device);
+    hipStreamSynchronize(h->stream);
+    h->stream = static_cast<hipStream_t>(stream);
+    return CSC_OK;
+}
+
+extern "C" const char *csc_last_error(csc_handle h) { return h ? h->err.c_str() : "null handle"; }
+
+extern "C" int csc_lipschitz_code(csc_handle h, const float *d, int K, int m, int max_side, double *L_out) {
+    if (!h) return CSC_EINVAL;
+    int st = check_filters(h, K, m);
+    if (st) return st;
+    if (!d || !L_out) return fail(h, CSC_EINVAL, "null pointer argument");
+    if (max_side < 1 || max_side > (1 << 16)) return fail(h, CSC_EINVAL, "max_side must lie in [1, 65536]");
+    HIPCHK(hipSetDevice(h->device));
+    return lipschitz(h, d, K, m, max_side, L_out);
+}
+
+extern "C" int csc_mask(csc_handle h, const csc_images *im, int K, double p, uint64_t seed, uint32_t draw,
+                        uint8_t *mask) {
+    if (!h) return CSC_EINVAL;
+    int st = check_images(h, im);
+    if (!st) st = check_filters(h, K, 3);
+    if (st) return st;
+    if (!(p > 0.0 && p <= 1.0)) return fail(h, CSC_EINVAL, "p must lie in (0, 1]");
+    if (!mask) return fail(h, CSC_EINVAL, "null pointer argument");
+    HIPCHK(hipSetDevice(h->device));
+    if ((st = geometry(h, im))) return st;
+    const Geometry &g = h->geo;
+    const int W32 = (K + 31) / 32;
+    WS(mw, unsigned, WS_MASK, (size_t)W32 * g.n_pix);
+    WS(cnt32, unsigned, WS_CNT32, g.n_pix);
+    const unsigned long long thr = (unsigned long long)std::floor(std::ldexp(p, 32));
+    HIPCHK(launch_mask_count(g, K, thr, seed, draw, mw, cnt32, h->stream));
+    HIPCHK(launch_expand_mask(g, K, mw, mask, h->stream));
+    return CSC_OK;
+}
+
+extern "C" int csc_code_step(csc_handle h, const csc_images *im, const float *x, const uint8_t *W, const float *d,
+                             int K, int m, float *z, double lambda, double p, uint64_t seed, uint32_t draw,
+                             int n_iter, double step, int precision, csc_code_stats *stats) {
+    if (!h) return CSC_EINVAL;
+    int st = check_images(h, im);
+    if (!st) st = check_filters(h, K, m);
+    if (!st) st = check_precision(h, precision);
+    if (st) return st;
+    if (!x || !d || !z) return fail(h, CSC_EINVAL, "null pointer argument");
+    if (!(lambda >= 0.0) || !std::isfinite(lambda)) return fail(h, CSC_EINVAL, "lambda must be finite and >= 0");
+    if (!(p > 0.0 && p <= 1.0)) return fail(h, CSC_EINVAL, "p must lie in (0, 1]");
+    if (n_iter < 0) return fail(h, CSC_EINVAL, "n_iter must be >= 0");
+    if (!std::isfinite(step)) return fail(h, CSC_EINVAL, "step must be finite");
+    if (precision != CSC_FP32) return fail(h, CSC_EUNSUPPORTED, "BF16 code step not built yet");
+    HIPCHK(hipSetDevice(h->device));
+    if ((st = geometry(h, im))) return st;
+    const Geometry &g = h->geo;
+
+    double Lz = 0.0, eta = step;
+    if (step <= 0.0) {
+        if ((st = lipschitz(h, d, K, m, g.max_side, &Lz))) return st;
+        if (!(Lz > 0.0)) return fail(h, CSC_EINVAL, "all filters are zero (L_z = 0); pass an explicit step");
+        eta = 1.0 / Lz;
+    }
+    const int W32 = (K + 31) / 32;
+    WS(mw, unsigned, WS_MASK, (size_t)W32 * g.n_pix);
+    WS(cnt32, unsigned, WS_CNT32, g.n_pix);
+    WS(soff, unsigned, WS_OFF, g.n_pix + 1);
+    WS(tmp, unsigned long long, WS_SCANTMP, scan_tmp_elems(g.n_pix));
+    WS(sc, double, WS_SCAL, SC_COUNT);
+    unsigned long long *total = reinterpret_cast<unsigned long long *>(sc + SC_TOTAL);
+    const unsigned long long thr = (unsigned long long)std::floor(std::ldexp(p, 32));
+    HIPCHK(launch_mask_count(g, K, thr, seed, draw, mw, cnt32, h->stream));
+    HIPCHK(launch_scan(cnt32, soff, g.n_pix, tmp, total, h->stream));
+    if ((st = read_scalars(h, sc, SC_COUNT))) return st;
+    unsigned long long nsel;
+    std::memcpy(&nsel, &h->h_pinned[SC_TOTAL], sizeof(nsel));
+    if (nsel >= (1ULL << 32)) return fail(h, CSC_EUNSUPPORTED, "more than 2^32 selected coordinates");
+    Pair *pairs[2];
+    unsigned short *nzc[2];
+    {
+        WS(p0, Pair, WS_PAIRS0, nsel + 1);
+        WS(p1, Pair, WS_PAIRS1, nsel + 1);
+        WS(c0, unsigned short, WS_NZC0, g.n_pix);
+        WS(c1, unsigned short, WS_NZC1, g.n_pix);
+        pairs[0] = p0;
+        pairs[1] = p1;
+        nzc[0] = c0;
+        nzc[1] = c1;
+    }
+    WS(R, float, WS_R, g.n_pix);
+    HIPCHK(launch_gather_selected(g, K, mw, soff, z, pairs[0], nzc[0], h->stream));
+    const float feta = (float)eta, fthr = (float)(eta * lambda);
+    int cur = 0;
+    for (int it = 0; it < n_iter; ++it) {
+        HIPCHK(launch_synth(g, K, m, Lists{soff, nzc[cur], pairs[cur]}, d, x, W, R, SYNTH_RESIDUAL, h->stream));
+        HIPCHK(launch_adjoint_shrink(g, K, m, mw, soff, pairs[cur], nzc[cur], pairs[cur ^ 1], nzc[cur ^ 1], R, d,
+                                     feta, fthr, h->stream));
+        cur ^= 1;
+    }
+    HIPCHK(launch_scatter_dense(g, K, Lists{soff, nzc[cur], pairs[cur]}, z, h->stream));
+    if (stats) {
+        unsigned long long *nnz = reinterpret_cast<unsigned long long *>(sc + SC_NNZ);
+        HIPCHK(hipMemsetAsync(nnz, 0, sizeof(unsigned long long), h->stream));
+        HIPCHK(launch_sum_counts(nzc[cur], g.n_pix, nnz, h->stream));
+        if ((st = read_scalars(h, sc, SC_COUNT))) return st;
+        unsigned long long v;
+        std::memcpy(&v, &h->h_pinned[SC_NNZ], sizeof(v));
+        stats->sampled = (int64_t)nsel;
+        stats->nnz = (int64_t)v;
+        stats->L_z = Lz;
+        stats->step = eta;
+    }
+    return CSC_OK;
+}
+
+extern "C" int csc_dict_step(csc_handle h, const csc_images *im, const float *x, const uint8_t *W, const float *z,
+                             float *d, int K, int m, csc_surrogate *sur, int n_iter, double step, int n_power,
+                             int precision, double *L_d_out) {
+    if (!h) return CSC_EINVAL;
+    int st = check_images(h, im);
+    if (!st) st = check_filters(h, K, m);
+    if (!st) st = check_precision(h, precision);
+    if (st) return st;
+    if (!x || !d || !z) return fail(h, CSC_EINVAL, "null pointer argument");
+    if (n_iter < 0) return fail(h, CSC_EINVAL, "n_iter must be >= 0");
+    if (n_power < 1) return fail(h, CSC_EINVAL, "n_power must be >= 1");
+    if (!std::isfinite(step)) return fail(h, CSC_EINVAL, "step must be finite");
+    if (sur && (!sur->C || !sur->B || sur->t < 0 || !(sur->Ld_sum >= 0.0)))
+        return fail(h, CSC_EINVAL, "surrogate: need C, B, t >= 0 and Ld_sum >= 0");
+    if (precision != CSC_FP32) return fail(h, CSC_EUNSUPPORTED, "BF16 filter step not built yet");
+    HIPCHK(hipSetDevice(h->device));
+    if ((st = geometry(h, im))) return st;
+    const Geometry &g = h->geo;
+    const int M = m * m;
+    Lists L;
+    if ((st = build_nonzero_lists(h, K, z, &L))) return st;
+    WS(sc, double, WS_SCAL, SC_COUNT);
+    const bool need_ld = sur || step <= 0.0 || L_d_out;
+    if (need_ld) {
+        if ((st = power_iteration(h, K, m, L, W, n_power))) return st;
+    }
+    double Ld = 0.0;
+    if (sur || L_d_out) {
+        if ((st = read_scalars(h, sc, SC_COUNT))) return st;
+        Ld = h->h_pinned[SC_LAM];
+    }
+    if (!sur) {
+        if (step > 0.0) {
+            double lam = 1.0 / step;
+            HIPCHK(hipMemcpyAsync(sc + SC_LAM, &lam, sizeof(double), hipMemcpyHostToDevice, h->stream));
+            HIPCHK(hipStreamSynchronize(h->stream));
+        }
+        WS(G, float, WS_G, K * M);
+        WS(R, float, WS_R, g.n_pix);
+        for (int it = 0; it < n_iter; ++it) {
+            HIPCHK(launch_synth(g, K, m, L, d, x, W, R, SYNTH_RESIDUAL, h->stream));
+            if ((st = filter_corr_lists(h, K, m, L, R, G))) return st;
+            HIPCHK(launch_batch_update(d, G, sc + SC_LAM, K, M, h->stream));
+        }
+    } else {
+        HIPCHK(launch_surrogate_accumulate(g, K, m, L, W, sur->C, h->stream));
+        const int nb = corr_blocks(g);
+        {
+            WS(part, double, WS_PART, (size_t)nb * K * M);
+            HIPCHK(launch_filter_corr_f64(g, K, m, L, x, W, part, nb, h->stream));
+            HIPCHK(launch_reduce_partials_f64_add(part, nb, K * M, sur->B, h->stream));
+        }
+        sur->t += 1;
+        sur->Ld_sum += Ld;
+        if (sur->Ld_sum > 0.0) {
+            WS(y, double, WS_Y, K * M);
+            WS(part, double, WS_PART, surrogate_matvec_partial_elems(K, m));
+            for (int it = 0; it < n_iter; ++it) {
+                HIPCHK(launch_surrogate_matvec(K, m, sur->C, d, part, y, h->stream));
+                HIPCHK(launch_online_update(d, y, sur->B, sur->Ld_sum, K, M, h->stream));
+            }
+        } else {
+            for (int it = 0; it < n_iter; ++it) HIPCHK(launch_batch_update(d, nullptr, sc + SC_LAM, K, M, h->stream));
+        }
+    }
+    if (L_d_out) *L_d_out = Ld;
+    return CSC_OK;
+}
+
+extern "C" int csc_objective(csc_handle h, const csc_images *im, const float *x, const uint8_t *W, const float *d,
+                             int K, int m, const float *z, double lambda, double *f_out, double *terms_out) {
+    if (!h) return CSC_EINVAL;
+    int st = check_images(h, im);
+    if (!st) st = check_filters(h, K, m);
+    if (st) return st;
+    if (!x || !d || !z || !f_out) return fail(h, CSC_EINVAL, "null pointer argument");
+    if (!(lambda >= 0.0) || !std::isfinite(lambda)) return fail(h, CSC_EINVAL, "lambda must be finite and >= 0");
+    HIPCHK(hipSetDevice(h->device));
+    if ((st = geometry(h, im))) return st;
+    const Geometry &g = h->geo;
+    WS(part, double, WS_PART, 2 * (size_t)g.n_tiles);
+    WS(sc, double, WS_SCAL, SC_COUNT);
+    HIPCHK(launch_objective(g, K, m, x, W, d, z, part, sc + SC_OBJ, h->stream));
+    if ((st = read_scalars(h, sc, SC_COUNT))) return st;
+    const double data = h->h_pinned[SC_OBJ], l1 = h->h_pinned[SC_OBJ + 1];
+    *f_out = data + lambda * l1;
+    if (terms_out) {
+        terms_out[0] = data;
+        terms_out[1] = l1;
+    }
+    return CSC_OK;
+}
+
+extern "C" int csc_synthesize(csc_handle h, const csc_images *im, const float *d, int K, int m, const float *z,
+                              float *y, int precision) {
+    if (!h) return CSC_EINVAL;
+    int st = check_images(h, im);
+    if (!st) st = check_filters(h, K, m);
+    if (!st) st = check_precision(h, precision);
+    if (st) return st;
+    if (!d || !z || !y) return fail(h, CSC_EINVAL, "null pointer argument");
+    HIPCHK(hipSetDevice(h->device));
+    if ((st = geometry(h, im))) return st;
+    Lists L;
+    if ((st = build_nonzero_lists(h, K, z, &L))) return st;
+    HIPCHK(launch_synth(h->geo, K, m, L, d, nullptr, nullptr, y, SYNTH_PLAIN, h->stream));
+    return CSC_OK;
+}
+
+extern "C" int csc_adjoint(csc_handle h, const csc_images *im, const float *d, int K, int m, const float *r, float *g,
+                           int precision) {
+    if (!h) return CSC_EINVAL;
+    int st = check_images(h, im);
+    if (!st) st = check_filters(h, K, m);
+    if (!st) st = check_precision(h, precision);
+    if (st) return st;
+    if (!d || !r || !g) return fail(h, CSC_EINVAL, "null pointer argument");
+    HIPCHK(hipSetDevice(h->device));
+    if ((st = geometry(h, im))) return st;
+    HIPCHK(launch_adjoint_dense(h->geo, K, m, r, d, g, h->stream));
+    return CSC_OK;
+}
+
+extern "C" int csc_filter_corr(csc_handle h, const csc_images *im, const float *z, int K, int m, const float *r,
+                               float *G, int precision) {
+    if (!h) return CSC_EINVAL;
+    int st = check_images(h, im);
+    if (!st) st = check_filters(h, K, m);
+    if (!st) st = check_precision(h, precision);
+    if (st) return st;
+    if (!z || !r || !G) return fail(h, CSC_EINVAL, "null pointer argument");
+    HIPCHK(hipSetDevice(h->device));
+    if ((st = geometry(h, im))) return st;
+    Lists L;
+    if ((st = build_nonzero_lists(h, K, z, &L))) return st;
+    return filter_corr_lists(h, K, m, L, r, G);
+}

@@ -1,0 +1,625 @@
+// Code-update kernels for gfx950: Bernoulli selection (eq. 2), compact per-pixel
+// code lists, the synthesis / masked residual of eq. (3) and one proximal-gradient
+// step (adjoint correlation at the selected coordinates + soft-threshold).
+//
+// Data structures.  For every pixel p of the batch the selected coordinates are a
+// bit set over k (mask_words[w][p], w = k / 32).  The codes that are currently
+// non-zero are kept as a short list of (k, value) pairs sorted by k, stored at
+// [off[p], off[p] + cnt[p]) of a packed pair array; off[] is the exclusive prefix
+// of the per-pixel capacity (the number of selected k in a code step, the number
+// of non-zeros when lists are built from dense codes).  Since a converged code
+// map is very sparse, the synthesis touches only non-zero codes, and the
+// proximal step touches only selected coordinates.
+#include "scsc_internal.h"
+
+#include <climits>
+
+namespace scsc {
+
+namespace {
+
+struct PixelCtx {
+    TileInfo t;
+    ImgInfo im;
+    int ly, lx, y, x;
+    bool valid;
+    long long p_img;  // y * W + x
+    long long gp;     // packed pixel index
+};
+
+__device__ __forceinline__ PixelCtx pixel_ctx(const ImgInfo *imgs, const TileInfo *tiles) {
+    PixelCtx c;
+    c.t = tiles[blockIdx.x];
+    c.im = imgs[c.t.img];
+    c.ly = threadIdx.x / TS;
+    c.lx = threadIdx.x % TS;
+    c.y = c.t.ty * TS + c.ly;
+    c.x = c.t.tx * TS + c.lx;
+    c.valid = c.y < c.im.H && c.x < c.im.W;
+    c.p_img = (long long)c.y * c.im.W + c.x;
+    c.gp = c.im.pix_off + c.p_img;
+    return c;
+}
+
+// ---------------------------------------------------------------------------
+// Selection (eq. 2): one Philox call yields the words of 4 consecutive
+// coordinate indices l = (y W + x) K + k, so a pixel needs about K / 4 calls.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(TPB) void k_mask_count(const ImgInfo *imgs, const TileInfo *tiles, int K,
+                                                    unsigned long long thr, uint2 key, unsigned draw,
+                                                    long long n_pix, unsigned *mask_words, unsigned *cnt) {
+    PixelCtx c = pixel_ctx(imgs, tiles);
+    if (!c.valid) return;
+    const unsigned long long l0 = (unsigned long long)c.p_img * (unsigned long long)K;
+    const unsigned long long l1 = l0 + (unsigned long long)K;
+    const bool all = thr > 0xFFFFFFFFull;
+    unsigned cur = 0;
+    int total = 0;
+    for (unsigned long long g4 = l0 >> 2; (g4 << 2) < l1; ++g4) {
+        uint4 w = philox4x32_10(make_uint4((unsigned)g4, (unsigned)(g4 >> 32), (unsigned)c.im.index, draw), key);
+        unsigned ws[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            unsigned long long l = (g4 << 2) + j;
+            if (l < l0 || l >= l1) continue;
+            int k = (int)(l - l0);
+            if (all || (unsigned long long)ws[j] < thr) {
+                cur |= 1u << (k & 31);
+                ++total;
+            }
+            if ((k & 31) == 31 || k == K - 1) {
+                mask_words[(long long)(k >> 5) * n_pix + c.gp] = cur;
+                cur = 0;
+            }
+        }
+    }
+    cnt[c.gp] = (unsigned)total;
+}
+
+__global__ __launch_bounds__(TPB) void k_expand_mask(const ImgInfo *imgs, const TileInfo *tiles, int K,
+                                                     long long n_pix, const unsigned *mask_words,
+                                                     unsigned char *mask) {
+    PixelCtx c = pixel_ctx(imgs, tiles);
+    if (!c.valid) return;
+    const long long HW = (long long)c.im.H * c.im.W;
+    const long long zb = (long long)K * c.im.pix_off + c.p_img;
+    unsigned bits = 0;
+    for (int k = 0; k < K; ++k) {
+        if ((k & 31) == 0) bits = mask_words[(long long)(k >> 5) * n_pix + c.gp];
+        mask[zb + (long long)k * HW] = (bits >> (k & 31)) & 1u;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Exclusive scan of per-pixel counts (three passes, 1024 elements per block).
+// ---------------------------------------------------------------------------
+constexpr int SCAN_PER_THREAD = 4;
+constexpr int SCAN_BLOCK = TPB * SCAN_PER_THREAD;
+
+__global__ __launch_bounds__(TPB) void k_scan_local(const unsigned *cnt, unsigned *off, long long n,
+                                                    unsigned long long *bsum) {
+    __shared__ int scratch[TPB];
+    const long long base = (long long)blockIdx.x * SCAN_BLOCK + (long long)threadIdx.x * SCAN_PER_THREAD;
+    unsigned v[SCAN_PER_THREAD];
+    int s = 0;
+#pragma unroll
+    for (int j = 0; j < SCAN_PER_THREAD; ++j) {
+        v[j] = (base + j < n) ? cnt[base + j] : 0u;
+        s += (int)v[j];
+    }
+    int total;
+    int ex = block_exclusive_scan(s, scratch, &total);
+#pragma unroll
+    for (int j = 0; j < SCAN_PER_THREAD; ++j) {
+        if (base + j < n) off[base + j] = (unsigned)ex;
+        ex += (int)v[j];
+    }
+    if (threadIdx.x == 0) bsum[blockIdx.x] = (unsigned long long)total;
+}
+
+__global__ __launch_bounds__(TPB) void k_scan_blocks(unsigned long long *bsum, long long nb, unsigned *off,
+                                                     long long n, unsigned long long *total64) {
+    __shared__ unsigned long long sc[TPB];
+    unsigned long long carry = 0;
+    for (long long b0 = 0; b0 < nb; b0 += TPB) {
+        const long long i = b0 + threadIdx.x;
+        unsigned long long v = i < nb ? bsum[i] : 0ull;
+        sc[threadIdx.x] = v;
+        __syncthreads();
+        for (int o = 1; o < TPB; o <<= 1) {
+            unsigned long long a = threadIdx.x >= o ? sc[threadIdx.x - o] : 0ull;
+            __syncthreads();
+            sc[threadIdx.x] += a;
+            __syncthreads();
+        }
+        if (i < nb) bsum[i] = carry + sc[threadIdx.x] - v;
+        unsigned long long tot = sc[TPB - 1];
+        __syncthreads();
+        carry += tot;
+    }
+    if (threadIdx.x == 0) {
+        *total64 = carry;
+        off[n] = (unsigned)carry;
+    }
+}
+
+__global__ __launch_bounds__(TPB) void k_scan_add(unsigned *off, long long n, const unsigned long long *bsum) {
+    const long long i = (long long)blockIdx.x * TPB + threadIdx.x;
+    if (i < n) off[i] += (unsigned)bsum[i / SCAN_BLOCK];
+}
+
+// ---------------------------------------------------------------------------
+// Lists from dense codes.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(TPB) void k_gather_selected(const ImgInfo *imgs, const TileInfo *tiles, int K,
+                                                         long long n_pix, const unsigned *mask_words,
+                                                         const unsigned *soff, const float *z, Pair *pairs,
+                                                         unsigned short *cnt) {
+    PixelCtx c = pixel_ctx(imgs, tiles);
+    if (!c.valid) return;
+    const long long HW = (long long)c.im.H * c.im.W;
+    const float *zp = z + (long long)K * c.im.pix_off + c.p_img;
+    const unsigned base = soff[c.gp];
+    int nn = 0;
+    unsigned bits = 0;
+    for (int k = 0; k < K; ++k) {
+        if ((k & 31) == 0) bits = mask_words[(long long)(k >> 5) * n_pix + c.gp];
+        if ((bits >> (k & 31)) & 1u) {
+            float v = zp[(long long)k * HW];
+            if (v != 0.f) {
+                pairs[base + nn] = Pair{k, v};
+                ++nn;
+            }
+        }
+    }
+    cnt[c.gp] = (unsigned short)nn;
+}
+
+__global__ __launch_bounds__(TPB) void k_count_nonzero(const ImgInfo *imgs, const TileInfo *tiles, int K,
+                                                       const float *z, unsigned *cnt) {
+    PixelCtx c = pixel_ctx(imgs, tiles);
+    if (!c.valid) return;
+    const long long HW = (long long)c.im.H * c.im.W;
+    const float *zp = z + (long long)K * c.im.pix_off + c.p_img;
+    unsigned nn = 0;
+    for (int k = 0; k < K; ++k) nn += zp[(long long)k * HW] != 0.f;
+    cnt[c.gp] = nn;
+}
+
+__global__ __launch_bounds__(TPB) void k_fill_nonzero(const ImgInfo *imgs, const TileInfo *tiles, int K,
+                                                      const float *z, const unsigned *off, Pair *pairs,
+                                                      unsigned short *cnt) {
+    PixelCtx c = pixel_ctx(imgs, tiles);
+    if (!c.valid) return;
+    const long long HW = (long long)c.im.H * c.im.W;
+    const float *zp = z + (long long)K * c.im.pix_off + c.p_img;
+    const unsigned base = off[c.gp];
+    int nn = 0;
+    for (int k = 0; k < K; ++k) {
+        float v = zp[(long long)k * HW];
+        if (v != 0.f) {
+            pairs[base + nn] = Pair{k, v};
+            ++nn;
+        }
+    }
+    cnt[c.gp] = (unsigned short)nn;
+}
+
+__global__ __launch_bounds__(TPB) void k_scatter_dense(const ImgInfo *imgs, const TileInfo *tiles, int K,
+                                                       Lists zl, float *z) {
+    PixelCtx c = pixel_ctx(imgs, tiles);
+    if (!c.valid) return;
+    const long long HW = (long long)c.im.H * c.im.W;
+    float *zp = z + (long long)K * c.im.pix_off + c.p_img;
+    const unsigned base = zl.off[c.gp];
+    const int n = zl.cnt[c.gp];
+    int i = 0;
+    Pair e = n > 0 ? zl.pairs[base] : Pair{INT_MAX, 0.f};
+    for (int k = 0; k < K; ++k) {
+        float v = 0.f;
+        if (e.k == k) {
+            v = e.v;
+            ++i;
+            e = i < n ? zl.pairs[base + i] : Pair{INT_MAX, 0.f};
+        }
+        zp[(long long)k * HW] = v;
+    }
+}
+
+__global__ void k_sum_counts(const unsigned short *cnt, long long n, unsigned long long *out) {
+    __shared__ unsigned long long red[TPB];
+    unsigned long long s = 0;
+    for (long long i = (long long)blockIdx.x * TPB + threadIdx.x; i < n; i += (long long)gridDim.x * TPB)
+        s += cnt[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = TPB / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicAdd(out, red[0]);
+}
+
+// ---------------------------------------------------------------------------
+// Synthesis from code lists (deterministic gather).
+// The tile's output pixels depend on the codes of the tile grown by c pixels.
+// Their list headers are staged in LDS, a block scan gives LDS offsets and,
+// when the region holds at most SYN_CAP pairs, the pairs themselves are staged.
+// Each output pixel then walks its m x m taps in a fixed order.
+// ---------------------------------------------------------------------------
+constexpr int SYN_CAP = 4096;
+
+template <int MM>
+__global__ __launch_bounds__(TPB) void k_synth(const ImgInfo *imgs, const TileInfo *tiles, int K, Lists zl,
+                                               const float *__restrict__ d, const float *__restrict__ x,
+                                               const unsigned char *__restrict__ W, float *__restrict__ out,
+                                               int mode) {
+    constexpr int C = MM / 2, RW = TS + 2 * C, R = RW * RW, M = MM * MM;
+    constexpr int CH = (R + TPB - 1) / TPB;
+    __shared__ unsigned lgoff[R];
+    __shared__ int lstart[R];
+    __shared__ int lcnt[R];
+    __shared__ Pair lp[SYN_CAP];
+    __shared__ int scratch[TPB];
+
+    PixelCtx c = pixel_ctx(imgs, tiles);
+    const int oy = c.t.ty * TS - C, ox = c.t.tx * TS - C;
+    int mysum = 0;
+#pragma unroll
+    for (int j = 0; j < CH; ++j) {
+        const int i = threadIdx.x * CH + j;
+        if (i < R) {
+            const int gy = oy + i / RW, gx = ox + i % RW;
+            int n = 0;
+            unsigned o = 0;
+            if (gy >= 0 && gy < c.im.H && gx >= 0 && gx < c.im.W) {
+                const long long gp = c.im.pix_off + (long long)gy * c.im.W + gx;
+                n = zl.cnt[gp];
+                o = zl.off[gp];
+            }
+            lcnt[i] = n;
+            lgoff[i] = o;
+            mysum += n;
+        }
+    }
+    int total;
+    int ex = block_exclusive_scan(mysum, scratch, &total);
+    const bool staged = total <= SYN_CAP;
+#pragma unroll
+    for (int j = 0; j < CH; ++j) {
+        const int i = threadIdx.x * CH + j;
+        if (i < R) {
+            lstart[i] = ex;
+            if (staged)
+                for (int q = 0; q < lcnt[i]; ++q) lp[ex + q] = zl.pairs[lgoff[i] + q];
+            ex += lcnt[i];
+        }
+    }
+    __syncthreads();
+    if (!c.valid) return;
+    float acc = 0.f;
+    if (staged) {
+        for (int sy = -C; sy <= C; ++sy) {
+            for (int sx = -C; sx <= C; ++sx) {
+                const int i = (c.ly + C - sy) * RW + (c.lx + C - sx);
+                const int n = lcnt[i];
+                const Pair *src = lp + lstart[i];
+                const float *dt = d + (sy + C) * MM + (sx + C);
+                for (int q = 0; q < n; ++q) {
+                    const Pair e = src[q];
+                    acc = fmaf(dt[e.k * M], e.v, acc);
+                }
+            }
+        }
+    } else {
+        for (int sy = -C; sy <= C; ++sy) {
+            for (int sx = -C; sx <= C; ++sx) {
+                const int i = (c.ly + C - sy) * RW + (c.lx + C - sx);
+                const int n = lcnt[i];
+                const Pair *src = zl.pairs + lgoff[i];
+                const float *dt = d + (sy + C) * MM + (sx + C);
+                for (int q = 0; q < n; ++q) {
+                    const Pair e = src[q];
+                    acc = fmaf(dt[e.k * M], e.v, acc);
+                }
+            }
+        }
+    }
+    float o;
+    if (mode == SYNTH_RESIDUAL) {
+        o = x[c.gp] - acc;
+        if (W && !W[c.gp]) o = 0.f;
+    } else if (mode == SYNTH_WEIGHTED) {
+        o = (W && !W[c.gp]) ? 0.f : acc;
+    } else {
+        o = acc;
+    }
+    out[c.gp] = o;
+}
+
+// ---------------------------------------------------------------------------
+// One proximal-gradient iteration at the selected coordinates (FP32 VALU).
+// Thread <-> pixel q: the m x m residual window around q is held in registers
+// and reused for every selected k of q; filters are staged in LDS in chunks of
+// at most KC filters, rows padded to a multiple of 4 taps for 16-byte reads.
+// The old list of q (read buffer) is merged by k; the new non-zeros are
+// appended, in k order, to the write buffer.
+// ---------------------------------------------------------------------------
+template <int MM>
+__global__ __launch_bounds__(TPB) void k_adjoint_shrink(const ImgInfo *imgs, const TileInfo *tiles, int K,
+                                                        long long n_pix, const unsigned *__restrict__ mask_words,
+                                                        const unsigned *__restrict__ soff,
+                                                        const Pair *__restrict__ oldp,
+                                                        const unsigned short *__restrict__ oldc,
+                                                        Pair *__restrict__ newp, unsigned short *__restrict__ newc,
+                                                        const float *__restrict__ r, const float *__restrict__ d,
+                                                        float eta, float thr, int KC) {
+    constexpr int C = MM / 2, RW = TS + 2 * C, M = MM * MM, M4 = (M + 3) / 4 * 4;
+    __shared__ float rr[RW * RW];
+    extern __shared__ float4 dl4[];
+    float *dl = reinterpret_cast<float *>(dl4);
+
+    PixelCtx c = pixel_ctx(imgs, tiles);
+    const int oy = c.t.ty * TS - C, ox = c.t.tx * TS - C;
+    for (int i = threadIdx.x; i < RW * RW; i += TPB) {
+        const int gy = oy + i / RW, gx = ox + i % RW;
+        float v = 0.f;
+        if (gy >= 0 && gy < c.im.H && gx >= 0 && gx < c.im.W) v = r[c.im.pix_off + (long long)gy * c.im.W + gx];
+        rr[i] = v;
+    }
+    __syncthreads();
+    float win[M4];
+#pragma unroll
+    for (int j = 0; j < M4; ++j) {
+        if (j < M) {
+            const int sy = j / MM - C, sx = j % MM - C;
+            win[j] = rr[(c.ly + C + sy) * RW + (c.lx + C + sx)];
+        } else {
+            win[j] = 0.f;
+        }
+    }
+    const unsigned base = c.valid ? soff[c.gp] : 0u;
+    const int ocnt = c.valid ? (int)oldc[c.gp] : 0;
+    int oi = 0;
+    Pair oe = ocnt > 0 ? oldp[base] : Pair{INT_MAX, 0.f};
+    int nn = 0;
+    for (int k0 = 0; k0 < K; k0 += KC) {
+        const int k1 = min(K, k0 + KC);
+        __syncthreads();
+        for (int i = threadIdx.x; i < (k1 - k0) * M4; i += TPB) {
+            const int kk = i / M4, j = i % M4;
+            dl[i] = j < M ? d[(long long)(k0 + kk) * M + j] : 0.f;
+        }
+        __syncthreads();
+        if (!c.valid) continue;
+        for (int w = k0 >> 5; w <= (k1 - 1) >> 5; ++w) {
+            unsigned bits = mask_words[(long long)w * n_pix + c.gp];
+            const int lo = k0 - 32 * w, hi = k1 - 32 * w;
+            if (lo > 0) bits &= ~0u << lo;
+            if (hi < 32) bits &= (1u << hi) - 1u;
+            while (bits) {
+                const int b = __builtin_ctz(bits);
+                bits &= bits - 1u;
+                const int k = 32 * w + b;
+                const float4 *dr = dl4 + (k - k0) * (M4 / 4);
+                float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+#pragma unroll
+                for (int j = 0; j < M4 / 4; ++j) {
+                    const float4 q = dr[j];
+                    a0 = fmaf(q.x, win[4 * j + 0], a0);
+                    a1 = fmaf(q.y, win[4 * j + 1], a1);
+                    a2 = fmaf(q.z, win[4 * j + 2], a2);
+                    a3 = fmaf(q.w, win[4 * j + 3], a3);
+                }
+                const float g = (a0 + a1) + (a2 + a3);
+                while (oe.k < k) {
+                    ++oi;
+                    oe = oi < ocnt ? oldp[base + oi] : Pair{INT_MAX, 0.f};
+                }
+                float zold = 0.f;
+                if (oe.k == k) {
+                    zold = oe.v;
+                    ++oi;
+                    oe = oi < ocnt ? oldp[base + oi] : Pair{INT_MAX, 0.f};
+                }
+                const float v = soft_threshold(fmaf(eta, g, zold), thr);
+                if (v != 0.f) {
+                    newp[base + nn] = Pair{k, v};
+                    ++nn;
+                }
+            }
+        }
+    }
+    if (c.valid) newc[c.gp] = (unsigned short)nn;
+}
+
+// Dense adjoint D^T r at every coordinate.  Thread <-> pixel with its residual
+// window in registers; all lanes walk the same k, so filter reads from LDS are
+// broadcasts and the stores of one k are coalesced.
+template <int MM>
+__global__ __launch_bounds__(TPB) void k_adjoint_dense(const ImgInfo *imgs, const TileInfo *tiles, int K,
+                                                       const float *__restrict__ r, const float *__restrict__ d,
+                                                       float *__restrict__ out, int KC) {
+    constexpr int C = MM / 2, RW = TS + 2 * C, M = MM * MM, M4 = (M + 3) / 4 * 4;
+    __shared__ float rr[RW * RW];
+    extern __shared__ float4 dl4[];
+    float *dl = reinterpret_cast<float *>(dl4);
+    PixelCtx c = pixel_ctx(imgs, tiles);
+    const int oy = c.t.ty * TS - C, ox = c.t.tx * TS - C;
+    for (int i = threadIdx.x; i < RW * RW; i += TPB) {
+        const int gy = oy + i / RW, gx = ox + i % RW;
+        float v = 0.f;
+        if (gy >= 0 && gy < c.im.H && gx >= 0 && gx < c.im.W) v = r[c.im.pix_off + (long long)gy * c.im.W + gx];
+        rr[i] = v;
+    }
+    __syncthreads();
+    float win[M4];
+#pragma unroll
+    for (int j = 0; j < M4; ++j) {
+        if (j < M) {
+            const int sy = j / MM - C, sx = j % MM - C;
+            win[j] = rr[(c.ly + C + sy) * RW + (c.lx + C + sx)];
+        } else {
+            win[j] = 0.f;
+        }
+    }
+    const long long HW = (long long)c.im.H * c.im.W;
+    float *op = out + (long long)K * c.im.pix_off + c.p_img;
+    for (int k0 = 0; k0 < K; k0 += KC) {
+        const int k1 = min(K, k0 + KC);
+        __syncthreads();
+        for (int i = threadIdx.x; i < (k1 - k0) * M4; i += TPB) {
+            const int kk = i / M4, j = i % M4;
+            dl[i] = j < M ? d[(long long)(k0 + kk) * M + j] : 0.f;
+        }
+        __syncthreads();
+        if (!c.valid) continue;
+        for (int k = k0; k < k1; ++k) {
+            const float4 *dr = dl4 + (k - k0) * (M4 / 4);
+            float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+#pragma unroll
+            for (int j = 0; j < M4 / 4; ++j) {
+                const float4 q = dr[j];
+                a0 = fmaf(q.x, win[4 * j + 0], a0);
+                a1 = fmaf(q.y, win[4 * j + 1], a1);
+                a2 = fmaf(q.z, win[4 * j + 2], a2);
+                a3 = fmaf(q.w, win[4 * j + 3], a3);
+            }
+            op[(long long)k * HW] = (a0 + a1) + (a2 + a3);
+        }
+    }
+}
+
+// Filters per LDS chunk: at most 56 KiB of staged filters, a multiple of 4.
+template <int MM>
+int filter_chunk() {
+    constexpr int M = MM * MM, M4 = (M + 3) / 4 * 4;
+    int kc = (56 * 1024) / (M4 * 4);
+    kc = kc / 4 * 4;
+    return kc > MAX_K ? MAX_K : kc;
+}
+
+}  // namespace
+
+#define SCSC_DISPATCH_M(m, FN, ...)         \
+    switch (m) {                            \
+        case 3: return FN<3>(__VA_ARGS__);  \
+        case 5: return FN<5>(__VA_ARGS__);  \
+        case 7: return FN<7>(__VA_ARGS__);  \
+        case 9: return FN<9>(__VA_ARGS__);  \
+        case 11: return FN<11>(__VA_ARGS__); \
+        default: return hipErrorInvalidValue; \
+    }
+
+hipError_t launch_mask_count(const Geometry &g, int K, unsigned long long thr, unsigned long long seed,
+                             unsigned draw, unsigned *mask_words, unsigned *cnt, hipStream_t s) {
+    uint2 key = make_uint2((unsigned)seed, (unsigned)(seed >> 32));
+    hipLaunchKernelGGL(k_mask_count, dim3(g.n_tiles), dim3(TPB), 0, s, g.d_img, g.d_tiles, K, thr, key, draw,
+                       g.n_pix, mask_words, cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_expand_mask(const Geometry &g, int K, const unsigned *mask_words, unsigned char *mask,
+                              hipStream_t s) {
+    hipLaunchKernelGGL(k_expand_mask, dim3(g.n_tiles), dim3(TPB), 0, s, g.d_img, g.d_tiles, K, g.n_pix,
+                       mask_words, mask);
+    return hipGetLastError();
+}
+
+long long scan_tmp_elems(long long n) { return (n + SCAN_BLOCK - 1) / SCAN_BLOCK + 1; }
+
+hipError_t launch_scan(const unsigned *cnt, unsigned *off, long long n, unsigned long long *tmp,
+                       unsigned long long *total64, hipStream_t s) {
+    const long long nb = (n + SCAN_BLOCK - 1) / SCAN_BLOCK;
+    if (nb > 0) hipLaunchKernelGGL(k_scan_local, dim3((unsigned)nb), dim3(TPB), 0, s, cnt, off, n, tmp);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(TPB), 0, s, tmp, nb, off, n, total64);
+    if (n > 0) hipLaunchKernelGGL(k_scan_add, dim3((unsigned)((n + TPB - 1) / TPB)), dim3(TPB), 0, s, off, n, tmp);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_selected(const Geometry &g, int K, const unsigned *mask_words, const unsigned *soff,
+                                  const float *z, Pair *pairs, unsigned short *cnt, hipStream_t s) {
+    hipLaunchKernelGGL(k_gather_selected, dim3(g.n_tiles), dim3(TPB), 0, s, g.d_img, g.d_tiles, K, g.n_pix,
+                       mask_words, soff, z, pairs, cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_nonzero(const Geometry &g, int K, const float *z, unsigned *cnt, hipStream_t s) {
+    hipLaunchKernelGGL(k_count_nonzero, dim3(g.n_tiles), dim3(TPB), 0, s, g.d_img, g.d_tiles, K, z, cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_nonzero(const Geometry &g, int K, const float *z, const unsigned *off, Pair *pairs,
+                               unsigned short *cnt, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_nonzero, dim3(g.n_tiles), dim3(TPB), 0, s, g.d_img, g.d_tiles, K, z, off, pairs,
+                       cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_dense(const Geometry &g, int K, Lists z, float *zout, hipStream_t s) {
+    hipLaunchKernelGGL(k_scatter_dense, dim3(g.n_tiles), dim3(TPB), 0, s, g.d_img, g.d_tiles, K, z, zout);
+    return hipGetLastError();
+}
+
+hipError_t launch_sum_counts(const unsigned short *cnt, long long n, unsigned long long *out, hipStream_t s) {
+    long long nb = (n + TPB - 1) / TPB;
+    if (nb > 1024) nb = 1024;
+    if (nb < 1) nb = 1;
+    hipLaunchKernelGGL(k_sum_counts, dim3((unsigned)nb), dim3(TPB), 0, s, cnt, n, out);
+    return hipGetLastError();
+}
+
+namespace {
+template <int MM>
+hipError_t synth_impl(const Geometry &g, int K, Lists z, const float *d, const float *x, const unsigned char *W,
+                      float *out, SynthMode mode, hipStream_t s) {
+    hipLaunchKernelGGL(k_synth<MM>, dim3(g.n_tiles), dim3(TPB), 0, s, g.d_img, g.d_tiles, K, z, d, x, W, out,
+                       (int)mode);
+    return hipGetLastError();
+}
+
+template <int MM>
+hipError_t adjoint_shrink_impl(const Geometry &g, int K, const unsigned *mw, const unsigned *soff,
+                               const Pair *oldp, const unsigned short *oldc, Pair *newp, unsigned short *newc,
+                               const float *r, const float *d, float eta, float thr, hipStream_t s) {
+    constexpr int M = MM * MM, M4 = (M + 3) / 4 * 4;
+    const int KC = filter_chunk<MM>();
+    const int kc = K < KC ? K : KC;
+    const size_t shm = (size_t)kc * M4 * sizeof(float);
+    hipLaunchKernelGGL(k_adjoint_shrink<MM>, dim3(g.n_tiles), dim3(TPB), shm, s, g.d_img, g.d_tiles, K, g.n_pix,
+                       mw, soff, oldp, oldc, newp, newc, r, d, eta, thr, KC);
+    return hipGetLastError();
+}
+
+template <int MM>
+hipError_t adjoint_dense_impl(const Geometry &g, int K, const float *r, const float *d, float *out,
+                              hipStream_t s) {
+    constexpr int M = MM * MM, M4 = (M + 3) / 4 * 4;
+    const int KC = filter_chunk<MM>();
+    const int kc = K < KC ? K : KC;
+    const size_t shm = (size_t)kc * M4 * sizeof(float);
+    hipLaunchKernelGGL(k_adjoint_dense<MM>, dim3(g.n_tiles), dim3(TPB), shm, s, g.d_img, g.d_tiles, K, r, d, out,
+                       KC);
+    return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_synth(const Geometry &g, int K, int m, Lists z, const float *d, const float *x,
+                        const unsigned char *W, float *out, SynthMode mode, hipStream_t s) {
+    SCSC_DISPATCH_M(m, synth_impl, g, K, z, d, x, W, out, mode, s);
+}
+
+hipError_t launch_adjoint_shrink(const Geometry &g, int K, int m, const unsigned *mask_words,
+                                 const unsigned *soff, const Pair *old_pairs, const unsigned short *old_cnt,
+                                 Pair *new_pairs, unsigned short *new_cnt, const float *r, const float *d,
+                                 float eta, float thr, hipStream_t s) {
+    SCSC_DISPATCH_M(m, adjoint_shrink_impl, g, K, mask_words, soff, old_pairs, old_cnt, new_pairs, new_cnt, r, d,
+                    eta, thr, s);
+}
+
+hipError_t launch_adjoint_dense(const Geometry &g, int K, int m, const float *r, const float *d, float *out,
+                                hipStream_t s) {
+    SCSC_DISPATCH_M(m, adjoint_dense_impl, g, K, r, d, out, s);
+}
+
+}  // namespace scsc

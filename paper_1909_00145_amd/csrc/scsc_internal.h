@@ -1,0 +1,178 @@
+// Internal declarations of the gfx950 stochastic-CSC library: batch geometry,
+// the compact per-pixel code lists, device helpers and kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "scsc.h"
+
+namespace scsc {
+
+// Every per-pixel kernel works on square output tiles of TS x TS pixels, one
+// workgroup of TS*TS threads (4 wave64s) per tile, thread (ty, tx) <-> pixel.
+constexpr int TS = 16;
+constexpr int TPB = TS * TS;
+constexpr int MAX_K = 1024;
+constexpr int MAX_C = 5;                  // largest half-width (m = 11)
+constexpr int MAX_RW = TS + 2 * MAX_C;    // side of a tile plus one filter halo
+constexpr int MAX_RW2 = TS + 4 * MAX_C;   // side of a tile plus two filter halos
+
+struct ImgInfo {
+    int H, W;
+    long long pix_off;  // first pixel of the image in the packed pixel arrays
+    int tiles_x, tiles_y;
+    int tile_off;
+    int index;          // image index used by the sampler
+};
+
+struct TileInfo {
+    int img, ty, tx, pad;
+};
+
+// One non-zero (or selected) code of a pixel: filter index and value.  The
+// per-pixel lists are sorted by k and live at [off[p], off[p] + cnt[p]).
+struct __align__(8) Pair {
+    int k;
+    float v;
+};
+
+// Device view of a batch: per-image info and the flattened tile list.
+struct Geometry {
+    int n_img = 0;
+    int n_tiles = 0;
+    long long n_pix = 0;
+    int max_side = 0;
+    ImgInfo *d_img = nullptr;
+    TileInfo *d_tiles = nullptr;
+    std::vector<ImgInfo> h_img;
+    std::vector<TileInfo> h_tiles;
+};
+
+// Compact list structure over all pixels of a batch.
+struct Lists {
+    const unsigned *off;       // [n_pix + 1] exclusive prefix of list capacities
+    const unsigned short *cnt; // [n_pix] current list lengths
+    const Pair *pairs;         // [off[n_pix]]
+};
+
+// ---- device helpers ------------------------------------------------------
+
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint2 k) {
+    // Philox-4x32 bijection, 10 rounds (Salmon et al., SC'11).
+    const unsigned M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    const unsigned W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k.x += W0;
+            k.y += W1;
+        }
+        unsigned hi0 = __umulhi(M0, c.x), lo0 = M0 * c.x;
+        unsigned hi1 = __umulhi(M1, c.z), lo1 = M1 * c.z;
+        c = make_uint4(hi1 ^ c.y ^ k.x, lo1, hi0 ^ c.w ^ k.y, lo0);
+    }
+    return c;
+}
+
+__device__ __forceinline__ float soft_threshold(float u, float t) {
+    float a = fabsf(u) - t;
+    return a > 0.f ? copysignf(a, u) : 0.f;
+}
+
+// Exclusive prefix sum over the TPB threads of a block.  `scratch` must hold
+// TPB ints of shared memory.  Returns the thread's exclusive prefix; *total
+// receives the block sum.  Contains __syncthreads.
+__device__ __forceinline__ int block_exclusive_scan(int v, int *scratch, int *total) {
+    const int t = threadIdx.x;
+    scratch[t] = v;
+    __syncthreads();
+    for (int o = 1; o < TPB; o <<= 1) {
+        int a = (t >= o) ? scratch[t - o] : 0;
+        __syncthreads();
+        scratch[t] += a;
+        __syncthreads();
+    }
+    int incl = scratch[t];
+    *total = scratch[TPB - 1];
+    __syncthreads();
+    return incl - v;
+}
+
+// ---- launchers (host) ----------------------------------------------------
+// All launchers return hipSuccess or the launch error.
+
+// mask_words[w][p] bit b <=> coordinate k = 32 w + b of pixel p is selected;
+// cnt[p] = number of selected coordinates of pixel p.
+hipError_t launch_mask_count(const Geometry &g, int K, unsigned long long thr, unsigned long long seed,
+                             unsigned draw, unsigned *mask_words, unsigned *cnt, hipStream_t s);
+// Exclusive prefix of cnt[0..n) into off[0..n]; off[n] = low 32 bits of the total,
+// total64 (device) = the exact total.  tmp needs scan_tmp_elems(n) u64.
+long long scan_tmp_elems(long long n);
+hipError_t launch_scan(const unsigned *cnt, unsigned *off, long long n, unsigned long long *tmp,
+                       unsigned long long *total64, hipStream_t s);
+// Warm start: list of non-zero selected codes of z_prev (eq. 4 restricted to S).
+hipError_t launch_gather_selected(const Geometry &g, int K, const unsigned *mask_words, const unsigned *soff,
+                                  const float *z, Pair *pairs, unsigned short *cnt, hipStream_t s);
+// Mode of the synthesis kernel.
+enum SynthMode { SYNTH_RESIDUAL = 0, SYNTH_PLAIN = 1, SYNTH_WEIGHTED = 2 };
+// out = W (x - D z) (RESIDUAL), D z (PLAIN) or W (D z) (WEIGHTED); z given as lists.
+hipError_t launch_synth(const Geometry &g, int K, int m, Lists z, const float *d, const float *x,
+                        const unsigned char *W, float *out, SynthMode mode, hipStream_t s);
+// One proximal-gradient iteration on the selected coordinates (FP32 VALU).
+hipError_t launch_adjoint_shrink(const Geometry &g, int K, int m, const unsigned *mask_words,
+                                 const unsigned *soff, const Pair *old_pairs, const unsigned short *old_cnt,
+                                 Pair *new_pairs, unsigned short *new_cnt, const float *r, const float *d,
+                                 float eta, float thr, hipStream_t s);
+// Dense codes from lists (zeros elsewhere).
+hipError_t launch_scatter_dense(const Geometry &g, int K, Lists z, float *zout, hipStream_t s);
+// Lists of the non-zero codes of a dense z: count, then fill.
+hipError_t launch_count_nonzero(const Geometry &g, int K, const float *z, unsigned *cnt, hipStream_t s);
+hipError_t launch_fill_nonzero(const Geometry &g, int K, const float *z, const unsigned *off, Pair *pairs,
+                               unsigned short *cnt, hipStream_t s);
+// Selection bytes (csc_mask).
+hipError_t launch_expand_mask(const Geometry &g, int K, const unsigned *mask_words, unsigned char *mask,
+                              hipStream_t s);
+// Sum of cnt over all pixels into *out (device u64).
+hipError_t launch_sum_counts(const unsigned short *cnt, long long n, unsigned long long *out, hipStream_t s);
+
+// Filter correlation: partial[b][k][t] over block b's tiles, then a fixed-order reduction.
+int corr_blocks(const Geometry &g);
+hipError_t launch_filter_corr_f32(const Geometry &g, int K, int m, Lists z, const float *r, float *partial,
+                                  int nblocks, hipStream_t s);
+hipError_t launch_filter_corr_f64(const Geometry &g, int K, int m, Lists z, const float *x,
+                                  const unsigned char *W, double *partial, int nblocks, hipStream_t s);
+hipError_t launch_reduce_partials_f32(const float *partial, int nblocks, int n, float *out, hipStream_t s);
+hipError_t launch_reduce_partials_f64_add(const double *partial, int nblocks, int n, double *inout,
+                                          hipStream_t s);
+// Dense adjoint D^T r (every coordinate).
+hipError_t launch_adjoint_dense(const Geometry &g, int K, int m, const float *r, const float *d, float *out,
+                                hipStream_t s);
+
+// Filter updates.
+hipError_t launch_fill(float *v, int n, float val, hipStream_t s);
+// Power-iteration step: lam = <v, w>, v = w / ||w|| (kept when w = 0, lam = 0).
+hipError_t launch_power_update(float *v, const float *w, int n, double *lam, hipStream_t s);
+// d_k <- P(d_k + G_k / lam) (lam <= 0: P(d_k)).
+hipError_t launch_batch_update(float *d, const float *G, const double *lam, int K, int M, hipStream_t s);
+// d_k <- P(d_k - (y_k - B_k) / Ld_sum).
+hipError_t launch_online_update(float *d, const double *y, const double *B, double Ld_sum, int K, int M,
+                                hipStream_t s);
+// Surrogates (lag layout): C += sum Z^T W Z, and y = C d.
+hipError_t launch_surrogate_accumulate(const Geometry &g, int K, int m, Lists z, const unsigned char *W,
+                                       double *C, hipStream_t s);
+hipError_t launch_surrogate_matvec(int K, int m, const double *C, const float *d, double *partial, double *y,
+                                   hipStream_t s);
+long long surrogate_matvec_partial_elems(int K, int m);
+
+// FP64 objective: out[0] = data term, out[1] = L1 norm.
+hipError_t launch_objective(const Geometry &g, int K, int m, const float *x, const unsigned char *W,
+                            const float *d, const float *z, double *partial, double *out, hipStream_t s);
+// FP64 Lipschitz bound of the code gradient.
+hipError_t launch_lipschitz_code(const float *d, int K, int m, int P, double *tmp, double *out, hipStream_t s);
+long long lipschitz_tmp_elems(int K, int m, int P);
+
+}  // namespace scsc
