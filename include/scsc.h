@@ -179,6 +179,33 @@ int64_t csc_surrogate_size(int K, int m);
  * argument is out of range.  Host only. */
 int64_t csc_surrogate_index(int K, int m, int k, int sy, int sx, int k2, int sy2, int sx2);
 
+/* ---- per-kernel timing -------------------------------------------------------- */
+
+/* Kernel classes timed by csc_profile_read. */
+typedef enum {
+    CSC_PK_SELECT = 0,   /* Bernoulli selection and the prefix scan of list capacities   */
+    CSC_PK_GATHER = 1,   /* warm start: selected non-zero codes into lists              */
+    CSC_PK_SYNTH = 2,    /* synthesis / masked residual from code lists                  */
+    CSC_PK_ADJOINT = 3,  /* proximal-gradient step: adjoint at S + soft-threshold         */
+    CSC_PK_SCATTER = 4,  /* upsampling of eq. (4): lists back to dense codes             */
+    CSC_PK_LISTS = 5,    /* non-zero lists from dense codes                              */
+    CSC_PK_CORR = 6,     /* filter correlation Z^T r (and Z^T W x) with its reduction    */
+    CSC_PK_UPDATE = 7,   /* power-iteration and projected filter updates                */
+    CSC_PK_SUR_ACC = 8,  /* surrogate accumulation C_bar += Z^T W Z                      */
+    CSC_PK_SUR_MV = 9,   /* surrogate product C_bar d                                    */
+    CSC_PK_OBJECTIVE = 10,
+    CSC_PK_LIPSCHITZ = 11,
+    CSC_PK_DENSE = 12,   /* dense operator helpers (csc_adjoint)                         */
+    CSC_PK_COUNT = 13
+} csc_kernel_class;
+
+/* enable != 0: record a pair of HIP events on the handle's stream around every
+ * kernel launch from now on, clearing previous records; enable == 0: stop. */
+int csc_profile_enable(csc_handle h, int enable);
+/* Launch count and summed event time (milliseconds) of one kernel class since
+ * profiling was enabled.  Host outputs.  Synchronises the stream. */
+int csc_profile_read(csc_handle h, int kernel_class, int64_t *launches, double *total_ms);
+
 #ifdef __cplusplus
 }
 #endif

@@ -68,7 +68,13 @@ SIGNATURES = {
     "csc_lipschitz_code": (_i, [_vp, _vp, _i, _i, _i, C.POINTER(_d)]),
     "csc_surrogate_size": (C.c_int64, [_i, _i]),
     "csc_surrogate_index": (C.c_int64, [_i, _i, _i, _i, _i, _i, _i, _i]),
+    "csc_profile_enable": (_i, [_vp, _i]),
+    "csc_profile_read": (_i, [_vp, _i, C.POINTER(C.c_int64), C.POINTER(_d)]),
 }
+
+# csc_kernel_class
+KERNEL_CLASSES = ["select", "gather", "synth", "adjoint", "scatter", "lists", "corr", "update", "sur_acc",
+                  "sur_mv", "objective", "lipschitz", "dense"]
 
 
 def load(path: str = LIB_PATH) -> C.CDLL:

@@ -30,6 +30,12 @@ enum Slot {
     WS_G,
     WS_Y,
     WS_LIP,
+    WS_ROWS,
+    WS_FMCNT,
+    WS_FMOFF,
+    WS_FM,
+    WS_LAG,
+    WS_ES,
     WS_COUNT
 };
 
@@ -52,6 +58,16 @@ struct csc_ctx {
     std::vector<int32_t> geo_key;
     bool geo_valid = false;
     double *h_pinned = nullptr;  // host readback staging (SC_COUNT doubles)
+    // per-kernel-class event timing (csc_profile_enable / csc_profile_read)
+    bool prof = false;
+    struct Rec {
+        int cls;
+        hipEvent_t a, b;
+    };
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<Rec> recs;
+    long long prof_launches[CSC_PK_COUNT] = {};
+    double prof_ms[CSC_PK_COUNT] = {};
 };
 
 namespace {
@@ -60,6 +76,60 @@ int fail(csc_ctx *h, int code, const std::string &msg) {
     if (h) h->err = msg;
     return code;
 }
+
+hipEvent_t take_event(csc_ctx *h) {
+    if (!h->ev_pool.empty()) {
+        hipEvent_t e = h->ev_pool.back();
+        h->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) {
+        hipGetLastError();
+        return nullptr;
+    }
+    return e;
+}
+
+// Fold finished records into the per-class totals (waits for the events).
+void fold_records(csc_ctx *h) {
+    for (auto &r : h->recs) {
+        float ms = 0.f;
+        hipEventSynchronize(r.b);
+        if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+            h->prof_launches[r.cls] += 1;
+            h->prof_ms[r.cls] += ms;
+        } else {
+            hipGetLastError();
+        }
+        h->ev_pool.push_back(r.a);
+        h->ev_pool.push_back(r.b);
+    }
+    h->recs.clear();
+}
+
+// Records an event pair around the launches of its scope when profiling is on.
+struct ProfScope {
+    csc_ctx *h;
+    int cls;
+    hipEvent_t a = nullptr;
+    ProfScope(csc_ctx *h_, int cls_) : h(h_), cls(cls_) {
+        if (h->prof) {
+            a = take_event(h);
+            if (a) hipEventRecord(a, h->stream);
+        }
+    }
+    ~ProfScope() {
+        if (!a) return;
+        hipEvent_t b = take_event(h);
+        if (!b) return;
+        hipEventRecord(b, h->stream);
+        h->recs.push_back(csc_ctx::Rec{cls, a, b});
+        if (h->recs.size() > 100000) fold_records(h);
+    }
+};
+
+#define PROF(cls) ProfScope prof_scope_(h, cls)
 
 #define HIPCHK(expr)                                                                              \
     do {                                                                                          \
@@ -134,7 +204,8 @@ int geometry(csc_ctx *h, const csc_images *im) {
     g.h_img.assign(im->n, ImgInfo{});
     g.h_tiles.clear();
     long long pix = 0;
-    int tiles = 0, max_side = 0;
+    int tiles = 0, max_side = 0, rows = 0;
+    std::vector<int> row_img;
     for (int i = 0; i < im->n; ++i) {
         ImgInfo &ii = g.h_img[i];
         ii.H = im->hw[2 * i];
@@ -144,6 +215,9 @@ int geometry(csc_ctx *h, const csc_images *im) {
         ii.tiles_x = (ii.W + TS - 1) / TS;
         ii.tile_off = tiles;
         ii.index = im->index_base + i;
+        ii.row_off = rows;
+        rows += ii.H;
+        row_img.insert(row_img.end(), ii.H, i);
         for (int ty = 0; ty < ii.tiles_y; ++ty)
             for (int tx = 0; tx < ii.tiles_x; ++tx) g.h_tiles.push_back(TileInfo{i, ty, tx, 0});
         tiles += ii.tiles_y * ii.tiles_x;
@@ -154,14 +228,18 @@ int geometry(csc_ctx *h, const csc_images *im) {
     g.n_tiles = tiles;
     g.n_pix = pix;
     g.max_side = max_side;
+    g.n_rows = rows;
     h->geo_valid = false;
     WS(dimg, ImgInfo, WS_IMG, g.n_img);
     WS(dtiles, TileInfo, WS_TILES, g.n_tiles);
+    WS(drows, int, WS_ROWS, g.n_rows);
+    HIPCHK(hipMemcpyAsync(drows, row_img.data(), sizeof(int) * g.n_rows, hipMemcpyHostToDevice, h->stream));
     HIPCHK(hipMemcpyAsync(dimg, g.h_img.data(), sizeof(ImgInfo) * g.n_img, hipMemcpyHostToDevice, h->stream));
     HIPCHK(hipMemcpyAsync(dtiles, g.h_tiles.data(), sizeof(TileInfo) * g.n_tiles, hipMemcpyHostToDevice, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     g.d_img = dimg;
     g.d_tiles = dtiles;
+    g.d_row_img = drows;
     h->geo_key = key;
     h->geo_valid = true;
     return CSC_OK;
@@ -183,7 +261,10 @@ int lipschitz(csc_ctx *h, const float *d, int K, int m, int max_side, double *ou
     const int P = dft_size(max_side, m);
     WS(tmp, double, WS_LIP, lipschitz_tmp_elems(K, m, P));
     WS(sc, double, WS_SCAL, SC_COUNT);
-    HIPCHK(launch_lipschitz_code(d, K, m, P, tmp, sc + SC_LZ, h->stream));
+    {
+        PROF(CSC_PK_LIPSCHITZ);
+        HIPCHK(launch_lipschitz_code(d, K, m, P, tmp, sc + SC_LZ, h->stream));
+    }
     int st = read_scalars(h, sc, SC_COUNT);
     if (st) return st;
     *out = h->h_pinned[SC_LZ];
@@ -191,15 +272,18 @@ int lipschitz(csc_ctx *h, const float *d, int K, int m, int max_side, double *ou
 }
 
 // Lists of the non-zero codes of a dense z (capacity = exact count).
-int build_nonzero_lists(csc_ctx *h, int K, const float *z, Lists *out) {
+int build_nonzero_lists(csc_ctx *h, int K, const float *z, Lists *out, unsigned long long *nnz_out = nullptr) {
     const Geometry &g = h->geo;
     WS(cnt32, unsigned, WS_CNT32, g.n_pix);
     WS(off, unsigned, WS_OFF, g.n_pix + 1);
     WS(tmp, unsigned long long, WS_SCANTMP, scan_tmp_elems(g.n_pix));
     WS(sc, double, WS_SCAL, SC_COUNT);
     unsigned long long *total = reinterpret_cast<unsigned long long *>(sc + SC_TOTAL);
-    HIPCHK(launch_count_nonzero(g, K, z, cnt32, h->stream));
-    HIPCHK(launch_scan(cnt32, off, g.n_pix, tmp, total, h->stream));
+    {
+        PROF(CSC_PK_LISTS);
+        HIPCHK(launch_count_nonzero(g, K, z, cnt32, h->stream));
+        HIPCHK(launch_scan(cnt32, off, g.n_pix, tmp, total, h->stream));
+    }
     int st = read_scalars(h, sc, SC_COUNT);
     if (st) return st;
     unsigned long long nz;
@@ -207,8 +291,12 @@ int build_nonzero_lists(csc_ctx *h, int K, const float *z, Lists *out) {
     if (nz >= (1ULL << 32)) return fail(h, CSC_EUNSUPPORTED, "more than 2^32 non-zero codes");
     WS(pairs, Pair, WS_PAIRS0, nz + 1);
     WS(nzc, unsigned short, WS_NZC0, g.n_pix);
-    HIPCHK(launch_fill_nonzero(g, K, z, off, pairs, nzc, h->stream));
+    {
+        PROF(CSC_PK_LISTS);
+        HIPCHK(launch_fill_nonzero(g, K, z, off, pairs, nzc, h->stream));
+    }
     *out = Lists{off, nzc, pairs};
+    if (nnz_out) *nnz_out = nz;
     return CSC_OK;
 }
 
@@ -218,6 +306,7 @@ int filter_corr_lists(csc_ctx *h, int K, int m, Lists L, const float *r, float *
     const int M = m * m;
     const int nb = corr_blocks(g);
     WS(part, float, WS_PART, (size_t)nb * K * M);
+    PROF(CSC_PK_CORR);
     HIPCHK(launch_filter_corr_f32(g, K, m, L, r, part, nb, h->stream));
     HIPCHK(launch_reduce_partials_f32(part, nb, K * M, G, h->stream));
     return CSC_OK;
@@ -234,9 +323,13 @@ int power_iteration(csc_ctx *h, int K, int m, Lists L, const unsigned char *W, i
     HIPCHK(launch_fill(v, K * M, (float)(1.0 / std::sqrt((double)K * M)), h->stream));
     HIPCHK(hipMemsetAsync(sc + SC_LAM, 0, sizeof(double), h->stream));
     for (int it = 0; it < n_power; ++it) {
-        HIPCHK(launch_synth(g, K, m, L, v, nullptr, W, R, SYNTH_WEIGHTED, h->stream));
+        {
+            PROF(CSC_PK_SYNTH);
+            HIPCHK(launch_synth(g, K, m, L, v, nullptr, W, R, SYNTH_WEIGHTED, h->stream));
+        }
         int st = filter_corr_lists(h, K, m, L, R, w);
         if (st) return st;
+        PROF(CSC_PK_UPDATE);
         HIPCHK(launch_power_update(v, w, K * M, sc + SC_LAM, h->stream));
     }
     return CSC_OK;
@@ -275,6 +368,8 @@ extern "C" int csc_destroy(csc_handle h) {
     if (!h) return CSC_EINVAL;
     hipSetDevice(h->device);
     hipStreamSynchronize(h->stream);
+    fold_records(h);
+    for (auto e : h->ev_pool) hipEventDestroy(e);
     for (auto &b : h->ws)
         if (b.p) hipFree(b.p);
     if (h->h_pinned) hipHostFree(h->h_pinned);
@@ -354,8 +449,11 @@ extern "C" int csc_code_step(csc_handle h, const csc_images *im, const float *x,
     WS(sc, double, WS_SCAL, SC_COUNT);
     unsigned long long *total = reinterpret_cast<unsigned long long *>(sc + SC_TOTAL);
     const unsigned long long thr = (unsigned long long)std::floor(std::ldexp(p, 32));
-    HIPCHK(launch_mask_count(g, K, thr, seed, draw, mw, cnt32, h->stream));
-    HIPCHK(launch_scan(cnt32, soff, g.n_pix, tmp, total, h->stream));
+    {
+        PROF(CSC_PK_SELECT);
+        HIPCHK(launch_mask_count(g, K, thr, seed, draw, mw, cnt32, h->stream));
+        HIPCHK(launch_scan(cnt32, soff, g.n_pix, tmp, total, h->stream));
+    }
     if ((st = read_scalars(h, sc, SC_COUNT))) return st;
     unsigned long long nsel;
     std::memcpy(&nsel, &h->h_pinned[SC_TOTAL], sizeof(nsel));
@@ -373,16 +471,28 @@ extern "C" int csc_code_step(csc_handle h, const csc_images *im, const float *x,
         nzc[1] = c1;
     }
     WS(R, float, WS_R, g.n_pix);
-    HIPCHK(launch_gather_selected(g, K, mw, soff, z, pairs[0], nzc[0], h->stream));
+    {
+        PROF(CSC_PK_GATHER);
+        HIPCHK(launch_gather_selected(g, K, mw, soff, z, pairs[0], nzc[0], h->stream));
+    }
     const float feta = (float)eta, fthr = (float)(eta * lambda);
     int cur = 0;
     for (int it = 0; it < n_iter; ++it) {
-        HIPCHK(launch_synth(g, K, m, Lists{soff, nzc[cur], pairs[cur]}, d, x, W, R, SYNTH_RESIDUAL, h->stream));
-        HIPCHK(launch_adjoint_shrink(g, K, m, mw, soff, pairs[cur], nzc[cur], pairs[cur ^ 1], nzc[cur ^ 1], R, d,
-                                     feta, fthr, h->stream));
+        {
+            PROF(CSC_PK_SYNTH);
+            HIPCHK(launch_synth(g, K, m, Lists{soff, nzc[cur], pairs[cur]}, d, x, W, R, SYNTH_RESIDUAL, h->stream));
+        }
+        {
+            PROF(CSC_PK_ADJOINT);
+            HIPCHK(launch_adjoint_shrink(g, K, m, mw, soff, pairs[cur], nzc[cur], pairs[cur ^ 1], nzc[cur ^ 1], R,
+                                         d, feta, fthr, h->stream));
+        }
         cur ^= 1;
     }
-    HIPCHK(launch_scatter_dense(g, K, Lists{soff, nzc[cur], pairs[cur]}, z, h->stream));
+    {
+        PROF(CSC_PK_SCATTER);
+        HIPCHK(launch_scatter_dense(g, K, Lists{soff, nzc[cur], pairs[cur]}, z, h->stream));
+    }
     if (stats) {
         unsigned long long *nnz = reinterpret_cast<unsigned long long *>(sc + SC_NNZ);
         HIPCHK(hipMemsetAsync(nnz, 0, sizeof(unsigned long long), h->stream));
@@ -418,7 +528,8 @@ extern "C" int csc_dict_step(csc_handle h, const csc_images *im, const float *x,
     const Geometry &g = h->geo;
     const int M = m * m;
     Lists L;
-    if ((st = build_nonzero_lists(h, K, z, &L))) return st;
+    unsigned long long nz = 0;
+    if ((st = build_nonzero_lists(h, K, z, &L, &nz))) return st;
     WS(sc, double, WS_SCAL, SC_COUNT);
     const bool need_ld = sur || step <= 0.0 || L_d_out;
     if (need_ld) {
@@ -438,15 +549,38 @@ extern "C" int csc_dict_step(csc_handle h, const csc_images *im, const float *x,
         WS(G, float, WS_G, K * M);
         WS(R, float, WS_R, g.n_pix);
         for (int it = 0; it < n_iter; ++it) {
-            HIPCHK(launch_synth(g, K, m, L, d, x, W, R, SYNTH_RESIDUAL, h->stream));
+            {
+                PROF(CSC_PK_SYNTH);
+                HIPCHK(launch_synth(g, K, m, L, d, x, W, R, SYNTH_RESIDUAL, h->stream));
+            }
             if ((st = filter_corr_lists(h, K, m, L, R, G))) return st;
+            PROF(CSC_PK_UPDATE);
             HIPCHK(launch_batch_update(d, G, sc + SC_LAM, K, M, h->stream));
         }
     } else {
-        HIPCHK(launch_surrogate_accumulate(g, K, m, L, W, sur->C, h->stream));
+        {
+            if (g.max_side > 65535) return fail(h, CSC_EUNSUPPORTED, "online step: image sides must be < 65536");
+            const long long KR = (long long)K * g.n_rows;
+            WS(fmcnt, unsigned, WS_FMCNT, KR);
+            WS(fmoff, unsigned, WS_FMOFF, KR + 1);
+            WS(tmp, unsigned long long, WS_SCANTMP, scan_tmp_elems(KR));
+            WS(fm, uint2, WS_FM, nz + 1);
+            PROF(CSC_PK_SUR_ACC);
+            unsigned long long *total = reinterpret_cast<unsigned long long *>(sc + SC_NNZ);
+            HIPCHK(launch_fm_lists(g, K, L, fmcnt, fmoff, fm, tmp, total, h->stream));
+            if (W) {
+                HIPCHK(launch_surrogate_blocks(g, K, m, fmoff, fm, W, sur->C, h->stream));
+            } else {
+                const long long nl = surrogate_lag_elems(K, m);
+                WS(Rl, double, WS_LAG, nl);
+                WS(Es, double, WS_ES, nl * 4 * (m / 2 > 0 ? m / 2 : 1));
+                HIPCHK(launch_surrogate_unmasked(g, K, m, L, fmoff, fm, Rl, Es, sur->C, h->stream));
+            }
+        }
         const int nb = corr_blocks(g);
         {
             WS(part, double, WS_PART, (size_t)nb * K * M);
+            PROF(CSC_PK_CORR);
             HIPCHK(launch_filter_corr_f64(g, K, m, L, x, W, part, nb, h->stream));
             HIPCHK(launch_reduce_partials_f64_add(part, nb, K * M, sur->B, h->stream));
         }
@@ -456,7 +590,11 @@ extern "C" int csc_dict_step(csc_handle h, const csc_images *im, const float *x,
             WS(y, double, WS_Y, K * M);
             WS(part, double, WS_PART, surrogate_matvec_partial_elems(K, m));
             for (int it = 0; it < n_iter; ++it) {
-                HIPCHK(launch_surrogate_matvec(K, m, sur->C, d, part, y, h->stream));
+                {
+                    PROF(CSC_PK_SUR_MV);
+                    HIPCHK(launch_surrogate_matvec(K, m, sur->C, d, part, y, h->stream));
+                }
+                PROF(CSC_PK_UPDATE);
                 HIPCHK(launch_online_update(d, y, sur->B, sur->Ld_sum, K, M, h->stream));
             }
         } else {
@@ -480,7 +618,10 @@ extern "C" int csc_objective(csc_handle h, const csc_images *im, const float *x,
     const Geometry &g = h->geo;
     WS(part, double, WS_PART, 2 * (size_t)g.n_tiles);
     WS(sc, double, WS_SCAL, SC_COUNT);
-    HIPCHK(launch_objective(g, K, m, x, W, d, z, part, sc + SC_OBJ, h->stream));
+    {
+        PROF(CSC_PK_OBJECTIVE);
+        HIPCHK(launch_objective(g, K, m, x, W, d, z, part, sc + SC_OBJ, h->stream));
+    }
     if ((st = read_scalars(h, sc, SC_COUNT))) return st;
     const double data = h->h_pinned[SC_OBJ], l1 = h->h_pinned[SC_OBJ + 1];
     *f_out = data + lambda * l1;
@@ -503,7 +644,10 @@ extern "C" int csc_synthesize(csc_handle h, const csc_images *im, const float *d
     if ((st = geometry(h, im))) return st;
     Lists L;
     if ((st = build_nonzero_lists(h, K, z, &L))) return st;
-    HIPCHK(launch_synth(h->geo, K, m, L, d, nullptr, nullptr, y, SYNTH_PLAIN, h->stream));
+    {
+        PROF(CSC_PK_SYNTH);
+        HIPCHK(launch_synth(h->geo, K, m, L, d, nullptr, nullptr, y, SYNTH_PLAIN, h->stream));
+    }
     return CSC_OK;
 }
 
@@ -517,7 +661,10 @@ extern "C" int csc_adjoint(csc_handle h, const csc_images *im, const float *d, i
     if (!d || !r || !g) return fail(h, CSC_EINVAL, "null pointer argument");
     HIPCHK(hipSetDevice(h->device));
     if ((st = geometry(h, im))) return st;
-    HIPCHK(launch_adjoint_dense(h->geo, K, m, r, d, g, h->stream));
+    {
+        PROF(CSC_PK_DENSE);
+        HIPCHK(launch_adjoint_dense(h->geo, K, m, r, d, g, h->stream));
+    }
     return CSC_OK;
 }
 
@@ -534,4 +681,29 @@ extern "C" int csc_filter_corr(csc_handle h, const csc_images *im, const float *
     Lists L;
     if ((st = build_nonzero_lists(h, K, z, &L))) return st;
     return filter_corr_lists(h, K, m, L, r, G);
+}
+
+extern "C" int csc_profile_enable(csc_handle h, int enable) {
+    if (!h) return CSC_EINVAL;
+    HIPCHK(hipSetDevice(h->device));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    fold_records(h);
+    for (int i = 0; i < CSC_PK_COUNT; ++i) {
+        h->prof_launches[i] = 0;
+        h->prof_ms[i] = 0.0;
+    }
+    h->prof = enable != 0;
+    return CSC_OK;
+}
+
+extern "C" int csc_profile_read(csc_handle h, int kernel_class, int64_t *launches, double *total_ms) {
+    if (!h) return CSC_EINVAL;
+    if (kernel_class < 0 || kernel_class >= CSC_PK_COUNT || !launches || !total_ms)
+        return fail(h, CSC_EINVAL, "profile: bad kernel class or null output");
+    HIPCHK(hipSetDevice(h->device));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    fold_records(h);
+    *launches = h->prof_launches[kernel_class];
+    *total_ms = h->prof_ms[kernel_class];
+    return CSC_OK;
 }

@@ -247,9 +247,16 @@ __global__ void k_sum_counts(const unsigned short *cnt, long long n, unsigned lo
 // when the region holds at most SYN_CAP pairs, the pairs themselves are staged.
 // Each output pixel then walks its m x m taps in a fixed order.
 // ---------------------------------------------------------------------------
-constexpr int SYN_CAP = 4096;
+constexpr int SYN_CAP = 2880;
+constexpr int SYN_DCAP = 12288;  // filters staged in LDS when K m^2 <= 12288 floats (48 KiB)
 
-template <int MM>
+// A staged code of the synthesis region: filter, region column, value.
+struct __align__(8) SynPair {
+    unsigned short k, col;
+    float v;
+};
+
+template <int MM, bool DLDS>
 __global__ __launch_bounds__(TPB) void k_synth(const ImgInfo *imgs, const TileInfo *tiles, int K, Lists zl,
                                                const float *__restrict__ d, const float *__restrict__ x,
                                                const unsigned char *__restrict__ W, float *__restrict__ out,
@@ -257,12 +264,15 @@ __global__ __launch_bounds__(TPB) void k_synth(const ImgInfo *imgs, const TileIn
     constexpr int C = MM / 2, RW = TS + 2 * C, R = RW * RW, M = MM * MM;
     constexpr int CH = (R + TPB - 1) / TPB;
     __shared__ unsigned lgoff[R];
-    __shared__ int lstart[R];
-    __shared__ int lcnt[R];
-    __shared__ Pair lp[SYN_CAP];
+    __shared__ int lstart[R + 1];
+    __shared__ unsigned short lcnt[R];
+    __shared__ SynPair lp[SYN_CAP];
     __shared__ int scratch[TPB];
+    __shared__ float dl[DLDS ? SYN_DCAP : 1];
 
     PixelCtx c = pixel_ctx(imgs, tiles);
+    if (DLDS)
+        for (int i = threadIdx.x; i < K * M; i += TPB) dl[i] = d[i];
     const int oy = c.t.ty * TS - C, ox = c.t.tx * TS - C;
     int mysum = 0;
 #pragma unroll
@@ -277,7 +287,7 @@ __global__ __launch_bounds__(TPB) void k_synth(const ImgInfo *imgs, const TileIn
                 n = zl.cnt[gp];
                 o = zl.off[gp];
             }
-            lcnt[i] = n;
+            lcnt[i] = (unsigned short)n;
             lgoff[i] = o;
             mysum += n;
         }
@@ -290,25 +300,39 @@ __global__ __launch_bounds__(TPB) void k_synth(const ImgInfo *imgs, const TileIn
         const int i = threadIdx.x * CH + j;
         if (i < R) {
             lstart[i] = ex;
+            const int n = lcnt[i];
             if (staged)
-                for (int q = 0; q < lcnt[i]; ++q) lp[ex + q] = zl.pairs[lgoff[i] + q];
-            ex += lcnt[i];
+                for (int q = 0; q < n; ++q) {
+                    const Pair e = zl.pairs[lgoff[i] + q];
+                    lp[ex + q] = SynPair{(unsigned short)e.k, (unsigned short)(i % RW), e.v};
+                }
+            ex += n;
         }
     }
+    if (threadIdx.x == 0) lstart[R] = total;
     __syncthreads();
     if (!c.valid) return;
-    float acc = 0.f;
+    const float *dd = DLDS ? dl : d;
+    float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, acc3 = 0.f;
     if (staged) {
+        // Output p, tap s: code pixel q = p - s sits at region column lx + c - s_x, so
+        // for a tap row s_y the codes of the 2c + 1 columns lx .. lx + 2c form one
+        // contiguous run of the staged pairs.
         for (int sy = -C; sy <= C; ++sy) {
-            for (int sx = -C; sx <= C; ++sx) {
-                const int i = (c.ly + C - sy) * RW + (c.lx + C - sx);
-                const int n = lcnt[i];
-                const Pair *src = lp + lstart[i];
-                const float *dt = d + (sy + C) * MM + (sx + C);
-                for (int q = 0; q < n; ++q) {
-                    const Pair e = src[q];
-                    acc = fmaf(dt[e.k * M], e.v, acc);
-                }
+            const int rb = (c.ly + C - sy) * RW + c.lx;
+            const int j0 = lstart[rb], j1 = lstart[rb + 2 * C + 1];
+            const float *drow = dd + (sy + C) * MM + 2 * C + c.lx;  // tap column = 2c - (col - lx)
+            int j = j0;
+            for (; j + 3 < j1; j += 4) {
+                const SynPair e0 = lp[j], e1 = lp[j + 1], e2 = lp[j + 2], e3 = lp[j + 3];
+                acc0 = fmaf(drow[e0.k * M - e0.col], e0.v, acc0);
+                acc1 = fmaf(drow[e1.k * M - e1.col], e1.v, acc1);
+                acc2 = fmaf(drow[e2.k * M - e2.col], e2.v, acc2);
+                acc3 = fmaf(drow[e3.k * M - e3.col], e3.v, acc3);
+            }
+            for (; j < j1; ++j) {
+                const SynPair e = lp[j];
+                acc0 = fmaf(drow[e.k * M - e.col], e.v, acc0);
             }
         }
     } else {
@@ -317,14 +341,15 @@ __global__ __launch_bounds__(TPB) void k_synth(const ImgInfo *imgs, const TileIn
                 const int i = (c.ly + C - sy) * RW + (c.lx + C - sx);
                 const int n = lcnt[i];
                 const Pair *src = zl.pairs + lgoff[i];
-                const float *dt = d + (sy + C) * MM + (sx + C);
+                const float *dt = dd + (sy + C) * MM + (sx + C);
                 for (int q = 0; q < n; ++q) {
                     const Pair e = src[q];
-                    acc = fmaf(dt[e.k * M], e.v, acc);
+                    acc0 = fmaf(dt[e.k * M], e.v, acc0);
                 }
             }
         }
     }
+    const float acc = (acc0 + acc1) + (acc2 + acc3);
     float o;
     if (mode == SYNTH_RESIDUAL) {
         o = x[c.gp] - acc;
@@ -337,14 +362,24 @@ __global__ __launch_bounds__(TPB) void k_synth(const ImgInfo *imgs, const TileIn
     out[c.gp] = o;
 }
 
-// ---------------------------------------------------------------------------
-// One proximal-gradient iteration at the selected coordinates (FP32 VALU).
-// Thread <-> pixel q: the m x m residual window around q is held in registers
-// and reused for every selected k of q; filters are staged in LDS in chunks of
-// at most KC filters, rows padded to a multiple of 4 taps for 16-byte reads.
-// The old list of q (read buffer) is merged by k; the new non-zeros are
-// appended, in k order, to the write buffer.
-// ---------------------------------------------------------------------------
+constexpr int ADJ_CAP = 2048;
+
+// Dot product of an LDS filter row (float4-aligned, zero padded) with the
+// register window.
+template <int M4>
+__device__ __forceinline__ float dot_window(const float4 *dr, const float (&win)[M4]) {
+    float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+#pragma unroll
+    for (int j = 0; j < M4 / 4; ++j) {
+        const float4 q = dr[j];
+        a0 = fmaf(q.x, win[4 * j + 0], a0);
+        a1 = fmaf(q.y, win[4 * j + 1], a1);
+        a2 = fmaf(q.z, win[4 * j + 2], a2);
+        a3 = fmaf(q.w, win[4 * j + 3], a3);
+    }
+    return (a0 + a1) + (a2 + a3);
+}
+
 template <int MM>
 __global__ __launch_bounds__(TPB) void k_adjoint_shrink(const ImgInfo *imgs, const TileInfo *tiles, int K,
                                                         long long n_pix, const unsigned *__restrict__ mask_words,
@@ -356,6 +391,8 @@ __global__ __launch_bounds__(TPB) void k_adjoint_shrink(const ImgInfo *imgs, con
                                                         float eta, float thr, int KC) {
     constexpr int C = MM / 2, RW = TS + 2 * C, M = MM * MM, M4 = (M + 3) / 4 * 4;
     __shared__ float rr[RW * RW];
+    __shared__ Pair op[ADJ_CAP];
+    __shared__ int scratch[TPB];
     extern __shared__ float4 dl4[];
     float *dl = reinterpret_cast<float *>(dl4);
 
@@ -367,6 +404,13 @@ __global__ __launch_bounds__(TPB) void k_adjoint_shrink(const ImgInfo *imgs, con
         if (gy >= 0 && gy < c.im.H && gx >= 0 && gx < c.im.W) v = r[c.im.pix_off + (long long)gy * c.im.W + gx];
         rr[i] = v;
     }
+    const unsigned base = c.valid ? soff[c.gp] : 0u;
+    const int ocnt = c.valid ? (int)oldc[c.gp] : 0;
+    int total;
+    const int ex = block_exclusive_scan(ocnt, scratch, &total);
+    const bool staged = total <= ADJ_CAP;
+    if (staged)
+        for (int j = 0; j < ocnt; ++j) op[ex + j] = oldp[base + j];
     __syncthreads();
     float win[M4];
 #pragma unroll
@@ -378,10 +422,8 @@ __global__ __launch_bounds__(TPB) void k_adjoint_shrink(const ImgInfo *imgs, con
             win[j] = 0.f;
         }
     }
-    const unsigned base = c.valid ? soff[c.gp] : 0u;
-    const int ocnt = c.valid ? (int)oldc[c.gp] : 0;
     int oi = 0;
-    Pair oe = ocnt > 0 ? oldp[base] : Pair{INT_MAX, 0.f};
+    Pair oe = ocnt > 0 ? (staged ? op[ex] : oldp[base]) : Pair{INT_MAX, 0.f};
     int nn = 0;
     for (int k0 = 0; k0 < K; k0 += KC) {
         const int k1 = min(K, k0 + KC);
@@ -401,27 +443,18 @@ __global__ __launch_bounds__(TPB) void k_adjoint_shrink(const ImgInfo *imgs, con
                 const int b = __builtin_ctz(bits);
                 bits &= bits - 1u;
                 const int k = 32 * w + b;
-                const float4 *dr = dl4 + (k - k0) * (M4 / 4);
-                float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
-#pragma unroll
-                for (int j = 0; j < M4 / 4; ++j) {
-                    const float4 q = dr[j];
-                    a0 = fmaf(q.x, win[4 * j + 0], a0);
-                    a1 = fmaf(q.y, win[4 * j + 1], a1);
-                    a2 = fmaf(q.z, win[4 * j + 2], a2);
-                    a3 = fmaf(q.w, win[4 * j + 3], a3);
-                }
-                const float g = (a0 + a1) + (a2 + a3);
                 while (oe.k < k) {
                     ++oi;
-                    oe = oi < ocnt ? oldp[base + oi] : Pair{INT_MAX, 0.f};
+                    oe = oi < ocnt ? (staged ? op[ex + oi] : oldp[base + oi]) : Pair{INT_MAX, 0.f};
                 }
                 float zold = 0.f;
                 if (oe.k == k) {
                     zold = oe.v;
                     ++oi;
-                    oe = oi < ocnt ? oldp[base + oi] : Pair{INT_MAX, 0.f};
+                    oe = oi < ocnt ? (staged ? op[ex + oi] : oldp[base + oi]) : Pair{INT_MAX, 0.f};
                 }
+                __builtin_amdgcn_sched_barrier(0);
+                const float g = dot_window<M4>(dl4 + (k - k0) * (M4 / 4), win);
                 const float v = soft_threshold(fmaf(eta, g, zold), thr);
                 if (v != 0.f) {
                     newp[base + nn] = Pair{k, v};
@@ -474,19 +507,7 @@ __global__ __launch_bounds__(TPB) void k_adjoint_dense(const ImgInfo *imgs, cons
         }
         __syncthreads();
         if (!c.valid) continue;
-        for (int k = k0; k < k1; ++k) {
-            const float4 *dr = dl4 + (k - k0) * (M4 / 4);
-            float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
-#pragma unroll
-            for (int j = 0; j < M4 / 4; ++j) {
-                const float4 q = dr[j];
-                a0 = fmaf(q.x, win[4 * j + 0], a0);
-                a1 = fmaf(q.y, win[4 * j + 1], a1);
-                a2 = fmaf(q.z, win[4 * j + 2], a2);
-                a3 = fmaf(q.w, win[4 * j + 3], a3);
-            }
-            op[(long long)k * HW] = (a0 + a1) + (a2 + a3);
-        }
+        for (int k = k0; k < k1; ++k) op[(long long)k * HW] = dot_window<M4>(dl4 + (k - k0) * (M4 / 4), win);
     }
 }
 
@@ -494,7 +515,7 @@ __global__ __launch_bounds__(TPB) void k_adjoint_dense(const ImgInfo *imgs, cons
 template <int MM>
 int filter_chunk() {
     constexpr int M = MM * MM, M4 = (M + 3) / 4 * 4;
-    int kc = (56 * 1024) / (M4 * 4);
+    int kc = (52 * 1024) / (M4 * 4);
     kc = kc / 4 * 4;
     return kc > MAX_K ? MAX_K : kc;
 }
@@ -573,8 +594,12 @@ namespace {
 template <int MM>
 hipError_t synth_impl(const Geometry &g, int K, Lists z, const float *d, const float *x, const unsigned char *W,
                       float *out, SynthMode mode, hipStream_t s) {
-    hipLaunchKernelGGL(k_synth<MM>, dim3(g.n_tiles), dim3(TPB), 0, s, g.d_img, g.d_tiles, K, z, d, x, W, out,
-                       (int)mode);
+    if (K * MM * MM <= SYN_DCAP)
+        hipLaunchKernelGGL((k_synth<MM, true>), dim3(g.n_tiles), dim3(TPB), 0, s, g.d_img, g.d_tiles, K, z, d, x, W,
+                           out, (int)mode);
+    else
+        hipLaunchKernelGGL((k_synth<MM, false>), dim3(g.n_tiles), dim3(TPB), 0, s, g.d_img, g.d_tiles, K, z, d, x,
+                           W, out, (int)mode);
     return hipGetLastError();
 }
 

@@ -17,80 +17,185 @@ constexpr int CORR_MAX_BLOCKS = 512;
 // single writer and a fixed accumulation order: the result is deterministic.
 // FROM_X selects the right-hand side W x (for B of eq. 7) instead of r.
 // ---------------------------------------------------------------------------
-template <int MM, typename ACC, bool FROM_X>
-__global__ __launch_bounds__(TPB) void k_filter_corr(const ImgInfo *imgs, const TileInfo *tiles, int n_tiles, int K,
-                                                     Lists zl, const float *__restrict__ r,
-                                                     const unsigned char *__restrict__ W, ACC *__restrict__ partial,
-                                                     int KC) {
+constexpr int CORR_CAP = 2048;
+constexpr double FIX_SCALE = 1099511627776.0;  // 2^40
+constexpr double FIX_INV = 1.0 / 1099511627776.0;
+
+// Stage the "right-hand side" region (r, or W x) and the tile's non-zero codes.
+// Returns through the shared arrays; contains block barriers.
+template <int MM, bool FROM_X>
+__device__ __forceinline__ bool corr_stage_tile(const ImgInfo &im, const TileInfo &t, Lists zl,
+                                                const float *__restrict__ r, const unsigned char *__restrict__ W,
+                                                float *rr, unsigned *loff, int *lst, int *lc, Pair *ent,
+                                                int *scratch) {
+    constexpr int C = MM / 2, RW = TS + 2 * C;
+    const int oy = t.ty * TS - C, ox = t.tx * TS - C;
+    for (int i = threadIdx.x; i < RW * RW; i += TPB) {
+        const int gy = oy + i / RW, gx = ox + i % RW;
+        float v = 0.f;
+        if (gy >= 0 && gy < im.H && gx >= 0 && gx < im.W) {
+            const long long gp = im.pix_off + (long long)gy * im.W + gx;
+            v = r[gp];
+            if (FROM_X && W && !W[gp]) v = 0.f;
+        }
+        rr[i] = v;
+    }
+    int n = 0;
+    unsigned o = 0;
+    {
+        const int ly = threadIdx.x / TS, lx = threadIdx.x % TS;
+        const int y = t.ty * TS + ly, x = t.tx * TS + lx;
+        if (y < im.H && x < im.W) {
+            const long long gp = im.pix_off + (long long)y * im.W + x;
+            n = zl.cnt[gp];
+            o = zl.off[gp];
+        }
+    }
+    int total;
+    const int ex = block_exclusive_scan(n, scratch, &total);
+    const bool staged = total <= CORR_CAP;
+    lc[threadIdx.x] = n;
+    loff[threadIdx.x] = o;
+    lst[threadIdx.x] = ex;
+    if (staged)
+        for (int j = 0; j < n; ++j) ent[ex + j] = zl.pairs[o + j];
+    __syncthreads();
+    return staged;
+}
+
+// FP32 filter correlation G_k[s] = sum_q z_k[q] r[q + s].  Each block owns a
+// fixed, strided set of tiles and a chunk of filters.  Waves take whole codes,
+// lanes the taps; the exact FP64 product of two floats is rounded to a 2^-40
+// fixed-point grid and added with an integer LDS atomic, so the block partial
+// does not depend on the order of the additions (deterministic).
+template <int MM>
+__global__ __launch_bounds__(TPB) void k_filter_corr_fix(const ImgInfo *imgs, const TileInfo *tiles, int n_tiles,
+                                                         int K, Lists zl, const float *__restrict__ r,
+                                                         float *__restrict__ partial, int KC) {
     constexpr int C = MM / 2, RW = TS + 2 * C, M = MM * MM;
     __shared__ float rr[RW * RW];
     __shared__ unsigned loff[TPB];
+    __shared__ int lst[TPB];
     __shared__ int lc[TPB];
+    __shared__ Pair ent[CORR_CAP];
+    __shared__ int scratch[TPB];
     extern __shared__ double gshm[];
-    ACC *Gp = reinterpret_cast<ACC *>(gshm);
+    unsigned long long *Gp = reinterpret_cast<unsigned long long *>(gshm);
     const int k0 = blockIdx.y * KC;
     const int k1 = min(K, k0 + KC);
-    for (int i = threadIdx.x; i < (k1 - k0) * M; i += TPB) Gp[i] = ACC(0);
+    for (int i = threadIdx.x; i < (k1 - k0) * M; i += TPB) Gp[i] = 0ull;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         __syncthreads();
         const TileInfo t = tiles[tile];
         const ImgInfo im = imgs[t.img];
-        const int oy = t.ty * TS - C, ox = t.tx * TS - C;
-        for (int i = threadIdx.x; i < RW * RW; i += TPB) {
-            const int gy = oy + i / RW, gx = ox + i % RW;
-            float v = 0.f;
-            if (gy >= 0 && gy < im.H && gx >= 0 && gx < im.W) {
-                const long long gp = im.pix_off + (long long)gy * im.W + gx;
-                v = r[gp];
-                if (FROM_X && W && !W[gp]) v = 0.f;
-            }
-            rr[i] = v;
-        }
-        {
-            const int ly = threadIdx.x / TS, lx = threadIdx.x % TS;
-            const int y = t.ty * TS + ly, x = t.tx * TS + lx;
-            int n = 0;
-            unsigned o = 0;
-            if (y < im.H && x < im.W) {
-                const long long gp = im.pix_off + (long long)y * im.W + x;
-                n = zl.cnt[gp];
-                o = zl.off[gp];
-            }
-            lc[threadIdx.x] = n;
-            loff[threadIdx.x] = o;
-        }
-        __syncthreads();
-        for (int px = 0; px < TPB; ++px) {
-            const int n = lc[px];
-            if (n == 0) continue;
-            const unsigned o = loff[px];
-            const int qy = px / TS, qx = px % TS;
-            for (int j = 0; j < n; ++j) {
-                const Pair e = zl.pairs[o + j];
-                if (e.k < k0 || e.k >= k1 || ((e.k - k0) & 3) != wave) continue;
-                const ACC v = (ACC)e.v;
-                ACC *row = Gp + (e.k - k0) * M;
+        const bool staged = corr_stage_tile<MM, false>(im, t, zl, r, nullptr, rr, loff, lst, lc, ent, scratch);
+        if (staged) {
+            // flat walk over the tile's codes; pixel of code e from the prefix lst
+            int px = 0;
+            const int total = lst[TPB - 1] + lc[TPB - 1];
+            for (int e = wave; e < total; e += TPB / 64) {
+                while (px + 1 < TPB && lst[px + 1] <= e) ++px;
+                const Pair en = ent[e];
+                if (en.k < k0 || en.k >= k1) continue;
+                const int qy = px / TS, qx = px % TS;
+                const double v = (double)en.v;
+                unsigned long long *row = Gp + (en.k - k0) * M;
                 for (int tt = lane; tt < M; tt += 64) {
                     const int sy = tt / MM - C, sx = tt % MM - C;
-                    row[tt] += v * (ACC)rr[(qy + C + sy) * RW + (qx + C + sx)];
+                    const double prod = v * (double)rr[(qy + C + sy) * RW + (qx + C + sx)];
+                    atomicAdd(row + tt, (unsigned long long)__double2ll_rn(prod * FIX_SCALE));
+                }
+            }
+        } else {
+            for (int px = wave; px < TPB; px += TPB / 64) {
+                const int cnt = lc[px];
+                const int qy = px / TS, qx = px % TS;
+                for (int j = 0; j < cnt; ++j) {
+                    const Pair en = zl.pairs[loff[px] + j];
+                    if (en.k < k0 || en.k >= k1) continue;
+                    const double v = (double)en.v;
+                    unsigned long long *row = Gp + (en.k - k0) * M;
+                    for (int tt = lane; tt < M; tt += 64) {
+                        const int sy = tt / MM - C, sx = tt % MM - C;
+                        const double prod = v * (double)rr[(qy + C + sy) * RW + (qx + C + sx)];
+                        atomicAdd(row + tt, (unsigned long long)__double2ll_rn(prod * FIX_SCALE));
+                    }
                 }
             }
         }
     }
     __syncthreads();
-    ACC *dst = partial + (long long)blockIdx.x * K * M + (long long)k0 * M;
+    float *dst = partial + (long long)blockIdx.x * K * M + (long long)k0 * M;
+    for (int i = threadIdx.x; i < (k1 - k0) * M; i += TPB) dst[i] = (float)((double)(long long)Gp[i] * FIX_INV);
+}
+
+// FP64 correlation with the observation-weighted image, Z^T (W x) for B of
+// eq. (7).  Wave w owns the filters k with (k - k0) % 4 == w and lane l the taps
+// l, l + 64, so every partial cell has one writer and a fixed order.
+template <int MM>
+__global__ __launch_bounds__(TPB) void k_filter_corr_x64(const ImgInfo *imgs, const TileInfo *tiles, int n_tiles,
+                                                         int K, Lists zl, const float *__restrict__ x,
+                                                         const unsigned char *__restrict__ W,
+                                                         double *__restrict__ partial, int KC) {
+    constexpr int C = MM / 2, RW = TS + 2 * C, M = MM * MM;
+    __shared__ float rr[RW * RW];
+    __shared__ unsigned loff[TPB];
+    __shared__ int lst[TPB];
+    __shared__ int lc[TPB];
+    __shared__ Pair ent[CORR_CAP];
+    __shared__ int scratch[TPB];
+    extern __shared__ double gshm[];
+    double *Gp = gshm;
+    const int k0 = blockIdx.y * KC;
+    const int k1 = min(K, k0 + KC);
+    for (int i = threadIdx.x; i < (k1 - k0) * M; i += TPB) Gp[i] = 0.0;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        __syncthreads();
+        const TileInfo t = tiles[tile];
+        const ImgInfo im = imgs[t.img];
+        const bool staged = corr_stage_tile<MM, true>(im, t, zl, x, W, rr, loff, lst, lc, ent, scratch);
+        for (int px = 0; px < TPB; ++px) {
+            const int cnt = lc[px];
+            if (cnt == 0) continue;
+            const int qy = px / TS, qx = px % TS;
+            for (int j = 0; j < cnt; ++j) {
+                const Pair e = staged ? ent[lst[px] + j] : zl.pairs[loff[px] + j];
+                if (e.k < k0 || e.k >= k1 || ((e.k - k0) & 3) != wave) continue;
+                const double v = (double)e.v;
+                double *row = Gp + (e.k - k0) * M;
+                for (int tt = lane; tt < M; tt += 64) {
+                    const int sy = tt / MM - C, sx = tt % MM - C;
+                    row[tt] += v * (double)rr[(qy + C + sy) * RW + (qx + C + sx)];
+                }
+            }
+        }
+    }
+    __syncthreads();
+    double *dst = partial + (long long)blockIdx.x * K * M + (long long)k0 * M;
     for (int i = threadIdx.x; i < (k1 - k0) * M; i += TPB) dst[i] = Gp[i];
 }
 
+// out[i] (+)= sum_b partial[b][i]: blocks of 16 elements x 16 slices; slice j
+// sums the partials b = j, j + 16, ... and the 16 slice sums are added in a
+// fixed order, so the result is deterministic.
 template <typename ACC>
-__global__ void k_reduce_partials(const ACC *__restrict__ partial, int nblocks, int n, ACC *__restrict__ out,
-                                  int accumulate) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+__global__ __launch_bounds__(256) void k_reduce_partials(const ACC *__restrict__ partial, int nblocks, int n,
+                                                         ACC *__restrict__ out, int accumulate) {
+    __shared__ ACC red[16][17];
+    const int e = threadIdx.x & 15, slice = threadIdx.x >> 4;
+    const int i = blockIdx.x * 16 + e;
     ACC s = ACC(0);
-    for (int b = 0; b < nblocks; ++b) s += partial[(long long)b * n + i];
-    out[i] = accumulate ? out[i] + s : s;
+    if (i < n)
+        for (int b = slice; b < nblocks; b += 16) s += partial[(long long)b * n + i];
+    red[slice][e] = s;
+    __syncthreads();
+    if (slice == 0 && i < n) {
+        ACC t = ACC(0);
+        for (int j = 0; j < 16; ++j) t += red[j][e];
+        out[i] = accumulate ? out[i] + t : t;
+    }
 }
 
 __global__ void k_fill(float *v, int n, float val) {
@@ -161,18 +266,6 @@ __global__ __launch_bounds__(128) void k_online_update(float *d, const double *y
     if (threadIdx.x < M) d[k * M + threadIdx.x] = (float)(nrm > 1.0 ? v / nrm : v);
 }
 
-// ---------------------------------------------------------------------------
-// Surrogate C_bar += sum_p W[p] w_p w_p^T, w_p the row of Z at pixel p (eq. 7).
-// Lag layout: entry ((k, s), (k2, s2)) sits in block (k, k2) at lag
-// delta = s - s2; a pair of non-zero codes (k, q, v), (k2, q2, v2) with
-// q2 - q = delta adds v v2 W[q + s] to every s of that lag whose pixel q + s
-// lies in the image, a contiguous run of the lag's row-major s rectangle.
-// Blocks own tiles of first codes; partner codes come from the tile grown by
-// 2c pixels, staged in LDS.  Lanes of a wave cover the s of one pair, so the
-// FP64 atomics of a pair hit consecutive addresses.
-// ---------------------------------------------------------------------------
-constexpr int SUR_CAP = 4096;
-
 __host__ __device__ __forceinline__ int lag_prefix(int a, int m) {
     // sum_{b = -(m-1)}^{a-1} (m - |b|)
     if (a <= 0) return (m + a - 1) * (m + a) / 2;
@@ -180,173 +273,29 @@ __host__ __device__ __forceinline__ int lag_prefix(int a, int m) {
 }
 
 template <int MM>
-__global__ __launch_bounds__(TPB) void k_surrogate_accumulate(const ImgInfo *imgs, const TileInfo *tiles, int K,
-                                                              Lists zl, const unsigned char *__restrict__ W,
-                                                              double *__restrict__ Cbar) {
-    constexpr int C = MM / 2, RW = TS + 4 * C, R = RW * RW, M = MM * MM, M2 = M * M;
-    constexpr int CH = (R + TPB - 1) / TPB;
-    __shared__ unsigned lgoff[R];
-    __shared__ int lstart[R];
-    __shared__ int lcnt[R];
-    __shared__ Pair lp[SUR_CAP];
-    __shared__ int scratch[TPB];
-    const TileInfo t = tiles[blockIdx.x];
-    const ImgInfo im = imgs[t.img];
-    const int oy = t.ty * TS - 2 * C, ox = t.tx * TS - 2 * C;
-    int mysum = 0;
-#pragma unroll
-    for (int j = 0; j < CH; ++j) {
-        const int i = threadIdx.x * CH + j;
-        if (i < R) {
-            const int gy = oy + i / RW, gx = ox + i % RW;
-            int n = 0;
-            unsigned o = 0;
-            if (gy >= 0 && gy < im.H && gx >= 0 && gx < im.W) {
-                const long long gp = im.pix_off + (long long)gy * im.W + gx;
-                n = zl.cnt[gp];
-                o = zl.off[gp];
-            }
-            lcnt[i] = n;
-            lgoff[i] = o;
-            mysum += n;
-        }
-    }
-    int total;
-    int ex = block_exclusive_scan(mysum, scratch, &total);
-    const bool staged = total <= SUR_CAP;
-#pragma unroll
-    for (int j = 0; j < CH; ++j) {
-        const int i = threadIdx.x * CH + j;
-        if (i < R) {
-            lstart[i] = ex;
-            if (staged)
-                for (int q = 0; q < lcnt[i]; ++q) lp[ex + q] = zl.pairs[lgoff[i] + q];
-            ex += lcnt[i];
-        }
-    }
-    __syncthreads();
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    int e_idx = 0;
-    for (int px = 0; px < TPB; ++px) {
-        const int ly = px / TS, lx = px % TS;
-        const int qy = t.ty * TS + ly, qx = t.tx * TS + lx;
-        if (qy >= im.H || qx >= im.W) continue;
-        const int ri = (ly + 2 * C) * RW + (lx + 2 * C);
-        const int n1 = lcnt[ri];
-        for (int a = 0; a < n1; ++a, ++e_idx) {
-            if ((e_idx & 3) != wave) continue;
-            const Pair e1 = staged ? lp[lstart[ri] + a] : zl.pairs[lgoff[ri] + a];
-            for (int dy = -2 * C; dy <= 2 * C; ++dy) {
-                const int wy = MM - (dy < 0 ? -dy : dy);
-                const int sylo = max(-C, dy - C);
-                for (int dx = -2 * C; dx <= 2 * C; ++dx) {
-                    const int rj = (ly + 2 * C + dy) * RW + (lx + 2 * C + dx);
-                    const int n2 = lcnt[rj];
-                    if (n2 == 0) continue;
-                    const int wx = MM - (dx < 0 ? -dx : dx);
-                    const int sxlo = max(-C, dx - C);
-                    const long long lag_off = (long long)lag_prefix(dy, MM) * M + (long long)wy * lag_prefix(dx, MM);
-                    const int nrect = wy * wx;
-                    for (int b = 0; b < n2; ++b) {
-                        const Pair e2 = staged ? lp[lstart[rj] + b] : zl.pairs[lgoff[rj] + b];
-                        const double vv = (double)e1.v * (double)e2.v;
-                        double *blk = Cbar + ((long long)e1.k * K + e2.k) * M2 + lag_off;
-                        for (int ti = lane; ti < nrect; ti += 64) {
-                            const int sy = sylo + ti / wx, sx = sxlo + ti % wx;
-                            const int py = qy + sy, pxx = qx + sx;
-                            if (py < 0 || py >= im.H || pxx < 0 || pxx >= im.W) continue;
-                            if (W && !W[im.pix_off + (long long)py * im.W + pxx]) continue;
-                            atomicAdd(blk + ti, vv);
-                        }
-                    }
-                }
-            }
-        }
-    }
-}
-
-// y = C_bar d in the lag layout.  Block (k, chunk of SMV_KB filters k2),
-// thread <-> tap s of row k; for each lag the valid threads read a contiguous
-// run of the block.  Partials over k2 chunks are reduced in a fixed order.
-constexpr int SMV_KB = 4;
-
-template <int MM>
-__global__ __launch_bounds__(128) void k_surrogate_matvec(int K, const double *__restrict__ Cbar,
-                                                          const float *__restrict__ d, double *__restrict__ partial) {
-    constexpr int C = MM / 2, M = MM * MM, M2 = M * M;
-    __shared__ double dl[SMV_KB * M];
-    const int k = blockIdx.x;
-    const int kc = blockIdx.y;
-    const int k2a = kc * SMV_KB, k2b = min(K, k2a + SMV_KB);
-    for (int i = threadIdx.x; i < (k2b - k2a) * M; i += 128) dl[i] = (double)d[(long long)k2a * M + i];
-    __syncthreads();
-    const int tt = threadIdx.x;
-    const bool active = tt < M;
-    const int sy = active ? tt / MM - C : 0, sx = active ? tt % MM - C : 0;
-    double acc = 0.0;
-    for (int k2 = k2a; k2 < k2b; ++k2) {
-        const double *blk = Cbar + ((long long)k * K + k2) * M2;
-        const double *dk = dl + (k2 - k2a) * M;
-        long long off = 0;
-        for (int dy = -(MM - 1); dy <= MM - 1; ++dy) {
-            const int wy = MM - (dy < 0 ? -dy : dy);
-            const int sylo = max(-C, dy - C), syhi = min(C, dy + C);
-            const bool rowok = active && sy >= sylo && sy <= syhi;
-            for (int dx = -(MM - 1); dx <= MM - 1; ++dx) {
-                const int wx = MM - (dx < 0 ? -dx : dx);
-                const int sxlo = max(-C, dx - C), sxhi = min(C, dx + C);
-                if (rowok && sx >= sxlo && sx <= sxhi) {
-                    const double c = blk[off + (sy - sylo) * wx + (sx - sxlo)];
-                    acc += c * dk[(sy - dy + C) * MM + (sx - dx + C)];
-                }
-                off += wy * wx;
-            }
-        }
-    }
-    if (active) partial[(long long)kc * K * M + (long long)k * M + tt] = acc;
-}
-
-template <int MM, typename ACC, bool FROM_X>
-hipError_t corr_impl(const Geometry &g, int K, Lists z, const float *r, const unsigned char *W, ACC *partial,
-                     int nblocks, hipStream_t s) {
-    constexpr int M = MM * MM;
-    int KC = (56 * 1024) / (M * (int)sizeof(ACC));
-    KC = KC / 4 * 4;
-    if (KC > K) KC = K;
-    const int nkc = (K + KC - 1) / KC;
-    const size_t shm = (size_t)KC * M * sizeof(ACC);
-    hipLaunchKernelGGL((k_filter_corr<MM, ACC, FROM_X>), dim3(nblocks, nkc), dim3(TPB), shm, s, g.d_img, g.d_tiles,
-                       g.n_tiles, K, z, r, W, partial, KC);
-    return hipGetLastError();
-}
-
-template <int MM>
 hipError_t corr_f32_impl(const Geometry &g, int K, Lists z, const float *r, float *partial, int nblocks,
                          hipStream_t s) {
-    return corr_impl<MM, float, false>(g, K, z, r, nullptr, partial, nblocks, s);
+    constexpr int M = MM * MM;
+    int KC = (96 * 1024) / (M * 8);
+    if (KC > K) KC = K;
+    const int nkc = (K + KC - 1) / KC;
+    const size_t shm = (size_t)KC * M * 8;
+    hipLaunchKernelGGL(k_filter_corr_fix<MM>, dim3(nblocks, nkc), dim3(TPB), shm, s, g.d_img, g.d_tiles, g.n_tiles,
+                       K, z, r, partial, KC);
+    return hipGetLastError();
 }
 
 template <int MM>
 hipError_t corr_f64_impl(const Geometry &g, int K, Lists z, const float *x, const unsigned char *W, double *partial,
                          int nblocks, hipStream_t s) {
-    return corr_impl<MM, double, true>(g, K, z, x, W, partial, nblocks, s);
-}
-
-template <int MM>
-hipError_t sur_acc_impl(const Geometry &g, int K, Lists z, const unsigned char *W, double *C, hipStream_t s) {
-    hipLaunchKernelGGL(k_surrogate_accumulate<MM>, dim3(g.n_tiles), dim3(TPB), 0, s, g.d_img, g.d_tiles, K, z, W, C);
-    return hipGetLastError();
-}
-
-template <int MM>
-hipError_t sur_mv_impl(int K, const double *C, const float *d, double *partial, double *y, hipStream_t s) {
     constexpr int M = MM * MM;
-    const int nkc = (K + SMV_KB - 1) / SMV_KB;
-    hipLaunchKernelGGL(k_surrogate_matvec<MM>, dim3(K, nkc), dim3(128), 0, s, K, C, d, partial);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    const int n = K * M;
-    hipLaunchKernelGGL(k_reduce_partials<double>, dim3((n + 255) / 256), dim3(256), 0, s, partial, nkc, n, y, 0);
+    int KC = (96 * 1024) / (M * 8);
+    KC = KC / 4 * 4;
+    if (KC > K) KC = K;
+    const int nkc = (K + KC - 1) / KC;
+    const size_t shm = (size_t)KC * M * 8;
+    hipLaunchKernelGGL(k_filter_corr_x64<MM>, dim3(nblocks, nkc), dim3(TPB), shm, s, g.d_img, g.d_tiles, g.n_tiles,
+                       K, z, x, W, partial, KC);
     return hipGetLastError();
 }
 
@@ -375,12 +324,12 @@ hipError_t launch_filter_corr_f64(const Geometry &g, int K, int m, Lists z, cons
 }
 
 hipError_t launch_reduce_partials_f32(const float *partial, int nblocks, int n, float *out, hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce_partials<float>, dim3((n + 255) / 256), dim3(256), 0, s, partial, nblocks, n, out, 0);
+    hipLaunchKernelGGL(k_reduce_partials<float>, dim3((n + 15) / 16), dim3(256), 0, s, partial, nblocks, n, out, 0);
     return hipGetLastError();
 }
 
 hipError_t launch_reduce_partials_f64_add(const double *partial, int nblocks, int n, double *inout, hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce_partials<double>, dim3((n + 255) / 256), dim3(256), 0, s, partial, nblocks, n, inout,
+    hipLaunchKernelGGL(k_reduce_partials<double>, dim3((n + 15) / 16), dim3(256), 0, s, partial, nblocks, n, inout,
                        1);
     return hipGetLastError();
 }
@@ -404,20 +353,6 @@ hipError_t launch_online_update(float *d, const double *y, const double *B, doub
                                 hipStream_t s) {
     hipLaunchKernelGGL(k_online_update, dim3(K), dim3(128), 0, s, d, y, B, Ld_sum, M);
     return hipGetLastError();
-}
-
-hipError_t launch_surrogate_accumulate(const Geometry &g, int K, int m, Lists z, const unsigned char *W, double *C,
-                                       hipStream_t s) {
-    SCSC_DISPATCH_M(m, sur_acc_impl, g, K, z, W, C, s);
-}
-
-long long surrogate_matvec_partial_elems(int K, int m) {
-    return (long long)((K + SMV_KB - 1) / SMV_KB) * K * m * m;
-}
-
-hipError_t launch_surrogate_matvec(int K, int m, const double *C, const float *d, double *partial, double *y,
-                                   hipStream_t s) {
-    SCSC_DISPATCH_M(m, sur_mv_impl, K, C, d, partial, y, s);
 }
 
 }  // namespace scsc

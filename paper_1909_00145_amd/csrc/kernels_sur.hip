@@ -1,0 +1,576 @@
+// Online surrogate kernels for gfx950 (eqs. 7-8), FP64:
+//   C_bar += sum_n Z_n^T W_n Z_n   and   y = C_bar d.
+//
+// Entry ((k, s), (k2, s2)) of Z^T W Z is sum_p W[p] z_k[p - s] z_k2[p - s2], p over
+// the image.  With z zero outside the image and no observation mask it equals
+//     R(delta) - E(delta, s),      delta = s - s2,
+// where R(delta) = sum_q z_k[q] z_k2[q + delta] sums every pair of codes at lag
+// delta, and E sums the same products over the output pixels p outside the
+// image (a ring of width c).  Splitting the ring into its top and bottom rows
+// (all columns) and left and right columns (all rows) double counts its four
+// c x c corners, so
+//     E = E_top(delta, s_y) + E_bottom(delta, s_y) + E_left(delta, s_x)
+//         + E_right(delta, s_x) - E_corners(delta, s),
+// and each side term is a prefix sum over the first (last) c rows (columns) of
+// the image of the lag sums restricted to codes in that row (column).  The lag
+// sums are accumulated by workgroups that own one filter k and 64 lags (lane ->
+// lag, wave -> code), the corner term exactly from the corner ring pixels.
+// With an observation mask the masked pixels are excluded as well; that case
+// uses a tiled kernel that enumerates every excluded pixel.
+#include "scsc_internal.h"
+
+namespace scsc {
+
+namespace {
+
+__host__ __device__ __forceinline__ int lagp(int a, int m) {
+    // sum_{b = -(m-1)}^{a-1} (m - |b|)
+    if (a <= 0) return (m + a - 1) * (m + a) / 2;
+    return m * (m - 1) / 2 + a * m - a * (a - 1) / 2;
+}
+
+// ---- per-filter row lists ---------------------------------------------------
+// fm_cnt[k * R + r] = number of non-zero codes of filter k in global row r.
+__global__ __launch_bounds__(256) void k_fm_count(const ImgInfo *imgs, const int *row_img, Lists zl, int R,
+                                                  unsigned *fm_cnt) {
+    const int r = blockIdx.x;
+    const ImgInfo im = imgs[row_img[r]];
+    const int y = r - im.row_off;
+    const long long gp0 = im.pix_off + (long long)y * im.W;
+    for (int x = threadIdx.x; x < im.W; x += 256) {
+        const long long gp = gp0 + x;
+        const unsigned o = zl.off[gp];
+        const int n = zl.cnt[gp];
+        for (int j = 0; j < n; ++j) atomicAdd(&fm_cnt[(long long)zl.pairs[o + j].k * R + r], 1u);
+    }
+}
+
+constexpr int FM_CAP = 4096;
+
+// Row r's entries, regrouped by filter in x order: fm[fm_off[k * R + r] + j] = (y << 16 | x, v).
+// Requires the pixel lists of the row to be contiguous (exact-capacity lists).
+__global__ __launch_bounds__(256) void k_fm_fill(const ImgInfo *imgs, const int *row_img, Lists zl, int R, int K,
+                                                 const unsigned *fm_off, uint2 *fm) {
+    __shared__ Pair ent[FM_CAP];
+    __shared__ unsigned short ex[FM_CAP];
+    const int r = blockIdx.x;
+    const ImgInfo im = imgs[row_img[r]];
+    const int y = r - im.row_off;
+    const long long gp0 = im.pix_off + (long long)y * im.W;
+    const unsigned base = zl.off[gp0];
+    const unsigned total = zl.off[gp0 + im.W] - base;
+    const bool staged = total <= FM_CAP;
+    if (staged) {
+        for (int x = threadIdx.x; x < im.W; x += 256) {
+            const long long gp = gp0 + x;
+            const unsigned o = zl.off[gp];
+            const int n = zl.cnt[gp];
+            for (int j = 0; j < n; ++j) {
+                ent[o - base + j] = zl.pairs[o + j];
+                ex[o - base + j] = (unsigned short)x;
+            }
+        }
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < K; k += 256) {
+        unsigned w = fm_off[(long long)k * R + r];
+        if (staged) {
+            for (unsigned e = 0; e < total; ++e) {
+                const Pair p = ent[e];
+                if (p.k == k) fm[w++] = make_uint2(((unsigned)y << 16) | ex[e], __float_as_uint(p.v));
+            }
+        } else {
+            for (int x = 0; x < im.W; ++x) {
+                const long long gp = gp0 + x;
+                const unsigned o = zl.off[gp];
+                const int n = zl.cnt[gp];
+                for (int j = 0; j < n; ++j) {
+                    const Pair p = zl.pairs[o + j];
+                    if (p.k == k) fm[w++] = make_uint2(((unsigned)y << 16) | (unsigned)x, __float_as_uint(p.v));
+                }
+            }
+        }
+    }
+}
+
+// ---- block accumulation -----------------------------------------------------
+// With z zero outside the image, entry ((k, s), (k2, s2)) of the batch term is
+//     R(delta) - E(delta, s),   delta = s - s2,
+// where R(delta) = sum_q z_k[q] z_k2[q + delta] is the full-lag sum over every
+// pair of codes, and E(delta, s) = sum_{p excluded} z_k[p - s] z_k2[p - s2] runs
+// over the output pixels the objective does not contain: the ring of width c
+// around the image and, with an observation mask, the masked pixels.  Both are
+// accumulated per image tile of SB_TQ x SB_TQ code positions from dense planes
+// of the two filters' codes on the tile grown by 2c, with per-row occupancy
+// bitmasks to enumerate partners.  Every pair costs one FP64 LDS atomic.
+constexpr int SB_THREADS = 512;
+constexpr int SB_TQ = 32;
+
+template <int MM>
+__global__ __launch_bounds__(SB_THREADS) void k_sur_block(const ImgInfo *imgs, int n_img, int K, int R,
+                                                          const unsigned *__restrict__ fm_off,
+                                                          const uint2 *__restrict__ fm,
+                                                          const unsigned char *__restrict__ W,
+                                                          double *__restrict__ Cbar) {
+    constexpr int C = MM / 2, M = MM * MM, M2 = M * M, L = 2 * MM - 1;
+    constexpr int PW = SB_TQ + 4 * C;  // region side (<= 64: one 64-bit mask per row)
+    constexpr int XW = SB_TQ + 2 * C;  // side of the tile grown by c
+    static_assert(PW <= 64, "region rows must fit a 64-bit mask");
+    __shared__ double Cb[M2];                    // -E, lag layout
+    __shared__ double Rb[L * L];                 // R per lag
+    __shared__ float pl[2][PW * PW];             // code planes of k and k2 on the region
+    __shared__ unsigned long long bm[2][PW];     // row occupancy of the planes
+    __shared__ unsigned short el[SB_TQ * SB_TQ]; // codes of k inside the tile (region index)
+    __shared__ int nel;
+    const int k = blockIdx.y, k2 = blockIdx.x;
+    if (k2 < k) return;
+    for (int i = threadIdx.x; i < M2; i += SB_THREADS) Cb[i] = 0.0;
+    for (int i = threadIdx.x; i < L * L; i += SB_THREADS) Rb[i] = 0.0;
+    const int f2[2] = {k, k2};
+    for (int n = 0; n < n_img; ++n) {
+        const ImgInfo im = imgs[n];
+        const unsigned a = fm_off[(long long)k * R + im.row_off];
+        const unsigned b = fm_off[(long long)k * R + im.row_off + im.H];
+        const unsigned a2 = fm_off[(long long)k2 * R + im.row_off];
+        const unsigned b2 = fm_off[(long long)k2 * R + im.row_off + im.H];
+        if (a == b || a2 == b2) continue;  // no pair in this image
+        for (int y0 = 0; y0 < im.H; y0 += SB_TQ) {
+            for (int x0 = 0; x0 < im.W; x0 += SB_TQ) {
+                const int ry0 = y0 - 2 * C, rx0 = x0 - 2 * C;  // region origin
+                __syncthreads();
+                for (int i = threadIdx.x; i < 2 * PW * PW; i += SB_THREADS) (&pl[0][0])[i] = 0.f;
+                if (threadIdx.x < 2 * PW) (&bm[0][0])[threadIdx.x] = 0ull;
+                if (threadIdx.x == 0) nel = 0;
+                __syncthreads();
+                // planes: one thread per (filter, region row) scans that row's list
+                if (threadIdx.x < 2 * PW) {
+                    const int f = threadIdx.x / PW, rr = threadIdx.x % PW;
+                    const int gy = ry0 + rr;
+                    if (gy >= 0 && gy < im.H) {
+                        const long long row = (long long)f2[f] * R + im.row_off + gy;
+                        const unsigned j1 = fm_off[row + 1];
+                        unsigned long long bits = 0;
+                        for (unsigned j = fm_off[row]; j < j1; ++j) {
+                            const uint2 e = fm[j];
+                            const int c = (int)(e.x & 0xFFFFu) - rx0;
+                            if (c < 0) continue;
+                            if (c >= PW) break;
+                            pl[f][rr * PW + c] = __uint_as_float(e.y);
+                            bits |= 1ull << c;
+                        }
+                        bm[f][rr] = bits;
+                    }
+                }
+                __syncthreads();
+                // codes of k inside the tile
+                if (threadIdx.x < SB_TQ) {
+                    const int rr = 2 * C + threadIdx.x;
+                    unsigned long long bits = (bm[0][rr] >> (2 * C)) & ((1ull << SB_TQ) - 1ull);
+                    if (bits) {
+                        int pos = atomicAdd(&nel, __popcll(bits));
+                        while (bits) {
+                            const int c = __ffsll((long long)bits) - 1;
+                            bits &= bits - 1ull;
+                            el[pos++] = (unsigned short)(rr * PW + 2 * C + c);
+                        }
+                    }
+                }
+                __syncthreads();
+                // R: every pair (q in tile, q + delta anywhere)
+                for (int e = threadIdx.x; e < nel; e += SB_THREADS) {
+                    const int ri = el[e];
+                    const int ry = ri / PW, rx = ri % PW;
+                    const double v = (double)pl[0][ri];
+#pragma unroll
+                    for (int dy = -2 * C; dy <= 2 * C; ++dy) {
+                        unsigned long long bits = (bm[1][ry + dy] >> (rx - 2 * C)) & ((1ull << L) - 1ull);
+                        while (bits) {
+                            const int bx = __ffsll((long long)bits) - 1;
+                            bits &= bits - 1ull;
+                            const double v2 = (double)pl[1][(ry + dy) * PW + rx - 2 * C + bx];
+                            atomicAdd(&Rb[(dy + 2 * C) * L + bx], v * v2);
+                        }
+                    }
+                }
+                // E: excluded output pixels owned by this tile (ring pixels whose
+                // clamped position lies in the tile; masked pixels of the tile)
+                for (int idx = threadIdx.x; idx < XW * XW; idx += SB_THREADS) {
+                    const int py_r = C + idx / XW, px_r = C + idx % XW;
+                    const int py = ry0 + py_r, px = rx0 + px_r;
+                    const bool inside = py >= 0 && py < im.H && px >= 0 && px < im.W;
+                    bool excluded;
+                    if (inside) {
+                        excluded = W && py >= y0 && py < y0 + SB_TQ && px >= x0 && px < x0 + SB_TQ &&
+                                   !W[im.pix_off + (long long)py * im.W + px];
+                    } else {
+                        const int cy = min(max(py, 0), im.H - 1), cx = min(max(px, 0), im.W - 1);
+                        excluded = cy >= y0 && cy < y0 + SB_TQ && cx >= x0 && cx < x0 + SB_TQ &&
+                                   py >= -C && py < im.H + C && px >= -C && px < im.W + C;
+                    }
+                    if (!excluded) continue;
+                    // codes of k and k2 in the window p + [-c, c]^2
+                    for (int wa = -C; wa <= C; ++wa) {
+                        unsigned long long ba = (bm[0][py_r + wa] >> (px_r - C)) & ((1ull << MM) - 1ull);
+                        while (ba) {
+                            const int ca = __ffsll((long long)ba) - 1;
+                            ba &= ba - 1ull;
+                            // code a at region (py_r + wa, px_r - C + ca): s = p - q_a
+                            const int sy = -wa, sx = C - ca;
+                            const double va = (double)pl[0][(py_r + wa) * PW + px_r - C + ca];
+                            for (int wb = -C; wb <= C; ++wb) {
+                                unsigned long long bb = (bm[1][py_r + wb] >> (px_r - C)) & ((1ull << MM) - 1ull);
+                                while (bb) {
+                                    const int cb = __ffsll((long long)bb) - 1;
+                                    bb &= bb - 1ull;
+                                    const int sy2 = -wb, sx2 = C - cb;
+                                    const double vb = (double)pl[1][(py_r + wb) * PW + px_r - C + cb];
+                                    const int dy = sy - sy2, dx = sx - sx2;
+                                    const int wx = MM - (dx < 0 ? -dx : dx);
+                                    const int sylo = max(-C, dy - C), sxlo = max(-C, dx - C);
+                                    const int wy = MM - (dy < 0 ? -dy : dy);
+                                    const int off = lagp(dy, MM) * M + wy * lagp(dx, MM);
+                                    atomicAdd(&Cb[off + (sy - sylo) * wx + (sx - sxlo)], -va * vb);
+                                }
+                            }
+                        }
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    // C_bar(k, k2) += R + (-E); C_bar(k2, k) gets the transpose, which in the
+    // lag layout is the same run under lag -delta.
+    double *blk = Cbar + ((long long)k * K + k2) * M2;
+    double *blkT = Cbar + ((long long)k2 * K + k) * M2;
+    const int slot = threadIdx.x / 128, t = threadIdx.x % 128;
+    for (int di = slot; di < L * L; di += SB_THREADS / 128) {
+        const int dy = di / L - (MM - 1), dx = di % L - (MM - 1);
+        const int wy = MM - (dy < 0 ? -dy : dy), wx = MM - (dx < 0 ? -dx : dx);
+        if (t >= wy * wx) continue;
+        const int off = lagp(dy, MM) * M + wy * lagp(dx, MM);
+        const double val = Cb[off + t] + Rb[di];
+        blk[off + t] += val;
+        if (k2 != k) {
+            const int offT = lagp(-dy, MM) * M + wy * lagp(-dx, MM);
+            blkT[offT + t] += val;
+        }
+    }
+}
+
+// ---- lag sums: R and the side terms --------------------------------------------
+constexpr int LG_THREADS = 512;
+constexpr int LG_DC = 64;   // lags per workgroup (one per lane)
+constexpr int LG_KB = 96;   // partner filters per workgroup (lag sums R)
+constexpr int LG_KB_SIDE = 32;  // partner filters per workgroup (band sums: c accumulators per lag)
+
+// Rout[k][k2][lag] = sum over codes (k, q) of the batch of z_k[q] z_k2[q + delta] for k2 >= k.
+// side < 0: every code; side 0..3 (top, bottom, left, right): only codes in the
+// first / last c rows / columns of their image, split by that row (column)
+// index j into Rout[(side * c + j)][k][k2][lag].
+template <int MM>
+__global__ __launch_bounds__(LG_THREADS) void k_sur_lag(const ImgInfo *imgs, int n_img, int K, int R,
+                                                        const unsigned *__restrict__ fm_off,
+                                                        const uint2 *__restrict__ fm, Lists zl, int side, int KB,
+                                                        double *__restrict__ Rout) {
+    constexpr int C = MM / 2, L = 2 * MM - 1, LL = L * L;
+    constexpr int NJ = C > 0 ? C : 1;
+    extern __shared__ double acc[];  // [nj][KB][LG_DC]
+    const int dc = blockIdx.x, k = blockIdx.y;
+    const int k2lo = blockIdx.z * KB, k2hi = min(K, k2lo + KB);
+    if (k2hi <= k) return;
+    const int nj = side < 0 ? 1 : NJ;
+    for (int i = threadIdx.x; i < nj * KB * LG_DC; i += LG_THREADS) acc[i] = 0.0;
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int di = dc * LG_DC + lane;
+    const bool active = di < LL;
+    const int dy = di / L - 2 * C, dx = di % L - 2 * C;
+    for (int n = 0; n < n_img; ++n) {
+        const ImgInfo im = imgs[n];
+        int ya = 0, yb = im.H;
+        if (side == 0) yb = min(C, im.H);
+        if (side == 1) ya = max(0, im.H - C);
+        const unsigned a = fm_off[(long long)k * R + im.row_off + ya];
+        const unsigned b = fm_off[(long long)k * R + im.row_off + yb];
+        for (unsigned e = a + wave; e < b; e += LG_THREADS / 64) {
+            const uint2 en = fm[e];
+            const int y = (int)(en.x >> 16), x = (int)(en.x & 0xFFFFu);
+            int j = 0;
+            if (side == 0) j = y;
+            else if (side == 1) j = im.H - 1 - y;
+            else if (side == 2) j = x;
+            else if (side == 3) j = im.W - 1 - x;
+            if (side >= 2 && j >= C) continue;  // not in the band (uniform per wave)
+            if (!active) continue;
+            const int y2 = y + dy, x2 = x + dx;
+            if (y2 < 0 || y2 >= im.H || x2 < 0 || x2 >= im.W) continue;
+            const double v = (double)__uint_as_float(en.y);
+            const long long gp = im.pix_off + (long long)y2 * im.W + x2;
+            const unsigned o = zl.off[gp];
+            const int c = zl.cnt[gp];
+            double *row = acc + (long long)j * KB * LG_DC + lane;
+            for (int t = 0; t < c; ++t) {
+                const Pair p2 = zl.pairs[o + t];
+                if (p2.k < k2lo || p2.k >= k2hi || p2.k < k) continue;
+                atomicAdd(row + (p2.k - k2lo) * LG_DC, v * (double)p2.v);
+            }
+        }
+    }
+    __syncthreads();
+    if (!active) return;
+    for (int jj = 0; jj < nj; ++jj) {
+        const int cls = side < 0 ? 0 : side * C + jj;
+        for (int k2 = max(k, k2lo); k2 < k2hi; ++k2)
+            Rout[(((long long)cls * K + k) * K + k2) * LL + di] = acc[((long long)jj * KB + (k2 - k2lo)) * LG_DC + lane];
+    }
+}
+
+// C_bar(k, k2) += R - E_top - E_bottom - E_left - E_right (and the transpose into
+// C_bar(k2, k)); Es holds the per-row / per-column lag sums of the bands,
+// Es[(side * c + j)][k][k2][lag].
+template <int MM>
+__global__ __launch_bounds__(256) void k_sur_expand(int K, const double *__restrict__ Rl,
+                                                    const double *__restrict__ Es, double *__restrict__ Cbar) {
+    constexpr int C = MM / 2, M = MM * MM, M2 = M * M, L = 2 * MM - 1, LL = L * L;
+    __shared__ double r[LL];
+    __shared__ double es[4 * (C > 0 ? C : 1)][LL];
+    const int k = blockIdx.y, k2 = blockIdx.x;
+    if (k2 < k) return;
+    for (int i = threadIdx.x; i < LL; i += 256) r[i] = Rl[((long long)k * K + k2) * LL + i];
+    for (int i = threadIdx.x; i < 4 * C * LL; i += 256) {
+        const int cls = i / LL, di = i % LL;
+        es[cls][di] = Es[(((long long)cls * K + k) * K + k2) * LL + di];
+    }
+    __syncthreads();
+    double *blk = Cbar + ((long long)k * K + k2) * M2;
+    double *blkT = Cbar + ((long long)k2 * K + k) * M2;
+    const int slot = threadIdx.x / 128, t = threadIdx.x % 128;
+    for (int di = slot; di < LL; di += 2) {
+        const int dy = di / L - (MM - 1), dx = di % L - (MM - 1);
+        const int wy = MM - (dy < 0 ? -dy : dy), wx = MM - (dx < 0 ? -dx : dx);
+        if (t >= wy * wx) continue;
+        const int sy = max(-C, dy - C) + t / wx, sx = max(-C, dx - C) + t % wx;
+        double val = r[di];
+        for (int j = 0; j < -sy; ++j) val -= es[0 * C + j][di];  // top rows a < -s_y
+        for (int j = 0; j < sy; ++j) val -= es[1 * C + j][di];   // bottom rows H-1-a < s_y
+        for (int j = 0; j < -sx; ++j) val -= es[2 * C + j][di];  // left columns
+        for (int j = 0; j < sx; ++j) val -= es[3 * C + j][di];   // right columns
+        const int off = lagp(dy, MM) * M + wy * lagp(dx, MM);
+        blk[off + t] += val;
+        if (k2 != k) blkT[lagp(-dy, MM) * M + wy * lagp(-dx, MM) + t] += val;
+    }
+}
+
+// E_corners: the ring pixels p in the four c x c corner blocks outside an image
+// were subtracted twice; add back the products of all pairs of codes in their
+// windows (at most c x c image pixels each).  One workgroup per (image, corner),
+// threads over pairs of window pixels; FP64 atomics into C_bar.
+template <int MM>
+__global__ __launch_bounds__(256) void k_sur_corner(const ImgInfo *imgs, int K, Lists zl, double *__restrict__ Cbar) {
+    constexpr int C = MM / 2, M = MM * MM, M2 = M * M;
+    __shared__ int cq[M];     // window pixels inside the image (tap index s = p - q)
+    __shared__ long long cg[M];
+    __shared__ int ncell;
+    const ImgInfo im = imgs[blockIdx.x];
+    const int corner = blockIdx.y;
+    for (int ring = 0; ring < C * C; ++ring) {
+        const int i = ring / C + 1, j = ring % C + 1;
+        const int py = (corner & 1) ? im.H - 1 + i : -i;
+        const int px = (corner & 2) ? im.W - 1 + j : -j;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int n = 0;
+            for (int t = 0; t < M; ++t) {
+                const int qy = py - (t / MM - C), qx = px - (t % MM - C);  // q = p - s
+                if (qy < 0 || qy >= im.H || qx < 0 || qx >= im.W) continue;
+                cq[n] = t;
+                cg[n] = im.pix_off + (long long)qy * im.W + qx;
+                ++n;
+            }
+            ncell = n;
+        }
+        __syncthreads();
+        const int n = ncell;
+        for (int pi = threadIdx.x; pi < n * n; pi += 256) {
+            const int a = pi / n, b = pi % n;
+            const int sa = cq[a], sb = cq[b];
+            const int say = sa / MM - C, sax = sa % MM - C, sby = sb / MM - C, sbx = sb % MM - C;
+            const int dy = say - sby, dx = sax - sbx;
+            const int wy = MM - (dy < 0 ? -dy : dy), wx = MM - (dx < 0 ? -dx : dx);
+            const int sylo = max(-C, dy - C), sxlo = max(-C, dx - C);
+            const long long within = (long long)lagp(dy, MM) * M + wy * lagp(dx, MM) + (say - sylo) * wx + (sax - sxlo);
+            const int ca = zl.cnt[cg[a]], cb = zl.cnt[cg[b]];
+            const unsigned oa = zl.off[cg[a]], ob = zl.off[cg[b]];
+            for (int u = 0; u < ca; ++u) {
+                const Pair ea = zl.pairs[oa + u];
+                for (int w = 0; w < cb; ++w) {
+                    const Pair eb = zl.pairs[ob + w];
+                    atomicAdd(Cbar + ((long long)ea.k * K + eb.k) * M2 + within, (double)ea.v * (double)eb.v);
+                }
+            }
+        }
+    }
+}
+
+// ---- y = C_bar d using the symmetric half --------------------------------------
+// Block (k, k2 >= k) streams its lag-layout block once: thread t plays tap s = t
+// of row k (y_k += C(k,k2) d_k2) and tap s2 = t of row k2 (y_k2 += C(k,k2)^T d_k),
+// walking the lags in a fixed order, so the result is deterministic.  Partials
+// are reduced per row in a fixed order.
+constexpr int MV_THREADS = 128;
+
+template <int MM>
+__global__ __launch_bounds__(MV_THREADS) void k_sur_matvec(int K, const double *__restrict__ Cbar,
+                                                           const float *__restrict__ d, double *__restrict__ part) {
+    constexpr int C = MM / 2, M = MM * MM, M2 = M * M;
+    __shared__ double da[M], db[M];
+    const int k = blockIdx.y, k2 = blockIdx.x;
+    if (k2 < k) return;
+    for (int i = threadIdx.x; i < M; i += MV_THREADS) {
+        da[i] = (double)d[(long long)k * M + i];
+        db[i] = (double)d[(long long)k2 * M + i];
+    }
+    __syncthreads();
+    const double *blk = Cbar + ((long long)k * K + k2) * M2;
+    const int t = threadIdx.x;
+    const bool active = t < M;
+    const int ty = active ? t / MM - C : 0, tx = active ? t % MM - C : 0;
+    const bool both = k2 != k;
+    double ya = 0.0, yb = 0.0;
+    int off = 0;
+    for (int dy = -(MM - 1); dy <= MM - 1; ++dy) {
+        const int wy = MM - (dy < 0 ? -dy : dy);
+        const int sylo = max(-C, dy - C), syhi = min(C, dy + C);
+#pragma unroll 3
+        for (int dx = -(MM - 1); dx <= MM - 1; ++dx) {
+            const int wx = MM - (dx < 0 ? -dx : dx);
+            const int sxlo = max(-C, dx - C), sxhi = min(C, dx + C);
+            if (active) {
+                // row role: s = t, s2 = t - delta
+                if (ty >= sylo && ty <= syhi && tx >= sxlo && tx <= sxhi)
+                    ya += blk[off + (ty - sylo) * wx + (tx - sxlo)] * db[(ty - dy + C) * MM + (tx - dx + C)];
+                // column role: s2 = t, s = t + delta
+                const int uy = ty + dy, ux = tx + dx;
+                if (both && uy >= sylo && uy <= syhi && ux >= sxlo && ux <= sxhi)
+                    yb += blk[off + (uy - sylo) * wx + (ux - sxlo)] * da[(uy + C) * MM + (ux + C)];
+            }
+            off += wy * wx;
+        }
+    }
+    // part layout: [k][k2][2][M]
+    if (active) {
+        double *pp = part + (((long long)k * K + k2) * 2) * M;
+        pp[t] = ya;
+        pp[M + t] = yb;
+    }
+}
+
+// y[k] = sum_{k2 >= k} part[k][k2][0] + sum_{k1 < k} part[k1][k][1], fixed order.
+__global__ void k_sur_matvec_reduce(int K, int M, const double *__restrict__ part, double *__restrict__ y) {
+    const int k = blockIdx.x;
+    for (int i = threadIdx.x; i < M; i += blockDim.x) {
+        double s = 0.0;
+        for (int k1 = 0; k1 < k; ++k1) s += part[(((long long)k1 * K + k) * 2 + 1) * M + i];
+        for (int k2 = k; k2 < K; ++k2) s += part[(((long long)k * K + k2) * 2) * M + i];
+        y[(long long)k * M + i] = s;
+    }
+}
+
+template <int MM>
+hipError_t sur_block_impl(const Geometry &g, int K, int R, const unsigned *fm_off, const uint2 *fm,
+                          const unsigned char *W, double *C, hipStream_t s) {
+    hipLaunchKernelGGL(k_sur_block<MM>, dim3(K, K), dim3(SB_THREADS), 0, s, g.d_img, g.n_img, K, R, fm_off, fm, W, C);
+    return hipGetLastError();
+}
+
+template <int MM>
+hipError_t sur_mv_impl(int K, const double *C, const float *d, double *part, double *y, hipStream_t s) {
+    hipLaunchKernelGGL(k_sur_matvec<MM>, dim3(K, K), dim3(MV_THREADS), 0, s, K, C, d, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sur_matvec_reduce, dim3(K), dim3(128), 0, s, K, MM * MM, part, y);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_fm_lists(const Geometry &g, int K, Lists z, unsigned *fm_cnt, unsigned *fm_off, uint2 *fm,
+                           unsigned long long *scan_tmp, unsigned long long *total64, hipStream_t s) {
+    const int R = g.n_rows;
+    hipError_t e = hipMemsetAsync(fm_cnt, 0, sizeof(unsigned) * (size_t)K * R, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_fm_count, dim3(R), dim3(256), 0, s, g.d_img, g.d_row_img, z, R, fm_cnt);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = launch_scan(fm_cnt, fm_off, (long long)K * R, scan_tmp, total64, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_fm_fill, dim3(R), dim3(256), 0, s, g.d_img, g.d_row_img, z, R, K, fm_off, fm);
+    return hipGetLastError();
+}
+
+hipError_t launch_surrogate_blocks(const Geometry &g, int K, int m, const unsigned *fm_off, const uint2 *fm,
+                                   const unsigned char *W, double *C, hipStream_t s) {
+    const int R = g.n_rows;
+    switch (m) {
+        case 3: return sur_block_impl<3>(g, K, R, fm_off, fm, W, C, s);
+        case 5: return sur_block_impl<5>(g, K, R, fm_off, fm, W, C, s);
+        case 7: return sur_block_impl<7>(g, K, R, fm_off, fm, W, C, s);
+        case 9: return sur_block_impl<9>(g, K, R, fm_off, fm, W, C, s);
+        case 11: return sur_block_impl<11>(g, K, R, fm_off, fm, W, C, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+long long surrogate_matvec_partial_elems(int K, int m) { return (long long)K * K * 2 * m * m; }
+
+long long surrogate_lag_elems(int K, int m) { return (long long)K * K * (2 * m - 1) * (2 * m - 1); }
+
+namespace {
+template <int MM>
+hipError_t sur_unmasked_impl(const Geometry &g, int K, Lists z, const unsigned *fm_off, const uint2 *fm, double *Rl,
+                             double *Es, double *C, hipStream_t s) {
+    constexpr int Cc = MM / 2, L = 2 * MM - 1, LL = L * L;
+    const int R = g.n_rows;
+    const int ndc = (LL + LG_DC - 1) / LG_DC, nkb = (K + LG_KB - 1) / LG_KB;
+    hipLaunchKernelGGL(k_sur_lag<MM>, dim3(ndc, K, nkb), dim3(LG_THREADS), sizeof(double) * LG_KB * LG_DC, s, g.d_img,
+                       g.n_img, K, R, fm_off, fm, z, -1, LG_KB, Rl);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int nkbs = (K + LG_KB_SIDE - 1) / LG_KB_SIDE;
+    for (int side = 0; side < 4 && Cc > 0; ++side) {
+        hipLaunchKernelGGL(k_sur_lag<MM>, dim3(ndc, K, nkbs), dim3(LG_THREADS),
+                           sizeof(double) * Cc * LG_KB_SIDE * LG_DC, s, g.d_img, g.n_img, K, R, fm_off, fm, z, side,
+                           LG_KB_SIDE, Es);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_sur_expand<MM>, dim3(K, K), dim3(256), 0, s, K, Rl, Es, C);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sur_corner<MM>, dim3(g.n_img, 4), dim3(256), 0, s, g.d_img, K, z, C);
+    return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_surrogate_unmasked(const Geometry &g, int K, int m, Lists z, const unsigned *fm_off, const uint2 *fm,
+                                     double *Rl, double *Es, double *C, hipStream_t s) {
+    switch (m) {
+        case 3: return sur_unmasked_impl<3>(g, K, z, fm_off, fm, Rl, Es, C, s);
+        case 5: return sur_unmasked_impl<5>(g, K, z, fm_off, fm, Rl, Es, C, s);
+        case 7: return sur_unmasked_impl<7>(g, K, z, fm_off, fm, Rl, Es, C, s);
+        case 9: return sur_unmasked_impl<9>(g, K, z, fm_off, fm, Rl, Es, C, s);
+        case 11: return sur_unmasked_impl<11>(g, K, z, fm_off, fm, Rl, Es, C, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_surrogate_matvec(int K, int m, const double *C, const float *d, double *partial, double *y,
+                                   hipStream_t s) {
+    switch (m) {
+        case 3: return sur_mv_impl<3>(K, C, d, partial, y, s);
+        case 5: return sur_mv_impl<5>(K, C, d, partial, y, s);
+        case 7: return sur_mv_impl<7>(K, C, d, partial, y, s);
+        case 9: return sur_mv_impl<9>(K, C, d, partial, y, s);
+        case 11: return sur_mv_impl<11>(K, C, d, partial, y, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace scsc

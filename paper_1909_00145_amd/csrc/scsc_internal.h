@@ -27,6 +27,8 @@ struct ImgInfo {
     int tiles_x, tiles_y;
     int tile_off;
     int index;          // image index used by the sampler
+    int row_off;        // first row of the image in the global row numbering
+    int pad;
 };
 
 struct TileInfo {
@@ -46,8 +48,10 @@ struct Geometry {
     int n_tiles = 0;
     long long n_pix = 0;
     int max_side = 0;
+    int n_rows = 0;  // sum of image heights
     ImgInfo *d_img = nullptr;
     TileInfo *d_tiles = nullptr;
+    int *d_row_img = nullptr;  // image of every global row
     std::vector<ImgInfo> h_img;
     std::vector<TileInfo> h_tiles;
 };
@@ -161,9 +165,16 @@ hipError_t launch_batch_update(float *d, const float *G, const double *lam, int 
 // d_k <- P(d_k - (y_k - B_k) / Ld_sum).
 hipError_t launch_online_update(float *d, const double *y, const double *B, double Ld_sum, int K, int M,
                                 hipStream_t s);
-// Surrogates (lag layout): C += sum Z^T W Z, and y = C d.
-hipError_t launch_surrogate_accumulate(const Geometry &g, int K, int m, Lists z, const unsigned char *W,
-                                       double *C, hipStream_t s);
+// Surrogates (lag layout).  Per-filter row lists of the non-zero codes (from
+// exact-capacity lists), C += sum Z^T W Z by owner blocks, and y = C d.
+hipError_t launch_fm_lists(const Geometry &g, int K, Lists z, unsigned *fm_cnt, unsigned *fm_off, uint2 *fm,
+                           unsigned long long *scan_tmp, unsigned long long *total64, hipStream_t s);
+hipError_t launch_surrogate_blocks(const Geometry &g, int K, int m, const unsigned *fm_off, const uint2 *fm,
+                                   const unsigned char *W, double *C, hipStream_t s);
+// Unmasked case: lag sums (Rl: surrogate_lag_elems doubles, Es: 4 c of them), expansion, corners.
+long long surrogate_lag_elems(int K, int m);
+hipError_t launch_surrogate_unmasked(const Geometry &g, int K, int m, Lists z, const unsigned *fm_off, const uint2 *fm,
+                                     double *Rl, double *Es, double *C, hipStream_t s);
 hipError_t launch_surrogate_matvec(int K, int m, const double *C, const float *d, double *partial, double *y,
                                    hipStream_t s);
 long long surrogate_matvec_partial_elems(int K, int m);

@@ -1,0 +1,83 @@
+"""Outer loops of the method on top of the library: batch (Alg. 1) and online (Alg. 2).
+
+Both alternate a subsampled code update (eqs. 2-4) with a filter update; the
+batch learner solves eq. (5) over all images each outer iteration, the online
+learner draws a mini-batch per iteration and updates the surrogates of eq. (7)
+before solving eq. (8).  Mini-batching (the paper's extension of Alg. 2) is the
+batch dimension of every call.
+"""
+
+from __future__ import annotations
+
+import torch
+
+from .ops import Context, Images, Surrogate
+
+
+class BatchLearner:
+    """Stochastic batch CSC (Alg. 1): codes of every image are kept across outer
+    iterations and warm-started on the new sample."""
+
+    def __init__(self, ctx: Context, im: Images, x, d, lam: float, p: float, n_code_iter: int = 20,
+                 seed: int = 1, n_dict_iter: int = 1, n_power: int = 20, W=None, precision: str = "fp32"):
+        self.ctx, self.im, self.x, self.d, self.W = ctx, im, x, d, W
+        self.K, self.m = int(d.shape[0]), int(d.shape[-1])
+        self.lam, self.p, self.T, self.seed = lam, p, n_code_iter, seed
+        self.n_dict_iter, self.n_power, self.precision = n_dict_iter, n_power, precision
+        self.z = torch.zeros(self.K * im.n_pix, dtype=torch.float32, device=x.device)
+        self.t = 0
+
+    def step(self):
+        """One outer iteration: sample, code update for every image, filter update."""
+        self.t += 1
+        st = self.ctx.code_step(self.im, self.x, self.d, self.z, self.lam, self.p, self.seed, self.t, self.T,
+                                W=self.W, precision=self.precision, stats=True)
+        Ld = self.ctx.dict_step(self.im, self.x, self.z, self.d, n_iter=self.n_dict_iter, n_power=self.n_power,
+                                W=self.W, precision=self.precision)
+        return st, Ld
+
+    def objective(self):
+        return self.ctx.objective(self.im, self.x, self.d, self.z, self.lam, W=self.W)
+
+
+class OnlineLearner:
+    """Stochastic online CSC (Alg. 2) with mini-batches: every step codes a new
+    mini-batch from zero, folds it into the surrogates and updates the filters."""
+
+    def __init__(self, ctx: Context, im: Images, d, lam: float, p: float, n_code_iter: int = 20, seed: int = 1,
+                 n_dict_iter: int = 1, n_power: int = 20, precision: str = "fp32"):
+        self.ctx, self.im, self.d = ctx, im, d
+        self.K, self.m = int(d.shape[0]), int(d.shape[-1])
+        self.lam, self.p, self.T, self.seed = lam, p, n_code_iter, seed
+        self.n_dict_iter, self.n_power, self.precision = n_dict_iter, n_power, precision
+        self.sur = Surrogate(self.K, self.m, device=d.device)
+        self.z = torch.zeros(self.K * im.n_pix, dtype=torch.float32, device=d.device)
+
+    @property
+    def t(self):
+        return self.sur.t
+
+    def step(self, x, W=None):
+        """Process one mini-batch x (packed like ``im``)."""
+        draw = self.sur.t + 1
+        self.z.zero_()
+        st = self.ctx.code_step(self.im, x, self.d, self.z, self.lam, self.p, self.seed, draw, self.T, W=W,
+                                precision=self.precision, stats=True)
+        Ld = self.ctx.dict_step(self.im, x, self.z, self.d, n_iter=self.n_dict_iter, n_power=self.n_power, W=W,
+                                surrogate=self.sur, precision=self.precision)
+        return st, Ld
+
+    def evaluate(self, im: Images, x, n_iter: int = 50, lam: float | None = None, W=None):
+        """Objective of eq. (1) on held-out images with codes fitted at p = 1 from zero."""
+        lam = self.lam if lam is None else lam
+        z = torch.zeros(self.K * im.n_pix, dtype=torch.float32, device=x.device)
+        self.ctx.code_step(im, x, self.d, z, lam, 1.0, self.seed, 0, n_iter, W=W, precision="fp32")
+        return self.ctx.objective(im, x, self.d, z, lam, W=W)
+
+    def state_dict(self):
+        return {"d": self.d.detach().clone(), "sur": {k: (v.clone() if torch.is_tensor(v) else v)
+                                                      for k, v in self.sur.state_dict().items()}}
+
+    def load_state_dict(self, sd):
+        self.d.copy_(sd["d"])
+        self.sur.load_state_dict(sd["sur"])
