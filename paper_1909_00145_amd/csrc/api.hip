@@ -36,6 +36,8 @@ enum Slot {
     WS_FM,
     WS_LAG,
     WS_ES,
+    WS_TAB,
+    WS_TILESBIG,
     WS_COUNT
 };
 
@@ -203,6 +205,7 @@ int geometry(csc_ctx *h, const csc_images *im) {
     Geometry &g = h->geo;
     g.h_img.assign(im->n, ImgInfo{});
     g.h_tiles.clear();
+    g.h_tiles_big.clear();
     long long pix = 0;
     int tiles = 0, max_side = 0, rows = 0;
     std::vector<int> row_img;
@@ -220,6 +223,8 @@ int geometry(csc_ctx *h, const csc_images *im) {
         row_img.insert(row_img.end(), ii.H, i);
         for (int ty = 0; ty < ii.tiles_y; ++ty)
             for (int tx = 0; tx < ii.tiles_x; ++tx) g.h_tiles.push_back(TileInfo{i, ty, tx, 0});
+        for (int ty = 0; ty < (ii.H + TS_BIG - 1) / TS_BIG; ++ty)
+            for (int tx = 0; tx < (ii.W + TS_BIG - 1) / TS_BIG; ++tx) g.h_tiles_big.push_back(TileInfo{i, ty, tx, 0});
         tiles += ii.tiles_y * ii.tiles_x;
         pix += (long long)ii.H * ii.W;
         max_side = std::max(max_side, std::max(ii.H, ii.W));
@@ -229,10 +234,14 @@ int geometry(csc_ctx *h, const csc_images *im) {
     g.n_pix = pix;
     g.max_side = max_side;
     g.n_rows = rows;
+    g.n_tiles_big = (int)g.h_tiles_big.size();
     h->geo_valid = false;
     WS(dimg, ImgInfo, WS_IMG, g.n_img);
     WS(dtiles, TileInfo, WS_TILES, g.n_tiles);
     WS(drows, int, WS_ROWS, g.n_rows);
+    WS(dtb, TileInfo, WS_TILESBIG, g.n_tiles_big);
+    HIPCHK(hipMemcpyAsync(dtb, g.h_tiles_big.data(), sizeof(TileInfo) * g.n_tiles_big, hipMemcpyHostToDevice,
+                          h->stream));
     HIPCHK(hipMemcpyAsync(drows, row_img.data(), sizeof(int) * g.n_rows, hipMemcpyHostToDevice, h->stream));
     HIPCHK(hipMemcpyAsync(dimg, g.h_img.data(), sizeof(ImgInfo) * g.n_img, hipMemcpyHostToDevice, h->stream));
     HIPCHK(hipMemcpyAsync(dtiles, g.h_tiles.data(), sizeof(TileInfo) * g.n_tiles, hipMemcpyHostToDevice, h->stream));
@@ -240,6 +249,7 @@ int geometry(csc_ctx *h, const csc_images *im) {
     g.d_img = dimg;
     g.d_tiles = dtiles;
     g.d_row_img = drows;
+    g.d_tiles_big = dtb;
     h->geo_key = key;
     h->geo_valid = true;
     return CSC_OK;
@@ -300,20 +310,42 @@ int build_nonzero_lists(csc_ctx *h, int K, const float *z, Lists *out, unsigned 
     return CSC_OK;
 }
 
-// G = sum_i Z_i^T r_i into `G` (FP32, [K][M]) from lists.
-int filter_corr_lists(csc_ctx *h, int K, int m, Lists L, const float *r, float *G) {
+// Per-filter lists of the non-zero codes (FmLists), built from exact-capacity pixel lists.
+struct FmLists {
+    const unsigned *off;
+    const FmCode *codes;
+};
+
+int build_fm_lists(csc_ctx *h, int K, Lists L, unsigned long long nz, FmLists *out) {
+    const Geometry &g = h->geo;
+    if (g.max_side > 65535) return fail(h, CSC_EUNSUPPORTED, "filter step: image sides must be < 65536");
+    const long long KR = (long long)K * g.n_rows;
+    WS(fmcnt, unsigned, WS_FMCNT, KR);
+    WS(fmoff, unsigned, WS_FMOFF, KR + 1);
+    WS(tmp, unsigned long long, WS_SCANTMP, scan_tmp_elems(KR));
+    WS(fm, FmCode, WS_FM, nz + 1);
+    WS(sc, double, WS_SCAL, SC_COUNT);
+    PROF(CSC_PK_LISTS);
+    unsigned long long *total = reinterpret_cast<unsigned long long *>(sc + SC_NNZ);
+    HIPCHK(launch_fm_lists(g, K, L, fmcnt, fmoff, fm, tmp, total, h->stream));
+    *out = FmLists{fmoff, fm};
+    return CSC_OK;
+}
+
+// G = sum_i Z_i^T r_i into `G` (FP32, [K][M]) from per-filter lists (FP64 accumulation).
+int filter_corr_lists(csc_ctx *h, int K, int m, FmLists F, const float *r, float *G) {
     const Geometry &g = h->geo;
     const int M = m * m;
-    const int nb = corr_blocks(g);
-    WS(part, float, WS_PART, (size_t)nb * K * M);
+    const int nch = corr_chunks(K);
+    WS(part, double, WS_PART, (size_t)nch * K * M);
     PROF(CSC_PK_CORR);
-    HIPCHK(launch_filter_corr_f32(g, K, m, L, r, part, nb, h->stream));
-    HIPCHK(launch_reduce_partials_f32(part, nb, K * M, G, h->stream));
+    HIPCHK(launch_corr_fm(g, K, m, F.off, F.codes, r, nullptr, false, part, h->stream));
+    HIPCHK(launch_reduce_partials_f64_to_f32(part, nch, K * M, G, h->stream));
     return CSC_OK;
 }
 
 // Power iteration on sum_i Z_i^T W_i Z_i; leaves the estimate in the device scalar SC_LAM.
-int power_iteration(csc_ctx *h, int K, int m, Lists L, const unsigned char *W, int n_power) {
+int power_iteration(csc_ctx *h, int K, int m, Lists L, FmLists F, const unsigned char *W, int n_power) {
     const Geometry &g = h->geo;
     const int M = m * m;
     WS(v, float, WS_V, K * M);
@@ -327,7 +359,7 @@ int power_iteration(csc_ctx *h, int K, int m, Lists L, const unsigned char *W, i
             PROF(CSC_PK_SYNTH);
             HIPCHK(launch_synth(g, K, m, L, v, nullptr, W, R, SYNTH_WEIGHTED, h->stream));
         }
-        int st = filter_corr_lists(h, K, m, L, R, w);
+        int st = filter_corr_lists(h, K, m, F, R, w);
         if (st) return st;
         PROF(CSC_PK_UPDATE);
         HIPCHK(launch_power_update(v, w, K * M, sc + SC_LAM, h->stream));
@@ -530,10 +562,12 @@ extern "C" int csc_dict_step(csc_handle h, const csc_images *im, const float *x,
     Lists L;
     unsigned long long nz = 0;
     if ((st = build_nonzero_lists(h, K, z, &L, &nz))) return st;
+    FmLists F;
+    if ((st = build_fm_lists(h, K, L, nz, &F))) return st;
     WS(sc, double, WS_SCAL, SC_COUNT);
     const bool need_ld = sur || step <= 0.0 || L_d_out;
     if (need_ld) {
-        if ((st = power_iteration(h, K, m, L, W, n_power))) return st;
+        if ((st = power_iteration(h, K, m, L, F, W, n_power))) return st;
     }
     double Ld = 0.0;
     if (sur || L_d_out) {
@@ -553,36 +587,29 @@ extern "C" int csc_dict_step(csc_handle h, const csc_images *im, const float *x,
                 PROF(CSC_PK_SYNTH);
                 HIPCHK(launch_synth(g, K, m, L, d, x, W, R, SYNTH_RESIDUAL, h->stream));
             }
-            if ((st = filter_corr_lists(h, K, m, L, R, G))) return st;
+            if ((st = filter_corr_lists(h, K, m, F, R, G))) return st;
             PROF(CSC_PK_UPDATE);
             HIPCHK(launch_batch_update(d, G, sc + SC_LAM, K, M, h->stream));
         }
     } else {
         {
-            if (g.max_side > 65535) return fail(h, CSC_EUNSUPPORTED, "online step: image sides must be < 65536");
-            const long long KR = (long long)K * g.n_rows;
-            WS(fmcnt, unsigned, WS_FMCNT, KR);
-            WS(fmoff, unsigned, WS_FMOFF, KR + 1);
-            WS(tmp, unsigned long long, WS_SCANTMP, scan_tmp_elems(KR));
-            WS(fm, uint2, WS_FM, nz + 1);
             PROF(CSC_PK_SUR_ACC);
-            unsigned long long *total = reinterpret_cast<unsigned long long *>(sc + SC_NNZ);
-            HIPCHK(launch_fm_lists(g, K, L, fmcnt, fmoff, fm, tmp, total, h->stream));
             if (W) {
-                HIPCHK(launch_surrogate_blocks(g, K, m, fmoff, fm, W, sur->C, h->stream));
+                HIPCHK(launch_surrogate_blocks(g, K, m, F.off, F.codes, W, sur->C, h->stream));
             } else {
                 const long long nl = surrogate_lag_elems(K, m);
                 WS(Rl, double, WS_LAG, nl);
                 WS(Es, double, WS_ES, nl * 4 * (m / 2 > 0 ? m / 2 : 1));
-                HIPCHK(launch_surrogate_unmasked(g, K, m, L, fmoff, fm, Rl, Es, sur->C, h->stream));
+                WS(tab, unsigned short, WS_TAB, (size_t)M * M);
+                HIPCHK(launch_surrogate_unmasked(g, K, m, L, F.off, F.codes, Rl, Es, tab, sur->C, h->stream));
             }
         }
-        const int nb = corr_blocks(g);
         {
-            WS(part, double, WS_PART, (size_t)nb * K * M);
+            const int nch = corr_chunks(K);
+            WS(part, double, WS_PART, (size_t)nch * K * M);
             PROF(CSC_PK_CORR);
-            HIPCHK(launch_filter_corr_f64(g, K, m, L, x, W, part, nb, h->stream));
-            HIPCHK(launch_reduce_partials_f64_add(part, nb, K * M, sur->B, h->stream));
+            HIPCHK(launch_corr_fm(g, K, m, F.off, F.codes, x, W, true, part, h->stream));
+            HIPCHK(launch_reduce_partials_f64_add(part, nch, K * M, sur->B, h->stream));
         }
         sur->t += 1;
         sur->Ld_sum += Ld;
@@ -679,8 +706,11 @@ extern "C" int csc_filter_corr(csc_handle h, const csc_images *im, const float *
     HIPCHK(hipSetDevice(h->device));
     if ((st = geometry(h, im))) return st;
     Lists L;
-    if ((st = build_nonzero_lists(h, K, z, &L))) return st;
-    return filter_corr_lists(h, K, m, L, r, G);
+    unsigned long long nz = 0;
+    if ((st = build_nonzero_lists(h, K, z, &L, &nz))) return st;
+    FmLists F;
+    if ((st = build_fm_lists(h, K, L, nz, &F))) return st;
+    return filter_corr_lists(h, K, m, F, r, G);
 }
 
 extern "C" int csc_profile_enable(csc_handle h, int enable) {

@@ -256,24 +256,32 @@ struct __align__(8) SynPair {
     float v;
 };
 
-template <int MM, bool DLDS>
-__global__ __launch_bounds__(TPB) void k_synth(const ImgInfo *imgs, const TileInfo *tiles, int K, Lists zl,
-                                               const float *__restrict__ d, const float *__restrict__ x,
-                                               const unsigned char *__restrict__ W, float *__restrict__ out,
-                                               int mode) {
-    constexpr int C = MM / 2, RW = TS + 2 * C, R = RW * RW, M = MM * MM;
-    constexpr int CH = (R + TPB - 1) / TPB;
+// Synthesis on TT x TT output tiles, one thread per output pixel.  The
+// codes of the tile grown by c are staged in LDS in region row-major order, so
+// for output p and tap row s_y the codes of the 2c + 1 pixels q = p - s form one
+// contiguous run; filters are staged in LDS when they fit.
+template <int MM, bool DLDS, int TT>
+__global__ __launch_bounds__(TT * TT) void k_synth(const ImgInfo *imgs, const TileInfo *tiles, int K, Lists zl,
+                                                   const float *__restrict__ d, const float *__restrict__ x,
+                                                   const unsigned char *__restrict__ W, float *__restrict__ out,
+                                                   int mode) {
+    constexpr int C = MM / 2, RW = TT + 2 * C, R = RW * RW, M = MM * MM, NT = TT * TT;
+    constexpr int CH = (R + NT - 1) / NT;
     __shared__ unsigned lgoff[R];
     __shared__ int lstart[R + 1];
     __shared__ unsigned short lcnt[R];
     __shared__ SynPair lp[SYN_CAP];
-    __shared__ int scratch[TPB];
+    __shared__ int scratch[NT];
     __shared__ float dl[DLDS ? SYN_DCAP : 1];
 
-    PixelCtx c = pixel_ctx(imgs, tiles);
+    const TileInfo t = tiles[blockIdx.x];
+    const ImgInfo im = imgs[t.img];
+    const int ly = threadIdx.x / TT, lx = threadIdx.x % TT;
+    const int y = t.ty * TT + ly, xx = t.tx * TT + lx;
+    const bool valid = y < im.H && xx < im.W;
     if (DLDS)
-        for (int i = threadIdx.x; i < K * M; i += TPB) dl[i] = d[i];
-    const int oy = c.t.ty * TS - C, ox = c.t.tx * TS - C;
+        for (int i = threadIdx.x; i < K * M; i += NT) dl[i] = d[i];
+    const int oy = t.ty * TT - C, ox = t.tx * TT - C;
     int mysum = 0;
 #pragma unroll
     for (int j = 0; j < CH; ++j) {
@@ -282,8 +290,8 @@ __global__ __launch_bounds__(TPB) void k_synth(const ImgInfo *imgs, const TileIn
             const int gy = oy + i / RW, gx = ox + i % RW;
             int n = 0;
             unsigned o = 0;
-            if (gy >= 0 && gy < c.im.H && gx >= 0 && gx < c.im.W) {
-                const long long gp = c.im.pix_off + (long long)gy * c.im.W + gx;
+            if (gy >= 0 && gy < im.H && gx >= 0 && gx < im.W) {
+                const long long gp = im.pix_off + (long long)gy * im.W + gx;
                 n = zl.cnt[gp];
                 o = zl.off[gp];
             }
@@ -293,7 +301,7 @@ __global__ __launch_bounds__(TPB) void k_synth(const ImgInfo *imgs, const TileIn
         }
     }
     int total;
-    int ex = block_exclusive_scan(mysum, scratch, &total);
+    int ex = block_exclusive_scan_n<NT>(mysum, scratch, &total);
     const bool staged = total <= SYN_CAP;
 #pragma unroll
     for (int j = 0; j < CH; ++j) {
@@ -311,17 +319,14 @@ __global__ __launch_bounds__(TPB) void k_synth(const ImgInfo *imgs, const TileIn
     }
     if (threadIdx.x == 0) lstart[R] = total;
     __syncthreads();
-    if (!c.valid) return;
+    if (!valid) return;
     const float *dd = DLDS ? dl : d;
     float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, acc3 = 0.f;
     if (staged) {
-        // Output p, tap s: code pixel q = p - s sits at region column lx + c - s_x, so
-        // for a tap row s_y the codes of the 2c + 1 columns lx .. lx + 2c form one
-        // contiguous run of the staged pairs.
         for (int sy = -C; sy <= C; ++sy) {
-            const int rb = (c.ly + C - sy) * RW + c.lx;
+            const int rb = (ly + C - sy) * RW + lx;
             const int j0 = lstart[rb], j1 = lstart[rb + 2 * C + 1];
-            const float *drow = dd + (sy + C) * MM + 2 * C + c.lx;  // tap column = 2c - (col - lx)
+            const float *drow = dd + (sy + C) * MM + 2 * C + lx;  // tap column = 2c - (col - lx)
             int j = j0;
             for (; j + 3 < j1; j += 4) {
                 const SynPair e0 = lp[j], e1 = lp[j + 1], e2 = lp[j + 2], e3 = lp[j + 3];
@@ -338,7 +343,7 @@ __global__ __launch_bounds__(TPB) void k_synth(const ImgInfo *imgs, const TileIn
     } else {
         for (int sy = -C; sy <= C; ++sy) {
             for (int sx = -C; sx <= C; ++sx) {
-                const int i = (c.ly + C - sy) * RW + (c.lx + C - sx);
+                const int i = (ly + C - sy) * RW + (lx + C - sx);
                 const int n = lcnt[i];
                 const Pair *src = zl.pairs + lgoff[i];
                 const float *dt = dd + (sy + C) * MM + (sx + C);
@@ -350,16 +355,17 @@ __global__ __launch_bounds__(TPB) void k_synth(const ImgInfo *imgs, const TileIn
         }
     }
     const float acc = (acc0 + acc1) + (acc2 + acc3);
+    const long long gp = im.pix_off + (long long)y * im.W + xx;
     float o;
     if (mode == SYNTH_RESIDUAL) {
-        o = x[c.gp] - acc;
-        if (W && !W[c.gp]) o = 0.f;
+        o = x[gp] - acc;
+        if (W && !W[gp]) o = 0.f;
     } else if (mode == SYNTH_WEIGHTED) {
-        o = (W && !W[c.gp]) ? 0.f : acc;
+        o = (W && !W[gp]) ? 0.f : acc;
     } else {
         o = acc;
     }
-    out[c.gp] = o;
+    out[gp] = o;
 }
 
 constexpr int ADJ_CAP = 2048;
@@ -595,10 +601,10 @@ template <int MM>
 hipError_t synth_impl(const Geometry &g, int K, Lists z, const float *d, const float *x, const unsigned char *W,
                       float *out, SynthMode mode, hipStream_t s) {
     if (K * MM * MM <= SYN_DCAP)
-        hipLaunchKernelGGL((k_synth<MM, true>), dim3(g.n_tiles), dim3(TPB), 0, s, g.d_img, g.d_tiles, K, z, d, x, W,
-                           out, (int)mode);
+        hipLaunchKernelGGL((k_synth<MM, true, TS>), dim3(g.n_tiles), dim3(TPB), 0, s, g.d_img, g.d_tiles, K, z, d, x,
+                           W, out, (int)mode);
     else
-        hipLaunchKernelGGL((k_synth<MM, false>), dim3(g.n_tiles), dim3(TPB), 0, s, g.d_img, g.d_tiles, K, z, d, x,
+        hipLaunchKernelGGL((k_synth<MM, false, TS>), dim3(g.n_tiles), dim3(TPB), 0, s, g.d_img, g.d_tiles, K, z, d, x,
                            W, out, (int)mode);
     return hipGetLastError();
 }

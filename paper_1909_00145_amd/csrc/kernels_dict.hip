@@ -17,164 +17,51 @@ constexpr int CORR_MAX_BLOCKS = 512;
 // single writer and a fixed accumulation order: the result is deterministic.
 // FROM_X selects the right-hand side W x (for B of eq. 7) instead of r.
 // ---------------------------------------------------------------------------
-constexpr int CORR_CAP = 2048;
-constexpr double FIX_SCALE = 1099511627776.0;  // 2^40
-constexpr double FIX_INV = 1.0 / 1099511627776.0;
+// ---------------------------------------------------------------------------
+// Filter correlation G_k[s] = sum_q z_k[q] r[q + s] (r zero outside the image),
+// filter-major: workgroup (chunk c, filter k), thread t <-> tap s.  Every thread
+// walks the same codes of filter k (a contiguous range of the per-filter list,
+// uniform loads) in list order and accumulates v * r[q + s] in FP64, so the
+// result is deterministic and needs no atomics.  weight_rhs multiplies the
+// right-hand side by the observation mask (for Z^T W x).
+// ---------------------------------------------------------------------------
+constexpr int CORR_TARGET_BLOCKS = 4096;
 
-// Stage the "right-hand side" region (r, or W x) and the tile's non-zero codes.
-// Returns through the shared arrays; contains block barriers.
-template <int MM, bool FROM_X>
-__device__ __forceinline__ bool corr_stage_tile(const ImgInfo &im, const TileInfo &t, Lists zl,
-                                                const float *__restrict__ r, const unsigned char *__restrict__ W,
-                                                float *rr, unsigned *loff, int *lst, int *lc, Pair *ent,
-                                                int *scratch) {
-    constexpr int C = MM / 2, RW = TS + 2 * C;
-    const int oy = t.ty * TS - C, ox = t.tx * TS - C;
-    for (int i = threadIdx.x; i < RW * RW; i += TPB) {
-        const int gy = oy + i / RW, gx = ox + i % RW;
-        float v = 0.f;
-        if (gy >= 0 && gy < im.H && gx >= 0 && gx < im.W) {
-            const long long gp = im.pix_off + (long long)gy * im.W + gx;
-            v = r[gp];
-            if (FROM_X && W && !W[gp]) v = 0.f;
-        }
-        rr[i] = v;
-    }
-    int n = 0;
-    unsigned o = 0;
-    {
-        const int ly = threadIdx.x / TS, lx = threadIdx.x % TS;
-        const int y = t.ty * TS + ly, x = t.tx * TS + lx;
-        if (y < im.H && x < im.W) {
-            const long long gp = im.pix_off + (long long)y * im.W + x;
-            n = zl.cnt[gp];
-            o = zl.off[gp];
-        }
-    }
-    int total;
-    const int ex = block_exclusive_scan(n, scratch, &total);
-    const bool staged = total <= CORR_CAP;
-    lc[threadIdx.x] = n;
-    loff[threadIdx.x] = o;
-    lst[threadIdx.x] = ex;
-    if (staged)
-        for (int j = 0; j < n; ++j) ent[ex + j] = zl.pairs[o + j];
-    __syncthreads();
-    return staged;
-}
-
-// FP32 filter correlation G_k[s] = sum_q z_k[q] r[q + s].  Each block owns a
-// fixed, strided set of tiles and a chunk of filters.  Waves take whole codes,
-// lanes the taps; the exact FP64 product of two floats is rounded to a 2^-40
-// fixed-point grid and added with an integer LDS atomic, so the block partial
-// does not depend on the order of the additions (deterministic).
 template <int MM>
-__global__ __launch_bounds__(TPB) void k_filter_corr_fix(const ImgInfo *imgs, const TileInfo *tiles, int n_tiles,
-                                                         int K, Lists zl, const float *__restrict__ r,
-                                                         float *__restrict__ partial, int KC) {
-    constexpr int C = MM / 2, RW = TS + 2 * C, M = MM * MM;
-    __shared__ float rr[RW * RW];
-    __shared__ unsigned loff[TPB];
-    __shared__ int lst[TPB];
-    __shared__ int lc[TPB];
-    __shared__ Pair ent[CORR_CAP];
-    __shared__ int scratch[TPB];
-    extern __shared__ double gshm[];
-    unsigned long long *Gp = reinterpret_cast<unsigned long long *>(gshm);
-    const int k0 = blockIdx.y * KC;
-    const int k1 = min(K, k0 + KC);
-    for (int i = threadIdx.x; i < (k1 - k0) * M; i += TPB) Gp[i] = 0ull;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-        __syncthreads();
-        const TileInfo t = tiles[tile];
-        const ImgInfo im = imgs[t.img];
-        const bool staged = corr_stage_tile<MM, false>(im, t, zl, r, nullptr, rr, loff, lst, lc, ent, scratch);
-        if (staged) {
-            // flat walk over the tile's codes; pixel of code e from the prefix lst
-            int px = 0;
-            const int total = lst[TPB - 1] + lc[TPB - 1];
-            for (int e = wave; e < total; e += TPB / 64) {
-                while (px + 1 < TPB && lst[px + 1] <= e) ++px;
-                const Pair en = ent[e];
-                if (en.k < k0 || en.k >= k1) continue;
-                const int qy = px / TS, qx = px % TS;
-                const double v = (double)en.v;
-                unsigned long long *row = Gp + (en.k - k0) * M;
-                for (int tt = lane; tt < M; tt += 64) {
-                    const int sy = tt / MM - C, sx = tt % MM - C;
-                    const double prod = v * (double)rr[(qy + C + sy) * RW + (qx + C + sx)];
-                    atomicAdd(row + tt, (unsigned long long)__double2ll_rn(prod * FIX_SCALE));
-                }
-            }
-        } else {
-            for (int px = wave; px < TPB; px += TPB / 64) {
-                const int cnt = lc[px];
-                const int qy = px / TS, qx = px % TS;
-                for (int j = 0; j < cnt; ++j) {
-                    const Pair en = zl.pairs[loff[px] + j];
-                    if (en.k < k0 || en.k >= k1) continue;
-                    const double v = (double)en.v;
-                    unsigned long long *row = Gp + (en.k - k0) * M;
-                    for (int tt = lane; tt < M; tt += 64) {
-                        const int sy = tt / MM - C, sx = tt % MM - C;
-                        const double prod = v * (double)rr[(qy + C + sy) * RW + (qx + C + sx)];
-                        atomicAdd(row + tt, (unsigned long long)__double2ll_rn(prod * FIX_SCALE));
-                    }
-                }
+__global__ __launch_bounds__(128) void k_corr_fm(const ImgInfo *imgs, int K, int R, const unsigned *__restrict__ fm_off,
+                                                 const FmCode *__restrict__ fm, const float *__restrict__ r,
+                                                 const unsigned char *__restrict__ W, int weight_rhs,
+                                                 double *__restrict__ partial) {
+    constexpr int C = MM / 2, M = MM * MM;
+    const int k = blockIdx.y, ch = blockIdx.x, nch = gridDim.x;
+    const unsigned a = fm_off[(long long)k * R], b = fm_off[(long long)k * R + R];
+    const unsigned n = b - a;
+    const unsigned e0 = a + (unsigned)(((unsigned long long)n * ch) / nch);
+    const unsigned e1 = a + (unsigned)(((unsigned long long)n * (ch + 1)) / nch);
+    const int t = threadIdx.x;
+    const bool active = t < M;
+    const int sy = active ? t / MM - C : 0, sx = active ? t % MM - C : 0;
+    constexpr int U = 4;
+    double acc[U] = {0.0, 0.0, 0.0, 0.0};
+    for (unsigned e = e0; e < e1; e += U) {
+        FmCode c[U];
+        float rv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) c[u] = (e + u < e1) ? fm[e + u] : FmCode{0u, 0.f, 0, 0};
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const ImgInfo im = imgs[c[u].img];
+            const int y = (int)(c[u].yx >> 16) + sy, x = (int)(c[u].yx & 0xFFFFu) + sx;
+            rv[u] = 0.f;
+            if (active && e + u < e1 && y >= 0 && y < im.H && x >= 0 && x < im.W) {
+                const long long gp = im.pix_off + (long long)y * im.W + x;
+                rv[u] = (weight_rhs && W && !W[gp]) ? 0.f : r[gp];
             }
         }
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc[u] += (double)c[u].v * (double)rv[u];
     }
-    __syncthreads();
-    float *dst = partial + (long long)blockIdx.x * K * M + (long long)k0 * M;
-    for (int i = threadIdx.x; i < (k1 - k0) * M; i += TPB) dst[i] = (float)((double)(long long)Gp[i] * FIX_INV);
-}
-
-// FP64 correlation with the observation-weighted image, Z^T (W x) for B of
-// eq. (7).  Wave w owns the filters k with (k - k0) % 4 == w and lane l the taps
-// l, l + 64, so every partial cell has one writer and a fixed order.
-template <int MM>
-__global__ __launch_bounds__(TPB) void k_filter_corr_x64(const ImgInfo *imgs, const TileInfo *tiles, int n_tiles,
-                                                         int K, Lists zl, const float *__restrict__ x,
-                                                         const unsigned char *__restrict__ W,
-                                                         double *__restrict__ partial, int KC) {
-    constexpr int C = MM / 2, RW = TS + 2 * C, M = MM * MM;
-    __shared__ float rr[RW * RW];
-    __shared__ unsigned loff[TPB];
-    __shared__ int lst[TPB];
-    __shared__ int lc[TPB];
-    __shared__ Pair ent[CORR_CAP];
-    __shared__ int scratch[TPB];
-    extern __shared__ double gshm[];
-    double *Gp = gshm;
-    const int k0 = blockIdx.y * KC;
-    const int k1 = min(K, k0 + KC);
-    for (int i = threadIdx.x; i < (k1 - k0) * M; i += TPB) Gp[i] = 0.0;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-        __syncthreads();
-        const TileInfo t = tiles[tile];
-        const ImgInfo im = imgs[t.img];
-        const bool staged = corr_stage_tile<MM, true>(im, t, zl, x, W, rr, loff, lst, lc, ent, scratch);
-        for (int px = 0; px < TPB; ++px) {
-            const int cnt = lc[px];
-            if (cnt == 0) continue;
-            const int qy = px / TS, qx = px % TS;
-            for (int j = 0; j < cnt; ++j) {
-                const Pair e = staged ? ent[lst[px] + j] : zl.pairs[loff[px] + j];
-                if (e.k < k0 || e.k >= k1 || ((e.k - k0) & 3) != wave) continue;
-                const double v = (double)e.v;
-                double *row = Gp + (e.k - k0) * M;
-                for (int tt = lane; tt < M; tt += 64) {
-                    const int sy = tt / MM - C, sx = tt % MM - C;
-                    row[tt] += v * (double)rr[(qy + C + sy) * RW + (qx + C + sx)];
-                }
-            }
-        }
-    }
-    __syncthreads();
-    double *dst = partial + (long long)blockIdx.x * K * M + (long long)k0 * M;
-    for (int i = threadIdx.x; i < (k1 - k0) * M; i += TPB) dst[i] = Gp[i];
+    if (active) partial[((long long)ch * K + k) * M + t] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
 }
 
 // out[i] (+)= sum_b partial[b][i]: blocks of 16 elements x 16 slices; slice j
@@ -273,29 +160,10 @@ __host__ __device__ __forceinline__ int lag_prefix(int a, int m) {
 }
 
 template <int MM>
-hipError_t corr_f32_impl(const Geometry &g, int K, Lists z, const float *r, float *partial, int nblocks,
-                         hipStream_t s) {
-    constexpr int M = MM * MM;
-    int KC = (96 * 1024) / (M * 8);
-    if (KC > K) KC = K;
-    const int nkc = (K + KC - 1) / KC;
-    const size_t shm = (size_t)KC * M * 8;
-    hipLaunchKernelGGL(k_filter_corr_fix<MM>, dim3(nblocks, nkc), dim3(TPB), shm, s, g.d_img, g.d_tiles, g.n_tiles,
-                       K, z, r, partial, KC);
-    return hipGetLastError();
-}
-
-template <int MM>
-hipError_t corr_f64_impl(const Geometry &g, int K, Lists z, const float *x, const unsigned char *W, double *partial,
-                         int nblocks, hipStream_t s) {
-    constexpr int M = MM * MM;
-    int KC = (96 * 1024) / (M * 8);
-    KC = KC / 4 * 4;
-    if (KC > K) KC = K;
-    const int nkc = (K + KC - 1) / KC;
-    const size_t shm = (size_t)KC * M * 8;
-    hipLaunchKernelGGL(k_filter_corr_x64<MM>, dim3(nblocks, nkc), dim3(TPB), shm, s, g.d_img, g.d_tiles, g.n_tiles,
-                       K, z, x, W, partial, KC);
+hipError_t corr_fm_impl(const Geometry &g, int K, const unsigned *fm_off, const FmCode *fm, const float *r,
+                        const unsigned char *W, bool weight_rhs, double *partial, hipStream_t s) {
+    hipLaunchKernelGGL(k_corr_fm<MM>, dim3(corr_chunks(K), K), dim3(128), 0, s, g.d_img, K, g.n_rows, fm_off, fm, r, W,
+                       weight_rhs ? 1 : 0, partial);
     return hipGetLastError();
 }
 
@@ -311,20 +179,34 @@ hipError_t corr_f64_impl(const Geometry &g, int K, Lists z, const float *x, cons
         default: return hipErrorInvalidValue; \
     }
 
-int corr_blocks(const Geometry &g) { return g.n_tiles < CORR_MAX_BLOCKS ? g.n_tiles : CORR_MAX_BLOCKS; }
-
-hipError_t launch_filter_corr_f32(const Geometry &g, int K, int m, Lists z, const float *r, float *partial,
-                                  int nblocks, hipStream_t s) {
-    SCSC_DISPATCH_M(m, corr_f32_impl, g, K, z, r, partial, nblocks, s);
+int corr_chunks(int K) {
+    int c = (CORR_TARGET_BLOCKS + K - 1) / K;
+    return c < 1 ? 1 : (c > 64 ? 64 : c);
 }
 
-hipError_t launch_filter_corr_f64(const Geometry &g, int K, int m, Lists z, const float *x, const unsigned char *W,
-                                  double *partial, int nblocks, hipStream_t s) {
-    SCSC_DISPATCH_M(m, corr_f64_impl, g, K, z, x, W, partial, nblocks, s);
+hipError_t launch_corr_fm(const Geometry &g, int K, int m, const unsigned *fm_off, const FmCode *fm, const float *r,
+                          const unsigned char *W, bool weight_rhs, double *partial, hipStream_t s) {
+    SCSC_DISPATCH_M(m, corr_fm_impl, g, K, fm_off, fm, r, W, weight_rhs, partial, s);
 }
 
 hipError_t launch_reduce_partials_f32(const float *partial, int nblocks, int n, float *out, hipStream_t s) {
     hipLaunchKernelGGL(k_reduce_partials<float>, dim3((n + 15) / 16), dim3(256), 0, s, partial, nblocks, n, out, 0);
+    return hipGetLastError();
+}
+
+namespace {
+__global__ __launch_bounds__(256) void k_reduce_f64_to_f32(const double *__restrict__ partial, int nblocks, int n,
+                                                          float *__restrict__ out) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0;
+    for (int b = 0; b < nblocks; ++b) s += partial[(long long)b * n + i];
+    out[i] = (float)s;
+}
+}  // namespace
+
+hipError_t launch_reduce_partials_f64_to_f32(const double *partial, int nblocks, int n, float *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce_f64_to_f32, dim3((n + 255) / 256), dim3(256), 0, s, partial, nblocks, n, out);
     return hipGetLastError();
 }
 

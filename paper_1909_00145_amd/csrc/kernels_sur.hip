@@ -50,7 +50,7 @@ constexpr int FM_CAP = 4096;
 // Row r's entries, regrouped by filter in x order: fm[fm_off[k * R + r] + j] = (y << 16 | x, v).
 // Requires the pixel lists of the row to be contiguous (exact-capacity lists).
 __global__ __launch_bounds__(256) void k_fm_fill(const ImgInfo *imgs, const int *row_img, Lists zl, int R, int K,
-                                                 const unsigned *fm_off, uint2 *fm) {
+                                                 const unsigned *fm_off, FmCode *fm) {
     __shared__ Pair ent[FM_CAP];
     __shared__ unsigned short ex[FM_CAP];
     const int r = blockIdx.x;
@@ -77,7 +77,7 @@ __global__ __launch_bounds__(256) void k_fm_fill(const ImgInfo *imgs, const int 
         if (staged) {
             for (unsigned e = 0; e < total; ++e) {
                 const Pair p = ent[e];
-                if (p.k == k) fm[w++] = make_uint2(((unsigned)y << 16) | ex[e], __float_as_uint(p.v));
+                if (p.k == k) fm[w++] = FmCode{((unsigned)y << 16) | ex[e], p.v, row_img[r], 0};
             }
         } else {
             for (int x = 0; x < im.W; ++x) {
@@ -86,7 +86,7 @@ __global__ __launch_bounds__(256) void k_fm_fill(const ImgInfo *imgs, const int 
                 const int n = zl.cnt[gp];
                 for (int j = 0; j < n; ++j) {
                     const Pair p = zl.pairs[o + j];
-                    if (p.k == k) fm[w++] = make_uint2(((unsigned)y << 16) | (unsigned)x, __float_as_uint(p.v));
+                    if (p.k == k) fm[w++] = FmCode{((unsigned)y << 16) | (unsigned)x, p.v, row_img[r], 0};
                 }
             }
         }
@@ -109,7 +109,7 @@ constexpr int SB_TQ = 32;
 template <int MM>
 __global__ __launch_bounds__(SB_THREADS) void k_sur_block(const ImgInfo *imgs, int n_img, int K, int R,
                                                           const unsigned *__restrict__ fm_off,
-                                                          const uint2 *__restrict__ fm,
+                                                          const FmCode *__restrict__ fm,
                                                           const unsigned char *__restrict__ W,
                                                           double *__restrict__ Cbar) {
     constexpr int C = MM / 2, M = MM * MM, M2 = M * M, L = 2 * MM - 1;
@@ -151,11 +151,11 @@ __global__ __launch_bounds__(SB_THREADS) void k_sur_block(const ImgInfo *imgs, i
                         const unsigned j1 = fm_off[row + 1];
                         unsigned long long bits = 0;
                         for (unsigned j = fm_off[row]; j < j1; ++j) {
-                            const uint2 e = fm[j];
-                            const int c = (int)(e.x & 0xFFFFu) - rx0;
+                            const FmCode e = fm[j];
+                            const int c = (int)(e.yx & 0xFFFFu) - rx0;
                             if (c < 0) continue;
                             if (c >= PW) break;
-                            pl[f][rr * PW + c] = __uint_as_float(e.y);
+                            pl[f][rr * PW + c] = e.v;
                             bits |= 1ull << c;
                         }
                         bm[f][rr] = bits;
@@ -271,7 +271,7 @@ constexpr int LG_KB_SIDE = 32;  // partner filters per workgroup (band sums: c a
 template <int MM>
 __global__ __launch_bounds__(LG_THREADS) void k_sur_lag(const ImgInfo *imgs, int n_img, int K, int R,
                                                         const unsigned *__restrict__ fm_off,
-                                                        const uint2 *__restrict__ fm, Lists zl, int side, int KB,
+                                                        const FmCode *__restrict__ fm, Lists zl, int side, int KB,
                                                         double *__restrict__ Rout) {
     constexpr int C = MM / 2, L = 2 * MM - 1, LL = L * L;
     constexpr int NJ = C > 0 ? C : 1;
@@ -293,27 +293,44 @@ __global__ __launch_bounds__(LG_THREADS) void k_sur_lag(const ImgInfo *imgs, int
         if (side == 1) ya = max(0, im.H - C);
         const unsigned a = fm_off[(long long)k * R + im.row_off + ya];
         const unsigned b = fm_off[(long long)k * R + im.row_off + yb];
-        for (unsigned e = a + wave; e < b; e += LG_THREADS / 64) {
-            const uint2 en = fm[e];
-            const int y = (int)(en.x >> 16), x = (int)(en.x & 0xFFFFu);
-            int j = 0;
-            if (side == 0) j = y;
-            else if (side == 1) j = im.H - 1 - y;
-            else if (side == 2) j = x;
-            else if (side == 3) j = im.W - 1 - x;
-            if (side >= 2 && j >= C) continue;  // not in the band (uniform per wave)
-            if (!active) continue;
-            const int y2 = y + dy, x2 = x + dx;
-            if (y2 < 0 || y2 >= im.H || x2 < 0 || x2 >= im.W) continue;
-            const double v = (double)__uint_as_float(en.y);
-            const long long gp = im.pix_off + (long long)y2 * im.W + x2;
-            const unsigned o = zl.off[gp];
-            const int c = zl.cnt[gp];
-            double *row = acc + (long long)j * KB * LG_DC + lane;
-            for (int t = 0; t < c; ++t) {
-                const Pair p2 = zl.pairs[o + t];
-                if (p2.k < k2lo || p2.k >= k2hi || p2.k < k) continue;
-                atomicAdd(row + (p2.k - k2lo) * LG_DC, v * (double)p2.v);
+        // two codes per wave in flight: their partner-list headers load together
+        constexpr int NW = LG_THREADS / 64;
+        for (unsigned e = a + wave; e < b; e += 2 * NW) {
+            int jv[2], cnt[2];
+            unsigned off[2];
+            double v[2];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                cnt[u] = 0;
+                off[u] = 0;
+                jv[u] = 0;
+                v[u] = 0.0;
+                const unsigned eu = e + u * NW;
+                if (eu >= b) continue;
+                const FmCode en = fm[eu];
+                const int y = (int)(en.yx >> 16), x = (int)(en.yx & 0xFFFFu);
+                int j = 0;
+                if (side == 0) j = y;
+                else if (side == 1) j = im.H - 1 - y;
+                else if (side == 2) j = x;
+                else if (side == 3) j = im.W - 1 - x;
+                if (side >= 2 && j >= C) continue;  // not in the band
+                const int y2 = y + dy, x2 = x + dx;
+                if (!active || y2 < 0 || y2 >= im.H || x2 < 0 || x2 >= im.W) continue;
+                const long long gp = im.pix_off + (long long)y2 * im.W + x2;
+                off[u] = zl.off[gp];
+                cnt[u] = zl.cnt[gp];
+                jv[u] = j;
+                v[u] = (double)en.v;
+            }
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                double *row = acc + (long long)jv[u] * KB * LG_DC + lane;
+                for (int t = 0; t < cnt[u]; ++t) {
+                    const Pair p2 = zl.pairs[off[u] + t];
+                    if (p2.k < k2lo || p2.k >= k2hi || p2.k < k) continue;
+                    atomicAdd(row + (p2.k - k2lo) * LG_DC, v[u] * (double)p2.v);
+                }
             }
         }
     }
@@ -326,39 +343,75 @@ __global__ __launch_bounds__(LG_THREADS) void k_sur_lag(const ImgInfo *imgs, int
     }
 }
 
-// C_bar(k, k2) += R - E_top - E_bottom - E_left - E_right (and the transpose into
-// C_bar(k2, k)); Es holds the per-row / per-column lag sums of the bands,
-// Es[(side * c + j)][k][k2][lag].
+// Lag-layout position table: tab[i] = lag index * 128 + position inside the lag's run.
 template <int MM>
-__global__ __launch_bounds__(256) void k_sur_expand(int K, const double *__restrict__ Rl,
-                                                    const double *__restrict__ Es, double *__restrict__ Cbar) {
-    constexpr int C = MM / 2, M = MM * MM, M2 = M * M, L = 2 * MM - 1, LL = L * L;
+__global__ void k_lag_table(unsigned short *tab) {
+    constexpr int M = MM * MM, L = 2 * MM - 1, LL = L * L;
+    const int di = blockIdx.x * blockDim.x + threadIdx.x;
+    if (di >= LL) return;
+    const int dy = di / L - (MM - 1), dx = di % L - (MM - 1);
+    const int wy = MM - (dy < 0 ? -dy : dy), wx = MM - (dx < 0 ? -dx : dx);
+    const int off = lagp(dy, MM) * M + wy * lagp(dx, MM);
+    for (int t = 0; t < wy * wx; ++t) tab[off + t] = (unsigned short)(di * 128 + t);
+}
+
+// C_bar(a, b) += R - E_top - E_bottom - E_left - E_right for every block (a, b).
+// The lag sums are kept for k <= k2 only; block (a, b) with b < a is the
+// transpose of (b, a), whose run at lag -delta holds the same values in the same
+// order.  Each workgroup reads and writes its own block with coalesced accesses.
+constexpr int EX_THREADS = 256;
+constexpr int EX_BATCH = 8;
+
+template <int MM>
+__global__ __launch_bounds__(EX_THREADS) void k_sur_expand(int K, const double *__restrict__ Rl,
+                                                           const double *__restrict__ Es,
+                                                           const unsigned short *__restrict__ tab,
+                                                           double *__restrict__ Cbar) {
+    constexpr int C = MM / 2, M2 = MM * MM * MM * MM, L = 2 * MM - 1, LL = L * L;
+    constexpr int NC = C > 0 ? C : 1;
     __shared__ double r[LL];
-    __shared__ double es[4 * (C > 0 ? C : 1)][LL];
-    const int k = blockIdx.y, k2 = blockIdx.x;
-    if (k2 < k) return;
-    for (int i = threadIdx.x; i < LL; i += 256) r[i] = Rl[((long long)k * K + k2) * LL + i];
-    for (int i = threadIdx.x; i < 4 * C * LL; i += 256) {
+    __shared__ double es[4 * NC][LL];
+    const int a = blockIdx.y, b = blockIdx.x;
+    const bool tr = b < a;
+    const int k = tr ? b : a, k2 = tr ? a : b;
+    for (int i = threadIdx.x; i < LL; i += EX_THREADS) r[i] = Rl[((long long)k * K + k2) * LL + i];
+    for (int i = threadIdx.x; i < 4 * C * LL; i += EX_THREADS) {
         const int cls = i / LL, di = i % LL;
         es[cls][di] = Es[(((long long)cls * K + k) * K + k2) * LL + di];
     }
     __syncthreads();
-    double *blk = Cbar + ((long long)k * K + k2) * M2;
-    double *blkT = Cbar + ((long long)k2 * K + k) * M2;
-    const int slot = threadIdx.x / 128, t = threadIdx.x % 128;
-    for (int di = slot; di < LL; di += 2) {
-        const int dy = di / L - (MM - 1), dx = di % L - (MM - 1);
-        const int wy = MM - (dy < 0 ? -dy : dy), wx = MM - (dx < 0 ? -dx : dx);
-        if (t >= wy * wx) continue;
-        const int sy = max(-C, dy - C) + t / wx, sx = max(-C, dx - C) + t % wx;
-        double val = r[di];
-        for (int j = 0; j < -sy; ++j) val -= es[0 * C + j][di];  // top rows a < -s_y
-        for (int j = 0; j < sy; ++j) val -= es[1 * C + j][di];   // bottom rows H-1-a < s_y
-        for (int j = 0; j < -sx; ++j) val -= es[2 * C + j][di];  // left columns
-        for (int j = 0; j < sx; ++j) val -= es[3 * C + j][di];   // right columns
-        const int off = lagp(dy, MM) * M + wy * lagp(dx, MM);
-        blk[off + t] += val;
-        if (k2 != k) blkT[lagp(-dy, MM) * M + wy * lagp(-dx, MM) + t] += val;
+    double *blk = Cbar + ((long long)a * K + b) * M2;
+    for (int i0 = threadIdx.x; i0 < M2; i0 += EX_THREADS * EX_BATCH) {
+        double val[EX_BATCH], old[EX_BATCH];
+#pragma unroll
+        for (int u = 0; u < EX_BATCH; ++u) {
+            const int i = i0 + u * EX_THREADS;
+            val[u] = 0.0;
+            if (i >= M2) continue;
+            const int code = tab[i];
+            int di = code >> 7;
+            const int t = code & 127;
+            if (tr) di = LL - 1 - di;  // lag -delta of the stored (k, k2) block
+            const int dy = di / L - (MM - 1), dx = di % L - (MM - 1);
+            const int wx = MM - (dx < 0 ? -dx : dx);
+            const int sy = max(-C, dy - C) + t / wx, sx = max(-C, dx - C) + t % wx;
+            double v = r[di];
+            for (int j = 0; j < -sy; ++j) v -= es[0 * NC + j][di];  // top rows a < -s_y
+            for (int j = 0; j < sy; ++j) v -= es[1 * NC + j][di];   // bottom rows
+            for (int j = 0; j < -sx; ++j) v -= es[2 * NC + j][di];  // left columns
+            for (int j = 0; j < sx; ++j) v -= es[3 * NC + j][di];   // right columns
+            val[u] = v;
+        }
+#pragma unroll
+        for (int u = 0; u < EX_BATCH; ++u) {
+            const int i = i0 + u * EX_THREADS;
+            old[u] = i < M2 ? blk[i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < EX_BATCH; ++u) {
+            const int i = i0 + u * EX_THREADS;
+            if (i < M2) blk[i] = old[u] + val[u];
+        }
     }
 }
 
@@ -478,7 +531,7 @@ __global__ void k_sur_matvec_reduce(int K, int M, const double *__restrict__ par
 }
 
 template <int MM>
-hipError_t sur_block_impl(const Geometry &g, int K, int R, const unsigned *fm_off, const uint2 *fm,
+hipError_t sur_block_impl(const Geometry &g, int K, int R, const unsigned *fm_off, const FmCode *fm,
                           const unsigned char *W, double *C, hipStream_t s) {
     hipLaunchKernelGGL(k_sur_block<MM>, dim3(K, K), dim3(SB_THREADS), 0, s, g.d_img, g.n_img, K, R, fm_off, fm, W, C);
     return hipGetLastError();
@@ -495,7 +548,7 @@ hipError_t sur_mv_impl(int K, const double *C, const float *d, double *part, dou
 
 }  // namespace
 
-hipError_t launch_fm_lists(const Geometry &g, int K, Lists z, unsigned *fm_cnt, unsigned *fm_off, uint2 *fm,
+hipError_t launch_fm_lists(const Geometry &g, int K, Lists z, unsigned *fm_cnt, unsigned *fm_off, FmCode *fm,
                            unsigned long long *scan_tmp, unsigned long long *total64, hipStream_t s) {
     const int R = g.n_rows;
     hipError_t e = hipMemsetAsync(fm_cnt, 0, sizeof(unsigned) * (size_t)K * R, s);
@@ -507,7 +560,7 @@ hipError_t launch_fm_lists(const Geometry &g, int K, Lists z, unsigned *fm_cnt, 
     return hipGetLastError();
 }
 
-hipError_t launch_surrogate_blocks(const Geometry &g, int K, int m, const unsigned *fm_off, const uint2 *fm,
+hipError_t launch_surrogate_blocks(const Geometry &g, int K, int m, const unsigned *fm_off, const FmCode *fm,
                                    const unsigned char *W, double *C, hipStream_t s) {
     const int R = g.n_rows;
     switch (m) {
@@ -526,8 +579,8 @@ long long surrogate_lag_elems(int K, int m) { return (long long)K * K * (2 * m -
 
 namespace {
 template <int MM>
-hipError_t sur_unmasked_impl(const Geometry &g, int K, Lists z, const unsigned *fm_off, const uint2 *fm, double *Rl,
-                             double *Es, double *C, hipStream_t s) {
+hipError_t sur_unmasked_impl(const Geometry &g, int K, Lists z, const unsigned *fm_off, const FmCode *fm, double *Rl,
+                             double *Es, unsigned short *tab, double *C, hipStream_t s) {
     constexpr int Cc = MM / 2, L = 2 * MM - 1, LL = L * L;
     const int R = g.n_rows;
     const int ndc = (LL + LG_DC - 1) / LG_DC, nkb = (K + LG_KB - 1) / LG_KB;
@@ -542,21 +595,23 @@ hipError_t sur_unmasked_impl(const Geometry &g, int K, Lists z, const unsigned *
                            LG_KB_SIDE, Es);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_sur_expand<MM>, dim3(K, K), dim3(256), 0, s, K, Rl, Es, C);
+    hipLaunchKernelGGL(k_lag_table<MM>, dim3((LL + 63) / 64), dim3(64), 0, s, tab);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sur_expand<MM>, dim3(K, K), dim3(EX_THREADS), 0, s, K, Rl, Es, tab, C);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_sur_corner<MM>, dim3(g.n_img, 4), dim3(256), 0, s, g.d_img, K, z, C);
     return hipGetLastError();
 }
 }  // namespace
 
-hipError_t launch_surrogate_unmasked(const Geometry &g, int K, int m, Lists z, const unsigned *fm_off, const uint2 *fm,
-                                     double *Rl, double *Es, double *C, hipStream_t s) {
+hipError_t launch_surrogate_unmasked(const Geometry &g, int K, int m, Lists z, const unsigned *fm_off, const FmCode *fm,
+                                     double *Rl, double *Es, unsigned short *tab, double *C, hipStream_t s) {
     switch (m) {
-        case 3: return sur_unmasked_impl<3>(g, K, z, fm_off, fm, Rl, Es, C, s);
-        case 5: return sur_unmasked_impl<5>(g, K, z, fm_off, fm, Rl, Es, C, s);
-        case 7: return sur_unmasked_impl<7>(g, K, z, fm_off, fm, Rl, Es, C, s);
-        case 9: return sur_unmasked_impl<9>(g, K, z, fm_off, fm, Rl, Es, C, s);
-        case 11: return sur_unmasked_impl<11>(g, K, z, fm_off, fm, Rl, Es, C, s);
+        case 3: return sur_unmasked_impl<3>(g, K, z, fm_off, fm, Rl, Es, tab, C, s);
+        case 5: return sur_unmasked_impl<5>(g, K, z, fm_off, fm, Rl, Es, tab, C, s);
+        case 7: return sur_unmasked_impl<7>(g, K, z, fm_off, fm, Rl, Es, tab, C, s);
+        case 9: return sur_unmasked_impl<9>(g, K, z, fm_off, fm, Rl, Es, tab, C, s);
+        case 11: return sur_unmasked_impl<11>(g, K, z, fm_off, fm, Rl, Es, tab, C, s);
         default: return hipErrorInvalidValue;
     }
 }

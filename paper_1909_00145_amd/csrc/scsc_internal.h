@@ -20,6 +20,8 @@ constexpr int MAX_K = 1024;
 constexpr int MAX_C = 5;                  // largest half-width (m = 11)
 constexpr int MAX_RW = TS + 2 * MAX_C;    // side of a tile plus one filter halo
 constexpr int MAX_RW2 = TS + 4 * MAX_C;   // side of a tile plus two filter halos
+constexpr int TS_BIG = 32;                // synthesis tiles: TS_BIG x TS_BIG pixels, one thread each
+constexpr int TPB_BIG = TS_BIG * TS_BIG;
 
 struct ImgInfo {
     int H, W;
@@ -42,6 +44,16 @@ struct __align__(8) Pair {
     float v;
 };
 
+// One non-zero code in the per-filter lists: position (y << 16 | x) inside its
+// image, value and image.  The lists of filter k are ordered by global row
+// then x and live at [fm_off[k R + r], fm_off[k R + r + 1]) for row r.
+struct __align__(16) FmCode {
+    unsigned yx;
+    float v;
+    int img;
+    int pad;
+};
+
 // Device view of a batch: per-image info and the flattened tile list.
 struct Geometry {
     int n_img = 0;
@@ -52,6 +64,9 @@ struct Geometry {
     ImgInfo *d_img = nullptr;
     TileInfo *d_tiles = nullptr;
     int *d_row_img = nullptr;  // image of every global row
+    int n_tiles_big = 0;             // tiles of TS_BIG x TS_BIG pixels (synthesis)
+    TileInfo *d_tiles_big = nullptr;
+    std::vector<TileInfo> h_tiles_big;
     std::vector<ImgInfo> h_img;
     std::vector<TileInfo> h_tiles;
 };
@@ -106,6 +121,24 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int *scratch, int *to
     return incl - v;
 }
 
+// Exclusive prefix sum over the NT threads of a block (NT a power of two).
+template <int NT>
+__device__ __forceinline__ int block_exclusive_scan_n(int v, int *scratch, int *total) {
+    const int t = threadIdx.x;
+    scratch[t] = v;
+    __syncthreads();
+    for (int o = 1; o < NT; o <<= 1) {
+        int a = (t >= o) ? scratch[t - o] : 0;
+        __syncthreads();
+        scratch[t] += a;
+        __syncthreads();
+    }
+    int incl = scratch[t];
+    *total = scratch[NT - 1];
+    __syncthreads();
+    return incl - v;
+}
+
 // ---- launchers (host) ----------------------------------------------------
 // All launchers return hipSuccess or the launch error.
 
@@ -143,12 +176,12 @@ hipError_t launch_expand_mask(const Geometry &g, int K, const unsigned *mask_wor
 // Sum of cnt over all pixels into *out (device u64).
 hipError_t launch_sum_counts(const unsigned short *cnt, long long n, unsigned long long *out, hipStream_t s);
 
-// Filter correlation: partial[b][k][t] over block b's tiles, then a fixed-order reduction.
-int corr_blocks(const Geometry &g);
-hipError_t launch_filter_corr_f32(const Geometry &g, int K, int m, Lists z, const float *r, float *partial,
-                                  int nblocks, hipStream_t s);
-hipError_t launch_filter_corr_f64(const Geometry &g, int K, int m, Lists z, const float *x,
-                                  const unsigned char *W, double *partial, int nblocks, hipStream_t s);
+// Filter-major correlation from the per-filter lists: partial[c][k][t] over
+// chunk c of filter k's codes (corr_chunks(K) chunks), FP64 accumulation.
+int corr_chunks(int K);
+hipError_t launch_corr_fm(const Geometry &g, int K, int m, const unsigned *fm_off, const FmCode *fm, const float *r,
+                          const unsigned char *W, bool weight_rhs, double *partial, hipStream_t s);
+hipError_t launch_reduce_partials_f64_to_f32(const double *partial, int nblocks, int n, float *out, hipStream_t s);
 hipError_t launch_reduce_partials_f32(const float *partial, int nblocks, int n, float *out, hipStream_t s);
 hipError_t launch_reduce_partials_f64_add(const double *partial, int nblocks, int n, double *inout,
                                           hipStream_t s);
@@ -167,14 +200,14 @@ hipError_t launch_online_update(float *d, const double *y, const double *B, doub
                                 hipStream_t s);
 // Surrogates (lag layout).  Per-filter row lists of the non-zero codes (from
 // exact-capacity lists), C += sum Z^T W Z by owner blocks, and y = C d.
-hipError_t launch_fm_lists(const Geometry &g, int K, Lists z, unsigned *fm_cnt, unsigned *fm_off, uint2 *fm,
+hipError_t launch_fm_lists(const Geometry &g, int K, Lists z, unsigned *fm_cnt, unsigned *fm_off, FmCode *fm,
                            unsigned long long *scan_tmp, unsigned long long *total64, hipStream_t s);
-hipError_t launch_surrogate_blocks(const Geometry &g, int K, int m, const unsigned *fm_off, const uint2 *fm,
+hipError_t launch_surrogate_blocks(const Geometry &g, int K, int m, const unsigned *fm_off, const FmCode *fm,
                                    const unsigned char *W, double *C, hipStream_t s);
 // Unmasked case: lag sums (Rl: surrogate_lag_elems doubles, Es: 4 c of them), expansion, corners.
 long long surrogate_lag_elems(int K, int m);
-hipError_t launch_surrogate_unmasked(const Geometry &g, int K, int m, Lists z, const unsigned *fm_off, const uint2 *fm,
-                                     double *Rl, double *Es, double *C, hipStream_t s);
+hipError_t launch_surrogate_unmasked(const Geometry &g, int K, int m, Lists z, const unsigned *fm_off, const FmCode *fm,
+                                     double *Rl, double *Es, unsigned short *tab, double *C, hipStream_t s);
 hipError_t launch_surrogate_matvec(int K, int m, const double *C, const float *d, double *partial, double *y,
                                    hipStream_t s);
 long long surrogate_matvec_partial_elems(int K, int m);
