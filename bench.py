@@ -133,11 +133,15 @@ def main():
     torch.cuda.synchronize()
     ctx.lib.csc_profile_enable(ctx.h, 1)
     sampled = 0
+    nnz_iter = 0
+    nnz_dict = 0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.warmup, total_steps):
         st, _ = step(i)
         sampled += st.sampled
+        nnz_iter += st.nnz_iter_sum
+        nnz_dict += st.nnz
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     kernels = {}
@@ -153,25 +157,51 @@ def main():
 
     updates = sampled * w["T"]
     value = updates / el
-    # roofline of the dominant kernel class
-    dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
-    avg_s = kernels[dom]["avg_us"] * 1e-6
     M = m * m
-    if dom == "adjoint":
-        per_launch = (sampled / args.steps) * (2 * M + 4)
-        roof = {"bound": "alu", "achieved": per_launch / avg_s / 1e12, "peak": PEAK_FP32_VECTOR / 1e12,
-                "unit": "TFLOP/s"}
-    elif dom == "sur_mv":
-        per_launch = 8.0 * (K * M) ** 2
-        roof = {"bound": "hbm", "achieved": per_launch / avg_s / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s"}
+    c = m // 2
+    L2 = (2 * m - 1) ** 2
+    n_power = 20
+    # Algorithmic work of every timed launch of a kernel class, summed over the timed steps.
+    work = {
+        # one dot product of M taps per selected coordinate, then u = z + eta g and the shrink
+        "adjoint": ("alu", (2 * M + 3) * sampled * w["T"], PEAK_FP32_VECTOR),
+        # M multiply-adds per non-zero code entering a synthesis (code step + power iteration)
+        "synth": ("alu", 2 * M * (nnz_iter + n_power * nnz_dict), PEAK_FP32_VECTOR),
+        # M multiply-adds per non-zero code per correlation (power iteration + Z^T W x)
+        "corr": ("alu", 2 * M * (n_power + 1) * nnz_dict, PEAK_FP32_VECTOR),
+        # one pass over the FP64 lag-layout matrix
+        "sur_mv": ("hbm", 8.0 * (K * M) ** 2 * args.steps, PEAK_HBM),
+        # read-modify-write of C_bar plus the lag and band sums read for both halves
+        "sur_expand": ("hbm", (16.0 * (K * M) ** 2 + 8.0 * K * K * L2 * (1 + 4 * c)) * args.steps, PEAK_HBM),
+    }
+    if args.workload != "online":
+        # batch filter step: power iteration, then one residual synthesis and one correlation
+        work.pop("sur_mv")
+        work.pop("sur_expand")
+        work["synth"] = ("alu", 2 * M * (nnz_iter + (n_power + 1) * nnz_dict), PEAK_FP32_VECTOR)
+        work["corr"] = ("alu", 2 * M * (n_power + 1) * nnz_dict, PEAK_FP32_VECTOR)
+    dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
+    modelled = [k for k in kernels if k in work]
+    pick = dom if dom in work else max(modelled, key=lambda k: kernels[k]["total_ms"])
+    bound, total_work, peak = work[pick]
+    avg_s = kernels[pick]["avg_us"] * 1e-6
+    per_launch = total_work / kernels[pick]["launches"]
+    if bound == "hbm":
+        roof = {"bound": "hbm", "achieved": per_launch / avg_s / 1e9, "peak": peak / 1e9, "unit": "GB/s"}
     else:
-        roof = {"bound": "unmodelled", "achieved": None, "peak": None, "unit": None}
-    if roof["achieved"] is not None:
-        roof["frac"] = roof["achieved"] / roof["peak"]
-    else:
-        roof["frac"] = None
-    roof["kernel"] = dom
+        roof = {"bound": "alu", "achieved": per_launch / avg_s / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
     roof["traffic"] = None
+    roof["kernel"] = pick
+    roof["per_launch_work"] = per_launch
+    roof["avg_launch_us"] = kernels[pick]["avg_us"]
+    if dom != pick:
+        roof["dominant_unmodelled"] = dom
+    others = {}
+    for k in modelled:
+        b2, tw, pk = work[k]
+        ach = tw / kernels[k]["launches"] / (kernels[k]["avg_us"] * 1e-6)
+        others[k] = {"bound": b2, "frac": ach / pk}
 
     out = {
         "metric": "sampled code-coord updates/sec",
@@ -190,7 +220,9 @@ def main():
                    "K": K, "filter": m, "p": w["p"], "lambda": w["lam"], "ista_iters": w["T"],
                    "precision": args.precision},
         "roofline": roof,
+        "roofline_all": others,
         "kernels": kernels,
+        "code_density": nnz_dict / (args.steps * K * im.n_pix),
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)

@@ -74,10 +74,12 @@ typedef struct {
 
 /* Statistics of one code step (host struct, filled when non-NULL). */
 typedef struct {
-    int64_t sampled; /* |S|: selected coordinates, summed over images              */
-    int64_t nnz;     /* non-zero codes after the step                               */
-    double L_z;      /* Lipschitz bound used (0 when the caller passed a step)      */
-    double step;     /* step size used                                              */
+    int64_t sampled;      /* |S|: selected coordinates, summed over images                */
+    int64_t nnz;          /* non-zero codes after the step                                 */
+    double L_z;           /* Lipschitz bound used (0 when the caller passed a step)        */
+    double step;          /* step size used                                                */
+    int64_t nnz_iter_sum; /* sum over the iterations of the non-zero count entering each
+                             iteration's synthesis (the work of the synthesis kernel)      */
 } csc_code_stats;
 
 /* Online surrogates of eq. (7), kept as unscaled sums:
@@ -191,12 +193,15 @@ typedef enum {
     CSC_PK_LISTS = 5,    /* non-zero lists from dense codes                              */
     CSC_PK_CORR = 6,     /* filter correlation Z^T r (and Z^T W x) with its reduction    */
     CSC_PK_UPDATE = 7,   /* power-iteration and projected filter updates                */
-    CSC_PK_SUR_ACC = 8,  /* surrogate accumulation C_bar += Z^T W Z                      */
+    CSC_PK_SUR_ACC = 8,  /* surrogate accumulation C_bar += Z^T W Z with an observation mask */
     CSC_PK_SUR_MV = 9,   /* surrogate product C_bar d                                    */
     CSC_PK_OBJECTIVE = 10,
     CSC_PK_LIPSCHITZ = 11,
     CSC_PK_DENSE = 12,   /* dense operator helpers (csc_adjoint)                         */
-    CSC_PK_COUNT = 13
+    CSC_PK_SUR_LAG = 13, /* surrogate lag sums R and the band sums of the image border    */
+    CSC_PK_SUR_EXPAND = 14, /* C_bar += R - band terms, all blocks                       */
+    CSC_PK_SUR_CORNER = 15, /* corner-ring correction of C_bar                            */
+    CSC_PK_COUNT = 16
 } csc_kernel_class;
 
 /* enable != 0: record a pair of HIP events on the handle's stream around every

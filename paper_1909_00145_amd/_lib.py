@@ -35,7 +35,8 @@ class csc_images(C.Structure):
 
 
 class csc_code_stats(C.Structure):
-    _fields_ = [("sampled", C.c_int64), ("nnz", C.c_int64), ("L_z", C.c_double), ("step", C.c_double)]
+    _fields_ = [("sampled", C.c_int64), ("nnz", C.c_int64), ("L_z", C.c_double), ("step", C.c_double),
+                ("nnz_iter_sum", C.c_int64)]
 
 
 class csc_surrogate(C.Structure):
@@ -74,7 +75,7 @@ SIGNATURES = {
 
 # csc_kernel_class
 KERNEL_CLASSES = ["select", "gather", "synth", "adjoint", "scatter", "lists", "corr", "update", "sur_acc",
-                  "sur_mv", "objective", "lipschitz", "dense"]
+                  "sur_mv", "objective", "lipschitz", "dense", "sur_lag", "sur_expand", "sur_corner"]
 
 
 def load(path: str = LIB_PATH) -> C.CDLL:

@@ -42,7 +42,7 @@ enum Slot {
 };
 
 // Device scalars (doubles / u64) inside WS_SCAL.
-enum Scalar { SC_TOTAL = 0, SC_NNZ = 1, SC_LAM = 2, SC_LZ = 3, SC_OBJ = 4 /* 2 */, SC_COUNT = 8 };
+enum Scalar { SC_TOTAL = 0, SC_NNZ = 1, SC_LAM = 2, SC_LZ = 3, SC_OBJ = 4 /* 2 */, SC_NNZSUM = 6, SC_COUNT = 8 };
 
 struct Buffer {
     void *p = nullptr;
@@ -503,9 +503,11 @@ extern "C" int csc_code_step(csc_handle h, const csc_images *im, const float *x,
         nzc[1] = c1;
     }
     WS(R, float, WS_R, g.n_pix);
+    unsigned long long *nnzsum = reinterpret_cast<unsigned long long *>(sc + SC_NNZSUM);
+    HIPCHK(hipMemsetAsync(nnzsum, 0, sizeof(unsigned long long), h->stream));
     {
         PROF(CSC_PK_GATHER);
-        HIPCHK(launch_gather_selected(g, K, mw, soff, z, pairs[0], nzc[0], h->stream));
+        HIPCHK(launch_gather_selected(g, K, mw, soff, z, pairs[0], nzc[0], nnzsum, h->stream));
     }
     const float feta = (float)eta, fthr = (float)(eta * lambda);
     int cur = 0;
@@ -517,7 +519,7 @@ extern "C" int csc_code_step(csc_handle h, const csc_images *im, const float *x,
         {
             PROF(CSC_PK_ADJOINT);
             HIPCHK(launch_adjoint_shrink(g, K, m, mw, soff, pairs[cur], nzc[cur], pairs[cur ^ 1], nzc[cur ^ 1], R,
-                                         d, feta, fthr, h->stream));
+                                         d, feta, fthr, nnzsum, h->stream));
         }
         cur ^= 1;
     }
@@ -530,10 +532,13 @@ extern "C" int csc_code_step(csc_handle h, const csc_images *im, const float *x,
         HIPCHK(hipMemsetAsync(nnz, 0, sizeof(unsigned long long), h->stream));
         HIPCHK(launch_sum_counts(nzc[cur], g.n_pix, nnz, h->stream));
         if ((st = read_scalars(h, sc, SC_COUNT))) return st;
-        unsigned long long v;
+        unsigned long long v, vs;
         std::memcpy(&v, &h->h_pinned[SC_NNZ], sizeof(v));
+        std::memcpy(&vs, &h->h_pinned[SC_NNZSUM], sizeof(vs));
         stats->sampled = (int64_t)nsel;
         stats->nnz = (int64_t)v;
+        // counts written: z^0 (gather) and z^1..z^T; the synthesis consumed z^0..z^{T-1}
+        stats->nnz_iter_sum = n_iter > 0 ? (int64_t)(vs - v) : 0;
         stats->L_z = Lz;
         stats->step = eta;
     }
@@ -592,16 +597,25 @@ extern "C" int csc_dict_step(csc_handle h, const csc_images *im, const float *x,
             HIPCHK(launch_batch_update(d, G, sc + SC_LAM, K, M, h->stream));
         }
     } else {
-        {
+        if (W) {
             PROF(CSC_PK_SUR_ACC);
-            if (W) {
-                HIPCHK(launch_surrogate_blocks(g, K, m, F.off, F.codes, W, sur->C, h->stream));
-            } else {
-                const long long nl = surrogate_lag_elems(K, m);
-                WS(Rl, double, WS_LAG, nl);
-                WS(Es, double, WS_ES, nl * 4 * (m / 2 > 0 ? m / 2 : 1));
-                WS(tab, unsigned short, WS_TAB, (size_t)M * M);
-                HIPCHK(launch_surrogate_unmasked(g, K, m, L, F.off, F.codes, Rl, Es, tab, sur->C, h->stream));
+            HIPCHK(launch_surrogate_blocks(g, K, m, F.off, F.codes, W, sur->C, h->stream));
+        } else {
+            const long long nl = surrogate_lag_elems(K, m);
+            WS(Rl, double, WS_LAG, nl);
+            WS(Es, double, WS_ES, nl * 4 * (m / 2 > 0 ? m / 2 : 1));
+            WS(tab, unsigned short, WS_TAB, (size_t)M * M);
+            {
+                PROF(CSC_PK_SUR_LAG);
+                HIPCHK(launch_surrogate_lag(g, K, m, L, F.off, F.codes, Rl, Es, h->stream));
+            }
+            {
+                PROF(CSC_PK_SUR_EXPAND);
+                HIPCHK(launch_surrogate_expand(K, m, Rl, Es, tab, sur->C, h->stream));
+            }
+            {
+                PROF(CSC_PK_SUR_CORNER);
+                HIPCHK(launch_surrogate_corner(g, K, m, L, sur->C, h->stream));
             }
         }
         {

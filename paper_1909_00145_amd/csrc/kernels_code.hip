@@ -154,9 +154,16 @@ __global__ __launch_bounds__(TPB) void k_scan_add(unsigned *off, long long n, co
 __global__ __launch_bounds__(TPB) void k_gather_selected(const ImgInfo *imgs, const TileInfo *tiles, int K,
                                                          long long n_pix, const unsigned *mask_words,
                                                          const unsigned *soff, const float *z, Pair *pairs,
-                                                         unsigned short *cnt) {
+                                                         unsigned short *cnt, unsigned long long *nnz_acc) {
+    __shared__ int bsum;
+    if (threadIdx.x == 0) bsum = 0;
+    __syncthreads();
     PixelCtx c = pixel_ctx(imgs, tiles);
-    if (!c.valid) return;
+    if (!c.valid) {
+        __syncthreads();
+        if (threadIdx.x == 0 && nnz_acc && bsum) atomicAdd(nnz_acc, (unsigned long long)bsum);
+        return;
+    }
     const long long HW = (long long)c.im.H * c.im.W;
     const float *zp = z + (long long)K * c.im.pix_off + c.p_img;
     const unsigned base = soff[c.gp];
@@ -173,6 +180,9 @@ __global__ __launch_bounds__(TPB) void k_gather_selected(const ImgInfo *imgs, co
         }
     }
     cnt[c.gp] = (unsigned short)nn;
+    if (nn) atomicAdd(&bsum, nn);
+    __syncthreads();
+    if (threadIdx.x == 0 && nnz_acc && bsum) atomicAdd(nnz_acc, (unsigned long long)bsum);
 }
 
 __global__ __launch_bounds__(TPB) void k_count_nonzero(const ImgInfo *imgs, const TileInfo *tiles, int K,
@@ -394,11 +404,13 @@ __global__ __launch_bounds__(TPB) void k_adjoint_shrink(const ImgInfo *imgs, con
                                                         const unsigned short *__restrict__ oldc,
                                                         Pair *__restrict__ newp, unsigned short *__restrict__ newc,
                                                         const float *__restrict__ r, const float *__restrict__ d,
-                                                        float eta, float thr, int KC) {
+                                                        float eta, float thr, int KC,
+                                                        unsigned long long *__restrict__ nnz_acc) {
     constexpr int C = MM / 2, RW = TS + 2 * C, M = MM * MM, M4 = (M + 3) / 4 * 4;
     __shared__ float rr[RW * RW];
     __shared__ Pair op[ADJ_CAP];
     __shared__ int scratch[TPB];
+    __shared__ int bsum;
     extern __shared__ float4 dl4[];
     float *dl = reinterpret_cast<float *>(dl4);
 
@@ -470,6 +482,11 @@ __global__ __launch_bounds__(TPB) void k_adjoint_shrink(const ImgInfo *imgs, con
         }
     }
     if (c.valid) newc[c.gp] = (unsigned short)nn;
+    if (threadIdx.x == 0) bsum = 0;
+    __syncthreads();
+    if (nn) atomicAdd(&bsum, nn);
+    __syncthreads();
+    if (threadIdx.x == 0 && nnz_acc && bsum) atomicAdd(nnz_acc, (unsigned long long)bsum);
 }
 
 // Dense adjoint D^T r at every coordinate.  Thread <-> pixel with its residual
@@ -565,9 +582,10 @@ hipError_t launch_scan(const unsigned *cnt, unsigned *off, long long n, unsigned
 }
 
 hipError_t launch_gather_selected(const Geometry &g, int K, const unsigned *mask_words, const unsigned *soff,
-                                  const float *z, Pair *pairs, unsigned short *cnt, hipStream_t s) {
+                                  const float *z, Pair *pairs, unsigned short *cnt, unsigned long long *nnz_acc,
+                                  hipStream_t s) {
     hipLaunchKernelGGL(k_gather_selected, dim3(g.n_tiles), dim3(TPB), 0, s, g.d_img, g.d_tiles, K, g.n_pix,
-                       mask_words, soff, z, pairs, cnt);
+                       mask_words, soff, z, pairs, cnt, nnz_acc);
     return hipGetLastError();
 }
 
@@ -612,13 +630,14 @@ hipError_t synth_impl(const Geometry &g, int K, Lists z, const float *d, const f
 template <int MM>
 hipError_t adjoint_shrink_impl(const Geometry &g, int K, const unsigned *mw, const unsigned *soff,
                                const Pair *oldp, const unsigned short *oldc, Pair *newp, unsigned short *newc,
-                               const float *r, const float *d, float eta, float thr, hipStream_t s) {
+                               const float *r, const float *d, float eta, float thr, unsigned long long *nnz_acc,
+                               hipStream_t s) {
     constexpr int M = MM * MM, M4 = (M + 3) / 4 * 4;
     const int KC = filter_chunk<MM>();
     const int kc = K < KC ? K : KC;
     const size_t shm = (size_t)kc * M4 * sizeof(float);
     hipLaunchKernelGGL(k_adjoint_shrink<MM>, dim3(g.n_tiles), dim3(TPB), shm, s, g.d_img, g.d_tiles, K, g.n_pix,
-                       mw, soff, oldp, oldc, newp, newc, r, d, eta, thr, KC);
+                       mw, soff, oldp, oldc, newp, newc, r, d, eta, thr, KC, nnz_acc);
     return hipGetLastError();
 }
 
@@ -643,9 +662,9 @@ hipError_t launch_synth(const Geometry &g, int K, int m, Lists z, const float *d
 hipError_t launch_adjoint_shrink(const Geometry &g, int K, int m, const unsigned *mask_words,
                                  const unsigned *soff, const Pair *old_pairs, const unsigned short *old_cnt,
                                  Pair *new_pairs, unsigned short *new_cnt, const float *r, const float *d,
-                                 float eta, float thr, hipStream_t s) {
+                                 float eta, float thr, unsigned long long *nnz_acc, hipStream_t s) {
     SCSC_DISPATCH_M(m, adjoint_shrink_impl, g, K, mask_words, soff, old_pairs, old_cnt, new_pairs, new_cnt, r, d,
-                    eta, thr, s);
+                    eta, thr, nnz_acc, s);
 }
 
 hipError_t launch_adjoint_dense(const Geometry &g, int K, int m, const float *r, const float *d, float *out,

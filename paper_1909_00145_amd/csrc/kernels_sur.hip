@@ -355,6 +355,112 @@ __global__ void k_lag_table(unsigned short *tab) {
     for (int t = 0; t < wy * wx; ++t) tab[off + t] = (unsigned short)(di * 128 + t);
 }
 
+// Lag-major accumulation: workgroup (lag delta, chunk of first filters, pixel
+// chunk or band class) owns the K x K matrix R_delta[k][k2] = sum_q z_k[q]
+// z_k2[q + delta] in LDS and adds the outer products of the code lists of every
+// pixel pair (q, q + delta) of its pixel set.
+//   band == 0: every pixel of the batch, split into gridDim.z chunks; lags delta >= 0
+//     only, since R_{-delta} = R_delta^T; both halves are written into Rl[k][k2][lag]
+//     (k <= k2), added atomically when there is more than one chunk (Rl zeroed first).
+//   band == 1: blockIdx.z = side * c + j selects row (column) j of the top, bottom,
+//     left or right band of every image; every lag; stored into Es[cls][k][k2][lag].
+constexpr int LO_THREADS = 512;
+
+template <int MM>
+__global__ __launch_bounds__(LO_THREADS) void k_lag_outer(const ImgInfo *imgs, int n_img, long long n_pix, int K,
+                                                          Lists zl, int band, int KC, double *__restrict__ out) {
+    constexpr int C = MM / 2, L = 2 * MM - 1, LL = L * L;
+    constexpr int NC = C > 0 ? C : 1;
+    extern __shared__ double Rd[];  // [KC][K]
+    const int di = band ? (int)blockIdx.x : (LL - 1) / 2 + (int)blockIdx.x;
+    const int dy = di / L - 2 * C, dx = di % L - 2 * C;
+    const int klo = blockIdx.y * KC, khi = min(K, klo + KC);
+    for (int i = threadIdx.x; i < KC * K; i += LO_THREADS) Rd[i] = 0.0;
+    __syncthreads();
+    const int cls = band ? (int)blockIdx.z : -1;
+    const int side = band ? cls / NC : -1, j = band ? cls % NC : 0;
+    // pixel chunk of the batch (band == 0)
+    const long long chunk = band ? 0 : (n_pix + gridDim.z - 1) / gridDim.z;
+    const long long plo = band ? 0 : chunk * blockIdx.z, phi = band ? 0 : min(n_pix, plo + chunk);
+    for (int n = 0; n < n_img; ++n) {
+        const ImgInfo im = imgs[n];
+        const long long isz = (long long)im.H * im.W;
+        long long tlo = 0, thi;
+        if (!band) {
+            tlo = max(0LL, plo - im.pix_off);
+            thi = min(isz, phi - im.pix_off);
+        } else if (side < 2) {
+            thi = (j < im.H) ? im.W : 0;
+        } else {
+            thi = (j < im.W) ? im.H : 0;
+        }
+        for (long long t = tlo + threadIdx.x; t < thi; t += LO_THREADS) {
+            int y, x;
+            if (!band) {
+                y = (int)(t / im.W);
+                x = (int)(t % im.W);
+            } else if (side == 0) {
+                y = j;
+                x = (int)t;
+            } else if (side == 1) {
+                y = im.H - 1 - j;
+                x = (int)t;
+            } else if (side == 2) {
+                y = (int)t;
+                x = j;
+            } else {
+                y = (int)t;
+                x = im.W - 1 - j;
+            }
+            const int y2 = y + dy, x2 = x + dx;
+            if (y2 < 0 || y2 >= im.H || x2 < 0 || x2 >= im.W) continue;
+            const long long gp = im.pix_off + (long long)y * im.W + x;
+            const int ca = zl.cnt[gp];
+            if (ca == 0) continue;
+            const long long gp2 = im.pix_off + (long long)y2 * im.W + x2;
+            const int cb = zl.cnt[gp2];
+            if (cb == 0) continue;
+            const unsigned oa = zl.off[gp], ob = zl.off[gp2];
+            for (int u = 0; u < ca; ++u) {
+                const Pair ea = zl.pairs[oa + u];
+                if (ea.k < klo || ea.k >= khi) continue;
+                double *row = Rd + (long long)(ea.k - klo) * K;
+                const double va = (double)ea.v;
+                for (int w = 0; w < cb; ++w) {
+                    const Pair eb = zl.pairs[ob + w];
+                    atomicAdd(row + eb.k, va * (double)eb.v);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    const bool accumulate = !band && gridDim.z > 1;
+    const int centre = (LL - 1) / 2;
+    for (int i = threadIdx.x; i < (khi - klo) * K; i += LO_THREADS) {
+        const int k = klo + i / K, k2 = i % K;
+        const double v = Rd[i];
+        if (band) {
+            if (k <= k2) out[(((long long)cls * K + k) * K + k2) * LL + di] = v;
+            continue;
+        }
+        // R_delta[k][k2] is entry (k, k2) at lag delta and entry (k2, k) at lag -delta
+        // (a diagonal block k == k2 takes both)
+        for (int h = 0; h < 2; ++h) {
+            long long pos;
+            if (h == 0 && k <= k2) pos = ((long long)k * K + k2) * LL + di;
+            else if (h == 1 && k2 <= k && di != centre) pos = ((long long)k2 * K + k) * LL + (LL - 1 - di);
+            else continue;
+            if (accumulate) atomicAdd(out + pos, v);
+            else out[pos] = v;
+        }
+    }
+}
+
+__global__ void k_zero_f64(double *p, long long n) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        p[i] = 0.0;
+}
+
 // C_bar(a, b) += R - E_top - E_bottom - E_left - E_right for every block (a, b).
 // The lag sums are kept for k <= k2 only; block (a, b) with b < a is the
 // transpose of (b, a), whose run at lag -delta holds the same values in the same
@@ -575,47 +681,6 @@ hipError_t launch_surrogate_blocks(const Geometry &g, int K, int m, const unsign
 
 long long surrogate_matvec_partial_elems(int K, int m) { return (long long)K * K * 2 * m * m; }
 
-long long surrogate_lag_elems(int K, int m) { return (long long)K * K * (2 * m - 1) * (2 * m - 1); }
-
-namespace {
-template <int MM>
-hipError_t sur_unmasked_impl(const Geometry &g, int K, Lists z, const unsigned *fm_off, const FmCode *fm, double *Rl,
-                             double *Es, unsigned short *tab, double *C, hipStream_t s) {
-    constexpr int Cc = MM / 2, L = 2 * MM - 1, LL = L * L;
-    const int R = g.n_rows;
-    const int ndc = (LL + LG_DC - 1) / LG_DC, nkb = (K + LG_KB - 1) / LG_KB;
-    hipLaunchKernelGGL(k_sur_lag<MM>, dim3(ndc, K, nkb), dim3(LG_THREADS), sizeof(double) * LG_KB * LG_DC, s, g.d_img,
-                       g.n_img, K, R, fm_off, fm, z, -1, LG_KB, Rl);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    const int nkbs = (K + LG_KB_SIDE - 1) / LG_KB_SIDE;
-    for (int side = 0; side < 4 && Cc > 0; ++side) {
-        hipLaunchKernelGGL(k_sur_lag<MM>, dim3(ndc, K, nkbs), dim3(LG_THREADS),
-                           sizeof(double) * Cc * LG_KB_SIDE * LG_DC, s, g.d_img, g.n_img, K, R, fm_off, fm, z, side,
-                           LG_KB_SIDE, Es);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL(k_lag_table<MM>, dim3((LL + 63) / 64), dim3(64), 0, s, tab);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_sur_expand<MM>, dim3(K, K), dim3(EX_THREADS), 0, s, K, Rl, Es, tab, C);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_sur_corner<MM>, dim3(g.n_img, 4), dim3(256), 0, s, g.d_img, K, z, C);
-    return hipGetLastError();
-}
-}  // namespace
-
-hipError_t launch_surrogate_unmasked(const Geometry &g, int K, int m, Lists z, const unsigned *fm_off, const FmCode *fm,
-                                     double *Rl, double *Es, unsigned short *tab, double *C, hipStream_t s) {
-    switch (m) {
-        case 3: return sur_unmasked_impl<3>(g, K, z, fm_off, fm, Rl, Es, tab, C, s);
-        case 5: return sur_unmasked_impl<5>(g, K, z, fm_off, fm, Rl, Es, tab, C, s);
-        case 7: return sur_unmasked_impl<7>(g, K, z, fm_off, fm, Rl, Es, tab, C, s);
-        case 9: return sur_unmasked_impl<9>(g, K, z, fm_off, fm, Rl, Es, tab, C, s);
-        case 11: return sur_unmasked_impl<11>(g, K, z, fm_off, fm, Rl, Es, tab, C, s);
-        default: return hipErrorInvalidValue;
-    }
-}
-
 hipError_t launch_surrogate_matvec(int K, int m, const double *C, const float *d, double *partial, double *y,
                                    hipStream_t s) {
     switch (m) {
@@ -626,6 +691,82 @@ hipError_t launch_surrogate_matvec(int K, int m, const double *C, const float *d
         case 11: return sur_mv_impl<11>(K, C, d, partial, y, s);
         default: return hipErrorInvalidValue;
     }
+}
+
+long long surrogate_lag_elems(int K, int m) { return (long long)K * K * (2 * m - 1) * (2 * m - 1); }
+
+namespace {
+template <int MM>
+hipError_t sur_lag_impl(const Geometry &g, int K, Lists z, const unsigned *fm_off, const FmCode *fm, double *Rl,
+                        double *Es, hipStream_t s) {
+    (void)fm_off;
+    (void)fm;
+    constexpr int Cc = MM / 2, L = 2 * MM - 1, LL = L * L;
+    int KC = (80 * 1024) / (8 * K);
+    if (KC > K) KC = K;
+    if (KC < 1) KC = 1;
+    const int nkc = (K + KC - 1) / KC;
+    const size_t shm = sizeof(double) * (size_t)KC * K;
+    const int nlag = (LL + 1) / 2;
+    // pixel chunks: enough workgroups to cover the chip a few times, at least 2048 pixels each
+    long long P = 2048 / ((long long)nlag * nkc);
+    P = std::max(1LL, std::min(P, (long long)(g.n_pix / 2048)));
+    hipError_t e;
+    if (P > 1) {
+        const long long n = (long long)K * K * LL;
+        hipLaunchKernelGGL(k_zero_f64, dim3(1024), dim3(256), 0, s, Rl, n);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_lag_outer<MM>, dim3(nlag, nkc, (unsigned)P), dim3(LO_THREADS), shm, s, g.d_img, g.n_img,
+                       (long long)g.n_pix, K, z, 0, KC, Rl);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (Cc > 0) {
+        hipLaunchKernelGGL(k_lag_outer<MM>, dim3(LL, nkc, 4 * Cc), dim3(LO_THREADS), shm, s, g.d_img, g.n_img,
+                           (long long)g.n_pix, K, z, 1, KC, Es);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+template <int MM>
+hipError_t sur_expand_impl(int K, const double *Rl, const double *Es, unsigned short *tab, double *C, hipStream_t s) {
+    constexpr int L = 2 * MM - 1, LL = L * L;
+    hipLaunchKernelGGL(k_lag_table<MM>, dim3((LL + 63) / 64), dim3(64), 0, s, tab);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sur_expand<MM>, dim3(K, K), dim3(EX_THREADS), 0, s, K, Rl, Es, tab, C);
+    return hipGetLastError();
+}
+
+template <int MM>
+hipError_t sur_corner_impl(const Geometry &g, int K, Lists z, double *C, hipStream_t s) {
+    hipLaunchKernelGGL(k_sur_corner<MM>, dim3(g.n_img, 4), dim3(256), 0, s, g.d_img, K, z, C);
+    return hipGetLastError();
+}
+}  // namespace
+
+#define SCSC_DISPATCH_M(m, FN, ...)          \
+    switch (m) {                             \
+        case 3: return FN<3>(__VA_ARGS__);   \
+        case 5: return FN<5>(__VA_ARGS__);   \
+        case 7: return FN<7>(__VA_ARGS__);   \
+        case 9: return FN<9>(__VA_ARGS__);   \
+        case 11: return FN<11>(__VA_ARGS__); \
+        default: return hipErrorInvalidValue; \
+    }
+
+hipError_t launch_surrogate_lag(const Geometry &g, int K, int m, Lists z, const unsigned *fm_off, const FmCode *fm,
+                                double *Rl, double *Es, hipStream_t s) {
+    SCSC_DISPATCH_M(m, sur_lag_impl, g, K, z, fm_off, fm, Rl, Es, s);
+}
+
+hipError_t launch_surrogate_expand(int K, int m, const double *Rl, const double *Es, unsigned short *tab, double *C,
+                                   hipStream_t s) {
+    SCSC_DISPATCH_M(m, sur_expand_impl, K, Rl, Es, tab, C, s);
+}
+
+hipError_t launch_surrogate_corner(const Geometry &g, int K, int m, Lists z, double *C, hipStream_t s) {
+    SCSC_DISPATCH_M(m, sur_corner_impl, g, K, z, C, s);
 }
 
 }  // namespace scsc

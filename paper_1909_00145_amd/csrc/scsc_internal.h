@@ -152,8 +152,10 @@ long long scan_tmp_elems(long long n);
 hipError_t launch_scan(const unsigned *cnt, unsigned *off, long long n, unsigned long long *tmp,
                        unsigned long long *total64, hipStream_t s);
 // Warm start: list of non-zero selected codes of z_prev (eq. 4 restricted to S).
+// nnz_acc (device, may be null) accumulates the number of non-zeros written.
 hipError_t launch_gather_selected(const Geometry &g, int K, const unsigned *mask_words, const unsigned *soff,
-                                  const float *z, Pair *pairs, unsigned short *cnt, hipStream_t s);
+                                  const float *z, Pair *pairs, unsigned short *cnt, unsigned long long *nnz_acc,
+                                  hipStream_t s);
 // Mode of the synthesis kernel.
 enum SynthMode { SYNTH_RESIDUAL = 0, SYNTH_PLAIN = 1, SYNTH_WEIGHTED = 2 };
 // out = W (x - D z) (RESIDUAL), D z (PLAIN) or W (D z) (WEIGHTED); z given as lists.
@@ -163,7 +165,7 @@ hipError_t launch_synth(const Geometry &g, int K, int m, Lists z, const float *d
 hipError_t launch_adjoint_shrink(const Geometry &g, int K, int m, const unsigned *mask_words,
                                  const unsigned *soff, const Pair *old_pairs, const unsigned short *old_cnt,
                                  Pair *new_pairs, unsigned short *new_cnt, const float *r, const float *d,
-                                 float eta, float thr, hipStream_t s);
+                                 float eta, float thr, unsigned long long *nnz_acc, hipStream_t s);
 // Dense codes from lists (zeros elsewhere).
 hipError_t launch_scatter_dense(const Geometry &g, int K, Lists z, float *zout, hipStream_t s);
 // Lists of the non-zero codes of a dense z: count, then fill.
@@ -206,8 +208,11 @@ hipError_t launch_surrogate_blocks(const Geometry &g, int K, int m, const unsign
                                    const unsigned char *W, double *C, hipStream_t s);
 // Unmasked case: lag sums (Rl: surrogate_lag_elems doubles, Es: 4 c of them), expansion, corners.
 long long surrogate_lag_elems(int K, int m);
-hipError_t launch_surrogate_unmasked(const Geometry &g, int K, int m, Lists z, const unsigned *fm_off, const FmCode *fm,
-                                     double *Rl, double *Es, unsigned short *tab, double *C, hipStream_t s);
+hipError_t launch_surrogate_lag(const Geometry &g, int K, int m, Lists z, const unsigned *fm_off, const FmCode *fm,
+                                double *Rl, double *Es, hipStream_t s);
+hipError_t launch_surrogate_expand(int K, int m, const double *Rl, const double *Es, unsigned short *tab, double *C,
+                                   hipStream_t s);
+hipError_t launch_surrogate_corner(const Geometry &g, int K, int m, Lists z, double *C, hipStream_t s);
 hipError_t launch_surrogate_matvec(int K, int m, const double *C, const float *d, double *partial, double *y,
                                    hipStream_t s);
 long long surrogate_matvec_partial_elems(int K, int m);

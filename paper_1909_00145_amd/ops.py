@@ -70,6 +70,7 @@ class CodeStats:
     nnz: int
     L_z: float
     step: float
+    nnz_iter_sum: int = 0
 
 
 class Surrogate:
@@ -187,7 +188,7 @@ class Context:
             PRECISIONS[precision], C.byref(st) if stats else None)
         self._check(rc)
         if stats:
-            return CodeStats(st.sampled, st.nnz, st.L_z, st.step)
+            return CodeStats(st.sampled, st.nnz, st.L_z, st.step, st.nnz_iter_sum)
         return None
 
     def dict_step(self, im: Images, x, z, d, n_iter=1, step=0.0, n_power=20, W=None, surrogate: Surrogate = None,

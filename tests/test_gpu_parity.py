@@ -153,6 +153,15 @@ def test_code_step_warm_start_and_zero_iterations(ctx):
     assert rel_err(got[0], refs[0]) < TOL32
 
 
+def test_code_step_nnz_iter_sum(ctx):
+    """nnz_iter_sum counts the non-zeros entering each iteration's synthesis."""
+    hw = [(40, 37)]
+    got1, refs1, st1, _ = run_code_step(ctx, hw, 9, 5, 0.3, 0.5, 4, 2, 1)
+    _, _, st2, _ = run_code_step(ctx, hw, 9, 5, 0.3, 0.5, 4, 2, 2)
+    assert st1.nnz_iter_sum == 0  # z^0 = 0
+    assert st2.nnz_iter_sum == st1.nnz == int(np.count_nonzero(got1[0]))  # z^0 = 0, then z^1
+
+
 def test_code_step_large_lambda_is_zero(ctx):
     got, refs, st, _ = run_code_step(ctx, [(30, 30)], 8, 5, 1e6, 0.5, 1, 1, 5)
     assert np.count_nonzero(got[0]) == 0 and st.nnz == 0
