@@ -34,6 +34,32 @@ if ROOT not in sys.path:
 PEAK_FP32_VECTOR = 157.3e12
 PEAK_HBM = 8.0e12
 
+# HBM bytes per launch of each kernel class's main kernel on the online workload, from
+# rocprofv3 FETCH_SIZE / WRITE_SIZE passes scaled by a 512 MiB copy (read x 2.000, write x 1.000),
+# valid only for the kernel source they were taken on (first 16 hex digits of its SHA-256).
+TRAFFIC = {
+    "synth": ("kernels_code.hip", "188f7209c24cf146", 31.69e6, 1.02e6),
+    "adjoint": ("kernels_code.hip", "188f7209c24cf146", 34.19e6, 11.20e6),
+    "corr": ("kernels_dict.hip", "98c4ceeed6c06dea", 27.00e6, 4.07e6),
+    "sur_mv": ("kernels_sur.hip", "e6370a4aa64d03a0", 597.03e6, 9.91e6),
+    "sur_expand": ("kernels_sur.hip", "e6370a4aa64d03a0", 1943.22e6, 1171.86e6),
+}
+
+
+def traffic_for(cls, workload):
+    """Calibrated HBM bytes per launch, or None when the kernel changed since the counters were taken."""
+    import hashlib
+
+    if workload != "online" or cls not in TRAFFIC:
+        return None
+    src, sha, rd, wr = TRAFFIC[cls]
+    path = os.path.join(ROOT, "paper_1909_00145_amd", "csrc", src)
+    try:
+        cur = hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    return rd + wr if cur == sha else None
+
 WORKLOADS = {
     "online": dict(N=20, H=100, W=100, K=100, m=11, p=0.1, lam=1.0, T=20, cfg=3,
                    name="online SOCSC: mini-batches of 20 images 100x100 (1/f^2), K=100 filters 11x11, "
@@ -54,6 +80,9 @@ def parse():
     ap.add_argument("--p", type=float, default=None, help="override the sampling rate")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="after the timed steps, copy a buffer of this many MiB 3 times (a traffic-counter "
+                         "calibration kernel of known size; outside the timed region)")
     return ap.parse_args()
 
 
@@ -155,6 +184,15 @@ def main():
             kernels[name] = {"launches": int(n.value), "avg_us": 1e3 * ms.value / n.value, "total_ms": ms.value}
     ctx.lib.csc_profile_enable(ctx.h, 0)
 
+    if args.copy_probe_mb > 0:
+        nb = args.copy_probe_mb << 20
+        src = torch.ones(nb // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     updates = sampled * w["T"]
     value = updates / el
     M = m * m
@@ -169,8 +207,8 @@ def main():
         "synth": ("alu", 2 * M * (nnz_iter + n_power * nnz_dict), PEAK_FP32_VECTOR),
         # M multiply-adds per non-zero code per correlation (power iteration + Z^T W x)
         "corr": ("alu", 2 * M * (n_power + 1) * nnz_dict, PEAK_FP32_VECTOR),
-        # one pass over the FP64 lag-layout matrix
-        "sur_mv": ("hbm", 8.0 * (K * M) ** 2 * args.steps, PEAK_HBM),
+        # one pass over the blocks (k, k2 >= k) of the FP64 lag-layout matrix (the rest is their transpose)
+        "sur_mv": ("hbm", 8.0 * (K * (K + 1) // 2) * M * M * args.steps, PEAK_HBM),
         # read-modify-write of C_bar plus the lag and band sums read for both halves
         "sur_expand": ("hbm", (16.0 * (K * M) ** 2 + 8.0 * K * K * L2 * (1 + 4 * c)) * args.steps, PEAK_HBM),
     }
@@ -191,7 +229,7 @@ def main():
     else:
         roof = {"bound": "alu", "achieved": per_launch / avg_s / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
+    roof["traffic"] = traffic_for(pick, args.workload)
     roof["kernel"] = pick
     roof["per_launch_work"] = per_launch
     roof["avg_launch_us"] = kernels[pick]["avg_us"]
@@ -201,7 +239,7 @@ def main():
     for k in modelled:
         b2, tw, pk = work[k]
         ach = tw / kernels[k]["launches"] / (kernels[k]["avg_us"] * 1e-6)
-        others[k] = {"bound": b2, "frac": ach / pk}
+        others[k] = {"bound": b2, "frac": ach / pk, "traffic": traffic_for(k, args.workload)}
 
     out = {
         "metric": "sampled code-coord updates/sec",

@@ -5,7 +5,7 @@
  * (VMV 2019).  The library computes the data-parallel hot path of that method:
  * the Bernoulli-subsampled code update (Sec. 3.1, eqs. 2-4, solved here by
  * proximal gradient), the filter update of eq. (5), the online surrogates of
- * eqs. (7)-(8), and the objective of eq. (1).
+ * eqs. (8)-(9), and the objective of eq. (1).
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -82,9 +82,9 @@ typedef struct {
                              iteration's synthesis (the work of the synthesis kernel)      */
 } csc_code_stats;
 
-/* Online surrogates of eq. (7), kept as unscaled sums:
+/* Online surrogates of eq. (8), kept as unscaled sums:
  *   C_bar = sum_t sum_{i in batch t} Z_i^T W_i Z_i,  B_bar = sum_t sum_i Z_i^T W_i x_i,
- * so that C^t = C_bar / t and B^t = B_bar / t equal the recursion of eq. (7).
+ * so that C^t = C_bar / t and B^t = B_bar / t equal the recursion of eq. (8).
  * C is stored in the lag layout (csc_surrogate_index gives the position of any
  * dense entry); B is [K][m][m].  t and Ld_sum live on the host and are updated
  * by csc_dict_step.  Start from C = 0, B = 0, t = 0, Ld_sum = 0. */
@@ -136,7 +136,7 @@ int csc_code_step(csc_handle h, const csc_images *im, const float *x, const uint
  *   step <= 0 selects 1 / L_d, L_d = power-iteration estimate (n_power iterations from
  *   the normalised all-ones vector, last Rayleigh quotient) of
  *   lambda_max(sum_i Z_i^T W_i Z_i); when L_d = 0 the codes are all zero and d is only projected.
- * sur != NULL: online problem, eqs. (7)-(8): C_bar += sum_i Z_i^T W_i Z_i,
+ * sur != NULL: online problem, eqs. (8)-(9): C_bar += sum_i Z_i^T W_i Z_i,
  *   B_bar += sum_i Z_i^T W_i x_i, t += 1, Ld_sum += L_d(this batch); then n_iter steps
  *     d <- P(d - (C_bar d - B_bar) / Ld_sum)      (= P(d - (C^t d - B^t) / (Ld_sum / t))).
  *   step is ignored in this mode.

@@ -16,7 +16,7 @@ Pins (all in ``tests/test_oracle_*.py``, run without a GPU):
 * step sizes: L_z >= ||D||^2 by SVD of the explicit operator, L_d against
   eigvalsh of the explicit normal matrix;
 * filter steps: the single-delta-code closed form, the surrogate identity
-  C d - B = -Z^T W r, symmetry / PSD and the eq. (7) recursion.
+  C d - B = -Z^T W r, symmetry / PSD and the eq. (8) recursion.
 """
 
 from .csc import (  # noqa: F401

@@ -24,7 +24,7 @@ is listed with its reason in the design notes):
 * Code solver: proximal gradient (ISTA) on the subsampled LASSO of eq. (3),
   step 1/L_z, unselected coordinates held at zero (the upsampling of eq. (4)).
 * Filter solver: projected gradient on eq. (5) (batch) or on the surrogate
-  problem eq. (8) with surrogates accumulated per eq. (7) (online).
+  problem eq. (9) with surrogates accumulated per eq. (8) (online).
 
 Every array is float64 unless noted.  Batches are Python lists (images may have
 different sizes).
@@ -254,7 +254,7 @@ def objective(xs, d, zs, lam: float, Ws=None):
 
 
 # ---------------------------------------------------------------------------
-# Filter update: eq. (5) (batch) and eqs. (7)-(8) (online)
+# Filter update: eq. (5) (batch) and eqs. (8)-(9) (online)
 # ---------------------------------------------------------------------------
 
 
@@ -324,7 +324,7 @@ def dict_step_batch(xs, Ws, zs, d: np.ndarray, n_iter: int = 1, step: float | No
 
 
 def surrogate_increment(xs, Ws, zs, K: int, m: int):
-    """(sum_n Z_n^T W_n Z_n, sum_n Z_n^T W_n x_n): the batch terms of eq. (7).
+    """(sum_n Z_n^T W_n Z_n, sum_n Z_n^T W_n x_n): the batch terms of eq. (8).
 
     Returned dense: C_inc [K*m*m, K*m*m], B_inc [K*m*m] (row-major flattening of d).
     """
@@ -343,7 +343,7 @@ def surrogate_increment(xs, Ws, zs, K: int, m: int):
 class OnlineState:
     """State of the online learner: unscaled sums C_bar, B_bar, the count t and the
     running sum of per-batch L_d estimates.  C^t = C_bar / t and B^t = B_bar / t
-    equal the recursion of eq. (7) started from zero."""
+    equal the recursion of eq. (8) started from zero."""
 
     def __init__(self, K: int, m: int):
         KM = K * m * m

@@ -1,6 +1,6 @@
 // Filter-update kernels for gfx950: the filter correlation Z^T r of eq. (5),
 // power iteration for its step size, the projected updates, and the online
-// surrogates of eqs. (7)-(8) in FP64.
+// surrogates of eqs. (8)-(9) in FP64.
 #include "scsc_internal.h"
 
 namespace scsc {
@@ -15,7 +15,7 @@ constexpr int CORR_MAX_BLOCKS = 512;
 // partial G lives in LDS.  Wave w of the block owns the filters k with
 // (k - k0) % 4 == w and lane l the taps l, l + 64, so every partial cell has a
 // single writer and a fixed accumulation order: the result is deterministic.
-// FROM_X selects the right-hand side W x (for B of eq. 7) instead of r.
+// FROM_X selects the right-hand side W x (for B of eq. 8) instead of r.
 // ---------------------------------------------------------------------------
 // ---------------------------------------------------------------------------
 // Filter correlation G_k[s] = sum_q z_k[q] r[q + s] (r zero outside the image),

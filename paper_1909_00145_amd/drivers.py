@@ -2,8 +2,8 @@
 
 Both alternate a subsampled code update (eqs. 2-4) with a filter update; the
 batch learner solves eq. (5) over all images each outer iteration, the online
-learner draws a mini-batch per iteration and updates the surrogates of eq. (7)
-before solving eq. (8).  Mini-batching (the paper's extension of Alg. 2) is the
+learner draws a mini-batch per iteration and updates the surrogates of eq. (8)
+before solving eq. (9).  Mini-batching (the paper's extension of Alg. 2) is the
 batch dimension of every call.
 """
 

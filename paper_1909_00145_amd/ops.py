@@ -74,7 +74,7 @@ class CodeStats:
 
 
 class Surrogate:
-    """Online surrogates of eq. (7) as unscaled sums on the device (FP64).
+    """Online surrogates of eq. (8) as unscaled sums on the device (FP64).
 
     ``C`` is in the library's lag layout (``csc_surrogate_index``); ``dense_C()``
     reorders it for inspection (small K only)."""

@@ -1,11 +1,11 @@
-"""Pins for the oracle's filter updates: batch eq. (5) and online eqs. (7)-(8).
+"""Pins for the oracle's filter updates: batch eq. (5) and online eqs. (8)-(9).
 
 * one delta code (K = 1, z = e_q inside the image): Z^T Z = I, L_d = 1 and one
   projected step from any d lands on P(patch_q(x)) -- exactly;
 * L_d from power iteration against eigvalsh of the explicit normal matrix;
 * surrogates: symmetric PSD, diag(C)_(k,s) = sum_p z_k[p - s]^2 (written from
   the definition with loops), C d - B = -Z^T W (x - Z d), and the running
-  sums divided by t equal the eq. (7) recursion;
+  sums divided by t equal the eq. (8) recursion;
 * the online step at t = 1 equals the batch projected-gradient step with the
   same step size.
 """
