@@ -134,8 +134,12 @@ int csc_code_step(csc_handle h, const csc_images *im, const float *x, const uint
  * sur == NULL: batch problem eq. (5), n_iter projected-gradient steps
  *     d <- P(d + step * sum_i Z_i^T W_i (x_i - Z_i d)),   P = projection onto ||d_k|| <= 1,
  *   step <= 0 selects 1 / L_d, L_d = power-iteration estimate (n_power iterations from
- *   the normalised all-ones vector, last Rayleigh quotient) of
- *   lambda_max(sum_i Z_i^T W_i Z_i); when L_d = 0 the codes are all zero and d is only projected.
+ *   the normalised all-ones vector, last Rayleigh quotient) of lambda_max(A):
+ *   with an observation mask A = sum_i Z_i^T W_i Z_i; without one A is the
+ *   zero-padded normal matrix (codes embedded in c zero pixels), whose entry
+ *   (k, s; k2, s2) is the lag sum sum_q z_k[q] z_k2[q + s - s2]; it dominates
+ *   sum_i Z_i^T Z_i, so 1 / L_d stays a descent step.  When L_d = 0 the codes are
+ *   all zero and d is only projected.
  * sur != NULL: online problem, eqs. (8)-(9): C_bar += sum_i Z_i^T W_i Z_i,
  *   B_bar += sum_i Z_i^T W_i x_i, t += 1, Ld_sum += L_d(this batch); then n_iter steps
  *     d <- P(d - (C_bar d - B_bar) / Ld_sum)      (= P(d - (C^t d - B^t) / (Ld_sum / t))).
@@ -201,7 +205,8 @@ typedef enum {
     CSC_PK_SUR_LAG = 13, /* surrogate lag sums R and the band sums of the image border    */
     CSC_PK_SUR_EXPAND = 14, /* C_bar += R - band terms, all blocks                       */
     CSC_PK_SUR_CORNER = 15, /* corner-ring correction of C_bar                            */
-    CSC_PK_COUNT = 16
+    CSC_PK_POWER = 16,   /* power-iteration products with the lag-sum normal matrix      */
+    CSC_PK_COUNT = 17
 } csc_kernel_class;
 
 /* enable != 0: record a pair of HIP events on the handle's stream around every
@@ -210,6 +215,17 @@ int csc_profile_enable(csc_handle h, int enable);
 /* Launch count and summed event time (milliseconds) of one kernel class since
  * profiling was enabled.  Host outputs.  Synchronises the stream. */
 int csc_profile_read(csc_handle h, int kernel_class, int64_t *launches, double *total_ms);
+
+/* Launch-variant autotuning (tile shape / threads per output pixel) of the
+ * kernels that have several variants.  enable != 0 (the default): the first
+ * call with a new (kernel, m, K, batch size class) times every variant on that
+ * call's own data and keeps the fastest for the handle's lifetime; this first
+ * call synchronises the stream and is skipped while the stream is being
+ * captured.  enable == 0: the first variant is always used and the tuned
+ * choices are forgotten.  enable = -(v + 1) < 0: variant v is always used where
+ * it exists (the first variant elsewhere), for testing.  Every variant computes
+ * bit-identical results, so the setting changes timing only. */
+int csc_set_autotune(csc_handle h, int enable);
 
 #ifdef __cplusplus
 }

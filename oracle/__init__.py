@@ -14,7 +14,8 @@ Pins (all in ``tests/test_oracle_*.py``, run without a GPU):
   converged solution against scikit-learn's coordinate-descent Lasso on the
   explicit subsampled operator;
 * step sizes: L_z >= ||D||^2 by SVD of the explicit operator, L_d against
-  eigvalsh of the explicit normal matrix;
+  eigvalsh of the explicit (masked, or zero-padded) normal matrix, the padded
+  matrix against brute-force lag sums and its dominance over the exact one;
 * filter steps: the single-delta-code closed form, the surrogate identity
   C d - B = -Z^T W r, symmetry / PSD and the eq. (8) recursion.
 """
@@ -32,6 +33,7 @@ from .csc import (  # noqa: F401
     lipschitz_code,
     lipschitz_filter,
     normal_matvec,
+    pad_codes,
     objective,
     project_ball,
     sample_threshold,

@@ -268,30 +268,54 @@ def _weight(Ws, i):
     return None if Ws is None or Ws[i] is None else Ws[i].astype(np.float64)
 
 
-def normal_matvec(zs, Ws, v: np.ndarray) -> np.ndarray:
-    """sum_n Z_n^T W_n Z_n v (v filter-shaped [K, m, m])."""
+def pad_codes(z: np.ndarray, c: int) -> np.ndarray:
+    """Codes [K, H, W] embedded with c zero pixels on every side: [K, H + 2c, W + 2c]."""
+    K, H, W = z.shape
+    zp = np.zeros((K, H + 2 * c, W + 2 * c))
+    zp[:, c : c + H, c : c + W] = z
+    return zp
+
+
+def normal_matvec(zs, Ws, v: np.ndarray, padded: bool = False) -> np.ndarray:
+    """sum_n Z_n^T W_n Z_n v (v filter-shaped [K, m, m]).
+
+    padded: use the operator Z_n on codes embedded in c zero pixels, i.e. the
+    synthesis over the image grown by c (every window that meets the image).
+    Its normal matrix is block Toeplitz in the taps: entry (k, s; k2, s2) is the
+    lag sum sum_q z_k[q] z_k2[q + s - s2] over the whole image, and it dominates
+    the exact sum_n Z_n^T Z_n.  Only defined without an observation mask."""
     m = v.shape[1]
     out = np.zeros_like(v)
     for i, z in enumerate(zs):
-        y = synthesize(v, z)
         Wm = _weight(Ws, i)
+        if padded:
+            if Wm is not None:
+                raise ValueError("the padded normal operator has no observation mask")
+            z = pad_codes(z, m // 2)
+        y = synthesize(v, z)
         if Wm is not None:
             y = Wm * y
         out += filter_corr(z, y, m)
     return out
 
 
-def lipschitz_filter(zs, Ws, K: int, m: int, n_power: int = 20) -> float:
-    """Power-iteration estimate of lambda_max(sum_n Z_n^T W_n Z_n).
+def lipschitz_filter(zs, Ws, K: int, m: int, n_power: int = 20, padded: bool | None = None) -> float:
+    """Power-iteration estimate of the filter-step Lipschitz constant L_d.
 
+    The operator is sum_n Z_n^T W_n Z_n with an observation mask, and the
+    zero-padded sum_n Z_n^T Z_n of ``normal_matvec(padded=True)`` without one
+    (padded=None picks this way).  The padded matrix dominates the exact one,
+    so 1 / L_d remains a safe step, and it is built from lag sums alone.
     Starts from the normalised all-ones vector; each iteration takes
     w = A v, the Rayleigh quotient v^T w, and v <- w / ||w||.  Returns the
     last Rayleigh quotient (0 when A v vanishes).
     """
+    if padded is None:
+        padded = Ws is None or all(w is None for w in Ws)
     v = np.ones((K, m, m)) / math.sqrt(K * m * m)
     lam = 0.0
     for _ in range(n_power):
-        w = normal_matvec(zs, Ws, v)
+        w = normal_matvec(zs, None if padded else Ws, v, padded=padded)
         lam = float(np.sum(v * w))
         nw = math.sqrt(float(np.sum(w * w)))
         if nw == 0.0:

@@ -71,11 +71,12 @@ SIGNATURES = {
     "csc_surrogate_index": (C.c_int64, [_i, _i, _i, _i, _i, _i, _i, _i]),
     "csc_profile_enable": (_i, [_vp, _i]),
     "csc_profile_read": (_i, [_vp, _i, C.POINTER(C.c_int64), C.POINTER(_d)]),
+    "csc_set_autotune": (_i, [_vp, _i]),
 }
 
 # csc_kernel_class
 KERNEL_CLASSES = ["select", "gather", "synth", "adjoint", "scatter", "lists", "corr", "update", "sur_acc",
-                  "sur_mv", "objective", "lipschitz", "dense", "sur_lag", "sur_expand", "sur_corner"]
+                  "sur_mv", "objective", "lipschitz", "dense", "sur_lag", "sur_expand", "sur_corner", "power"]
 
 
 def load(path: str = LIB_PATH) -> C.CDLL:

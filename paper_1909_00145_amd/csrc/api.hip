@@ -1,7 +1,10 @@
 // C ABI of the gfx950 stochastic-CSC library: handle, workspaces, argument
 // validation, batch geometry, and the entry points declared in scsc.h.
+#include <array>
 #include <cmath>
 #include <cstring>
+#include <functional>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -70,6 +73,10 @@ struct csc_ctx {
     std::vector<Rec> recs;
     long long prof_launches[CSC_PK_COUNT] = {};
     double prof_ms[CSC_PK_COUNT] = {};
+    // autotuner: launch variant per (kernel, m, K, log2 pixel count, mode)
+    bool autotune = true;
+    int force_variant = -1;
+    std::map<std::array<int, 5>, int> tuned;
 };
 
 namespace {
@@ -138,6 +145,78 @@ struct ProfScope {
         hipError_t e_ = (expr);                                                                   \
         if (e_ != hipSuccess) return fail(h, CSC_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
     } while (0)
+
+// Kernels with several launch variants that compute bit-identical results.
+enum TunedKernel { TK_SYNTH = 0 };
+
+int ilog2(long long v) {
+    int r = 0;
+    while (v > 1) {
+        v >>= 1;
+        ++r;
+    }
+    return r;
+}
+
+// Launch the variant chosen for `key`.  The first time a key is seen (and the
+// stream is not being captured) every variant is timed on the call's own data
+// with HIP events and the fastest is kept for the handle's lifetime.  Variants
+// write the same outputs from the same inputs, so the extra launches leave the
+// call's result unchanged.
+hipError_t tuned_launch(csc_ctx *h, const std::array<int, 5> &key, int n_variants,
+                        const std::function<hipError_t(int)> &launch, bool representative = true) {
+    if (h->force_variant >= 0) return launch(h->force_variant < n_variants ? h->force_variant : 0);
+    auto it = h->tuned.find(key);
+    if (it != h->tuned.end()) return launch(it->second);
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (!representative || !h->autotune || n_variants < 2 || hipStreamIsCapturing(h->stream, &cs) != hipSuccess ||
+        cs != hipStreamCaptureStatusNone) {
+        hipGetLastError();
+        return launch(0);
+    }
+    hipEvent_t a = nullptr, b = nullptr;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+        hipGetLastError();
+        if (a) hipEventDestroy(a);
+        return launch(0);
+    }
+    int best = 0;
+    float best_ms = 0.f;
+    hipError_t e = hipSuccess;
+    for (int v = 0; v < n_variants && e == hipSuccess; ++v) {
+        e = launch(v);  // warm-up
+        if (e != hipSuccess) break;
+        hipEventRecord(a, h->stream);
+        e = launch(v);
+        if (e == hipSuccess) e = launch(v);
+        hipEventRecord(b, h->stream);
+        if (e != hipSuccess) break;
+        if ((e = hipEventSynchronize(b)) != hipSuccess) break;
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, a, b);
+        if (v == 0 || ms < best_ms) {
+            best = v;
+            best_ms = ms;
+        }
+    }
+    hipEventDestroy(a);
+    hipEventDestroy(b);
+    if (e != hipSuccess) return e;
+    h->tuned[key] = best;
+    return hipSuccess;
+}
+
+// Synthesis / residual through the tuned launcher (tile shape and threads per
+// output pixel).  `representative` marks calls whose code density is typical of
+// the key (not the first iterations of a code step from zero codes); only those
+// may tune.
+hipError_t synth(csc_ctx *h, int K, int m, Lists L, const float *d, const float *x, const unsigned char *W,
+                 float *out, SynthMode mode, bool representative = true) {
+    const Geometry &g = h->geo;
+    return tuned_launch(
+        h, {TK_SYNTH, m, K, ilog2(g.n_pix), (int)mode}, 4,
+        [&](int v) { return launch_synth(g, K, m, L, d, x, W, out, mode, v, h->stream); }, representative);
+}
 
 // Device workspace of at least `bytes` (contents undefined).  Growing frees the
 // old buffer after the stream has drained.
@@ -357,10 +436,33 @@ int power_iteration(csc_ctx *h, int K, int m, Lists L, FmLists F, const unsigned
     for (int it = 0; it < n_power; ++it) {
         {
             PROF(CSC_PK_SYNTH);
-            HIPCHK(launch_synth(g, K, m, L, v, nullptr, W, R, SYNTH_WEIGHTED, h->stream));
+            HIPCHK(synth(h, K, m, L, v, nullptr, W, R, SYNTH_WEIGHTED));
         }
         int st = filter_corr_lists(h, K, m, F, R, w);
         if (st) return st;
+        PROF(CSC_PK_UPDATE);
+        HIPCHK(launch_power_update(v, w, K * M, sc + SC_LAM, h->stream));
+    }
+    return CSC_OK;
+}
+
+// Power iteration on the zero-padded normal matrix given by the lag sums Rl
+// (no observation mask); leaves the estimate in the device scalar SC_LAM.
+int power_iteration_lag(csc_ctx *h, int K, int m, const double *Rl, int n_power) {
+    const int M = m * m;
+    const int nch = lag_matvec_chunks(K);
+    WS(v, float, WS_V, K * M);
+    WS(w, float, WS_W, K * M);
+    WS(part, double, WS_PART, (size_t)nch * K * M);
+    WS(sc, double, WS_SCAL, SC_COUNT);
+    HIPCHK(launch_fill(v, K * M, (float)(1.0 / std::sqrt((double)K * M)), h->stream));
+    HIPCHK(hipMemsetAsync(sc + SC_LAM, 0, sizeof(double), h->stream));
+    for (int it = 0; it < n_power; ++it) {
+        {
+            PROF(CSC_PK_POWER);
+            HIPCHK(launch_lag_matvec(K, m, Rl, v, part, h->stream));
+            HIPCHK(launch_reduce_partials_f64_to_f32(part, nch, K * M, w, h->stream));
+        }
         PROF(CSC_PK_UPDATE);
         HIPCHK(launch_power_update(v, w, K * M, sc + SC_LAM, h->stream));
     }
@@ -514,7 +616,7 @@ extern "C" int csc_code_step(csc_handle h, const csc_images *im, const float *x,
     for (int it = 0; it < n_iter; ++it) {
         {
             PROF(CSC_PK_SYNTH);
-            HIPCHK(launch_synth(g, K, m, Lists{soff, nzc[cur], pairs[cur]}, d, x, W, R, SYNTH_RESIDUAL, h->stream));
+            HIPCHK(synth(h, K, m, Lists{soff, nzc[cur], pairs[cur]}, d, x, W, R, SYNTH_RESIDUAL, it == n_iter - 1));
         }
         {
             PROF(CSC_PK_ADJOINT);
@@ -571,8 +673,26 @@ extern "C" int csc_dict_step(csc_handle h, const csc_images *im, const float *x,
     if ((st = build_fm_lists(h, K, L, nz, &F))) return st;
     WS(sc, double, WS_SCAL, SC_COUNT);
     const bool need_ld = sur || step <= 0.0 || L_d_out;
+    // Without an observation mask the lag sums R of the batch give both the
+    // surrogate increment and the zero-padded normal matrix used for L_d.
+    double *Rl = nullptr, *Es = nullptr;
+    if (!W && (sur || need_ld)) {
+        const long long nl = surrogate_lag_elems(K, m);
+        {
+            WS(rl, double, WS_LAG, nl);
+            Rl = rl;
+        }
+        if (sur) {
+            WS(es, double, WS_ES, nl * 4 * (m / 2 > 0 ? m / 2 : 1));
+            Es = es;
+        }
+        PROF(CSC_PK_SUR_LAG);
+        HIPCHK(launch_surrogate_lag(g, K, m, L, F.off, F.codes, Rl, Es, h->stream));
+    }
     if (need_ld) {
-        if ((st = power_iteration(h, K, m, L, F, W, n_power))) return st;
+        if (W) st = power_iteration(h, K, m, L, F, W, n_power);
+        else st = power_iteration_lag(h, K, m, Rl, n_power);
+        if (st) return st;
     }
     double Ld = 0.0;
     if (sur || L_d_out) {
@@ -590,7 +710,7 @@ extern "C" int csc_dict_step(csc_handle h, const csc_images *im, const float *x,
         for (int it = 0; it < n_iter; ++it) {
             {
                 PROF(CSC_PK_SYNTH);
-                HIPCHK(launch_synth(g, K, m, L, d, x, W, R, SYNTH_RESIDUAL, h->stream));
+                HIPCHK(synth(h, K, m, L, d, x, W, R, SYNTH_RESIDUAL));
             }
             if ((st = filter_corr_lists(h, K, m, F, R, G))) return st;
             PROF(CSC_PK_UPDATE);
@@ -601,14 +721,7 @@ extern "C" int csc_dict_step(csc_handle h, const csc_images *im, const float *x,
             PROF(CSC_PK_SUR_ACC);
             HIPCHK(launch_surrogate_blocks(g, K, m, F.off, F.codes, W, sur->C, h->stream));
         } else {
-            const long long nl = surrogate_lag_elems(K, m);
-            WS(Rl, double, WS_LAG, nl);
-            WS(Es, double, WS_ES, nl * 4 * (m / 2 > 0 ? m / 2 : 1));
             WS(tab, unsigned short, WS_TAB, (size_t)M * M);
-            {
-                PROF(CSC_PK_SUR_LAG);
-                HIPCHK(launch_surrogate_lag(g, K, m, L, F.off, F.codes, Rl, Es, h->stream));
-            }
             {
                 PROF(CSC_PK_SUR_EXPAND);
                 HIPCHK(launch_surrogate_expand(K, m, Rl, Es, tab, sur->C, h->stream));
@@ -687,7 +800,7 @@ extern "C" int csc_synthesize(csc_handle h, const csc_images *im, const float *d
     if ((st = build_nonzero_lists(h, K, z, &L))) return st;
     {
         PROF(CSC_PK_SYNTH);
-        HIPCHK(launch_synth(h->geo, K, m, L, d, nullptr, nullptr, y, SYNTH_PLAIN, h->stream));
+        HIPCHK(synth(h, K, m, L, d, nullptr, nullptr, y, SYNTH_PLAIN));
     }
     return CSC_OK;
 }
@@ -725,6 +838,14 @@ extern "C" int csc_filter_corr(csc_handle h, const csc_images *im, const float *
     FmLists F;
     if ((st = build_fm_lists(h, K, L, nz, &F))) return st;
     return filter_corr_lists(h, K, m, F, r, G);
+}
+
+extern "C" int csc_set_autotune(csc_handle h, int enable) {
+    if (!h) return CSC_EINVAL;
+    h->autotune = enable > 0;
+    h->force_variant = enable < 0 ? -enable - 1 : -1;
+    if (!h->autotune) h->tuned.clear();
+    return CSC_OK;
 }
 
 extern "C" int csc_profile_enable(csc_handle h, int enable) {

@@ -266,32 +266,44 @@ struct __align__(8) SynPair {
     float v;
 };
 
-// Synthesis on TT x TT output tiles, one thread per output pixel.  The
-// codes of the tile grown by c are staged in LDS in region row-major order, so
-// for output p and tap row s_y the codes of the 2c + 1 pixels q = p - s form one
-// contiguous run; filters are staged in LDS when they fit.
-template <int MM, bool DLDS, int TT>
-__global__ __launch_bounds__(TT * TT) void k_synth(const ImgInfo *imgs, const TileInfo *tiles, int K, Lists zl,
-                                                   const float *__restrict__ d, const float *__restrict__ x,
-                                                   const unsigned char *__restrict__ W, float *__restrict__ out,
-                                                   int mode) {
-    constexpr int C = MM / 2, RW = TT + 2 * C, R = RW * RW, M = MM * MM, NT = TT * TT;
+// Synthesis on TT x TY output tiles (TY divides the 16-row geometry tiles) with
+// SP threads per output pixel.  The codes of the tile grown by c are staged in
+// LDS in region row-major order, so for output p and tap row s_y the codes of
+// the 2c + 1 pixels q = p - s form one contiguous run; filters are staged in
+// LDS when they fit.  Thread part j of a pixel takes a contiguous range of tap
+// rows.  Each tap row's sum is formed the same way for every tile shape and SP,
+// and the row sums are added in row order, so the result does not depend on
+// the launch variant.  A region whose codes exceed the staging capacity reads
+// them from global memory instead, in the same order.
+template <int MM, bool DLDS, int TT, int TY, int SP>
+__global__ __launch_bounds__(TT *TY *SP) void k_synth(const ImgInfo *imgs, const TileInfo *tiles, int K, Lists zl,
+                                                      const float *__restrict__ d, const float *__restrict__ x,
+                                                      const unsigned char *__restrict__ W, float *__restrict__ out,
+                                                      int mode) {
+    constexpr int C = MM / 2, RW = TT + 2 * C, RH = TY + 2 * C, R = RW * RH, M = MM * MM, NP = TT * TY,
+                  NT = NP * SP;
     constexpr int CH = (R + NT - 1) / NT;
+    constexpr int RP = (MM + SP - 1) / SP;  // tap rows per part
+    constexpr int SUB = TS / TY;            // blocks per geometry tile
     __shared__ unsigned lgoff[R];
     __shared__ int lstart[R + 1];
     __shared__ unsigned short lcnt[R];
     __shared__ SynPair lp[SYN_CAP];
     __shared__ int scratch[NT];
+    __shared__ float rows[SP > 1 ? MM : 1][SP > 1 ? NP : 1];
     __shared__ float dl[DLDS ? SYN_DCAP : 1];
 
-    const TileInfo t = tiles[blockIdx.x];
+    const TileInfo t = tiles[blockIdx.x / SUB];
     const ImgInfo im = imgs[t.img];
-    const int ly = threadIdx.x / TT, lx = threadIdx.x % TT;
-    const int y = t.ty * TT + ly, xx = t.tx * TT + lx;
+    const int y0 = t.ty * TS + (int)(blockIdx.x % SUB) * TY, x0 = t.tx * TT;
+    if (y0 >= im.H) return;  // whole workgroup below the image
+    const int o = threadIdx.x % NP, part = threadIdx.x / NP;
+    const int ly = o / TT, lx = o % TT;
+    const int y = y0 + ly, xx = x0 + lx;
     const bool valid = y < im.H && xx < im.W;
     if (DLDS)
         for (int i = threadIdx.x; i < K * M; i += NT) dl[i] = d[i];
-    const int oy = t.ty * TT - C, ox = t.tx * TT - C;
+    const int oy = y0 - C, ox = x0 - C;
     int mysum = 0;
 #pragma unroll
     for (int j = 0; j < CH; ++j) {
@@ -299,14 +311,14 @@ __global__ __launch_bounds__(TT * TT) void k_synth(const ImgInfo *imgs, const Ti
         if (i < R) {
             const int gy = oy + i / RW, gx = ox + i % RW;
             int n = 0;
-            unsigned o = 0;
+            unsigned off = 0;
             if (gy >= 0 && gy < im.H && gx >= 0 && gx < im.W) {
                 const long long gp = im.pix_off + (long long)gy * im.W + gx;
                 n = zl.cnt[gp];
-                o = zl.off[gp];
+                off = zl.off[gp];
             }
             lcnt[i] = (unsigned short)n;
-            lgoff[i] = o;
+            lgoff[i] = off;
             mysum += n;
         }
     }
@@ -329,53 +341,78 @@ __global__ __launch_bounds__(TT * TT) void k_synth(const ImgInfo *imgs, const Ti
     }
     if (threadIdx.x == 0) lstart[R] = total;
     __syncthreads();
-    if (!valid) return;
     const float *dd = DLDS ? dl : d;
-    float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, acc3 = 0.f;
-    if (staged) {
-        for (int sy = -C; sy <= C; ++sy) {
+    float acc = 0.f;
+    if (valid) {
+        const int r0 = part * RP, r1 = r0 + RP < MM ? r0 + RP : MM;
+        for (int r = r0; r < r1; ++r) {
+            const int sy = r - C;
+            float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
             const int rb = (ly + C - sy) * RW + lx;
-            const int j0 = lstart[rb], j1 = lstart[rb + 2 * C + 1];
-            const float *drow = dd + (sy + C) * MM + 2 * C + lx;  // tap column = 2c - (col - lx)
-            int j = j0;
-            for (; j + 3 < j1; j += 4) {
-                const SynPair e0 = lp[j], e1 = lp[j + 1], e2 = lp[j + 2], e3 = lp[j + 3];
-                acc0 = fmaf(drow[e0.k * M - e0.col], e0.v, acc0);
-                acc1 = fmaf(drow[e1.k * M - e1.col], e1.v, acc1);
-                acc2 = fmaf(drow[e2.k * M - e2.col], e2.v, acc2);
-                acc3 = fmaf(drow[e3.k * M - e3.col], e3.v, acc3);
-            }
-            for (; j < j1; ++j) {
-                const SynPair e = lp[j];
-                acc0 = fmaf(drow[e.k * M - e.col], e.v, acc0);
-            }
-        }
-    } else {
-        for (int sy = -C; sy <= C; ++sy) {
-            for (int sx = -C; sx <= C; ++sx) {
-                const int i = (ly + C - sy) * RW + (lx + C - sx);
-                const int n = lcnt[i];
-                const Pair *src = zl.pairs + lgoff[i];
-                const float *dt = dd + (sy + C) * MM + (sx + C);
-                for (int q = 0; q < n; ++q) {
-                    const Pair e = src[q];
-                    acc0 = fmaf(dt[e.k * M], e.v, acc0);
+            if (staged) {
+                const int j0 = lstart[rb], j1 = lstart[rb + 2 * C + 1];
+                const float *drow = dd + r * MM + 2 * C + lx;  // tap column = 2c - (col - lx)
+                int j = j0;
+                for (; j + 3 < j1; j += 4) {
+                    const SynPair e0 = lp[j], e1 = lp[j + 1], e2 = lp[j + 2], e3 = lp[j + 3];
+                    a0 = fmaf(drow[e0.k * M - e0.col], e0.v, a0);
+                    a1 = fmaf(drow[e1.k * M - e1.col], e1.v, a1);
+                    a2 = fmaf(drow[e2.k * M - e2.col], e2.v, a2);
+                    a3 = fmaf(drow[e3.k * M - e3.col], e3.v, a3);
+                }
+                // tail: element j - j0 goes to accumulator (j - j0) mod 4 as in the loop
+                if (j < j1) a0 = fmaf(drow[lp[j].k * M - lp[j].col], lp[j].v, a0);
+                if (j + 1 < j1) a1 = fmaf(drow[lp[j + 1].k * M - lp[j + 1].col], lp[j + 1].v, a1);
+                if (j + 2 < j1) a2 = fmaf(drow[lp[j + 2].k * M - lp[j + 2].col], lp[j + 2].v, a2);
+            } else {
+                // same elements in the same order; b0 always takes the next element and the
+                // four accumulators rotate, so element u lands in accumulator u mod 4
+                float b0 = 0.f, b1 = 0.f, b2 = 0.f, b3 = 0.f;
+                int u = 0;
+                for (int w = 0; w < MM; ++w) {
+                    const int n = lcnt[rb + w];
+                    const Pair *src = zl.pairs + lgoff[rb + w];
+                    const float *dt = dd + r * MM + (MM - 1 - w);
+                    for (int q = 0; q < n; ++q, ++u) {
+                        const Pair e = src[q];
+                        const float nb = fmaf(dt[e.k * M], e.v, b0);
+                        b0 = b1;
+                        b1 = b2;
+                        b2 = b3;
+                        b3 = nb;
+                    }
+                }
+                // b_i now holds accumulator (u + i) mod 4
+                switch (u & 3) {
+                    case 0: a0 = b0; a1 = b1; a2 = b2; a3 = b3; break;
+                    case 1: a1 = b0; a2 = b1; a3 = b2; a0 = b3; break;
+                    case 2: a2 = b0; a3 = b1; a0 = b2; a1 = b3; break;
+                    default: a3 = b0; a0 = b1; a1 = b2; a2 = b3; break;
                 }
             }
+            const float rs = (a0 + a1) + (a2 + a3);
+            if (SP > 1) rows[r][o] = rs;
+            else acc += rs;
         }
     }
-    const float acc = (acc0 + acc1) + (acc2 + acc3);
-    const long long gp = im.pix_off + (long long)y * im.W + xx;
-    float o;
-    if (mode == SYNTH_RESIDUAL) {
-        o = x[gp] - acc;
-        if (W && !W[gp]) o = 0.f;
-    } else if (mode == SYNTH_WEIGHTED) {
-        o = (W && !W[gp]) ? 0.f : acc;
-    } else {
-        o = acc;
+    if (SP > 1) {
+        __syncthreads();
+        if (part != 0) return;
+        if (valid)
+            for (int r = 0; r < MM; ++r) acc += rows[r][o];
     }
-    out[gp] = o;
+    if (!valid) return;
+    const long long gp = im.pix_off + (long long)y * im.W + xx;
+    float ov;
+    if (mode == SYNTH_RESIDUAL) {
+        ov = x[gp] - acc;
+        if (W && !W[gp]) ov = 0.f;
+    } else if (mode == SYNTH_WEIGHTED) {
+        ov = (W && !W[gp]) ? 0.f : acc;
+    } else {
+        ov = acc;
+    }
+    out[gp] = ov;
 }
 
 constexpr int ADJ_CAP = 2048;
@@ -615,16 +652,28 @@ hipError_t launch_sum_counts(const unsigned short *cnt, long long n, unsigned lo
 }
 
 namespace {
+template <int MM, int TY, int SP>
+hipError_t synth_sp(const Geometry &g, int K, Lists z, const float *d, const float *x, const unsigned char *W,
+                    float *out, SynthMode mode, hipStream_t s) {
+    const dim3 grid(g.n_tiles * (TS / TY)), block(TS * TY * SP);
+    if (K * MM * MM <= SYN_DCAP)
+        hipLaunchKernelGGL((k_synth<MM, true, TS, TY, SP>), grid, block, 0, s, g.d_img, g.d_tiles, K, z, d, x, W,
+                           out, (int)mode);
+    else
+        hipLaunchKernelGGL((k_synth<MM, false, TS, TY, SP>), grid, block, 0, s, g.d_img, g.d_tiles, K, z, d, x, W,
+                           out, (int)mode);
+    return hipGetLastError();
+}
+
 template <int MM>
 hipError_t synth_impl(const Geometry &g, int K, Lists z, const float *d, const float *x, const unsigned char *W,
-                      float *out, SynthMode mode, hipStream_t s) {
-    if (K * MM * MM <= SYN_DCAP)
-        hipLaunchKernelGGL((k_synth<MM, true, TS>), dim3(g.n_tiles), dim3(TPB), 0, s, g.d_img, g.d_tiles, K, z, d, x,
-                           W, out, (int)mode);
-    else
-        hipLaunchKernelGGL((k_synth<MM, false, TS>), dim3(g.n_tiles), dim3(TPB), 0, s, g.d_img, g.d_tiles, K, z, d, x,
-                           W, out, (int)mode);
-    return hipGetLastError();
+                      float *out, SynthMode mode, int variant, hipStream_t s) {
+    switch (variant) {
+        case 1: return synth_sp<MM, 16, 4>(g, K, z, d, x, W, out, mode, s);
+        case 2: return synth_sp<MM, 8, 2>(g, K, z, d, x, W, out, mode, s);
+        case 3: return synth_sp<MM, 8, 4>(g, K, z, d, x, W, out, mode, s);
+        default: return synth_sp<MM, 16, 1>(g, K, z, d, x, W, out, mode, s);
+    }
 }
 
 template <int MM>
@@ -655,8 +704,8 @@ hipError_t adjoint_dense_impl(const Geometry &g, int K, const float *r, const fl
 }  // namespace
 
 hipError_t launch_synth(const Geometry &g, int K, int m, Lists z, const float *d, const float *x,
-                        const unsigned char *W, float *out, SynthMode mode, hipStream_t s) {
-    SCSC_DISPATCH_M(m, synth_impl, g, K, z, d, x, W, out, mode, s);
+                        const unsigned char *W, float *out, SynthMode mode, int variant, hipStream_t s) {
+    SCSC_DISPATCH_M(m, synth_impl, g, K, z, d, x, W, out, mode, variant, s);
 }
 
 hipError_t launch_adjoint_shrink(const Geometry &g, int K, int m, const unsigned *mask_words,

@@ -456,6 +456,60 @@ __global__ __launch_bounds__(LO_THREADS) void k_lag_outer(const ImgInfo *imgs, i
     }
 }
 
+// Product with the zero-padded normal matrix of the batch, whose entry
+// (k, s; k2, s2) is the lag sum R_{s - s2}[k][k2] (block Toeplitz in the taps):
+// part[chunk][k][s] = sum_{k2 in chunk} sum_{s2} R_{s - s2}[k][k2] v[k2][s2], FP64.
+// Workgroup (k, chunk of RM_KB partner filters); thread (k2, tap row s_y) keeps the
+// m outputs of its row in registers and reads each lag row once per s2_y; the
+// partner filters are then summed in a fixed order.
+constexpr int RM_KB = 16;
+
+template <int MM>
+__global__ __launch_bounds__(MM *RM_KB) void k_lag_matvec(int K, const double *__restrict__ Rl,
+                                                          const float *__restrict__ v, double *__restrict__ part) {
+    constexpr int C = MM / 2, M = MM * MM, L = 2 * MM - 1, LL = L * L, NT = MM * RM_KB;
+    __shared__ double r[RM_KB][LL];
+    __shared__ double vv[RM_KB][M];
+    const int k = blockIdx.x, ch = blockIdx.y;
+    const int k2lo = ch * RM_KB, nk = min(RM_KB, K - k2lo);
+    for (int i = threadIdx.x; i < nk * LL; i += NT) {
+        const int j = i / LL, di = i % LL, k2 = k2lo + j;
+        // R_delta[k][k2] is stored for k <= k2; otherwise it is R_{-delta}[k2][k]
+        r[j][di] = k <= k2 ? Rl[((long long)k * K + k2) * LL + di] : Rl[((long long)k2 * K + k) * LL + (LL - 1 - di)];
+    }
+    for (int i = threadIdx.x; i < nk * M; i += NT) vv[i / M][i % M] = (double)v[(long long)(k2lo + i / M) * M + i % M];
+    __syncthreads();
+    const int j = threadIdx.x / MM, sy = threadIdx.x % MM;
+    double acc[MM];
+#pragma unroll
+    for (int sx = 0; sx < MM; ++sx) acc[sx] = 0.0;
+    if (j < nk) {
+        for (int s2y = 0; s2y < MM; ++s2y) {
+            const double *rrow = &r[j][(sy - s2y + 2 * C) * L];  // lags (dy, dx = sx - s2x + 2c)
+            const double *vrow = &vv[j][s2y * MM];
+            double rv[L], vx[MM];
+#pragma unroll
+            for (int i = 0; i < L; ++i) rv[i] = rrow[i];
+#pragma unroll
+            for (int i = 0; i < MM; ++i) vx[i] = vrow[i];
+#pragma unroll
+            for (int sx = 0; sx < MM; ++sx)
+#pragma unroll
+                for (int s2x = 0; s2x < MM; ++s2x) acc[sx] = fma(rv[sx - s2x + 2 * C], vx[s2x], acc[sx]);
+        }
+    }
+    __syncthreads();
+    double *red = &r[0][0];  // [RM_KB][M], reuses the lag rows
+#pragma unroll
+    for (int sx = 0; sx < MM; ++sx) red[j * M + sy * MM + sx] = acc[sx];
+    __syncthreads();
+    for (int s = threadIdx.x; s < M; s += NT) {
+        double t = 0.0;
+        for (int jj = 0; jj < nk; ++jj) t += red[jj * M + s];
+        part[((long long)ch * K + k) * M + s] = t;
+    }
+}
+
 __global__ void k_zero_f64(double *p, long long n) {
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
         p[i] = 0.0;
@@ -720,7 +774,7 @@ hipError_t sur_lag_impl(const Geometry &g, int K, Lists z, const unsigned *fm_of
     hipLaunchKernelGGL(k_lag_outer<MM>, dim3(nlag, nkc, (unsigned)P), dim3(LO_THREADS), shm, s, g.d_img, g.n_img,
                        (long long)g.n_pix, K, z, 0, KC, Rl);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (Cc > 0) {
+    if (Cc > 0 && Es) {
         hipLaunchKernelGGL(k_lag_outer<MM>, dim3(LL, nkc, 4 * Cc), dim3(LO_THREADS), shm, s, g.d_img, g.n_img,
                            (long long)g.n_pix, K, z, 1, KC, Es);
         if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -735,6 +789,12 @@ hipError_t sur_expand_impl(int K, const double *Rl, const double *Es, unsigned s
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_sur_expand<MM>, dim3(K, K), dim3(EX_THREADS), 0, s, K, Rl, Es, tab, C);
+    return hipGetLastError();
+}
+
+template <int MM>
+hipError_t lag_matvec_impl(int K, const double *Rl, const float *v, double *part, hipStream_t s) {
+    hipLaunchKernelGGL(k_lag_matvec<MM>, dim3(K, (K + RM_KB - 1) / RM_KB), dim3(MM * RM_KB), 0, s, K, Rl, v, part);
     return hipGetLastError();
 }
 
@@ -767,6 +827,12 @@ hipError_t launch_surrogate_expand(int K, int m, const double *Rl, const double 
 
 hipError_t launch_surrogate_corner(const Geometry &g, int K, int m, Lists z, double *C, hipStream_t s) {
     SCSC_DISPATCH_M(m, sur_corner_impl, g, K, z, C, s);
+}
+
+int lag_matvec_chunks(int K) { return (K + RM_KB - 1) / RM_KB; }
+
+hipError_t launch_lag_matvec(int K, int m, const double *Rl, const float *v, double *part, hipStream_t s) {
+    SCSC_DISPATCH_M(m, lag_matvec_impl, K, Rl, v, part, s);
 }
 
 }  // namespace scsc

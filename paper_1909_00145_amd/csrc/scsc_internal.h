@@ -159,8 +159,10 @@ hipError_t launch_gather_selected(const Geometry &g, int K, const unsigned *mask
 // Mode of the synthesis kernel.
 enum SynthMode { SYNTH_RESIDUAL = 0, SYNTH_PLAIN = 1, SYNTH_WEIGHTED = 2 };
 // out = W (x - D z) (RESIDUAL), D z (PLAIN) or W (D z) (WEIGHTED); z given as lists.
+// variant (identical results): 0: 16x16 tiles, 1 thread per output pixel; 1: 16x16, 4 threads;
+// 2: 16x8, 2 threads; 3: 16x8, 4 threads.
 hipError_t launch_synth(const Geometry &g, int K, int m, Lists z, const float *d, const float *x,
-                        const unsigned char *W, float *out, SynthMode mode, hipStream_t s);
+                        const unsigned char *W, float *out, SynthMode mode, int variant, hipStream_t s);
 // One proximal-gradient iteration on the selected coordinates (FP32 VALU).
 hipError_t launch_adjoint_shrink(const Geometry &g, int K, int m, const unsigned *mask_words,
                                  const unsigned *soff, const Pair *old_pairs, const unsigned short *old_cnt,
@@ -206,10 +208,15 @@ hipError_t launch_fm_lists(const Geometry &g, int K, Lists z, unsigned *fm_cnt, 
                            unsigned long long *scan_tmp, unsigned long long *total64, hipStream_t s);
 hipError_t launch_surrogate_blocks(const Geometry &g, int K, int m, const unsigned *fm_off, const FmCode *fm,
                                    const unsigned char *W, double *C, hipStream_t s);
-// Unmasked case: lag sums (Rl: surrogate_lag_elems doubles, Es: 4 c of them), expansion, corners.
+// Unmasked case: lag sums (Rl: surrogate_lag_elems doubles, Es: 4 c of them, skipped
+// when Es is null), expansion, corners.
 long long surrogate_lag_elems(int K, int m);
 hipError_t launch_surrogate_lag(const Geometry &g, int K, int m, Lists z, const unsigned *fm_off, const FmCode *fm,
                                 double *Rl, double *Es, hipStream_t s);
+// Product of the zero-padded normal matrix (lag sums Rl) with v [K][m*m]:
+// part[lag_matvec_chunks(K)][K][m*m] FP64 partial sums.
+int lag_matvec_chunks(int K);
+hipError_t launch_lag_matvec(int K, int m, const double *Rl, const float *v, double *part, hipStream_t s);
 hipError_t launch_surrogate_expand(int K, int m, const double *Rl, const double *Es, unsigned short *tab, double *C,
                                    hipStream_t s);
 hipError_t launch_surrogate_corner(const Geometry &g, int K, int m, Lists z, double *C, hipStream_t s);

@@ -164,6 +164,11 @@ class Context:
         except Exception:
             pass
 
+    def set_autotune(self, enable, variant=None):
+        """enable: tune launch variants on first use (default on); variant: force one variant."""
+        mode = -(int(variant) + 1) if variant is not None else (1 if enable else 0)
+        self._check(self.lib.csc_set_autotune(self.h, mode))
+
     def _sync_stream(self):
         s = torch.cuda.current_stream(self.device).cuda_stream
         if s != self._stream:

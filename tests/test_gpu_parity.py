@@ -77,6 +77,34 @@ def test_operators(ctx, K, m, hw):
     assert rel_err(G, sum(oracle.filter_corr(z, r, m) for z, r in zip(zs, rs)).ravel()) < TOL32
 
 
+def test_launch_variants_bit_identical(ctx):
+    """Every launch variant of the tuned kernels gives the same bits (synthesis and a code step)."""
+    say("launch variants")
+    hw = [(70, 45), (33, 100)]
+    K, m = 24, 11
+    rng = np.random.default_rng(11)
+    im = Images(hw)
+    d = to_dev(f32(rng.standard_normal((K, m, m))))
+    z = packed(im, [f32(rng.standard_normal((K, H, W)) * (rng.random((K, H, W)) < 0.05)) for H, W in hw])
+    xs, _, _ = make_problem(5, hw, K, m)
+    outs, codes = [], []
+    try:
+        for v in range(4):
+            ctx.set_autotune(True, variant=v)
+            outs.append(ctx.synthesize(im, d, z).cpu().numpy())
+            zz = torch.zeros(K * im.n_pix, dtype=torch.float32, device="cuda")
+            ctx.code_step(im, packed(im, xs), d, zz, 0.5, 0.3, 7, 1, 10)
+            codes.append(zz.cpu().numpy())
+        ctx.set_autotune(True)
+        outs.append(ctx.synthesize(im, d, z).cpu().numpy())
+    finally:
+        ctx.set_autotune(True)
+    for o in outs[1:]:
+        np.testing.assert_array_equal(o, outs[0])
+    for c in codes[1:]:
+        np.testing.assert_array_equal(c, codes[0])
+
+
 # ---------------------------------------------------------------------------
 # objective (eq. 1), FP64 on both sides
 # ---------------------------------------------------------------------------

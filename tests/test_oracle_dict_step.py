@@ -44,6 +44,37 @@ def test_lipschitz_filter_vs_eigvalsh(rng):
     assert 0.99 * top <= est <= top * (1 + 1e-12)
 
 
+def test_padded_normal_matrix_is_lag_sums_and_dominates(rng):
+    """Zero-padded normal matrix: entry (k, s; k2, s2) = sum_q z_k[q] z_k2[q + s - s2] (brute force),
+    it dominates the exact sum Z^T Z, and the power estimate matches its top eigenvalue."""
+    K, m, H, W = 2, 5, 7, 9
+    c = m // 2
+    M = m * m
+    zs = [rng.standard_normal((K, H, W)) * (rng.random((K, H, W)) < 0.5), rng.standard_normal((K, 4, 6))]
+    A = sum(oracle.code_matrix(z, m).T @ oracle.code_matrix(z, m) for z in zs)
+    P = sum(oracle.code_matrix(oracle.pad_codes(z, c), m).T @ oracle.code_matrix(oracle.pad_codes(z, c), m)
+            for z in zs)
+    for k in range(K):
+        for k2 in range(K):
+            for s in range(M):
+                for s2 in range(M):
+                    dy = s // m - s2 // m
+                    dx = s % m - s2 % m
+                    ref = 0.0
+                    for z in zs:
+                        Hh, Ww = z.shape[1:]
+                        for y in range(Hh):
+                            for x in range(Ww):
+                                if 0 <= y + dy < Hh and 0 <= x + dx < Ww:
+                                    ref += z[k, y, x] * z[k2, y + dy, x + dx]
+                    assert abs(P[k * M + s, k2 * M + s2] - ref) <= 1e-12 * (1 + abs(ref))
+    assert np.linalg.eigvalsh(P - A)[0] >= -1e-10  # P - A is PSD
+    top = np.linalg.eigvalsh(P)[-1]
+    est = oracle.lipschitz_filter(zs, None, K, m, n_power=300)
+    assert 0.99 * top <= est <= top * (1 + 1e-12)
+    assert est >= np.linalg.eigvalsh(A)[-1] * 0.99
+
+
 def test_zero_codes_leave_filters(rng):
     d = oracle.project_ball(rng.standard_normal((2, 3, 3)))
     x = rng.standard_normal((6, 6))
