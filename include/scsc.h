@@ -216,6 +216,28 @@ int csc_profile_enable(csc_handle h, int enable);
  * profiling was enabled.  Host outputs.  Synchronises the stream. */
 int csc_profile_read(csc_handle h, int kernel_class, int64_t *launches, double *total_ms);
 
+/* ---- Unrolled proximal-gradient layers (differentiable code updates) ----------
+ * One layer is one iteration of the subsampled code update of eqs. (3)-(4) with a
+ * fixed selection `mask` (u8, packed like z: 1 = selected), step eta > 0 and
+ * threshold eta * lambda:
+ *     r = W (x - D z_in),   u = z_in + eta D^T r,   z_out = mask * shrink(u, eta * lambda).
+ * Dense packed codes; x, W as in csc_code_step; FP32 (BF16 returns CSC_EUNSUPPORTED).
+ * z_out may alias z_in.  Asynchronous apart from list sizing, which synchronises. */
+int csc_ista_forward(csc_handle h, const csc_images *im, const float *x, const uint8_t *W,
+                     const float *d, int K, int m, const uint8_t *mask, const float *z_in, float *z_out,
+                     double eta, double lambda, int precision);
+/* Reverse mode of one layer, recomputing r and u from z_in (only the layer input
+ * is kept between the passes).  Given g_out = dL/dz_out:
+ *     g_u = g_out on {mask, |u| > eta lambda}, 0 elsewhere;   t = W (D g_u);
+ *     g_z = g_u - eta D^T t   [packed like z],
+ *     g_d = eta (sum_i Z(g_u)_i^T r_i - sum_i Z(z_in)_i^T t_i)   [K][m][m],
+ *     g_x = eta t   [packed like x; may be NULL].
+ * Z(a)^T b is the filter correlation of csc_filter_corr.  Outputs are overwritten. */
+int csc_ista_backward(csc_handle h, const csc_images *im, const float *x, const uint8_t *W,
+                      const float *d, int K, int m, const uint8_t *mask, const float *z_in,
+                      const float *g_out, double eta, double lambda, float *g_z, float *g_d, float *g_x,
+                      int precision);
+
 /* Launch-variant autotuning (tile shape / threads per output pixel) of the
  * kernels that have several variants.  enable != 0 (the default): the first
  * call with a new (kernel, m, K, batch size class) times every variant on that

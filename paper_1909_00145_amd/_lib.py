@@ -72,6 +72,8 @@ SIGNATURES = {
     "csc_profile_enable": (_i, [_vp, _i]),
     "csc_profile_read": (_i, [_vp, _i, C.POINTER(C.c_int64), C.POINTER(_d)]),
     "csc_set_autotune": (_i, [_vp, _i]),
+    "csc_ista_forward": (_i, [_vp, _pimg, _vp, _vp, _vp, _i, _i, _vp, _vp, _vp, _d, _d, _i]),
+    "csc_ista_backward": (_i, [_vp, _pimg, _vp, _vp, _vp, _i, _i, _vp, _vp, _vp, _d, _d, _vp, _vp, _vp, _i]),
 }
 
 # csc_kernel_class

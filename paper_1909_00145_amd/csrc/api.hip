@@ -41,6 +41,9 @@ enum Slot {
     WS_ES,
     WS_TAB,
     WS_TILESBIG,
+    WS_DG,
+    WS_GU,
+    WS_T,
     WS_COUNT
 };
 
@@ -838,6 +841,122 @@ extern "C" int csc_filter_corr(csc_handle h, const csc_images *im, const float *
     FmLists F;
     if ((st = build_fm_lists(h, K, L, nz, &F))) return st;
     return filter_corr_lists(h, K, m, F, r, G);
+}
+
+// ---------------------------------------------------------------------------
+// Unrolled proximal-gradient layer (forward and checkpointed backward)
+// ---------------------------------------------------------------------------
+namespace {
+int check_layer_args(csc_ctx *h, const csc_images *im, int K, int m, int precision, double eta, double lambda) {
+    int st = check_images(h, im);
+    if (!st) st = check_filters(h, K, m);
+    if (!st) st = check_precision(h, precision);
+    if (st) return st;
+    if (!(eta > 0.0) || !std::isfinite(eta)) return fail(h, CSC_EINVAL, "eta must be finite and > 0");
+    if (!(lambda >= 0.0) || !std::isfinite(lambda)) return fail(h, CSC_EINVAL, "lambda must be finite and >= 0");
+    if (precision != CSC_FP32) return fail(h, CSC_EUNSUPPORTED, "BF16 unrolled layers not built yet");
+    return CSC_OK;
+}
+
+// r = W (x - D z) into R and g = D^T r (dense) into G.
+int layer_residual_gradient(csc_ctx *h, int K, int m, const float *x, const uint8_t *W, const float *d,
+                            const float *z, float **R_out, float **G_out) {
+    const Geometry &g = h->geo;
+    Lists L;
+    int st = build_nonzero_lists(h, K, z, &L);
+    if (st) return st;
+    WS(R, float, WS_R, g.n_pix);
+    WS(G, float, WS_DG, (size_t)K * g.n_pix);
+    {
+        PROF(CSC_PK_SYNTH);
+        HIPCHK(synth(h, K, m, L, d, x, W, R, SYNTH_RESIDUAL));
+    }
+    {
+        PROF(CSC_PK_DENSE);
+        HIPCHK(launch_adjoint_dense(g, K, m, R, d, G, h->stream));
+    }
+    *R_out = R;
+    *G_out = G;
+    return CSC_OK;
+}
+
+// G_out = sum_i Z(a)_i^T b_i for dense codes a (lists built here).
+int corr_dense(csc_ctx *h, int K, int m, const float *a, const float *b, float *G_out) {
+    Lists L;
+    unsigned long long nz = 0;
+    int st = build_nonzero_lists(h, K, a, &L, &nz);
+    if (st) return st;
+    FmLists F;
+    if ((st = build_fm_lists(h, K, L, nz, &F))) return st;
+    return filter_corr_lists(h, K, m, F, b, G_out);
+}
+}  // namespace
+
+extern "C" int csc_ista_forward(csc_handle h, const csc_images *im, const float *x, const uint8_t *W,
+                                const float *d, int K, int m, const uint8_t *mask, const float *z_in, float *z_out,
+                                double eta, double lambda, int precision) {
+    if (!h) return CSC_EINVAL;
+    int st = check_layer_args(h, im, K, m, precision, eta, lambda);
+    if (st) return st;
+    if (!x || !d || !mask || !z_in || !z_out) return fail(h, CSC_EINVAL, "null pointer argument");
+    HIPCHK(hipSetDevice(h->device));
+    if ((st = geometry(h, im))) return st;
+    const long long n = (long long)K * h->geo.n_pix;
+    float *R = nullptr, *G = nullptr;
+    if ((st = layer_residual_gradient(h, K, m, x, W, d, z_in, &R, &G))) return st;
+    PROF(CSC_PK_UPDATE);
+    HIPCHK(launch_ista_update(n, z_in, G, mask, (float)eta, (float)(eta * lambda), z_out, h->stream));
+    return CSC_OK;
+}
+
+extern "C" int csc_ista_backward(csc_handle h, const csc_images *im, const float *x, const uint8_t *W,
+                                 const float *d, int K, int m, const uint8_t *mask, const float *z_in,
+                                 const float *g_out, double eta, double lambda, float *g_z, float *g_d, float *g_x,
+                                 int precision) {
+    if (!h) return CSC_EINVAL;
+    int st = check_layer_args(h, im, K, m, precision, eta, lambda);
+    if (st) return st;
+    if (!x || !d || !mask || !z_in || !g_out || !g_z || !g_d) return fail(h, CSC_EINVAL, "null pointer argument");
+    HIPCHK(hipSetDevice(h->device));
+    if ((st = geometry(h, im))) return st;
+    const Geometry &g = h->geo;
+    const int M = m * m;
+    const long long n = (long long)K * g.n_pix;
+    const float feta = (float)eta;
+    // recompute r and u from the layer input, then g_u = g_out on the active selected set
+    float *R = nullptr, *G = nullptr;
+    if ((st = layer_residual_gradient(h, K, m, x, W, d, z_in, &R, &G))) return st;
+    WS(GU, float, WS_GU, (size_t)n);
+    {
+        PROF(CSC_PK_UPDATE);
+        HIPCHK(launch_ista_grad_u(n, z_in, G, mask, g_out, feta, (float)(eta * lambda), GU, h->stream));
+    }
+    // t = W (D g_u)
+    WS(T, float, WS_T, g.n_pix);
+    {
+        Lists Lu;
+        if ((st = build_nonzero_lists(h, K, GU, &Lu))) return st;
+        PROF(CSC_PK_SYNTH);
+        HIPCHK(synth(h, K, m, Lu, d, nullptr, W, T, SYNTH_WEIGHTED));
+    }
+    // g_d = eta (Z(g_u)^T r - Z(z)^T t)
+    WS(G1, float, WS_G, K * M);
+    WS(G2, float, WS_W, K * M);
+    if ((st = corr_dense(h, K, m, GU, R, G1))) return st;
+    if ((st = corr_dense(h, K, m, z_in, T, G2))) return st;
+    {
+        PROF(CSC_PK_UPDATE);
+        HIPCHK(launch_axpby(K * M, feta, G1, -feta, G2, g_d, h->stream));
+        if (g_x) HIPCHK(launch_axpby(g.n_pix, feta, T, 0.f, nullptr, g_x, h->stream));
+    }
+    // g_z = g_u - eta D^T t  (G is free again)
+    {
+        PROF(CSC_PK_DENSE);
+        HIPCHK(launch_adjoint_dense(g, K, m, T, d, G, h->stream));
+    }
+    PROF(CSC_PK_UPDATE);
+    HIPCHK(launch_axpby(n, 1.f, GU, -feta, G, g_z, h->stream));
+    return CSC_OK;
 }
 
 extern "C" int csc_set_autotune(csc_handle h, int enable) {

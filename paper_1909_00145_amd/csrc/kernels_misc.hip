@@ -192,4 +192,55 @@ hipError_t launch_lipschitz_code(const float *d, int K, int m, int P, double *tm
     return hipGetLastError();
 }
 
+
+// ---------------------------------------------------------------------------
+// Elementwise kernels of an unrolled proximal-gradient layer (dense codes).
+// ---------------------------------------------------------------------------
+namespace {
+__global__ void k_ista_update(long long n, const float *__restrict__ z, const float *__restrict__ g,
+                              const unsigned char *__restrict__ mask, float eta, float thr, float *__restrict__ out) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const float u = fmaf(eta, g[i], z[i]);
+        out[i] = mask[i] ? soft_threshold(u, thr) : 0.f;
+    }
+}
+
+__global__ void k_ista_grad_u(long long n, const float *__restrict__ z, const float *__restrict__ g,
+                              const unsigned char *__restrict__ mask, const float *__restrict__ gout, float eta,
+                              float thr, float *__restrict__ gu) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const float u = fmaf(eta, g[i], z[i]);
+        gu[i] = (mask[i] && fabsf(u) > thr) ? gout[i] : 0.f;
+    }
+}
+
+__global__ void k_axpby(long long n, float a, const float *__restrict__ x, float b, const float *__restrict__ y,
+                        float *__restrict__ out) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        out[i] = y ? a * x[i] + b * y[i] : a * x[i];
+}
+
+unsigned ew_blocks(long long n) {
+    long long b = (n + 255) / 256;
+    return (unsigned)(b < 1 ? 1 : (b > 8192 ? 8192 : b));
+}
+}  // namespace
+
+hipError_t launch_ista_update(long long n, const float *z, const float *g, const unsigned char *mask, float eta,
+                              float thr, float *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_ista_update, dim3(ew_blocks(n)), dim3(256), 0, s, n, z, g, mask, eta, thr, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_ista_grad_u(long long n, const float *z, const float *g, const unsigned char *mask,
+                              const float *gout, float eta, float thr, float *gu, hipStream_t s) {
+    hipLaunchKernelGGL(k_ista_grad_u, dim3(ew_blocks(n)), dim3(256), 0, s, n, z, g, mask, gout, eta, thr, gu);
+    return hipGetLastError();
+}
+
+hipError_t launch_axpby(long long n, float a, const float *x, float b, const float *y, float *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_axpby, dim3(ew_blocks(n)), dim3(256), 0, s, n, a, x, b, y, out);
+    return hipGetLastError();
+}
+
 }  // namespace scsc

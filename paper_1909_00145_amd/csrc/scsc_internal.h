@@ -224,6 +224,15 @@ hipError_t launch_surrogate_matvec(int K, int m, const double *C, const float *d
                                    hipStream_t s);
 long long surrogate_matvec_partial_elems(int K, int m);
 
+// Unrolled-layer elementwise kernels over n dense code entries:
+// out = mask ? shrink(z + eta g, thr) : 0;  gu = (mask && |z + eta g| > thr) ? gout : 0;
+// out = a x + b y (y may be null: out = a x).
+hipError_t launch_ista_update(long long n, const float *z, const float *g, const unsigned char *mask, float eta,
+                              float thr, float *out, hipStream_t s);
+hipError_t launch_ista_grad_u(long long n, const float *z, const float *g, const unsigned char *mask,
+                              const float *gout, float eta, float thr, float *gu, hipStream_t s);
+hipError_t launch_axpby(long long n, float a, const float *x, float b, const float *y, float *out, hipStream_t s);
+
 // FP64 objective: out[0] = data term, out[1] = L1 norm.
 hipError_t launch_objective(const Geometry &g, int K, int m, const float *x, const unsigned char *W,
                             const float *d, const float *z, double *partial, double *out, hipStream_t s);

@@ -258,6 +258,32 @@ class Context:
                                              _ptr(out, torch.float32, "G", K * m * m), PRECISIONS[precision]))
         return out
 
+    def ista_forward(self, im: Images, x, d, mask, z_in, eta, lam, W=None, out=None, precision="fp32"):
+        K, m = int(d.shape[0]), int(d.shape[-1])
+        out = torch.empty_like(z_in) if out is None else out
+        self._sync_stream()
+        self._check(self.lib.csc_ista_forward(
+            self.h, im.cref(), _ptr(x, torch.float32, "x", im.n_pix), _ptr(W, torch.uint8, "W", im.n_pix),
+            _ptr(d, torch.float32, "d", K * m * m), K, m, _ptr(mask, torch.uint8, "mask", K * im.n_pix),
+            _ptr(z_in, torch.float32, "z_in", K * im.n_pix), _ptr(out, torch.float32, "z_out", K * im.n_pix),
+            float(eta), float(lam), PRECISIONS[precision]))
+        return out
+
+    def ista_backward(self, im: Images, x, d, mask, z_in, g_out, eta, lam, W=None, want_x=True, precision="fp32"):
+        K, m = int(d.shape[0]), int(d.shape[-1])
+        g_z = torch.empty_like(z_in)
+        g_d = torch.empty_like(d)
+        g_x = torch.empty_like(x) if want_x else None
+        self._sync_stream()
+        self._check(self.lib.csc_ista_backward(
+            self.h, im.cref(), _ptr(x, torch.float32, "x", im.n_pix), _ptr(W, torch.uint8, "W", im.n_pix),
+            _ptr(d, torch.float32, "d", K * m * m), K, m, _ptr(mask, torch.uint8, "mask", K * im.n_pix),
+            _ptr(z_in, torch.float32, "z_in", K * im.n_pix), _ptr(g_out, torch.float32, "g_out", K * im.n_pix),
+            float(eta), float(lam), _ptr(g_z, torch.float32, "g_z", K * im.n_pix),
+            _ptr(g_d, torch.float32, "g_d", K * m * m), _ptr(g_x, torch.float32, "g_x", im.n_pix),
+            PRECISIONS[precision]))
+        return g_z, g_d, g_x
+
     def mask(self, im: Images, K, p, seed, draw, out=None):
         out = torch.empty(K * im.n_pix, dtype=torch.uint8, device=torch.device("cuda", self.device)) \
             if out is None else out

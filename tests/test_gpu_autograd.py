@@ -1,0 +1,132 @@
+"""GPU parity of the differentiable operators and the unrolled subsampled ISTA
+against the FP64 oracle (whose gradients are pinned by finite differences)."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import unrolled
+from gpu_helpers import f32, make_problem, packed, rel_err, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+TOL32 = 1e-5
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1909_00145_amd.ops import Context
+
+    torch.cuda.set_device(0)
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def test_synthesis_and_adjoint_gradients(ctx):
+    from paper_1909_00145_amd.autograd import adjoint, synthesis
+    from paper_1909_00145_amd.ops import Images
+
+    say("autograd synthesis/adjoint")
+    hw = [(40, 37), (23, 50)]
+    K, m = 6, 7
+    rng = np.random.default_rng(21)
+    im = Images(hw)
+    d = f32(rng.standard_normal((K, m, m)))
+    zs = [f32(rng.standard_normal((K, H, W)) * (rng.random((K, H, W)) < 0.2)) for H, W in hw]
+    gs = [f32(rng.standard_normal((H, W))) for H, W in hw]
+    dt = to_dev(d).requires_grad_(True)
+    zt = packed(im, zs).requires_grad_(True)
+    y = synthesis(ctx, im, zt, dt)
+    (y * packed(im, gs)).sum().backward()
+    assert rel_err(zt.grad.cpu().numpy(), im.pack([oracle.adjoint(d, g) for g in gs])) < TOL32
+    assert rel_err(dt.grad.cpu().numpy(), sum(oracle.filter_corr(z, g, m) for z, g in zip(zs, gs))) < TOL32
+
+    rs = gs
+    gzs = [f32(rng.standard_normal((K, H, W))) for H, W in hw]
+    dt2 = to_dev(d).requires_grad_(True)
+    rt = packed(im, rs).requires_grad_(True)
+    g = adjoint(ctx, im, rt, dt2)
+    (g * packed(im, gzs)).sum().backward()
+    assert rel_err(rt.grad.cpu().numpy(), im.pack([oracle.synthesize(d, gz) for gz in gzs])) < TOL32
+    assert rel_err(dt2.grad.cpu().numpy(), sum(oracle.filter_corr(gz, r, m) for gz, r in zip(gzs, rs))) < TOL32
+
+
+def _unrolled_case(ctx, hw, K, m, p, lam, T, with_W, seed=4):
+    from paper_1909_00145_amd.ops import Images
+
+    xs, d, Ws = make_problem(seed, hw, K, m, with_W)
+    im = Images(hw)
+    mask = ctx.mask(im, K, p, seed, 1)
+    masks = [a.astype(bool) for a in im.unpack(mask.cpu().numpy(), K)]
+    eta = 1.0 / oracle.lipschitz_code(d, im.max_side)
+    rng = np.random.default_rng(seed)
+    z0s = [np.where(S, f32(0.05 * rng.standard_normal(S.shape)), 0.0) for S in masks]
+    return im, xs, d, Ws, mask, masks, eta, z0s
+
+
+@pytest.mark.parametrize("hw,K,m,p,lam,T,with_W", [
+    ([(32, 32)] * 4, 24, 11, 0.2, 0.5, 10, False),
+    ([(30, 41), (17, 22)], 8, 5, 0.5, 0.2, 4, True),
+])
+def test_unrolled_ista_gradients(ctx, hw, K, m, p, lam, T, with_W):
+    from paper_1909_00145_amd.autograd import synthesis, unrolled_ista
+
+    say("autograd unrolled", hw, K, m, T, with_W)
+    im, xs, d, Ws, mask, masks, eta, z0s = _unrolled_case(ctx, hw, K, m, p, lam, T, with_W)
+    x = packed(im, xs).requires_grad_(True)
+    dt = to_dev(d).requires_grad_(True)
+    z0 = packed(im, z0s).requires_grad_(True)
+    Wt = packed(im, Ws, torch.uint8) if Ws else None
+    zT = unrolled_ista(ctx, im, x, dt, z0, mask, eta, lam, T, W=Wt)
+    e = x - synthesis(ctx, im, zT, dt)
+    loss = 0.5 * (e * e).sum()
+    loss.backward()
+    ref_loss, ref_gz, ref_gd, ref_gx = 0.0, [], np.zeros_like(d), []
+    for i in range(len(hw)):
+        l, gz, gd, gx = unrolled.loss_and_grads(xs[i], d, z0s[i], masks[i], eta, lam, T, None if Ws is None else Ws[i])
+        ref_loss += l
+        ref_gz.append(gz)
+        ref_gd += gd
+        ref_gx.append(gx)
+    lv = float(loss.detach())
+    say("  loss", lv, ref_loss)
+    assert abs(lv - ref_loss) <= 1e-5 * ref_loss
+    for got, ref, name in ((z0.grad, im.pack(ref_gz), "z0"), (dt.grad, ref_gd, "d"), (x.grad, im.pack(ref_gx), "x")):
+        err = rel_err(got.detach().cpu().numpy(), ref)
+        say("  grad", name, err)
+        assert err < 1e-4
+
+
+def test_checkpoint_segments_give_identical_gradients(ctx):
+    from paper_1909_00145_amd.autograd import synthesis, unrolled_ista
+
+    say("autograd checkpoint segments")
+    hw = [(28, 33), (20, 20)]
+    K, m, p, lam, T = 10, 7, 0.3, 0.3, 6
+    im, xs, d, Ws, mask, masks, eta, z0s = _unrolled_case(ctx, hw, K, m, p, lam, T, False, seed=9)
+    grads = []
+    for every in (1, 4):
+        x = packed(im, xs).requires_grad_(True)
+        dt = to_dev(d).requires_grad_(True)
+        zT = unrolled_ista(ctx, im, x, dt, packed(im, z0s), mask, eta, lam, T, checkpoint_every=every)
+        e = x - synthesis(ctx, im, zT, dt)
+        (0.5 * (e * e).sum()).backward()
+        grads.append((dt.grad.cpu().numpy(), x.grad.cpu().numpy()))
+    np.testing.assert_array_equal(grads[0][0], grads[1][0])
+    np.testing.assert_array_equal(grads[0][1], grads[1][1])
+
+
+def test_layer_rejects_bad_step(ctx):
+    from paper_1909_00145_amd._lib import CSCError
+    from paper_1909_00145_amd.ops import Images
+
+    im = Images([(8, 8)])
+    K, m = 2, 3
+    z = torch.zeros(K * 64, device="cuda")
+    out = torch.full_like(z, 7.0)
+    with pytest.raises(CSCError):
+        ctx.ista_forward(im, torch.zeros(64, device="cuda"), torch.zeros(K, m, m, device="cuda"),
+                         torch.ones(K * 64, dtype=torch.uint8, device="cuda"), z, 0.0, 0.1, out=out)
+    assert float(out.min()) == 7.0 and float(out.max()) == 7.0
