@@ -124,7 +124,11 @@ int csc_version(void);
  *   n_iter : proximal-gradient iterations, >= 0.
  *   step   : > 0 to force a step; <= 0 selects 1 / L_z with L_z from csc_lipschitz_code
  *            (max_side = the largest image side of the batch).
- *   precision : csc_precision.   stats : host, may be NULL (filling it synchronises). */
+ *   precision : csc_precision.  CSC_BF16: the adjoint correlation of each 16 x 16 pixel tile
+ *            is one GEMM on the matrix cores (filters x pixels x taps) with d and r rounded
+ *            to BF16 and FP32 accumulation; the selected-set update, the residual and the
+ *            codes stay FP32.
+ *   stats  : host, may be NULL (filling it synchronises). */
 int csc_code_step(csc_handle h, const csc_images *im, const float *x, const uint8_t *W,
                   const float *d, int K, int m, float *z, double lambda, double p,
                   uint64_t seed, uint32_t draw, int n_iter, double step, int precision,
@@ -144,6 +148,10 @@ int csc_code_step(csc_handle h, const csc_images *im, const float *x, const uint
  *   B_bar += sum_i Z_i^T W_i x_i, t += 1, Ld_sum += L_d(this batch); then n_iter steps
  *     d <- P(d - (C_bar d - B_bar) / Ld_sum)      (= P(d - (C^t d - B^t) / (Ld_sum / t))).
  *   step is ignored in this mode.
+ *   precision : CSC_BF16 computes the batch gradient Z^T W r (and, with an observation
+ *     mask, the power-iteration products Z^T y) on the matrix cores with BF16 operands and
+ *     FP32 accumulation; the surrogates, their products and the lag-sum power iteration
+ *     are FP64 in both precisions.
  *   z : codes, packed, FP32 (read only).   d : filters, in/out.
  *   L_d_out : host, may be NULL; receives this batch's L_d (synchronises). */
 int csc_dict_step(csc_handle h, const csc_images *im, const float *x, const uint8_t *W,

@@ -426,8 +426,18 @@ int filter_corr_lists(csc_ctx *h, int K, int m, FmLists F, const float *r, float
     return CSC_OK;
 }
 
+// G = sum_i Z_i^T r_i with BF16 operands on the matrix cores (per-pixel lists).
+int filter_corr_bf16(csc_ctx *h, int K, int m, Lists L, const float *r, float *G) {
+    const Geometry &g = h->geo;
+    WS(part, float, WS_PART, (size_t)corr_mfma_blocks(g, K) * K * m * m);
+    PROF(CSC_PK_CORR);
+    HIPCHK(launch_corr_mfma(g, K, m, L, r, part, G, h->stream));
+    return CSC_OK;
+}
+
 // Power iteration on sum_i Z_i^T W_i Z_i; leaves the estimate in the device scalar SC_LAM.
-int power_iteration(csc_ctx *h, int K, int m, Lists L, FmLists F, const unsigned char *W, int n_power) {
+int power_iteration(csc_ctx *h, int K, int m, Lists L, FmLists F, const unsigned char *W, int n_power,
+                    int precision) {
     const Geometry &g = h->geo;
     const int M = m * m;
     WS(v, float, WS_V, K * M);
@@ -441,7 +451,7 @@ int power_iteration(csc_ctx *h, int K, int m, Lists L, FmLists F, const unsigned
             PROF(CSC_PK_SYNTH);
             HIPCHK(synth(h, K, m, L, v, nullptr, W, R, SYNTH_WEIGHTED));
         }
-        int st = filter_corr_lists(h, K, m, F, R, w);
+        int st = precision == CSC_BF16 ? filter_corr_bf16(h, K, m, L, R, w) : filter_corr_lists(h, K, m, F, R, w);
         if (st) return st;
         PROF(CSC_PK_UPDATE);
         HIPCHK(launch_power_update(v, w, K * M, sc + SC_LAM, h->stream));
@@ -567,7 +577,6 @@ extern "C" int csc_code_step(csc_handle h, const csc_images *im, const float *x,
     if (!(p > 0.0 && p <= 1.0)) return fail(h, CSC_EINVAL, "p must lie in (0, 1]");
     if (n_iter < 0) return fail(h, CSC_EINVAL, "n_iter must be >= 0");
     if (!std::isfinite(step)) return fail(h, CSC_EINVAL, "step must be finite");
-    if (precision != CSC_FP32) return fail(h, CSC_EUNSUPPORTED, "BF16 code step not built yet");
     HIPCHK(hipSetDevice(h->device));
     if ((st = geometry(h, im))) return st;
     const Geometry &g = h->geo;
@@ -623,8 +632,12 @@ extern "C" int csc_code_step(csc_handle h, const csc_images *im, const float *x,
         }
         {
             PROF(CSC_PK_ADJOINT);
-            HIPCHK(launch_adjoint_shrink(g, K, m, mw, soff, pairs[cur], nzc[cur], pairs[cur ^ 1], nzc[cur ^ 1], R,
-                                         d, feta, fthr, nnzsum, h->stream));
+            if (precision == CSC_BF16)
+                HIPCHK(launch_adjoint_shrink_mfma(g, K, m, mw, soff, pairs[cur], nzc[cur], pairs[cur ^ 1],
+                                                  nzc[cur ^ 1], R, d, feta, fthr, nnzsum, h->stream));
+            else
+                HIPCHK(launch_adjoint_shrink(g, K, m, mw, soff, pairs[cur], nzc[cur], pairs[cur ^ 1], nzc[cur ^ 1],
+                                             R, d, feta, fthr, nnzsum, h->stream));
         }
         cur ^= 1;
     }
@@ -664,7 +677,6 @@ extern "C" int csc_dict_step(csc_handle h, const csc_images *im, const float *x,
     if (!std::isfinite(step)) return fail(h, CSC_EINVAL, "step must be finite");
     if (sur && (!sur->C || !sur->B || sur->t < 0 || !(sur->Ld_sum >= 0.0)))
         return fail(h, CSC_EINVAL, "surrogate: need C, B, t >= 0 and Ld_sum >= 0");
-    if (precision != CSC_FP32) return fail(h, CSC_EUNSUPPORTED, "BF16 filter step not built yet");
     HIPCHK(hipSetDevice(h->device));
     if ((st = geometry(h, im))) return st;
     const Geometry &g = h->geo;
@@ -693,7 +705,7 @@ extern "C" int csc_dict_step(csc_handle h, const csc_images *im, const float *x,
         HIPCHK(launch_surrogate_lag(g, K, m, L, F.off, F.codes, Rl, Es, h->stream));
     }
     if (need_ld) {
-        if (W) st = power_iteration(h, K, m, L, F, W, n_power);
+        if (W) st = power_iteration(h, K, m, L, F, W, n_power, precision);
         else st = power_iteration_lag(h, K, m, Rl, n_power);
         if (st) return st;
     }
@@ -715,7 +727,8 @@ extern "C" int csc_dict_step(csc_handle h, const csc_images *im, const float *x,
                 PROF(CSC_PK_SYNTH);
                 HIPCHK(synth(h, K, m, L, d, x, W, R, SYNTH_RESIDUAL));
             }
-            if ((st = filter_corr_lists(h, K, m, F, R, G))) return st;
+            st = precision == CSC_BF16 ? filter_corr_bf16(h, K, m, L, R, G) : filter_corr_lists(h, K, m, F, R, G);
+            if (st) return st;
             PROF(CSC_PK_UPDATE);
             HIPCHK(launch_batch_update(d, G, sc + SC_LAM, K, M, h->stream));
         }
@@ -838,6 +851,7 @@ extern "C" int csc_filter_corr(csc_handle h, const csc_images *im, const float *
     Lists L;
     unsigned long long nz = 0;
     if ((st = build_nonzero_lists(h, K, z, &L, &nz))) return st;
+    if (precision == CSC_BF16) return filter_corr_bf16(h, K, m, L, r, G);
     FmLists F;
     if ((st = build_fm_lists(h, K, L, nz, &F))) return st;
     return filter_corr_lists(h, K, m, F, r, G);

@@ -18,29 +18,6 @@ namespace scsc {
 
 namespace {
 
-struct PixelCtx {
-    TileInfo t;
-    ImgInfo im;
-    int ly, lx, y, x;
-    bool valid;
-    long long p_img;  // y * W + x
-    long long gp;     // packed pixel index
-};
-
-__device__ __forceinline__ PixelCtx pixel_ctx(const ImgInfo *imgs, const TileInfo *tiles) {
-    PixelCtx c;
-    c.t = tiles[blockIdx.x];
-    c.im = imgs[c.t.img];
-    c.ly = threadIdx.x / TS;
-    c.lx = threadIdx.x % TS;
-    c.y = c.t.ty * TS + c.ly;
-    c.x = c.t.tx * TS + c.lx;
-    c.valid = c.y < c.im.H && c.x < c.im.W;
-    c.p_img = (long long)c.y * c.im.W + c.x;
-    c.gp = c.im.pix_off + c.p_img;
-    return c;
-}
-
 // ---------------------------------------------------------------------------
 // Selection (eq. 2): one Philox call yields the words of 4 consecutive
 // coordinate indices l = (y W + x) K + k, so a pixel needs about K / 4 calls.
@@ -529,6 +506,140 @@ __global__ __launch_bounds__(TPB) void k_adjoint_shrink(const ImgInfo *imgs, con
 // Dense adjoint D^T r at every coordinate.  Thread <-> pixel with its residual
 // window in registers; all lanes walk the same k, so filter reads from LDS are
 // broadcasts and the stores of one k are coalesced.
+// ---------------------------------------------------------------------------
+// BF16 variant of the proximal-gradient iteration: the adjoint correlation of
+// the whole 16 x 16 tile is an implicit-im2col GEMM on the matrix cores,
+//     G[k][q] = sum_t d_k[t] r[q + t]   (M = filters, N = the tile's pixels,
+//                                        K-dim = the m^2 taps padded to 32s),
+// with both operands rounded to BF16 (round to nearest even) and FP32
+// accumulation (v_mfma_f32_16x16x32_bf16).  Wave w owns pixel rows 4w..4w+3 (four
+// 16-pixel column tiles) and keeps their im2col fragments in registers; filters
+// are taken 32 at a time, their G written to LDS, and the same selected-set
+// epilogue as the FP32 kernel (u = z + eta g, shrink, new lists) reads it there.
+// Fragment layout of the 16x16x32 instruction (lane l, element i):
+//   A: row l % 16, k 8 (l / 16) + i;  B: k 8 (l / 16) + i, column l % 16;
+//   D: row 4 (l / 16) + i, column l % 16.
+// ---------------------------------------------------------------------------
+constexpr int MF_KB = 32;  // filters per chunk
+
+template <int MM>
+__global__ __launch_bounds__(TPB) void k_adjoint_shrink_mfma(const ImgInfo *imgs, const TileInfo *tiles, int K,
+                                                             long long n_pix, const unsigned *__restrict__ mask_words,
+                                                             const unsigned *__restrict__ soff,
+                                                             const Pair *__restrict__ oldp,
+                                                             const unsigned short *__restrict__ oldc,
+                                                             Pair *__restrict__ newp,
+                                                             unsigned short *__restrict__ newc,
+                                                             const float *__restrict__ r, const float *__restrict__ d,
+                                                             float eta, float thr,
+                                                             unsigned long long *__restrict__ nnz_acc) {
+    constexpr int C = MM / 2, RW = TS + 2 * C, M = MM * MM, NKS = (M + 31) / 32, MP = 32 * NKS;
+    __shared__ __bf16 rb[RW * RW];
+    __shared__ bf16x8 db[MF_KB * MP / 8];  // [MF_KB][MP] filter chunk, taps zero padded
+    __shared__ float gc[MF_KB][TPB];       // G of the chunk, [filter][tile pixel]
+    __shared__ Pair op[ADJ_CAP];
+    __shared__ int scratch[TPB];
+    __shared__ int bsum;
+
+    PixelCtx c = pixel_ctx(imgs, tiles);
+    const int oy = c.t.ty * TS - C, ox = c.t.tx * TS - C;
+    for (int i = threadIdx.x; i < RW * RW; i += TPB) {
+        const int gy = oy + i / RW, gx = ox + i % RW;
+        float v = 0.f;
+        if (gy >= 0 && gy < c.im.H && gx >= 0 && gx < c.im.W) v = r[c.im.pix_off + (long long)gy * c.im.W + gx];
+        rb[i] = (__bf16)v;
+    }
+    const unsigned base = c.valid ? soff[c.gp] : 0u;
+    const int ocnt = c.valid ? (int)oldc[c.gp] : 0;
+    int total;
+    const int ex = block_exclusive_scan(ocnt, scratch, &total);
+    const bool staged = total <= ADJ_CAP;
+    if (staged)
+        for (int j = 0; j < ocnt; ++j) op[ex + j] = oldp[base + j];
+    __syncthreads();
+
+    // im2col fragments of this wave's four column tiles (pixel rows 4w..4w+3)
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int fcol = lane & 15, fk = 8 * (lane >> 4);
+    bf16x8 bfr[4][NKS];
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) {
+        const int py = wave * 4 + ct;
+#pragma unroll
+        for (int ks = 0; ks < NKS; ++ks) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int t = ks * 32 + fk + i;
+                bfr[ct][ks][i] = t < M ? rb[(py + t / MM) * RW + fcol + t % MM] : (__bf16)0.f;
+            }
+        }
+    }
+
+    int oi = 0;
+    Pair oe = ocnt > 0 ? (staged ? op[ex] : oldp[base]) : Pair{INT_MAX, 0.f};
+    int nn = 0;
+    for (int k0 = 0; k0 < K; k0 += MF_KB) {
+        const int nk = min(MF_KB, K - k0);
+        __syncthreads();  // the previous chunk's epilogue is done with db and gc
+        for (int i = threadIdx.x; i < MF_KB * MP; i += TPB) {
+            const int kk = i / MP, t = i % MP;
+            reinterpret_cast<__bf16 *>(db)[i] = (kk < nk && t < M) ? (__bf16)d[(long long)(k0 + kk) * M + t] : (__bf16)0.f;
+        }
+        __syncthreads();
+        const int nrt = (nk + 15) >> 4;
+        for (int rt = 0; rt < nrt; ++rt) {
+            bf16x8 afr[NKS];
+#pragma unroll
+            for (int ks = 0; ks < NKS; ++ks) afr[ks] = db[(rt * 16 + fcol) * (MP / 8) + ks * 4 + (lane >> 4)];
+#pragma unroll
+            for (int ct = 0; ct < 4; ++ct) {
+                f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int ks = 0; ks < NKS; ++ks)
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr[ks], bfr[ct][ks], acc, 0, 0, 0);
+                const int px = (wave * 4 + ct) * TS + fcol;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) gc[rt * 16 + (lane >> 4) * 4 + i][px] = acc[i];
+            }
+        }
+        __syncthreads();
+        if (!c.valid) continue;
+        const int k1 = k0 + nk;
+        for (int w = k0 >> 5; w <= (k1 - 1) >> 5; ++w) {
+            unsigned bits = mask_words[(long long)w * n_pix + c.gp];
+            const int lo = k0 - 32 * w, hi = k1 - 32 * w;
+            if (lo > 0) bits &= ~0u << lo;
+            if (hi < 32) bits &= (1u << hi) - 1u;
+            while (bits) {
+                const int b = __builtin_ctz(bits);
+                bits &= bits - 1u;
+                const int k = 32 * w + b;
+                while (oe.k < k) {
+                    ++oi;
+                    oe = oi < ocnt ? (staged ? op[ex + oi] : oldp[base + oi]) : Pair{INT_MAX, 0.f};
+                }
+                float zold = 0.f;
+                if (oe.k == k) {
+                    zold = oe.v;
+                    ++oi;
+                    oe = oi < ocnt ? (staged ? op[ex + oi] : oldp[base + oi]) : Pair{INT_MAX, 0.f};
+                }
+                const float v = soft_threshold(fmaf(eta, gc[k - k0][threadIdx.x], zold), thr);
+                if (v != 0.f) {
+                    newp[base + nn] = Pair{k, v};
+                    ++nn;
+                }
+            }
+        }
+    }
+    if (c.valid) newc[c.gp] = (unsigned short)nn;
+    if (threadIdx.x == 0) bsum = 0;
+    __syncthreads();
+    if (nn) atomicAdd(&bsum, nn);
+    __syncthreads();
+    if (threadIdx.x == 0 && nnz_acc && bsum) atomicAdd(nnz_acc, (unsigned long long)bsum);
+}
+
 template <int MM>
 __global__ __launch_bounds__(TPB) void k_adjoint_dense(const ImgInfo *imgs, const TileInfo *tiles, int K,
                                                        const float *__restrict__ r, const float *__restrict__ d,
@@ -691,6 +802,16 @@ hipError_t adjoint_shrink_impl(const Geometry &g, int K, const unsigned *mw, con
 }
 
 template <int MM>
+hipError_t adjoint_shrink_mfma_impl(const Geometry &g, int K, const unsigned *mw, const unsigned *soff,
+                                    const Pair *oldp, const unsigned short *oldc, Pair *newp, unsigned short *newc,
+                                    const float *r, const float *d, float eta, float thr,
+                                    unsigned long long *nnz_acc, hipStream_t s) {
+    hipLaunchKernelGGL(k_adjoint_shrink_mfma<MM>, dim3(g.n_tiles), dim3(TPB), 0, s, g.d_img, g.d_tiles, K, g.n_pix,
+                       mw, soff, oldp, oldc, newp, newc, r, d, eta, thr, nnz_acc);
+    return hipGetLastError();
+}
+
+template <int MM>
 hipError_t adjoint_dense_impl(const Geometry &g, int K, const float *r, const float *d, float *out,
                               hipStream_t s) {
     constexpr int M = MM * MM, M4 = (M + 3) / 4 * 4;
@@ -714,6 +835,14 @@ hipError_t launch_adjoint_shrink(const Geometry &g, int K, int m, const unsigned
                                  float eta, float thr, unsigned long long *nnz_acc, hipStream_t s) {
     SCSC_DISPATCH_M(m, adjoint_shrink_impl, g, K, mask_words, soff, old_pairs, old_cnt, new_pairs, new_cnt, r, d,
                     eta, thr, nnz_acc, s);
+}
+
+hipError_t launch_adjoint_shrink_mfma(const Geometry &g, int K, int m, const unsigned *mask_words,
+                                      const unsigned *soff, const Pair *old_pairs, const unsigned short *old_cnt,
+                                      Pair *new_pairs, unsigned short *new_cnt, const float *r, const float *d,
+                                      float eta, float thr, unsigned long long *nnz_acc, hipStream_t s) {
+    SCSC_DISPATCH_M(m, adjoint_shrink_mfma_impl, g, K, mask_words, soff, old_pairs, old_cnt, new_pairs, new_cnt, r,
+                    d, eta, thr, nnz_acc, s);
 }
 
 hipError_t launch_adjoint_dense(const Geometry &g, int K, int m, const float *r, const float *d, float *out,

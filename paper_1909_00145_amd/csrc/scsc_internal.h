@@ -97,6 +97,35 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint2 k) {
     return c;
 }
 
+// Pixel of a 16 x 16 geometry tile owned by thread threadIdx.x of workgroup
+// blockIdx.x (row-major inside the tile).
+struct PixelCtx {
+    TileInfo t;
+    ImgInfo im;
+    int ly, lx, y, x;
+    bool valid;
+    long long p_img;  // y * W + x
+    long long gp;     // packed pixel index
+};
+
+__device__ __forceinline__ PixelCtx pixel_ctx(const ImgInfo *imgs, const TileInfo *tiles, int tile = -1) {
+    PixelCtx c;
+    c.t = tiles[tile < 0 ? (int)blockIdx.x : tile];
+    c.im = imgs[c.t.img];
+    c.ly = threadIdx.x / TS;
+    c.lx = threadIdx.x % TS;
+    c.y = c.t.ty * TS + c.ly;
+    c.x = c.t.tx * TS + c.lx;
+    c.valid = c.y < c.im.H && c.x < c.im.W;
+    c.p_img = (long long)c.y * c.im.W + c.x;
+    c.gp = c.im.pix_off + c.p_img;
+    return c;
+}
+
+// Matrix-core fragment types (v_mfma_f32_16x16x32_bf16 operands and result).
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(4))) float f32x4;
+
 __device__ __forceinline__ float soft_threshold(float u, float t) {
     float a = fabsf(u) - t;
     return a > 0.f ? copysignf(a, u) : 0.f;
@@ -164,6 +193,11 @@ enum SynthMode { SYNTH_RESIDUAL = 0, SYNTH_PLAIN = 1, SYNTH_WEIGHTED = 2 };
 hipError_t launch_synth(const Geometry &g, int K, int m, Lists z, const float *d, const float *x,
                         const unsigned char *W, float *out, SynthMode mode, int variant, hipStream_t s);
 // One proximal-gradient iteration on the selected coordinates (FP32 VALU).
+// BF16 operands on the matrix cores, FP32 accumulation; same lists and epilogue.
+hipError_t launch_adjoint_shrink_mfma(const Geometry &g, int K, int m, const unsigned *mask_words,
+                                      const unsigned *soff, const Pair *old_pairs, const unsigned short *old_cnt,
+                                      Pair *new_pairs, unsigned short *new_cnt, const float *r, const float *d,
+                                      float eta, float thr, unsigned long long *nnz_acc, hipStream_t s);
 hipError_t launch_adjoint_shrink(const Geometry &g, int K, int m, const unsigned *mask_words,
                                  const unsigned *soff, const Pair *old_pairs, const unsigned short *old_cnt,
                                  Pair *new_pairs, unsigned short *new_cnt, const float *r, const float *d,
@@ -223,6 +257,12 @@ hipError_t launch_surrogate_corner(const Geometry &g, int K, int m, Lists z, dou
 hipError_t launch_surrogate_matvec(int K, int m, const double *C, const float *d, double *partial, double *y,
                                    hipStream_t s);
 long long surrogate_matvec_partial_elems(int K, int m);
+
+// G = sum_i Z_i^T r_i ([K][m][m], FP32) on the matrix cores from per-pixel code lists,
+// BF16 operands, FP32 accumulation; part needs corr_mfma_blocks(g, K) * K * m^2 floats.
+int corr_mfma_blocks(const Geometry &g, int K);
+hipError_t launch_corr_mfma(const Geometry &g, int K, int m, Lists z, const float *r, float *part, float *G,
+                            hipStream_t s);
 
 // Unrolled-layer elementwise kernels over n dense code entries:
 // out = mask ? shrink(z + eta g, thr) : 0;  gu = (mask && |z + eta g| > thr) ? gout : 0;
