@@ -214,7 +214,8 @@ typedef enum {
     CSC_PK_SUR_EXPAND = 14, /* C_bar += R - band terms, all blocks                       */
     CSC_PK_SUR_CORNER = 15, /* corner-ring correction of C_bar                            */
     CSC_PK_POWER = 16,   /* power-iteration products with the lag-sum normal matrix      */
-    CSC_PK_COUNT = 17
+    CSC_PK_GRAPH = 17,   /* replay of the captured proximal-gradient iterations (csc_set_graph) */
+    CSC_PK_COUNT = 18
 } csc_kernel_class;
 
 /* enable != 0: record a pair of HIP events on the handle's stream around every
@@ -245,6 +246,16 @@ int csc_ista_backward(csc_handle h, const csc_images *im, const float *x, const 
                       const float *d, int K, int m, const uint8_t *mask, const float *z_in,
                       const float *g_out, double eta, double lambda, float *g_z, float *g_d, float *g_x,
                       int precision);
+
+/* enable != 0: csc_code_step captures its n_iter proximal-gradient iterations
+ * (synthesis + adjoint launches of every image of the batch) into one HIP graph
+ * and replays it on later calls with the same shapes, options and workspaces;
+ * x, W and d are first copied into handle-owned buffers, and the step and
+ * threshold are read from device memory, so new values need no re-capture.
+ * Results are identical to the eager launches.  A graph is captured only once
+ * the synthesis variant is settled (autotuned or fixed).  enable == 0 (the
+ * default): eager launches; the cached graph is released. */
+int csc_set_graph(csc_handle h, int enable);
 
 /* Launch-variant autotuning (tile shape / threads per output pixel) of the
  * kernels that have several variants.  enable != 0 (the default): the first

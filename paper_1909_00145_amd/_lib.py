@@ -72,13 +72,14 @@ SIGNATURES = {
     "csc_profile_enable": (_i, [_vp, _i]),
     "csc_profile_read": (_i, [_vp, _i, C.POINTER(C.c_int64), C.POINTER(_d)]),
     "csc_set_autotune": (_i, [_vp, _i]),
+    "csc_set_graph": (_i, [_vp, _i]),
     "csc_ista_forward": (_i, [_vp, _pimg, _vp, _vp, _vp, _i, _i, _vp, _vp, _vp, _d, _d, _i]),
     "csc_ista_backward": (_i, [_vp, _pimg, _vp, _vp, _vp, _i, _i, _vp, _vp, _vp, _d, _d, _vp, _vp, _vp, _i]),
 }
 
 # csc_kernel_class
 KERNEL_CLASSES = ["select", "gather", "synth", "adjoint", "scatter", "lists", "corr", "update", "sur_acc",
-                  "sur_mv", "objective", "lipschitz", "dense", "sur_lag", "sur_expand", "sur_corner", "power"]
+                  "sur_mv", "objective", "lipschitz", "dense", "sur_lag", "sur_expand", "sur_corner", "power", "ista_graph"]
 
 
 def load(path: str = LIB_PATH) -> C.CDLL:

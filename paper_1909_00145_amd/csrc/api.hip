@@ -44,11 +44,23 @@ enum Slot {
     WS_DG,
     WS_GU,
     WS_T,
+    WS_XC,
+    WS_WC,
+    WS_DC,
     WS_COUNT
 };
 
 // Device scalars (doubles / u64) inside WS_SCAL.
-enum Scalar { SC_TOTAL = 0, SC_NNZ = 1, SC_LAM = 2, SC_LZ = 3, SC_OBJ = 4 /* 2 */, SC_NNZSUM = 6, SC_COUNT = 8 };
+enum Scalar {
+    SC_TOTAL = 0,
+    SC_NNZ = 1,
+    SC_LAM = 2,
+    SC_LZ = 3,
+    SC_OBJ = 4 /* 2 */,
+    SC_NNZSUM = 6,
+    SC_ETHR = 7 /* two floats: step, threshold */,
+    SC_COUNT = 8
+};
 
 struct Buffer {
     void *p = nullptr;
@@ -76,6 +88,13 @@ struct csc_ctx {
     std::vector<Rec> recs;
     long long prof_launches[CSC_PK_COUNT] = {};
     double prof_ms[CSC_PK_COUNT] = {};
+    // graph replay of the proximal-gradient iterations (csc_set_graph)
+    bool graphs = false;
+    bool capturing = false;
+    std::vector<uintptr_t> graph_key;
+    hipGraphExec_t graph_exec = nullptr;
+    hipStream_t graph_stream = nullptr;  // capture / replay stream when the handle's stream is the null stream
+    hipEvent_t graph_ev[2] = {nullptr, nullptr};
     // autotuner: launch variant per (kernel, m, K, log2 pixel count, mode)
     bool autotune = true;
     int force_variant = -1;
@@ -126,7 +145,7 @@ struct ProfScope {
     int cls;
     hipEvent_t a = nullptr;
     ProfScope(csc_ctx *h_, int cls_) : h(h_), cls(cls_) {
-        if (h->prof) {
+        if (h->prof && !h->capturing) {
             a = take_event(h);
             if (a) hipEventRecord(a, h->stream);
         }
@@ -209,6 +228,16 @@ hipError_t tuned_launch(csc_ctx *h, const std::array<int, 5> &key, int n_variant
     return hipSuccess;
 }
 
+// True when the variant of `key` is fixed (tuned, forced or tuning off), i.e.
+// a launch would not time variants.
+bool variant_settled(csc_ctx *h, const std::array<int, 5> &key) {
+    return h->force_variant >= 0 || !h->autotune || h->tuned.count(key) > 0;
+}
+
+std::array<int, 5> synth_key(csc_ctx *h, int K, int m, SynthMode mode) {
+    return {TK_SYNTH, m, K, ilog2(h->geo.n_pix), (int)mode};
+}
+
 // Synthesis / residual through the tuned launcher (tile shape and threads per
 // output pixel).  `representative` marks calls whose code density is typical of
 // the key (not the first iterations of a code step from zero codes); only those
@@ -217,7 +246,7 @@ hipError_t synth(csc_ctx *h, int K, int m, Lists L, const float *d, const float 
                  float *out, SynthMode mode, bool representative = true) {
     const Geometry &g = h->geo;
     return tuned_launch(
-        h, {TK_SYNTH, m, K, ilog2(g.n_pix), (int)mode}, 4,
+        h, synth_key(h, K, m, mode), 4,
         [&](int v) { return launch_synth(g, K, m, L, d, x, W, out, mode, v, h->stream); }, representative);
 }
 
@@ -516,6 +545,13 @@ extern "C" int csc_destroy(csc_handle h) {
     hipSetDevice(h->device);
     hipStreamSynchronize(h->stream);
     fold_records(h);
+    if (h->graph_exec) hipGraphExecDestroy(h->graph_exec);
+    if (h->graph_stream) {
+        hipStreamSynchronize(h->graph_stream);
+        hipStreamDestroy(h->graph_stream);
+    }
+    for (auto e : h->graph_ev)
+        if (e) hipEventDestroy(e);
     for (auto e : h->ev_pool) hipEventDestroy(e);
     for (auto &b : h->ws)
         if (b.p) hipFree(b.p);
@@ -624,23 +660,104 @@ extern "C" int csc_code_step(csc_handle h, const csc_images *im, const float *x,
         HIPCHK(launch_gather_selected(g, K, mw, soff, z, pairs[0], nzc[0], nnzsum, h->stream));
     }
     const float feta = (float)eta, fthr = (float)(eta * lambda);
-    int cur = 0;
-    for (int it = 0; it < n_iter; ++it) {
-        {
-            PROF(CSC_PK_SYNTH);
-            HIPCHK(synth(h, K, m, Lists{soff, nzc[cur], pairs[cur]}, d, x, W, R, SYNTH_RESIDUAL, it == n_iter - 1));
+    float *ethr = reinterpret_cast<float *>(sc + SC_ETHR);
+    HIPCHK(launch_set2(ethr, feta, fthr, h->stream));
+    // The n_iter iterations only launch kernels; their step and threshold are
+    // read from device scalars, so the same launches can be replayed as a graph.
+    const float *xi = x, *di = d;
+    const uint8_t *Wi = W;
+    const bool use_graph = h->graphs && n_iter > 0 && variant_settled(h, synth_key(h, K, m, SYNTH_RESIDUAL));
+    if (use_graph) {
+        // stable copies of the inputs the graph reads
+        WS(xc, float, WS_XC, g.n_pix);
+        WS(dc, float, WS_DC, (size_t)K * m * m);
+        HIPCHK(hipMemcpyAsync(xc, x, sizeof(float) * g.n_pix, hipMemcpyDeviceToDevice, h->stream));
+        HIPCHK(hipMemcpyAsync(dc, d, sizeof(float) * K * m * m, hipMemcpyDeviceToDevice, h->stream));
+        xi = xc;
+        di = dc;
+        if (W) {
+            WS(wc, uint8_t, WS_WC, g.n_pix);
+            HIPCHK(hipMemcpyAsync(wc, W, g.n_pix, hipMemcpyDeviceToDevice, h->stream));
+            Wi = wc;
         }
-        {
-            PROF(CSC_PK_ADJOINT);
-            if (precision == CSC_BF16)
-                HIPCHK(launch_adjoint_shrink_mfma(g, K, m, mw, soff, pairs[cur], nzc[cur], pairs[cur ^ 1],
-                                                  nzc[cur ^ 1], R, d, feta, fthr, nnzsum, h->stream));
-            else
-                HIPCHK(launch_adjoint_shrink(g, K, m, mw, soff, pairs[cur], nzc[cur], pairs[cur ^ 1], nzc[cur ^ 1],
-                                             R, d, feta, fthr, nnzsum, h->stream));
-        }
-        cur ^= 1;
     }
+    auto iterations = [&]() -> int {
+        int c = 0;
+        for (int it = 0; it < n_iter; ++it) {
+            {
+                PROF(CSC_PK_SYNTH);
+                HIPCHK(synth(h, K, m, Lists{soff, nzc[c], pairs[c]}, di, xi, Wi, R, SYNTH_RESIDUAL, it == n_iter - 1));
+            }
+            {
+                PROF(CSC_PK_ADJOINT);
+                if (precision == CSC_BF16)
+                    HIPCHK(launch_adjoint_shrink_mfma(g, K, m, mw, soff, pairs[c], nzc[c], pairs[c ^ 1], nzc[c ^ 1],
+                                                      R, di, ethr, nnzsum, h->stream));
+                else
+                    HIPCHK(launch_adjoint_shrink(g, K, m, mw, soff, pairs[c], nzc[c], pairs[c ^ 1], nzc[c ^ 1], R,
+                                                 di, ethr, nnzsum, h->stream));
+            }
+            c ^= 1;
+        }
+        return CSC_OK;
+    };
+    if (use_graph) {
+        const std::vector<uintptr_t> key = {
+            (uintptr_t)K, (uintptr_t)m, (uintptr_t)precision, (uintptr_t)n_iter, (uintptr_t)g.n_tiles,
+            (uintptr_t)g.n_pix, (uintptr_t)(h->force_variant + 1), (uintptr_t)h->tuned[synth_key(h, K, m, SYNTH_RESIDUAL)],
+            (uintptr_t)g.d_img, (uintptr_t)g.d_tiles, (uintptr_t)mw, (uintptr_t)soff, (uintptr_t)pairs[0],
+            (uintptr_t)pairs[1], (uintptr_t)nzc[0], (uintptr_t)nzc[1], (uintptr_t)R, (uintptr_t)sc, (uintptr_t)xi,
+            (uintptr_t)di, (uintptr_t)Wi};
+        // the null stream cannot be captured: use a private (default-priority) stream,
+        // ordered after and before the handle's stream with events
+        hipStream_t gs = h->stream;
+        if (gs == nullptr) {
+            if (!h->graph_stream) {
+                HIPCHK(hipStreamCreateWithFlags(&h->graph_stream, hipStreamNonBlocking));
+                HIPCHK(hipEventCreateWithFlags(&h->graph_ev[0], hipEventDisableTiming));
+                HIPCHK(hipEventCreateWithFlags(&h->graph_ev[1], hipEventDisableTiming));
+            }
+            gs = h->graph_stream;
+        }
+        if (!h->graph_exec || key != h->graph_key) {
+            if (h->graph_exec) {
+                HIPCHK(hipStreamSynchronize(gs));
+                hipGraphExecDestroy(h->graph_exec);
+                h->graph_exec = nullptr;
+            }
+            hipStream_t saved = h->stream;
+            HIPCHK(hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal));
+            h->stream = gs;
+            h->capturing = true;
+            const int cst = iterations();
+            h->capturing = false;
+            h->stream = saved;
+            hipGraph_t graph = nullptr;
+            const hipError_t ce = hipStreamEndCapture(gs, &graph);
+            if (cst) {
+                if (graph) hipGraphDestroy(graph);
+                return cst;
+            }
+            HIPCHK(ce);
+            const hipError_t ie = hipGraphInstantiate(&h->graph_exec, graph, nullptr, nullptr, 0);
+            hipGraphDestroy(graph);
+            HIPCHK(ie);
+            h->graph_key = key;
+        }
+        PROF(CSC_PK_GRAPH);
+        if (gs != h->stream) {
+            HIPCHK(hipEventRecord(h->graph_ev[0], h->stream));
+            HIPCHK(hipStreamWaitEvent(gs, h->graph_ev[0], 0));
+            HIPCHK(hipGraphLaunch(h->graph_exec, gs));
+            HIPCHK(hipEventRecord(h->graph_ev[1], gs));
+            HIPCHK(hipStreamWaitEvent(h->stream, h->graph_ev[1], 0));
+        } else {
+            HIPCHK(hipGraphLaunch(h->graph_exec, gs));
+        }
+    } else if ((st = iterations())) {
+        return st;
+    }
+    const int cur = n_iter & 1;
     {
         PROF(CSC_PK_SCATTER);
         HIPCHK(launch_scatter_dense(g, K, Lists{soff, nzc[cur], pairs[cur]}, z, h->stream));
@@ -970,6 +1087,19 @@ extern "C" int csc_ista_backward(csc_handle h, const csc_images *im, const float
     }
     PROF(CSC_PK_UPDATE);
     HIPCHK(launch_axpby(n, 1.f, GU, -feta, G, g_z, h->stream));
+    return CSC_OK;
+}
+
+extern "C" int csc_set_graph(csc_handle h, int enable) {
+    if (!h) return CSC_EINVAL;
+    h->graphs = enable != 0;
+    if (!h->graphs && h->graph_exec) {
+        hipSetDevice(h->device);
+        hipStreamSynchronize(h->stream);
+        hipGraphExecDestroy(h->graph_exec);
+        h->graph_exec = nullptr;
+        h->graph_key.clear();
+    }
     return CSC_OK;
 }
 

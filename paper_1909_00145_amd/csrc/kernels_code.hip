@@ -234,7 +234,11 @@ __global__ void k_sum_counts(const unsigned short *cnt, long long n, unsigned lo
 // when the region holds at most SYN_CAP pairs, the pairs themselves are staged.
 // Each output pixel then walks its m x m taps in a fixed order.
 // ---------------------------------------------------------------------------
-constexpr int SYN_CAP = 2880;
+// staging capacity (pairs) of a synthesis region: 16-row tiles / 8-row tiles
+template <int TY>
+constexpr int syn_cap() {
+    return TY >= 16 ? 2880 : 2048;
+}
 constexpr int SYN_DCAP = 12288;  // filters staged in LDS when K m^2 <= 12288 floats (48 KiB)
 
 // A staged code of the synthesis region: filter, region column, value.
@@ -253,143 +257,149 @@ struct __align__(8) SynPair {
 // the launch variant.  A region whose codes exceed the staging capacity reads
 // them from global memory instead, in the same order.
 template <int MM, bool DLDS, int TT, int TY, int SP>
-__global__ __launch_bounds__(TT *TY *SP) void k_synth(const ImgInfo *imgs, const TileInfo *tiles, int K, Lists zl,
-                                                      const float *__restrict__ d, const float *__restrict__ x,
-                                                      const unsigned char *__restrict__ W, float *__restrict__ out,
-                                                      int mode) {
+__global__ __launch_bounds__(TT *TY *SP) void k_synth(const ImgInfo *imgs, const TileInfo *tiles, int n_tiles, int K,
+                                                      Lists zl, const float *__restrict__ d,
+                                                      const float *__restrict__ x, const unsigned char *__restrict__ W,
+                                                      float *__restrict__ out, int mode) {
     constexpr int C = MM / 2, RW = TT + 2 * C, RH = TY + 2 * C, R = RW * RH, M = MM * MM, NP = TT * TY,
                   NT = NP * SP;
     constexpr int CH = (R + NT - 1) / NT;
     constexpr int RP = (MM + SP - 1) / SP;  // tap rows per part
-    constexpr int SUB = TS / TY;            // blocks per geometry tile
+    constexpr int SUB = TS / TY;            // work items per geometry tile
+    constexpr int CAP = syn_cap<TY>();
     __shared__ unsigned lgoff[R];
     __shared__ int lstart[R + 1];
     __shared__ unsigned short lcnt[R];
-    __shared__ SynPair lp[SYN_CAP];
+    __shared__ SynPair lp[CAP];
     __shared__ int scratch[NT];
     __shared__ float rows[SP > 1 ? MM : 1][SP > 1 ? NP : 1];
     __shared__ float dl[DLDS ? SYN_DCAP : 1];
 
-    const TileInfo t = tiles[blockIdx.x / SUB];
-    const ImgInfo im = imgs[t.img];
-    const int y0 = t.ty * TS + (int)(blockIdx.x % SUB) * TY, x0 = t.tx * TT;
-    if (y0 >= im.H) return;  // whole workgroup below the image
-    const int o = threadIdx.x % NP, part = threadIdx.x / NP;
-    const int ly = o / TT, lx = o % TT;
-    const int y = y0 + ly, xx = x0 + lx;
-    const bool valid = y < im.H && xx < im.W;
     if (DLDS)
         for (int i = threadIdx.x; i < K * M; i += NT) dl[i] = d[i];
-    const int oy = y0 - C, ox = x0 - C;
-    int mysum = 0;
-#pragma unroll
-    for (int j = 0; j < CH; ++j) {
-        const int i = threadIdx.x * CH + j;
-        if (i < R) {
-            const int gy = oy + i / RW, gx = ox + i % RW;
-            int n = 0;
-            unsigned off = 0;
-            if (gy >= 0 && gy < im.H && gx >= 0 && gx < im.W) {
-                const long long gp = im.pix_off + (long long)gy * im.W + gx;
-                n = zl.cnt[gp];
-                off = zl.off[gp];
-            }
-            lcnt[i] = (unsigned short)n;
-            lgoff[i] = off;
-            mysum += n;
-        }
-    }
-    int total;
-    int ex = block_exclusive_scan_n<NT>(mysum, scratch, &total);
-    const bool staged = total <= SYN_CAP;
-#pragma unroll
-    for (int j = 0; j < CH; ++j) {
-        const int i = threadIdx.x * CH + j;
-        if (i < R) {
-            lstart[i] = ex;
-            const int n = lcnt[i];
-            if (staged)
-                for (int q = 0; q < n; ++q) {
-                    const Pair e = zl.pairs[lgoff[i] + q];
-                    lp[ex + q] = SynPair{(unsigned short)e.k, (unsigned short)(i % RW), e.v};
-                }
-            ex += n;
-        }
-    }
-    if (threadIdx.x == 0) lstart[R] = total;
-    __syncthreads();
     const float *dd = DLDS ? dl : d;
-    float acc = 0.f;
-    if (valid) {
-        const int r0 = part * RP, r1 = r0 + RP < MM ? r0 + RP : MM;
-        for (int r = r0; r < r1; ++r) {
-            const int sy = r - C;
-            float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
-            const int rb = (ly + C - sy) * RW + lx;
-            if (staged) {
-                const int j0 = lstart[rb], j1 = lstart[rb + 2 * C + 1];
-                const float *drow = dd + r * MM + 2 * C + lx;  // tap column = 2c - (col - lx)
-                int j = j0;
-                for (; j + 3 < j1; j += 4) {
-                    const SynPair e0 = lp[j], e1 = lp[j + 1], e2 = lp[j + 2], e3 = lp[j + 3];
-                    a0 = fmaf(drow[e0.k * M - e0.col], e0.v, a0);
-                    a1 = fmaf(drow[e1.k * M - e1.col], e1.v, a1);
-                    a2 = fmaf(drow[e2.k * M - e2.col], e2.v, a2);
-                    a3 = fmaf(drow[e3.k * M - e3.col], e3.v, a3);
+    const int o = threadIdx.x % NP, part = threadIdx.x / NP;
+    const int ly = o / TT, lx = o % TT;
+    long long first, step, end;
+    xcd_work((long long)n_tiles * SUB, first, step, end);
+    for (long long item = first; item < end; item += step) {
+        const TileInfo t = tiles[item / SUB];
+        const ImgInfo im = imgs[t.img];
+        const int y0 = t.ty * TS + (int)(item % SUB) * TY, x0 = t.tx * TT;
+        if (y0 >= im.H) continue;  // work item below the image (uniform over the workgroup)
+        __syncthreads();           // LDS of the previous item is no longer read
+        const int y = y0 + ly, xx = x0 + lx;
+        const bool valid = y < im.H && xx < im.W;
+        const int oy = y0 - C, ox = x0 - C;
+        int mysum = 0;
+#pragma unroll
+        for (int j = 0; j < CH; ++j) {
+            const int i = threadIdx.x * CH + j;
+            if (i < R) {
+                const int gy = oy + i / RW, gx = ox + i % RW;
+                int n = 0;
+                unsigned off = 0;
+                if (gy >= 0 && gy < im.H && gx >= 0 && gx < im.W) {
+                    const long long gp = im.pix_off + (long long)gy * im.W + gx;
+                    n = zl.cnt[gp];
+                    off = zl.off[gp];
                 }
-                // tail: element j - j0 goes to accumulator (j - j0) mod 4 as in the loop
-                if (j < j1) a0 = fmaf(drow[lp[j].k * M - lp[j].col], lp[j].v, a0);
-                if (j + 1 < j1) a1 = fmaf(drow[lp[j + 1].k * M - lp[j + 1].col], lp[j + 1].v, a1);
-                if (j + 2 < j1) a2 = fmaf(drow[lp[j + 2].k * M - lp[j + 2].col], lp[j + 2].v, a2);
-            } else {
-                // same elements in the same order; b0 always takes the next element and the
-                // four accumulators rotate, so element u lands in accumulator u mod 4
-                float b0 = 0.f, b1 = 0.f, b2 = 0.f, b3 = 0.f;
-                int u = 0;
-                for (int w = 0; w < MM; ++w) {
-                    const int n = lcnt[rb + w];
-                    const Pair *src = zl.pairs + lgoff[rb + w];
-                    const float *dt = dd + r * MM + (MM - 1 - w);
-                    for (int q = 0; q < n; ++q, ++u) {
-                        const Pair e = src[q];
-                        const float nb = fmaf(dt[e.k * M], e.v, b0);
-                        b0 = b1;
-                        b1 = b2;
-                        b2 = b3;
-                        b3 = nb;
+                lcnt[i] = (unsigned short)n;
+                lgoff[i] = off;
+                mysum += n;
+            }
+        }
+        int total;
+        int ex = block_exclusive_scan_n<NT>(mysum, scratch, &total);
+        const bool staged = total <= CAP;
+#pragma unroll
+        for (int j = 0; j < CH; ++j) {
+            const int i = threadIdx.x * CH + j;
+            if (i < R) {
+                lstart[i] = ex;
+                const int n = lcnt[i];
+                if (staged)
+                    for (int q = 0; q < n; ++q) {
+                        const Pair e = zl.pairs[lgoff[i] + q];
+                        lp[ex + q] = SynPair{(unsigned short)e.k, (unsigned short)(i % RW), e.v};
+                    }
+                ex += n;
+            }
+        }
+        if (threadIdx.x == 0) lstart[R] = total;
+        __syncthreads();
+        float acc = 0.f;
+        if (valid) {
+            const int r0 = part * RP, r1 = r0 + RP < MM ? r0 + RP : MM;
+            for (int r = r0; r < r1; ++r) {
+                const int sy = r - C;
+                float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+                const int rb = (ly + C - sy) * RW + lx;
+                if (staged) {
+                    const int j0 = lstart[rb], j1 = lstart[rb + 2 * C + 1];
+                    const float *drow = dd + r * MM + 2 * C + lx;  // tap column = 2c - (col - lx)
+                    int j = j0;
+                    for (; j + 3 < j1; j += 4) {
+                        const SynPair e0 = lp[j], e1 = lp[j + 1], e2 = lp[j + 2], e3 = lp[j + 3];
+                        a0 = fmaf(drow[e0.k * M - e0.col], e0.v, a0);
+                        a1 = fmaf(drow[e1.k * M - e1.col], e1.v, a1);
+                        a2 = fmaf(drow[e2.k * M - e2.col], e2.v, a2);
+                        a3 = fmaf(drow[e3.k * M - e3.col], e3.v, a3);
+                    }
+                    // tail: element j - j0 goes to accumulator (j - j0) mod 4 as in the loop
+                    if (j < j1) a0 = fmaf(drow[lp[j].k * M - lp[j].col], lp[j].v, a0);
+                    if (j + 1 < j1) a1 = fmaf(drow[lp[j + 1].k * M - lp[j + 1].col], lp[j + 1].v, a1);
+                    if (j + 2 < j1) a2 = fmaf(drow[lp[j + 2].k * M - lp[j + 2].col], lp[j + 2].v, a2);
+                } else {
+                    // same elements in the same order; b0 always takes the next element and the
+                    // four accumulators rotate, so element u lands in accumulator u mod 4
+                    float b0 = 0.f, b1 = 0.f, b2 = 0.f, b3 = 0.f;
+                    int u = 0;
+                    for (int w = 0; w < MM; ++w) {
+                        const int n = lcnt[rb + w];
+                        const Pair *src = zl.pairs + lgoff[rb + w];
+                        const float *dt = dd + r * MM + (MM - 1 - w);
+                        for (int q = 0; q < n; ++q, ++u) {
+                            const Pair e = src[q];
+                            const float nb = fmaf(dt[e.k * M], e.v, b0);
+                            b0 = b1;
+                            b1 = b2;
+                            b2 = b3;
+                            b3 = nb;
+                        }
+                    }
+                    // b_i now holds accumulator (u + i) mod 4
+                    switch (u & 3) {
+                        case 0: a0 = b0; a1 = b1; a2 = b2; a3 = b3; break;
+                        case 1: a1 = b0; a2 = b1; a3 = b2; a0 = b3; break;
+                        case 2: a2 = b0; a3 = b1; a0 = b2; a1 = b3; break;
+                        default: a3 = b0; a0 = b1; a1 = b2; a2 = b3; break;
                     }
                 }
-                // b_i now holds accumulator (u + i) mod 4
-                switch (u & 3) {
-                    case 0: a0 = b0; a1 = b1; a2 = b2; a3 = b3; break;
-                    case 1: a1 = b0; a2 = b1; a3 = b2; a0 = b3; break;
-                    case 2: a2 = b0; a3 = b1; a0 = b2; a1 = b3; break;
-                    default: a3 = b0; a0 = b1; a1 = b2; a2 = b3; break;
-                }
+                const float rs = (a0 + a1) + (a2 + a3);
+                if (SP > 1) rows[r][o] = rs;
+                else acc += rs;
             }
-            const float rs = (a0 + a1) + (a2 + a3);
-            if (SP > 1) rows[r][o] = rs;
-            else acc += rs;
+        }
+        if (SP > 1) {
+            __syncthreads();
+            if (part == 0 && valid)
+                for (int r = 0; r < MM; ++r) acc += rows[r][o];
+        }
+        if (part == 0 && valid) {
+            const long long gp = im.pix_off + (long long)y * im.W + xx;
+            float ov;
+            if (mode == SYNTH_RESIDUAL) {
+                ov = x[gp] - acc;
+                if (W && !W[gp]) ov = 0.f;
+            } else if (mode == SYNTH_WEIGHTED) {
+                ov = (W && !W[gp]) ? 0.f : acc;
+            } else {
+                ov = acc;
+            }
+            out[gp] = ov;
         }
     }
-    if (SP > 1) {
-        __syncthreads();
-        if (part != 0) return;
-        if (valid)
-            for (int r = 0; r < MM; ++r) acc += rows[r][o];
-    }
-    if (!valid) return;
-    const long long gp = im.pix_off + (long long)y * im.W + xx;
-    float ov;
-    if (mode == SYNTH_RESIDUAL) {
-        ov = x[gp] - acc;
-        if (W && !W[gp]) ov = 0.f;
-    } else if (mode == SYNTH_WEIGHTED) {
-        ov = (W && !W[gp]) ? 0.f : acc;
-    } else {
-        ov = acc;
-    }
-    out[gp] = ov;
 }
 
 constexpr int ADJ_CAP = 2048;
@@ -411,14 +421,14 @@ __device__ __forceinline__ float dot_window(const float4 *dr, const float (&win)
 }
 
 template <int MM>
-__global__ __launch_bounds__(TPB) void k_adjoint_shrink(const ImgInfo *imgs, const TileInfo *tiles, int K,
-                                                        long long n_pix, const unsigned *__restrict__ mask_words,
+__global__ __launch_bounds__(TPB) void k_adjoint_shrink(const ImgInfo *imgs, const TileInfo *tiles, int n_tiles,
+                                                        int K, long long n_pix, const unsigned *__restrict__ mask_words,
                                                         const unsigned *__restrict__ soff,
                                                         const Pair *__restrict__ oldp,
                                                         const unsigned short *__restrict__ oldc,
                                                         Pair *__restrict__ newp, unsigned short *__restrict__ newc,
                                                         const float *__restrict__ r, const float *__restrict__ d,
-                                                        float eta, float thr, int KC,
+                                                        const float *__restrict__ ethr, int KC,
                                                         unsigned long long *__restrict__ nnz_acc) {
     constexpr int C = MM / 2, RW = TS + 2 * C, M = MM * MM, M4 = (M + 3) / 4 * 4;
     __shared__ float rr[RW * RW];
@@ -427,78 +437,90 @@ __global__ __launch_bounds__(TPB) void k_adjoint_shrink(const ImgInfo *imgs, con
     __shared__ int bsum;
     extern __shared__ float4 dl4[];
     float *dl = reinterpret_cast<float *>(dl4);
-
-    PixelCtx c = pixel_ctx(imgs, tiles);
-    const int oy = c.t.ty * TS - C, ox = c.t.tx * TS - C;
-    for (int i = threadIdx.x; i < RW * RW; i += TPB) {
-        const int gy = oy + i / RW, gx = ox + i % RW;
-        float v = 0.f;
-        if (gy >= 0 && gy < c.im.H && gx >= 0 && gx < c.im.W) v = r[c.im.pix_off + (long long)gy * c.im.W + gx];
-        rr[i] = v;
-    }
-    const unsigned base = c.valid ? soff[c.gp] : 0u;
-    const int ocnt = c.valid ? (int)oldc[c.gp] : 0;
-    int total;
-    const int ex = block_exclusive_scan(ocnt, scratch, &total);
-    const bool staged = total <= ADJ_CAP;
-    if (staged)
-        for (int j = 0; j < ocnt; ++j) op[ex + j] = oldp[base + j];
-    __syncthreads();
-    float win[M4];
-#pragma unroll
-    for (int j = 0; j < M4; ++j) {
-        if (j < M) {
-            const int sy = j / MM - C, sx = j % MM - C;
-            win[j] = rr[(c.ly + C + sy) * RW + (c.lx + C + sx)];
-        } else {
-            win[j] = 0.f;
-        }
-    }
-    int oi = 0;
-    Pair oe = ocnt > 0 ? (staged ? op[ex] : oldp[base]) : Pair{INT_MAX, 0.f};
-    int nn = 0;
-    for (int k0 = 0; k0 < K; k0 += KC) {
-        const int k1 = min(K, k0 + KC);
-        __syncthreads();
-        for (int i = threadIdx.x; i < (k1 - k0) * M4; i += TPB) {
+    const float eta = ethr[0], thr = ethr[1];
+    const bool one_chunk = K <= KC;
+    if (threadIdx.x == 0) bsum = 0;
+    if (one_chunk)
+        for (int i = threadIdx.x; i < K * M4; i += TPB) {
             const int kk = i / M4, j = i % M4;
-            dl[i] = j < M ? d[(long long)(k0 + kk) * M + j] : 0.f;
+            dl[i] = j < M ? d[(long long)kk * M + j] : 0.f;
         }
+    long long first, step, end;
+    xcd_work(n_tiles, first, step, end);
+    for (long long tile = first; tile < end; tile += step) {
+        PixelCtx c = pixel_ctx(imgs, tiles, (int)tile);
+        __syncthreads();  // LDS of the previous tile is no longer read
+        const int oy = c.t.ty * TS - C, ox = c.t.tx * TS - C;
+        for (int i = threadIdx.x; i < RW * RW; i += TPB) {
+            const int gy = oy + i / RW, gx = ox + i % RW;
+            float v = 0.f;
+            if (gy >= 0 && gy < c.im.H && gx >= 0 && gx < c.im.W) v = r[c.im.pix_off + (long long)gy * c.im.W + gx];
+            rr[i] = v;
+        }
+        const unsigned base = c.valid ? soff[c.gp] : 0u;
+        const int ocnt = c.valid ? (int)oldc[c.gp] : 0;
+        int total;
+        const int ex = block_exclusive_scan(ocnt, scratch, &total);
+        const bool staged = total <= ADJ_CAP;
+        if (staged)
+            for (int j = 0; j < ocnt; ++j) op[ex + j] = oldp[base + j];
         __syncthreads();
-        if (!c.valid) continue;
-        for (int w = k0 >> 5; w <= (k1 - 1) >> 5; ++w) {
-            unsigned bits = mask_words[(long long)w * n_pix + c.gp];
-            const int lo = k0 - 32 * w, hi = k1 - 32 * w;
-            if (lo > 0) bits &= ~0u << lo;
-            if (hi < 32) bits &= (1u << hi) - 1u;
-            while (bits) {
-                const int b = __builtin_ctz(bits);
-                bits &= bits - 1u;
-                const int k = 32 * w + b;
-                while (oe.k < k) {
-                    ++oi;
-                    oe = oi < ocnt ? (staged ? op[ex + oi] : oldp[base + oi]) : Pair{INT_MAX, 0.f};
+        float win[M4];
+#pragma unroll
+        for (int j = 0; j < M4; ++j) {
+            if (j < M) {
+                const int sy = j / MM - C, sx = j % MM - C;
+                win[j] = rr[(c.ly + C + sy) * RW + (c.lx + C + sx)];
+            } else {
+                win[j] = 0.f;
+            }
+        }
+        int oi = 0;
+        Pair oe = ocnt > 0 ? (staged ? op[ex] : oldp[base]) : Pair{INT_MAX, 0.f};
+        int nn = 0;
+        for (int k0 = 0; k0 < K; k0 += KC) {
+            const int k1 = min(K, k0 + KC);
+            if (!one_chunk) {
+                __syncthreads();
+                for (int i = threadIdx.x; i < (k1 - k0) * M4; i += TPB) {
+                    const int kk = i / M4, j = i % M4;
+                    dl[i] = j < M ? d[(long long)(k0 + kk) * M + j] : 0.f;
                 }
-                float zold = 0.f;
-                if (oe.k == k) {
-                    zold = oe.v;
-                    ++oi;
-                    oe = oi < ocnt ? (staged ? op[ex + oi] : oldp[base + oi]) : Pair{INT_MAX, 0.f};
-                }
-                __builtin_amdgcn_sched_barrier(0);
-                const float g = dot_window<M4>(dl4 + (k - k0) * (M4 / 4), win);
-                const float v = soft_threshold(fmaf(eta, g, zold), thr);
-                if (v != 0.f) {
-                    newp[base + nn] = Pair{k, v};
-                    ++nn;
+                __syncthreads();
+            }
+            if (!c.valid) continue;
+            for (int w = k0 >> 5; w <= (k1 - 1) >> 5; ++w) {
+                unsigned bits = mask_words[(long long)w * n_pix + c.gp];
+                const int lo = k0 - 32 * w, hi = k1 - 32 * w;
+                if (lo > 0) bits &= ~0u << lo;
+                if (hi < 32) bits &= (1u << hi) - 1u;
+                while (bits) {
+                    const int b = __builtin_ctz(bits);
+                    bits &= bits - 1u;
+                    const int k = 32 * w + b;
+                    while (oe.k < k) {
+                        ++oi;
+                        oe = oi < ocnt ? (staged ? op[ex + oi] : oldp[base + oi]) : Pair{INT_MAX, 0.f};
+                    }
+                    float zold = 0.f;
+                    if (oe.k == k) {
+                        zold = oe.v;
+                        ++oi;
+                        oe = oi < ocnt ? (staged ? op[ex + oi] : oldp[base + oi]) : Pair{INT_MAX, 0.f};
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                    const float g = dot_window<M4>(dl4 + (k - k0) * (M4 / 4), win);
+                    const float v = soft_threshold(fmaf(eta, g, zold), thr);
+                    if (v != 0.f) {
+                        newp[base + nn] = Pair{k, v};
+                        ++nn;
+                    }
                 }
             }
         }
+        if (c.valid) newc[c.gp] = (unsigned short)nn;
+        if (nn) atomicAdd(&bsum, nn);
     }
-    if (c.valid) newc[c.gp] = (unsigned short)nn;
-    if (threadIdx.x == 0) bsum = 0;
-    __syncthreads();
-    if (nn) atomicAdd(&bsum, nn);
     __syncthreads();
     if (threadIdx.x == 0 && nnz_acc && bsum) atomicAdd(nnz_acc, (unsigned long long)bsum);
 }
@@ -531,7 +553,7 @@ __global__ __launch_bounds__(TPB) void k_adjoint_shrink_mfma(const ImgInfo *imgs
                                                              Pair *__restrict__ newp,
                                                              unsigned short *__restrict__ newc,
                                                              const float *__restrict__ r, const float *__restrict__ d,
-                                                             float eta, float thr,
+                                                             const float *__restrict__ ethr,
                                                              unsigned long long *__restrict__ nnz_acc) {
     constexpr int C = MM / 2, RW = TS + 2 * C, M = MM * MM, NKS = (M + 31) / 32, MP = 32 * NKS;
     __shared__ __bf16 rb[RW * RW];
@@ -541,6 +563,7 @@ __global__ __launch_bounds__(TPB) void k_adjoint_shrink_mfma(const ImgInfo *imgs
     __shared__ int scratch[TPB];
     __shared__ int bsum;
 
+    const float eta = ethr[0], thr = ethr[1];
     PixelCtx c = pixel_ctx(imgs, tiles);
     const int oy = c.t.ty * TS - C, ox = c.t.tx * TS - C;
     for (int i = threadIdx.x; i < RW * RW; i += TPB) {
@@ -763,17 +786,22 @@ hipError_t launch_sum_counts(const unsigned short *cnt, long long n, unsigned lo
 }
 
 namespace {
+template <int MM, bool DLDS, int TY, int SP>
+hipError_t synth_launch(const Geometry &g, int K, Lists z, const float *d, const float *x, const unsigned char *W,
+                        float *out, SynthMode mode, hipStream_t s) {
+    const void *kfn = reinterpret_cast<const void *>(&k_synth<MM, DLDS, TS, TY, SP>);
+    const int block = TS * TY * SP;
+    const int grid = persistent_grid(kfn, block, 0, (long long)g.n_tiles * (TS / TY));
+    hipLaunchKernelGGL((k_synth<MM, DLDS, TS, TY, SP>), dim3(grid), dim3(block), 0, s, g.d_img, g.d_tiles, g.n_tiles,
+                       K, z, d, x, W, out, (int)mode);
+    return hipGetLastError();
+}
+
 template <int MM, int TY, int SP>
 hipError_t synth_sp(const Geometry &g, int K, Lists z, const float *d, const float *x, const unsigned char *W,
                     float *out, SynthMode mode, hipStream_t s) {
-    const dim3 grid(g.n_tiles * (TS / TY)), block(TS * TY * SP);
-    if (K * MM * MM <= SYN_DCAP)
-        hipLaunchKernelGGL((k_synth<MM, true, TS, TY, SP>), grid, block, 0, s, g.d_img, g.d_tiles, K, z, d, x, W,
-                           out, (int)mode);
-    else
-        hipLaunchKernelGGL((k_synth<MM, false, TS, TY, SP>), grid, block, 0, s, g.d_img, g.d_tiles, K, z, d, x, W,
-                           out, (int)mode);
-    return hipGetLastError();
+    if (K * MM * MM <= SYN_DCAP) return synth_launch<MM, true, TY, SP>(g, K, z, d, x, W, out, mode, s);
+    return synth_launch<MM, false, TY, SP>(g, K, z, d, x, W, out, mode, s);
 }
 
 template <int MM>
@@ -790,24 +818,25 @@ hipError_t synth_impl(const Geometry &g, int K, Lists z, const float *d, const f
 template <int MM>
 hipError_t adjoint_shrink_impl(const Geometry &g, int K, const unsigned *mw, const unsigned *soff,
                                const Pair *oldp, const unsigned short *oldc, Pair *newp, unsigned short *newc,
-                               const float *r, const float *d, float eta, float thr, unsigned long long *nnz_acc,
+                               const float *r, const float *d, const float *ethr, unsigned long long *nnz_acc,
                                hipStream_t s) {
     constexpr int M = MM * MM, M4 = (M + 3) / 4 * 4;
     const int KC = filter_chunk<MM>();
     const int kc = K < KC ? K : KC;
     const size_t shm = (size_t)kc * M4 * sizeof(float);
-    hipLaunchKernelGGL(k_adjoint_shrink<MM>, dim3(g.n_tiles), dim3(TPB), shm, s, g.d_img, g.d_tiles, K, g.n_pix,
-                       mw, soff, oldp, oldc, newp, newc, r, d, eta, thr, KC, nnz_acc);
+    const int grid = persistent_grid(reinterpret_cast<const void *>(&k_adjoint_shrink<MM>), TPB, shm, g.n_tiles);
+    hipLaunchKernelGGL(k_adjoint_shrink<MM>, dim3(grid), dim3(TPB), shm, s, g.d_img, g.d_tiles, g.n_tiles, K,
+                       g.n_pix, mw, soff, oldp, oldc, newp, newc, r, d, ethr, KC, nnz_acc);
     return hipGetLastError();
 }
 
 template <int MM>
 hipError_t adjoint_shrink_mfma_impl(const Geometry &g, int K, const unsigned *mw, const unsigned *soff,
                                     const Pair *oldp, const unsigned short *oldc, Pair *newp, unsigned short *newc,
-                                    const float *r, const float *d, float eta, float thr,
+                                    const float *r, const float *d, const float *ethr,
                                     unsigned long long *nnz_acc, hipStream_t s) {
     hipLaunchKernelGGL(k_adjoint_shrink_mfma<MM>, dim3(g.n_tiles), dim3(TPB), 0, s, g.d_img, g.d_tiles, K, g.n_pix,
-                       mw, soff, oldp, oldc, newp, newc, r, d, eta, thr, nnz_acc);
+                       mw, soff, oldp, oldc, newp, newc, r, d, ethr, nnz_acc);
     return hipGetLastError();
 }
 
@@ -832,22 +861,44 @@ hipError_t launch_synth(const Geometry &g, int K, int m, Lists z, const float *d
 hipError_t launch_adjoint_shrink(const Geometry &g, int K, int m, const unsigned *mask_words,
                                  const unsigned *soff, const Pair *old_pairs, const unsigned short *old_cnt,
                                  Pair *new_pairs, unsigned short *new_cnt, const float *r, const float *d,
-                                 float eta, float thr, unsigned long long *nnz_acc, hipStream_t s) {
+                                 const float *ethr, unsigned long long *nnz_acc, hipStream_t s) {
     SCSC_DISPATCH_M(m, adjoint_shrink_impl, g, K, mask_words, soff, old_pairs, old_cnt, new_pairs, new_cnt, r, d,
-                    eta, thr, nnz_acc, s);
+                    ethr, nnz_acc, s);
 }
 
 hipError_t launch_adjoint_shrink_mfma(const Geometry &g, int K, int m, const unsigned *mask_words,
                                       const unsigned *soff, const Pair *old_pairs, const unsigned short *old_cnt,
                                       Pair *new_pairs, unsigned short *new_cnt, const float *r, const float *d,
-                                      float eta, float thr, unsigned long long *nnz_acc, hipStream_t s) {
+                                      const float *ethr, unsigned long long *nnz_acc, hipStream_t s) {
     SCSC_DISPATCH_M(m, adjoint_shrink_mfma_impl, g, K, mask_words, soff, old_pairs, old_cnt, new_pairs, new_cnt, r,
-                    d, eta, thr, nnz_acc, s);
+                    d, ethr, nnz_acc, s);
 }
 
 hipError_t launch_adjoint_dense(const Geometry &g, int K, int m, const float *r, const float *d, float *out,
                                 hipStream_t s) {
     SCSC_DISPATCH_M(m, adjoint_dense_impl, g, K, r, d, out, s);
+}
+
+int persistent_grid(const void *kernel, int block_threads, size_t dyn_lds, long long items) {
+    static int n_cu = 0;
+    if (n_cu == 0) {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+            n_cu = v;
+        else
+            n_cu = 256;
+    }
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block_threads, dyn_lds) != hipSuccess ||
+        per_cu < 1) {
+        (void)hipGetLastError();
+        per_cu = 1;
+    }
+    long long g = (long long)per_cu * n_cu;
+    if (g > items) g = items;
+    if (g >= N_XCD) g -= g % N_XCD;
+    return (int)(g < 1 ? 1 : g);
 }
 
 }  // namespace scsc

@@ -220,6 +220,11 @@ __global__ void k_axpby(long long n, float a, const float *__restrict__ x, float
         out[i] = y ? a * x[i] + b * y[i] : a * x[i];
 }
 
+__global__ void k_set2(float *dst, float a, float b) {
+    if (threadIdx.x == 0) dst[0] = a;
+    if (threadIdx.x == 1) dst[1] = b;
+}
+
 unsigned ew_blocks(long long n) {
     long long b = (n + 255) / 256;
     return (unsigned)(b < 1 ? 1 : (b > 8192 ? 8192 : b));
@@ -235,6 +240,11 @@ hipError_t launch_ista_update(long long n, const float *z, const float *g, const
 hipError_t launch_ista_grad_u(long long n, const float *z, const float *g, const unsigned char *mask,
                               const float *gout, float eta, float thr, float *gu, hipStream_t s) {
     hipLaunchKernelGGL(k_ista_grad_u, dim3(ew_blocks(n)), dim3(256), 0, s, n, z, g, mask, gout, eta, thr, gu);
+    return hipGetLastError();
+}
+
+hipError_t launch_set2(float *dst, float a, float b, hipStream_t s) {
+    hipLaunchKernelGGL(k_set2, dim3(1), dim3(64), 0, s, dst, a, b);
     return hipGetLastError();
 }
 

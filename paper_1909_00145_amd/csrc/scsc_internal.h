@@ -122,6 +122,29 @@ __device__ __forceinline__ PixelCtx pixel_ctx(const ImgInfo *imgs, const TileInf
     return c;
 }
 
+// Work list of a persistent grid.  Hardware hands workgroup b to XCD b mod 8,
+// so the workgroups of one XCD take one contiguous eighth of the work items:
+// neighbouring tiles, which share halo data, are then served by the same L2.
+// Items first, first + step, ... below end belong to this workgroup.
+constexpr int N_XCD = 8;
+__device__ __forceinline__ void xcd_work(long long total, long long &first, long long &step, long long &end) {
+    const int G = gridDim.x;
+    if (G < N_XCD || G % N_XCD) {
+        first = blockIdx.x;
+        step = G;
+        end = total;
+        return;
+    }
+    const int x = blockIdx.x % N_XCD, slot = blockIdx.x / N_XCD;
+    first = total * x / N_XCD + slot;
+    step = G / N_XCD;
+    end = total * (x + 1) / N_XCD;
+}
+
+// Grid of a persistent kernel: resident workgroups on the whole device (a
+// multiple of 8 when possible), at most `items`.
+int persistent_grid(const void *kernel, int block_threads, size_t dyn_lds, long long items);
+
 // Matrix-core fragment types (v_mfma_f32_16x16x32_bf16 operands and result).
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
 typedef __attribute__((ext_vector_type(4))) float f32x4;
@@ -197,11 +220,11 @@ hipError_t launch_synth(const Geometry &g, int K, int m, Lists z, const float *d
 hipError_t launch_adjoint_shrink_mfma(const Geometry &g, int K, int m, const unsigned *mask_words,
                                       const unsigned *soff, const Pair *old_pairs, const unsigned short *old_cnt,
                                       Pair *new_pairs, unsigned short *new_cnt, const float *r, const float *d,
-                                      float eta, float thr, unsigned long long *nnz_acc, hipStream_t s);
+                                      const float *ethr, unsigned long long *nnz_acc, hipStream_t s);
 hipError_t launch_adjoint_shrink(const Geometry &g, int K, int m, const unsigned *mask_words,
                                  const unsigned *soff, const Pair *old_pairs, const unsigned short *old_cnt,
                                  Pair *new_pairs, unsigned short *new_cnt, const float *r, const float *d,
-                                 float eta, float thr, unsigned long long *nnz_acc, hipStream_t s);
+                                 const float *ethr, unsigned long long *nnz_acc, hipStream_t s);
 // Dense codes from lists (zeros elsewhere).
 hipError_t launch_scatter_dense(const Geometry &g, int K, Lists z, float *zout, hipStream_t s);
 // Lists of the non-zero codes of a dense z: count, then fill.
@@ -272,6 +295,8 @@ hipError_t launch_ista_update(long long n, const float *z, const float *g, const
 hipError_t launch_ista_grad_u(long long n, const float *z, const float *g, const unsigned char *mask,
                               const float *gout, float eta, float thr, float *gu, hipStream_t s);
 hipError_t launch_axpby(long long n, float a, const float *x, float b, const float *y, float *out, hipStream_t s);
+// dst[0] = a, dst[1] = b (device scalars written in stream order).
+hipError_t launch_set2(float *dst, float a, float b, hipStream_t s);
 
 // FP64 objective: out[0] = data term, out[1] = L1 norm.
 hipError_t launch_objective(const Geometry &g, int K, int m, const float *x, const unsigned char *W,

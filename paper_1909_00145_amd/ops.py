@@ -164,6 +164,10 @@ class Context:
         except Exception:
             pass
 
+    def set_graph(self, enable: bool):
+        """Replay the code step's proximal-gradient iterations from a captured HIP graph."""
+        self._check(self.lib.csc_set_graph(self.h, 1 if enable else 0))
+
     def set_autotune(self, enable, variant=None):
         """enable: tune launch variants on first use (default on); variant: force one variant."""
         mode = -(int(variant) + 1) if variant is not None else (1 if enable else 0)
