@@ -32,6 +32,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_FP32_VECTOR = 157.3e12
+PEAK_FP64_VECTOR = 78.6e12
 PEAK_HBM = 8.0e12
 
 # HBM bytes per launch of each kernel class's main kernel on the online workload, from
@@ -67,6 +68,9 @@ WORKLOADS = {
     "batch": dict(N=10, H=100, W=100, K=100, m=11, p=0.1, lam=1.0, T=20, cfg=2,
                   name="batch SBCSC: 10 images 100x100 (1/f^2), K=100 filters 11x11, p=0.1, lambda=1, "
                        "20 ISTA iterations + 1 projected filter step"),
+    "ragged": dict(N=256, H=None, W=None, K=100, m=11, p=0.1, lam=0.5, T=30, cfg=4,
+                   name="ragged code step: 256 images with sides uniform in [64, 512] (1/f^2), K=100 filters "
+                        "11x11, p=0.1, lambda=0.5, 30 ISTA iterations in one batch"),
 }
 
 
@@ -80,14 +84,18 @@ def parse():
     ap.add_argument("--p", type=float, default=None, help="override the sampling rate")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--graph", action="store_true", help="replay the code step's iterations from a HIP graph")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="after the timed steps, copy a buffer of this many MiB 3 times (a traffic-counter "
                          "calibration kernel of known size; outside the timed region)")
     return ap.parse_args()
 
 
-def cpu_baseline(w, budget_s):
-    """Time the FP64 oracle's code step on a bounded sample of the same workload."""
+def cpu_baseline(w, budget_s, sizes):
+    """Time the FP64 oracle's code step on a bounded sample of the same workload.
+
+    sizes: (H, W) of the images of one step, in order; image n of the sample is
+    image n of the step."""
     import oracle
     import scsc_inputs as si
 
@@ -98,13 +106,14 @@ def cpu_baseline(w, budget_s):
     except Exception:  # pragma: no cover
         threads = 1
     d = si.filters(w["cfg"], w["K"], w["m"]).astype(np.float32).astype(np.float64)
-    Lz = oracle.lipschitz_code(d, max(w["H"], w["W"]))
+    Lz = oracle.lipschitz_code(d, int(max(max(hw) for hw in sizes)))
     t0 = time.perf_counter()
     updates = 0
     n = 0
-    while n < w["N"]:
-        x = si.field(w["cfg"], n, w["H"], w["W"]).astype(np.float32).astype(np.float64)
-        z, S = oracle.code_step(x, d, np.zeros((w["K"], w["H"], w["W"])), w["lam"], w["p"], 1, 1, w["T"],
+    while n < len(sizes):
+        H, W = int(sizes[n][0]), int(sizes[n][1])
+        x = si.field(w["cfg"], n, H, W).astype(np.float32).astype(np.float64)
+        z, S = oracle.code_step(x, d, np.zeros((w["K"], H, W)), w["lam"], w["p"], 1, 1, w["T"],
                                 step=1.0 / Lz, image_index=n)
         updates += int(S.sum()) * w["T"]
         n += 1
@@ -116,8 +125,8 @@ def cpu_baseline(w, budget_s):
         "unit": "updates/s",
         "cores": threads,
         "kind": "oracle",
-        "sample": "code step (%d ISTA iterations, p=%g) of %d of the %d images of the first batch, "
-                  "FP64 NumPy, %.1f s; filter step not included" % (w["T"], w["p"], n, w["N"], el),
+        "sample": "code step (%d ISTA iterations, p=%g) of %d of the %d images of one step, "
+                  "FP64 NumPy, %.1f s; filter step not included" % (w["T"], w["p"], n, len(sizes), el),
     }
 
 
@@ -140,7 +149,10 @@ def main():
     torch.cuda.set_device(0)
     ctx = Context(0)
     K, m = w["K"], w["m"]
-    im = Images.uniform(w["N"], w["H"], w["W"])
+    if args.workload == "ragged":
+        im = Images(si.ragged_sizes(w["cfg"], w["N"], 64, 512))
+    else:
+        im = Images.uniform(w["N"], w["H"], w["W"])
     d = torch.from_numpy(si.filters(w["cfg"], K, m).astype(np.float32)).cuda()
     total_steps = args.warmup + args.steps
     if args.workload == "online":
@@ -150,6 +162,17 @@ def main():
 
         def step(i):
             return learner.step(xs[i])
+    elif args.workload == "ragged":
+        x = torch.from_numpy(im.pack([si.field(w["cfg"], n, int(H), int(Wd)).astype(np.float32)
+                                      for n, (H, Wd) in enumerate(im.hw)])).cuda()
+        z = torch.zeros(K * im.n_pix, dtype=torch.float32, device="cuda")
+        if args.graph:
+            ctx.set_graph(True)
+
+        def step(i):
+            st = ctx.code_step(im, x, d, z, w["lam"], w["p"], w["cfg"], i + 1, w["T"], precision=args.precision,
+                               stats=True)
+            return st, None
     else:
         x = torch.from_numpy(si.batch(w["cfg"], w["N"], w["H"], w["W"]).astype(np.float32).reshape(-1)).cuda()
         learner = BatchLearner(ctx, im, x, d, w["lam"], w["p"], n_code_iter=w["T"], precision=args.precision)
@@ -203,21 +226,27 @@ def main():
     work = {
         # one dot product of M taps per selected coordinate, then u = z + eta g and the shrink
         "adjoint": ("alu", (2 * M + 3) * sampled * w["T"], PEAK_FP32_VECTOR),
-        # M multiply-adds per non-zero code entering a synthesis (code step + power iteration)
-        "synth": ("alu", 2 * M * (nnz_iter + n_power * nnz_dict), PEAK_FP32_VECTOR),
-        # M multiply-adds per non-zero code per correlation (power iteration + Z^T W x)
-        "corr": ("alu", 2 * M * (n_power + 1) * nnz_dict, PEAK_FP32_VECTOR),
+        # M multiply-adds per non-zero code entering a synthesis
+        "synth": ("alu", 2 * M * nnz_iter, PEAK_FP32_VECTOR),
+        # M multiply-adds per non-zero code of one correlation (B_bar = Z^T x)
+        "corr": ("alu", 2 * M * nnz_dict, PEAK_FP32_VECTOR),
+        # K^2 M^2 FP64 multiply-adds per product with the lag-sum normal matrix (20 per step)
+        "power": ("alu64", 2.0 * K * K * M * M * n_power * args.steps, PEAK_FP64_VECTOR),
         # one pass over the blocks (k, k2 >= k) of the FP64 lag-layout matrix (the rest is their transpose)
         "sur_mv": ("hbm", 8.0 * (K * (K + 1) // 2) * M * M * args.steps, PEAK_HBM),
         # read-modify-write of C_bar plus the lag and band sums read for both halves
         "sur_expand": ("hbm", (16.0 * (K * M) ** 2 + 8.0 * K * K * L2 * (1 + 4 * c)) * args.steps, PEAK_HBM),
     }
-    if args.workload != "online":
-        # batch filter step: power iteration, then one residual synthesis and one correlation
+    # a replayed graph runs the synthesis and adjoint launches of all iterations together
+    work["ista_graph"] = ("alu", work["adjoint"][1] + work["synth"][1], PEAK_FP32_VECTOR)
+    if args.workload == "ragged":
+        # code steps only
+        work = {k: work[k] for k in ("adjoint", "synth", "ista_graph")}
+    elif args.workload != "online":
+        # batch filter step: one residual synthesis and one gradient correlation; lag-sum power iteration
         work.pop("sur_mv")
         work.pop("sur_expand")
-        work["synth"] = ("alu", 2 * M * (nnz_iter + (n_power + 1) * nnz_dict), PEAK_FP32_VECTOR)
-        work["corr"] = ("alu", 2 * M * (n_power + 1) * nnz_dict, PEAK_FP32_VECTOR)
+        work["synth"] = ("alu", 2 * M * (nnz_iter + nnz_dict), PEAK_FP32_VECTOR)
     dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
     modelled = [k for k in kernels if k in work]
     pick = dom if dom in work else max(modelled, key=lambda k: kernels[k]["total_ms"])
@@ -228,6 +257,8 @@ def main():
         roof = {"bound": "hbm", "achieved": per_launch / avg_s / 1e9, "peak": peak / 1e9, "unit": "GB/s"}
     else:
         roof = {"bound": "alu", "achieved": per_launch / avg_s / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s"}
+        if bound == "alu64":
+            roof["precision"] = "fp64"
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["traffic"] = traffic_for(pick, args.workload)
     roof["kernel"] = pick
@@ -255,6 +286,7 @@ def main():
         "dtype": args.precision,
         "data": "synthetic",
         "config": {"workload": w["name"], "images_per_step": w["N"], "height": w["H"], "width": w["W"],
+                   "pixels_per_step": im.n_pix, "graph": bool(args.graph),
                    "K": K, "filter": m, "p": w["p"], "lambda": w["lam"], "ista_iters": w["T"],
                    "precision": args.precision},
         "roofline": roof,
@@ -263,7 +295,7 @@ def main():
         "code_density": nnz_dict / (args.steps * K * im.n_pix),
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds, [tuple(hw) for hw in im.hw])
     print(json.dumps(out), flush=True)
     return 0
 
