@@ -243,7 +243,7 @@ constexpr int SYN_DCAP = 12288;  // filters staged in LDS when K m^2 <= 12288 fl
 
 // A staged code of the synthesis region: filter, region column, value.
 struct __align__(8) SynPair {
-    unsigned short k, col;
+    int doff;  // k * m^2 - (region column): the code's offset into the filters for tap column 0
     float v;
 };
 
@@ -312,17 +312,35 @@ __global__ __launch_bounds__(TT *TY *SP) void k_synth(const ImgInfo *imgs, const
         int total;
         int ex = block_exclusive_scan_n<NT>(mysum, scratch, &total);
         const bool staged = total <= CAP;
+        // staging: the first SB codes of every region pixel of this thread are loaded
+        // together (independent loads in flight), longer lists finish in a loop
+        constexpr int SB = 6;
+        Pair pre[CH][SB];
+#pragma unroll
+        for (int j = 0; j < CH; ++j) {
+            const int i = threadIdx.x * CH + j;
+            const int n = i < R && staged ? (int)lcnt[i] : 0;
+            const Pair *src = zl.pairs + (i < R ? lgoff[i] : 0u);
+#pragma unroll
+            for (int q = 0; q < SB; ++q)
+                if (q < n) pre[j][q] = src[q];
+        }
 #pragma unroll
         for (int j = 0; j < CH; ++j) {
             const int i = threadIdx.x * CH + j;
             if (i < R) {
                 lstart[i] = ex;
                 const int n = lcnt[i];
-                if (staged)
-                    for (int q = 0; q < n; ++q) {
+                if (staged) {
+                    const int col = i % RW;
+#pragma unroll
+                    for (int q = 0; q < SB; ++q)
+                        if (q < n) lp[ex + q] = SynPair{pre[j][q].k * M - col, pre[j][q].v};
+                    for (int q = SB; q < n; ++q) {
                         const Pair e = zl.pairs[lgoff[i] + q];
-                        lp[ex + q] = SynPair{(unsigned short)e.k, (unsigned short)(i % RW), e.v};
+                        lp[ex + q] = SynPair{e.k * M - col, e.v};
                     }
+                }
                 ex += n;
             }
         }
@@ -339,17 +357,33 @@ __global__ __launch_bounds__(TT *TY *SP) void k_synth(const ImgInfo *imgs, const
                     const int j0 = lstart[rb], j1 = lstart[rb + 2 * C + 1];
                     const float *drow = dd + r * MM + 2 * C + lx;  // tap column = 2c - (col - lx)
                     int j = j0;
-                    for (; j + 3 < j1; j += 4) {
+                    // eight elements per step, element j - j0 into accumulator (j - j0) mod 4
+                    for (; j + 7 < j1; j += 8) {
                         const SynPair e0 = lp[j], e1 = lp[j + 1], e2 = lp[j + 2], e3 = lp[j + 3];
-                        a0 = fmaf(drow[e0.k * M - e0.col], e0.v, a0);
-                        a1 = fmaf(drow[e1.k * M - e1.col], e1.v, a1);
-                        a2 = fmaf(drow[e2.k * M - e2.col], e2.v, a2);
-                        a3 = fmaf(drow[e3.k * M - e3.col], e3.v, a3);
+                        const SynPair e4 = lp[j + 4], e5 = lp[j + 5], e6 = lp[j + 6], e7 = lp[j + 7];
+                        const float f0 = drow[e0.doff], f1 = drow[e1.doff], f2 = drow[e2.doff], f3 = drow[e3.doff];
+                        const float f4 = drow[e4.doff], f5 = drow[e5.doff], f6 = drow[e6.doff], f7 = drow[e7.doff];
+                        a0 = fmaf(f0, e0.v, a0);
+                        a1 = fmaf(f1, e1.v, a1);
+                        a2 = fmaf(f2, e2.v, a2);
+                        a3 = fmaf(f3, e3.v, a3);
+                        a0 = fmaf(f4, e4.v, a0);
+                        a1 = fmaf(f5, e5.v, a1);
+                        a2 = fmaf(f6, e6.v, a2);
+                        a3 = fmaf(f7, e7.v, a3);
+                    }
+                    if (j + 3 < j1) {
+                        const SynPair e0 = lp[j], e1 = lp[j + 1], e2 = lp[j + 2], e3 = lp[j + 3];
+                        a0 = fmaf(drow[e0.doff], e0.v, a0);
+                        a1 = fmaf(drow[e1.doff], e1.v, a1);
+                        a2 = fmaf(drow[e2.doff], e2.v, a2);
+                        a3 = fmaf(drow[e3.doff], e3.v, a3);
+                        j += 4;
                     }
                     // tail: element j - j0 goes to accumulator (j - j0) mod 4 as in the loop
-                    if (j < j1) a0 = fmaf(drow[lp[j].k * M - lp[j].col], lp[j].v, a0);
-                    if (j + 1 < j1) a1 = fmaf(drow[lp[j + 1].k * M - lp[j + 1].col], lp[j + 1].v, a1);
-                    if (j + 2 < j1) a2 = fmaf(drow[lp[j + 2].k * M - lp[j + 2].col], lp[j + 2].v, a2);
+                    if (j < j1) a0 = fmaf(drow[lp[j].doff], lp[j].v, a0);
+                    if (j + 1 < j1) a1 = fmaf(drow[lp[j + 1].doff], lp[j + 1].v, a1);
+                    if (j + 2 < j1) a2 = fmaf(drow[lp[j + 2].doff], lp[j + 2].v, a2);
                 } else {
                     // same elements in the same order; b0 always takes the next element and the
                     // four accumulators rotate, so element u lands in accumulator u mod 4
@@ -403,6 +437,18 @@ __global__ __launch_bounds__(TT *TY *SP) void k_synth(const ImgInfo *imgs, const
 }
 
 constexpr int ADJ_CAP = 2048;
+
+// Copy a short code list into LDS with its first eight loads issued together.
+__device__ __forceinline__ void stage_pairs(const Pair *__restrict__ src, int n, Pair *dst) {
+    Pair t[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+        if (q < n) t[q] = src[q];
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+        if (q < n) dst[q] = t[q];
+    for (int q = 8; q < n; ++q) dst[q] = src[q];
+}
 
 // Dot product of an LDS filter row (float4-aligned, zero padded) with the
 // register window.
@@ -462,8 +508,7 @@ __global__ __launch_bounds__(TPB) void k_adjoint_shrink(const ImgInfo *imgs, con
         int total;
         const int ex = block_exclusive_scan(ocnt, scratch, &total);
         const bool staged = total <= ADJ_CAP;
-        if (staged)
-            for (int j = 0; j < ocnt; ++j) op[ex + j] = oldp[base + j];
+        if (staged) stage_pairs(oldp + base, ocnt, op + ex);
         __syncthreads();
         float win[M4];
 #pragma unroll
@@ -577,8 +622,7 @@ __global__ __launch_bounds__(TPB) void k_adjoint_shrink_mfma(const ImgInfo *imgs
     int total;
     const int ex = block_exclusive_scan(ocnt, scratch, &total);
     const bool staged = total <= ADJ_CAP;
-    if (staged)
-        for (int j = 0; j < ocnt; ++j) op[ex + j] = oldp[base + j];
+    if (staged) stage_pairs(oldp + base, ocnt, op + ex);
     __syncthreads();
 
     // im2col fragments of this wave's four column tiles (pixel rows 4w..4w+3)
