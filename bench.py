@@ -85,6 +85,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph", action="store_true", help="replay the code step's iterations from a HIP graph")
+    ap.add_argument("--tto", action="store_true",
+                    help="also measure time-to-objective of online learning, FP32 against BF16 (adds ~1 min)")
+    ap.add_argument("--tto-batches", type=int, default=100, help="mini-batches of the time-to-objective run")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="after the timed steps, copy a buffer of this many MiB 3 times (a traffic-counter "
                          "calibration kernel of known size; outside the timed region)")
@@ -128,6 +131,56 @@ def cpu_baseline(w, budget_s, sizes):
         "sample": "code step (%d ISTA iterations, p=%g) of %d of the %d images of one step, "
                   "FP64 NumPy, %.1f s; filter step not included" % (w["T"], w["p"], n, len(sizes), el),
     }
+
+
+def time_to_objective(ctx, w, n_batches):
+    """Online learning over a stream of n_batches mini-batches in FP32 and in BF16.
+
+    After every mini-batch the held-out objective (eq. 1) is evaluated with the
+    clock stopped: 20 held-out images, codes fitted from zero at p = 1 with 50
+    FP32 iterations.  The target is FP32's final held-out objective F*; each
+    precision reports the training time until its held-out objective first
+    reaches F* (1 + 1e-3)."""
+    import torch
+
+    import scsc_inputs as si
+    from paper_1909_00145_amd.drivers import OnlineLearner
+    from paper_1909_00145_amd.ops import Images
+
+    K, m, N, H, W = w["K"], w["m"], w["N"], w["H"], w["W"]
+    im = Images.uniform(N, H, W)
+    xs = torch.from_numpy(np.stack([si.stream_batch(w["cfg"], t, N, H, W).astype(np.float32).reshape(-1)
+                                    for t in range(1, n_batches + 1)])).cuda()
+    held = torch.from_numpy(si.batch(33, 20, H, W).astype(np.float32).reshape(-1)).cuda()
+    him = Images.uniform(20, H, W)
+    curves = {}
+    for prec in ("fp32", "bf16"):
+        d = torch.from_numpy(si.filters(w["cfg"], K, m).astype(np.float32)).cuda()
+        learner = OnlineLearner(ctx, im, d, w["lam"], w["p"], n_code_iter=w["T"], precision=prec)
+        elapsed, curve = 0.0, []
+        for t in range(n_batches):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            learner.step(xs[t])
+            torch.cuda.synchronize()
+            elapsed += time.perf_counter() - t0
+            F, _, _ = learner.evaluate(him, held)
+            curve.append((elapsed, F))
+        curves[prec] = curve
+    target = curves["fp32"][-1][1]
+    out = {"target_F": target, "tolerance": 1e-3, "mini_batches": n_batches,
+           "eval": "held-out 20 images 100x100 (cfg 33), codes from zero at p=1, 50 FP32 iterations, lambda=%g"
+                   % w["lam"],
+           "criterion": "first mini-batch whose held-out objective is within 1e-3 (relative) of FP32's final one"}
+    ref = [F for _, F in curves["fp32"]]
+    for prec, curve in curves.items():
+        hit = next((i for i, (_, F) in enumerate(curve) if abs(F - target) <= 1e-3 * abs(target)), None)
+        out[prec] = {"seconds": curve[hit][0] if hit is not None else None,
+                     "mini_batches": hit + 1 if hit is not None else None,
+                     "final_F": curve[-1][1], "train_seconds": curve[-1][0],
+                     "max_rel_dev_from_fp32": max(abs(F - r) / abs(r) for (_, F), r in zip(curve, ref)),
+                     "F_every_10": [round(F, 3) for _, F in curve[9::10]]}
+    return out
 
 
 def main():
@@ -294,6 +347,8 @@ def main():
         "kernels": kernels,
         "code_density": nnz_dict / (args.steps * K * im.n_pix),
     }
+    if args.tto:
+        out["time_to_objective"] = time_to_objective(ctx, WORKLOADS["online"], args.tto_batches)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds, [tuple(hw) for hw in im.hw])
     print(json.dumps(out), flush=True)
