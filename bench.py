@@ -287,8 +287,8 @@ def main():
         "power": ("alu64", 2.0 * K * K * M * M * n_power * args.steps, PEAK_FP64_VECTOR),
         # one pass over the blocks (k, k2 >= k) of the FP64 lag-layout matrix (the rest is their transpose)
         "sur_mv": ("hbm", 8.0 * (K * (K + 1) // 2) * M * M * args.steps, PEAK_HBM),
-        # read-modify-write of C_bar plus the lag and band sums read for both halves
-        "sur_expand": ("hbm", (16.0 * (K * M) ** 2 + 8.0 * K * K * L2 * (1 + 4 * c)) * args.steps, PEAK_HBM),
+        # read-modify-write of the stored blocks (k <= k2) of C_bar plus their lag and band sums
+        "sur_expand": ("hbm", (K * (K + 1) // 2) * (16.0 * M * M + 8.0 * L2 * (1 + 4 * c)) * args.steps, PEAK_HBM),
     }
     # a replayed graph runs the synthesis and adjoint launches of all iterations together
     work["ista_graph"] = ("alu", work["adjoint"][1] + work["synth"][1], PEAK_FP32_VECTOR)

@@ -85,9 +85,12 @@ typedef struct {
 /* Online surrogates of eq. (8), kept as unscaled sums:
  *   C_bar = sum_t sum_{i in batch t} Z_i^T W_i Z_i,  B_bar = sum_t sum_i Z_i^T W_i x_i,
  * so that C^t = C_bar / t and B^t = B_bar / t equal the recursion of eq. (8).
- * C is stored in the lag layout (csc_surrogate_index gives the position of any
- * dense entry); B is [K][m][m].  t and Ld_sum live on the host and are updated
- * by csc_dict_step.  Start from C = 0, B = 0, t = 0, Ld_sum = 0. */
+ * C_bar is symmetric: only its K (K + 1) / 2 blocks (k, k2 >= k) of m^2 x m^2
+ * entries are stored, in row-major order of the upper triangle, each in the lag
+ * layout (csc_surrogate_index gives the position of any dense entry; entry
+ * (k, s; k2, s2) with k > k2 is the stored entry (k2, s2; k, s)).  B is
+ * [K][m][m].  t and Ld_sum live on the host and are updated by csc_dict_step.
+ * Start from C = 0, B = 0, t = 0, Ld_sum = 0. */
 typedef struct {
     double *C;     /* device, csc_surrogate_size(K, m) doubles                       */
     double *B;     /* device, K*m*m doubles                                          */
@@ -184,13 +187,14 @@ int csc_mask(csc_handle h, const csc_images *im, int K, double p, uint64_t seed,
  * smallest power of two >= max_side + m - 1.  FP64.  L_out is host.  Synchronises. */
 int csc_lipschitz_code(csc_handle h, const float *d, int K, int m, int max_side, double *L_out);
 
-/* Number of doubles of the lag-layout surrogate C for K filters of side m (= (K m^2)^2). */
+/* Number of doubles of the stored surrogate C for K filters of side m (= K (K + 1) / 2 m^4). */
 int64_t csc_surrogate_size(int K, int m);
-/* Position in the lag layout of the dense entry C[(k, s), (k2, s2)], where s = (sy, sx)
- * and s2 = (sy2, sx2) are tap offsets in [-c, c].  Layout: blocks (k, k2) row-major, each
- * of m^4 doubles; inside a block, lags delta = s - s2 in [-(m-1), m-1]^2 row-major, each
- * holding the (m-|delta_y|) x (m-|delta_x|) valid s, row-major.  Returns -1 when an
- * argument is out of range.  Host only. */
+/* Position of the dense entry C[(k, s), (k2, s2)], where s = (sy, sx) and s2 = (sy2, sx2)
+ * are tap offsets in [-c, c].  Layout: blocks (k, k2 >= k) in row-major order of the upper
+ * triangle, each of m^4 doubles; inside a block, lags delta = s - s2 in [-(m-1), m-1]^2
+ * row-major, each holding the (m-|delta_y|) x (m-|delta_x|) valid s, row-major.  For
+ * k > k2 the position of (k2, s2; k, s) is returned.  Returns -1 when an argument is out
+ * of range.  Host only. */
 int64_t csc_surrogate_index(int K, int m, int k, int sy, int sx, int k2, int sy2, int sx2);
 
 /* ---- per-kernel timing -------------------------------------------------------- */

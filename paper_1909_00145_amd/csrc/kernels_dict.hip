@@ -242,7 +242,7 @@ hipError_t launch_online_update(float *d, const double *y, const double *B, doub
 extern "C" int64_t csc_surrogate_size(int K, int m) {
     if (K < 1 || m < 1) return -1;
     const int64_t M = (int64_t)m * m;
-    return (int64_t)K * K * M * M;
+    return (int64_t)K * (K + 1) / 2 * M * M;
 }
 
 extern "C" int64_t csc_surrogate_index(int K, int m, int k, int sy, int sx, int k2, int sy2, int sx2) {
@@ -250,11 +250,22 @@ extern "C" int64_t csc_surrogate_index(int K, int m, int k, int sy, int sx, int 
     const int c = m / 2;
     if (k < 0 || k >= K || k2 < 0 || k2 >= K) return -1;
     if (sy < -c || sy > c || sx < -c || sx > c || sy2 < -c || sy2 > c || sx2 < -c || sx2 > c) return -1;
+    if (k > k2) {  // stored as the transposed entry of block (k2, k)
+        int t = k;
+        k = k2;
+        k2 = t;
+        t = sy;
+        sy = sy2;
+        sy2 = t;
+        t = sx;
+        sx = sx2;
+        sx2 = t;
+    }
     const int dy = sy - sy2, dx = sx - sx2;
     const int64_t M = (int64_t)m * m;
     const int wy = m - (dy < 0 ? -dy : dy), wx = m - (dx < 0 ? -dx : dx);
     const int sylo = dy - c > -c ? dy - c : -c;
     const int sxlo = dx - c > -c ? dx - c : -c;
     const int64_t off = (int64_t)scsc::lag_prefix(dy, m) * M + (int64_t)wy * scsc::lag_prefix(dx, m);
-    return ((int64_t)k * K + k2) * M * M + off + (int64_t)(sy - sylo) * wx + (sx - sxlo);
+    return scsc::tri_block(k, k2, K) * M * M + off + (int64_t)(sy - sylo) * wx + (sx - sxlo);
 }

@@ -239,22 +239,15 @@ __global__ __launch_bounds__(SB_THREADS) void k_sur_block(const ImgInfo *imgs, i
         }
     }
     __syncthreads();
-    // C_bar(k, k2) += R + (-E); C_bar(k2, k) gets the transpose, which in the
-    // lag layout is the same run under lag -delta.
-    double *blk = Cbar + ((long long)k * K + k2) * M2;
-    double *blkT = Cbar + ((long long)k2 * K + k) * M2;
+    // C_bar(k, k2) += R + (-E) (upper-triangle block storage)
+    double *blk = Cbar + tri_block(k, k2, K) * M2;
     const int slot = threadIdx.x / 128, t = threadIdx.x % 128;
     for (int di = slot; di < L * L; di += SB_THREADS / 128) {
         const int dy = di / L - (MM - 1), dx = di % L - (MM - 1);
         const int wy = MM - (dy < 0 ? -dy : dy), wx = MM - (dx < 0 ? -dx : dx);
         if (t >= wy * wx) continue;
         const int off = lagp(dy, MM) * M + wy * lagp(dx, MM);
-        const double val = Cb[off + t] + Rb[di];
-        blk[off + t] += val;
-        if (k2 != k) {
-            const int offT = lagp(-dy, MM) * M + wy * lagp(-dx, MM);
-            blkT[offT + t] += val;
-        }
+        blk[off + t] += Cb[off + t] + Rb[di];
     }
 }
 
@@ -515,10 +508,9 @@ __global__ void k_zero_f64(double *p, long long n) {
         p[i] = 0.0;
 }
 
-// C_bar(a, b) += R - E_top - E_bottom - E_left - E_right for every block (a, b).
-// The lag sums are kept for k <= k2 only; block (a, b) with b < a is the
-// transpose of (b, a), whose run at lag -delta holds the same values in the same
-// order.  Each workgroup reads and writes its own block with coalesced accesses.
+// C_bar(k, k2) += R - E_top - E_bottom - E_left - E_right for every stored block
+// k <= k2 (one workgroup per block, blockIdx.x = its upper-triangle index).
+// Each workgroup reads and writes its own block with coalesced accesses.
 constexpr int EX_THREADS = 256;
 constexpr int EX_BATCH = 8;
 
@@ -531,16 +523,18 @@ __global__ __launch_bounds__(EX_THREADS) void k_sur_expand(int K, const double *
     constexpr int NC = C > 0 ? C : 1;
     __shared__ double r[LL];
     __shared__ double es[4 * NC][LL];
-    const int a = blockIdx.y, b = blockIdx.x;
-    const bool tr = b < a;
-    const int k = tr ? b : a, k2 = tr ? a : b;
+    // decode the upper-triangle block index into (k, k2)
+    const long long bi = blockIdx.x;
+    int k = 0;
+    while (tri_block(k + 1, k + 1, K) <= bi) ++k;
+    const int k2 = k + (int)(bi - tri_block(k, k, K));
     for (int i = threadIdx.x; i < LL; i += EX_THREADS) r[i] = Rl[((long long)k * K + k2) * LL + i];
     for (int i = threadIdx.x; i < 4 * C * LL; i += EX_THREADS) {
         const int cls = i / LL, di = i % LL;
         es[cls][di] = Es[(((long long)cls * K + k) * K + k2) * LL + di];
     }
     __syncthreads();
-    double *blk = Cbar + ((long long)a * K + b) * M2;
+    double *blk = Cbar + bi * M2;
     for (int i0 = threadIdx.x; i0 < M2; i0 += EX_THREADS * EX_BATCH) {
         double val[EX_BATCH], old[EX_BATCH];
 #pragma unroll
@@ -549,9 +543,8 @@ __global__ __launch_bounds__(EX_THREADS) void k_sur_expand(int K, const double *
             val[u] = 0.0;
             if (i >= M2) continue;
             const int code = tab[i];
-            int di = code >> 7;
+            const int di = code >> 7;
             const int t = code & 127;
-            if (tr) di = LL - 1 - di;  // lag -delta of the stored (k, k2) block
             const int dy = di / L - (MM - 1), dx = di % L - (MM - 1);
             const int wx = MM - (dx < 0 ? -dx : dx);
             const int sy = max(-C, dy - C) + t / wx, sx = max(-C, dx - C) + t % wx;
@@ -615,11 +608,14 @@ __global__ __launch_bounds__(256) void k_sur_corner(const ImgInfo *imgs, int K, 
             const long long within = (long long)lagp(dy, MM) * M + wy * lagp(dx, MM) + (say - sylo) * wx + (sax - sxlo);
             const int ca = zl.cnt[cg[a]], cb = zl.cnt[cg[b]];
             const unsigned oa = zl.off[cg[a]], ob = zl.off[cg[b]];
+            // entry (k_a, s_a; k_b, s_b) is stored when k_a <= k_b; the mirror of an
+            // entry with k_a > k_b comes from the pair (b, a)
             for (int u = 0; u < ca; ++u) {
                 const Pair ea = zl.pairs[oa + u];
                 for (int w = 0; w < cb; ++w) {
                     const Pair eb = zl.pairs[ob + w];
-                    atomicAdd(Cbar + ((long long)ea.k * K + eb.k) * M2 + within, (double)ea.v * (double)eb.v);
+                    if (ea.k > eb.k) continue;
+                    atomicAdd(Cbar + tri_block(ea.k, eb.k, K) * M2 + within, (double)ea.v * (double)eb.v);
                 }
             }
         }
@@ -645,7 +641,7 @@ __global__ __launch_bounds__(MV_THREADS) void k_sur_matvec(int K, const double *
         db[i] = (double)d[(long long)k2 * M + i];
     }
     __syncthreads();
-    const double *blk = Cbar + ((long long)k * K + k2) * M2;
+    const double *blk = Cbar + tri_block(k, k2, K) * M2;
     const int t = threadIdx.x;
     const bool active = t < M;
     const int ty = active ? t / MM - C : 0, tx = active ? t % MM - C : 0;
@@ -788,7 +784,8 @@ hipError_t sur_expand_impl(int K, const double *Rl, const double *Es, unsigned s
     hipLaunchKernelGGL(k_lag_table<MM>, dim3((LL + 63) / 64), dim3(64), 0, s, tab);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_sur_expand<MM>, dim3(K, K), dim3(EX_THREADS), 0, s, K, Rl, Es, tab, C);
+    hipLaunchKernelGGL(k_sur_expand<MM>, dim3((unsigned)tri_block(K, K, K)), dim3(EX_THREADS), 0, s, K, Rl, Es, tab,
+                       C);
     return hipGetLastError();
 }
 

@@ -122,6 +122,12 @@ __device__ __forceinline__ PixelCtx pixel_ctx(const ImgInfo *imgs, const TileInf
     return c;
 }
 
+// Surrogate storage: only the blocks (k, k2) with k <= k2 are kept (C_bar is
+// symmetric), in row-major order of the upper triangle.
+__host__ __device__ __forceinline__ long long tri_block(int k, int k2, int K) {
+    return (long long)k * (2LL * K - k + 1) / 2 + (k2 - k);
+}
+
 // Work list of a persistent grid.  Hardware hands workgroup b to XCD b mod 8,
 // so the workgroups of one XCD take one contiguous eighth of the work items:
 // neighbouring tiles, which share halo data, are then served by the same L2.

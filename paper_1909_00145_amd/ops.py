@@ -76,8 +76,9 @@ class CodeStats:
 class Surrogate:
     """Online surrogates of eq. (8) as unscaled sums on the device (FP64).
 
-    ``C`` is in the library's lag layout (``csc_surrogate_index``); ``dense_C()``
-    reorders it for inspection (small K only)."""
+    ``C`` holds the upper blocks (k <= k2) of the symmetric matrix in the
+    library's lag layout (``csc_surrogate_index``); ``dense_C()`` expands it for
+    inspection (small K only)."""
 
     def __init__(self, K: int, m: int, device=None):
         self.K, self.m = K, m
@@ -103,7 +104,10 @@ class Surrogate:
 
 
 def lag_index_map(K: int, m: int) -> np.ndarray:
-    """[KM, KM] int64 positions of the dense surrogate entries in the lag layout."""
+    """[KM, KM] int64 positions of the dense surrogate entries in the stored layout.
+
+    Blocks (k, k2 >= k) are stored in row-major order of the upper triangle; an
+    entry of a lower block (k > k2) is the transposed entry of block (k2, k)."""
     c = m // 2
     M = m * m
     s = np.arange(M)
@@ -118,8 +122,12 @@ def lag_index_map(K: int, m: int) -> np.ndarray:
     sylo = np.maximum(-c, dy - c)
     sxlo = np.maximum(-c, dx - c)
     within = prefix(dy) * M + wy * prefix(dx) + (sy[:, None] - sylo) * wx + (sx[:, None] - sxlo)
-    blocks = (np.arange(K)[:, None] * K + np.arange(K)[None, :]) * M * M
-    full = blocks[:, None, :, None] + within[None, :, None, :]
+    k = np.arange(K)
+    lo = np.minimum(k[:, None], k[None, :])
+    hi = np.maximum(k[:, None], k[None, :])
+    tri = (lo * (2 * K - lo + 1) // 2 + (hi - lo)) * M * M  # [K, K]
+    upper = (k[:, None] <= k[None, :])[:, None, :, None]
+    full = tri[:, None, :, None] + np.where(upper, within[None, :, None, :], within.T[None, :, None, :])
     return full.reshape(K * M, K * M).astype(np.int64)
 
 

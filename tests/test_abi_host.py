@@ -41,15 +41,23 @@ def test_version(lib):
     assert lib.csc_version() == 100
 
 
-def test_surrogate_layout_is_a_permutation(lib):
+def test_surrogate_layout_covers_the_upper_blocks_once(lib):
+    """Blocks (k, k2 >= k) are stored; every stored position holds one entry of the
+    upper blocks, and for k != k2 entry (k, s; k2, s2) shares its position with
+    (k2, s2; k, s) (a diagonal block keeps all of its entries)."""
     from paper_1909_00145_amd.ops import lag_index_map
 
-    for K, m in [(1, 3), (2, 5), (3, 3)]:
-        assert lib.csc_surrogate_size(K, m) == (K * m * m) ** 2
-        idx = lag_index_map(K, m)
-        np.testing.assert_array_equal(np.sort(idx.ravel()), np.arange((K * m * m) ** 2))
-        c = m // 2
+    for K, m in [(1, 3), (2, 5), (3, 3), (4, 5)]:
         M = m * m
+        size = K * (K + 1) // 2 * M * M
+        assert lib.csc_surrogate_size(K, m) == size
+        idx = lag_index_map(K, m)
+        off = np.kron(1 - np.eye(K, dtype=np.int64), np.ones((M, M), dtype=np.int64)).astype(bool)
+        np.testing.assert_array_equal(idx[off], idx.T[off])
+        upper = np.concatenate([idx[k * M:(k + 1) * M, k2 * M:(k2 + 1) * M].ravel()
+                                for k in range(K) for k2 in range(k, K)])
+        np.testing.assert_array_equal(np.sort(upper), np.arange(size))
+        c = m // 2
         for i in range(0, K * M, 3):
             for j in range(0, K * M, 2):
                 k, s = divmod(i, M)
