@@ -367,6 +367,13 @@ __global__ __launch_bounds__(LO_THREADS) void k_lag_outer(const ImgInfo *imgs, i
     extern __shared__ double Rd[];  // [KC][K]
     const int di = band ? (int)blockIdx.x : (LL - 1) / 2 + (int)blockIdx.x;
     const int dy = di / L - 2 * C, dx = di % L - 2 * C;
+    if (band) {
+        // The expansion uses band row j of a side only where it lies inside the
+        // strip cut off by some tap offset of this lag: j < min(c, c -+ delta).
+        const int sd = (int)blockIdx.z / NC, jj = (int)blockIdx.z % NC;
+        const int dlt = sd == 0 ? -dy : sd == 1 ? dy : sd == 2 ? -dx : dx;
+        if (jj >= min(C, C + dlt)) return;  // this (lag, band row) is never read
+    }
     const int klo = blockIdx.y * KC, khi = min(K, klo + KC);
     for (int i = threadIdx.x; i < KC * K; i += LO_THREADS) Rd[i] = 0.0;
     __syncthreads();
@@ -518,11 +525,13 @@ template <int MM>
 __global__ __launch_bounds__(EX_THREADS) void k_sur_expand(int K, const double *__restrict__ Rl,
                                                            const double *__restrict__ Es,
                                                            const unsigned short *__restrict__ tab,
-                                                           double *__restrict__ Cbar) {
+                                                           double *__restrict__ Cbar, const float *__restrict__ d,
+                                                           double *__restrict__ part) {
     constexpr int C = MM / 2, M2 = MM * MM * MM * MM, L = 2 * MM - 1, LL = L * L;
     constexpr int NC = C > 0 ? C : 1;
     __shared__ double r[LL];
     __shared__ double es[4 * NC][LL];
+    __shared__ double ya[MM * MM], yb[MM * MM], dka[MM * MM], dkb[MM * MM];
     // decode the upper-triangle block index into (k, k2)
     const long long bi = blockIdx.x;
     int k = 0;
@@ -533,6 +542,14 @@ __global__ __launch_bounds__(EX_THREADS) void k_sur_expand(int K, const double *
         const int cls = i / LL, di = i % LL;
         es[cls][di] = Es[(((long long)cls * K + k) * K + k2) * LL + di];
     }
+    constexpr int M = MM * MM;
+    if (d)  // the product C_bar d of the updated block (first filter iteration), fused
+        for (int i = threadIdx.x; i < M; i += EX_THREADS) {
+            ya[i] = 0.0;
+            yb[i] = 0.0;
+            dka[i] = (double)d[(long long)k * M + i];
+            dkb[i] = (double)d[(long long)k2 * M + i];
+        }
     __syncthreads();
     double *blk = Cbar + bi * M2;
     for (int i0 = threadIdx.x; i0 < M2; i0 += EX_THREADS * EX_BATCH) {
@@ -563,7 +580,29 @@ __global__ __launch_bounds__(EX_THREADS) void k_sur_expand(int K, const double *
 #pragma unroll
         for (int u = 0; u < EX_BATCH; ++u) {
             const int i = i0 + u * EX_THREADS;
-            if (i < M2) blk[i] = old[u] + val[u];
+            if (i >= M2) continue;
+            const double nv = old[u] + val[u];
+            blk[i] = nv;
+            if (d) {
+                // entry (k, s; k2, s2 = s - delta): row k gets C d_k2, row k2 gets C^T d_k
+                const int code = tab[i];
+                const int di = code >> 7, t = code & 127;
+                const int dy = di / L - (MM - 1), dx = di % L - (MM - 1);
+                const int wx = MM - (dx < 0 ? -dx : dx);
+                const int sy = max(-C, dy - C) + t / wx, sx = max(-C, dx - C) + t % wx;
+                const int si = (sy + C) * MM + sx + C, s2i = (sy - dy + C) * MM + sx - dx + C;
+                atomicAdd(&ya[si], nv * dkb[s2i]);
+                if (k != k2) atomicAdd(&yb[s2i], nv * dka[si]);
+            }
+        }
+    }
+    if (d) {
+        __syncthreads();
+        // part layout of the product: [k][k2][2][M]
+        double *pp = part + (((long long)k * K + k2) * 2) * M;
+        for (int i = threadIdx.x; i < M; i += EX_THREADS) {
+            pp[i] = ya[i];
+            pp[M + i] = yb[i];
         }
     }
 }
@@ -575,48 +614,43 @@ __global__ __launch_bounds__(EX_THREADS) void k_sur_expand(int K, const double *
 template <int MM>
 __global__ __launch_bounds__(256) void k_sur_corner(const ImgInfo *imgs, int K, Lists zl, double *__restrict__ Cbar) {
     constexpr int C = MM / 2, M = MM * MM, M2 = M * M;
-    __shared__ int cq[M];     // window pixels inside the image (tap index s = p - q)
+    __shared__ int cq[M];  // window pixels inside the image (tap index s = p - q)
     __shared__ long long cg[M];
     __shared__ int ncell;
     const ImgInfo im = imgs[blockIdx.x];
-    const int corner = blockIdx.y;
-    for (int ring = 0; ring < C * C; ++ring) {
-        const int i = ring / C + 1, j = ring % C + 1;
-        const int py = (corner & 1) ? im.H - 1 + i : -i;
-        const int px = (corner & 2) ? im.W - 1 + j : -j;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            int n = 0;
-            for (int t = 0; t < M; ++t) {
-                const int qy = py - (t / MM - C), qx = px - (t % MM - C);  // q = p - s
-                if (qy < 0 || qy >= im.H || qx < 0 || qx >= im.W) continue;
-                cq[n] = t;
-                cg[n] = im.pix_off + (long long)qy * im.W + qx;
-                ++n;
-            }
-            ncell = n;
-        }
-        __syncthreads();
-        const int n = ncell;
-        for (int pi = threadIdx.x; pi < n * n; pi += 256) {
-            const int a = pi / n, b = pi % n;
-            const int sa = cq[a], sb = cq[b];
-            const int say = sa / MM - C, sax = sa % MM - C, sby = sb / MM - C, sbx = sb % MM - C;
-            const int dy = say - sby, dx = sax - sbx;
-            const int wy = MM - (dy < 0 ? -dy : dy), wx = MM - (dx < 0 ? -dx : dx);
-            const int sylo = max(-C, dy - C), sxlo = max(-C, dx - C);
-            const long long within = (long long)lagp(dy, MM) * M + wy * lagp(dx, MM) + (say - sylo) * wx + (sax - sxlo);
-            const int ca = zl.cnt[cg[a]], cb = zl.cnt[cg[b]];
-            const unsigned oa = zl.off[cg[a]], ob = zl.off[cg[b]];
-            // entry (k_a, s_a; k_b, s_b) is stored when k_a <= k_b; the mirror of an
-            // entry with k_a > k_b comes from the pair (b, a)
-            for (int u = 0; u < ca; ++u) {
-                const Pair ea = zl.pairs[oa + u];
-                for (int w = 0; w < cb; ++w) {
-                    const Pair eb = zl.pairs[ob + w];
-                    if (ea.k > eb.k) continue;
-                    atomicAdd(Cbar + tri_block(ea.k, eb.k, K) * M2 + within, (double)ea.v * (double)eb.v);
-                }
+    const int corner = blockIdx.y, ring = blockIdx.z;
+    const int i = ring / C + 1, j = ring % C + 1;
+    const int py = (corner & 1) ? im.H - 1 + i : -i;
+    const int px = (corner & 2) ? im.W - 1 + j : -j;
+    if (threadIdx.x == 0) ncell = 0;
+    __syncthreads();
+    for (int t = threadIdx.x; t < M; t += 256) {
+        const int qy = py - (t / MM - C), qx = px - (t % MM - C);  // q = p - s
+        if (qy < 0 || qy >= im.H || qx < 0 || qx >= im.W) continue;
+        const int slot = atomicAdd(&ncell, 1);
+        cq[slot] = t;
+        cg[slot] = im.pix_off + (long long)qy * im.W + qx;
+    }
+    __syncthreads();
+    const int n = ncell;
+    for (int pi = threadIdx.x; pi < n * n; pi += 256) {
+        const int a = pi / n, b = pi % n;
+        const int sa = cq[a], sb = cq[b];
+        const int say = sa / MM - C, sax = sa % MM - C, sby = sb / MM - C, sbx = sb % MM - C;
+        const int dy = say - sby, dx = sax - sbx;
+        const int wy = MM - (dy < 0 ? -dy : dy), wx = MM - (dx < 0 ? -dx : dx);
+        const int sylo = max(-C, dy - C), sxlo = max(-C, dx - C);
+        const long long within = (long long)lagp(dy, MM) * M + wy * lagp(dx, MM) + (say - sylo) * wx + (sax - sxlo);
+        const int ca = zl.cnt[cg[a]], cb = zl.cnt[cg[b]];
+        const unsigned oa = zl.off[cg[a]], ob = zl.off[cg[b]];
+        // entry (k_a, s_a; k_b, s_b) is stored when k_a <= k_b; the mirror of an
+        // entry with k_a > k_b comes from the pair (b, a)
+        for (int u = 0; u < ca; ++u) {
+            const Pair ea = zl.pairs[oa + u];
+            for (int w = 0; w < cb; ++w) {
+                const Pair eb = zl.pairs[ob + w];
+                if (ea.k > eb.k) continue;
+                atomicAdd(Cbar + tri_block(ea.k, eb.k, K) * M2 + within, (double)ea.v * (double)eb.v);
             }
         }
     }
@@ -779,13 +813,18 @@ hipError_t sur_lag_impl(const Geometry &g, int K, Lists z, const unsigned *fm_of
 }
 
 template <int MM>
-hipError_t sur_expand_impl(int K, const double *Rl, const double *Es, unsigned short *tab, double *C, hipStream_t s) {
+hipError_t sur_expand_impl(int K, const double *Rl, const double *Es, unsigned short *tab, double *C, const float *d,
+                           double *part, double *y, hipStream_t s) {
     constexpr int L = 2 * MM - 1, LL = L * L;
     hipLaunchKernelGGL(k_lag_table<MM>, dim3((LL + 63) / 64), dim3(64), 0, s, tab);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_sur_expand<MM>, dim3((unsigned)tri_block(K, K, K)), dim3(EX_THREADS), 0, s, K, Rl, Es, tab,
-                       C);
+                       C, d, part);
+    if (d) {
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_sur_matvec_reduce, dim3(K), dim3(128), 0, s, K, MM * MM, part, y);
+    }
     return hipGetLastError();
 }
 
@@ -797,7 +836,9 @@ hipError_t lag_matvec_impl(int K, const double *Rl, const float *v, double *part
 
 template <int MM>
 hipError_t sur_corner_impl(const Geometry &g, int K, Lists z, double *C, hipStream_t s) {
-    hipLaunchKernelGGL(k_sur_corner<MM>, dim3(g.n_img, 4), dim3(256), 0, s, g.d_img, K, z, C);
+    constexpr int Cc = MM / 2;
+    if (Cc == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sur_corner<MM>, dim3(g.n_img, 4, Cc * Cc), dim3(256), 0, s, g.d_img, K, z, C);
     return hipGetLastError();
 }
 }  // namespace
@@ -818,8 +859,9 @@ hipError_t launch_surrogate_lag(const Geometry &g, int K, int m, Lists z, const 
 }
 
 hipError_t launch_surrogate_expand(int K, int m, const double *Rl, const double *Es, unsigned short *tab, double *C,
+                                   const float *d, double *part, double *y,
                                    hipStream_t s) {
-    SCSC_DISPATCH_M(m, sur_expand_impl, K, Rl, Es, tab, C, s);
+    SCSC_DISPATCH_M(m, sur_expand_impl, K, Rl, Es, tab, C, d, part, y, s);
 }
 
 hipError_t launch_surrogate_corner(const Geometry &g, int K, int m, Lists z, double *C, hipStream_t s) {

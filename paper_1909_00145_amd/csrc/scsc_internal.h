@@ -280,8 +280,11 @@ hipError_t launch_surrogate_lag(const Geometry &g, int K, int m, Lists z, const 
 // part[lag_matvec_chunks(K)][K][m*m] FP64 partial sums.
 int lag_matvec_chunks(int K);
 hipError_t launch_lag_matvec(int K, int m, const double *Rl, const float *v, double *part, hipStream_t s);
+// C_bar += R - band terms for the stored blocks; with d non-null also y = C_bar d of
+// the updated C_bar (part: surrogate_matvec_partial_elems doubles).  The corner
+// correction must already be in C_bar.
 hipError_t launch_surrogate_expand(int K, int m, const double *Rl, const double *Es, unsigned short *tab, double *C,
-                                   hipStream_t s);
+                                   const float *d, double *part, double *y, hipStream_t s);
 hipError_t launch_surrogate_corner(const Geometry &g, int K, int m, Lists z, double *C, hipStream_t s);
 hipError_t launch_surrogate_matvec(int K, int m, const double *C, const float *d, double *partial, double *y,
                                    hipStream_t s);
