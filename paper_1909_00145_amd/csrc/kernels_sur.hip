@@ -357,7 +357,8 @@ __global__ void k_lag_table(unsigned short *tab) {
 //     (k <= k2), added atomically when there is more than one chunk (Rl zeroed first).
 //   band == 1: blockIdx.z = side * c + j selects row (column) j of the top, bottom,
 //     left or right band of every image; every lag; stored into Es[cls][k][k2][lag].
-constexpr int LO_THREADS = 512;
+constexpr int LO_THREADS = 1024;
+constexpr int LO_U = 8;  // list entries per pixel held in registers
 
 template <int MM>
 __global__ __launch_bounds__(LO_THREADS) void k_lag_outer(const ImgInfo *imgs, int n_img, long long n_pix, int K,
@@ -421,7 +422,27 @@ __global__ __launch_bounds__(LO_THREADS) void k_lag_outer(const ImgInfo *imgs, i
             const int cb = zl.cnt[gp2];
             if (cb == 0) continue;
             const unsigned oa = zl.off[gp], ob = zl.off[gp2];
-            for (int u = 0; u < ca; ++u) {
+            // the first LO_U codes of both lists are loaded together into registers
+            Pair A[LO_U], B[LO_U];
+#pragma unroll
+            for (int u = 0; u < LO_U; ++u) {
+                if (u < ca) A[u] = zl.pairs[oa + u];
+                if (u < cb) B[u] = zl.pairs[ob + u];
+            }
+#pragma unroll
+            for (int u = 0; u < LO_U; ++u) {
+                if (u >= ca || A[u].k < klo || A[u].k >= khi) continue;
+                double *row = Rd + (long long)(A[u].k - klo) * K;
+                const double va = (double)A[u].v;
+#pragma unroll
+                for (int w = 0; w < LO_U; ++w)
+                    if (w < cb) atomicAdd(row + B[w].k, va * (double)B[w].v);
+                for (int w = LO_U; w < cb; ++w) {
+                    const Pair eb = zl.pairs[ob + w];
+                    atomicAdd(row + eb.k, va * (double)eb.v);
+                }
+            }
+            for (int u = LO_U; u < ca; ++u) {  // long lists
                 const Pair ea = zl.pairs[oa + u];
                 if (ea.k < klo || ea.k >= khi) continue;
                 double *row = Rd + (long long)(ea.k - klo) * K;
