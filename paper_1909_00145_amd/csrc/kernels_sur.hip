@@ -361,8 +361,9 @@ constexpr int LO_THREADS = 1024;
 constexpr int LO_U = 8;  // list entries per pixel held in registers
 
 template <int MM>
-__global__ __launch_bounds__(LO_THREADS) void k_lag_outer(const ImgInfo *imgs, int n_img, long long n_pix, int K,
-                                                          Lists zl, int band, int KC, double *__restrict__ out) {
+__global__ __launch_bounds__(LO_THREADS) void k_lag_outer(const ImgInfo *imgs, int n_img, long long n_pix,
+                                                          int max_side, int K, Lists zl, int band, int KC,
+                                                          double *__restrict__ out) {
     constexpr int C = MM / 2, L = 2 * MM - 1, LL = L * L;
     constexpr int NC = C > 0 ? C : 1;
     extern __shared__ double Rd[];  // [KC][K]
@@ -380,38 +381,45 @@ __global__ __launch_bounds__(LO_THREADS) void k_lag_outer(const ImgInfo *imgs, i
     __syncthreads();
     const int cls = band ? (int)blockIdx.z : -1;
     const int side = band ? cls / NC : -1, j = band ? cls % NC : 0;
-    // pixel chunk of the batch (band == 0)
+    // band == 0: a chunk of the packed pixels; band == 1: slot (image n, position)
+    // of a flat range over all images, so every image's band row is in flight at once
     const long long chunk = band ? 0 : (n_pix + gridDim.z - 1) / gridDim.z;
-    const long long plo = band ? 0 : chunk * blockIdx.z, phi = band ? 0 : min(n_pix, plo + chunk);
-    for (int n = 0; n < n_img; ++n) {
-        const ImgInfo im = imgs[n];
-        const long long isz = (long long)im.H * im.W;
-        long long tlo = 0, thi;
-        if (!band) {
-            tlo = max(0LL, plo - im.pix_off);
-            thi = min(isz, phi - im.pix_off);
-        } else if (side < 2) {
-            thi = (j < im.H) ? im.W : 0;
-        } else {
-            thi = (j < im.W) ? im.H : 0;
-        }
-        for (long long t = tlo + threadIdx.x; t < thi; t += LO_THREADS) {
+    const long long plo = band ? 0 : chunk * blockIdx.z, phi = band ? (long long)n_img * max_side : min(n_pix, plo + chunk);
+    int n = 0;
+    ImgInfo im = imgs[0];
+    long long iend = (long long)im.H * im.W;
+    {
+        for (long long t = plo + threadIdx.x; t < phi; t += LO_THREADS) {
             int y, x;
             if (!band) {
-                y = (int)(t / im.W);
-                x = (int)(t % im.W);
-            } else if (side == 0) {
-                y = j;
-                x = (int)t;
-            } else if (side == 1) {
-                y = im.H - 1 - j;
-                x = (int)t;
-            } else if (side == 2) {
-                y = (int)t;
-                x = j;
+                while (t >= iend) {  // advance to the image holding packed pixel t
+                    im = imgs[++n];
+                    iend = im.pix_off + (long long)im.H * im.W;
+                }
+                const long long pi = t - im.pix_off;
+                y = (int)(pi / im.W);
+                x = (int)(pi % im.W);
             } else {
-                y = (int)t;
-                x = im.W - 1 - j;
+                const int nn = (int)(t / max_side), pos = (int)(t % max_side);
+                if (nn != n || t == threadIdx.x) {
+                    n = nn;
+                    im = imgs[n];
+                }
+                const int len = side < 2 ? im.W : im.H, across = side < 2 ? im.H : im.W;
+                if (pos >= len || j >= across) continue;
+                if (side == 0) {
+                    y = j;
+                    x = pos;
+                } else if (side == 1) {
+                    y = im.H - 1 - j;
+                    x = pos;
+                } else if (side == 2) {
+                    y = pos;
+                    x = j;
+                } else {
+                    y = pos;
+                    x = im.W - 1 - j;
+                }
             }
             const int y2 = y + dy, x2 = x + dx;
             if (y2 < 0 || y2 >= im.H || x2 < 0 || x2 >= im.W) continue;
@@ -548,22 +556,28 @@ __global__ __launch_bounds__(EX_THREADS) void k_sur_expand(int K, const double *
                                                            const unsigned short *__restrict__ tab,
                                                            double *__restrict__ Cbar, const float *__restrict__ d,
                                                            double *__restrict__ part) {
-    constexpr int C = MM / 2, M2 = MM * MM * MM * MM, L = 2 * MM - 1, LL = L * L;
+    constexpr int C = MM / 2, M = MM * MM, M2 = M * M, L = 2 * MM - 1, LL = L * L;
     constexpr int NC = C > 0 ? C : 1;
     __shared__ double r[LL];
-    __shared__ double es[4 * NC][LL];
-    __shared__ double ya[MM * MM], yb[MM * MM], dka[MM * MM], dkb[MM * MM];
+    __shared__ double ec[4][NC][LL];  // band prefix sums: ec[side][a][delta] = sum_{j <= a} E_side,j(delta)
+    __shared__ double ya[M], yb[M], dka[M], dkb[M];
     // decode the upper-triangle block index into (k, k2)
     const long long bi = blockIdx.x;
     int k = 0;
     while (tri_block(k + 1, k + 1, K) <= bi) ++k;
     const int k2 = k + (int)(bi - tri_block(k, k, K));
     for (int i = threadIdx.x; i < LL; i += EX_THREADS) r[i] = Rl[((long long)k * K + k2) * LL + i];
-    for (int i = threadIdx.x; i < 4 * C * LL; i += EX_THREADS) {
-        const int cls = i / LL, di = i % LL;
-        es[cls][di] = Es[(((long long)cls * K + k) * K + k2) * LL + di];
+    for (int i = threadIdx.x; i < 4 * LL && C > 0; i += EX_THREADS) {
+        const int sd = i / LL, di = i % LL;
+        const int dy = di / L - 2 * C, dx = di % L - 2 * C;
+        const int dlt = sd == 0 ? -dy : sd == 1 ? dy : sd == 2 ? -dx : dx;
+        const int nj = min(C, C + dlt);  // band rows this lag reads (the rest were not formed)
+        double acc = 0.0;
+        for (int j = 0; j < nj; ++j) {
+            acc += Es[(((long long)(sd * C + j) * K + k) * K + k2) * LL + di];
+            ec[sd][j][di] = acc;
+        }
     }
-    constexpr int M = MM * MM;
     if (d)  // the product C_bar d of the updated block (first filter iteration), fused
         for (int i = threadIdx.x; i < M; i += EX_THREADS) {
             ya[i] = 0.0;
@@ -575,10 +589,12 @@ __global__ __launch_bounds__(EX_THREADS) void k_sur_expand(int K, const double *
     double *blk = Cbar + bi * M2;
     for (int i0 = threadIdx.x; i0 < M2; i0 += EX_THREADS * EX_BATCH) {
         double val[EX_BATCH], old[EX_BATCH];
+        int si[EX_BATCH], s2i[EX_BATCH];
 #pragma unroll
         for (int u = 0; u < EX_BATCH; ++u) {
             const int i = i0 + u * EX_THREADS;
             val[u] = 0.0;
+            si[u] = s2i[u] = 0;
             if (i >= M2) continue;
             const int code = tab[i];
             const int di = code >> 7;
@@ -586,12 +602,16 @@ __global__ __launch_bounds__(EX_THREADS) void k_sur_expand(int K, const double *
             const int dy = di / L - (MM - 1), dx = di % L - (MM - 1);
             const int wx = MM - (dx < 0 ? -dx : dx);
             const int sy = max(-C, dy - C) + t / wx, sx = max(-C, dx - C) + t % wx;
+            // R minus the codes whose partner window is cut by the image border:
+            // the first -s_y rows (top), last s_y rows (bottom), likewise columns
             double v = r[di];
-            for (int j = 0; j < -sy; ++j) v -= es[0 * NC + j][di];  // top rows a < -s_y
-            for (int j = 0; j < sy; ++j) v -= es[1 * NC + j][di];   // bottom rows
-            for (int j = 0; j < -sx; ++j) v -= es[2 * NC + j][di];  // left columns
-            for (int j = 0; j < sx; ++j) v -= es[3 * NC + j][di];   // right columns
+            if (sy < 0) v -= ec[0][-sy - 1][di];
+            if (sy > 0) v -= ec[1][sy - 1][di];
+            if (sx < 0) v -= ec[2][-sx - 1][di];
+            if (sx > 0) v -= ec[3][sx - 1][di];
             val[u] = v;
+            si[u] = (sy + C) * MM + sx + C;
+            s2i[u] = (sy - dy + C) * MM + sx - dx + C;
         }
 #pragma unroll
         for (int u = 0; u < EX_BATCH; ++u) {
@@ -606,14 +626,8 @@ __global__ __launch_bounds__(EX_THREADS) void k_sur_expand(int K, const double *
             blk[i] = nv;
             if (d) {
                 // entry (k, s; k2, s2 = s - delta): row k gets C d_k2, row k2 gets C^T d_k
-                const int code = tab[i];
-                const int di = code >> 7, t = code & 127;
-                const int dy = di / L - (MM - 1), dx = di % L - (MM - 1);
-                const int wx = MM - (dx < 0 ? -dx : dx);
-                const int sy = max(-C, dy - C) + t / wx, sx = max(-C, dx - C) + t % wx;
-                const int si = (sy + C) * MM + sx + C, s2i = (sy - dy + C) * MM + sx - dx + C;
-                atomicAdd(&ya[si], nv * dkb[s2i]);
-                if (k != k2) atomicAdd(&yb[s2i], nv * dka[si]);
+                atomicAdd(&ya[si[u]], nv * dkb[s2i[u]]);
+                if (k != k2) atomicAdd(&yb[s2i[u]], nv * dka[si[u]]);
             }
         }
     }
@@ -823,11 +837,11 @@ hipError_t sur_lag_impl(const Geometry &g, int K, Lists z, const unsigned *fm_of
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     hipLaunchKernelGGL(k_lag_outer<MM>, dim3(nlag, nkc, (unsigned)P), dim3(LO_THREADS), shm, s, g.d_img, g.n_img,
-                       (long long)g.n_pix, K, z, 0, KC, Rl);
+                       (long long)g.n_pix, g.max_side, K, z, 0, KC, Rl);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (Cc > 0 && Es) {
         hipLaunchKernelGGL(k_lag_outer<MM>, dim3(LL, nkc, 4 * Cc), dim3(LO_THREADS), shm, s, g.d_img, g.n_img,
-                           (long long)g.n_pix, K, z, 1, KC, Es);
+                           (long long)g.n_pix, g.max_side, K, z, 1, KC, Es);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     return hipSuccess;
