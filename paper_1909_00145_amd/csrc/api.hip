@@ -49,6 +49,7 @@ enum Slot {
     WS_XC,
     WS_WC,
     WS_DC,
+    WS_LAGF,
     WS_COUNT
 };
 
@@ -506,12 +507,15 @@ int power_iteration_lag(csc_ctx *h, int K, int m, const double *Rl, int n_power)
     WS(w, float, WS_W, K * M);
     WS(part, double, WS_PART, (size_t)nch * K * M);
     WS(sc, double, WS_SCAL, SC_COUNT);
+    const long long nl = surrogate_lag_elems(K, m);
+    WS(Rf, float, WS_LAGF, nl);
+    HIPCHK(launch_f64_to_f32(nl, Rl, Rf, h->stream));
     HIPCHK(launch_fill(v, K * M, (float)(1.0 / std::sqrt((double)K * M)), h->stream));
     HIPCHK(hipMemsetAsync(sc + SC_LAM, 0, sizeof(double), h->stream));
     for (int it = 0; it < n_power; ++it) {
         {
             PROF(CSC_PK_POWER);
-            HIPCHK(launch_lag_matvec(K, m, Rl, v, part, h->stream));
+            HIPCHK(launch_lag_matvec(K, m, Rf, v, part, h->stream));
             HIPCHK(launch_reduce_partials_f64_to_f32(part, nch, K * M, w, h->stream));
         }
         PROF(CSC_PK_UPDATE);

@@ -494,10 +494,10 @@ __global__ __launch_bounds__(LO_THREADS) void k_lag_outer(const ImgInfo *imgs, i
 constexpr int RM_KB = 16;
 
 template <int MM>
-__global__ __launch_bounds__(MM *RM_KB) void k_lag_matvec(int K, const double *__restrict__ Rl,
+__global__ __launch_bounds__(MM *RM_KB) void k_lag_matvec(int K, const float *__restrict__ Rl,
                                                           const float *__restrict__ v, double *__restrict__ part) {
     constexpr int C = MM / 2, M = MM * MM, L = 2 * MM - 1, LL = L * L, NT = MM * RM_KB;
-    __shared__ double r[RM_KB][LL];
+    __shared__ float r[RM_KB][LL];
     __shared__ double vv[RM_KB][M];
     const int k = blockIdx.x, ch = blockIdx.y;
     const int k2lo = ch * RM_KB, nk = min(RM_KB, K - k2lo);
@@ -514,11 +514,11 @@ __global__ __launch_bounds__(MM *RM_KB) void k_lag_matvec(int K, const double *_
     for (int sx = 0; sx < MM; ++sx) acc[sx] = 0.0;
     if (j < nk) {
         for (int s2y = 0; s2y < MM; ++s2y) {
-            const double *rrow = &r[j][(sy - s2y + 2 * C) * L];  // lags (dy, dx = sx - s2x + 2c)
+            const float *rrow = &r[j][(sy - s2y + 2 * C) * L];  // lags (dy, dx = sx - s2x + 2c)
             const double *vrow = &vv[j][s2y * MM];
             double rv[L], vx[MM];
 #pragma unroll
-            for (int i = 0; i < L; ++i) rv[i] = rrow[i];
+            for (int i = 0; i < L; ++i) rv[i] = (double)rrow[i];
 #pragma unroll
             for (int i = 0; i < MM; ++i) vx[i] = vrow[i];
 #pragma unroll
@@ -528,7 +528,7 @@ __global__ __launch_bounds__(MM *RM_KB) void k_lag_matvec(int K, const double *_
         }
     }
     __syncthreads();
-    double *red = &r[0][0];  // [RM_KB][M], reuses the lag rows
+    double *red = &vv[0][0];  // [RM_KB][M], reuses the filter rows
 #pragma unroll
     for (int sx = 0; sx < MM; ++sx) red[j * M + sy * MM + sx] = acc[sx];
     __syncthreads();
@@ -864,7 +864,7 @@ hipError_t sur_expand_impl(int K, const double *Rl, const double *Es, unsigned s
 }
 
 template <int MM>
-hipError_t lag_matvec_impl(int K, const double *Rl, const float *v, double *part, hipStream_t s) {
+hipError_t lag_matvec_impl(int K, const float *Rl, const float *v, double *part, hipStream_t s) {
     hipLaunchKernelGGL(k_lag_matvec<MM>, dim3(K, (K + RM_KB - 1) / RM_KB), dim3(MM * RM_KB), 0, s, K, Rl, v, part);
     return hipGetLastError();
 }
@@ -905,7 +905,19 @@ hipError_t launch_surrogate_corner(const Geometry &g, int K, int m, Lists z, dou
 
 int lag_matvec_chunks(int K) { return (K + RM_KB - 1) / RM_KB; }
 
-hipError_t launch_lag_matvec(int K, int m, const double *Rl, const float *v, double *part, hipStream_t s) {
+__global__ void k_f64_to_f32(long long n, const double *__restrict__ src, float *__restrict__ dst) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        dst[i] = (float)src[i];
+}
+
+hipError_t launch_f64_to_f32(long long n, const double *src, float *dst, hipStream_t s) {
+    long long b = (n + 255) / 256;
+    if (b > 8192) b = 8192;
+    hipLaunchKernelGGL(k_f64_to_f32, dim3((unsigned)(b < 1 ? 1 : b)), dim3(256), 0, s, n, src, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_lag_matvec(int K, int m, const float *Rl, const float *v, double *part, hipStream_t s) {
     SCSC_DISPATCH_M(m, lag_matvec_impl, K, Rl, v, part, s);
 }
 

@@ -279,7 +279,9 @@ hipError_t launch_surrogate_lag(const Geometry &g, int K, int m, Lists z, const 
 // Product of the zero-padded normal matrix (lag sums Rl) with v [K][m*m]:
 // part[lag_matvec_chunks(K)][K][m*m] FP64 partial sums.
 int lag_matvec_chunks(int K);
-hipError_t launch_lag_matvec(int K, int m, const double *Rl, const float *v, double *part, hipStream_t s);
+// Rl: the lag sums rounded to FP32 (a step-size estimate needs no more); FP64 accumulation.
+hipError_t launch_lag_matvec(int K, int m, const float *Rl, const float *v, double *part, hipStream_t s);
+hipError_t launch_f64_to_f32(long long n, const double *src, float *dst, hipStream_t s);
 // C_bar += R - band terms for the stored blocks; with d non-null also y = C_bar d of
 // the updated C_bar (part: surrogate_matvec_partial_elems doubles).  The corner
 // correction must already be in C_bar.
