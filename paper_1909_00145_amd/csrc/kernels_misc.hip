@@ -109,40 +109,50 @@ __global__ void k_dft_rows(const float *d, int K, int m, int P, double2 *F1) {
     F1[i] = make_double2(re, im);
 }
 
-// Column DFT and the power sum over filters at every frequency (v, u), with a
-// block maximum folded into *out through an integer max on the (non-negative)
-// FP64 bit pattern.
-__global__ __launch_bounds__(256) void k_dft_cols_max(const double2 *F1, int K, int m, int P,
-                                                      unsigned long long *out) {
+// Column DFT and the power sum over a chunk of DFT_KC filters at every
+// frequency (v, u): part[chunk][v P + u].
+constexpr int DFT_KC = 8;
+
+__global__ __launch_bounds__(256) void k_dft_cols(const double2 *F1, int K, int m, int P, double *part) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= (long long)P * P) return;
+    const int u = (int)(i % P), v = (int)(i / P);
+    double tc[2 * MAX_C + 1], ts[2 * MAX_C + 1];
+#pragma unroll
+    for (int a = 0; a < 2 * MAX_C + 1; ++a) {
+        tc[a] = 0.0;
+        ts[a] = 0.0;
+        if (a < m) {
+            const int ph = (int)(((long long)v * a) % P);
+            sincos(-2.0 * M_PI * (double)ph / (double)P, &ts[a], &tc[a]);
+        }
+    }
+    const int k0 = blockIdx.y * DFT_KC, k1 = min(K, k0 + DFT_KC);
+    double S = 0.0;
+    for (int k = k0; k < k1; ++k) {
+        double re = 0.0, im = 0.0;
+        const double2 *f1 = F1 + (long long)k * m * P + u;
+#pragma unroll
+        for (int a = 0; a < 2 * MAX_C + 1; ++a) {
+            if (a < m) {
+                const double2 f = f1[(long long)a * P];
+                re += f.x * tc[a] - f.y * ts[a];
+                im += f.x * ts[a] + f.y * tc[a];
+            }
+        }
+        S += re * re + im * im;
+    }
+    part[(long long)blockIdx.y * P * P + i] = S;
+}
+
+// Sum of the chunks in order at every frequency, block maximum folded into
+// *out through an integer max on the (non-negative) FP64 bit pattern.
+__global__ __launch_bounds__(256) void k_dft_max(const double *part, int nch, long long n, unsigned long long *out) {
     __shared__ double red[256];
     const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
     double S = 0.0;
-    if (i < (long long)P * P) {
-        const int u = (int)(i % P), v = (int)(i / P);
-        double tc[2 * MAX_C + 1], ts[2 * MAX_C + 1];
-#pragma unroll
-        for (int a = 0; a < 2 * MAX_C + 1; ++a) {
-            tc[a] = 0.0;
-            ts[a] = 0.0;
-            if (a < m) {
-                const int ph = (int)(((long long)v * a) % P);
-                sincos(-2.0 * M_PI * (double)ph / (double)P, &ts[a], &tc[a]);
-            }
-        }
-        for (int k = 0; k < K; ++k) {
-            double re = 0.0, im = 0.0;
-            const double2 *f1 = F1 + (long long)k * m * P + u;
-#pragma unroll
-            for (int a = 0; a < 2 * MAX_C + 1; ++a) {
-                if (a < m) {
-                    const double2 f = f1[(long long)a * P];
-                    re += f.x * tc[a] - f.y * ts[a];
-                    im += f.x * ts[a] + f.y * tc[a];
-                }
-            }
-            S += re * re + im * im;
-        }
-    }
+    if (i < n)
+        for (int c = 0; c < nch; ++c) S += part[(long long)c * n + i];
     red[threadIdx.x] = S;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
@@ -176,7 +186,9 @@ hipError_t launch_objective(const Geometry &g, int K, int m, const float *x, con
     }
 }
 
-long long lipschitz_tmp_elems(int K, int m, int P) { return 2LL * K * m * P + 1; }
+long long lipschitz_tmp_elems(int K, int m, int P) {
+    return 2LL * K * m * P + (long long)((K + DFT_KC - 1) / DFT_KC) * P * P + 1;
+}
 
 hipError_t launch_lipschitz_code(const float *d, int K, int m, int P, double *tmp, double *out, hipStream_t s) {
     double2 *F1 = reinterpret_cast<double2 *>(tmp);
@@ -187,7 +199,11 @@ hipError_t launch_lipschitz_code(const float *d, int K, int m, int P, double *tm
     e = hipMemsetAsync(out, 0, sizeof(double), s);
     if (e != hipSuccess) return e;
     const long long n2 = (long long)P * P;
-    hipLaunchKernelGGL(k_dft_cols_max, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, s, F1, K, m, P,
+    const int nch = (K + DFT_KC - 1) / DFT_KC;
+    double *part = tmp + 2LL * K * m * P;
+    hipLaunchKernelGGL(k_dft_cols, dim3((unsigned)((n2 + 255) / 256), nch), dim3(256), 0, s, F1, K, m, P, part);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_dft_max, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, s, part, nch, n2,
                        reinterpret_cast<unsigned long long *>(out));
     return hipGetLastError();
 }
