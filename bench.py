@@ -39,11 +39,11 @@ PEAK_HBM = 8.0e12
 # rocprofv3 FETCH_SIZE / WRITE_SIZE passes scaled by a 512 MiB copy (read x 2.000, write x 1.000),
 # valid only for the kernel source they were taken on (first 16 hex digits of its SHA-256).
 TRAFFIC = {
-    "synth": ("kernels_code.hip", "188f7209c24cf146", 31.69e6, 1.02e6),
-    "adjoint": ("kernels_code.hip", "188f7209c24cf146", 34.19e6, 11.20e6),
-    "corr": ("kernels_dict.hip", "98c4ceeed6c06dea", 27.00e6, 4.07e6),
-    "sur_mv": ("kernels_sur.hip", "e6370a4aa64d03a0", 597.03e6, 9.91e6),
-    "sur_expand": ("kernels_sur.hip", "e6370a4aa64d03a0", 1943.22e6, 1171.86e6),
+    "synth": ("kernels_code.hip", "fd3c0a6613139af6", 18.12e6, 0.81e6),
+    "adjoint": ("kernels_code.hip", "fd3c0a6613139af6", 20.94e6, 10.64e6),
+    "corr": ("kernels_dict.hip", "e012d4f63c9433b4", 26.99e6, 4.07e6),
+    "sur_expand": ("kernels_sur.hip", "b615432a09d95e95", 912.31e6, 601.56e6),
+    "power": ("kernels_sur.hip", "b615432a09d95e95", 17.64e6, 0.69e6),
 }
 
 
