@@ -61,8 +61,9 @@ typedef enum {
 
 typedef enum {
     CSC_FP32 = 0, /* FP32 operands and accumulation                                        */
-    CSC_BF16 = 1  /* adjoint / filter-gradient contractions with BF16 operands on MFMA and
-                     FP32 accumulation; codes, filters and residual stay FP32             */
+    CSC_BF16 = 1  /* synthesis, adjoint and filter-gradient contractions with BF16 operands
+                     on the matrix cores and FP32 accumulation; codes, filters and the
+                     residual stay FP32                                                    */
 } csc_precision;
 
 /* A batch of images (host struct). */
@@ -127,10 +128,11 @@ int csc_version(void);
  *   n_iter : proximal-gradient iterations, >= 0.
  *   step   : > 0 to force a step; <= 0 selects 1 / L_z with L_z from csc_lipschitz_code
  *            (max_side = the largest image side of the batch).
- *   precision : csc_precision.  CSC_BF16: the adjoint correlation of each 16 x 16 pixel tile
- *            is one GEMM on the matrix cores (filters x pixels x taps) with d and r rounded
- *            to BF16 and FP32 accumulation; the selected-set update, the residual and the
- *            codes stay FP32.
+ *   precision : csc_precision.  CSC_BF16: per 16 x 16 pixel tile the adjoint correlation
+ *            is one GEMM on the matrix cores (filters x pixels x taps) and the synthesis
+ *            one GEMM per tap row (taps x pixels x filters) followed by a shifted sum,
+ *            with d, r and z rounded to BF16 and FP32 accumulation; the selected-set
+ *            update, the residual and the codes stay FP32.
  *   stats  : host, may be NULL (filling it synchronises). */
 int csc_code_step(csc_handle h, const csc_images *im, const float *x, const uint8_t *W,
                   const float *d, int K, int m, float *z, double lambda, double p,

@@ -50,6 +50,7 @@ enum Slot {
     WS_WC,
     WS_DC,
     WS_LAGF,
+    WS_SDA,
     WS_COUNT
 };
 
@@ -172,7 +173,7 @@ struct ProfScope {
     } while (0)
 
 // Kernels with several launch variants that compute bit-identical results.
-enum TunedKernel { TK_SYNTH = 0 };
+enum TunedKernel { TK_SYNTH = 0, TK_SYNTH_BF16 = 1 };
 
 int ilog2(long long v) {
     int r = 0;
@@ -244,17 +245,42 @@ bool variant_settled(csc_ctx *h, const std::array<int, 5> &key) {
     return h->force_variant >= 0 || !h->autotune || h->tuned.count(key) > 0;
 }
 
-std::array<int, 5> synth_key(csc_ctx *h, int K, int m, SynthMode mode) {
-    return {TK_SYNTH, m, K, ilog2(h->geo.n_pix), (int)mode};
+// Variant chosen for `key` (-1 when not tuned yet); does not insert.
+int tuned_variant(csc_ctx *h, const std::array<int, 5> &key) {
+    auto it = h->tuned.find(key);
+    return it == h->tuned.end() ? -1 : it->second;
+}
+
+std::array<int, 5> synth_key(csc_ctx *h, int K, int m, SynthMode mode, int precision = CSC_FP32) {
+    return {precision == CSC_BF16 ? TK_SYNTH_BF16 : TK_SYNTH, m, K, ilog2(h->geo.n_pix), (int)mode};
 }
 
 // Synthesis / residual through the tuned launcher (tile shape and threads per
 // output pixel).  `representative` marks calls whose code density is typical of
 // the key (not the first iterations of a code step from zero codes); only those
 // may tune.
+void *ws(csc_ctx *h, Slot s, size_t bytes, int *status);
+
+// With BF16 the filters enter as the matrix-core operand: `dA` when the caller
+// prepared it (launch_synth_mfma_prep), else prepared here into WS_SDA.
 hipError_t synth(csc_ctx *h, int K, int m, Lists L, const float *d, const float *x, const unsigned char *W,
-                 float *out, SynthMode mode, bool representative = true) {
+                 float *out, SynthMode mode, bool representative = true, int precision = CSC_FP32,
+                 const __bf16 *dA = nullptr) {
     const Geometry &g = h->geo;
+    if (precision == CSC_BF16) {
+        if (!dA) {
+            int st = CSC_OK;
+            __bf16 *buf = static_cast<__bf16 *>(ws(h, WS_SDA, sizeof(__bf16) * synth_mfma_prep_elems(K), &st));
+            if (!buf) return hipErrorOutOfMemory;
+            const hipError_t e = launch_synth_mfma_prep(d, K, m, buf, h->stream);
+            if (e != hipSuccess) return e;
+            dA = buf;
+        }
+        return tuned_launch(
+            h, synth_key(h, K, m, mode, precision), 2,
+            [&](int v) { return launch_synth_mfma(g, K, m, L, dA, x, W, out, (int)mode, v, h->stream); },
+            representative);
+    }
     return tuned_launch(
         h, synth_key(h, K, m, mode), 4,
         [&](int v) { return launch_synth(g, K, m, L, d, x, W, out, mode, v, h->stream); }, representative);
@@ -488,7 +514,7 @@ int power_iteration(csc_ctx *h, int K, int m, Lists L, FmLists F, const unsigned
     for (int it = 0; it < n_power; ++it) {
         {
             PROF(CSC_PK_SYNTH);
-            HIPCHK(synth(h, K, m, L, v, nullptr, W, R, SYNTH_WEIGHTED));
+            HIPCHK(synth(h, K, m, L, v, nullptr, W, R, SYNTH_WEIGHTED, true, precision));
         }
         int st = precision == CSC_BF16 ? filter_corr_bf16(h, K, m, L, R, w) : filter_corr_lists(h, K, m, F, R, w);
         if (st) return st;
@@ -679,7 +705,8 @@ extern "C" int csc_code_step(csc_handle h, const csc_images *im, const float *x,
     // read from device scalars, so the same launches can be replayed as a graph.
     const float *xi = x, *di = d;
     const uint8_t *Wi = W;
-    const bool use_graph = h->graphs && n_iter > 0 && variant_settled(h, synth_key(h, K, m, SYNTH_RESIDUAL));
+    const bool use_graph = h->graphs && n_iter > 0 &&
+                           variant_settled(h, synth_key(h, K, m, SYNTH_RESIDUAL, precision));
     if (use_graph) {
         // stable copies of the inputs the graph reads
         WS(xc, float, WS_XC, g.n_pix);
@@ -694,12 +721,19 @@ extern "C" int csc_code_step(csc_handle h, const csc_images *im, const float *x,
             Wi = wc;
         }
     }
+    __bf16 *sda = nullptr;
+    if (precision == CSC_BF16 && n_iter > 0) {
+        WS(buf, __bf16, WS_SDA, synth_mfma_prep_elems(K));
+        HIPCHK(launch_synth_mfma_prep(di, K, m, buf, h->stream));
+        sda = buf;
+    }
     auto iterations = [&]() -> int {
         int c = 0;
         for (int it = 0; it < n_iter; ++it) {
             {
                 PROF(CSC_PK_SYNTH);
-                HIPCHK(synth(h, K, m, Lists{soff, nzc[c], pairs[c]}, di, xi, Wi, R, SYNTH_RESIDUAL, it == n_iter - 1));
+                HIPCHK(synth(h, K, m, Lists{soff, nzc[c], pairs[c]}, di, xi, Wi, R, SYNTH_RESIDUAL, it == n_iter - 1,
+                             precision, sda));
             }
             {
                 PROF(CSC_PK_ADJOINT);
@@ -717,10 +751,10 @@ extern "C" int csc_code_step(csc_handle h, const csc_images *im, const float *x,
     if (use_graph) {
         const std::vector<uintptr_t> key = {
             (uintptr_t)K, (uintptr_t)m, (uintptr_t)precision, (uintptr_t)n_iter, (uintptr_t)g.n_tiles,
-            (uintptr_t)g.n_pix, (uintptr_t)(h->force_variant + 1), (uintptr_t)h->tuned[synth_key(h, K, m, SYNTH_RESIDUAL)],
+            (uintptr_t)g.n_pix, (uintptr_t)(h->force_variant + 1), (uintptr_t)tuned_variant(h, synth_key(h, K, m, SYNTH_RESIDUAL, precision)),
             (uintptr_t)g.d_img, (uintptr_t)g.d_tiles, (uintptr_t)mw, (uintptr_t)soff, (uintptr_t)pairs[0],
             (uintptr_t)pairs[1], (uintptr_t)nzc[0], (uintptr_t)nzc[1], (uintptr_t)R, (uintptr_t)sc, (uintptr_t)xi,
-            (uintptr_t)di, (uintptr_t)Wi};
+            (uintptr_t)di, (uintptr_t)Wi, (uintptr_t)sda};
         // the null stream cannot be captured: use a private (default-priority) stream,
         // ordered after and before the handle's stream with events
         hipStream_t gs = h->stream;
@@ -855,7 +889,7 @@ extern "C" int csc_dict_step(csc_handle h, const csc_images *im, const float *x,
         for (int it = 0; it < n_iter; ++it) {
             {
                 PROF(CSC_PK_SYNTH);
-                HIPCHK(synth(h, K, m, L, d, x, W, R, SYNTH_RESIDUAL));
+                HIPCHK(synth(h, K, m, L, d, x, W, R, SYNTH_RESIDUAL, true, precision));
             }
             st = precision == CSC_BF16 ? filter_corr_bf16(h, K, m, L, R, G) : filter_corr_lists(h, K, m, F, R, G);
             if (st) return st;
@@ -952,7 +986,7 @@ extern "C" int csc_synthesize(csc_handle h, const csc_images *im, const float *d
     if ((st = build_nonzero_lists(h, K, z, &L))) return st;
     {
         PROF(CSC_PK_SYNTH);
-        HIPCHK(synth(h, K, m, L, d, nullptr, nullptr, y, SYNTH_PLAIN));
+        HIPCHK(synth(h, K, m, L, d, nullptr, nullptr, y, SYNTH_PLAIN, true, precision));
     }
     return CSC_OK;
 }

@@ -118,6 +118,222 @@ hipError_t corr_mfma_impl(const Geometry &g, int K, Lists z, const float *r, flo
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Synthesis with BF16 operands on the matrix cores (FP32 accumulation and FP32
+// residual).  For a 16 x 16 output tile (origin shifted by -c), one GEMM per
+// tile forms, for every input row y' of the tile's region and output column x,
+//     V[r][y'][x] = sum_k sum_u' d_k[r][2c - u'] z_k[y'][x + u']
+//         M = tap row r (padded to 16), N = the 16 output columns,
+//         K-dim = (filter, reversed tap column u'), 8 filters x 4 tap columns
+//         per 32-wide step;
+// the output is the sum over tap rows of V shifted along y:
+//     y[ly][lx] = sum_r V[r][ly + 2c - r][lx] = sum_k sum_s d_k[s] z_k[p - s].
+// Codes are scattered from the per-pixel lists into a dense BF16 tile of the
+// region with the 8 filters of a group innermost, so that one aligned 16-byte
+// LDS read gives a lane its 8 operand values; a chunk holds SM_FG groups.
+// Operand A comes prepared as dA[r][group][u'][8 filters] (k_synth_prep_a).
+// ---------------------------------------------------------------------------
+constexpr int SM_CAP = 4096;  // code entries of a region staged in LDS
+
+template <int MM>
+constexpr int sm_steps() { return (MM + 3) / 4; }  // 4 tap columns per step
+
+template <int MM>
+__global__ void k_synth_prep_a(const float *__restrict__ d, int K, __bf16 *__restrict__ dA) {
+    constexpr int M = MM * MM, C = MM / 2, U = 4 * sm_steps<MM>();
+    const int K8 = (K + 7) / 8;
+    const long long n = 16LL * K8 * U * 8;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const int f = (int)(i % 8), up = (int)((i / 8) % U);
+        const int fg = (int)((i / (8 * U)) % K8), r = (int)(i / (8LL * U * K8));
+        const int k = 8 * fg + f, u = 2 * C - up;
+        dA[i] = (r < MM && up < MM && k < K) ? (__bf16)d[(long long)k * M + r * MM + u] : (__bf16)0.f;
+    }
+}
+
+// Exclusive prefix over the block of one int per thread; returns the total.
+__device__ __forceinline__ int block_exclusive_scan(int v, int *excl, int *wsum) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int incl = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += t;
+    }
+    if (lane == 63) wsum[wave] = incl;
+    __syncthreads();
+    int before = 0, total = 0;
+#pragma unroll
+    for (int w = 0; w < TPB / 64; ++w) {
+        before += (w < wave) ? wsum[w] : 0;
+        total += wsum[w];
+    }
+    *excl = before + incl - v;
+    return total;
+}
+
+template <int MM, int FG>
+__global__ __launch_bounds__(TPB) void k_synth_mfma(const ImgInfo *imgs, const TileInfo *tiles, int K, Lists zl,
+                                                    const __bf16 *__restrict__ dA, const float *__restrict__ x,
+                                                    const unsigned char *__restrict__ W, float *__restrict__ out,
+                                                    int mode) {
+    constexpr int C = MM / 2, RW = TS + 2 * C, NS = sm_steps<MM>(), U = 4 * NS;
+    constexpr int ZC = TS + U - 1;              // columns x + u' that a step reads
+    static_assert(ZC >= RW, "code tile narrower than the region");
+    constexpr int NPT = (RW * RW + TPB - 1) / TPB;  // region pixels per thread
+    constexpr int NCW = (RW + 3) / 4;           // input rows per wave
+    constexpr int GT = RW * ZC;                 // 16-byte cells per filter group
+    constexpr int ZB = FG * GT * 16;            // bytes of the code tile
+    constexpr int LB = ZB + SM_CAP * 6;         // + staged entries (key, value)
+    constexpr int VB = 16 * RW * TS;            // floats of the V staging
+    static_assert(VB * 4 <= LB, "V staging must fit in the shared buffer");
+    __shared__ bf16x8 lds8[LB / 16];
+    __shared__ int wsum[TPB / 64];
+    bf16x8 *zt8 = lds8;                                   // [group][input row][column][8 filters]
+    __bf16 *zt = reinterpret_cast<__bf16 *>(lds8);
+    unsigned *skey = reinterpret_cast<unsigned *>(reinterpret_cast<char *>(lds8) + ZB);  // k << 10 | region pixel
+    __bf16 *sval = reinterpret_cast<__bf16 *>(skey + SM_CAP);
+
+    const PixelCtx c = pixel_ctx(imgs, tiles);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int fcol = lane & 15, kg = lane >> 4;
+    const int oy = c.t.ty * TS - C, ox = c.t.tx * TS - C;
+    const int K8 = (K + 7) / 8;
+
+    // this thread's region pixels and their lists
+    unsigned po[NPT];
+    int pn[NPT], ntot = 0;
+#pragma unroll
+    for (int q = 0; q < NPT; ++q) {
+        const int i = threadIdx.x + q * TPB;
+        const int gy = oy + i / RW, gx = ox + i % RW;
+        pn[q] = 0;
+        po[q] = 0;
+        if (i < RW * RW && gy >= 0 && gy < c.im.H && gx >= 0 && gx < c.im.W) {
+            const long long gp = c.im.pix_off + (long long)gy * c.im.W + gx;
+            po[q] = zl.off[gp];
+            pn[q] = zl.cnt[gp];
+        }
+        ntot += pn[q];
+    }
+    int ebeg;
+    const int total = block_exclusive_scan(ntot, &ebeg, wsum);
+    const bool staged = total <= SM_CAP;  // uniform over the block
+    if (staged) {
+        int e = ebeg;
+#pragma unroll
+        for (int q = 0; q < NPT; ++q) {
+            const unsigned pix = threadIdx.x + q * TPB;
+#pragma unroll 4
+            for (int j = 0; j < pn[q]; ++j) {
+                const Pair pr = zl.pairs[po[q] + j];
+                skey[e + j] = ((unsigned)pr.k << 10) | pix;
+                sval[e + j] = (__bf16)pr.v;
+            }
+            e += pn[q];
+        }
+    }
+
+    const bf16x8 *dA8 = reinterpret_cast<const bf16x8 *>(dA) + (long long)fcol * K8 * U + kg;
+    f32x4 acc[NCW];
+#pragma unroll
+    for (int j = 0; j < NCW; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int g0 = 0; g0 < K8; g0 += FG) {
+        const int ng = min(FG, K8 - g0);
+        // operand A of the whole chunk, issued before the scatter hides its latency
+        bf16x8 afr[FG][NS];
+#pragma unroll
+        for (int gl = 0; gl < FG; ++gl)
+#pragma unroll
+            for (int st = 0; st < NS; ++st) afr[gl][st] = dA8[(long long)(g0 + min(gl, ng - 1)) * U + 4 * st];
+        __syncthreads();  // the previous chunk's operands have been read (and the entries staged)
+        for (int i = threadIdx.x; i < FG * GT; i += TPB) zt8[i] = bf16x8{};
+        __syncthreads();
+        const unsigned k0 = 8 * g0, k1 = min(K, 8 * (g0 + ng));
+        if (staged) {
+            for (int e = ebeg; e < ebeg + ntot; ++e) {
+                const unsigned key = skey[e], k = key >> 10;
+                if (k >= k0 && k < k1) {
+                    const unsigned kl = k - k0, pix = key & 1023u;
+                    const unsigned yr = pix / RW, xr = pix % RW;
+                    zt[(((kl >> 3) * RW + yr) * ZC + xr) * 8 + (kl & 7)] = sval[e];
+                }
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < NPT; ++q) {
+                const int pix = threadIdx.x + q * TPB;
+                const int yr = pix / RW, xr = pix % RW;
+                for (int j = 0; j < pn[q]; ++j) {
+                    const Pair pr = zl.pairs[po[q] + j];
+                    if ((unsigned)pr.k >= k0 && (unsigned)pr.k < k1) {
+                        const int kl = pr.k - (int)k0;
+                        zt[(((kl >> 3) * RW + yr) * ZC + xr) * 8 + (kl & 7)] = (__bf16)pr.v;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int gl = 0; gl < FG; ++gl) {
+            if (gl >= ng) break;
+#pragma unroll
+            for (int st = 0; st < NS; ++st) {
+#pragma unroll
+                for (int cw = 0; cw < NCW; ++cw) {
+                    const int ct = wave + 4 * cw;  // input row
+                    if (ct >= RW) continue;
+                    const bf16x8 bfr = zt8[(gl * RW + ct) * ZC + fcol + 4 * st + kg];
+                    acc[cw] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr[gl][st], bfr, acc[cw], 0, 0, 0);
+                }
+            }
+        }
+    }
+    __syncthreads();  // the shared buffer becomes the V staging
+    float *vb = reinterpret_cast<float *>(lds8);  // [r][input row][column]
+#pragma unroll
+    for (int cw = 0; cw < NCW; ++cw) {
+        const int ct = wave + 4 * cw;
+        if (ct >= RW) continue;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) vb[((kg * 4 + i) * RW + ct) * TS + fcol] = acc[cw][i];
+    }
+    __syncthreads();
+    if (!c.valid) return;
+    float y = 0.f;
+#pragma unroll
+    for (int r = 0; r < MM; ++r) y += vb[(r * RW + c.ly + 2 * C - r) * TS + c.lx];
+    float ov;
+    if (mode == SYNTH_RESIDUAL) {
+        ov = x[c.gp] - y;
+        if (W && !W[c.gp]) ov = 0.f;
+    } else if (mode == SYNTH_WEIGHTED) {
+        ov = (W && !W[c.gp]) ? 0.f : y;
+    } else {
+        ov = y;
+    }
+    out[c.gp] = ov;
+}
+
+template <int MM>
+hipError_t synth_mfma_prep_impl(const float *d, int K, __bf16 *dA, hipStream_t s) {
+    const long long n = 16LL * ((K + 7) / 8) * 4 * sm_steps<MM>() * 8;
+    hipLaunchKernelGGL(k_synth_prep_a<MM>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, d, K, dA);
+    return hipGetLastError();
+}
+
+template <int MM>
+hipError_t synth_mfma_impl(const Geometry &g, int K, Lists z, const __bf16 *dA, const float *x,
+                           const unsigned char *W, float *out, int mode, int variant, hipStream_t s) {
+    if (variant == 0)
+        hipLaunchKernelGGL((k_synth_mfma<MM, 2>), dim3(g.n_tiles), dim3(TPB), 0, s, g.d_img, g.d_tiles, K, z, dA, x, W,
+                           out, mode);
+    else
+        hipLaunchKernelGGL((k_synth_mfma<MM, 4>), dim3(g.n_tiles), dim3(TPB), 0, s, g.d_img, g.d_tiles, K, z, dA, x, W,
+                           out, mode);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 int corr_mfma_blocks(const Geometry &g, int K) {
@@ -125,6 +341,31 @@ int corr_mfma_blocks(const Geometry &g, int K) {
     int nb = 512 / ngroups;
     if (nb < 1) nb = 1;
     return nb < g.n_tiles ? nb : g.n_tiles;
+}
+
+size_t synth_mfma_prep_elems(int K) { return (size_t)16 * ((K + 7) / 8) * 12 * 8; }  // up to 12 tap columns
+
+hipError_t launch_synth_mfma_prep(const float *d, int K, int m, __bf16 *dA, hipStream_t s) {
+    switch (m) {
+        case 3: return synth_mfma_prep_impl<3>(d, K, dA, s);
+        case 5: return synth_mfma_prep_impl<5>(d, K, dA, s);
+        case 7: return synth_mfma_prep_impl<7>(d, K, dA, s);
+        case 9: return synth_mfma_prep_impl<9>(d, K, dA, s);
+        case 11: return synth_mfma_prep_impl<11>(d, K, dA, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_synth_mfma(const Geometry &g, int K, int m, Lists z, const __bf16 *dA, const float *x,
+                             const unsigned char *W, float *out, int mode, int variant, hipStream_t s) {
+    switch (m) {
+        case 3: return synth_mfma_impl<3>(g, K, z, dA, x, W, out, mode, variant, s);
+        case 5: return synth_mfma_impl<5>(g, K, z, dA, x, W, out, mode, variant, s);
+        case 7: return synth_mfma_impl<7>(g, K, z, dA, x, W, out, mode, variant, s);
+        case 9: return synth_mfma_impl<9>(g, K, z, dA, x, W, out, mode, variant, s);
+        case 11: return synth_mfma_impl<11>(g, K, z, dA, x, W, out, mode, variant, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_corr_mfma(const Geometry &g, int K, int m, Lists z, const float *r, float *part, float *G,

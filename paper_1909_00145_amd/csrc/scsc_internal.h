@@ -295,6 +295,14 @@ long long surrogate_matvec_partial_elems(int K, int m);
 // G = sum_i Z_i^T r_i ([K][m][m], FP32) on the matrix cores from per-pixel code lists,
 // BF16 operands, FP32 accumulation; part needs corr_mfma_blocks(g, K) * K * m^2 floats.
 int corr_mfma_blocks(const Geometry &g, int K);
+// out = W (x - D z) / D z / W (D z) (mode as launch_synth) with BF16 operands on the
+// matrix cores and FP32 accumulation.  The filters enter as dA, the BF16 operand
+// written by launch_synth_mfma_prep (synth_mfma_prep_elems(K) elements).
+size_t synth_mfma_prep_elems(int K);
+hipError_t launch_synth_mfma_prep(const float *d, int K, int m, __bf16 *dA, hipStream_t s);
+// variant 0: 16 filters per LDS chunk, 1: 32.
+hipError_t launch_synth_mfma(const Geometry &g, int K, int m, Lists z, const __bf16 *dA, const float *x,
+                             const unsigned char *W, float *out, int mode, int variant, hipStream_t s);
 hipError_t launch_corr_mfma(const Geometry &g, int K, int m, Lists z, const float *r, float *part, float *G,
                             hipStream_t s);
 

@@ -7,6 +7,7 @@ import pytest
 import torch
 
 import oracle
+import scsc_inputs as si
 from gpu_helpers import f32, make_problem, packed, rel_err, say, to_dev
 
 pytestmark = pytest.mark.gpu
@@ -143,3 +144,50 @@ def test_dict_step_batch_bf16(ctx, hw, K, m, with_W):
     say("  L_d", Ld, Ldr, "d err", rel_err(dg.cpu().numpy(), dr))
     assert abs(Ld - Ldr) <= TOLBF * Ldr
     assert rel_err(dg.cpu().numpy(), dr) < TOLBF
+
+
+# density 0.6 with K = 40 puts more code entries in a tile's region than the
+# kernel stages in LDS, so those tiles read the lists from memory per chunk
+@pytest.mark.parametrize("hw,K,m,density", [([(40, 36)], 16, 11, 0.1), ([(23, 50), (31, 17)], 33, 7, 0.1),
+                                            ([(19, 21)], 5, 3, 0.1), ([(30, 30), (7, 70)], 70, 5, 0.1),
+                                            ([(18, 40)], 20, 9, 0.1), ([(40, 36)], 40, 11, 0.6)])
+def test_synthesis_bf16_rounded_operands(ctx, hw, K, m, density):
+    """D z on the matrix cores equals the FP64 synthesis of BF16-rounded d and z."""
+    from paper_1909_00145_amd.ops import Images
+
+    say("bf16 synthesis", hw, K, m, density)
+    rng = np.random.default_rng(K + 3 * m)
+    im = Images(hw)
+    d = f32(rng.standard_normal((K, m, m)))
+    zs = [f32(rng.standard_normal((K, H, W)) * (rng.random((K, H, W)) < density)) for H, W in hw]
+    y = ctx.synthesize(im, to_dev(d), packed(im, zs), precision="bf16").cpu().numpy()
+    ref = im.pack([oracle.synthesize(bf16_round(d), bf16_round(z)) for z in zs])
+    err = rel_err(y, ref)
+    say("  rel err", err)
+    assert err < 1e-5
+
+
+def test_synthesis_bf16_variants_bit_identical(ctx):
+    """Both LDS chunk sizes of the BF16 synthesis give the same bits (synthesis and a code step)."""
+    from paper_1909_00145_amd.ops import Images
+
+    say("bf16 synthesis variants")
+    hw = [(70, 45), (33, 100)]
+    K, m = 44, 11
+    rng = np.random.default_rng(12)
+    im = Images(hw)
+    d = to_dev(f32(rng.standard_normal((K, m, m))))
+    z = packed(im, [f32(rng.standard_normal((K, H, W)) * (rng.random((K, H, W)) < 0.05)) for H, W in hw])
+    xs = [f32(si.field(4, i, H, W)) for i, (H, W) in enumerate(hw)]
+    outs, codes = [], []
+    try:
+        for v in range(2):
+            ctx.set_autotune(True, variant=v)
+            outs.append(ctx.synthesize(im, d, z, precision="bf16").cpu().numpy())
+            zz = torch.zeros(K * im.n_pix, dtype=torch.float32, device="cuda")
+            ctx.code_step(im, packed(im, xs), d, zz, 0.5, 0.3, 7, 1, 10, precision="bf16")
+            codes.append(zz.cpu().numpy())
+    finally:
+        ctx.set_autotune(True)
+    np.testing.assert_array_equal(outs[1], outs[0])
+    np.testing.assert_array_equal(codes[1], codes[0])
