@@ -547,7 +547,7 @@ __global__ void k_zero_f64(double *p, long long n) {
 // C_bar(k, k2) += R - E_top - E_bottom - E_left - E_right for every stored block
 // k <= k2 (one workgroup per block, blockIdx.x = its upper-triangle index).
 // Each workgroup reads and writes its own block with coalesced accesses.
-constexpr int EX_THREADS = 256;
+constexpr int EX_THREADS = 512;
 constexpr int EX_BATCH = 8;
 
 template <int MM>
@@ -567,14 +567,35 @@ __global__ __launch_bounds__(EX_THREADS) void k_sur_expand(int K, const double *
     while (tri_block(k + 1, k + 1, K) <= bi) ++k;
     const int k2 = k + (int)(bi - tri_block(k, k, K));
     for (int i = threadIdx.x; i < LL; i += EX_THREADS) r[i] = Rl[((long long)k * K + k2) * LL + i];
+    // band sums: all loads of the block issued EX_BATCH at a time, then the
+    // prefix over the band rows j in LDS
+    constexpr int NE = 4 * NC * LL;
+    for (int i0 = threadIdx.x; i0 < NE && C > 0; i0 += EX_THREADS * EX_BATCH) {
+        double ev[EX_BATCH];
+#pragma unroll
+        for (int u = 0; u < EX_BATCH; ++u) {
+            const int i = i0 + u * EX_THREADS;
+            ev[u] = 0.0;
+            if (i >= NE) continue;
+            const int cls = i / LL, di = i % LL;  // cls = side * c + j
+            const int sd = cls / NC, j = cls % NC;
+            const int dy = di / L - 2 * C, dx = di % L - 2 * C;
+            const int dlt = sd == 0 ? -dy : sd == 1 ? dy : sd == 2 ? -dx : dx;
+            // band rows j >= min(c, c + dlt) are never read for this lag (and were not formed)
+            if (j < min(C, C + dlt)) ev[u] = Es[(((long long)cls * K + k) * K + k2) * LL + di];
+        }
+#pragma unroll
+        for (int u = 0; u < EX_BATCH; ++u) {
+            const int i = i0 + u * EX_THREADS;
+            if (i < NE) (&ec[0][0][0])[i] = ev[u];
+        }
+    }
+    __syncthreads();
     for (int i = threadIdx.x; i < 4 * LL && C > 0; i += EX_THREADS) {
         const int sd = i / LL, di = i % LL;
-        const int dy = di / L - 2 * C, dx = di % L - 2 * C;
-        const int dlt = sd == 0 ? -dy : sd == 1 ? dy : sd == 2 ? -dx : dx;
-        const int nj = min(C, C + dlt);  // band rows this lag reads (the rest were not formed)
         double acc = 0.0;
-        for (int j = 0; j < nj; ++j) {
-            acc += Es[(((long long)(sd * C + j) * K + k) * K + k2) * LL + di];
+        for (int j = 0; j < NC; ++j) {
+            acc += ec[sd][j][di];
             ec[sd][j][di] = acc;
         }
     }
