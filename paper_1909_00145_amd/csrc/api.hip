@@ -51,6 +51,7 @@ enum Slot {
     WS_DC,
     WS_LAGF,
     WS_SDA,
+    WS_LAGPART,
     WS_COUNT
 };
 
@@ -865,8 +866,9 @@ extern "C" int csc_dict_step(csc_handle h, const csc_images *im, const float *x,
             WS(es, double, WS_ES, nl * 4 * (m / 2 > 0 ? m / 2 : 1));
             Es = es;
         }
+        WS(lpart, double, WS_LAGPART, surrogate_lag_part_elems(g, K, m));
         PROF(CSC_PK_SUR_LAG);
-        HIPCHK(launch_surrogate_lag(g, K, m, L, F.off, F.codes, Rl, Es, h->stream));
+        HIPCHK(launch_surrogate_lag(g, K, m, L, lpart, Rl, Es, h->stream));
     }
     if (need_ld) {
         if (W) st = power_iteration(h, K, m, L, F, W, n_power, precision);

@@ -353,10 +353,12 @@ __global__ void k_lag_table(unsigned short *tab) {
 // z_k2[q + delta] in LDS and adds the outer products of the code lists of every
 // pixel pair (q, q + delta) of its pixel set.
 //   band == 0: every pixel of the batch, split into gridDim.z chunks; lags delta >= 0
-//     only, since R_{-delta} = R_delta^T; both halves are written into Rl[k][k2][lag]
-//     (k <= k2), added atomically when there is more than one chunk (Rl zeroed first).
+//     only, since R_{-delta} = R_delta^T; chunk z writes its partial sums to
+//     out[z][delta][k][k2] (coalesced), and k_lag_sum adds the chunks and forms both
+//     halves of Rl[lag][k][k2].
 //   band == 1: blockIdx.z = side * c + j selects row (column) j of the top, bottom,
-//     left or right band of every image; every lag; stored into Es[cls][k][k2][lag].
+//     left or right band of every image; every lag; stored into Es[cls][lag][k][k2]
+//     (k <= k2).
 constexpr int LO_THREADS = 1024;
 constexpr int LO_U = 8;  // list entries per pixel held in registers
 
@@ -463,25 +465,38 @@ __global__ __launch_bounds__(LO_THREADS) void k_lag_outer(const ImgInfo *imgs, i
         }
     }
     __syncthreads();
-    const bool accumulate = !band && gridDim.z > 1;
-    const int centre = (LL - 1) / 2;
+    const long long row0 = band ? ((long long)cls * LL + di) * K : ((long long)blockIdx.z * gridDim.x + blockIdx.x) * K;
     for (int i = threadIdx.x; i < (khi - klo) * K; i += LO_THREADS) {
         const int k = klo + i / K, k2 = i % K;
-        const double v = Rd[i];
-        if (band) {
-            if (k <= k2) out[(((long long)cls * K + k) * K + k2) * LL + di] = v;
-            continue;
-        }
-        // R_delta[k][k2] is entry (k, k2) at lag delta and entry (k2, k) at lag -delta
-        // (a diagonal block k == k2 takes both)
-        for (int h = 0; h < 2; ++h) {
-            long long pos;
-            if (h == 0 && k <= k2) pos = ((long long)k * K + k2) * LL + di;
-            else if (h == 1 && k2 <= k && di != centre) pos = ((long long)k2 * K + k) * LL + (LL - 1 - di);
-            else continue;
-            if (accumulate) atomicAdd(out + pos, v);
-            else out[pos] = v;
-        }
+        if (!band || k <= k2) out[(row0 + k) * K + k2] = Rd[i];
+    }
+}
+
+// Rl[lag][a][b] = sum over the chunks z of part[z][delta][a][b] for the lag delta >= 0,
+// and Rl[-lag][b][a] = the same sum (R_{-delta} = R_delta^T), through a 32 x 32 LDS
+// tile so that both writes are coalesced.  Grid (delta, tiles of a, tiles of b).
+constexpr int LS_T = 32;
+
+template <int MM>
+__global__ __launch_bounds__(256) void k_lag_sum(int K, int n_chunks, const double *__restrict__ part,
+                                                 double *__restrict__ Rl) {
+    constexpr int L = 2 * MM - 1, LL = L * L, centre = (LL - 1) / 2, nlag = (LL + 1) / 2;
+    __shared__ double t[LS_T][LS_T + 1];
+    const int dl = blockIdx.x, a0 = blockIdx.y * LS_T, b0 = blockIdx.z * LS_T;
+    for (int i = threadIdx.x; i < LS_T * LS_T; i += 256) {
+        const int ia = i / LS_T, ib = i % LS_T, a = a0 + ia, b = b0 + ib;
+        if (a >= K || b >= K) continue;
+        double v = 0.0;
+        for (int z = 0; z < n_chunks; ++z) v += part[(((long long)z * nlag + dl) * K + a) * K + b];
+        t[ia][ib] = v;
+        Rl[((long long)(centre + dl) * K + a) * K + b] = v;
+    }
+    if (dl == 0) return;  // R_0 is written once (as summed for (a, b))
+    __syncthreads();
+    for (int i = threadIdx.x; i < LS_T * LS_T; i += 256) {
+        const int ib = i / LS_T, ia = i % LS_T, a = a0 + ia, b = b0 + ib;
+        if (a >= K || b >= K) continue;
+        Rl[((long long)(centre - dl) * K + b) * K + a] = t[ia][ib];
     }
 }
 
@@ -502,9 +517,8 @@ __global__ __launch_bounds__(MM *RM_KB) void k_lag_matvec(int K, const float *__
     const int k = blockIdx.x, ch = blockIdx.y;
     const int k2lo = ch * RM_KB, nk = min(RM_KB, K - k2lo);
     for (int i = threadIdx.x; i < nk * LL; i += NT) {
-        const int j = i / LL, di = i % LL, k2 = k2lo + j;
-        // R_delta[k][k2] is stored for k <= k2; otherwise it is R_{-delta}[k2][k]
-        r[j][di] = k <= k2 ? Rl[((long long)k * K + k2) * LL + di] : Rl[((long long)k2 * K + k) * LL + (LL - 1 - di)];
+        const int di = i / nk, j = i % nk;
+        r[j][di] = Rl[((long long)di * K + k) * K + k2lo + j];
     }
     for (int i = threadIdx.x; i < nk * M; i += NT) vv[i / M][i % M] = (double)v[(long long)(k2lo + i / M) * M + i % M];
     __syncthreads();
@@ -566,7 +580,7 @@ __global__ __launch_bounds__(EX_THREADS) void k_sur_expand(int K, const double *
     int k = 0;
     while (tri_block(k + 1, k + 1, K) <= bi) ++k;
     const int k2 = k + (int)(bi - tri_block(k, k, K));
-    for (int i = threadIdx.x; i < LL; i += EX_THREADS) r[i] = Rl[((long long)k * K + k2) * LL + i];
+    for (int i = threadIdx.x; i < LL; i += EX_THREADS) r[i] = Rl[((long long)i * K + k) * K + k2];
     // band sums: all loads of the block issued EX_BATCH at a time, then the
     // prefix over the band rows j in LDS
     constexpr int NE = 4 * NC * LL;
@@ -582,7 +596,7 @@ __global__ __launch_bounds__(EX_THREADS) void k_sur_expand(int K, const double *
             const int dy = di / L - 2 * C, dx = di % L - 2 * C;
             const int dlt = sd == 0 ? -dy : sd == 1 ? dy : sd == 2 ? -dx : dx;
             // band rows j >= min(c, c + dlt) are never read for this lag (and were not formed)
-            if (j < min(C, C + dlt)) ev[u] = Es[(((long long)cls * K + k) * K + k2) * LL + di];
+            if (j < min(C, C + dlt)) ev[u] = Es[(((long long)cls * LL + di) * K + k) * K + k2];
         }
 #pragma unroll
         for (int u = 0; u < EX_BATCH; ++u) {
@@ -836,36 +850,47 @@ hipError_t launch_surrogate_matvec(int K, int m, const double *C, const float *d
 long long surrogate_lag_elems(int K, int m) { return (long long)K * K * (2 * m - 1) * (2 * m - 1); }
 
 namespace {
+struct LagPlan {
+    int KC, nkc, nlag;
+    long long P;
+};
+
 template <int MM>
-hipError_t sur_lag_impl(const Geometry &g, int K, Lists z, const unsigned *fm_off, const FmCode *fm, double *Rl,
-                        double *Es, hipStream_t s) {
-    (void)fm_off;
-    (void)fm;
-    constexpr int Cc = MM / 2, L = 2 * MM - 1, LL = L * L;
-    int KC = (80 * 1024) / (8 * K);
-    if (KC > K) KC = K;
-    if (KC < 1) KC = 1;
-    const int nkc = (K + KC - 1) / KC;
-    const size_t shm = sizeof(double) * (size_t)KC * K;
-    const int nlag = (LL + 1) / 2;
+LagPlan lag_plan(const Geometry &g, int K) {
+    constexpr int L = 2 * MM - 1, LL = L * L;
+    LagPlan pl;
+    pl.KC = std::max(1, std::min(K, (80 * 1024) / (8 * K)));
+    pl.nkc = (K + pl.KC - 1) / pl.KC;
+    pl.nlag = (LL + 1) / 2;
     // pixel chunks: enough workgroups to cover the chip a few times, at least 2048 pixels each
-    long long P = 2048 / ((long long)nlag * nkc);
-    P = std::max(1LL, std::min(P, (long long)(g.n_pix / 2048)));
-    hipError_t e;
-    if (P > 1) {
-        const long long n = (long long)K * K * LL;
-        hipLaunchKernelGGL(k_zero_f64, dim3(1024), dim3(256), 0, s, Rl, n);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL(k_lag_outer<MM>, dim3(nlag, nkc, (unsigned)P), dim3(LO_THREADS), shm, s, g.d_img, g.n_img,
-                       (long long)g.n_pix, g.max_side, K, z, 0, KC, Rl);
+    pl.P = std::max(1LL, std::min(2048LL / ((long long)pl.nlag * pl.nkc), (long long)(g.n_pix / 2048)));
+    return pl;
+}
+
+template <int MM>
+hipError_t sur_lag_impl(const Geometry &g, int K, Lists z, double *part, double *Rl, double *Es, hipStream_t s) {
+    constexpr int Cc = MM / 2, L = 2 * MM - 1, LL = L * L;
+    const LagPlan pl = lag_plan<MM>(g, K);
+    const size_t shm = sizeof(double) * (size_t)pl.KC * K;
+    hipLaunchKernelGGL(k_lag_outer<MM>, dim3(pl.nlag, pl.nkc, (unsigned)pl.P), dim3(LO_THREADS), shm, s, g.d_img,
+                       g.n_img, (long long)g.n_pix, g.max_side, K, z, 0, pl.KC, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const unsigned nt = (unsigned)((K + LS_T - 1) / LS_T);
+    hipLaunchKernelGGL(k_lag_sum<MM>, dim3(pl.nlag, nt, nt), dim3(256), 0, s, K, (int)pl.P, part, Rl);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (Cc > 0 && Es) {
-        hipLaunchKernelGGL(k_lag_outer<MM>, dim3(LL, nkc, 4 * Cc), dim3(LO_THREADS), shm, s, g.d_img, g.n_img,
-                           (long long)g.n_pix, g.max_side, K, z, 1, KC, Es);
+        hipLaunchKernelGGL(k_lag_outer<MM>, dim3(LL, pl.nkc, 4 * Cc), dim3(LO_THREADS), shm, s, g.d_img, g.n_img,
+                           (long long)g.n_pix, g.max_side, K, z, 1, pl.KC, Es);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+template <int MM>
+long long lag_part_impl(const Geometry &g, int K) {
+    const LagPlan pl = lag_plan<MM>(g, K);
+    return pl.P * pl.nlag * (long long)K * K;
 }
 
 template <int MM>
@@ -909,9 +934,13 @@ hipError_t sur_corner_impl(const Geometry &g, int K, Lists z, double *C, hipStre
         default: return hipErrorInvalidValue; \
     }
 
-hipError_t launch_surrogate_lag(const Geometry &g, int K, int m, Lists z, const unsigned *fm_off, const FmCode *fm,
-                                double *Rl, double *Es, hipStream_t s) {
-    SCSC_DISPATCH_M(m, sur_lag_impl, g, K, z, fm_off, fm, Rl, Es, s);
+long long surrogate_lag_part_elems(const Geometry &g, int K, int m) {
+    SCSC_DISPATCH_M(m, lag_part_impl, g, K);
+}
+
+hipError_t launch_surrogate_lag(const Geometry &g, int K, int m, Lists z, double *part, double *Rl, double *Es,
+                                hipStream_t s) {
+    SCSC_DISPATCH_M(m, sur_lag_impl, g, K, z, part, Rl, Es, s);
 }
 
 hipError_t launch_surrogate_expand(int K, int m, const double *Rl, const double *Es, unsigned short *tab, double *C,

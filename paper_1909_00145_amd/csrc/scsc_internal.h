@@ -271,11 +271,13 @@ hipError_t launch_fm_lists(const Geometry &g, int K, Lists z, unsigned *fm_cnt, 
                            unsigned long long *scan_tmp, unsigned long long *total64, hipStream_t s);
 hipError_t launch_surrogate_blocks(const Geometry &g, int K, int m, const unsigned *fm_off, const FmCode *fm,
                                    const unsigned char *W, double *C, hipStream_t s);
-// Unmasked case: lag sums (Rl: surrogate_lag_elems doubles, Es: 4 c of them, skipped
-// when Es is null), expansion, corners.
+// Unmasked case: lag sums Rl[lag][k][k2] (surrogate_lag_elems doubles), band sums
+// Es[4 c][lag][k][k2] (k <= k2; skipped when Es is null), expansion, corners.
+// part: surrogate_lag_part_elems doubles of workspace (per-chunk partial sums).
 long long surrogate_lag_elems(int K, int m);
-hipError_t launch_surrogate_lag(const Geometry &g, int K, int m, Lists z, const unsigned *fm_off, const FmCode *fm,
-                                double *Rl, double *Es, hipStream_t s);
+long long surrogate_lag_part_elems(const Geometry &g, int K, int m);
+hipError_t launch_surrogate_lag(const Geometry &g, int K, int m, Lists z, double *part, double *Rl, double *Es,
+                                hipStream_t s);
 // Product of the zero-padded normal matrix (lag sums Rl) with v [K][m*m]:
 // part[lag_matvec_chunks(K)][K][m*m] FP64 partial sums.
 int lag_matvec_chunks(int K);
