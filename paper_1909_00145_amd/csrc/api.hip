@@ -52,6 +52,7 @@ enum Slot {
     WS_LAGF,
     WS_SDA,
     WS_LAGPART,
+    WS_PNORM,
     WS_COUNT
 };
 
@@ -528,26 +529,28 @@ int power_iteration(csc_ctx *h, int K, int m, Lists L, FmLists F, const unsigned
 // Power iteration on the zero-padded normal matrix given by the lag sums Rl
 // (no observation mask); leaves the estimate in the device scalar SC_LAM.
 int power_iteration_lag(csc_ctx *h, int K, int m, const double *Rl, int n_power) {
-    const int M = m * m;
-    const int nch = lag_matvec_chunks(K);
-    WS(v, float, WS_V, K * M);
-    WS(w, float, WS_W, K * M);
-    WS(part, double, WS_PART, (size_t)nch * K * M);
+    const int M = m * m, n = K * M;
+    const int nch = lag_matvec_chunks(K), nb = power_reduce_blocks(n);
+    WS(wa, float, WS_V, n);
+    WS(wb, float, WS_W, n);
+    WS(part, double, WS_PART, (size_t)nch * n);
+    WS(np, double, WS_PNORM, 3 * (size_t)nb);
     WS(sc, double, WS_SCAL, SC_COUNT);
-    const long long nl = surrogate_lag_elems(K, m);
-    WS(Rf, float, WS_LAGF, nl);
-    HIPCHK(launch_f64_to_f32(nl, Rl, Rf, h->stream));
-    HIPCHK(launch_fill(v, K * M, (float)(1.0 / std::sqrt((double)K * M)), h->stream));
+    WS(Rf, float, WS_LAGF, surrogate_lag_elems(K, m));
+    HIPCHK(launch_lag_to_f32(K, m, Rl, Rf, h->stream));
+    // start: v = the normalised ones vector, given as w = 1 with ||w||^2 = n
+    double *na = np, *nbp = np + nb, *dp = np + 2 * nb;
+    HIPCHK(launch_fill(wa, n, 1.0f, h->stream));
+    HIPCHK(launch_power_start(na, nb, (double)n, h->stream));
     HIPCHK(hipMemsetAsync(sc + SC_LAM, 0, sizeof(double), h->stream));
     for (int it = 0; it < n_power; ++it) {
-        {
-            PROF(CSC_PK_POWER);
-            HIPCHK(launch_lag_matvec(K, m, Rf, v, part, h->stream));
-            HIPCHK(launch_reduce_partials_f64_to_f32(part, nch, K * M, w, h->stream));
-        }
-        PROF(CSC_PK_UPDATE);
-        HIPCHK(launch_power_update(v, w, K * M, sc + SC_LAM, h->stream));
+        PROF(CSC_PK_POWER);
+        HIPCHK(launch_lag_matvec(K, m, Rf, wa, na, nb, part, h->stream));
+        HIPCHK(launch_power_reduce(part, nch, n, wb, wa, na, nb, nbp, dp, h->stream));
+        std::swap(wa, wb);
+        std::swap(na, nbp);
     }
+    if (n_power > 0) HIPCHK(launch_power_final(na, dp, nb, sc + SC_LAM, h->stream));
     return CSC_OK;
 }
 

@@ -503,24 +503,51 @@ __global__ __launch_bounds__(256) void k_lag_sum(int K, int n_chunks, const doub
 // Product with the zero-padded normal matrix of the batch, whose entry
 // (k, s; k2, s2) is the lag sum R_{s - s2}[k][k2] (block Toeplitz in the taps):
 // part[chunk][k][s] = sum_{k2 in chunk} sum_{s2} R_{s - s2}[k][k2] v[k2][s2], FP64.
-// Workgroup (k, chunk of RM_KB partner filters); thread (k2, tap row s_y) keeps the
-// m outputs of its row in registers and reads each lag row once per s2_y; the
-// partner filters are then summed in a fixed order.
+// The vector comes as the previous power-iteration product w and the block
+// partial sums of its squared norm: v = w / ||w||, rounded to FP32 as stored.
+// Rf is the FP32 copy of the lag sums in [k][k2][lag] order, so that the rows of a
+// workgroup's partner chunk are one contiguous range.  Workgroup (k, chunk of
+// RM_KB partner filters); thread (k2, tap row s_y) keeps the m outputs of its row
+// in registers and reads each lag row once per s2_y; the partner filters are then
+// summed in a fixed order.
 constexpr int RM_KB = 16;
+constexpr int RM_LB = 8;  // loads in flight per thread
 
 template <int MM>
-__global__ __launch_bounds__(MM *RM_KB) void k_lag_matvec(int K, const float *__restrict__ Rl,
-                                                          const float *__restrict__ v, double *__restrict__ part) {
+__global__ __launch_bounds__(MM *RM_KB) void k_lag_matvec(int K, const float *__restrict__ Rf,
+                                                          const float *__restrict__ w,
+                                                          const double *__restrict__ nparts, int n_nparts,
+                                                          double *__restrict__ part) {
     constexpr int C = MM / 2, M = MM * MM, L = 2 * MM - 1, LL = L * L, NT = MM * RM_KB;
-    __shared__ float r[RM_KB][LL];
+    __shared__ float r[RM_KB * LL];
     __shared__ double vv[RM_KB][M];
+    __shared__ double inv_s;
     const int k = blockIdx.x, ch = blockIdx.y;
     const int k2lo = ch * RM_KB, nk = min(RM_KB, K - k2lo);
-    for (int i = threadIdx.x; i < nk * LL; i += NT) {
-        const int di = i / nk, j = i % nk;
-        r[j][di] = Rl[((long long)di * K + k) * K + k2lo + j];
+    if (threadIdx.x == 0) {
+        double nn = 0.0;
+        for (int i = 0; i < n_nparts; ++i) nn += nparts[i];
+        inv_s = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
     }
-    for (int i = threadIdx.x; i < nk * M; i += NT) vv[i / M][i % M] = (double)v[(long long)(k2lo + i / M) * M + i % M];
+    const float *src = Rf + ((long long)k * K + k2lo) * LL;
+    const int nr = nk * LL;
+    for (int i0 = threadIdx.x; i0 < nr; i0 += NT * RM_LB) {
+        float t[RM_LB];
+#pragma unroll
+        for (int u = 0; u < RM_LB; ++u) {
+            const int i = i0 + u * NT;
+            t[u] = i < nr ? src[i] : 0.f;
+        }
+#pragma unroll
+        for (int u = 0; u < RM_LB; ++u) {
+            const int i = i0 + u * NT;
+            if (i < nr) r[i] = t[u];
+        }
+    }
+    __syncthreads();
+    const double inv = inv_s;
+    for (int i = threadIdx.x; i < nk * M; i += NT)
+        vv[i / M][i % M] = (double)(float)((double)w[(long long)k2lo * M + i] * inv);
     __syncthreads();
     const int j = threadIdx.x / MM, sy = threadIdx.x % MM;
     double acc[MM];
@@ -528,7 +555,7 @@ __global__ __launch_bounds__(MM *RM_KB) void k_lag_matvec(int K, const float *__
     for (int sx = 0; sx < MM; ++sx) acc[sx] = 0.0;
     if (j < nk) {
         for (int s2y = 0; s2y < MM; ++s2y) {
-            const float *rrow = &r[j][(sy - s2y + 2 * C) * L];  // lags (dy, dx = sx - s2x + 2c)
+            const float *rrow = &r[j * LL + (sy - s2y + 2 * C) * L];  // lags (dy, dx = sx - s2x + 2c)
             const double *vrow = &vv[j][s2y * MM];
             double rv[L], vx[MM];
 #pragma unroll
@@ -542,7 +569,7 @@ __global__ __launch_bounds__(MM *RM_KB) void k_lag_matvec(int K, const float *__
         }
     }
     __syncthreads();
-    double *red = &vv[0][0];  // [RM_KB][M], reuses the filter rows
+    double *red = &vv[0][0];  // [RM_KB][M], reuses the vector rows
 #pragma unroll
     for (int sx = 0; sx < MM; ++sx) red[j * M + sy * MM + sx] = acc[sx];
     __syncthreads();
@@ -551,6 +578,85 @@ __global__ __launch_bounds__(MM *RM_KB) void k_lag_matvec(int K, const float *__
         for (int jj = 0; jj < nk; ++jj) t += red[jj * M + s];
         part[((long long)ch * K + k) * M + s] = t;
     }
+}
+
+// Rf[a][b][lag] = (float) Rl[lag][a][b] through 32 x 32 LDS tiles (both sides coalesced).
+// Grid (a, tiles of b, tiles of lags).
+template <int MM>
+__global__ __launch_bounds__(256) void k_lag_to_f32_t(int K, const double *__restrict__ Rl, float *__restrict__ Rf) {
+    constexpr int L = 2 * MM - 1, LL = L * L;
+    __shared__ float t[32][33];
+    const int a = blockIdx.x, b0 = blockIdx.y * 32, l0 = blockIdx.z * 32;
+    for (int i = threadIdx.x; i < 32 * 32; i += 256) {
+        const int il = i / 32, ib = i % 32, lag = l0 + il, b = b0 + ib;
+        if (lag < LL && b < K) t[il][ib] = (float)Rl[((long long)lag * K + a) * K + b];
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < 32 * 32; i += 256) {
+        const int ib = i / 32, il = i % 32, lag = l0 + il, b = b0 + ib;
+        if (lag < LL && b < K) Rf[((long long)a * K + b) * LL + lag] = t[il][ib];
+    }
+}
+
+// One power-iteration reduction: w = sum of the chunk partials (rounded to FP32),
+// and per workgroup the partial sums of ||w||^2 and of v . w, with v the vector
+// of this product (w_prev / ||w_prev||, as the matvec formed it).
+constexpr int PR_THREADS = 256;
+
+__global__ __launch_bounds__(PR_THREADS) void k_power_reduce(const double *__restrict__ part, int nch, int n,
+                                                             float *__restrict__ w_out, const float *__restrict__ w_prev,
+                                                             const double *__restrict__ nparts_prev, int n_nparts,
+                                                             double *__restrict__ nparts_out,
+                                                             double *__restrict__ dparts_out) {
+    __shared__ double inv_s, rn[PR_THREADS], rd[PR_THREADS];
+    if (threadIdx.x == 0) {
+        double nn = 0.0;
+        for (int i = 0; i < n_nparts; ++i) nn += nparts_prev[i];
+        inv_s = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
+    }
+    __syncthreads();
+    const int i = blockIdx.x * PR_THREADS + threadIdx.x;
+    double nn = 0.0, dot = 0.0;
+    if (i < n) {
+        double sum = 0.0;
+        for (int c = 0; c < nch; ++c) sum += part[(long long)c * n + i];
+        const float wf = (float)sum;
+        w_out[i] = wf;
+        const double v = (double)(float)((double)w_prev[i] * inv_s);
+        nn = (double)wf * (double)wf;
+        dot = v * (double)wf;
+    }
+    rn[threadIdx.x] = nn;
+    rd[threadIdx.x] = dot;
+    __syncthreads();
+    for (int o = PR_THREADS / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            rn[threadIdx.x] += rn[threadIdx.x + o];
+            rd[threadIdx.x] += rd[threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        nparts_out[blockIdx.x] = rn[0];
+        dparts_out[blockIdx.x] = rd[0];
+    }
+}
+
+// The starting vector's norm partials: nparts = (nn0, 0, ..., 0).
+__global__ void k_power_start(double *nparts, int nb, double nn0) {
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) nparts[i] = i == 0 ? nn0 : 0.0;
+}
+
+// lam = v . w of the last product (0 when w = 0).
+__global__ void k_power_final(const double *__restrict__ nparts, const double *__restrict__ dparts, int nb,
+                              double *lam) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double nn = 0.0, dot = 0.0;
+    for (int i = 0; i < nb; ++i) {
+        nn += nparts[i];
+        dot += dparts[i];
+    }
+    *lam = nn > 0.0 ? dot : 0.0;
 }
 
 __global__ void k_zero_f64(double *p, long long n) {
@@ -910,8 +1016,17 @@ hipError_t sur_expand_impl(int K, const double *Rl, const double *Es, unsigned s
 }
 
 template <int MM>
-hipError_t lag_matvec_impl(int K, const float *Rl, const float *v, double *part, hipStream_t s) {
-    hipLaunchKernelGGL(k_lag_matvec<MM>, dim3(K, (K + RM_KB - 1) / RM_KB), dim3(MM * RM_KB), 0, s, K, Rl, v, part);
+hipError_t lag_matvec_impl(int K, const float *Rf, const float *w, const double *nparts, int n_nparts, double *part,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(k_lag_matvec<MM>, dim3(K, (K + RM_KB - 1) / RM_KB), dim3(MM * RM_KB), 0, s, K, Rf, w, nparts,
+                       n_nparts, part);
+    return hipGetLastError();
+}
+
+template <int MM>
+hipError_t lag_to_f32_impl(int K, const double *Rl, float *Rf, hipStream_t s) {
+    constexpr int L = 2 * MM - 1, LL = L * L;
+    hipLaunchKernelGGL(k_lag_to_f32_t<MM>, dim3(K, (K + 31) / 32, (LL + 31) / 32), dim3(256), 0, s, K, Rl, Rf);
     return hipGetLastError();
 }
 
@@ -955,20 +1070,33 @@ hipError_t launch_surrogate_corner(const Geometry &g, int K, int m, Lists z, dou
 
 int lag_matvec_chunks(int K) { return (K + RM_KB - 1) / RM_KB; }
 
-__global__ void k_f64_to_f32(long long n, const double *__restrict__ src, float *__restrict__ dst) {
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
-        dst[i] = (float)src[i];
+hipError_t launch_lag_matvec(int K, int m, const float *Rf, const float *w, const double *nparts, int n_nparts,
+                             double *part, hipStream_t s) {
+    SCSC_DISPATCH_M(m, lag_matvec_impl, K, Rf, w, nparts, n_nparts, part, s);
 }
 
-hipError_t launch_f64_to_f32(long long n, const double *src, float *dst, hipStream_t s) {
-    long long b = (n + 255) / 256;
-    if (b > 8192) b = 8192;
-    hipLaunchKernelGGL(k_f64_to_f32, dim3((unsigned)(b < 1 ? 1 : b)), dim3(256), 0, s, n, src, dst);
+hipError_t launch_lag_to_f32(int K, int m, const double *Rl, float *Rf, hipStream_t s) {
+    SCSC_DISPATCH_M(m, lag_to_f32_impl, K, Rl, Rf, s);
+}
+
+int power_reduce_blocks(int n) { return (n + PR_THREADS - 1) / PR_THREADS; }
+
+hipError_t launch_power_reduce(const double *part, int nch, int n, float *w_out, const float *w_prev,
+                               const double *nparts_prev, int n_nparts, double *nparts_out, double *dparts_out,
+                               hipStream_t s) {
+    hipLaunchKernelGGL(k_power_reduce, dim3(power_reduce_blocks(n)), dim3(PR_THREADS), 0, s, part, nch, n, w_out,
+                       w_prev, nparts_prev, n_nparts, nparts_out, dparts_out);
     return hipGetLastError();
 }
 
-hipError_t launch_lag_matvec(int K, int m, const float *Rl, const float *v, double *part, hipStream_t s) {
-    SCSC_DISPATCH_M(m, lag_matvec_impl, K, Rl, v, part, s);
+hipError_t launch_power_start(double *nparts, int nb, double nn0, hipStream_t s) {
+    hipLaunchKernelGGL(k_power_start, dim3(1), dim3(256), 0, s, nparts, nb, nn0);
+    return hipGetLastError();
+}
+
+hipError_t launch_power_final(const double *nparts, const double *dparts, int nb, double *lam, hipStream_t s) {
+    hipLaunchKernelGGL(k_power_final, dim3(1), dim3(64), 0, s, nparts, dparts, nb, lam);
+    return hipGetLastError();
 }
 
 }  // namespace scsc

@@ -278,12 +278,23 @@ long long surrogate_lag_elems(int K, int m);
 long long surrogate_lag_part_elems(const Geometry &g, int K, int m);
 hipError_t launch_surrogate_lag(const Geometry &g, int K, int m, Lists z, double *part, double *Rl, double *Es,
                                 hipStream_t s);
-// Product of the zero-padded normal matrix (lag sums Rl) with v [K][m*m]:
-// part[lag_matvec_chunks(K)][K][m*m] FP64 partial sums.
+// Power iteration on the zero-padded normal matrix given by the lag sums.
+// Rf = the lag sums rounded to FP32 (a step-size estimate needs no more), in
+// [k][k2][lag] order (launch_lag_to_f32).  The matvec multiplies v = w / ||w||,
+// ||w||^2 = sum of nparts[0, n_nparts), and writes part[lag_matvec_chunks(K)][K][m*m]
+// FP64 partial sums; launch_power_reduce sums them into the next w (FP32) with
+// power_reduce_blocks(n) partials of ||w||^2 and v . w; launch_power_final sets
+// lam = v . w of the last product.
 int lag_matvec_chunks(int K);
-// Rl: the lag sums rounded to FP32 (a step-size estimate needs no more); FP64 accumulation.
-hipError_t launch_lag_matvec(int K, int m, const float *Rl, const float *v, double *part, hipStream_t s);
-hipError_t launch_f64_to_f32(long long n, const double *src, float *dst, hipStream_t s);
+hipError_t launch_lag_to_f32(int K, int m, const double *Rl, float *Rf, hipStream_t s);
+hipError_t launch_lag_matvec(int K, int m, const float *Rf, const float *w, const double *nparts, int n_nparts,
+                             double *part, hipStream_t s);
+int power_reduce_blocks(int n);
+hipError_t launch_power_reduce(const double *part, int nch, int n, float *w_out, const float *w_prev,
+                               const double *nparts_prev, int n_nparts, double *nparts_out, double *dparts_out,
+                               hipStream_t s);
+hipError_t launch_power_start(double *nparts, int nb, double nn0, hipStream_t s);
+hipError_t launch_power_final(const double *nparts, const double *dparts, int nb, double *lam, hipStream_t s);
 // C_bar += R - band terms for the stored blocks; with d non-null also y = C_bar d of
 // the updated C_bar (part: surrogate_matvec_partial_elems doubles).  The corner
 // correction must already be in C_bar.
