@@ -53,6 +53,7 @@ enum Slot {
     WS_SDA,
     WS_LAGPART,
     WS_PNORM,
+    WS_ADA,
     WS_COUNT
 };
 
@@ -725,11 +726,14 @@ extern "C" int csc_code_step(csc_handle h, const csc_images *im, const float *x,
             Wi = wc;
         }
     }
-    __bf16 *sda = nullptr;
+    __bf16 *sda = nullptr, *ada = nullptr;
     if (precision == CSC_BF16 && n_iter > 0) {
         WS(buf, __bf16, WS_SDA, synth_mfma_prep_elems(K));
         HIPCHK(launch_synth_mfma_prep(di, K, m, buf, h->stream));
         sda = buf;
+        WS(abuf, __bf16, WS_ADA, adj_prep_elems(K, m));
+        HIPCHK(launch_adj_prep(di, K, m, abuf, h->stream));
+        ada = abuf;
     }
     auto iterations = [&]() -> int {
         int c = 0;
@@ -743,7 +747,7 @@ extern "C" int csc_code_step(csc_handle h, const csc_images *im, const float *x,
                 PROF(CSC_PK_ADJOINT);
                 if (precision == CSC_BF16)
                     HIPCHK(launch_adjoint_shrink_mfma(g, K, m, mw, soff, pairs[c], nzc[c], pairs[c ^ 1], nzc[c ^ 1],
-                                                      R, di, ethr, nnzsum, h->stream));
+                                                      R, ada, ethr, nnzsum, h->stream));
                 else
                     HIPCHK(launch_adjoint_shrink(g, K, m, mw, soff, pairs[c], nzc[c], pairs[c ^ 1], nzc[c ^ 1], R,
                                                  di, ethr, nnzsum, h->stream));
@@ -758,7 +762,7 @@ extern "C" int csc_code_step(csc_handle h, const csc_images *im, const float *x,
             (uintptr_t)g.n_pix, (uintptr_t)(h->force_variant + 1), (uintptr_t)tuned_variant(h, synth_key(h, K, m, SYNTH_RESIDUAL, precision)),
             (uintptr_t)g.d_img, (uintptr_t)g.d_tiles, (uintptr_t)mw, (uintptr_t)soff, (uintptr_t)pairs[0],
             (uintptr_t)pairs[1], (uintptr_t)nzc[0], (uintptr_t)nzc[1], (uintptr_t)R, (uintptr_t)sc, (uintptr_t)xi,
-            (uintptr_t)di, (uintptr_t)Wi, (uintptr_t)sda};
+            (uintptr_t)di, (uintptr_t)Wi, (uintptr_t)sda, (uintptr_t)ada};
         // the null stream cannot be captured: use a private (default-priority) stream,
         // ordered after and before the handle's stream with events
         hipStream_t gs = h->stream;

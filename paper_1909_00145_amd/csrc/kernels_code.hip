@@ -583,11 +583,25 @@ __global__ __launch_bounds__(TPB) void k_adjoint_shrink(const ImgInfo *imgs, con
 // 16-pixel column tiles) and keeps their im2col fragments in registers; filters
 // are taken 32 at a time, their G written to LDS, and the same selected-set
 // epilogue as the FP32 kernel (u = z + eta g, shrink, new lists) reads it there.
+// The filters come prepared as dA[k][32 ceil(m^2 / 32)] (BF16, taps zero padded,
+// rows padded to a multiple of 32 with zeros), so every lane loads its operand
+// fragments directly, one chunk ahead.
 // Fragment layout of the 16x16x32 instruction (lane l, element i):
 //   A: row l % 16, k 8 (l / 16) + i;  B: k 8 (l / 16) + i, column l % 16;
 //   D: row 4 (l / 16) + i, column l % 16.
 // ---------------------------------------------------------------------------
 constexpr int MF_KB = 32;  // filters per chunk
+constexpr int MF_MW = 4;   // selection words kept in registers (K <= 128)
+
+template <int MM>
+__global__ void k_adj_prep_a(const float *__restrict__ d, int K, int Kp, __bf16 *__restrict__ dA) {
+    constexpr int M = MM * MM, MP = 32 * ((M + 31) / 32);
+    const long long n = (long long)Kp * MP;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const int k = (int)(i / MP), t = (int)(i % MP);
+        dA[i] = (k < K && t < M) ? (__bf16)d[(long long)k * M + t] : (__bf16)0.f;
+    }
+}
 
 template <int MM>
 __global__ __launch_bounds__(TPB) void k_adjoint_shrink_mfma(const ImgInfo *imgs, const TileInfo *tiles, int K,
@@ -597,12 +611,12 @@ __global__ __launch_bounds__(TPB) void k_adjoint_shrink_mfma(const ImgInfo *imgs
                                                              const unsigned short *__restrict__ oldc,
                                                              Pair *__restrict__ newp,
                                                              unsigned short *__restrict__ newc,
-                                                             const float *__restrict__ r, const float *__restrict__ d,
+                                                             const float *__restrict__ r,
+                                                             const __bf16 *__restrict__ dA,
                                                              const float *__restrict__ ethr,
                                                              unsigned long long *__restrict__ nnz_acc) {
     constexpr int C = MM / 2, RW = TS + 2 * C, M = MM * MM, NKS = (M + 31) / 32, MP = 32 * NKS;
     __shared__ __bf16 rb[RW * RW];
-    __shared__ bf16x8 db[MF_KB * MP / 8];  // [MF_KB][MP] filter chunk, taps zero padded
     __shared__ float gc[MF_KB][TPB];       // G of the chunk, [filter][tile pixel]
     __shared__ Pair op[ADJ_CAP];
     __shared__ int scratch[TPB];
@@ -645,35 +659,54 @@ __global__ __launch_bounds__(TPB) void k_adjoint_shrink_mfma(const ImgInfo *imgs
     int oi = 0;
     Pair oe = ocnt > 0 ? (staged ? op[ex] : oldp[base]) : Pair{INT_MAX, 0.f};
     int nn = 0;
+    // the pixel's first MF_MW selection words, loaded once
+    unsigned mwr[MF_MW];
+#pragma unroll
+    for (int w = 0; w < MF_MW; ++w) mwr[w] = (c.valid && 32 * w < K) ? mask_words[(long long)w * n_pix + c.gp] : 0u;
+    // operand A of a chunk: rows k0 + 16 rt + fcol, K-dim 32 ks + 8 (lane / 16)
+    const bf16x8 *dA8 = reinterpret_cast<const bf16x8 *>(dA) + (long long)fcol * (MP / 8) + (lane >> 4);
+    bf16x8 afr[2][NKS], afn[2][NKS];
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int ks = 0; ks < NKS; ++ks) afn[rt][ks] = dA8[(long long)(rt * 16) * (MP / 8) + ks * 4];
     for (int k0 = 0; k0 < K; k0 += MF_KB) {
         const int nk = min(MF_KB, K - k0);
-        __syncthreads();  // the previous chunk's epilogue is done with db and gc
-        for (int i = threadIdx.x; i < MF_KB * MP; i += TPB) {
-            const int kk = i / MP, t = i % MP;
-            reinterpret_cast<__bf16 *>(db)[i] = (kk < nk && t < M) ? (__bf16)d[(long long)(k0 + kk) * M + t] : (__bf16)0.f;
-        }
-        __syncthreads();
-        const int nrt = (nk + 15) >> 4;
-        for (int rt = 0; rt < nrt; ++rt) {
-            bf16x8 afr[NKS];
 #pragma unroll
-            for (int ks = 0; ks < NKS; ++ks) afr[ks] = db[(rt * 16 + fcol) * (MP / 8) + ks * 4 + (lane >> 4)];
+        for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
-            for (int ct = 0; ct < 4; ++ct) {
-                f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+            for (int ks = 0; ks < NKS; ++ks) afr[rt][ks] = afn[rt][ks];
+        if (k0 + MF_KB < K)  // the next chunk's operands load during this chunk
+#pragma unroll
+            for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
                 for (int ks = 0; ks < NKS; ++ks)
-                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr[ks], bfr[ct][ks], acc, 0, 0, 0);
-                const int px = (wave * 4 + ct) * TS + fcol;
+                    afn[rt][ks] = dA8[(long long)(k0 + MF_KB + rt * 16) * (MP / 8) + ks * 4];
+        __syncthreads();  // the previous chunk's epilogue is done with gc
 #pragma unroll
-                for (int i = 0; i < 4; ++i) gc[rt * 16 + (lane >> 4) * 4 + i][px] = acc[i];
+        for (int rt = 0; rt < 2; ++rt) {
+            if (rt * 16 < nk) {  // (a guard, not a break: the loop stays unrolled)
+#pragma unroll
+                for (int ct = 0; ct < 4; ++ct) {
+                    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int ks = 0; ks < NKS; ++ks)
+                        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr[rt][ks], bfr[ct][ks], acc, 0, 0, 0);
+                    const int px = (wave * 4 + ct) * TS + fcol;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) gc[rt * 16 + (lane >> 4) * 4 + i][px] = acc[i];
+                }
             }
         }
         __syncthreads();
         if (!c.valid) continue;
         const int k1 = k0 + nk;
         for (int w = k0 >> 5; w <= (k1 - 1) >> 5; ++w) {
-            unsigned bits = mask_words[(long long)w * n_pix + c.gp];
+            unsigned bits = 0u;
+#pragma unroll
+            for (int q = 0; q < MF_MW; ++q)
+                if (q == w) bits = mwr[q];
+            if (w >= MF_MW) bits = mask_words[(long long)w * n_pix + c.gp];
             const int lo = k0 - 32 * w, hi = k1 - 32 * w;
             if (lo > 0) bits &= ~0u << lo;
             if (hi < 32) bits &= (1u << hi) - 1u;
@@ -877,10 +910,19 @@ hipError_t adjoint_shrink_impl(const Geometry &g, int K, const unsigned *mw, con
 template <int MM>
 hipError_t adjoint_shrink_mfma_impl(const Geometry &g, int K, const unsigned *mw, const unsigned *soff,
                                     const Pair *oldp, const unsigned short *oldc, Pair *newp, unsigned short *newc,
-                                    const float *r, const float *d, const float *ethr,
+                                    const float *r, const __bf16 *dA, const float *ethr,
                                     unsigned long long *nnz_acc, hipStream_t s) {
     hipLaunchKernelGGL(k_adjoint_shrink_mfma<MM>, dim3(g.n_tiles), dim3(TPB), 0, s, g.d_img, g.d_tiles, K, g.n_pix,
-                       mw, soff, oldp, oldc, newp, newc, r, d, ethr, nnz_acc);
+                       mw, soff, oldp, oldc, newp, newc, r, dA, ethr, nnz_acc);
+    return hipGetLastError();
+}
+
+template <int MM>
+hipError_t adj_prep_impl(const float *d, int K, __bf16 *dA, hipStream_t s) {
+    constexpr int M = MM * MM, MP = 32 * ((M + 31) / 32);
+    const int Kp = (K + MF_KB - 1) / MF_KB * MF_KB;
+    const long long n = (long long)Kp * MP;
+    hipLaunchKernelGGL(k_adj_prep_a<MM>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, d, K, Kp, dA);
     return hipGetLastError();
 }
 
@@ -910,12 +952,20 @@ hipError_t launch_adjoint_shrink(const Geometry &g, int K, int m, const unsigned
                     ethr, nnz_acc, s);
 }
 
+size_t adj_prep_elems(int K, int m) {
+    return (size_t)((K + MF_KB - 1) / MF_KB * MF_KB) * (size_t)(32 * ((m * m + 31) / 32));
+}
+
+hipError_t launch_adj_prep(const float *d, int K, int m, __bf16 *dA, hipStream_t s) {
+    SCSC_DISPATCH_M(m, adj_prep_impl, d, K, dA, s);
+}
+
 hipError_t launch_adjoint_shrink_mfma(const Geometry &g, int K, int m, const unsigned *mask_words,
                                       const unsigned *soff, const Pair *old_pairs, const unsigned short *old_cnt,
-                                      Pair *new_pairs, unsigned short *new_cnt, const float *r, const float *d,
+                                      Pair *new_pairs, unsigned short *new_cnt, const float *r, const __bf16 *dA,
                                       const float *ethr, unsigned long long *nnz_acc, hipStream_t s) {
     SCSC_DISPATCH_M(m, adjoint_shrink_mfma_impl, g, K, mask_words, soff, old_pairs, old_cnt, new_pairs, new_cnt, r,
-                    d, ethr, nnz_acc, s);
+                    dA, ethr, nnz_acc, s);
 }
 
 hipError_t launch_adjoint_dense(const Geometry &g, int K, int m, const float *r, const float *d, float *out,

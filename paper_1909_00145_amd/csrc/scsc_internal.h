@@ -223,9 +223,12 @@ hipError_t launch_synth(const Geometry &g, int K, int m, Lists z, const float *d
                         const unsigned char *W, float *out, SynthMode mode, int variant, hipStream_t s);
 // One proximal-gradient iteration on the selected coordinates (FP32 VALU).
 // BF16 operands on the matrix cores, FP32 accumulation; same lists and epilogue.
+// The filters enter as dA, written by launch_adj_prep (adj_prep_elems(K, m) elements).
+size_t adj_prep_elems(int K, int m);
+hipError_t launch_adj_prep(const float *d, int K, int m, __bf16 *dA, hipStream_t s);
 hipError_t launch_adjoint_shrink_mfma(const Geometry &g, int K, int m, const unsigned *mask_words,
                                       const unsigned *soff, const Pair *old_pairs, const unsigned short *old_cnt,
-                                      Pair *new_pairs, unsigned short *new_cnt, const float *r, const float *d,
+                                      Pair *new_pairs, unsigned short *new_cnt, const float *r, const __bf16 *dA,
                                       const float *ethr, unsigned long long *nnz_acc, hipStream_t s);
 hipError_t launch_adjoint_shrink(const Geometry &g, int K, int m, const unsigned *mask_words,
                                  const unsigned *soff, const Pair *old_pairs, const unsigned short *old_cnt,
