@@ -33,27 +33,29 @@ if ROOT not in sys.path:
 
 PEAK_FP32_VECTOR = 157.3e12
 PEAK_FP64_VECTOR = 78.6e12
+PEAK_BF16_MFMA = 2.5e15
 PEAK_HBM = 8.0e12
 
 # HBM bytes per launch of each kernel class's main kernel on the online workload, from
 # rocprofv3 FETCH_SIZE / WRITE_SIZE passes scaled by a 512 MiB copy (read x 2.000, write x 1.000),
 # valid only for the kernel source they were taken on (first 16 hex digits of its SHA-256).
+# Keyed by (kernel class, precision).
 TRAFFIC = {
-    "synth": ("kernels_code.hip", "fd3c0a6613139af6", 18.12e6, 0.81e6),
-    "adjoint": ("kernels_code.hip", "fd3c0a6613139af6", 20.94e6, 10.64e6),
-    "corr": ("kernels_dict.hip", "e012d4f63c9433b4", 26.99e6, 4.07e6),
-    "sur_expand": ("kernels_sur.hip", "b615432a09d95e95", 912.31e6, 601.56e6),
-    "power": ("kernels_sur.hip", "b615432a09d95e95", 17.64e6, 0.69e6),
+    ("synth", "fp32"): ("kernels_code.hip", "fd3c0a6613139af6", 18.12e6, 0.81e6),
+    ("adjoint", "fp32"): ("kernels_code.hip", "fd3c0a6613139af6", 20.94e6, 10.64e6),
+    ("corr", "fp32"): ("kernels_dict.hip", "e012d4f63c9433b4", 26.99e6, 4.07e6),
+    ("sur_expand", "fp32"): ("kernels_sur.hip", "b615432a09d95e95", 912.31e6, 601.56e6),
+    ("power", "fp32"): ("kernels_sur.hip", "b615432a09d95e95", 17.64e6, 0.69e6),
 }
 
 
-def traffic_for(cls, workload):
+def traffic_for(cls, workload, precision):
     """Calibrated HBM bytes per launch, or None when the kernel changed since the counters were taken."""
     import hashlib
 
-    if workload != "online" or cls not in TRAFFIC:
+    if workload != "online" or (cls, precision) not in TRAFFIC:
         return None
-    src, sha, rd, wr = TRAFFIC[cls]
+    src, sha, rd, wr = TRAFFIC[(cls, precision)]
     path = os.path.join(ROOT, "paper_1909_00145_amd", "csrc", src)
     try:
         cur = hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
@@ -80,7 +82,11 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="online")
-    ap.add_argument("--precision", choices=["fp32", "bf16"], default="fp32")
+    ap.add_argument("--precision", choices=["fp32", "bf16"], default="bf16",
+                    help="bf16: MFMA operands in BF16 with FP32 accumulation (the configured path); "
+                         "fp32: plain FP32")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the timed run of the other precision (FP32 plain next to BF16)")
     ap.add_argument("--p", type=float, default=None, help="override the sampling rate")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -206,59 +212,69 @@ def main():
         im = Images(si.ragged_sizes(w["cfg"], w["N"], 64, 512))
     else:
         im = Images.uniform(w["N"], w["H"], w["W"])
-    d = torch.from_numpy(si.filters(w["cfg"], K, m).astype(np.float32)).cuda()
     total_steps = args.warmup + args.steps
     if args.workload == "online":
         xs = torch.from_numpy(np.stack([si.stream_batch(w["cfg"], t, w["N"], w["H"], w["W"]).astype(np.float32)
                                         .reshape(-1) for t in range(1, total_steps + 1)])).cuda()
-        learner = OnlineLearner(ctx, im, d, w["lam"], w["p"], n_code_iter=w["T"], precision=args.precision)
-
-        def step(i):
-            return learner.step(xs[i])
     elif args.workload == "ragged":
         x = torch.from_numpy(im.pack([si.field(w["cfg"], n, int(H), int(Wd)).astype(np.float32)
                                       for n, (H, Wd) in enumerate(im.hw)])).cuda()
-        z = torch.zeros(K * im.n_pix, dtype=torch.float32, device="cuda")
-        if args.graph:
-            ctx.set_graph(True)
-
-        def step(i):
-            st = ctx.code_step(im, x, d, z, w["lam"], w["p"], w["cfg"], i + 1, w["T"], precision=args.precision,
-                               stats=True)
-            return st, None
     else:
         x = torch.from_numpy(si.batch(w["cfg"], w["N"], w["H"], w["W"]).astype(np.float32).reshape(-1)).cuda()
-        learner = BatchLearner(ctx, im, x, d, w["lam"], w["p"], n_code_iter=w["T"], precision=args.precision)
+    if args.graph:
+        ctx.set_graph(True)
 
-        def step(i):
-            return learner.step()
+    def timed_run(precision):
+        """Warm-up and timed steps of the workload in one precision, from the initial filters."""
+        d = torch.from_numpy(si.filters(w["cfg"], K, m).astype(np.float32)).cuda()
+        if args.workload == "online":
+            learner = OnlineLearner(ctx, im, d, w["lam"], w["p"], n_code_iter=w["T"], precision=precision)
 
-    for i in range(args.warmup):
-        step(i)
-    torch.cuda.synchronize()
-    ctx.lib.csc_profile_enable(ctx.h, 1)
-    sampled = 0
-    nnz_iter = 0
-    nnz_dict = 0
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.warmup, total_steps):
-        st, _ = step(i)
-        sampled += st.sampled
-        nnz_iter += st.nnz_iter_sum
-        nnz_dict += st.nnz
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    kernels = {}
-    import ctypes as C
+            def step(i):
+                return learner.step(xs[i])
+        elif args.workload == "ragged":
+            z = torch.zeros(K * im.n_pix, dtype=torch.float32, device="cuda")
 
-    for ci, name in enumerate(_lib.KERNEL_CLASSES):
-        n = C.c_int64()
-        ms = C.c_double()
-        ctx.lib.csc_profile_read(ctx.h, ci, C.byref(n), C.byref(ms))
-        if n.value:
-            kernels[name] = {"launches": int(n.value), "avg_us": 1e3 * ms.value / n.value, "total_ms": ms.value}
-    ctx.lib.csc_profile_enable(ctx.h, 0)
+            def step(i):
+                st = ctx.code_step(im, x, d, z, w["lam"], w["p"], w["cfg"], i + 1, w["T"], precision=precision,
+                                   stats=True)
+                return st, None
+        else:
+            learner = BatchLearner(ctx, im, x, d, w["lam"], w["p"], n_code_iter=w["T"], precision=precision)
+
+            def step(i):
+                return learner.step()
+
+        for i in range(args.warmup):
+            step(i)
+        torch.cuda.synchronize()
+        ctx.lib.csc_profile_enable(ctx.h, 1)
+        r = {"sampled": 0, "nnz_iter": 0, "nnz_dict": 0}
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.warmup, total_steps):
+            st, _ = step(i)
+            r["sampled"] += st.sampled
+            r["nnz_iter"] += st.nnz_iter_sum
+            r["nnz_dict"] += st.nnz
+        torch.cuda.synchronize()
+        r["el"] = time.perf_counter() - t0
+        kernels = {}
+        import ctypes as C
+
+        for ci, name in enumerate(_lib.KERNEL_CLASSES):
+            n = C.c_int64()
+            ms = C.c_double()
+            ctx.lib.csc_profile_read(ctx.h, ci, C.byref(n), C.byref(ms))
+            if n.value:
+                kernels[name] = {"launches": int(n.value), "avg_us": 1e3 * ms.value / n.value, "total_ms": ms.value}
+        ctx.lib.csc_profile_enable(ctx.h, 0)
+        r["kernels"] = kernels
+        return r
+
+    res = timed_run(args.precision)
+    kernels, el = res["kernels"], res["el"]
+    sampled, nnz_iter, nnz_dict = res["sampled"], res["nnz_iter"], res["nnz_dict"]
 
     if args.copy_probe_mb > 0:
         nb = args.copy_probe_mb << 20
@@ -275,13 +291,16 @@ def main():
     c = m // 2
     L2 = (2 * m - 1) ** 2
     n_power = 20
+    bf16 = args.precision == "bf16"
+    mm_peak = PEAK_BF16_MFMA if bf16 else PEAK_FP32_VECTOR
+    mm_bound = "mfma" if bf16 else "alu"
     # Algorithmic work of every timed launch of a kernel class, summed over the timed steps.
     work = {
         # one dot product of M taps per selected coordinate, then u = z + eta g and the shrink
-        "adjoint": ("alu", (2 * M + 3) * sampled * w["T"], PEAK_FP32_VECTOR),
+        "adjoint": (mm_bound, (2 * M + 3) * sampled * w["T"], mm_peak),
         # M multiply-adds per non-zero code entering a synthesis
-        "synth": ("alu", 2 * M * nnz_iter, PEAK_FP32_VECTOR),
-        # M multiply-adds per non-zero code of one correlation (B_bar = Z^T x)
+        "synth": (mm_bound, 2 * M * nnz_iter, mm_peak),
+        # M multiply-adds per non-zero code of one correlation (B_bar = Z^T x, FP32 in both precisions)
         "corr": ("alu", 2 * M * nnz_dict, PEAK_FP32_VECTOR),
         # K^2 M^2 FP64 multiply-adds per product with the lag-sum normal matrix (20 per step)
         "power": ("alu64", 2.0 * K * K * M * M * n_power * args.steps, PEAK_FP64_VECTOR),
@@ -290,8 +309,14 @@ def main():
         # read-modify-write of the stored blocks (k <= k2) of C_bar plus their lag and band sums
         "sur_expand": ("hbm", (K * (K + 1) // 2) * (16.0 * M * M + 8.0 * L2 * (1 + 4 * c)) * args.steps, PEAK_HBM),
     }
+    # MFMA work the BF16 kernels execute per launch (dense tiles, padded shapes), 16x16x32 = 16384 flop
+    executed = {}
+    if bf16:
+        tiles = sum(((int(H) + 15) // 16) * ((int(Wd) + 15) // 16) for H, Wd in im.hw)
+        executed["synth"] = tiles * ((K + 7) // 8) * ((m + 3) // 4) * (16 + 2 * c) * 16384.0
+        executed["adjoint"] = tiles * ((K + 15) // 16) * 16 * ((M + 31) // 32) * 16384.0
     # a replayed graph runs the synthesis and adjoint launches of all iterations together
-    work["ista_graph"] = ("alu", work["adjoint"][1] + work["synth"][1], PEAK_FP32_VECTOR)
+    work["ista_graph"] = (mm_bound, work["adjoint"][1] + work["synth"][1], mm_peak)
     if args.workload == "ragged":
         # code steps only
         work = {k: work[k] for k in ("adjoint", "synth", "ista_graph")}
@@ -299,31 +324,39 @@ def main():
         # batch filter step: one residual synthesis and one gradient correlation; lag-sum power iteration
         work.pop("sur_mv")
         work.pop("sur_expand")
-        work["synth"] = ("alu", 2 * M * (nnz_iter + nnz_dict), PEAK_FP32_VECTOR)
+        work["synth"] = (mm_bound, 2 * M * (nnz_iter + nnz_dict), mm_peak)
     dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
     modelled = [k for k in kernels if k in work]
     pick = dom if dom in work else max(modelled, key=lambda k: kernels[k]["total_ms"])
-    bound, total_work, peak = work[pick]
-    avg_s = kernels[pick]["avg_us"] * 1e-6
-    per_launch = total_work / kernels[pick]["launches"]
-    if bound == "hbm":
-        roof = {"bound": "hbm", "achieved": per_launch / avg_s / 1e9, "peak": peak / 1e9, "unit": "GB/s"}
-    else:
-        roof = {"bound": "alu", "achieved": per_launch / avg_s / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s"}
-        if bound == "alu64":
-            roof["precision"] = "fp64"
-    roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = traffic_for(pick, args.workload)
-    roof["kernel"] = pick
-    roof["per_launch_work"] = per_launch
-    roof["avg_launch_us"] = kernels[pick]["avg_us"]
+
+    def roof_of(k):
+        bound, total_work, peak = work[k]
+        avg_s = kernels[k]["avg_us"] * 1e-6
+        per_launch = total_work / kernels[k]["launches"]
+        if bound == "hbm":
+            r = {"bound": "hbm", "achieved": per_launch / avg_s / 1e9, "peak": peak / 1e9, "unit": "GB/s"}
+        else:
+            r = {"bound": "alu" if bound == "alu64" else bound, "achieved": per_launch / avg_s / 1e12,
+                 "peak": peak / 1e12, "unit": "TFLOP/s"}
+            if bound == "alu64":
+                r["precision"] = "fp64"
+        r["frac"] = r["achieved"] / r["peak"]
+        r["traffic"] = traffic_for(k, args.workload, args.precision)
+        r["kernel"] = k
+        r["per_launch_work"] = per_launch
+        r["avg_launch_us"] = kernels[k]["avg_us"]
+        if k in executed and not args.graph:
+            r["executed_mfma_tflops"] = executed[k] / avg_s / 1e12
+            r["executed_mfma_frac"] = executed[k] / avg_s / PEAK_BF16_MFMA
+        return r
+
+    roof = roof_of(pick)
     if dom != pick:
         roof["dominant_unmodelled"] = dom
     others = {}
     for k in modelled:
-        b2, tw, pk = work[k]
-        ach = tw / kernels[k]["launches"] / (kernels[k]["avg_us"] * 1e-6)
-        others[k] = {"bound": b2, "frac": ach / pk, "traffic": traffic_for(k, args.workload)}
+        r = roof_of(k)
+        others[k] = {key: r[key] for key in ("bound", "frac", "traffic", "executed_mfma_frac") if key in r}
 
     out = {
         "metric": "sampled code-coord updates/sec",
@@ -347,6 +380,14 @@ def main():
         "kernels": kernels,
         "code_density": nnz_dict / (args.steps * K * im.n_pix),
     }
+    if not args.no_compare:
+        other = "fp32" if bf16 else "bf16"
+        r2 = timed_run(other)
+        out["fp32_plain" if other == "fp32" else "bf16"] = {
+            "value": r2["sampled"] * w["T"] / r2["el"], "unit": "updates/s",
+            "ms_per_step": 1e3 * r2["el"] / args.steps,
+            "code_density": r2["nnz_dict"] / (args.steps * K * im.n_pix),
+            "kernels_avg_us": {k: round(v["avg_us"], 1) for k, v in r2["kernels"].items()}}
     if args.tto:
         out["time_to_objective"] = time_to_objective(ctx, WORKLOADS["online"], args.tto_batches)
     if not args.no_cpu_baseline:
