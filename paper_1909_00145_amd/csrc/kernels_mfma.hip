@@ -134,6 +134,7 @@ hipError_t corr_mfma_impl(const Geometry &g, int K, Lists z, const float *r, flo
 // Operand A comes prepared as dA[r][group][u'][8 filters] (k_synth_prep_a).
 // ---------------------------------------------------------------------------
 constexpr int SM_CAP = 4096;  // code entries of a region staged in LDS
+constexpr int SM_LB = 4;      // list loads in flight per thread while staging
 
 template <int MM>
 constexpr int sm_steps() { return (MM + 3) / 4; }  // 4 tap columns per step
@@ -220,17 +221,32 @@ __global__ __launch_bounds__(TPB) void k_synth_mfma(const ImgInfo *imgs, const T
     const int total = block_exclusive_scan(ntot, &ebeg, wsum);
     const bool staged = total <= SM_CAP;  // uniform over the block
     if (staged) {
-        int e = ebeg;
+        // this thread's entries, flattened over its pixels, SM_LB loads in flight
+        for (int j0 = 0; j0 < ntot; j0 += SM_LB) {
+            Pair pr[SM_LB];
+            unsigned pix[SM_LB];
 #pragma unroll
-        for (int q = 0; q < NPT; ++q) {
-            const unsigned pix = threadIdx.x + q * TPB;
-#pragma unroll 4
-            for (int j = 0; j < pn[q]; ++j) {
-                const Pair pr = zl.pairs[po[q] + j];
-                skey[e + j] = ((unsigned)pr.k << 10) | pix;
-                sval[e + j] = (__bf16)pr.v;
+            for (int u = 0; u < SM_LB; ++u) {
+                int jj = j0 + u, q = 0;
+#pragma unroll
+                for (int qq = 0; qq < NPT - 1; ++qq)
+                    if (q == qq && jj >= pn[qq]) {
+                        jj -= pn[qq];
+                        q = qq + 1;
+                    }
+                unsigned o = po[0];
+#pragma unroll
+                for (int qq = 1; qq < NPT; ++qq)
+                    if (q == qq) o = po[qq];
+                pix[u] = threadIdx.x + q * TPB;
+                if (j0 + u < ntot) pr[u] = zl.pairs[o + jj];
             }
-            e += pn[q];
+#pragma unroll
+            for (int u = 0; u < SM_LB; ++u)
+                if (j0 + u < ntot) {
+                    skey[ebeg + j0 + u] = ((unsigned)pr[u].k << 10) | pix[u];
+                    sval[ebeg + j0 + u] = (__bf16)pr[u].v;
+                }
         }
     }
 
@@ -251,12 +267,24 @@ __global__ __launch_bounds__(TPB) void k_synth_mfma(const ImgInfo *imgs, const T
         __syncthreads();
         const unsigned k0 = 8 * g0, k1 = min(K, 8 * (g0 + ng));
         if (staged) {
-            for (int e = ebeg; e < ebeg + ntot; ++e) {
-                const unsigned key = skey[e], k = key >> 10;
-                if (k >= k0 && k < k1) {
-                    const unsigned kl = k - k0, pix = key & 1023u;
-                    const unsigned yr = pix / RW, xr = pix % RW;
-                    zt[(((kl >> 3) * RW + yr) * ZC + xr) * 8 + (kl & 7)] = sval[e];
+            // all staged entries of the region, strided over the block (balanced), 4 at a time
+            for (int e0 = threadIdx.x; e0 < total; e0 += 4 * TPB) {
+                unsigned key[4];
+                __bf16 val[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int e = e0 + u * TPB;
+                    key[u] = e < total ? skey[e] : 0xffffffffu;
+                    val[u] = e < total ? sval[e] : (__bf16)0.f;
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const unsigned k = key[u] >> 10;
+                    if (k >= k0 && k < k1) {
+                        const unsigned kl = k - k0, pix = key[u] & 1023u;
+                        const unsigned yr = pix / RW, xr = pix % RW;
+                        zt[(((kl >> 3) * RW + yr) * ZC + xr) * 8 + (kl & 7)] = val[u];
+                    }
                 }
             }
         } else {
