@@ -681,8 +681,10 @@ __global__ __launch_bounds__(EX_THREADS) void k_sur_expand(int K, const double *
     __shared__ double r[LL];
     __shared__ double ec[4][NC][LL];  // band prefix sums: ec[side][a][delta] = sum_{j <= a} E_side,j(delta)
     __shared__ double ya[M], yb[M], dka[M], dkb[M];
-    // decode the upper-triangle block index into (k, k2)
-    const long long bi = blockIdx.x;
+    // decode the upper-triangle block index into (k, k2); neighbouring blocks
+    // (which read neighbouring lag and band sums) share an XCD
+    const long long bi = xcd_item(tri_block(K, K, K));
+    if (bi < 0) return;
     int k = 0;
     while (tri_block(k + 1, k + 1, K) <= bi) ++k;
     const int k2 = k + (int)(bi - tri_block(k, k, K));
@@ -1006,7 +1008,7 @@ hipError_t sur_expand_impl(int K, const double *Rl, const double *Es, unsigned s
     hipLaunchKernelGGL(k_lag_table<MM>, dim3((LL + 63) / 64), dim3(64), 0, s, tab);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_sur_expand<MM>, dim3((unsigned)tri_block(K, K, K)), dim3(EX_THREADS), 0, s, K, Rl, Es, tab,
+    hipLaunchKernelGGL(k_sur_expand<MM>, dim3(xcd_grid(tri_block(K, K, K))), dim3(EX_THREADS), 0, s, K, Rl, Es, tab,
                        C, d, part);
     if (d) {
         if ((e = hipGetLastError()) != hipSuccess) return e;

@@ -133,6 +133,16 @@ __host__ __device__ __forceinline__ long long tri_block(int k, int k2, int K) {
 // neighbouring tiles, which share halo data, are then served by the same L2.
 // Items first, first + step, ... below end belong to this workgroup.
 constexpr int N_XCD = 8;
+
+// One item per workgroup, grid = xcd_grid(n): workgroup b (on XCD b % 8) takes item
+// (b % 8) * (grid / 8) + b / 8, so each XCD's L2 serves a contiguous range of
+// items; returns -1 for the padding workgroups.
+inline unsigned xcd_grid(long long n) { return (unsigned)((n + N_XCD - 1) / N_XCD * N_XCD); }
+__device__ __forceinline__ long long xcd_item(long long n) {
+    const long long per = gridDim.x / N_XCD;
+    const long long item = (long long)(blockIdx.x % N_XCD) * per + blockIdx.x / N_XCD;
+    return item < n ? item : -1;
+}
 __device__ __forceinline__ void xcd_work(long long total, long long &first, long long &step, long long &end) {
     const int G = gridDim.x;
     if (G < N_XCD || G % N_XCD) {
