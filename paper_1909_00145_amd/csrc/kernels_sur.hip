@@ -363,7 +363,7 @@ constexpr int LO_THREADS = 1024;
 constexpr int LO_U = 8;  // list entries per pixel held in registers
 
 template <int MM>
-__global__ __launch_bounds__(LO_THREADS) void k_lag_outer(const ImgInfo *imgs, int n_img, long long n_pix,
+__global__ __launch_bounds__(LO_THREADS, 8) void k_lag_outer(const ImgInfo *imgs, int n_img, long long n_pix,
                                                           int max_side, int K, Lists zl, int band, int KC,
                                                           double *__restrict__ out) {
     constexpr int C = MM / 2, L = 2 * MM - 1, LL = L * L;
@@ -398,11 +398,18 @@ __global__ __launch_bounds__(LO_THREADS) void k_lag_outer(const ImgInfo *imgs, i
                     im = imgs[++n];
                     iend = im.pix_off + (long long)im.H * im.W;
                 }
-                const long long pi = t - im.pix_off;
-                y = (int)(pi / im.W);
-                x = (int)(pi % im.W);
+                const unsigned pi = (unsigned)(t - im.pix_off);  // < 2^31
+                y = (int)(pi / (unsigned)im.W);
+                x = (int)(pi - (unsigned)y * (unsigned)im.W);
             } else {
-                const int nn = (int)(t / max_side), pos = (int)(t % max_side);
+                int nn, pos;
+                if (phi < (1LL << 31)) {  // uniform: 32-bit division
+                    nn = (int)((unsigned)t / (unsigned)max_side);
+                    pos = (int)((unsigned)t - (unsigned)nn * (unsigned)max_side);
+                } else {
+                    nn = (int)(t / max_side);
+                    pos = (int)(t % max_side);
+                }
                 if (nn != n || t == threadIdx.x) {
                     n = nn;
                     im = imgs[n];
@@ -511,7 +518,7 @@ __global__ __launch_bounds__(256) void k_lag_sum(int K, int n_chunks, const doub
 // in registers and reads each lag row once per s2_y; the partner filters are then
 // summed in a fixed order.
 constexpr int RM_KB = 16;
-constexpr int RM_LB = 8;  // loads in flight per thread
+constexpr int RM_LB = 48;  // loads in flight per thread (RM_KB LL / threads for m = 11: one round trip)
 
 template <int MM>
 __global__ __launch_bounds__(MM *RM_KB) void k_lag_matvec(int K, const float *__restrict__ Rf,
@@ -558,13 +565,13 @@ __global__ __launch_bounds__(MM *RM_KB) void k_lag_matvec(int K, const float *__
             const float *rrow = &r[j * LL + (sy - s2y + 2 * C) * L];  // lags (dy, dx = sx - s2x + 2c)
             const double *vrow = &vv[j][s2y * MM];
             double rv[L], vx[MM];
-#pragma unroll
+#pragma clang loop unroll(full)
             for (int i = 0; i < L; ++i) rv[i] = (double)rrow[i];
-#pragma unroll
+#pragma clang loop unroll(full)
             for (int i = 0; i < MM; ++i) vx[i] = vrow[i];
-#pragma unroll
+#pragma clang loop unroll(full)
             for (int sx = 0; sx < MM; ++sx)
-#pragma unroll
+#pragma clang loop unroll(full)
                 for (int s2x = 0; s2x < MM; ++s2x) acc[sx] = fma(rv[sx - s2x + 2 * C], vx[s2x], acc[sx]);
         }
     }
