@@ -95,7 +95,8 @@ def parse():
     ap.add_argument("--p", type=float, default=None, help="override the sampling rate")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--graph", action="store_true", help="replay the code step's iterations from a HIP graph")
+    ap.add_argument("--eager", action="store_true",
+                    help="launch the code step's iterations one by one instead of replaying them from a HIP graph")
     ap.add_argument("--tto", action="store_true",
                     help="also measure time-to-objective of online learning, FP32 against BF16 (adds ~1 min)")
     ap.add_argument("--tto-batches", type=int, default=100, help="mini-batches of the time-to-objective run")
@@ -226,11 +227,13 @@ def main():
                                       for n, (H, Wd) in enumerate(im.hw)])).cuda()
     else:
         x = torch.from_numpy(si.batch(w["cfg"], w["N"], w["H"], w["W"]).astype(np.float32).reshape(-1)).cuda()
-    if args.graph:
-        ctx.set_graph(True)
+    def timed_run(precision, graph, profile):
+        """Warm-up and timed steps of the workload in one precision, from the initial filters.
 
-    def timed_run(precision):
-        """Warm-up and timed steps of the workload in one precision, from the initial filters."""
+        graph: replay the code step's iterations from a HIP graph; profile: time every
+        kernel class with HIP events on the library's stream (which needs eager launches
+        to attribute the code step's kernels)."""
+        ctx.set_graph(graph)
         d = torch.from_numpy(si.filters(w["cfg"], K, m).astype(np.float32)).cuda()
         if args.workload == "online":
             learner = OnlineLearner(ctx, im, d, w["lam"], w["p"], n_code_iter=w["T"], precision=precision)
@@ -253,7 +256,7 @@ def main():
         for i in range(args.warmup):
             step(i)
         torch.cuda.synchronize()
-        ctx.lib.csc_profile_enable(ctx.h, 1)
+        ctx.lib.csc_profile_enable(ctx.h, 1 if profile else 0)
         r = {"sampled": 0, "nnz_iter": 0, "nnz_dict": 0}
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -277,9 +280,16 @@ def main():
         r["kernels"] = kernels
         return r
 
-    res = timed_run(args.precision)
-    kernels, el = res["kernels"], res["el"]
+    graph = not args.eager
+    # the headline run (no event timing), then the same steps eagerly with every kernel
+    # class timed by HIP events, for the per-kernel figures and the roofline
+    res = timed_run(args.precision, graph, False)
+    el = res["el"]
     sampled, nnz_iter, nnz_dict = res["sampled"], res["nnz_iter"], res["nnz_dict"]
+    prof = timed_run(args.precision, False, True)
+    kernels = prof["kernels"]
+    if (prof["sampled"], prof["nnz_iter"], prof["nnz_dict"]) != (sampled, nnz_iter, nnz_dict):
+        raise RuntimeError("the profiled pass did not repeat the headline run's work")
 
     if args.copy_probe_mb > 0:
         nb = args.copy_probe_mb << 20
@@ -320,11 +330,9 @@ def main():
         tiles = sum(((int(H) + 15) // 16) * ((int(Wd) + 15) // 16) for H, Wd in im.hw)
         executed["synth"] = tiles * ((K + 7) // 8) * ((m + 3) // 4) * (16 + 2 * c) * 16384.0
         executed["adjoint"] = tiles * ((K + 15) // 16) * 16 * ((M + 31) // 32) * 16384.0
-    # a replayed graph runs the synthesis and adjoint launches of all iterations together
-    work["ista_graph"] = (mm_bound, work["adjoint"][1] + work["synth"][1], mm_peak)
     if args.workload == "ragged":
         # code steps only
-        work = {k: work[k] for k in ("adjoint", "synth", "ista_graph")}
+        work = {k: work[k] for k in ("adjoint", "synth")}
     elif args.workload != "online":
         # batch filter step: one residual synthesis and one gradient correlation; lag-sum power iteration
         work.pop("sur_mv")
@@ -350,7 +358,7 @@ def main():
         r["kernel"] = k
         r["per_launch_work"] = per_launch
         r["avg_launch_us"] = kernels[k]["avg_us"]
-        if k in executed and not args.graph:
+        if k in executed:
             r["executed_mfma_tflops"] = executed[k] / avg_s / 1e12
             r["executed_mfma_frac"] = executed[k] / avg_s / PEAK_BF16_MFMA
         return r
@@ -377,22 +385,25 @@ def main():
         "dtype": args.precision,
         "data": "synthetic",
         "config": {"workload": w["name"], "images_per_step": w["N"], "height": w["H"], "width": w["W"],
-                   "pixels_per_step": im.n_pix, "graph": bool(args.graph),
+                   "pixels_per_step": im.n_pix, "graph": graph,
                    "K": K, "filter": m, "p": w["p"], "lambda": w["lam"], "ista_iters": w["T"],
                    "precision": args.precision},
         "roofline": roof,
         "roofline_all": others,
         "kernels": kernels,
+        "kernels_note": "per-class HIP-event averages from an eager pass of the same steps (%.2f ms per step "
+                        "with the events)" % (1e3 * prof["el"] / args.steps),
         "code_density": nnz_dict / (args.steps * K * im.n_pix),
     }
     if not args.no_compare:
         other = "fp32" if bf16 else "bf16"
-        r2 = timed_run(other)
+        r2 = timed_run(other, graph, False)
+        p2 = timed_run(other, False, True)
         out["fp32_plain" if other == "fp32" else "bf16"] = {
             "value": r2["sampled"] * w["T"] / r2["el"], "unit": "updates/s",
             "ms_per_step": 1e3 * r2["el"] / args.steps,
             "code_density": r2["nnz_dict"] / (args.steps * K * im.n_pix),
-            "kernels_avg_us": {k: round(v["avg_us"], 1) for k, v in r2["kernels"].items()}}
+            "kernels_avg_us": {k: round(v["avg_us"], 1) for k, v in p2["kernels"].items()}}
     if args.tto:
         out["time_to_objective"] = time_to_objective(ctx, WORKLOADS["online"], args.tto_batches)
     if not args.no_cpu_baseline:

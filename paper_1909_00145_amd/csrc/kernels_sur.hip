@@ -675,7 +675,7 @@ __global__ void k_zero_f64(double *p, long long n) {
 // k <= k2 (one workgroup per block, blockIdx.x = its upper-triangle index).
 // Each workgroup reads and writes its own block with coalesced accesses.
 constexpr int EX_THREADS = 512;
-constexpr int EX_BATCH = 8;
+constexpr int EX_BATCH = 16;
 
 template <int MM>
 __global__ __launch_bounds__(EX_THREADS) void k_sur_expand(int K, const double *__restrict__ Rl,
