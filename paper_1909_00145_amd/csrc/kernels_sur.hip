@@ -31,32 +31,69 @@ __host__ __device__ __forceinline__ int lagp(int a, int m) {
 
 // ---- per-filter row lists ---------------------------------------------------
 // fm_cnt[k * R + r] = number of non-zero codes of filter k in global row r.
-__global__ __launch_bounds__(256) void k_fm_count(const ImgInfo *imgs, const int *row_img, Lists zl, int R,
+__global__ __launch_bounds__(256) void k_fm_count(const ImgInfo *imgs, const int *row_img, Lists zl, int R, int K,
                                                   unsigned *fm_cnt) {
+    extern __shared__ unsigned cntk[];  // [K]
     const int r = blockIdx.x;
     const ImgInfo im = imgs[row_img[r]];
     const int y = r - im.row_off;
     const long long gp0 = im.pix_off + (long long)y * im.W;
+    for (int k = threadIdx.x; k < K; k += 256) cntk[k] = 0u;
+    __syncthreads();
     for (int x = threadIdx.x; x < im.W; x += 256) {
         const long long gp = gp0 + x;
         const unsigned o = zl.off[gp];
         const int n = zl.cnt[gp];
-        for (int j = 0; j < n; ++j) atomicAdd(&fm_cnt[(long long)zl.pairs[o + j].k * R + r], 1u);
+        for (int j = 0; j < n; ++j) atomicAdd(&cntk[zl.pairs[o + j].k], 1u);
     }
+    __syncthreads();
+    for (int k = threadIdx.x; k < K; k += 256) fm_cnt[(long long)k * R + r] = cntk[k];
 }
 
 constexpr int FM_CAP = 4096;
+constexpr int FM_BM_BYTES = 48 * 1024;  // LDS for the per-filter occupancy bitmaps of one row
 
 // Row r's entries, regrouped by filter in x order: fm[fm_off[k * R + r] + j] = (y << 16 | x, v).
-// Requires the pixel lists of the row to be contiguous (exact-capacity lists).
+// With bitmaps (nww 64-bit words per filter, nww > 0): bit x of filter k's bitmap
+// marks pixel x holding a code of k, and an entry's slot is the number of set
+// bits below x (its rank among the row's codes of k in x order).  Otherwise each
+// filter scans the row's entries.  Requires the pixel lists of the row to be
+// contiguous (exact-capacity lists).
 __global__ __launch_bounds__(256) void k_fm_fill(const ImgInfo *imgs, const int *row_img, Lists zl, int R, int K,
-                                                 const unsigned *fm_off, FmCode *fm) {
+                                                 int nww, const unsigned *fm_off, FmCode *fm) {
+    extern __shared__ unsigned long long bm[];  // [K][nww] when nww > 0
     __shared__ Pair ent[FM_CAP];
     __shared__ unsigned short ex[FM_CAP];
     const int r = blockIdx.x;
-    const ImgInfo im = imgs[row_img[r]];
+    const int img = row_img[r];
+    const ImgInfo im = imgs[img];
     const int y = r - im.row_off;
     const long long gp0 = im.pix_off + (long long)y * im.W;
+    if (nww > 0) {
+        for (int i = threadIdx.x; i < K * nww; i += 256) bm[i] = 0ull;
+        __syncthreads();
+        for (int x = threadIdx.x; x < im.W; x += 256) {
+            const long long gp = gp0 + x;
+            const unsigned o = zl.off[gp];
+            const int n = zl.cnt[gp];
+            for (int j = 0; j < n; ++j)
+                atomicOr(&bm[(long long)zl.pairs[o + j].k * nww + (x >> 6)], 1ull << (x & 63));
+        }
+        __syncthreads();
+        for (int x = threadIdx.x; x < im.W; x += 256) {
+            const long long gp = gp0 + x;
+            const unsigned o = zl.off[gp];
+            const int n = zl.cnt[gp];
+            for (int j = 0; j < n; ++j) {
+                const Pair p = zl.pairs[o + j];
+                const unsigned long long *row = bm + (long long)p.k * nww;
+                unsigned rank = __popcll(row[x >> 6] & ((1ull << (x & 63)) - 1ull));
+                for (int w = 0; w < (x >> 6); ++w) rank += __popcll(row[w]);
+                fm[fm_off[(long long)p.k * R + r] + rank] = FmCode{((unsigned)y << 16) | (unsigned)x, p.v, img, 0};
+            }
+        }
+        return;
+    }
     const unsigned base = zl.off[gp0];
     const unsigned total = zl.off[gp0 + im.W] - base;
     const bool staged = total <= FM_CAP;
@@ -77,7 +114,7 @@ __global__ __launch_bounds__(256) void k_fm_fill(const ImgInfo *imgs, const int 
         if (staged) {
             for (unsigned e = 0; e < total; ++e) {
                 const Pair p = ent[e];
-                if (p.k == k) fm[w++] = FmCode{((unsigned)y << 16) | ex[e], p.v, row_img[r], 0};
+                if (p.k == k) fm[w++] = FmCode{((unsigned)y << 16) | ex[e], p.v, img, 0};
             }
         } else {
             for (int x = 0; x < im.W; ++x) {
@@ -86,7 +123,7 @@ __global__ __launch_bounds__(256) void k_fm_fill(const ImgInfo *imgs, const int 
                 const int n = zl.cnt[gp];
                 for (int j = 0; j < n; ++j) {
                     const Pair p = zl.pairs[o + j];
-                    if (p.k == k) fm[w++] = FmCode{((unsigned)y << 16) | (unsigned)x, p.v, row_img[r], 0};
+                    if (p.k == k) fm[w++] = FmCode{((unsigned)y << 16) | (unsigned)x, p.v, img, 0};
                 }
             }
         }
@@ -926,12 +963,17 @@ hipError_t sur_mv_impl(int K, const double *C, const float *d, double *part, dou
 hipError_t launch_fm_lists(const Geometry &g, int K, Lists z, unsigned *fm_cnt, unsigned *fm_off, FmCode *fm,
                            unsigned long long *scan_tmp, unsigned long long *total64, hipStream_t s) {
     const int R = g.n_rows;
-    hipError_t e = hipMemsetAsync(fm_cnt, 0, sizeof(unsigned) * (size_t)K * R, s);
+    hipLaunchKernelGGL(k_fm_count, dim3(R), dim3(256), sizeof(unsigned) * (size_t)K, s, g.d_img, g.d_row_img, z, R,
+                       K, fm_cnt);
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_fm_count, dim3(R), dim3(256), 0, s, g.d_img, g.d_row_img, z, R, fm_cnt);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = launch_scan(fm_cnt, fm_off, (long long)K * R, scan_tmp, total64, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_fm_fill, dim3(R), dim3(256), 0, s, g.d_img, g.d_row_img, z, R, K, fm_off, fm);
+    // bitmaps of the widest row when they fit, else the scanning fallback
+    const int nww = (g.max_side + 63) / 64;
+    const size_t bm_bytes = sizeof(unsigned long long) * (size_t)K * nww;
+    const bool use_bm = bm_bytes <= (size_t)FM_BM_BYTES;
+    hipLaunchKernelGGL(k_fm_fill, dim3(R), dim3(256), use_bm ? bm_bytes : 0, s, g.d_img, g.d_row_img, z, R, K,
+                       use_bm ? nww : 0, fm_off, fm);
     return hipGetLastError();
 }
 

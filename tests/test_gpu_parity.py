@@ -241,10 +241,14 @@ def sparse_codes(hw, K, density, seed):
     return [f32(rng.standard_normal((K, H, W)) * (rng.random((K, H, W)) < density)) for H, W in hw]
 
 
+# (20, 150): filter-major lists with several bitmap words per row; (3, 2000) with
+# K = 200: bitmaps too large for LDS, so the lists take the scanning fallback
 @pytest.mark.parametrize("hw,K,m,n_iter,with_W", [
     ([(64, 64)], 16, 11, 1, False),
     ([(37, 53), (20, 17)], 10, 5, 3, True),
     ([(40, 40)], 100, 11, 1, False),
+    ([(20, 150), (9, 70)], 12, 5, 1, True),
+    ([(3, 2000)], 200, 3, 1, False),
 ])
 def test_dict_step_batch(ctx, hw, K, m, n_iter, with_W):
     say("dict batch", hw, K, m)
