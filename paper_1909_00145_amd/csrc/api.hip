@@ -95,11 +95,12 @@ struct csc_ctx {
     std::vector<Rec> recs;
     long long prof_launches[CSC_PK_COUNT] = {};
     double prof_ms[CSC_PK_COUNT] = {};
-    // graph replay of the proximal-gradient iterations (csc_set_graph)
+    // graph replay (csc_set_graph) of the proximal-gradient iterations (slot 0) and of
+    // the power iteration on the lag sums (slot 1)
     bool graphs = false;
     bool capturing = false;
-    std::vector<uintptr_t> graph_key;
-    hipGraphExec_t graph_exec = nullptr;
+    std::vector<uintptr_t> graph_key[2];
+    hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
     hipStream_t graph_stream = nullptr;  // capture / replay stream when the handle's stream is the null stream
     hipEvent_t graph_ev[2] = {nullptr, nullptr};
     // autotuner: launch variant per (kernel, m, K, log2 pixel count, mode)
@@ -287,6 +288,59 @@ hipError_t synth(csc_ctx *h, int K, int m, Lists L, const float *d, const float 
     return tuned_launch(
         h, synth_key(h, K, m, mode), 4,
         [&](int v) { return launch_synth(g, K, m, L, d, x, W, out, mode, v, h->stream); }, representative);
+}
+
+// Capture `body` (kernel launches only) into graph slot `slot` the first time `key`
+// is seen, then replay it on the handle's stream.  The null stream cannot be
+// captured: a private (default-priority) stream is used instead, ordered after
+// and before the handle's stream with events.
+int graph_replay(csc_ctx *h, int slot, const std::vector<uintptr_t> &key, const std::function<int()> &body) {
+    hipStream_t gs = h->stream;
+    if (gs == nullptr) {
+        if (!h->graph_stream) {
+            HIPCHK(hipStreamCreateWithFlags(&h->graph_stream, hipStreamNonBlocking));
+            HIPCHK(hipEventCreateWithFlags(&h->graph_ev[0], hipEventDisableTiming));
+            HIPCHK(hipEventCreateWithFlags(&h->graph_ev[1], hipEventDisableTiming));
+        }
+        gs = h->graph_stream;
+    }
+    hipGraphExec_t &ge = h->graph_exec[slot];
+    if (!ge || key != h->graph_key[slot]) {
+        if (ge) {
+            HIPCHK(hipStreamSynchronize(gs));
+            hipGraphExecDestroy(ge);
+            ge = nullptr;
+        }
+        hipStream_t saved = h->stream;
+        HIPCHK(hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal));
+        h->stream = gs;
+        h->capturing = true;
+        const int cst = body();
+        h->capturing = false;
+        h->stream = saved;
+        hipGraph_t graph = nullptr;
+        const hipError_t ce = hipStreamEndCapture(gs, &graph);
+        if (cst) {
+            if (graph) hipGraphDestroy(graph);
+            return cst;
+        }
+        HIPCHK(ce);
+        const hipError_t ie = hipGraphInstantiate(&ge, graph, nullptr, nullptr, 0);
+        hipGraphDestroy(graph);
+        HIPCHK(ie);
+        h->graph_key[slot] = key;
+    }
+    PROF(CSC_PK_GRAPH);
+    if (gs != h->stream) {
+        HIPCHK(hipEventRecord(h->graph_ev[0], h->stream));
+        HIPCHK(hipStreamWaitEvent(gs, h->graph_ev[0], 0));
+        HIPCHK(hipGraphLaunch(ge, gs));
+        HIPCHK(hipEventRecord(h->graph_ev[1], gs));
+        HIPCHK(hipStreamWaitEvent(h->stream, h->graph_ev[1], 0));
+    } else {
+        HIPCHK(hipGraphLaunch(ge, gs));
+    }
+    return CSC_OK;
 }
 
 // Device workspace of at least `bytes` (contents undefined).  Growing frees the
@@ -544,15 +598,28 @@ int power_iteration_lag(csc_ctx *h, int K, int m, const double *Rl, int n_power)
     HIPCHK(launch_fill(wa, n, 1.0f, h->stream));
     HIPCHK(launch_power_start(na, nb, (double)n, h->stream));
     HIPCHK(hipMemsetAsync(sc + SC_LAM, 0, sizeof(double), h->stream));
-    for (int it = 0; it < n_power; ++it) {
-        PROF(CSC_PK_POWER);
-        HIPCHK(launch_lag_matvec(K, m, Rf, wa, na, nb, part, h->stream));
-        HIPCHK(launch_power_reduce(part, nch, n, wb, wa, na, nb, nbp, dp, h->stream));
-        std::swap(wa, wb);
-        std::swap(na, nbp);
+    // the products only launch kernels (their vectors and norms live on the device),
+    // so the same launches can be replayed as a graph
+    auto products = [&]() -> int {
+        float *a = wa, *b = wb;
+        double *p = na, *q = nbp;
+        for (int it = 0; it < n_power; ++it) {
+            PROF(CSC_PK_POWER);
+            HIPCHK(launch_lag_matvec(K, m, Rf, a, p, nb, part, h->stream));
+            HIPCHK(launch_power_reduce(part, nch, n, b, a, p, nb, q, dp, h->stream));
+            std::swap(a, b);
+            std::swap(p, q);
+        }
+        if (n_power > 0) HIPCHK(launch_power_final(p, dp, nb, sc + SC_LAM, h->stream));
+        return CSC_OK;
+    };
+    if (h->graphs && n_power > 0) {
+        const std::vector<uintptr_t> key = {(uintptr_t)K, (uintptr_t)m, (uintptr_t)n_power, (uintptr_t)Rf,
+                                            (uintptr_t)wa, (uintptr_t)wb, (uintptr_t)part, (uintptr_t)np,
+                                            (uintptr_t)sc};
+        return graph_replay(h, 1, key, products);
     }
-    if (n_power > 0) HIPCHK(launch_power_final(na, dp, nb, sc + SC_LAM, h->stream));
-    return CSC_OK;
+    return products();
 }
 
 }  // namespace
@@ -589,7 +656,8 @@ extern "C" int csc_destroy(csc_handle h) {
     hipSetDevice(h->device);
     hipStreamSynchronize(h->stream);
     fold_records(h);
-    if (h->graph_exec) hipGraphExecDestroy(h->graph_exec);
+    for (auto &ge : h->graph_exec)
+        if (ge) hipGraphExecDestroy(ge);
     if (h->graph_stream) {
         hipStreamSynchronize(h->graph_stream);
         hipStreamDestroy(h->graph_stream);
@@ -763,52 +831,7 @@ extern "C" int csc_code_step(csc_handle h, const csc_images *im, const float *x,
             (uintptr_t)g.d_img, (uintptr_t)g.d_tiles, (uintptr_t)mw, (uintptr_t)soff, (uintptr_t)pairs[0],
             (uintptr_t)pairs[1], (uintptr_t)nzc[0], (uintptr_t)nzc[1], (uintptr_t)R, (uintptr_t)sc, (uintptr_t)xi,
             (uintptr_t)di, (uintptr_t)Wi, (uintptr_t)sda, (uintptr_t)ada};
-        // the null stream cannot be captured: use a private (default-priority) stream,
-        // ordered after and before the handle's stream with events
-        hipStream_t gs = h->stream;
-        if (gs == nullptr) {
-            if (!h->graph_stream) {
-                HIPCHK(hipStreamCreateWithFlags(&h->graph_stream, hipStreamNonBlocking));
-                HIPCHK(hipEventCreateWithFlags(&h->graph_ev[0], hipEventDisableTiming));
-                HIPCHK(hipEventCreateWithFlags(&h->graph_ev[1], hipEventDisableTiming));
-            }
-            gs = h->graph_stream;
-        }
-        if (!h->graph_exec || key != h->graph_key) {
-            if (h->graph_exec) {
-                HIPCHK(hipStreamSynchronize(gs));
-                hipGraphExecDestroy(h->graph_exec);
-                h->graph_exec = nullptr;
-            }
-            hipStream_t saved = h->stream;
-            HIPCHK(hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal));
-            h->stream = gs;
-            h->capturing = true;
-            const int cst = iterations();
-            h->capturing = false;
-            h->stream = saved;
-            hipGraph_t graph = nullptr;
-            const hipError_t ce = hipStreamEndCapture(gs, &graph);
-            if (cst) {
-                if (graph) hipGraphDestroy(graph);
-                return cst;
-            }
-            HIPCHK(ce);
-            const hipError_t ie = hipGraphInstantiate(&h->graph_exec, graph, nullptr, nullptr, 0);
-            hipGraphDestroy(graph);
-            HIPCHK(ie);
-            h->graph_key = key;
-        }
-        PROF(CSC_PK_GRAPH);
-        if (gs != h->stream) {
-            HIPCHK(hipEventRecord(h->graph_ev[0], h->stream));
-            HIPCHK(hipStreamWaitEvent(gs, h->graph_ev[0], 0));
-            HIPCHK(hipGraphLaunch(h->graph_exec, gs));
-            HIPCHK(hipEventRecord(h->graph_ev[1], gs));
-            HIPCHK(hipStreamWaitEvent(h->stream, h->graph_ev[1], 0));
-        } else {
-            HIPCHK(hipGraphLaunch(h->graph_exec, gs));
-        }
+        if ((st = graph_replay(h, 0, key, iterations))) return st;
     } else if ((st = iterations())) {
         return st;
     }
@@ -1155,12 +1178,14 @@ extern "C" int csc_ista_backward(csc_handle h, const csc_images *im, const float
 extern "C" int csc_set_graph(csc_handle h, int enable) {
     if (!h) return CSC_EINVAL;
     h->graphs = enable != 0;
-    if (!h->graphs && h->graph_exec) {
+    if (!h->graphs) {
         hipSetDevice(h->device);
         hipStreamSynchronize(h->stream);
-        hipGraphExecDestroy(h->graph_exec);
-        h->graph_exec = nullptr;
-        h->graph_key.clear();
+        for (int i = 0; i < 2; ++i) {
+            if (h->graph_exec[i]) hipGraphExecDestroy(h->graph_exec[i]);
+            h->graph_exec[i] = nullptr;
+            h->graph_key[i].clear();
+        }
     }
     return CSC_OK;
 }

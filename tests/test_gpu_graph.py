@@ -44,3 +44,34 @@ def test_graph_replay_matches_eager(hw, K, m, precision, with_W):
     finally:
         eager.close()
         graph.close()
+
+
+def test_power_iteration_graph_matches_eager():
+    """The lag-sum power iteration replayed from a graph gives the same L_d and filters as eager launches."""
+    from paper_1909_00145_amd.ops import Context, Images
+
+    say("power iteration graph replay")
+    torch.cuda.set_device(0)
+    hw = [(40, 36), (23, 50)]
+    K, m = 12, 7
+    eager, graph = Context(0), Context(0)
+    graph.set_graph(True)
+    im = Images(hw)
+    try:
+        for call in range(4):
+            rng = np.random.default_rng(30 + call)
+            xs = [f32(si.field(9, 10 * call + i, H, Wd)) for i, (H, Wd) in enumerate(hw)]
+            zs = [f32(rng.standard_normal((K, H, Wd)) * (rng.random((K, H, Wd)) < 0.05)) for H, Wd in hw]
+            d0 = f32(si.filters(9 + call, K, m))
+            outs = []
+            for ctx in (eager, graph):
+                d = to_dev(d0)
+                Ld = ctx.dict_step(im, packed(im, xs), packed(im, zs), d)
+                outs.append((Ld, d.cpu().numpy()))
+                # unrelated eager work on the same stream between replays
+                ctx.synthesize(im, d, packed(im, zs))
+            assert outs[1][0] == outs[0][0]
+            np.testing.assert_array_equal(outs[1][1], outs[0][1])
+    finally:
+        eager.close()
+        graph.close()
