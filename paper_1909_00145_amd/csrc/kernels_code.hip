@@ -22,10 +22,10 @@ namespace {
 // Selection (eq. 2): one Philox call yields the words of 4 consecutive
 // coordinate indices l = (y W + x) K + k, so a pixel needs about K / 4 calls.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(TPB) void k_mask_count(const ImgInfo *imgs, const TileInfo *tiles, int K,
+__global__ __launch_bounds__(TPB) void k_mask_count(const ImgInfo *imgs, int n_img, int K,
                                                     unsigned long long thr, uint2 key, unsigned draw,
                                                     long long n_pix, unsigned *mask_words, unsigned *cnt) {
-    PixelCtx c = pixel_ctx(imgs, tiles);
+    PixelCtx c = flat_ctx(imgs, n_img, n_pix);
     if (!c.valid) return;
     const unsigned long long l0 = (unsigned long long)c.p_img * (unsigned long long)K;
     const unsigned long long l1 = l0 + (unsigned long long)K;
@@ -128,14 +128,14 @@ __global__ __launch_bounds__(TPB) void k_scan_add(unsigned *off, long long n, co
 // ---------------------------------------------------------------------------
 // Lists from dense codes.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(TPB) void k_gather_selected(const ImgInfo *imgs, const TileInfo *tiles, int K,
+__global__ __launch_bounds__(TPB) void k_gather_selected(const ImgInfo *imgs, int n_img, int K,
                                                          long long n_pix, const unsigned *mask_words,
                                                          const unsigned *soff, const float *z, Pair *pairs,
                                                          unsigned short *cnt, unsigned long long *nnz_acc) {
     __shared__ int bsum;
     if (threadIdx.x == 0) bsum = 0;
     __syncthreads();
-    PixelCtx c = pixel_ctx(imgs, tiles);
+    PixelCtx c = flat_ctx(imgs, n_img, n_pix);
     if (!c.valid) {
         __syncthreads();
         if (threadIdx.x == 0 && nnz_acc && bsum) atomicAdd(nnz_acc, (unsigned long long)bsum);
@@ -162,9 +162,9 @@ __global__ __launch_bounds__(TPB) void k_gather_selected(const ImgInfo *imgs, co
     if (threadIdx.x == 0 && nnz_acc && bsum) atomicAdd(nnz_acc, (unsigned long long)bsum);
 }
 
-__global__ __launch_bounds__(TPB) void k_count_nonzero(const ImgInfo *imgs, const TileInfo *tiles, int K,
+__global__ __launch_bounds__(TPB) void k_count_nonzero(const ImgInfo *imgs, int n_img, long long n_pix, int K,
                                                        const float *z, unsigned *cnt) {
-    PixelCtx c = pixel_ctx(imgs, tiles);
+    PixelCtx c = flat_ctx(imgs, n_img, n_pix);
     if (!c.valid) return;
     const long long HW = (long long)c.im.H * c.im.W;
     const float *zp = z + (long long)K * c.im.pix_off + c.p_img;
@@ -173,10 +173,10 @@ __global__ __launch_bounds__(TPB) void k_count_nonzero(const ImgInfo *imgs, cons
     cnt[c.gp] = nn;
 }
 
-__global__ __launch_bounds__(TPB) void k_fill_nonzero(const ImgInfo *imgs, const TileInfo *tiles, int K,
+__global__ __launch_bounds__(TPB) void k_fill_nonzero(const ImgInfo *imgs, int n_img, long long n_pix, int K,
                                                       const float *z, const unsigned *off, Pair *pairs,
                                                       unsigned short *cnt) {
-    PixelCtx c = pixel_ctx(imgs, tiles);
+    PixelCtx c = flat_ctx(imgs, n_img, n_pix);
     if (!c.valid) return;
     const long long HW = (long long)c.im.H * c.im.W;
     const float *zp = z + (long long)K * c.im.pix_off + c.p_img;
@@ -192,9 +192,9 @@ __global__ __launch_bounds__(TPB) void k_fill_nonzero(const ImgInfo *imgs, const
     cnt[c.gp] = (unsigned short)nn;
 }
 
-__global__ __launch_bounds__(TPB) void k_scatter_dense(const ImgInfo *imgs, const TileInfo *tiles, int K,
+__global__ __launch_bounds__(TPB) void k_scatter_dense(const ImgInfo *imgs, int n_img, long long n_pix, int K,
                                                        Lists zl, float *z) {
-    PixelCtx c = pixel_ctx(imgs, tiles);
+    PixelCtx c = flat_ctx(imgs, n_img, n_pix);
     if (!c.valid) return;
     const long long HW = (long long)c.im.H * c.im.W;
     float *zp = z + (long long)K * c.im.pix_off + c.p_img;
@@ -806,7 +806,7 @@ int filter_chunk() {
 hipError_t launch_mask_count(const Geometry &g, int K, unsigned long long thr, unsigned long long seed,
                              unsigned draw, unsigned *mask_words, unsigned *cnt, hipStream_t s) {
     uint2 key = make_uint2((unsigned)seed, (unsigned)(seed >> 32));
-    hipLaunchKernelGGL(k_mask_count, dim3(g.n_tiles), dim3(TPB), 0, s, g.d_img, g.d_tiles, K, thr, key, draw,
+    hipLaunchKernelGGL(k_mask_count, dim3(flat_grid(g.n_pix)), dim3(TPB), 0, s, g.d_img, g.n_img, K, thr, key, draw,
                        g.n_pix, mask_words, cnt);
     return hipGetLastError();
 }
@@ -832,25 +832,27 @@ hipError_t launch_scan(const unsigned *cnt, unsigned *off, long long n, unsigned
 hipError_t launch_gather_selected(const Geometry &g, int K, const unsigned *mask_words, const unsigned *soff,
                                   const float *z, Pair *pairs, unsigned short *cnt, unsigned long long *nnz_acc,
                                   hipStream_t s) {
-    hipLaunchKernelGGL(k_gather_selected, dim3(g.n_tiles), dim3(TPB), 0, s, g.d_img, g.d_tiles, K, g.n_pix,
+    hipLaunchKernelGGL(k_gather_selected, dim3(flat_grid(g.n_pix)), dim3(TPB), 0, s, g.d_img, g.n_img, K, g.n_pix,
                        mask_words, soff, z, pairs, cnt, nnz_acc);
     return hipGetLastError();
 }
 
 hipError_t launch_count_nonzero(const Geometry &g, int K, const float *z, unsigned *cnt, hipStream_t s) {
-    hipLaunchKernelGGL(k_count_nonzero, dim3(g.n_tiles), dim3(TPB), 0, s, g.d_img, g.d_tiles, K, z, cnt);
+    hipLaunchKernelGGL(k_count_nonzero, dim3(flat_grid(g.n_pix)), dim3(TPB), 0, s, g.d_img, g.n_img, g.n_pix, K, z,
+                       cnt);
     return hipGetLastError();
 }
 
 hipError_t launch_fill_nonzero(const Geometry &g, int K, const float *z, const unsigned *off, Pair *pairs,
                                unsigned short *cnt, hipStream_t s) {
-    hipLaunchKernelGGL(k_fill_nonzero, dim3(g.n_tiles), dim3(TPB), 0, s, g.d_img, g.d_tiles, K, z, off, pairs,
-                       cnt);
+    hipLaunchKernelGGL(k_fill_nonzero, dim3(flat_grid(g.n_pix)), dim3(TPB), 0, s, g.d_img, g.n_img, g.n_pix, K, z,
+                       off, pairs, cnt);
     return hipGetLastError();
 }
 
 hipError_t launch_scatter_dense(const Geometry &g, int K, Lists z, float *zout, hipStream_t s) {
-    hipLaunchKernelGGL(k_scatter_dense, dim3(g.n_tiles), dim3(TPB), 0, s, g.d_img, g.d_tiles, K, z, zout);
+    hipLaunchKernelGGL(k_scatter_dense, dim3(flat_grid(g.n_pix)), dim3(TPB), 0, s, g.d_img, g.n_img, g.n_pix, K, z,
+                       zout);
     return hipGetLastError();
 }
 

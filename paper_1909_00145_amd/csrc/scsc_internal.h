@@ -122,6 +122,30 @@ __device__ __forceinline__ PixelCtx pixel_ctx(const ImgInfo *imgs, const TileInf
     return c;
 }
 
+// Pixel of a flat launch over the packed pixels: thread blockIdx.x * TPB + threadIdx.x
+// is packed pixel gp, so the lanes of a wave walk consecutive pixels of an image
+// row (coalesced accesses to per-pixel and [K][H][W] arrays).  The image is found
+// by a binary search over the images' first pixels.  Tile fields are not set.
+__device__ __forceinline__ PixelCtx flat_ctx(const ImgInfo *imgs, int n_img, long long n_pix) {
+    PixelCtx c;
+    c.gp = (long long)blockIdx.x * TPB + threadIdx.x;
+    c.valid = c.gp < n_pix;
+    int lo = 0, hi = n_img - 1;
+    const long long q = c.valid ? c.gp : n_pix - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (imgs[mid].pix_off <= q) lo = mid;
+        else hi = mid - 1;
+    }
+    c.im = imgs[lo];
+    c.p_img = q - c.im.pix_off;
+    c.y = (int)(c.p_img / c.im.W);
+    c.x = (int)(c.p_img - (long long)c.y * c.im.W);
+    c.ly = c.lx = 0;
+    return c;
+}
+inline unsigned flat_grid(long long n_pix) { return (unsigned)((n_pix + TPB - 1) / TPB); }
+
 // Surrogate storage: only the blocks (k, k2) with k <= k2 are kept (C_bar is
 // symmetric), in row-major order of the upper triangle.
 __host__ __device__ __forceinline__ long long tri_block(int k, int k2, int K) {
