@@ -41,16 +41,16 @@ PEAK_HBM = 8.0e12
 # valid only for the kernel source they were taken on (first 16 hex digits of its SHA-256).
 # Keyed by (kernel class, precision).
 TRAFFIC = {
-    ("synth", "bf16"): ("kernels_mfma.hip", "5a76e8c6ce77b2bc", 43.36e6, 1.02e6),
-    ("adjoint", "bf16"): ("kernels_code.hip", "dcb260f8225bd5bd", 34.15e6, 11.07e6),
+    ("synth", "bf16"): ("kernels_mfma.hip", "5a76e8c6ce77b2bc", 43.43e6, 1.02e6),
+    ("adjoint", "bf16"): ("kernels_code.hip", "a27238401965974c", 34.16e6, 11.07e6),
     ("corr", "bf16"): ("kernels_dict.hip", "e012d4f63c9433b4", 26.99e6, 4.07e6),
-    ("sur_expand", "bf16"): ("kernels_sur.hip", "725ed89275188cba", 2836.52e6, 606.50e6),
-    ("power", "bf16"): ("kernels_sur.hip", "725ed89275188cba", 18.17e6, 0.69e6),
-    ("synth", "fp32"): ("kernels_code.hip", "dcb260f8225bd5bd", 18.11e6, 0.80e6),
-    ("adjoint", "fp32"): ("kernels_code.hip", "dcb260f8225bd5bd", 20.94e6, 10.63e6),
+    ("sur_expand", "bf16"): ("kernels_sur.hip", "8153fea8d2a85673", 923.66e6, 605.83e6),
+    ("power", "bf16"): ("kernels_sur.hip", "8153fea8d2a85673", 18.22e6, 0.69e6),
+    ("synth", "fp32"): ("kernels_code.hip", "a27238401965974c", 18.08e6, 0.81e6),
+    ("adjoint", "fp32"): ("kernels_code.hip", "a27238401965974c", 20.94e6, 10.63e6),
     ("corr", "fp32"): ("kernels_dict.hip", "e012d4f63c9433b4", 26.99e6, 4.07e6),
-    ("sur_expand", "fp32"): ("kernels_sur.hip", "725ed89275188cba", 2838.65e6, 606.51e6),
-    ("power", "fp32"): ("kernels_sur.hip", "725ed89275188cba", 18.17e6, 0.69e6),
+    ("sur_expand", "fp32"): ("kernels_sur.hip", "8153fea8d2a85673", 922.81e6, 605.86e6),
+    ("power", "fp32"): ("kernels_sur.hip", "8153fea8d2a85673", 18.22e6, 0.69e6),
 }
 
 
