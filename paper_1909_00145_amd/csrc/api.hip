@@ -485,7 +485,10 @@ int lipschitz(csc_ctx *h, const float *d, int K, int m, int max_side, double *ou
     return CSC_OK;
 }
 
-// Lists of the non-zero codes of a dense z (capacity = exact count).
+// Lists of the non-zero codes of a dense z, each pixel's list exactly as long as
+// its count (offsets = prefix of the counts).  *nnz_out is the size of the pair
+// buffer (an upper bound of the total), for sizing per-entry buffers.
+constexpr unsigned long long LIST_BOUND_BYTES = 1ULL << 30;
 int build_nonzero_lists(csc_ctx *h, int K, const float *z, Lists *out, unsigned long long *nnz_out = nullptr) {
     const Geometry &g = h->geo;
     WS(cnt32, unsigned, WS_CNT32, g.n_pix);
@@ -498,11 +501,16 @@ int build_nonzero_lists(csc_ctx *h, int K, const float *z, Lists *out, unsigned 
         HIPCHK(launch_count_nonzero(g, K, z, cnt32, h->stream));
         HIPCHK(launch_scan(cnt32, off, g.n_pix, tmp, total, h->stream));
     }
-    int st = read_scalars(h, sc, SC_COUNT);
-    if (st) return st;
-    unsigned long long nz;
-    std::memcpy(&nz, &h->h_pinned[SC_TOTAL], sizeof(nz));
-    if (nz >= (1ULL << 32)) return fail(h, CSC_EUNSUPPORTED, "more than 2^32 non-zero codes");
+    // capacity: every coordinate when that bound is modest (no read-back of the
+    // count, so the host does not wait for the GPU here), else the exact count
+    const unsigned long long bound = (unsigned long long)K * (unsigned long long)g.n_pix;
+    unsigned long long nz = bound;
+    if (bound >= (1ULL << 32) || bound * (sizeof(Pair) + sizeof(FmCode)) > LIST_BOUND_BYTES) {
+        int st = read_scalars(h, sc, SC_COUNT);
+        if (st) return st;
+        std::memcpy(&nz, &h->h_pinned[SC_TOTAL], sizeof(nz));
+        if (nz >= (1ULL << 32)) return fail(h, CSC_EUNSUPPORTED, "more than 2^32 non-zero codes");
+    }
     WS(pairs, Pair, WS_PAIRS0, nz + 1);
     WS(nzc, unsigned short, WS_NZC0, g.n_pix);
     {
@@ -729,12 +737,6 @@ extern "C" int csc_code_step(csc_handle h, const csc_images *im, const float *x,
     if ((st = geometry(h, im))) return st;
     const Geometry &g = h->geo;
 
-    double Lz = 0.0, eta = step;
-    if (step <= 0.0) {
-        if ((st = lipschitz(h, d, K, m, g.max_side, &Lz))) return st;
-        if (!(Lz > 0.0)) return fail(h, CSC_EINVAL, "all filters are zero (L_z = 0); pass an explicit step");
-        eta = 1.0 / Lz;
-    }
     const int W32 = (K + 31) / 32;
     WS(mw, unsigned, WS_MASK, (size_t)W32 * g.n_pix);
     WS(cnt32, unsigned, WS_CNT32, g.n_pix);
@@ -743,12 +745,26 @@ extern "C" int csc_code_step(csc_handle h, const csc_images *im, const float *x,
     WS(sc, double, WS_SCAL, SC_COUNT);
     unsigned long long *total = reinterpret_cast<unsigned long long *>(sc + SC_TOTAL);
     const unsigned long long thr = (unsigned long long)std::floor(std::ldexp(p, 32));
+    // L_z (when no step is given) and the selection are formed first and read back
+    // together, in one round trip; until then only workspace has been written
+    if (step <= 0.0) {
+        const int P = dft_size(g.max_side, m);
+        WS(ltmp, double, WS_LIP, lipschitz_tmp_elems(K, m, P));
+        PROF(CSC_PK_LIPSCHITZ);
+        HIPCHK(launch_lipschitz_code(d, K, m, P, ltmp, sc + SC_LZ, h->stream));
+    }
     {
         PROF(CSC_PK_SELECT);
         HIPCHK(launch_mask_count(g, K, thr, seed, draw, mw, cnt32, h->stream));
         HIPCHK(launch_scan(cnt32, soff, g.n_pix, tmp, total, h->stream));
     }
     if ((st = read_scalars(h, sc, SC_COUNT))) return st;
+    double Lz = 0.0, eta = step;
+    if (step <= 0.0) {
+        Lz = h->h_pinned[SC_LZ];
+        if (!(Lz > 0.0)) return fail(h, CSC_EINVAL, "all filters are zero (L_z = 0); pass an explicit step");
+        eta = 1.0 / Lz;
+    }
     unsigned long long nsel;
     std::memcpy(&nsel, &h->h_pinned[SC_TOTAL], sizeof(nsel));
     if (nsel >= (1ULL << 32)) return fail(h, CSC_EUNSUPPORTED, "more than 2^32 selected coordinates");
