@@ -189,11 +189,6 @@ hipError_t launch_corr_fm(const Geometry &g, int K, int m, const unsigned *fm_of
     SCSC_DISPATCH_M(m, corr_fm_impl, g, K, fm_off, fm, r, W, weight_rhs, partial, s);
 }
 
-hipError_t launch_reduce_partials_f32(const float *partial, int nblocks, int n, float *out, hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce_partials<float>, dim3((n + 15) / 16), dim3(256), 0, s, partial, nblocks, n, out, 0);
-    return hipGetLastError();
-}
-
 namespace {
 __global__ __launch_bounds__(256) void k_reduce_f64_to_f32(const double *__restrict__ partial, int nblocks, int n,
                                                           float *__restrict__ out) {

@@ -288,91 +288,6 @@ __global__ __launch_bounds__(SB_THREADS) void k_sur_block(const ImgInfo *imgs, i
     }
 }
 
-// ---- lag sums: R and the side terms --------------------------------------------
-constexpr int LG_THREADS = 512;
-constexpr int LG_DC = 64;   // lags per workgroup (one per lane)
-constexpr int LG_KB = 96;   // partner filters per workgroup (lag sums R)
-constexpr int LG_KB_SIDE = 32;  // partner filters per workgroup (band sums: c accumulators per lag)
-
-// Rout[k][k2][lag] = sum over codes (k, q) of the batch of z_k[q] z_k2[q + delta] for k2 >= k.
-// side < 0: every code; side 0..3 (top, bottom, left, right): only codes in the
-// first / last c rows / columns of their image, split by that row (column)
-// index j into Rout[(side * c + j)][k][k2][lag].
-template <int MM>
-__global__ __launch_bounds__(LG_THREADS) void k_sur_lag(const ImgInfo *imgs, int n_img, int K, int R,
-                                                        const unsigned *__restrict__ fm_off,
-                                                        const FmCode *__restrict__ fm, Lists zl, int side, int KB,
-                                                        double *__restrict__ Rout) {
-    constexpr int C = MM / 2, L = 2 * MM - 1, LL = L * L;
-    constexpr int NJ = C > 0 ? C : 1;
-    extern __shared__ double acc[];  // [nj][KB][LG_DC]
-    const int dc = blockIdx.x, k = blockIdx.y;
-    const int k2lo = blockIdx.z * KB, k2hi = min(K, k2lo + KB);
-    if (k2hi <= k) return;
-    const int nj = side < 0 ? 1 : NJ;
-    for (int i = threadIdx.x; i < nj * KB * LG_DC; i += LG_THREADS) acc[i] = 0.0;
-    __syncthreads();
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int di = dc * LG_DC + lane;
-    const bool active = di < LL;
-    const int dy = di / L - 2 * C, dx = di % L - 2 * C;
-    for (int n = 0; n < n_img; ++n) {
-        const ImgInfo im = imgs[n];
-        int ya = 0, yb = im.H;
-        if (side == 0) yb = min(C, im.H);
-        if (side == 1) ya = max(0, im.H - C);
-        const unsigned a = fm_off[(long long)k * R + im.row_off + ya];
-        const unsigned b = fm_off[(long long)k * R + im.row_off + yb];
-        // two codes per wave in flight: their partner-list headers load together
-        constexpr int NW = LG_THREADS / 64;
-        for (unsigned e = a + wave; e < b; e += 2 * NW) {
-            int jv[2], cnt[2];
-            unsigned off[2];
-            double v[2];
-#pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                cnt[u] = 0;
-                off[u] = 0;
-                jv[u] = 0;
-                v[u] = 0.0;
-                const unsigned eu = e + u * NW;
-                if (eu >= b) continue;
-                const FmCode en = fm[eu];
-                const int y = (int)(en.yx >> 16), x = (int)(en.yx & 0xFFFFu);
-                int j = 0;
-                if (side == 0) j = y;
-                else if (side == 1) j = im.H - 1 - y;
-                else if (side == 2) j = x;
-                else if (side == 3) j = im.W - 1 - x;
-                if (side >= 2 && j >= C) continue;  // not in the band
-                const int y2 = y + dy, x2 = x + dx;
-                if (!active || y2 < 0 || y2 >= im.H || x2 < 0 || x2 >= im.W) continue;
-                const long long gp = im.pix_off + (long long)y2 * im.W + x2;
-                off[u] = zl.off[gp];
-                cnt[u] = zl.cnt[gp];
-                jv[u] = j;
-                v[u] = (double)en.v;
-            }
-#pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                double *row = acc + (long long)jv[u] * KB * LG_DC + lane;
-                for (int t = 0; t < cnt[u]; ++t) {
-                    const Pair p2 = zl.pairs[off[u] + t];
-                    if (p2.k < k2lo || p2.k >= k2hi || p2.k < k) continue;
-                    atomicAdd(row + (p2.k - k2lo) * LG_DC, v[u] * (double)p2.v);
-                }
-            }
-        }
-    }
-    __syncthreads();
-    if (!active) return;
-    for (int jj = 0; jj < nj; ++jj) {
-        const int cls = side < 0 ? 0 : side * C + jj;
-        for (int k2 = max(k, k2lo); k2 < k2hi; ++k2)
-            Rout[(((long long)cls * K + k) * K + k2) * LL + di] = acc[((long long)jj * KB + (k2 - k2lo)) * LG_DC + lane];
-    }
-}
-
 // Lag-layout position table: tab[i] = lag index * 128 + position inside the lag's run.
 template <int MM>
 __global__ void k_lag_table(unsigned short *tab) {
@@ -701,11 +616,6 @@ __global__ void k_power_final(const double *__restrict__ nparts, const double *_
         dot += dparts[i];
     }
     *lam = nn > 0.0 ? dot : 0.0;
-}
-
-__global__ void k_zero_f64(double *p, long long n) {
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
-        p[i] = 0.0;
 }
 
 // C_bar(k, k2) += R - E_top - E_bottom - E_left - E_right for every stored block

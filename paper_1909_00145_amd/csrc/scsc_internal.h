@@ -286,7 +286,6 @@ int corr_chunks(int K);
 hipError_t launch_corr_fm(const Geometry &g, int K, int m, const unsigned *fm_off, const FmCode *fm, const float *r,
                           const unsigned char *W, bool weight_rhs, double *partial, hipStream_t s);
 hipError_t launch_reduce_partials_f64_to_f32(const double *partial, int nblocks, int n, float *out, hipStream_t s);
-hipError_t launch_reduce_partials_f32(const float *partial, int nblocks, int n, float *out, hipStream_t s);
 hipError_t launch_reduce_partials_f64_add(const double *partial, int nblocks, int n, double *inout,
                                           hipStream_t s);
 // Dense adjoint D^T r (every coordinate).
