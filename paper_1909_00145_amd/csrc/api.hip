@@ -54,6 +54,7 @@ enum Slot {
     WS_LAGPART,
     WS_PNORM,
     WS_ADA,
+    WS_XPAIRS,
     WS_COUNT
 };
 
@@ -487,9 +488,11 @@ int lipschitz(csc_ctx *h, const float *d, int K, int m, int max_side, double *ou
 
 // Lists of the non-zero codes of a dense z, each pixel's list exactly as long as
 // its count (offsets = prefix of the counts).  *nnz_out is the size of the pair
-// buffer (an upper bound of the total), for sizing per-entry buffers.
+// buffer (an upper bound of the total), for sizing per-entry buffers.  With
+// xp_out, the entries are also written tagged for row stride xmul (XPair).
 constexpr unsigned long long LIST_BOUND_BYTES = 1ULL << 30;
-int build_nonzero_lists(csc_ctx *h, int K, const float *z, Lists *out, unsigned long long *nnz_out = nullptr) {
+int build_nonzero_lists(csc_ctx *h, int K, const float *z, Lists *out, unsigned long long *nnz_out = nullptr,
+                        const XPair **xp_out = nullptr, unsigned xmul = 0) {
     const Geometry &g = h->geo;
     WS(cnt32, unsigned, WS_CNT32, g.n_pix);
     WS(off, unsigned, WS_OFF, g.n_pix + 1);
@@ -513,9 +516,15 @@ int build_nonzero_lists(csc_ctx *h, int K, const float *z, Lists *out, unsigned 
     }
     WS(pairs, Pair, WS_PAIRS0, nz + 1);
     WS(nzc, unsigned short, WS_NZC0, g.n_pix);
+    XPair *xp = nullptr;
+    if (xp_out) {
+        WS(xpb, XPair, WS_XPAIRS, nz + 1);
+        xp = xpb;
+        *xp_out = xp;
+    }
     {
         PROF(CSC_PK_LISTS);
-        HIPCHK(launch_fill_nonzero(g, K, z, off, pairs, nzc, h->stream));
+        HIPCHK(launch_fill_nonzero(g, K, z, off, pairs, nzc, xp, xmul, h->stream));
     }
     *out = Lists{off, nzc, pairs};
     if (nnz_out) *nnz_out = nz;
@@ -892,17 +901,20 @@ extern "C" int csc_dict_step(csc_handle h, const csc_images *im, const float *x,
     if ((st = geometry(h, im))) return st;
     const Geometry &g = h->geo;
     const int M = m * m;
+    const bool need_ld = sur || step <= 0.0 || L_d_out;
+    const bool lag_pass = !W && (sur || need_ld);
     Lists L;
     unsigned long long nz = 0;
-    if ((st = build_nonzero_lists(h, K, z, &L, &nz))) return st;
+    const XPair *xp = nullptr;
+    const unsigned xmul = lag_pass ? lag_rows_stride(g, K, m) : 0u;
+    if ((st = build_nonzero_lists(h, K, z, &L, &nz, xmul ? &xp : nullptr, xmul))) return st;
     FmLists F;
     if ((st = build_fm_lists(h, K, L, nz, &F))) return st;
     WS(sc, double, WS_SCAL, SC_COUNT);
-    const bool need_ld = sur || step <= 0.0 || L_d_out;
     // Without an observation mask the lag sums R of the batch give both the
     // surrogate increment and the zero-padded normal matrix used for L_d.
     double *Rl = nullptr, *Es = nullptr;
-    if (!W && (sur || need_ld)) {
+    if (lag_pass) {
         const long long nl = surrogate_lag_elems(K, m);
         {
             WS(rl, double, WS_LAG, nl);
@@ -914,7 +926,7 @@ extern "C" int csc_dict_step(csc_handle h, const csc_images *im, const float *x,
         }
         WS(lpart, double, WS_LAGPART, surrogate_lag_part_elems(g, K, m));
         PROF(CSC_PK_SUR_LAG);
-        HIPCHK(launch_surrogate_lag(g, K, m, L, lpart, Rl, Es, h->stream));
+        HIPCHK(launch_surrogate_lag(g, K, m, L, xp, F.off, F.codes, lpart, Rl, Es, h->stream));
     }
     if (need_ld) {
         if (W) st = power_iteration(h, K, m, L, F, W, n_power, precision);

@@ -175,7 +175,7 @@ __global__ __launch_bounds__(TPB) void k_count_nonzero(const ImgInfo *imgs, int 
 
 __global__ __launch_bounds__(TPB) void k_fill_nonzero(const ImgInfo *imgs, int n_img, long long n_pix, int K,
                                                       const float *z, const unsigned *off, Pair *pairs,
-                                                      unsigned short *cnt) {
+                                                      unsigned short *cnt, XPair *xp, unsigned xmul) {
     PixelCtx c = flat_ctx(imgs, n_img, n_pix);
     if (!c.valid) return;
     const long long HW = (long long)c.im.H * c.im.W;
@@ -186,6 +186,7 @@ __global__ __launch_bounds__(TPB) void k_fill_nonzero(const ImgInfo *imgs, int n
         float v = zp[(long long)k * HW];
         if (v != 0.f) {
             pairs[base + nn] = Pair{k, v};
+            if (xp) xp[base + nn] = XPair{((unsigned)c.x * xmul + (unsigned)k) * 8u, v};
             ++nn;
         }
     }
@@ -844,9 +845,9 @@ hipError_t launch_count_nonzero(const Geometry &g, int K, const float *z, unsign
 }
 
 hipError_t launch_fill_nonzero(const Geometry &g, int K, const float *z, const unsigned *off, Pair *pairs,
-                               unsigned short *cnt, hipStream_t s) {
+                               unsigned short *cnt, XPair *xp, unsigned xmul, hipStream_t s) {
     hipLaunchKernelGGL(k_fill_nonzero, dim3(flat_grid(g.n_pix)), dim3(TPB), 0, s, g.d_img, g.n_img, g.n_pix, K, z,
-                       off, pairs, cnt);
+                       off, pairs, cnt, xp, xmul);
     return hipGetLastError();
 }
 

@@ -459,6 +459,129 @@ __global__ __launch_bounds__(256) void k_lag_sum(int K, int n_chunks, const doub
     }
 }
 
+// Filter-major runs for the lags delta = (dy, dx) >= 0 (dy > 0, or dy = 0 and
+// dx >= 0).  Workgroup (row range z, chunk of KR first filters k, dy) holds
+// S[dx][k][k2] for every dx in LDS.  Each non-zero code a = z_k[y][x] of its
+// filters and rows meets the codes of the pixels (y + dy, x + dx), |dx| <= 2c:
+// one contiguous run of the per-pixel lists, whose entries carry their columns
+// (hence dx).  The codes are visited in groups of G rows, all filters of the
+// chunk per group, so that the runs that share a row of partners are read close
+// together (L1 reuse).  They are taken LR_NB at a time: first every thread
+// resolves one code's run (filter, position, image, run bounds) into an LDS
+// descriptor, then LR_SUB lanes read each run at consecutive entries, LR_UNROLL
+// loads in flight per lane, and add the products into S.  The workgroups of one
+// XCD take neighbouring row ranges, so that their L2 holds the runs they read.
+// Output as the pixel-slot pass: part[z][delta][k][k2] with z the row range.
+constexpr int LR_THREADS = 1024;
+constexpr int LR_SUB = 16;     // lanes per run
+constexpr int LR_UNROLL = 6;   // run entries in flight per lane
+constexpr int LR_NB = 512;     // descriptors per batch
+constexpr int LR_SEG = 256;    // (row group, filter) segments per workgroup
+constexpr int LR_LDS = 80 * 1024;
+struct RunDesc {
+    unsigned j0, len, sidx;
+    float va;
+};
+
+template <int MM>
+__global__ __launch_bounds__(LR_THREADS, 8) void k_lag_rows(const ImgInfo *__restrict__ imgs, int R, int K, int KR,
+                                                          int nkc, int P, const unsigned *__restrict__ fm_off,
+                                                          const FmCode *__restrict__ fm,
+                                                          const unsigned *__restrict__ off,
+                                                          const XPair *__restrict__ xp, double *__restrict__ out) {
+    constexpr int C2 = 2 * (MM / 2), L = 2 * MM - 1, LL = L * L, nlag = (LL + 1) / 2;
+    extern __shared__ double S[];  // [L][KR][K], then the descriptors and the segment table
+    RunDesc *desc = reinterpret_cast<RunDesc *>(S + (size_t)L * KR * K);
+    unsigned *sst = reinterpret_cast<unsigned *>(desc + LR_NB);  // [LR_SEG] first code of the segment
+    unsigned *spr = sst + LR_SEG;                                // [LR_SEG + 1] codes before the segment
+    const int per = P / N_XCD;
+    const int b = (int)blockIdx.x, xcd = b % N_XCD, bi = b / N_XCD;
+    const int z = xcd * per + bi % per, rest = bi / per;
+    const int kc = rest % nkc, dy = rest / nkc;
+    const int k0 = kc * KR, nk = min(KR, K - k0);
+    const int r0 = (int)((long long)R * z / P), r1 = (int)((long long)R * (z + 1) / P);
+    const int KRK = KR * K;
+    // segments (row group g, filter kk) in the order g major: G rows per group
+    const int gmax = LR_SEG / nk;  // groups that fit the table
+    const int G = max(8, (r1 - r0 + gmax - 1) / gmax);
+    const int ng = (r1 - r0 + G - 1) / G, nseg = ng * nk;
+    for (int t = threadIdx.x; t < L * KRK; t += LR_THREADS) S[t] = 0.0;
+    for (int sgi = threadIdx.x; sgi <= nseg; sgi += LR_THREADS) {
+        // codes before segment (g, kk): all filters' codes of the rows before group g,
+        // and the filters before kk in group g
+        const int g = sgi / nk, kk = sgi - g * nk;
+        const int rg = min(r1, r0 + g * G), re = min(r1, rg + G);
+        unsigned before = 0;
+        for (int q = 0; q < nk; ++q) {
+            const long long fr = (long long)(k0 + q) * R;
+            const unsigned base = fm_off[fr + r0];
+            before += fm_off[fr + (q < kk ? re : rg)] - base;
+        }
+        spr[sgi] = before;
+        if (sgi < nseg) sst[sgi] = fm_off[(long long)(k0 + kk) * R + rg];
+    }
+    __syncthreads();
+    const unsigned na = spr[nseg];
+    const int lane = (int)threadIdx.x % LR_SUB, sg = (int)threadIdx.x / LR_SUB;
+    for (unsigned v0 = 0; v0 < na; v0 += LR_NB) {
+        if (threadIdx.x < LR_NB) {
+            RunDesc dsc{0u, 0u, 0, 0.f};
+            const unsigned v = v0 + threadIdx.x;
+            if (v < na) {
+                int lo = 0, hi = nseg - 1;  // segment of the v-th code: the last one with spr <= v
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (spr[mid] <= v) lo = mid;
+                    else hi = mid - 1;
+                }
+                const int kk = lo % nk;
+                const FmCode a = fm[sst[lo] + (v - spr[lo])];
+                const ImgInfo im = imgs[a.img];
+                const int y2 = (int)(a.yx >> 16) + dy, x = (int)(a.yx & 0xffffu);
+                if (y2 < im.H) {
+                    const int xlo = max(0, x - (dy > 0 ? C2 : 0)), xhi = min(im.W - 1, x + C2);
+                    const long long rb = im.pix_off + (long long)y2 * im.W;
+                    dsc.j0 = off[rb + xlo];
+                    dsc.len = off[rb + xhi + 1] - dsc.j0;
+                    // byte offset of slot (dx = x_b - x, row kk) is sidx + the entry's tag, modulo 2^32
+                    dsc.sidx = ((unsigned)kk * (unsigned)K - (unsigned)(x - C2) * (unsigned)KRK) * 8u;
+                    dsc.va = a.v;
+                }
+            }
+            desc[threadIdx.x] = dsc;
+        }
+        __syncthreads();
+        for (int di = sg; di < LR_NB; di += LR_THREADS / LR_SUB) {
+            const RunDesc dsc = desc[di];
+            const double va = (double)dsc.va;
+            // the run read from the 64-byte boundary below its first entry; loads past
+            // its end repeat the last entry, so that no further cache sector is touched
+            const unsigned ja = dsc.j0 & ~7u, skip = dsc.j0 - ja;
+            const unsigned span = dsc.len ? dsc.len + skip : 0u;
+            const XPair *qa = xp + ja;
+            char *Sb = reinterpret_cast<char *>(S);
+            for (unsigned t0 = 0; t0 < span; t0 += LR_SUB * LR_UNROLL) {
+                XPair e[LR_UNROLL];
+#pragma unroll
+                for (int u = 0; u < LR_UNROLL; ++u) e[u] = qa[min(t0 + lane + u * LR_SUB, span - 1)];
+#pragma unroll
+                for (int u = 0; u < LR_UNROLL; ++u) {
+                    const unsigned t = t0 + lane + u * LR_SUB;
+                    if (t < span && t >= skip)
+                        atomicAdd(reinterpret_cast<double *>(Sb + (dsc.sidx + e[u].off)), va * (double)e[u].v);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    for (int t = threadIdx.x; t < L * nk * K; t += LR_THREADS) {
+        const int sl = t / (nk * K), rem = t - sl * (nk * K), kk = rem / K, k2 = rem - kk * K;
+        const int dx = sl - C2;
+        if (dy == 0 && dx < 0) continue;
+        out[(((long long)z * nlag + dy * L + dx) * K + k0 + kk) * K + k2] = S[sl * KRK + kk * K + k2];
+    }
+}
+
 // Product with the zero-padded normal matrix of the batch, whose entry
 // (k, s; k2, s2) is the lag sum R_{s - s2}[k][k2] (block Toeplitz in the taps):
 // part[chunk][k][s] = sum_{k2 in chunk} sum_{s2} R_{s - s2}[k][k2] v[k2][s2], FP64.
@@ -919,7 +1042,8 @@ long long surrogate_lag_elems(int K, int m) { return (long long)K * K * (2 * m -
 namespace {
 struct LagPlan {
     int KC, nkc, nlag;
-    long long P;
+    long long P;     // pixel chunks of the pixel-slot pass
+    int KR, nkr, PR;  // filter-major runs: filters per chunk, chunks, row ranges (0: not usable)
 };
 
 template <int MM>
@@ -931,20 +1055,48 @@ LagPlan lag_plan(const Geometry &g, int K) {
     pl.nlag = (LL + 1) / 2;
     // pixel chunks: enough workgroups to cover the chip a few times, at least 2048 pixels each
     pl.P = std::max(1LL, std::min(2048LL / ((long long)pl.nlag * pl.nkc), (long long)(g.n_pix / 2048)));
+    pl.KR = pl.nkr = pl.PR = 0;
+    const long long per_filter = 8LL * L * K, fixed = (long long)sizeof(RunDesc) * LR_NB + 8LL * LR_SEG + 4;
+    if (K <= 65535 && g.max_side <= 65535 && g.n_rows > 0 && per_filter + fixed <= LR_LDS) {
+        pl.KR = (int)std::min<long long>(K, (LR_LDS - fixed) / per_filter);
+        pl.nkr = (K + pl.KR - 1) / pl.KR;
+        const long long ny = MM / 2 * 2 + 1;
+        // row ranges: a multiple of the XCD count, about 2048 workgroups, ranges of >= 8 rows
+        long long q = (2048 + N_XCD * pl.nkr * ny - 1) / (N_XCD * pl.nkr * ny);
+        q = std::max(1LL, std::min(q, (long long)g.n_rows / (8 * N_XCD)));
+        pl.PR = (int)(N_XCD * q);
+    }
     return pl;
 }
 
 template <int MM>
-hipError_t sur_lag_impl(const Geometry &g, int K, Lists z, double *part, double *Rl, double *Es, hipStream_t s) {
+unsigned lag_rows_impl(const Geometry &g, int K) {
+    const LagPlan pl = lag_plan<MM>(g, K);
+    return pl.PR > 0 ? (unsigned)(pl.KR * K) : 0u;
+}
+
+template <int MM>
+hipError_t sur_lag_impl(const Geometry &g, int K, Lists z, const XPair *xp, const unsigned *fm_off,
+                        const FmCode *fm, double *part, double *Rl, double *Es, hipStream_t s) {
     constexpr int Cc = MM / 2, L = 2 * MM - 1, LL = L * L;
     const LagPlan pl = lag_plan<MM>(g, K);
     const size_t shm = sizeof(double) * (size_t)pl.KC * K;
-    hipLaunchKernelGGL(k_lag_outer<MM>, dim3(pl.nlag, pl.nkc, (unsigned)pl.P), dim3(LO_THREADS), shm, s, g.d_img,
-                       g.n_img, (long long)g.n_pix, g.max_side, K, z, 0, pl.KC, part);
+    int nparts = (int)pl.P;
+    if (pl.PR > 0 && xp && fm_off && fm) {
+        const size_t shr = sizeof(double) * (size_t)L * pl.KR * K + sizeof(RunDesc) * LR_NB +
+                           sizeof(unsigned) * (2 * (size_t)LR_SEG + 1);
+        const unsigned nb = (unsigned)((long long)pl.PR * pl.nkr * (Cc * 2 + 1));
+        hipLaunchKernelGGL(k_lag_rows<MM>, dim3(nb), dim3(LR_THREADS), shr, s, g.d_img, g.n_rows, K, pl.KR, pl.nkr,
+                           pl.PR, fm_off, fm, z.off, xp, part);
+        nparts = pl.PR;
+    } else {
+        hipLaunchKernelGGL(k_lag_outer<MM>, dim3(pl.nlag, pl.nkc, (unsigned)pl.P), dim3(LO_THREADS), shm, s, g.d_img,
+                           g.n_img, (long long)g.n_pix, g.max_side, K, z, 0, pl.KC, part);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const unsigned nt = (unsigned)((K + LS_T - 1) / LS_T);
-    hipLaunchKernelGGL(k_lag_sum<MM>, dim3(pl.nlag, nt, nt), dim3(256), 0, s, K, (int)pl.P, part, Rl);
+    hipLaunchKernelGGL(k_lag_sum<MM>, dim3(pl.nlag, nt, nt), dim3(256), 0, s, K, nparts, part, Rl);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (Cc > 0 && Es) {
         hipLaunchKernelGGL(k_lag_outer<MM>, dim3(LL, pl.nkc, 4 * Cc), dim3(LO_THREADS), shm, s, g.d_img, g.n_img,
@@ -957,7 +1109,7 @@ hipError_t sur_lag_impl(const Geometry &g, int K, Lists z, double *part, double 
 template <int MM>
 long long lag_part_impl(const Geometry &g, int K) {
     const LagPlan pl = lag_plan<MM>(g, K);
-    return pl.P * pl.nlag * (long long)K * K;
+    return std::max<long long>(pl.P, pl.PR) * pl.nlag * (long long)K * K;
 }
 
 template <int MM>
@@ -1014,9 +1166,20 @@ long long surrogate_lag_part_elems(const Geometry &g, int K, int m) {
     SCSC_DISPATCH_M(m, lag_part_impl, g, K);
 }
 
-hipError_t launch_surrogate_lag(const Geometry &g, int K, int m, Lists z, double *part, double *Rl, double *Es,
-                                hipStream_t s) {
-    SCSC_DISPATCH_M(m, sur_lag_impl, g, K, z, part, Rl, Es, s);
+unsigned lag_rows_stride(const Geometry &g, int K, int m) {
+    switch (m) {
+        case 3: return lag_rows_impl<3>(g, K);
+        case 5: return lag_rows_impl<5>(g, K);
+        case 7: return lag_rows_impl<7>(g, K);
+        case 9: return lag_rows_impl<9>(g, K);
+        case 11: return lag_rows_impl<11>(g, K);
+        default: return 0u;
+    }
+}
+
+hipError_t launch_surrogate_lag(const Geometry &g, int K, int m, Lists z, const XPair *xp, const unsigned *fm_off,
+                                const FmCode *fm, double *part, double *Rl, double *Es, hipStream_t s) {
+    SCSC_DISPATCH_M(m, sur_lag_impl, g, K, z, xp, fm_off, fm, part, Rl, Es, s);
 }
 
 hipError_t launch_surrogate_expand(int K, int m, const double *Rl, const double *Es, unsigned short *tab, double *C,

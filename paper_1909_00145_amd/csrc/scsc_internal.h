@@ -44,6 +44,15 @@ struct __align__(8) Pair {
     float v;
 };
 
+// A per-pixel list entry tagged with its pixel column x for a pass that reads
+// runs of pixels of one row: off = (x * xmul + k) * 8 modulo 2^32, the entry's
+// byte offset in an LDS table with rows of xmul doubles per column.  Written
+// beside the plain pairs of the non-zero lists.
+struct __align__(8) XPair {
+    unsigned off;
+    float v;
+};
+
 // One non-zero code in the per-filter lists: position (y << 16 | x) inside its
 // image, value and image.  The lists of filter k are ordered by global row
 // then x and live at [fm_off[k R + r], fm_off[k R + r + 1]) for row r.
@@ -272,8 +281,9 @@ hipError_t launch_adjoint_shrink(const Geometry &g, int K, int m, const unsigned
 hipError_t launch_scatter_dense(const Geometry &g, int K, Lists z, float *zout, hipStream_t s);
 // Lists of the non-zero codes of a dense z: count, then fill.
 hipError_t launch_count_nonzero(const Geometry &g, int K, const float *z, unsigned *cnt, hipStream_t s);
+// xp (may be null): the same entries tagged with their columns for row stride xmul.
 hipError_t launch_fill_nonzero(const Geometry &g, int K, const float *z, const unsigned *off, Pair *pairs,
-                               unsigned short *cnt, hipStream_t s);
+                               unsigned short *cnt, XPair *xp, unsigned xmul, hipStream_t s);
 // Selection bytes (csc_mask).
 hipError_t launch_expand_mask(const Geometry &g, int K, const unsigned *mask_words, unsigned char *mask,
                               hipStream_t s);
@@ -310,10 +320,14 @@ hipError_t launch_surrogate_blocks(const Geometry &g, int K, int m, const unsign
 // Unmasked case: lag sums Rl[lag][k][k2] (surrogate_lag_elems doubles), band sums
 // Es[4 c][lag][k][k2] (k <= k2; skipped when Es is null), expansion, corners.
 // part: surrogate_lag_part_elems doubles of workspace (per-chunk partial sums).
+// With xp (the entries of z tagged for row stride lag_rows_stride) and the
+// per-filter lists, the lags delta >= 0 are summed by filter-major runs, else by
+// pixel slots.
 long long surrogate_lag_elems(int K, int m);
 long long surrogate_lag_part_elems(const Geometry &g, int K, int m);
-hipError_t launch_surrogate_lag(const Geometry &g, int K, int m, Lists z, double *part, double *Rl, double *Es,
-                                hipStream_t s);
+unsigned lag_rows_stride(const Geometry &g, int K, int m);  // 0: the run pass does not apply
+hipError_t launch_surrogate_lag(const Geometry &g, int K, int m, Lists z, const XPair *xp, const unsigned *fm_off,
+                                const FmCode *fm, double *part, double *Rl, double *Es, hipStream_t s);
 // Power iteration on the zero-padded normal matrix given by the lag sums.
 // Rf = the lag sums rounded to FP32 (a step-size estimate needs no more), in
 // [k][k2][lag] order (launch_lag_to_f32).  The matvec multiplies v = w / ||w||,

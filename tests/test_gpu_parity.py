@@ -274,9 +274,10 @@ def test_dict_step_zero_codes(ctx):
     np.testing.assert_array_equal(dg.cpu().numpy(), d.astype(np.float32))
 
 
+# K = 30 with m = 11: the filter-major lag pass splits the filters into two chunks
 @pytest.mark.parametrize("hw,K,m,with_W", [([(30, 26)], 4, 5, False), ([(24, 20), (16, 21)], 3, 11, True),
                                             ([(40, 45), (33, 17)], 5, 11, False), ([(7, 9), (12, 5)], 3, 11, False),
-                                            ([(23, 31)], 6, 3, False)])
+                                            ([(23, 31)], 6, 3, False), ([(20, 24), (13, 30)], 30, 11, False)])
 def test_dict_step_online(ctx, hw, K, m, with_W):
     from paper_1909_00145_amd.ops import Surrogate
 
