@@ -328,7 +328,9 @@ __global__ __launch_bounds__(LO_THREADS, 8) void k_lag_outer(const ImgInfo *imgs
         // strip cut off by some tap offset of this lag: j < min(c, c -+ delta).
         const int sd = (int)blockIdx.z / NC, jj = (int)blockIdx.z % NC;
         const int dlt = sd == 0 ? -dy : sd == 1 ? dy : sd == 2 ? -dx : dx;
-        if (jj >= min(C, C + dlt)) return;  // this (lag, band row) is never read
+        // never read: band rows j >= min(c, c + dlt); identically zero (the partner
+        // pixel lies outside every image): dlt > j; the expansion takes those as 0
+        if (jj >= min(C, C + dlt) || dlt > jj) return;
     }
     const int klo = blockIdx.y * KC, khi = min(K, klo + KC);
     for (int i = threadIdx.x; i < KC * K; i += LO_THREADS) Rd[i] = 0.0;
@@ -780,8 +782,9 @@ __global__ __launch_bounds__(EX_THREADS) void k_sur_expand(int K, const double *
             const int sd = cls / NC, j = cls % NC;
             const int dy = di / L - 2 * C, dx = di % L - 2 * C;
             const int dlt = sd == 0 ? -dy : sd == 1 ? dy : sd == 2 ? -dx : dx;
-            // band rows j >= min(c, c + dlt) are never read for this lag (and were not formed)
-            if (j < min(C, C + dlt)) ev[u] = Es[(((long long)cls * LL + di) * K + k) * K + k2];
+            // band rows j >= min(c, c + dlt) are never read for this lag, and for dlt > j
+            // the partner pixel lies outside every image (the sum is 0); neither was formed
+            if (j < min(C, C + dlt) && dlt <= j) ev[u] = Es[(((long long)cls * LL + di) * K + k) * K + k2];
         }
 #pragma unroll
         for (int u = 0; u < EX_BATCH; ++u) {
