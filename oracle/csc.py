@@ -23,6 +23,9 @@ is listed with its reason in the design notes):
   word is < floor(p 2^32).
 * Code solver: proximal gradient (ISTA) on the subsampled LASSO of eq. (3),
   step 1/L_z, unselected coordinates held at zero (the upsampling of eq. (4)).
+  Optionally (``hold=True``) the unselected coordinates keep their previous
+  values instead, as the randomization paragraph of Sec. 3.1 describes (only
+  the pDK sampled variables change); their codes then stay in the residual.
 * Filter solver: projected gradient on eq. (5) (batch) or on the surrogate
   problem eq. (9) with surrogates accumulated per eq. (8) (online).
 
@@ -214,6 +217,7 @@ def code_step(
     W: np.ndarray | None = None,
     image_index: int = 0,
     max_side: int | None = None,
+    hold: bool = False,
 ):
     """One code update for one image.  Returns (z_new [K,H,W], sampled mask [K,H,W]).
 
@@ -221,6 +225,11 @@ def code_step(
     proximal-gradient iterations.  z starts from z_prev restricted to S; each
     iteration forms the masked residual r = W (x - D z), the gradient D^T r,
     and applies the soft-threshold on S; coordinates off S are zero (eq. 4).
+
+    hold=True: coordinates off S keep their values z_prev throughout (Sec. 3.1,
+    randomization paragraph: the variables that are not sampled remain
+    unchanged), so z starts from z_prev itself and every residual includes
+    them; only S is updated.
     """
     K = d.shape[0]
     H, Wd = x.shape
@@ -228,11 +237,12 @@ def code_step(
     if step is None:
         step = 1.0 / lipschitz_code(d, max(H, Wd) if max_side is None else max_side)
     Wm = np.ones_like(x) if W is None else W.astype(np.float64)
-    z = np.where(S, z_prev, 0.0)
+    off = np.asarray(z_prev, dtype=np.float64) if hold else 0.0
+    z = np.where(S, z_prev, off)
     for _ in range(n_iter):
         r = Wm * (x - synthesize(d, z))
         u = z + step * adjoint(d, r)
-        z = np.where(S, soft_threshold(u, step * lam), 0.0)
+        z = np.where(S, soft_threshold(u, step * lam), off)
     return z, S
 
 

@@ -7,6 +7,15 @@
 * after many iterations the result equals scikit-learn's coordinate-descent
   Lasso on the explicit subsampled operator D M^T (an independent solver);
 * L_z bounds ||D||^2 computed by SVD of the explicit operator.
+
+HOLD (the unselected variables keep their values, Sec. 3.1 randomization
+paragraph):
+* delta filter: S_lambda(x) on the sample, z_prev elsewhere -- exactly;
+* the unselected coordinates are returned bit for bit, and z_prev = 0 or
+  p = 1 reduce HOLD to the default;
+* converged, the sample equals scikit-learn's Lasso on the sampled columns with
+  the held part moved to the target (x - D_off z_prev); KKT holds there;
+* the full objective never increases at step 1/L_z.
 """
 
 import numpy as np
@@ -112,3 +121,75 @@ def test_dft_size():
     assert oracle.dft_size(118, 11) == 128
     assert oracle.dft_size(119, 11) == 256
     assert oracle.dft_size(64, 11) == 128
+
+
+def test_hold_delta_filter_closed_form(rng):
+    H, W, m = 9, 8, 3
+    d = np.zeros((1, m, m))
+    d[0, 1, 1] = 1.0
+    x = rng.standard_normal((H, W)) * 2
+    z0 = rng.standard_normal((1, H, W))
+    lam, p = 0.6, 0.4
+    z, S = oracle.code_step(x, d, z0, lam, p, seed=3, draw=1, n_iter=1, step=1.0, hold=True)
+    # on the sample u = z0 + (x - z0) = x up to one rounding of each operation
+    np.testing.assert_allclose(z[0][S[0]], soft_threshold(x, lam)[S[0]], rtol=0, atol=1e-14)
+    np.testing.assert_array_equal(z[0][~S[0]], z0[0][~S[0]])
+    assert 0 < S.sum() < S.size
+
+
+def test_hold_keeps_unselected_and_reduces_to_default(rng):
+    K, m, H, W = 3, 5, 11, 10
+    d = oracle.project_ball(rng.standard_normal((K, m, m)))
+    x = rng.standard_normal((H, W))
+    z0 = rng.standard_normal((K, H, W)) * (rng.random((K, H, W)) < 0.3)
+    z, S = oracle.code_step(x, d, z0, 0.2, 0.5, 7, 3, n_iter=4, hold=True)
+    np.testing.assert_array_equal(z[~S], z0[~S])
+    # zero start: nothing to hold
+    za, _ = oracle.code_step(x, d, np.zeros_like(z0), 0.2, 0.5, 7, 3, n_iter=4, hold=True)
+    zb, _ = oracle.code_step(x, d, np.zeros_like(z0), 0.2, 0.5, 7, 3, n_iter=4)
+    np.testing.assert_array_equal(za, zb)
+    # p = 1: every coordinate is sampled
+    za, S1 = oracle.code_step(x, d, z0, 0.2, 1.0, 7, 3, n_iter=4, hold=True)
+    zb, _ = oracle.code_step(x, d, z0, 0.2, 1.0, 7, 3, n_iter=4)
+    assert S1.all()
+    np.testing.assert_array_equal(za, zb)
+
+
+def test_hold_converged_matches_sklearn_lasso(rng):
+    from sklearn.linear_model import Lasso
+
+    K, m, H, W = 2, 3, 6, 5
+    d = oracle.project_ball(rng.standard_normal((K, m, m)))
+    x = rng.standard_normal((H, W))
+    z0 = rng.standard_normal((K, H, W)) * (rng.random((K, H, W)) < 0.5)
+    lam, p = 0.15, 0.6
+    z, S = oracle.code_step(x, d, z0, lam, p, 21, 4, n_iter=20000, hold=True)
+    D = explicit_D(d, H, W)
+    cols = S.reshape(-1)
+    A = D[:, cols]
+    target = x.ravel() - D[:, ~cols] @ z0.reshape(-1)[~cols]
+    n = A.shape[0]
+    las = Lasso(alpha=lam / n, fit_intercept=False, tol=1e-14, max_iter=1000000)
+    las.fit(A, target)
+    ref = z0.reshape(-1).copy()
+    ref[cols] = las.coef_
+    np.testing.assert_allclose(z.ravel(), ref, atol=2e-7, rtol=0)
+    g = oracle.adjoint(d, x - oracle.synthesize(d, z))[S]
+    zs = z[S]
+    assert np.all(np.abs(g[zs == 0]) <= lam + 1e-7)
+    np.testing.assert_allclose(g[zs != 0], lam * np.sign(zs[zs != 0]), atol=1e-7)
+
+
+def test_hold_objective_monotone(rng):
+    K, m, H, W = 4, 5, 16, 14
+    d = oracle.project_ball(rng.standard_normal((K, m, m)))
+    x = rng.standard_normal((H, W))
+    lam = 0.3
+    z = rng.standard_normal((K, H, W)) * (rng.random((K, H, W)) < 0.2)
+    L = oracle.lipschitz_code(d, max(H, W))
+    prev = oracle.objective([x], d, [z], lam)[0]
+    for it in range(12):
+        z, S = oracle.code_step(x, d, z, lam, 0.3, 5, it, n_iter=2, step=1.0 / L, hold=True)
+        f = oracle.objective([x], d, [z], lam)[0]
+        assert f <= prev + 1e-12 * abs(prev)
+        prev = f
