@@ -139,6 +139,22 @@ int csc_code_step(csc_handle h, const csc_images *im, const float *x, const uint
                   uint64_t seed, uint32_t draw, int n_iter, double step, int precision,
                   csc_code_stats *stats);
 
+/* Code update with the unselected coordinates held (Sec. 3.1, the paragraph on
+ * the randomization: each iteration changes only the pDK sampled variables and
+ * the rest remain unchanged).  As csc_code_step, except that z starts from its
+ * own values, the coordinates off S keep them throughout, and their codes enter
+ * every residual:
+ *     r = W (x - D z),  z = z_prev off S,
+ * which the library forms as r = W (x_eff - D z_S) with x_eff = x - D z_off
+ * (one synthesis of the held codes, in `precision`, before the iterations).
+ * Only the coordinates in S are written back to z; the others are untouched.
+ * Arguments, layouts, ownership and errors as csc_code_step; stats counts the
+ * sample (sampled, nnz of the codes on S). */
+int csc_code_step_hold(csc_handle h, const csc_images *im, const float *x, const uint8_t *W,
+                       const float *d, int K, int m, float *z, double lambda, double p,
+                       uint64_t seed, uint32_t draw, int n_iter, double step, int precision,
+                       csc_code_stats *stats);
+
 /* Filter update.
  * sur == NULL: batch problem eq. (5), n_iter projected-gradient steps
  *     d <- P(d + step * sum_i Z_i^T W_i (x_i - Z_i d)),   P = projection onto ||d_k|| <= 1,

@@ -55,6 +55,11 @@ enum Slot {
     WS_PNORM,
     WS_ADA,
     WS_XPAIRS,
+    WS_HCNT32,
+    WS_HOFF,
+    WS_HPAIRS,
+    WS_HNZC,
+    WS_XE,
     WS_COUNT
 };
 
@@ -729,9 +734,12 @@ extern "C" int csc_mask(csc_handle h, const csc_images *im, int K, double p, uin
     return CSC_OK;
 }
 
-extern "C" int csc_code_step(csc_handle h, const csc_images *im, const float *x, const uint8_t *W, const float *d,
-                             int K, int m, float *z, double lambda, double p, uint64_t seed, uint32_t draw,
-                             int n_iter, double step, int precision, csc_code_stats *stats) {
+// The code update of csc_code_step; hold: the unselected coordinates keep their
+// values (csc_code_step_hold).  Their codes enter every residual through
+// x_eff = x - D z_held, formed once, and only the sample is written back.
+int code_step_impl(csc_ctx *h, const csc_images *im, const float *x, const uint8_t *W, const float *d, int K, int m,
+                   float *z, double lambda, double p, uint64_t seed, uint32_t draw, int n_iter, double step,
+                   int precision, csc_code_stats *stats, bool hold) {
     if (!h) return CSC_EINVAL;
     int st = check_images(h, im);
     if (!st) st = check_filters(h, K, m);
@@ -799,9 +807,39 @@ extern "C" int csc_code_step(csc_handle h, const csc_images *im, const float *x,
     const float feta = (float)eta, fthr = (float)(eta * lambda);
     float *ethr = reinterpret_cast<float *>(sc + SC_ETHR);
     HIPCHK(launch_set2(ethr, feta, fthr, h->stream));
+    const float *xsrc = x;
+    if (hold && n_iter > 0) {
+        // lists of the held codes (non-zero, off the sample), then x_eff = x - D z_held
+        WS(hcnt, unsigned, WS_HCNT32, g.n_pix);
+        WS(hoff, unsigned, WS_HOFF, g.n_pix + 1);
+        {
+            PROF(CSC_PK_LISTS);
+            HIPCHK(launch_count_held(g, K, mw, z, hcnt, h->stream));
+            HIPCHK(launch_scan(hcnt, hoff, g.n_pix, tmp, total, h->stream));
+        }
+        // capacity: every unselected coordinate when that bound is modest, else the exact count
+        unsigned long long hcap = (unsigned long long)K * (unsigned long long)g.n_pix - nsel;
+        if (hcap >= (1ULL << 32) || hcap * sizeof(Pair) > LIST_BOUND_BYTES) {
+            if ((st = read_scalars(h, sc, SC_COUNT))) return st;
+            std::memcpy(&hcap, &h->h_pinned[SC_TOTAL], sizeof(hcap));
+            if (hcap >= (1ULL << 32)) return fail(h, CSC_EUNSUPPORTED, "more than 2^32 held codes");
+        }
+        WS(hp, Pair, WS_HPAIRS, hcap + 1);
+        WS(hc, unsigned short, WS_HNZC, g.n_pix);
+        WS(xe, float, WS_XE, g.n_pix);
+        {
+            PROF(CSC_PK_LISTS);
+            HIPCHK(launch_fill_held(g, K, mw, z, hoff, hp, hc, h->stream));
+        }
+        {
+            PROF(CSC_PK_SYNTH);
+            HIPCHK(synth(h, K, m, Lists{hoff, hc, hp}, d, x, nullptr, xe, SYNTH_RESIDUAL, false, precision));
+        }
+        xsrc = xe;
+    }
     // The n_iter iterations only launch kernels; their step and threshold are
     // read from device scalars, so the same launches can be replayed as a graph.
-    const float *xi = x, *di = d;
+    const float *xi = xsrc, *di = d;
     const uint8_t *Wi = W;
     const bool use_graph = h->graphs && n_iter > 0 &&
                            variant_settled(h, synth_key(h, K, m, SYNTH_RESIDUAL, precision));
@@ -809,7 +847,7 @@ extern "C" int csc_code_step(csc_handle h, const csc_images *im, const float *x,
         // stable copies of the inputs the graph reads
         WS(xc, float, WS_XC, g.n_pix);
         WS(dc, float, WS_DC, (size_t)K * m * m);
-        HIPCHK(hipMemcpyAsync(xc, x, sizeof(float) * g.n_pix, hipMemcpyDeviceToDevice, h->stream));
+        HIPCHK(hipMemcpyAsync(xc, xsrc, sizeof(float) * g.n_pix, hipMemcpyDeviceToDevice, h->stream));
         HIPCHK(hipMemcpyAsync(dc, d, sizeof(float) * K * m * m, hipMemcpyDeviceToDevice, h->stream));
         xi = xc;
         di = dc;
@@ -863,7 +901,8 @@ extern "C" int csc_code_step(csc_handle h, const csc_images *im, const float *x,
     const int cur = n_iter & 1;
     {
         PROF(CSC_PK_SCATTER);
-        HIPCHK(launch_scatter_dense(g, K, Lists{soff, nzc[cur], pairs[cur]}, z, h->stream));
+        if (hold) HIPCHK(launch_scatter_selected(g, K, mw, Lists{soff, nzc[cur], pairs[cur]}, z, h->stream));
+        else HIPCHK(launch_scatter_dense(g, K, Lists{soff, nzc[cur], pairs[cur]}, z, h->stream));
     }
     if (stats) {
         unsigned long long *nnz = reinterpret_cast<unsigned long long *>(sc + SC_NNZ);
@@ -881,6 +920,18 @@ extern "C" int csc_code_step(csc_handle h, const csc_images *im, const float *x,
         stats->step = eta;
     }
     return CSC_OK;
+}
+
+extern "C" int csc_code_step(csc_handle h, const csc_images *im, const float *x, const uint8_t *W, const float *d,
+                             int K, int m, float *z, double lambda, double p, uint64_t seed, uint32_t draw,
+                             int n_iter, double step, int precision, csc_code_stats *stats) {
+    return code_step_impl(h, im, x, W, d, K, m, z, lambda, p, seed, draw, n_iter, step, precision, stats, false);
+}
+
+extern "C" int csc_code_step_hold(csc_handle h, const csc_images *im, const float *x, const uint8_t *W,
+                                  const float *d, int K, int m, float *z, double lambda, double p, uint64_t seed,
+                                  uint32_t draw, int n_iter, double step, int precision, csc_code_stats *stats) {
+    return code_step_impl(h, im, x, W, d, K, m, z, lambda, p, seed, draw, n_iter, step, precision, stats, true);
 }
 
 extern "C" int csc_dict_step(csc_handle h, const csc_images *im, const float *x, const uint8_t *W, const float *z,

@@ -214,6 +214,69 @@ __global__ __launch_bounds__(TPB) void k_scatter_dense(const ImgInfo *imgs, int 
     }
 }
 
+// Held codes (the unselected coordinates keep their values): per pixel, the
+// non-zero codes of z whose coordinate is not in the sample (mask words clear).
+__global__ __launch_bounds__(TPB) void k_count_held(const ImgInfo *imgs, int n_img, long long n_pix, int K,
+                                                    const unsigned *mask_words, const float *z, unsigned *cnt) {
+    PixelCtx c = flat_ctx(imgs, n_img, n_pix);
+    if (!c.valid) return;
+    const long long HW = (long long)c.im.H * c.im.W;
+    const float *zp = z + (long long)K * c.im.pix_off + c.p_img;
+    unsigned nn = 0, bits = 0;
+    for (int k = 0; k < K; ++k) {
+        if ((k & 31) == 0) bits = mask_words[(long long)(k >> 5) * n_pix + c.gp];
+        nn += !((bits >> (k & 31)) & 1u) && zp[(long long)k * HW] != 0.f;
+    }
+    cnt[c.gp] = nn;
+}
+
+__global__ __launch_bounds__(TPB) void k_fill_held(const ImgInfo *imgs, int n_img, long long n_pix, int K,
+                                                   const unsigned *mask_words, const float *z, const unsigned *off,
+                                                   Pair *pairs, unsigned short *cnt) {
+    PixelCtx c = flat_ctx(imgs, n_img, n_pix);
+    if (!c.valid) return;
+    const long long HW = (long long)c.im.H * c.im.W;
+    const float *zp = z + (long long)K * c.im.pix_off + c.p_img;
+    const unsigned base = off[c.gp];
+    unsigned bits = 0;
+    int nn = 0;
+    for (int k = 0; k < K; ++k) {
+        if ((k & 31) == 0) bits = mask_words[(long long)(k >> 5) * n_pix + c.gp];
+        if ((bits >> (k & 31)) & 1u) continue;
+        const float v = zp[(long long)k * HW];
+        if (v != 0.f) {
+            pairs[base + nn] = Pair{k, v};
+            ++nn;
+        }
+    }
+    cnt[c.gp] = (unsigned short)nn;
+}
+
+// z = M^T z~ on the sample only: every selected coordinate takes its list value
+// (0 when absent), the unselected coordinates are left as they are.
+__global__ __launch_bounds__(TPB) void k_scatter_selected(const ImgInfo *imgs, int n_img, long long n_pix, int K,
+                                                          const unsigned *mask_words, Lists zl, float *z) {
+    PixelCtx c = flat_ctx(imgs, n_img, n_pix);
+    if (!c.valid) return;
+    const long long HW = (long long)c.im.H * c.im.W;
+    float *zp = z + (long long)K * c.im.pix_off + c.p_img;
+    const unsigned base = zl.off[c.gp];
+    const int n = zl.cnt[c.gp];
+    int i = 0;
+    Pair e = n > 0 ? zl.pairs[base] : Pair{INT_MAX, 0.f};
+    unsigned bits = 0;
+    for (int k = 0; k < K; ++k) {
+        if ((k & 31) == 0) bits = mask_words[(long long)(k >> 5) * n_pix + c.gp];
+        float v = 0.f;
+        if (e.k == k) {
+            v = e.v;
+            ++i;
+            e = i < n ? zl.pairs[base + i] : Pair{INT_MAX, 0.f};
+        }
+        if ((bits >> (k & 31)) & 1u) zp[(long long)k * HW] = v;
+    }
+}
+
 __global__ void k_sum_counts(const unsigned short *cnt, long long n, unsigned long long *out) {
     __shared__ unsigned long long red[TPB];
     unsigned long long s = 0;
@@ -854,6 +917,27 @@ hipError_t launch_fill_nonzero(const Geometry &g, int K, const float *z, const u
 hipError_t launch_scatter_dense(const Geometry &g, int K, Lists z, float *zout, hipStream_t s) {
     hipLaunchKernelGGL(k_scatter_dense, dim3(flat_grid(g.n_pix)), dim3(TPB), 0, s, g.d_img, g.n_img, g.n_pix, K, z,
                        zout);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_held(const Geometry &g, int K, const unsigned *mask_words, const float *z, unsigned *cnt,
+                             hipStream_t s) {
+    hipLaunchKernelGGL(k_count_held, dim3(flat_grid(g.n_pix)), dim3(TPB), 0, s, g.d_img, g.n_img, g.n_pix, K,
+                       mask_words, z, cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_held(const Geometry &g, int K, const unsigned *mask_words, const float *z, const unsigned *off,
+                            Pair *pairs, unsigned short *cnt, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_held, dim3(flat_grid(g.n_pix)), dim3(TPB), 0, s, g.d_img, g.n_img, g.n_pix, K,
+                       mask_words, z, off, pairs, cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_selected(const Geometry &g, int K, const unsigned *mask_words, Lists zl, float *z,
+                                   hipStream_t s) {
+    hipLaunchKernelGGL(k_scatter_selected, dim3(flat_grid(g.n_pix)), dim3(TPB), 0, s, g.d_img, g.n_img, g.n_pix, K,
+                       mask_words, zl, z);
     return hipGetLastError();
 }
 

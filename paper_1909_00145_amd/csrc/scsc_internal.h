@@ -284,6 +284,14 @@ hipError_t launch_count_nonzero(const Geometry &g, int K, const float *z, unsign
 // xp (may be null): the same entries tagged with their columns for row stride xmul.
 hipError_t launch_fill_nonzero(const Geometry &g, int K, const float *z, const unsigned *off, Pair *pairs,
                                unsigned short *cnt, XPair *xp, unsigned xmul, hipStream_t s);
+// Held codes: lists of the non-zero codes of z off the sample (count, then fill),
+// and the scatter of the sample only (the other coordinates of z unchanged).
+hipError_t launch_count_held(const Geometry &g, int K, const unsigned *mask_words, const float *z, unsigned *cnt,
+                             hipStream_t s);
+hipError_t launch_fill_held(const Geometry &g, int K, const unsigned *mask_words, const float *z, const unsigned *off,
+                            Pair *pairs, unsigned short *cnt, hipStream_t s);
+hipError_t launch_scatter_selected(const Geometry &g, int K, const unsigned *mask_words, Lists zl, float *z,
+                                   hipStream_t s);
 // Selection bytes (csc_mask).
 hipError_t launch_expand_mask(const Geometry &g, int K, const unsigned *mask_words, unsigned char *mask,
                               hipStream_t s);

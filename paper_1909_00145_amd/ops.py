@@ -194,11 +194,13 @@ class Context:
     # ---- hot path -----------------------------------------------------------
 
     def code_step(self, im: Images, x, d, z, lam, p, seed, draw, n_iter, step=0.0, W=None, precision="fp32",
-                  stats=False):
+                  stats=False, hold=False):
+        """hold=True: the unselected coordinates keep their values (csc_code_step_hold)."""
         K, m = int(d.shape[0]), int(d.shape[-1])
         self._sync_stream()
         st = _lib.csc_code_stats()
-        rc = self.lib.csc_code_step(
+        fn = self.lib.csc_code_step_hold if hold else self.lib.csc_code_step
+        rc = fn(
             self.h, im.cref(), _ptr(x, torch.float32, "x", im.n_pix), _ptr(W, torch.uint8, "W", im.n_pix),
             _ptr(d, torch.float32, "d", K * m * m), K, m, _ptr(z, torch.float32, "z", K * im.n_pix),
             float(lam), float(p), int(seed) & (2**64 - 1), int(draw) & (2**32 - 1), int(n_iter), float(step),
