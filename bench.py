@@ -14,7 +14,9 @@ outer iteration instead.
 
 Metric: selected code-coordinate updates per second = sum over the timed
 steps of (iterations x |S|) / wall time, with the inputs resident in HBM.
-Prints one JSON line.
+Prints one JSON line.  Its ``hold_vs_project`` object compares, on the batch
+workload, the objective against training time with the unselected codes zeroed
+(eq. 4) and held (the randomization paragraph of Sec. 3.1).
 """
 
 from __future__ import annotations
@@ -100,6 +102,10 @@ def parse():
     ap.add_argument("--tto", action="store_true",
                     help="also measure time-to-objective of online learning, FP32 against BF16 (adds ~1 min)")
     ap.add_argument("--tto-batches", type=int, default=100, help="mini-batches of the time-to-objective run")
+    ap.add_argument("--no-hold-compare", action="store_true",
+                    help="skip the batch-workload comparison of the objective against training time with the "
+                         "unselected codes held (HOLD) and zeroed (PROJECT); about a second on one GPU")
+    ap.add_argument("--hold-iters", type=int, default=60, help="outer iterations of the HOLD/PROJECT comparison")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="after the timed steps, copy a buffer of this many MiB 3 times (a traffic-counter "
                          "calibration kernel of known size; outside the timed region)")
@@ -192,6 +198,54 @@ def time_to_objective(ctx, w, n_batches):
                      "final_F": curve[-1][1], "train_seconds": curve[-1][0],
                      "max_rel_dev_from_fp32": max(abs(F - r) / abs(r) for (_, F), r in zip(curve, ref)),
                      "F_every_10": [round(F, 3) for _, F in curve[9::10]]}
+    return out
+
+
+def hold_vs_project(ctx, w, n_outer, precision):
+    """Batch learning (Alg. 1) on the batch workload with the unselected codes
+    zeroed (PROJECT, eq. 4) and held (HOLD, Sec. 3.1), from the same filters and
+    the same samples.  After every outer iteration the objective of eq. (1) over
+    the batch is evaluated with the clock stopped; reports both curves against
+    training time and the objectives at the time the faster mode finishes."""
+    import torch
+
+    import scsc_inputs as si
+    from paper_1909_00145_amd.drivers import BatchLearner
+    from paper_1909_00145_amd.ops import Images
+
+    K, m, N, H, W = w["K"], w["m"], w["N"], w["H"], w["W"]
+    im = Images.uniform(N, H, W)
+    x = torch.from_numpy(si.batch(w["cfg"], N, H, W).astype(np.float32).reshape(-1)).cuda()
+    curves = {}
+    for mode in ("project", "hold"):
+        d = torch.from_numpy(si.filters(w["cfg"], K, m).astype(np.float32)).cuda()
+        learner = BatchLearner(ctx, im, x, d, w["lam"], w["p"], n_code_iter=w["T"], precision=precision,
+                               hold=mode == "hold")
+        elapsed, curve = 0.0, []
+        for _ in range(n_outer):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            learner.step()
+            torch.cuda.synchronize()
+            elapsed += time.perf_counter() - t0
+            curve.append((elapsed, learner.objective()[0]))
+        curves[mode] = curve
+
+    def at(curve, t):
+        """Objective of the last evaluation at or before time t."""
+        F = curve[0][1]
+        for el, f in curve:
+            if el <= t:
+                F = f
+        return F
+
+    t_eq = min(c[-1][0] for c in curves.values())
+    out = {"workload": w["name"], "precision": precision, "outer_iterations": n_outer,
+           "eval": "objective of eq. (1) over the batch after each outer iteration (clock stopped)",
+           "equal_time_s": t_eq}
+    for mode, c in curves.items():
+        out[mode] = {"train_seconds": c[-1][0], "ms_per_outer": 1e3 * c[-1][0] / n_outer, "final_F": c[-1][1],
+                     "F_at_equal_time": at(c, t_eq), "F_every_10": [round(f, 2) for _, f in c[9::10]]}
     return out
 
 
@@ -406,6 +460,8 @@ def main():
             "kernels_avg_us": {k: round(v["avg_us"], 1) for k, v in p2["kernels"].items()}}
     if args.tto:
         out["time_to_objective"] = time_to_objective(ctx, WORKLOADS["online"], args.tto_batches)
+    if not args.no_hold_compare:
+        out["hold_vs_project"] = hold_vs_project(ctx, WORKLOADS["batch"], args.hold_iters, args.precision)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds, [tuple(hw) for hw in im.hw])
     print(json.dumps(out), flush=True)

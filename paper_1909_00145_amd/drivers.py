@@ -16,14 +16,16 @@ from .ops import Context, Images, Surrogate
 
 class BatchLearner:
     """Stochastic batch CSC (Alg. 1): codes of every image are kept across outer
-    iterations and warm-started on the new sample."""
+    iterations and warm-started on the new sample.  hold=True keeps the codes off
+    the sample as they are (the HOLD reading of Sec. 3.1) instead of zeroing them."""
 
     def __init__(self, ctx: Context, im: Images, x, d, lam: float, p: float, n_code_iter: int = 20,
-                 seed: int = 1, n_dict_iter: int = 1, n_power: int = 20, W=None, precision: str = "fp32"):
+                 seed: int = 1, n_dict_iter: int = 1, n_power: int = 20, W=None, precision: str = "fp32",
+                 hold: bool = False):
         self.ctx, self.im, self.x, self.d, self.W = ctx, im, x, d, W
         self.K, self.m = int(d.shape[0]), int(d.shape[-1])
         self.lam, self.p, self.T, self.seed = lam, p, n_code_iter, seed
-        self.n_dict_iter, self.n_power, self.precision = n_dict_iter, n_power, precision
+        self.n_dict_iter, self.n_power, self.precision, self.hold = n_dict_iter, n_power, precision, hold
         self.z = torch.zeros(self.K * im.n_pix, dtype=torch.float32, device=x.device)
         self.t = 0
 
@@ -31,7 +33,7 @@ class BatchLearner:
         """One outer iteration: sample, code update for every image, filter update."""
         self.t += 1
         st = self.ctx.code_step(self.im, self.x, self.d, self.z, self.lam, self.p, self.seed, self.t, self.T,
-                                W=self.W, precision=self.precision, stats=True)
+                                W=self.W, precision=self.precision, stats=True, hold=self.hold)
         Ld = self.ctx.dict_step(self.im, self.x, self.z, self.d, n_iter=self.n_dict_iter, n_power=self.n_power,
                                 W=self.W, precision=self.precision)
         return st, Ld
