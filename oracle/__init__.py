@@ -30,12 +30,14 @@ from .csc import (  # noqa: F401
     dict_step_batch,
     dict_step_online,
     filter_corr,
+    inpaint,
     lipschitz_code,
     lipschitz_filter,
     normal_matvec,
     pad_codes,
     objective,
     project_ball,
+    psnr,
     sample_threshold,
     soft_threshold,
     surrogate_increment,

@@ -264,6 +264,36 @@ def objective(xs, d, zs, lam: float, Ws=None):
 
 
 # ---------------------------------------------------------------------------
+# Inpainting (Sec. 4, over-complete dictionaries): reconstruction from a part
+# of the pixels
+# ---------------------------------------------------------------------------
+
+
+def inpaint(x, W, d, lam: float, n_iter: int, step: float | None = None, max_side: int | None = None):
+    """Reconstruction of a full image from its observed pixels (W = 1).
+
+    The codes solve the masked problem of eq. (1), min_z 1/2 ||W (x - D z)||^2 +
+    lam ||z||_1, over every coordinate (p = 1), by n_iter proximal-gradient
+    iterations from zero (the paper runs ADMM here); the reconstruction is D z on
+    all pixels.  Only x's observed pixels are read.  Returns (x_hat, z)."""
+    K = d.shape[0]
+    H, Wd = x.shape
+    xo = np.where(W != 0, x, 0.0)
+    z, _ = code_step(xo, d, np.zeros((K, H, Wd)), lam, 1.0, 0, 0, n_iter, step=step, W=W, max_side=max_side)
+    return synthesize(d, z), z
+
+
+def psnr(x_hat, x) -> float:
+    """Peak signal-to-noise ratio of x_hat against x in dB over all pixels, with the
+    peak taken as the dynamic range max(x) - min(x) of the original."""
+    x = np.asarray(x, dtype=np.float64)
+    err = np.asarray(x_hat, dtype=np.float64) - x
+    mse = float(np.mean(err * err))
+    peak = float(np.max(x) - np.min(x))
+    return 10.0 * math.log10(peak * peak / mse) if mse > 0 else math.inf
+
+
+# ---------------------------------------------------------------------------
 # Filter update: eq. (5) (batch) and eqs. (8)-(9) (online)
 # ---------------------------------------------------------------------------
 
