@@ -16,7 +16,9 @@ Metric: selected code-coordinate updates per second = sum over the timed
 steps of (iterations x |S|) / wall time, with the inputs resident in HBM.
 Prints one JSON line.  Its ``hold_vs_project`` object compares, on the batch
 workload, the objective against training time with the unselected codes zeroed
-(eq. 4) and held (the randomization paragraph of Sec. 3.1).
+(eq. 4) and held (the randomization paragraph of Sec. 3.1); its ``inpainting``
+object reports the reconstruction PSNR from half of the pixels (Sec. 4) with
+filters learned online.
 """
 
 from __future__ import annotations
@@ -106,6 +108,10 @@ def parse():
                     help="skip the batch-workload comparison of the objective against training time with the "
                          "unselected codes held (HOLD) and zeroed (PROJECT); about a second on one GPU")
     ap.add_argument("--hold-iters", type=int, default=60, help="outer iterations of the HOLD/PROJECT comparison")
+    ap.add_argument("--no-inpaint", action="store_true",
+                    help="skip the inpainting leg (10 synthetic 256x256 images, 50 %% observed, lambda 0.4, "
+                         "50 iterations, 5 trials, with filters learned online); a few seconds")
+    ap.add_argument("--inpaint-train", type=int, default=60, help="mini-batches of online learning before inpainting")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="after the timed steps, copy a buffer of this many MiB 3 times (a traffic-counter "
                          "calibration kernel of known size; outside the timed region)")
@@ -247,6 +253,53 @@ def hold_vs_project(ctx, w, n_outer, precision):
         out[mode] = {"train_seconds": c[-1][0], "ms_per_outer": 1e3 * c[-1][0] / n_outer, "final_F": c[-1][1],
                      "F_at_equal_time": at(c, t_eq), "F_every_10": [round(f, 2) for _, f in c[9::10]]}
     return out
+
+
+def inpainting(ctx, w, n_train, precision):
+    """Inpainting as in Sec. 4: 10 held-out synthetic 256 x 256 images, each pixel
+    observed with probability 0.5, codes of the masked problem over every
+    coordinate (lambda = 0.4, 50 iterations from zero), reconstruction D z.  PSNR
+    (peak = the original's dynamic range, all pixels) averaged over the images
+    and 5 observation masks, for the filters after n_train mini-batches of online
+    learning (the online workload's stream and settings), for the initial filters,
+    and for filling the unobserved pixels with zeros."""
+    import torch
+
+    import scsc_inputs as si
+    from paper_1909_00145_amd.drivers import OnlineLearner, inpaint, psnr
+    from paper_1909_00145_amd.ops import Images
+
+    K, m, N, H, W = w["K"], w["m"], w["N"], w["H"], w["W"]
+    d0 = torch.from_numpy(si.filters(w["cfg"], K, m).astype(np.float32)).cuda()
+    learner = OnlineLearner(ctx, Images.uniform(N, H, W), d0.clone(), w["lam"], w["p"], n_code_iter=w["T"],
+                            precision=precision)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for t in range(1, n_train + 1):
+        learner.step(torch.from_numpy(si.stream_batch(w["cfg"], t, N, H, W).astype(np.float32).reshape(-1)).cuda())
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    NT, HT, WT, trials, lam, iters = 10, 256, 256, 5, 0.4, 50
+    im = Images.uniform(NT, HT, WT)
+    x = torch.from_numpy(si.batch(33, NT, HT, WT).astype(np.float32).reshape(-1)).cuda()
+    res = {"learned": [], "initial": [], "zero_fill": []}
+    times = []
+    for tr in range(trials):
+        Wm = torch.from_numpy(np.stack([si.observation_mask(50 + tr, n, HT, WT) for n in range(NT)])
+                              .reshape(-1)).cuda()
+        res["zero_fill"] += psnr(im, x * Wm, x)
+        for name, d in (("learned", learner.d), ("initial", d0)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            xh, _ = inpaint(ctx, im, x, Wm, d, lam, iters, precision=precision)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+            res[name] += psnr(im, xh, x)
+    return {"images": "%d held-out synthetic %dx%d fields (1/f^2)" % (NT, HT, WT), "observed": 0.5,
+            "lambda": lam, "iterations": iters, "trials": trials, "precision": precision,
+            "train": "%d online mini-batches (%.2f s)" % (n_train, train_s),
+            "psnr_db": {k: round(float(np.mean(v)), 3) for k, v in res.items()},
+            "ms_per_reconstruction": round(1e3 * float(np.median(times)), 1)}
 
 
 def main():
@@ -462,6 +515,8 @@ def main():
         out["time_to_objective"] = time_to_objective(ctx, WORKLOADS["online"], args.tto_batches)
     if not args.no_hold_compare:
         out["hold_vs_project"] = hold_vs_project(ctx, WORKLOADS["batch"], args.hold_iters, args.precision)
+    if not args.no_inpaint:
+        out["inpainting"] = inpainting(ctx, WORKLOADS["online"], args.inpaint_train, args.precision)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds, [tuple(hw) for hw in im.hw])
     print(json.dumps(out), flush=True)

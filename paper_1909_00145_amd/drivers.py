@@ -9,6 +9,8 @@ batch dimension of every call.
 
 from __future__ import annotations
 
+import math
+
 import torch
 
 from .ops import Context, Images, Surrogate
@@ -83,3 +85,30 @@ class OnlineLearner:
     def load_state_dict(self, sd):
         self.d.copy_(sd["d"])
         self.sur.load_state_dict(sd["sur"])
+
+
+def inpaint(ctx: Context, im: Images, x, W, d, lam: float = 0.4, n_iter: int = 50, precision: str = "fp32"):
+    """Reconstruction of every image of the batch from its observed pixels (W = 1),
+    as in the inpainting experiment of Sec. 4: codes of the masked problem of
+    eq. (1) over every coordinate (p = 1) by n_iter proximal-gradient iterations
+    from zero, then D z on all pixels.  The unobserved pixels of x are not used.
+    Returns (x_hat, z), packed like x and z."""
+    K = int(d.shape[0])
+    z = torch.zeros(K * im.n_pix, dtype=torch.float32, device=x.device)
+    ctx.code_step(im, x, d, z, lam, 1.0, 0, 0, n_iter, W=W, precision=precision)
+    return ctx.synthesize(im, d, z, precision=precision), z
+
+
+def psnr(im: Images, x_hat, x):
+    """Per-image PSNR (dB) of x_hat against x over all pixels, with the peak taken as
+    the dynamic range max(x) - min(x) of the original image (an evaluation in
+    FP64 on the device)."""
+    out = []
+    for i, (H, W) in enumerate(im.hw):
+        o = int(im.offsets[i])
+        a = x[o:o + H * W].double()
+        e = x_hat[o:o + H * W].double() - a
+        mse = float((e * e).mean())
+        peak = float(a.max() - a.min())
+        out.append(10.0 * math.log10(peak * peak / mse) if mse > 0 else math.inf)
+    return out
