@@ -112,6 +112,12 @@ def parse():
                     help="skip the inpainting leg (10 synthetic 256x256 images, 50 %% observed, lambda 0.4, "
                          "50 iterations, 5 trials, with filters learned online); a few seconds")
     ap.add_argument("--inpaint-train", type=int, default=60, help="mini-batches of online learning before inpainting")
+    ap.add_argument("--eta-sweep", default="",
+                    help="comma-separated mini-batch sizes: online learning of an over-complete dictionary "
+                         "(--sweep-K filters) over the same --sweep-samples images for each size, with the "
+                         "held-out objective against training time (e.g. 1,5,20,50)")
+    ap.add_argument("--sweep-K", type=int, default=400)
+    ap.add_argument("--sweep-samples", type=int, default=200)
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="after the timed steps, copy a buffer of this many MiB 3 times (a traffic-counter "
                          "calibration kernel of known size; outside the timed region)")
@@ -300,6 +306,48 @@ def inpainting(ctx, w, n_train, precision):
             "train": "%d online mini-batches (%.2f s)" % (n_train, train_s),
             "psnr_db": {k: round(float(np.mean(v)), 3) for k, v in res.items()},
             "ms_per_reconstruction": round(1e3 * float(np.median(times)), 1)}
+
+
+def eta_sweep(ctx, w, K, etas, n_samples, precision):
+    """Mini-batch size sweep of online learning (Alg. 2 with mini-batches of eta
+    images; the over-complete experiment of Sec. 4): for each eta, K filters from
+    the same initial bank learn from the same stream of n_samples images.  About ten
+    times per run the held-out objective (20 images, codes from zero at p = 1, 50
+    FP32 iterations) is evaluated with the clock stopped."""
+    import torch
+
+    import scsc_inputs as si
+    from paper_1909_00145_amd.drivers import OnlineLearner
+    from paper_1909_00145_amd.ops import Images
+
+    m, H, W = w["m"], w["H"], w["W"]
+    stream = si.batch(w["cfg"], n_samples, H, W).astype(np.float32)
+    held = torch.from_numpy(si.batch(33, 20, H, W).astype(np.float32).reshape(-1)).cuda()
+    him = Images.uniform(20, H, W)
+    out = {"K": K, "m": m, "images": "%dx%d" % (H, W), "samples": n_samples, "precision": precision,
+           "eval": "held-out objective of eq. (1): 20 images, codes from zero at p = 1, 50 FP32 iterations"}
+    for eta in etas:
+        im = Images.uniform(eta, H, W)
+        d = torch.from_numpy(si.filters(w["cfg"], K, m).astype(np.float32)).cuda()
+        learner = OnlineLearner(ctx, im, d, w["lam"], w["p"], n_code_iter=w["T"], precision=precision)
+        steps = n_samples // eta
+        every = max(1, steps // 10)
+        elapsed, curve = 0.0, []
+        for t in range(steps):
+            x = torch.from_numpy(stream[t * eta:(t + 1) * eta].reshape(-1)).cuda()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            learner.step(x)
+            torch.cuda.synchronize()
+            elapsed += time.perf_counter() - t0
+            if (t + 1) % every == 0 or t == steps - 1:
+                curve.append(((t + 1) * eta, round(elapsed, 4), round(learner.evaluate(him, held)[0], 2)))
+        out["eta_%d" % eta] = {"steps": steps, "ms_per_step": round(1e3 * elapsed / steps, 2),
+                               "train_seconds": round(elapsed, 3), "final_F": curve[-1][2],
+                               "curve_samples_seconds_F": curve}
+        del learner
+        torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -517,6 +565,9 @@ def main():
         out["hold_vs_project"] = hold_vs_project(ctx, WORKLOADS["batch"], args.hold_iters, args.precision)
     if not args.no_inpaint:
         out["inpainting"] = inpainting(ctx, WORKLOADS["online"], args.inpaint_train, args.precision)
+    if args.eta_sweep:
+        out["eta_sweep"] = eta_sweep(ctx, WORKLOADS["online"], args.sweep_K,
+                                     [int(v) for v in args.eta_sweep.split(",")], args.sweep_samples, args.precision)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds, [tuple(hw) for hw in im.hw])
     print(json.dumps(out), flush=True)

@@ -1,0 +1,62 @@
+"""Over-complete dictionaries in the online filter step (the K = 400 experiment
+of Sec. 4), against the oracle computed matrix-free.
+
+The dense oracle surrogate would hold (K m^2)^2 doubles (18.7 GB at K = 400,
+m = 11), so the reference filter update is formed from oracle primitives:
+C_bar d = sum_n Z_n^T (Z_n d) = sum_n filter_corr(z_n, synthesize(d, z_n)),
+B_bar = sum_n filter_corr(z_n, x_n), and L_d from the oracle's power iteration
+on the zero-padded normal matrix.  Two mini-batches check the accumulation.
+K = 400 with m = 11 runs the filter-major lag pass with one filter per chunk;
+K = 1000 with m = 5 does not fit it and runs the pixel-slot pass.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from tests.gpu_helpers import f32, make_problem, packed, rel_err, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+TOL32 = 1e-5
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1909_00145_amd.ops import Context
+
+    torch.cuda.set_device(0)
+    c = Context(0)
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("K,m,hw", [(400, 11, [(24, 20), (17, 30)]), (1000, 5, [(20, 18)])])
+def test_online_step_overcomplete(ctx, K, m, hw):
+    from paper_1909_00145_amd.ops import Images, Surrogate
+
+    say("over-complete online", K, m, hw)
+    im = Images(hw)
+    _, d, _ = make_problem(8, hw, K, m)
+    d = f32(oracle.project_ball(d))
+    sur = Surrogate(K, m)
+    dg = to_dev(d)
+    dr = d.copy()
+    Cz, Bsum, Ld_sum = [], np.zeros((K, m, m)), 0.0
+    for t in range(2):
+        rng = np.random.default_rng(100 + t)
+        xs = [f32(rng.standard_normal((H, W))) for H, W in hw]
+        zs = [f32(rng.standard_normal((K, H, W)) * (rng.random((K, H, W)) < 0.03)) for H, W in hw]
+        ctx.dict_step(im, packed(im, xs), packed(im, zs), dg, surrogate=sur)
+        Cz += zs
+        Bsum += sum(oracle.filter_corr(z, x, m) for z, x in zip(zs, xs))
+        Ld_sum += oracle.lipschitz_filter(zs, None, K, m)
+        Cd = sum(oracle.filter_corr(z, oracle.synthesize(dr, z), m) for z in Cz)
+        dr = oracle.project_ball(dr - (Cd - Bsum) / Ld_sum)
+        err = rel_err(dg.cpu().numpy(), dr)
+        say("  step", t + 1, "d rel err", err, "Ld_sum", sur.Ld_sum, Ld_sum)
+        assert rel_err(sur.B.cpu().numpy(), Bsum.ravel()) < 1e-12
+        assert abs(sur.Ld_sum - Ld_sum) <= 1e-5 * Ld_sum
+        assert err < TOL32
+        dr = f32(dg.cpu().numpy())  # continue from the GPU's FP32 filters
