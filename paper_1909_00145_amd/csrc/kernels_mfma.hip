@@ -220,6 +220,9 @@ __global__ __launch_bounds__(TPB) void k_synth_mfma(const ImgInfo *imgs, const T
     int ebeg;
     const int total = block_exclusive_scan(ntot, &ebeg, wsum);
     const bool staged = total <= SM_CAP;  // uniform over the block
+    int cur[NPT];  // per-pixel list positions of the unstaged path
+#pragma unroll
+    for (int q = 0; q < NPT; ++q) cur[q] = 0;
     if (staged) {
         // this thread's entries, flattened over its pixels, SM_LB loads in flight
         for (int j0 = 0; j0 < ntot; j0 += SM_LB) {
@@ -288,16 +291,18 @@ __global__ __launch_bounds__(TPB) void k_synth_mfma(const ImgInfo *imgs, const T
                 }
             }
         } else {
+            // the lists are sorted by k and the chunks advance in k: one cursor per
+            // pixel reads each entry once over the whole loop (plus one look-ahead)
 #pragma unroll
             for (int q = 0; q < NPT; ++q) {
                 const int pix = threadIdx.x + q * TPB;
                 const int yr = pix / RW, xr = pix % RW;
-                for (int j = 0; j < pn[q]; ++j) {
-                    const Pair pr = zl.pairs[po[q] + j];
-                    if ((unsigned)pr.k >= k0 && (unsigned)pr.k < k1) {
-                        const int kl = pr.k - (int)k0;
-                        zt[(((kl >> 3) * RW + yr) * ZC + xr) * 8 + (kl & 7)] = (__bf16)pr.v;
-                    }
+                while (cur[q] < pn[q]) {
+                    const Pair pr = zl.pairs[po[q] + cur[q]];
+                    if ((unsigned)pr.k >= k1) break;
+                    const int kl = pr.k - (int)k0;
+                    zt[(((kl >> 3) * RW + yr) * ZC + xr) * 8 + (kl & 7)] = (__bf16)pr.v;
+                    ++cur[q];
                 }
             }
         }
