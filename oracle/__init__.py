@@ -26,6 +26,7 @@ from .csc import (  # noqa: F401
     bernoulli_mask,
     code_matrix,
     code_step,
+    code_step_admm,
     dft_size,
     dict_step_batch,
     dict_step_online,

@@ -246,6 +246,77 @@ def code_step(
     return z, S
 
 
+def code_step_admm(
+    x: np.ndarray,
+    d: np.ndarray,
+    z_prev: np.ndarray,
+    lam: float,
+    p: float,
+    seed: int,
+    draw: int,
+    n_admm: int = 10,
+    n_cg: int = 5,
+    rho: float | None = None,
+    alpha: float = 1.8,
+    W: np.ndarray | None = None,
+    image_index: int = 0,
+):
+    """The paper's code solver for the subsampled LASSO of eq. (3) (Sec. 3.2, the
+    paragraph after Alg. 1): ADMM splitting the data term from the L1 term, the
+    quadratic substep solved by conjugate gradient, the L1 substep by shrinkage,
+    with over-relaxation alpha and penalty rho = 10 lambda.  Returns (z_new, S).
+
+    With A = W D M^T (the sampled columns of D, rows weighted by the observation
+    mask), scaled dual u and split variable v, each of the n_admm iterations is
+        zt = argmin 1/2 ||W x - A zt||^2 + rho/2 ||zt - v + u||^2
+             (n_cg CG iterations on (A^T A + rho I) zt = A^T W x + rho (v - u),
+              warm-started from the previous zt),
+        zh = alpha zt + (1 - alpha) v,
+        v  = S_{lambda/rho}(zh + u),
+        u  = u + zh - v.
+    zt and v start from z_prev restricted to S, u from 0; the result is v on S and
+    zero elsewhere (eq. 4)."""
+    K = d.shape[0]
+    H, Wd = x.shape
+    S = bernoulli_mask(K, H, Wd, p, seed, draw, image_index)
+    rho = 10.0 * lam if rho is None else rho
+    Wm = np.ones_like(x) if W is None else W.astype(np.float64)
+
+    def A(v):  # S-restricted codes -> weighted image
+        return Wm * synthesize(d, np.where(S, v, 0.0))
+
+    def At(r):  # image -> codes on S
+        return np.where(S, adjoint(d, Wm * r), 0.0)
+
+    def op(v):
+        return At(A(v)) + rho * v
+
+    zt = np.where(S, z_prev, 0.0)
+    v = zt.copy()
+    u = np.zeros_like(zt)
+    b0 = At(x)
+    for _ in range(n_admm):
+        # conjugate gradient, warm start at the previous zt
+        b = b0 + rho * (v - u)
+        r = b - op(zt)
+        q = r.copy()
+        rr = float(np.sum(r * r))
+        for _ in range(n_cg):
+            if rr == 0.0:
+                break
+            Aq = op(q)
+            a = rr / float(np.sum(q * Aq))
+            zt = zt + a * q
+            r = r - a * Aq
+            rr_new = float(np.sum(r * r))
+            q = r + (rr_new / rr) * q
+            rr = rr_new
+        zh = alpha * zt + (1.0 - alpha) * v
+        v = np.where(S, soft_threshold(zh + u, lam / rho), 0.0)
+        u = u + zh - v
+    return v, S
+
+
 # ---------------------------------------------------------------------------
 # Objective (eq. 1, summed over the images)
 # ---------------------------------------------------------------------------

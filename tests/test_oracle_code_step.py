@@ -193,3 +193,65 @@ def test_hold_objective_monotone(rng):
         f = oracle.objective([x], d, [z], lam)[0]
         assert f <= prev + 1e-12 * abs(prev)
         prev = f
+
+
+# ADMM (the paper's code solver, Sec. 3.2)
+def test_admm_delta_filter_converges_to_shrinkage(rng):
+    """D = I: the subsampled LASSO's solution is S_lambda(x) on the sample."""
+    H, W, m = 9, 8, 3
+    d = np.zeros((1, m, m))
+    d[0, 1, 1] = 1.0
+    x = rng.standard_normal((H, W)) * 2
+    lam = 0.5
+    z, S = oracle.code_step_admm(x, d, np.zeros((1, H, W)), lam, 0.4, 3, 1, n_admm=200, n_cg=2)
+    np.testing.assert_allclose(z[0], np.where(S[0], soft_threshold(x, lam), 0.0), atol=1e-10)
+
+
+def test_admm_converged_matches_sklearn_lasso(rng):
+    from sklearn.linear_model import Lasso
+
+    K, m, H, W = 2, 3, 6, 5
+    d = oracle.project_ball(rng.standard_normal((K, m, m)))
+    x = rng.standard_normal((H, W))
+    lam, p = 0.15, 0.6
+    z, S = oracle.code_step_admm(x, d, np.zeros((K, H, W)), lam, p, 21, 4, n_admm=3000, n_cg=30)
+    D = explicit_D(d, H, W)
+    cols = S.reshape(-1)
+    A = D[:, cols]
+    las = Lasso(alpha=lam / A.shape[0], fit_intercept=False, tol=1e-14, max_iter=1000000)
+    las.fit(A, x.ravel())
+    ref = np.zeros(K * H * W)
+    ref[cols] = las.coef_
+    np.testing.assert_allclose(z.ravel(), ref, atol=1e-7, rtol=0)
+
+
+def test_admm_cg_solves_the_quadratic_substep(rng):
+    """With enough CG iterations, the first ADMM step's zt solves (A^T A + rho I) zt = A^T x
+    exactly (zero start): check the returned v against the shrinkage of the explicit solve."""
+    K, m, H, W = 2, 3, 5, 6
+    d = oracle.project_ball(rng.standard_normal((K, m, m)))
+    x = rng.standard_normal((H, W))
+    lam, p, alpha = 0.2, 0.7, 1.8
+    rho = 10 * lam
+    z, S = oracle.code_step_admm(x, d, np.zeros((K, H, W)), lam, p, 5, 2, n_admm=1, n_cg=200, alpha=alpha)
+    D = explicit_D(d, H, W)
+    cols = S.reshape(-1)
+    A = D[:, cols]
+    zt = np.linalg.solve(A.T @ A + rho * np.eye(A.shape[1]), A.T @ x.ravel())
+    v = soft_threshold(alpha * zt, lam / rho)  # v0 = u0 = 0
+    ref = np.zeros(K * H * W)
+    ref[cols] = v
+    np.testing.assert_allclose(z.ravel(), ref, atol=1e-10)
+
+
+def test_admm_with_mask_reduces_masked_objective(rng):
+    K, m, H, W = 3, 5, 12, 11
+    d = oracle.project_ball(rng.standard_normal((K, m, m)))
+    x = rng.standard_normal((H, W))
+    Wm = (rng.random((H, W)) < 0.6).astype(np.uint8)
+    lam = 0.2
+    z, S = oracle.code_step_admm(x, d, np.zeros((K, H, W)), lam, 0.5, 9, 1, W=Wm)
+    f0 = oracle.objective([x], d, [np.zeros((K, H, W))], lam, [Wm])[0]
+    f1 = oracle.objective([x], d, [z], lam, [Wm])[0]
+    assert f1 < 0.9 * f0
+    assert np.all(z[~S] == 0)
