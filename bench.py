@@ -112,6 +112,9 @@ def parse():
                     help="skip the inpainting leg (10 synthetic 256x256 images, 50 %% observed, lambda 0.4, "
                          "50 iterations, 5 trials, with filters learned online); a few seconds")
     ap.add_argument("--inpaint-train", type=int, default=60, help="mini-batches of online learning before inpainting")
+    ap.add_argument("--no-solver-compare", action="store_true",
+                    help="skip the code-solver comparison on one mini-batch: ISTA against the paper's ADMM "
+                         "(rho = 10 lambda, alpha = 1.8, 5 CG iterations per step), FP32")
     ap.add_argument("--eta-sweep", default="",
                     help="comma-separated mini-batch sizes: online learning of an over-complete dictionary "
                          "(--sweep-K filters) over the same --sweep-samples images for each size, with the "
@@ -350,6 +353,49 @@ def eta_sweep(ctx, w, K, etas, n_samples, precision):
     return out
 
 
+def solver_compare(ctx, w):
+    """Code solvers on one mini-batch of the online workload from zero codes, FP32:
+    ISTA (the path's solver) for several iteration counts against the paper's ADMM
+    (Sec. 3.2: rho = 10 lambda, alpha = 1.8, CG for the quadratic substep) for
+    several ADMM iteration counts.  Reports the time of each code update and the
+    objective of eq. (1) over the batch of the codes it returns (p = 0.1 sample)."""
+    import torch
+
+    import scsc_inputs as si
+    from paper_1909_00145_amd.ops import Images
+
+    K, m, N, H, W = w["K"], w["m"], w["N"], w["H"], w["W"]
+    im = Images.uniform(N, H, W)
+    x = torch.from_numpy(si.stream_batch(w["cfg"], 1, N, H, W).astype(np.float32).reshape(-1)).cuda()
+    d = torch.from_numpy(si.filters(w["cfg"], K, m).astype(np.float32)).cuda()
+    z = torch.zeros(K * im.n_pix, dtype=torch.float32, device="cuda")
+
+    def timed(fn):
+        fn()  # first call sizes the workspaces
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        return 1e3 * (time.perf_counter() - t0)
+
+    out = {"batch": "%d images %dx%d, K=%d, %dx%d, p=%g, lambda=%g, from zero codes, FP32" % (N, H, W, K, m, m,
+                                                                                             w["p"], w["lam"]),
+           "objective": "eq. (1) over the batch"}
+    for T in (5, 10, 20, 40):
+        def run():
+            z.zero_()
+            ctx.code_step(im, x, d, z, w["lam"], w["p"], 1, 1, T)
+        ms = timed(run)
+        out["ista_%d" % T] = {"ms": round(ms, 2), "F": round(ctx.objective(im, x, d, z, w["lam"])[0], 2)}
+    for n_admm in (2, 5, 10, 20):
+        def run():
+            z.zero_()
+            ctx.code_step_admm(im, x, d, z, w["lam"], w["p"], 1, 1, n_admm, 5)
+        ms = timed(run)
+        out["admm_%d" % n_admm] = {"ms": round(ms, 2), "F": round(ctx.objective(im, x, d, z, w["lam"])[0], 2)}
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -565,6 +611,8 @@ def main():
         out["hold_vs_project"] = hold_vs_project(ctx, WORKLOADS["batch"], args.hold_iters, args.precision)
     if not args.no_inpaint:
         out["inpainting"] = inpainting(ctx, WORKLOADS["online"], args.inpaint_train, args.precision)
+    if not args.no_solver_compare:
+        out["solver_compare"] = solver_compare(ctx, WORKLOADS["online"])
     if args.eta_sweep:
         out["eta_sweep"] = eta_sweep(ctx, WORKLOADS["online"], args.sweep_K,
                                      [int(v) for v in args.eta_sweep.split(",")], args.sweep_samples, args.precision)

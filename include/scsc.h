@@ -155,6 +155,25 @@ int csc_code_step_hold(csc_handle h, const csc_images *im, const float *x, const
                        uint64_t seed, uint32_t draw, int n_iter, double step, int precision,
                        csc_code_stats *stats);
 
+/* Code update by the paper's solver (Sec. 3.2, the paragraph after Alg. 1): ADMM
+ * on the subsampled LASSO of eq. (3), splitting the data term from the L1 term.
+ * With A = W D M^T restricted to the selection S (drawn as in csc_code_step),
+ * scaled dual u and split variable v, each of n_admm iterations does
+ *     zt: n_cg conjugate-gradient iterations on (A^T A + rho I) zt = A^T W x + rho (v - u),
+ *         warm-started from the previous zt;
+ *     zh = alpha zt + (1 - alpha) v   (over-relaxation);
+ *     v  = sign(zh + u) max(|zh + u| - lambda / rho, 0);   u = u + zh - v.
+ * zt and v start from z restricted to S, u from 0; v is written back (zero off S).
+ *   rho   : > 0, or <= 0 for the paper's 10 * lambda (then lambda must be > 0).
+ *   alpha : in (0, 2); the paper uses 1.8.   n_admm, n_cg >= 0 (the paper: 10 ADMM iterations).
+ *   FP32 throughout (the CG dot products in FP64, their scalars in device memory).
+ *   stats : sampled = |S|, nnz of the result, step = rho; L_z and nnz_iter_sum are 0.
+ * Other arguments, layouts, ownership and errors as csc_code_step. */
+int csc_code_step_admm(csc_handle h, const csc_images *im, const float *x, const uint8_t *W,
+                       const float *d, int K, int m, float *z, double lambda, double p,
+                       uint64_t seed, uint32_t draw, int n_admm, int n_cg, double rho, double alpha,
+                       csc_code_stats *stats);
+
 /* Filter update.
  * sur == NULL: batch problem eq. (5), n_iter projected-gradient steps
  *     d <- P(d + step * sum_i Z_i^T W_i (x_i - Z_i d)),   P = projection onto ||d_k|| <= 1,

@@ -61,6 +61,8 @@ SIGNATURES = {
                            C.POINTER(csc_code_stats)]),
     "csc_code_step_hold": (_i, [_vp, _pimg, _vp, _vp, _vp, _i, _i, _vp, _d, _d, _u64, _u32, _i, _d, _i,
                                 C.POINTER(csc_code_stats)]),
+    "csc_code_step_admm": (_i, [_vp, _pimg, _vp, _vp, _vp, _i, _i, _vp, _d, _d, _u64, _u32, _i, _i, _d, _d,
+                                C.POINTER(csc_code_stats)]),
     "csc_dict_step": (_i, [_vp, _pimg, _vp, _vp, _vp, _vp, _i, _i, C.POINTER(csc_surrogate), _i, _d, _i, _i,
                            C.POINTER(_d)]),
     "csc_objective": (_i, [_vp, _pimg, _vp, _vp, _vp, _i, _i, _vp, _d, C.POINTER(_d), C.POINTER(_d)]),

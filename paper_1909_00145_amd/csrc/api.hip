@@ -60,6 +60,11 @@ enum Slot {
     WS_HPAIRS,
     WS_HNZC,
     WS_XE,
+    WS_APACK,
+    WS_AVEC,
+    WS_AZC,
+    WS_ADOT,
+    WS_ASEG,
     WS_COUNT
 };
 
@@ -932,6 +937,139 @@ extern "C" int csc_code_step_hold(csc_handle h, const csc_images *im, const floa
                                   const float *d, int K, int m, float *z, double lambda, double p, uint64_t seed,
                                   uint32_t draw, int n_iter, double step, int precision, csc_code_stats *stats) {
     return code_step_impl(h, im, x, W, d, K, m, z, lambda, p, seed, draw, n_iter, step, precision, stats, true);
+}
+
+// The paper's ADMM code solver (csc_code_step_admm): the same selection as
+// csc_code_step, then n_admm iterations of ADMM on the subsampled LASSO with
+// S-vectors (kernels_admm.hip); the operator q -> A^T A q + rho q is a weighted
+// synthesis of q, the adjoint at S (threshold 0, step 1) and a merge back into
+// the S-vector layout.  The operator acts on every image at once; the CG
+// scalars are per image (each image's problem is solved on its own, Alg. 1).
+extern "C" int csc_code_step_admm(csc_handle h, const csc_images *im, const float *x, const uint8_t *W,
+                                  const float *d, int K, int m, float *z, double lambda, double p, uint64_t seed,
+                                  uint32_t draw, int n_admm, int n_cg, double rho, double alpha,
+                                  csc_code_stats *stats) {
+    if (!h) return CSC_EINVAL;
+    int st = check_images(h, im);
+    if (!st) st = check_filters(h, K, m);
+    if (st) return st;
+    if (!x || !d || !z) return fail(h, CSC_EINVAL, "null pointer argument");
+    if (!(lambda >= 0.0) || !std::isfinite(lambda)) return fail(h, CSC_EINVAL, "lambda must be finite and >= 0");
+    if (!(p > 0.0 && p <= 1.0)) return fail(h, CSC_EINVAL, "p must lie in (0, 1]");
+    if (n_admm < 0 || n_cg < 0) return fail(h, CSC_EINVAL, "n_admm and n_cg must be >= 0");
+    if (!std::isfinite(rho)) return fail(h, CSC_EINVAL, "rho must be finite");
+    if (rho <= 0.0) rho = 10.0 * lambda;
+    if (!(rho > 0.0)) return fail(h, CSC_EINVAL, "rho must be > 0 (rho <= 0 selects 10 lambda, and lambda is 0)");
+    if (!(alpha > 0.0 && alpha < 2.0)) return fail(h, CSC_EINVAL, "alpha must lie in (0, 2)");
+    if (im->n > 65535) return fail(h, CSC_EUNSUPPORTED, "ADMM: at most 65535 images per call");
+    HIPCHK(hipSetDevice(h->device));
+    if ((st = geometry(h, im))) return st;
+    const Geometry &g = h->geo;
+
+    const int W32 = (K + 31) / 32;
+    WS(mw, unsigned, WS_MASK, (size_t)W32 * g.n_pix);
+    WS(cnt32, unsigned, WS_CNT32, g.n_pix);
+    WS(soff, unsigned, WS_OFF, g.n_pix + 1);
+    WS(tmp, unsigned long long, WS_SCANTMP, scan_tmp_elems(g.n_pix));
+    WS(sc, double, WS_SCAL, SC_COUNT);
+    unsigned long long *total = reinterpret_cast<unsigned long long *>(sc + SC_TOTAL);
+    const unsigned long long thr = (unsigned long long)std::floor(std::ldexp(p, 32));
+    {
+        PROF(CSC_PK_SELECT);
+        HIPCHK(launch_mask_count(g, K, thr, seed, draw, mw, cnt32, h->stream));
+        HIPCHK(launch_scan(cnt32, soff, g.n_pix, tmp, total, h->stream));
+    }
+    if ((st = read_scalars(h, sc, SC_COUNT))) return st;
+    unsigned long long nsel;
+    std::memcpy(&nsel, &h->h_pinned[SC_TOTAL], sizeof(nsel));
+    if (nsel >= (1ULL << 32)) return fail(h, CSC_EUNSUPPORTED, "more than 2^32 selected coordinates");
+    const long long n = (long long)nsel;
+    WS(sel, Pair, WS_PAIRS0, nsel + 1);
+    WS(selc, unsigned short, WS_NZC0, g.n_pix);
+    WS(cl, Pair, WS_PAIRS1, nsel + 1);
+    WS(clc, unsigned short, WS_NZC1, g.n_pix);
+    WS(pb, Pair, WS_APACK, nsel + 1);
+    WS(vec, float, WS_AVEC, 7 * (nsel + 1));
+    WS(zc, unsigned short, WS_AZC, g.n_pix);
+    WS(dot, double, WS_ADOT, admm_dot_elems(g.n_img) + 3LL * g.n_img + 1);
+    WS(seg, unsigned, WS_ASEG, g.n_img + 1);
+    WS(Y, float, WS_R, g.n_pix);
+    float *zt = vec, *v = zt + (nsel + 1), *u = v + (nsel + 1), *b0 = u + (nsel + 1), *r = b0 + (nsel + 1),
+          *q = r + (nsel + 1), *Aq = q + (nsel + 1);
+    double *part = dot, *cgs = dot + admm_dot_elems(g.n_img);
+    HIPCHK(launch_seg(g, soff, seg, h->stream));
+    float *ethr = reinterpret_cast<float *>(sc + SC_ETHR);
+    HIPCHK(launch_set2(ethr, 1.0f, 0.0f, h->stream));  // the adjoint at S with step 1, no shrinkage
+    HIPCHK(hipMemsetAsync(zc, 0, sizeof(unsigned short) * g.n_pix, h->stream));
+    {
+        PROF(CSC_PK_GATHER);
+        HIPCHK(launch_sel_list(g, K, mw, soff, z, sel, selc, h->stream));
+        HIPCHK(launch_unpack(g, soff, sel, sel, selc, zt, h->stream));  // zt = v = z_prev on S
+        HIPCHK(launch_unpack(g, soff, sel, sel, selc, v, h->stream));
+        HIPCHK(hipMemsetAsync(u, 0, sizeof(float) * n, h->stream));
+    }
+    const float frho = (float)rho;
+    // out = A^T A vin + rho vin, with A = W D M^T
+    auto op = [&](const float *vin, float *out) -> int {
+        HIPCHK(launch_pack(sel, vin, pb, n, h->stream));
+        {
+            PROF(CSC_PK_SYNTH);
+            HIPCHK(synth(h, K, m, Lists{soff, selc, pb}, d, nullptr, W, Y, SYNTH_WEIGHTED, false, CSC_FP32));
+        }
+        {
+            PROF(CSC_PK_ADJOINT);
+            HIPCHK(launch_adjoint_shrink(g, K, m, mw, soff, pb, zc, cl, clc, Y, d, ethr, nullptr, h->stream));
+        }
+        HIPCHK(launch_unpack(g, soff, sel, cl, clc, out, h->stream));
+        HIPCHK(launch_add_scaled(out, vin, frho, n, h->stream));
+        return CSC_OK;
+    };
+    if (n_admm > 0) {
+        // b0 = A^T W x: the residual of zero codes is W x
+        {
+            PROF(CSC_PK_SYNTH);
+            HIPCHK(synth(h, K, m, Lists{soff, zc, pb}, d, x, W, Y, SYNTH_RESIDUAL, false, CSC_FP32));
+        }
+        {
+            PROF(CSC_PK_ADJOINT);
+            HIPCHK(launch_adjoint_shrink(g, K, m, mw, soff, pb, zc, cl, clc, Y, d, ethr, nullptr, h->stream));
+        }
+        HIPCHK(launch_unpack(g, soff, sel, cl, clc, b0, h->stream));
+    }
+    for (int it = 0; it < n_admm; ++it) {
+        PROF(CSC_PK_UPDATE);
+        if ((st = op(zt, Aq))) return st;
+        HIPCHK(launch_cg_init(r, q, b0, v, u, Aq, frho, n, h->stream));
+        HIPCHK(launch_cg_dot(g, r, r, seg, part, 0, cgs, h->stream));
+        for (int c = 0; c < n_cg; ++c) {
+            if ((st = op(q, Aq))) return st;
+            HIPCHK(launch_cg_dot(g, q, Aq, seg, part, 1, cgs, h->stream));
+            HIPCHK(launch_axpy_alpha(g, zt, q, cgs, seg, 1.f, h->stream));
+            HIPCHK(launch_axpy_alpha(g, r, Aq, cgs, seg, -1.f, h->stream));
+            HIPCHK(launch_cg_dot(g, r, r, seg, part, 2, cgs, h->stream));
+            HIPCHK(launch_cg_dir(g, q, r, cgs, seg, h->stream));
+        }
+        HIPCHK(launch_admm_update(zt, v, u, (float)alpha, (float)(lambda / rho), n, h->stream));
+    }
+    {
+        PROF(CSC_PK_SCATTER);
+        HIPCHK(launch_pack(sel, v, pb, n, h->stream));
+        HIPCHK(launch_scatter_dense(g, K, Lists{soff, selc, pb}, z, h->stream));
+    }
+    if (stats) {
+        unsigned long long *nnz = reinterpret_cast<unsigned long long *>(sc + SC_NNZ);
+        HIPCHK(hipMemsetAsync(nnz, 0, sizeof(unsigned long long), h->stream));
+        HIPCHK(launch_count_nz(v, n, nnz, h->stream));
+        if ((st = read_scalars(h, sc, SC_COUNT))) return st;
+        unsigned long long cnt;
+        std::memcpy(&cnt, &h->h_pinned[SC_NNZ], sizeof(cnt));
+        stats->sampled = (int64_t)nsel;
+        stats->nnz = (int64_t)cnt;
+        stats->nnz_iter_sum = 0;
+        stats->L_z = 0.0;
+        stats->step = rho;
+    }
+    return CSC_OK;
 }
 
 extern "C" int csc_dict_step(csc_handle h, const csc_images *im, const float *x, const uint8_t *W, const float *z,

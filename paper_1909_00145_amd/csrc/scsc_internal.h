@@ -292,6 +292,31 @@ hipError_t launch_fill_held(const Geometry &g, int K, const unsigned *mask_words
                             Pair *pairs, unsigned short *cnt, hipStream_t s);
 hipError_t launch_scatter_selected(const Geometry &g, int K, const unsigned *mask_words, Lists zl, float *z,
                                    hipStream_t s);
+// ADMM code solver on the sample (kernels_admm.hip).  S-vectors are FP32 over the
+// selected coordinates at [soff[p], soff[p + 1]), filters ascending per pixel.
+hipError_t launch_sel_list(const Geometry &g, int K, const unsigned *mask_words, const unsigned *soff, const float *z,
+                           Pair *pairs, unsigned short *cnt, hipStream_t s);
+hipError_t launch_pack(const Pair *sel, const float *val, Pair *pairs, long long n, hipStream_t s);
+hipError_t launch_unpack(const Geometry &g, const unsigned *soff, const Pair *sel, const Pair *cl,
+                         const unsigned short *ccnt, float *out, hipStream_t s);
+// Per-image segments seg[n_img + 1] of the S-vectors, and the segmented CG:
+// dot products into the scalars scs[n] = {rr, alpha, beta} of image n (mode 0
+// sets rr, mode 1 alpha = rr / dot, mode 2 beta = dot / rr and rr = dot);
+// part holds admm_dot_elems(n_img) doubles.
+long long admm_dot_elems(int n_img);
+hipError_t launch_seg(const Geometry &g, const unsigned *soff, unsigned *seg, hipStream_t s);
+hipError_t launch_cg_dot(const Geometry &g, const float *a, const float *b, const unsigned *seg, double *part,
+                         int mode, double *scs, hipStream_t s);
+hipError_t launch_axpy_alpha(const Geometry &g, float *y, const float *x, const double *scs, const unsigned *seg,
+                             float sgn, hipStream_t s);
+hipError_t launch_cg_dir(const Geometry &g, float *q, const float *r, const double *scs, const unsigned *seg,
+                         hipStream_t s);
+hipError_t launch_add_scaled(float *Aq, const float *q, float rho, long long n, hipStream_t s);
+hipError_t launch_cg_init(float *r, float *q, const float *b0, const float *v, const float *u, const float *Aq,
+                          float rho, long long n, hipStream_t s);
+hipError_t launch_admm_update(const float *zt, float *v, float *u, float alpha, float thr, long long n,
+                              hipStream_t s);
+hipError_t launch_count_nz(const float *v, long long n, unsigned long long *out, hipStream_t s);
 // Selection bytes (csc_mask).
 hipError_t launch_expand_mask(const Geometry &g, int K, const unsigned *mask_words, unsigned char *mask,
                               hipStream_t s);

@@ -210,6 +210,22 @@ class Context:
             return CodeStats(st.sampled, st.nnz, st.L_z, st.step, st.nnz_iter_sum)
         return None
 
+    def code_step_admm(self, im: Images, x, d, z, lam, p, seed, draw, n_admm=10, n_cg=5, rho=0.0, alpha=1.8, W=None,
+                       stats=False):
+        """Code update by ADMM (csc_code_step_admm); rho <= 0 selects 10 lambda."""
+        K, m = int(d.shape[0]), int(d.shape[-1])
+        self._sync_stream()
+        st = _lib.csc_code_stats()
+        rc = self.lib.csc_code_step_admm(
+            self.h, im.cref(), _ptr(x, torch.float32, "x", im.n_pix), _ptr(W, torch.uint8, "W", im.n_pix),
+            _ptr(d, torch.float32, "d", K * m * m), K, m, _ptr(z, torch.float32, "z", K * im.n_pix),
+            float(lam), float(p), int(seed) & (2**64 - 1), int(draw) & (2**32 - 1), int(n_admm), int(n_cg),
+            float(rho), float(alpha), C.byref(st) if stats else None)
+        self._check(rc)
+        if stats:
+            return CodeStats(st.sampled, st.nnz, st.L_z, st.step, st.nnz_iter_sum)
+        return None
+
     def dict_step(self, im: Images, x, z, d, n_iter=1, step=0.0, n_power=20, W=None, surrogate: Surrogate = None,
                   precision="fp32"):
         K, m = int(d.shape[0]), int(d.shape[-1])

@@ -123,7 +123,8 @@ def test_dft_size():
     assert oracle.dft_size(64, 11) == 128
 
 
-def test_hold_delta_filter_closed_form(rng):
+def test_hold_delta_filter_closed_form():
+    rng = np.random.default_rng(11)
     H, W, m = 9, 8, 3
     d = np.zeros((1, m, m))
     d[0, 1, 1] = 1.0
@@ -137,7 +138,8 @@ def test_hold_delta_filter_closed_form(rng):
     assert 0 < S.sum() < S.size
 
 
-def test_hold_keeps_unselected_and_reduces_to_default(rng):
+def test_hold_keeps_unselected_and_reduces_to_default():
+    rng = np.random.default_rng(12)
     K, m, H, W = 3, 5, 11, 10
     d = oracle.project_ball(rng.standard_normal((K, m, m)))
     x = rng.standard_normal((H, W))
@@ -155,7 +157,8 @@ def test_hold_keeps_unselected_and_reduces_to_default(rng):
     np.testing.assert_array_equal(za, zb)
 
 
-def test_hold_converged_matches_sklearn_lasso(rng):
+def test_hold_converged_matches_sklearn_lasso():
+    rng = np.random.default_rng(13)
     from sklearn.linear_model import Lasso
 
     K, m, H, W = 2, 3, 6, 5
@@ -180,7 +183,8 @@ def test_hold_converged_matches_sklearn_lasso(rng):
     np.testing.assert_allclose(g[zs != 0], lam * np.sign(zs[zs != 0]), atol=1e-7)
 
 
-def test_hold_objective_monotone(rng):
+def test_hold_objective_monotone():
+    rng = np.random.default_rng(14)
     K, m, H, W = 4, 5, 16, 14
     d = oracle.project_ball(rng.standard_normal((K, m, m)))
     x = rng.standard_normal((H, W))
@@ -196,7 +200,8 @@ def test_hold_objective_monotone(rng):
 
 
 # ADMM (the paper's code solver, Sec. 3.2)
-def test_admm_delta_filter_converges_to_shrinkage(rng):
+def test_admm_delta_filter_converges_to_shrinkage():
+    rng = np.random.default_rng(15)
     """D = I: the subsampled LASSO's solution is S_lambda(x) on the sample."""
     H, W, m = 9, 8, 3
     d = np.zeros((1, m, m))
@@ -207,7 +212,8 @@ def test_admm_delta_filter_converges_to_shrinkage(rng):
     np.testing.assert_allclose(z[0], np.where(S[0], soft_threshold(x, lam), 0.0), atol=1e-10)
 
 
-def test_admm_converged_matches_sklearn_lasso(rng):
+def test_admm_converged_matches_sklearn_lasso():
+    rng = np.random.default_rng(16)
     from sklearn.linear_model import Lasso
 
     K, m, H, W = 2, 3, 6, 5
@@ -225,7 +231,8 @@ def test_admm_converged_matches_sklearn_lasso(rng):
     np.testing.assert_allclose(z.ravel(), ref, atol=1e-7, rtol=0)
 
 
-def test_admm_cg_solves_the_quadratic_substep(rng):
+def test_admm_cg_solves_the_quadratic_substep():
+    rng = np.random.default_rng(17)
     """With enough CG iterations, the first ADMM step's zt solves (A^T A + rho I) zt = A^T x
     exactly (zero start): check the returned v against the shrinkage of the explicit solve."""
     K, m, H, W = 2, 3, 5, 6
@@ -244,7 +251,8 @@ def test_admm_cg_solves_the_quadratic_substep(rng):
     np.testing.assert_allclose(z.ravel(), ref, atol=1e-10)
 
 
-def test_admm_with_mask_reduces_masked_objective(rng):
+def test_admm_with_mask_reduces_masked_objective():
+    rng = np.random.default_rng(18)
     K, m, H, W = 3, 5, 12, 11
     d = oracle.project_ball(rng.standard_normal((K, m, m)))
     x = rng.standard_normal((H, W))

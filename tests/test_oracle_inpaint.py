@@ -52,7 +52,8 @@ def test_psnr_constant_error(rng):
     assert oracle.psnr(x, x) == math.inf
 
 
-def test_masked_kkt_at_convergence(rng):
+def test_masked_kkt_at_convergence():
+    rng = np.random.default_rng(2024)
     K, m, H, W = 2, 3, 7, 6
     d = oracle.project_ball(rng.standard_normal((K, m, m)))
     x = rng.standard_normal((H, W))
