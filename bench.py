@@ -45,16 +45,16 @@ PEAK_HBM = 8.0e12
 # valid only for the kernel source they were taken on (first 16 hex digits of its SHA-256).
 # Keyed by (kernel class, precision).
 TRAFFIC = {
-    ("synth", "bf16"): ("kernels_mfma.hip", "5a76e8c6ce77b2bc", 43.33e6, 1.02e6),
-    ("adjoint", "bf16"): ("kernels_code.hip", "d4d2f975defe01df", 34.14e6, 11.07e6),
+    ("synth", "bf16"): ("kernels_mfma.hip", "16ec6e23e6f32e19", 43.33e6, 1.02e6),
+    ("adjoint", "bf16"): ("kernels_code.hip", "4c7a90c9884dc8c4", 34.16e6, 11.07e6),
     ("corr", "bf16"): ("kernels_dict.hip", "0bf8d154ab50cc41", 27.00e6, 4.07e6),
-    ("sur_expand", "bf16"): ("kernels_sur.hip", "dd2d3a480058b5f0", 923.86e6, 605.80e6),
-    ("power", "bf16"): ("kernels_sur.hip", "dd2d3a480058b5f0", 18.21e6, 0.69e6),
-    ("synth", "fp32"): ("kernels_code.hip", "d4d2f975defe01df", 18.10e6, 0.80e6),
-    ("adjoint", "fp32"): ("kernels_code.hip", "d4d2f975defe01df", 20.94e6, 10.63e6),
+    ("sur_expand", "bf16"): ("kernels_sur.hip", "d1aa18db8753e5f7", 732.62e6, 603.90e6),
+    ("power", "bf16"): ("kernels_sur.hip", "d1aa18db8753e5f7", 18.21e6, 0.69e6),
+    ("synth", "fp32"): ("kernels_code.hip", "4c7a90c9884dc8c4", 18.08e6, 0.81e6),
+    ("adjoint", "fp32"): ("kernels_code.hip", "4c7a90c9884dc8c4", 20.94e6, 10.63e6),
     ("corr", "fp32"): ("kernels_dict.hip", "0bf8d154ab50cc41", 27.01e6, 4.07e6),
-    ("sur_expand", "fp32"): ("kernels_sur.hip", "dd2d3a480058b5f0", 923.77e6, 605.84e6),
-    ("power", "fp32"): ("kernels_sur.hip", "dd2d3a480058b5f0", 18.21e6, 0.69e6),
+    ("sur_expand", "fp32"): ("kernels_sur.hip", "d1aa18db8753e5f7", 732.90e6, 603.90e6),
+    ("power", "fp32"): ("kernels_sur.hip", "d1aa18db8753e5f7", 18.21e6, 0.69e6),
 }
 
 
