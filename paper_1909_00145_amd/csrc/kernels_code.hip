@@ -128,6 +128,8 @@ __global__ __launch_bounds__(TPB) void k_scan_add(unsigned *off, long long n, co
 // ---------------------------------------------------------------------------
 // Lists from dense codes.
 // ---------------------------------------------------------------------------
+constexpr int ZB = 8;  // filters (or list entries) per batch of loads in the per-pixel passes over dense z
+
 __global__ __launch_bounds__(TPB) void k_gather_selected(const ImgInfo *imgs, int n_img, int K,
                                                          long long n_pix, const unsigned *mask_words,
                                                          const unsigned *soff, const float *z, Pair *pairs,
@@ -146,12 +148,18 @@ __global__ __launch_bounds__(TPB) void k_gather_selected(const ImgInfo *imgs, in
     const unsigned base = soff[c.gp];
     int nn = 0;
     unsigned bits = 0;
-    for (int k = 0; k < K; ++k) {
-        if ((k & 31) == 0) bits = mask_words[(long long)(k >> 5) * n_pix + c.gp];
-        if ((bits >> (k & 31)) & 1u) {
-            float v = zp[(long long)k * HW];
-            if (v != 0.f) {
-                pairs[base + nn] = Pair{k, v};
+    // ZB filters at a time: their loads are issued together (the lanes of a wave
+    // read neighbouring pixels of one filter plane, so every load is coalesced)
+    for (int k0 = 0; k0 < K; k0 += ZB) {
+        float v[ZB];
+#pragma unroll
+        for (int u = 0; u < ZB; ++u) v[u] = k0 + u < K ? zp[(long long)(k0 + u) * HW] : 0.f;
+#pragma unroll
+        for (int u = 0; u < ZB; ++u) {
+            const int k = k0 + u;
+            if ((k & 31) == 0) bits = k < K ? mask_words[(long long)(k >> 5) * n_pix + c.gp] : 0u;
+            if (k < K && ((bits >> (k & 31)) & 1u) && v[u] != 0.f) {
+                pairs[base + nn] = Pair{k, v[u]};
                 ++nn;
             }
         }
@@ -169,7 +177,13 @@ __global__ __launch_bounds__(TPB) void k_count_nonzero(const ImgInfo *imgs, int 
     const long long HW = (long long)c.im.H * c.im.W;
     const float *zp = z + (long long)K * c.im.pix_off + c.p_img;
     unsigned nn = 0;
-    for (int k = 0; k < K; ++k) nn += zp[(long long)k * HW] != 0.f;
+    for (int k0 = 0; k0 < K; k0 += ZB) {
+        float v[ZB];
+#pragma unroll
+        for (int u = 0; u < ZB; ++u) v[u] = k0 + u < K ? zp[(long long)(k0 + u) * HW] : 0.f;
+#pragma unroll
+        for (int u = 0; u < ZB; ++u) nn += v[u] != 0.f;
+    }
     cnt[c.gp] = nn;
 }
 
@@ -182,12 +196,18 @@ __global__ __launch_bounds__(TPB) void k_fill_nonzero(const ImgInfo *imgs, int n
     const float *zp = z + (long long)K * c.im.pix_off + c.p_img;
     const unsigned base = off[c.gp];
     int nn = 0;
-    for (int k = 0; k < K; ++k) {
-        float v = zp[(long long)k * HW];
-        if (v != 0.f) {
-            pairs[base + nn] = Pair{k, v};
-            if (xp) xp[base + nn] = XPair{((unsigned)c.x * xmul + (unsigned)k) * 8u, v};
-            ++nn;
+    for (int k0 = 0; k0 < K; k0 += ZB) {
+        float v[ZB];
+#pragma unroll
+        for (int u = 0; u < ZB; ++u) v[u] = k0 + u < K ? zp[(long long)(k0 + u) * HW] : 0.f;
+#pragma unroll
+        for (int u = 0; u < ZB; ++u) {
+            const int k = k0 + u;
+            if (v[u] != 0.f) {  // (0 for k >= K)
+                pairs[base + nn] = Pair{k, v[u]};
+                if (xp) xp[base + nn] = XPair{((unsigned)c.x * xmul + (unsigned)k) * 8u, v[u]};
+                ++nn;
+            }
         }
     }
     cnt[c.gp] = (unsigned short)nn;
@@ -201,14 +221,28 @@ __global__ __launch_bounds__(TPB) void k_scatter_dense(const ImgInfo *imgs, int 
     float *zp = z + (long long)K * c.im.pix_off + c.p_img;
     const unsigned base = zl.off[c.gp];
     const int n = zl.cnt[c.gp];
+    // the first ZB entries of the list are loaded together; longer lists continue one by one
+    Pair ent[ZB];
+#pragma unroll
+    for (int u = 0; u < ZB; ++u) ent[u] = u < n ? zl.pairs[base + u] : Pair{INT_MAX, 0.f};
     int i = 0;
-    Pair e = n > 0 ? zl.pairs[base] : Pair{INT_MAX, 0.f};
+    Pair e = ent[0];
     for (int k = 0; k < K; ++k) {
         float v = 0.f;
         if (e.k == k) {
             v = e.v;
             ++i;
-            e = i < n ? zl.pairs[base + i] : Pair{INT_MAX, 0.f};
+            if (i < n) {
+                if (i < ZB) {
+#pragma unroll
+                    for (int u = 1; u < ZB; ++u)
+                        if (i == u) e = ent[u];
+                } else {
+                    e = zl.pairs[base + i];
+                }
+            } else {
+                e = Pair{INT_MAX, 0.f};
+            }
         }
         zp[(long long)k * HW] = v;
     }
