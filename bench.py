@@ -46,15 +46,19 @@ PEAK_HBM = 8.0e12
 # Keyed by (kernel class, precision).
 TRAFFIC = {
     ("synth", "bf16"): ("kernels_mfma.hip", "16ec6e23e6f32e19", 43.33e6, 1.02e6),
-    ("adjoint", "bf16"): ("kernels_code.hip", "4c7a90c9884dc8c4", 34.16e6, 11.07e6),
+    ("adjoint", "bf16"): ("kernels_code.hip", "82dce5536bf66e1f", 34.15e6, 11.07e6),
     ("corr", "bf16"): ("kernels_dict.hip", "0bf8d154ab50cc41", 27.00e6, 4.07e6),
-    ("sur_expand", "bf16"): ("kernels_sur.hip", "d1aa18db8753e5f7", 732.62e6, 603.90e6),
+    ("sur_expand", "bf16"): ("kernels_sur.hip", "d1aa18db8753e5f7", 732.62e6, 603.88e6),
     ("power", "bf16"): ("kernels_sur.hip", "d1aa18db8753e5f7", 18.21e6, 0.69e6),
-    ("synth", "fp32"): ("kernels_code.hip", "4c7a90c9884dc8c4", 18.08e6, 0.81e6),
-    ("adjoint", "fp32"): ("kernels_code.hip", "4c7a90c9884dc8c4", 20.94e6, 10.63e6),
+    ("gather", "bf16"): ("kernels_code.hip", "82dce5536bf66e1f", 89.16e6, 0.40e6),
+    ("scatter", "bf16"): ("kernels_code.hip", "82dce5536bf66e1f", 17.30e6, 80.05e6),
+    ("synth", "fp32"): ("kernels_code.hip", "82dce5536bf66e1f", 18.08e6, 0.81e6),
+    ("adjoint", "fp32"): ("kernels_code.hip", "82dce5536bf66e1f", 20.94e6, 10.63e6),
     ("corr", "fp32"): ("kernels_dict.hip", "0bf8d154ab50cc41", 27.01e6, 4.07e6),
-    ("sur_expand", "fp32"): ("kernels_sur.hip", "d1aa18db8753e5f7", 732.90e6, 603.90e6),
+    ("sur_expand", "fp32"): ("kernels_sur.hip", "d1aa18db8753e5f7", 732.71e6, 603.94e6),
     ("power", "fp32"): ("kernels_sur.hip", "d1aa18db8753e5f7", 18.21e6, 0.69e6),
+    ("gather", "fp32"): ("kernels_code.hip", "82dce5536bf66e1f", 89.16e6, 0.40e6),
+    ("scatter", "fp32"): ("kernels_code.hip", "82dce5536bf66e1f", 17.30e6, 80.05e6),
 }
 
 
@@ -522,8 +526,16 @@ def main():
         "power": ("alu64", 2.0 * K * K * M * M * n_power * args.steps, PEAK_FP64_VECTOR),
         # one pass over the blocks (k, k2 >= k) of the FP64 lag-layout matrix (the rest is their transpose)
         "sur_mv": ("hbm", 8.0 * (K * (K + 1) // 2) * M * M * args.steps, PEAK_HBM),
-        # read-modify-write of the stored blocks (k <= k2) of C_bar plus their lag and band sums
-        "sur_expand": ("hbm", (K * (K + 1) // 2) * (16.0 * M * M + 8.0 * L2 * (1 + 4 * c)) * args.steps, PEAK_HBM),
+        # read-modify-write of the stored blocks (k <= k2) of C_bar plus their lag sums and the
+        # 4 c^2 (2m - 1) band sums that can be non-zero
+        "sur_expand": ("hbm", (K * (K + 1) // 2) * (16.0 * M * M + 8.0 * (L2 + 4 * c * c * (2 * m - 1)))
+                       * args.steps, PEAK_HBM),
+        # gather: the K planes of z read once (a Bernoulli(p) sample touches nearly every 64-byte
+        # sector), the selection words, offsets and counts; the gathered pairs are not counted,
+        # so this is a lower bound
+        "gather": ("hbm", (4.0 * K + 4.0 * ((K + 31) // 32) + 6.0) * im.n_pix * args.steps, PEAK_HBM),
+        # scatter: the K planes of z written once, the offsets and counts, and the list entries
+        "scatter": ("hbm", (4.0 * K + 6.0) * im.n_pix * args.steps + 8.0 * nnz_dict, PEAK_HBM),
     }
     # MFMA work the BF16 kernels execute per launch (dense tiles, padded shapes), 16x16x32 = 16384 flop
     executed = {}
@@ -533,7 +545,7 @@ def main():
         executed["adjoint"] = tiles * ((K + 15) // 16) * 16 * ((M + 31) // 32) * 16384.0
     if args.workload == "ragged":
         # code steps only
-        work = {k: work[k] for k in ("adjoint", "synth")}
+        work = {k: work[k] for k in ("adjoint", "synth", "gather", "scatter")}
     elif args.workload != "online":
         # batch filter step: one residual synthesis and one gradient correlation; lag-sum power iteration
         work.pop("sur_mv")
