@@ -780,6 +780,47 @@ int code_step_impl(csc_ctx *h, const csc_images *im, const float *x, const uint8
         HIPCHK(launch_mask_count(g, K, thr, seed, draw, mw, cnt32, h->stream));
         HIPCHK(launch_scan(cnt32, soff, g.n_pix, tmp, total, h->stream));
     }
+    // The work that does not depend on the size of the selection is queued before
+    // the read-back, so that the GPU has it in hand when the host waits.
+    WS(R, float, WS_R, g.n_pix);
+    unsigned long long *nnzsum = reinterpret_cast<unsigned long long *>(sc + SC_NNZSUM);
+    HIPCHK(hipMemsetAsync(nnzsum, 0, sizeof(unsigned long long), h->stream));
+    // step and threshold as device scalars (from L_z on the device when no step is given)
+    float *ethr = reinterpret_cast<float *>(sc + SC_ETHR);
+    if (step > 0.0) HIPCHK(launch_set2(ethr, (float)step, (float)(step * lambda), h->stream));
+    else HIPCHK(launch_set_step(ethr, sc + SC_LZ, lambda, h->stream));
+    const float *xi = x, *di = d;
+    const uint8_t *Wi = W;
+    const bool use_graph = h->graphs && n_iter > 0 &&
+                           variant_settled(h, synth_key(h, K, m, SYNTH_RESIDUAL, precision));
+    // stable copies of the inputs the graph reads (x_eff is copied once it is formed)
+    auto copy_x = [&](const float *xs) -> int {
+        WS(xc, float, WS_XC, g.n_pix);
+        HIPCHK(hipMemcpyAsync(xc, xs, sizeof(float) * g.n_pix, hipMemcpyDeviceToDevice, h->stream));
+        xi = xc;
+        return CSC_OK;
+    };
+    const bool hold_x = hold && n_iter > 0;
+    if (use_graph) {
+        if (!hold_x && (st = copy_x(x))) return st;
+        WS(dc, float, WS_DC, (size_t)K * m * m);
+        HIPCHK(hipMemcpyAsync(dc, d, sizeof(float) * K * m * m, hipMemcpyDeviceToDevice, h->stream));
+        di = dc;
+        if (W) {
+            WS(wc, uint8_t, WS_WC, g.n_pix);
+            HIPCHK(hipMemcpyAsync(wc, W, g.n_pix, hipMemcpyDeviceToDevice, h->stream));
+            Wi = wc;
+        }
+    }
+    __bf16 *sda = nullptr, *ada = nullptr;
+    if (precision == CSC_BF16 && n_iter > 0) {
+        WS(buf, __bf16, WS_SDA, synth_mfma_prep_elems(K));
+        HIPCHK(launch_synth_mfma_prep(di, K, m, buf, h->stream));
+        sda = buf;
+        WS(abuf, __bf16, WS_ADA, adj_prep_elems(K, m));
+        HIPCHK(launch_adj_prep(di, K, m, abuf, h->stream));
+        ada = abuf;
+    }
     if ((st = read_scalars(h, sc, SC_COUNT))) return st;
     double Lz = 0.0, eta = step;
     if (step <= 0.0) {
@@ -802,18 +843,11 @@ int code_step_impl(csc_ctx *h, const csc_images *im, const float *x, const uint8
         nzc[0] = c0;
         nzc[1] = c1;
     }
-    WS(R, float, WS_R, g.n_pix);
-    unsigned long long *nnzsum = reinterpret_cast<unsigned long long *>(sc + SC_NNZSUM);
-    HIPCHK(hipMemsetAsync(nnzsum, 0, sizeof(unsigned long long), h->stream));
     {
         PROF(CSC_PK_GATHER);
         HIPCHK(launch_gather_selected(g, K, mw, soff, z, pairs[0], nzc[0], nnzsum, h->stream));
     }
-    const float feta = (float)eta, fthr = (float)(eta * lambda);
-    float *ethr = reinterpret_cast<float *>(sc + SC_ETHR);
-    HIPCHK(launch_set2(ethr, feta, fthr, h->stream));
-    const float *xsrc = x;
-    if (hold && n_iter > 0) {
+    if (hold_x) {
         // lists of the held codes (non-zero, off the sample), then x_eff = x - D z_held
         WS(hcnt, unsigned, WS_HCNT32, g.n_pix);
         WS(hoff, unsigned, WS_HOFF, g.n_pix + 1);
@@ -840,37 +874,14 @@ int code_step_impl(csc_ctx *h, const csc_images *im, const float *x, const uint8
             PROF(CSC_PK_SYNTH);
             HIPCHK(synth(h, K, m, Lists{hoff, hc, hp}, d, x, nullptr, xe, SYNTH_RESIDUAL, false, precision));
         }
-        xsrc = xe;
+        if (use_graph) {
+            if ((st = copy_x(xe))) return st;
+        } else {
+            xi = xe;
+        }
     }
     // The n_iter iterations only launch kernels; their step and threshold are
     // read from device scalars, so the same launches can be replayed as a graph.
-    const float *xi = xsrc, *di = d;
-    const uint8_t *Wi = W;
-    const bool use_graph = h->graphs && n_iter > 0 &&
-                           variant_settled(h, synth_key(h, K, m, SYNTH_RESIDUAL, precision));
-    if (use_graph) {
-        // stable copies of the inputs the graph reads
-        WS(xc, float, WS_XC, g.n_pix);
-        WS(dc, float, WS_DC, (size_t)K * m * m);
-        HIPCHK(hipMemcpyAsync(xc, xsrc, sizeof(float) * g.n_pix, hipMemcpyDeviceToDevice, h->stream));
-        HIPCHK(hipMemcpyAsync(dc, d, sizeof(float) * K * m * m, hipMemcpyDeviceToDevice, h->stream));
-        xi = xc;
-        di = dc;
-        if (W) {
-            WS(wc, uint8_t, WS_WC, g.n_pix);
-            HIPCHK(hipMemcpyAsync(wc, W, g.n_pix, hipMemcpyDeviceToDevice, h->stream));
-            Wi = wc;
-        }
-    }
-    __bf16 *sda = nullptr, *ada = nullptr;
-    if (precision == CSC_BF16 && n_iter > 0) {
-        WS(buf, __bf16, WS_SDA, synth_mfma_prep_elems(K));
-        HIPCHK(launch_synth_mfma_prep(di, K, m, buf, h->stream));
-        sda = buf;
-        WS(abuf, __bf16, WS_ADA, adj_prep_elems(K, m));
-        HIPCHK(launch_adj_prep(di, K, m, abuf, h->stream));
-        ada = abuf;
-    }
     auto iterations = [&]() -> int {
         int c = 0;
         for (int it = 0; it < n_iter; ++it) {
@@ -1123,11 +1134,16 @@ extern "C" int csc_dict_step(csc_handle h, const csc_images *im, const float *x,
         if (st) return st;
     }
     double Ld = 0.0;
-    if (sur || L_d_out) {
-        if ((st = read_scalars(h, sc, SC_COUNT))) return st;
-        Ld = h->h_pinned[SC_LAM];
-    }
+    auto read_ld = [&]() -> int {
+        if (sur || L_d_out) {
+            int st2 = read_scalars(h, sc, SC_COUNT);
+            if (st2) return st2;
+            Ld = h->h_pinned[SC_LAM];
+        }
+        return CSC_OK;
+    };
     if (!sur) {
+        if ((st = read_ld())) return st;
         if (step > 0.0) {
             double lam = 1.0 / step;
             HIPCHK(hipMemcpyAsync(sc + SC_LAM, &lam, sizeof(double), hipMemcpyHostToDevice, h->stream));
@@ -1146,10 +1162,11 @@ extern "C" int csc_dict_step(csc_handle h, const csc_images *im, const float *x,
             HIPCHK(launch_batch_update(d, G, sc + SC_LAM, K, M, h->stream));
         }
     } else {
-        // the first product C_bar d of the filter iterations is fused into the
-        // expansion when there is no observation mask
-        const bool step_d = sur->Ld_sum + Ld > 0.0;
-        const bool fused = !W && step_d && n_iter > 0;
+        // The surrogate increments do not depend on L_d: they are queued before its
+        // read-back.  Without an observation mask the first product C_bar d of the
+        // filter iterations is fused into the expansion (unused when the step turns
+        // out to be a projection only).
+        const bool fused = !W && n_iter > 0;
         WS(y, double, WS_Y, K * M);
         if (W) {
             PROF(CSC_PK_SUR_ACC);
@@ -1174,6 +1191,8 @@ extern "C" int csc_dict_step(csc_handle h, const csc_images *im, const float *x,
             HIPCHK(launch_corr_fm(g, K, m, F.off, F.codes, x, W, true, part, h->stream));
             HIPCHK(launch_reduce_partials_f64_add(part, nch, K * M, sur->B, h->stream));
         }
+        if ((st = read_ld())) return st;
+        const bool step_d = sur->Ld_sum + Ld > 0.0;
         sur->t += 1;
         sur->Ld_sum += Ld;
         if (step_d) {

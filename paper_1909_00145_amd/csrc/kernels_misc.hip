@@ -264,6 +264,21 @@ hipError_t launch_set2(float *dst, float a, float b, hipStream_t s) {
     return hipGetLastError();
 }
 
+// dst = {(float)(1 / L), (float)(lambda / L)} from the device scalar L (the FP64
+// operations the host would do with L); {0, 0} when L is not positive.
+__global__ void k_set_step(float *dst, const double *L, double lambda) {
+    if (threadIdx.x != 0) return;
+    const double Lv = *L;
+    const double eta = Lv > 0.0 ? 1.0 / Lv : 0.0;
+    dst[0] = (float)eta;
+    dst[1] = (float)(eta * lambda);
+}
+
+hipError_t launch_set_step(float *dst, const double *L, double lambda, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_step, dim3(1), dim3(64), 0, s, dst, L, lambda);
+    return hipGetLastError();
+}
+
 hipError_t launch_axpby(long long n, float a, const float *x, float b, const float *y, float *out, hipStream_t s) {
     hipLaunchKernelGGL(k_axpby, dim3(ew_blocks(n)), dim3(256), 0, s, n, a, x, b, y, out);
     return hipGetLastError();
