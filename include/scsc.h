@@ -198,6 +198,27 @@ int csc_dict_step(csc_handle h, const csc_images *im, const float *x, const uint
                   const float *z, float *d, int K, int m, csc_surrogate *sur, int n_iter,
                   double step, int n_power, int precision, double *L_d_out);
 
+/* One step of the online algorithm (Alg. 2) on a mini-batch, in one call: the codes of
+ * eqs. (3)-(4) from zero by n_iter ISTA iterations on the Bernoulli sample (as
+ * csc_code_step with z = 0 on entry), then the surrogate update of eq. (8) and n_dict_iter
+ * steps of eq. (9) on the filters (as csc_dict_step with sur).  The result equals those two
+ * calls in sequence; joined, the filter step takes the code step's final lists instead of
+ * rebuilding them from the dense codes, and the host waits for the GPU twice instead of
+ * four times (the selection count, then L_d together with the code statistics).
+ *   d : filters, in/out (the code step reads the filters given, the filter step updates them).
+ *   z : codes, out, packed [K][pixels] per image; may be NULL (the codes then stay on the
+ *       device as lists only and are not written out).
+ *   sur : surrogates (required), updated as by csc_dict_step.
+ *   n_dict_iter >= 0 : filter iterations (csc_dict_step's n_iter); n_power >= 1.
+ *   stats, L_d_out : host, may be NULL; as csc_code_step and csc_dict_step fill them.
+ *   Other arguments as csc_code_step.  Argument errors are reported before any output is
+ *   written; a failure after the code step has run leaves d and sur as the failing
+ *   filter step left them. */
+int csc_online_step(csc_handle h, const csc_images *im, const float *x, const uint8_t *W,
+                    float *d, int K, int m, float *z, double lambda, double p, uint64_t seed,
+                    uint32_t draw, int n_iter, double step, int precision, csc_surrogate *sur,
+                    int n_dict_iter, int n_power, csc_code_stats *stats, double *L_d_out);
+
 /* Objective of eq. (1) summed over the batch, in FP64:
  *   F = sum_i 1/2 ||W_i (x_i - D z_i)||^2 + lambda sum_i ||z_i||_1.
  * f_out (host) receives F; terms_out (host, may be NULL) receives {data term, L1 norm}.

@@ -65,6 +65,8 @@ SIGNATURES = {
                                 C.POINTER(csc_code_stats)]),
     "csc_dict_step": (_i, [_vp, _pimg, _vp, _vp, _vp, _vp, _i, _i, C.POINTER(csc_surrogate), _i, _d, _i, _i,
                            C.POINTER(_d)]),
+    "csc_online_step": (_i, [_vp, _pimg, _vp, _vp, _vp, _i, _i, _vp, _d, _d, _u64, _u32, _i, _d, _i,
+                             C.POINTER(csc_surrogate), _i, _i, C.POINTER(csc_code_stats), C.POINTER(_d)]),
     "csc_objective": (_i, [_vp, _pimg, _vp, _vp, _vp, _i, _i, _vp, _d, C.POINTER(_d), C.POINTER(_d)]),
     "csc_synthesize": (_i, [_vp, _pimg, _vp, _i, _i, _vp, _vp, _i]),
     "csc_adjoint": (_i, [_vp, _pimg, _vp, _i, _i, _vp, _vp, _i]),

@@ -65,6 +65,7 @@ enum Slot {
     WS_AZC,
     WS_ADOT,
     WS_ASEG,
+    WS_COFF,
     WS_COUNT
 };
 
@@ -77,7 +78,8 @@ enum Scalar {
     SC_OBJ = 4 /* 2 */,
     SC_NNZSUM = 6,
     SC_ETHR = 7 /* two floats: step, threshold */,
-    SC_COUNT = 8
+    SC_CNNZ = 8 /* non-zero codes after a code step whose statistics are read later */,
+    SC_COUNT = 9
 };
 
 struct Buffer {
@@ -739,18 +741,30 @@ extern "C" int csc_mask(csc_handle h, const csc_images *im, int K, double p, uin
     return CSC_OK;
 }
 
+// What a code step hands to a filter step that follows it in the same call
+// (csc_online_step): the codes start from zero (z is not read and, when null,
+// not written), and the statistics are left on the device (SC_CNNZ, SC_NNZSUM)
+// for the caller's read-back instead of being read here.
+struct CodeStepFused {
+    bool want_stats = false;
+    Lists lists{};                  // out: the final lists of the step (capacities from the selection)
+    unsigned long long nsel = 0;    // out: |S|, the total capacity of the lists
+    double Lz = 0.0, eta = 0.0;     // out
+};
+
 // The code update of csc_code_step; hold: the unselected coordinates keep their
 // values (csc_code_step_hold).  Their codes enter every residual through
 // x_eff = x - D z_held, formed once, and only the sample is written back.
 int code_step_impl(csc_ctx *h, const csc_images *im, const float *x, const uint8_t *W, const float *d, int K, int m,
                    float *z, double lambda, double p, uint64_t seed, uint32_t draw, int n_iter, double step,
-                   int precision, csc_code_stats *stats, bool hold) {
+                   int precision, csc_code_stats *stats, bool hold, CodeStepFused *fo = nullptr) {
     if (!h) return CSC_EINVAL;
     int st = check_images(h, im);
     if (!st) st = check_filters(h, K, m);
     if (!st) st = check_precision(h, precision);
     if (st) return st;
-    if (!x || !d || !z) return fail(h, CSC_EINVAL, "null pointer argument");
+    if (!x || !d || (!z && !fo)) return fail(h, CSC_EINVAL, "null pointer argument");
+    if (fo && hold) return fail(h, CSC_EINVAL, "a fused code step starts from zero codes");
     if (!(lambda >= 0.0) || !std::isfinite(lambda)) return fail(h, CSC_EINVAL, "lambda must be finite and >= 0");
     if (!(p > 0.0 && p <= 1.0)) return fail(h, CSC_EINVAL, "p must lie in (0, 1]");
     if (n_iter < 0) return fail(h, CSC_EINVAL, "n_iter must be >= 0");
@@ -843,7 +857,10 @@ int code_step_impl(csc_ctx *h, const csc_images *im, const float *x, const uint8
         nzc[0] = c0;
         nzc[1] = c1;
     }
-    {
+    if (fo) {
+        // codes from zero: every list starts empty
+        HIPCHK(hipMemsetAsync(nzc[0], 0, sizeof(unsigned short) * g.n_pix, h->stream));
+    } else {
         PROF(CSC_PK_GATHER);
         HIPCHK(launch_gather_selected(g, K, mw, soff, z, pairs[0], nzc[0], nnzsum, h->stream));
     }
@@ -915,10 +932,22 @@ int code_step_impl(csc_ctx *h, const csc_images *im, const float *x, const uint8
         return st;
     }
     const int cur = n_iter & 1;
-    {
+    if (z) {
         PROF(CSC_PK_SCATTER);
         if (hold) HIPCHK(launch_scatter_selected(g, K, mw, Lists{soff, nzc[cur], pairs[cur]}, z, h->stream));
         else HIPCHK(launch_scatter_dense(g, K, Lists{soff, nzc[cur], pairs[cur]}, z, h->stream));
+    }
+    if (fo) {
+        if (fo->want_stats) {
+            unsigned long long *nnz = reinterpret_cast<unsigned long long *>(sc + SC_CNNZ);
+            HIPCHK(hipMemsetAsync(nnz, 0, sizeof(unsigned long long), h->stream));
+            HIPCHK(launch_sum_counts(nzc[cur], g.n_pix, nnz, h->stream));
+        }
+        fo->lists = Lists{soff, nzc[cur], pairs[cur]};
+        fo->nsel = nsel;
+        fo->Lz = Lz;
+        fo->eta = eta;
+        return CSC_OK;
     }
     if (stats) {
         unsigned long long *nnz = reinterpret_cast<unsigned long long *>(sc + SC_NNZ);
@@ -1083,31 +1112,18 @@ extern "C" int csc_code_step_admm(csc_handle h, const csc_images *im, const floa
     return CSC_OK;
 }
 
-extern "C" int csc_dict_step(csc_handle h, const csc_images *im, const float *x, const uint8_t *W, const float *z,
-                             float *d, int K, int m, csc_surrogate *sur, int n_iter, double step, int n_power,
-                             int precision, double *L_d_out) {
-    if (!h) return CSC_EINVAL;
-    int st = check_images(h, im);
-    if (!st) st = check_filters(h, K, m);
-    if (!st) st = check_precision(h, precision);
-    if (st) return st;
-    if (!x || !d || !z) return fail(h, CSC_EINVAL, "null pointer argument");
-    if (n_iter < 0) return fail(h, CSC_EINVAL, "n_iter must be >= 0");
-    if (n_power < 1) return fail(h, CSC_EINVAL, "n_power must be >= 1");
-    if (!std::isfinite(step)) return fail(h, CSC_EINVAL, "step must be finite");
-    if (sur && (!sur->C || !sur->B || sur->t < 0 || !(sur->Ld_sum >= 0.0)))
-        return fail(h, CSC_EINVAL, "surrogate: need C, B, t >= 0 and Ld_sum >= 0");
-    HIPCHK(hipSetDevice(h->device));
-    if ((st = geometry(h, im))) return st;
+// The filter step of csc_dict_step from the lists of the non-zero codes: exact
+// capacities (offsets = prefix of the lengths), nz an upper bound of their
+// total, xp the entries tagged for the lag pass (row stride lag_rows_stride)
+// when that pass runs.  The arguments are checked and the geometry is set.
+static int dict_step_lists(csc_ctx *h, const float *x, const uint8_t *W, Lists L, unsigned long long nz, const XPair *xp,
+                    float *d, int K, int m, csc_surrogate *sur, int n_iter, double step, int n_power, int precision,
+                    double *L_d_out) {
     const Geometry &g = h->geo;
     const int M = m * m;
     const bool need_ld = sur || step <= 0.0 || L_d_out;
     const bool lag_pass = !W && (sur || need_ld);
-    Lists L;
-    unsigned long long nz = 0;
-    const XPair *xp = nullptr;
-    const unsigned xmul = lag_pass ? lag_rows_stride(g, K, m) : 0u;
-    if ((st = build_nonzero_lists(h, K, z, &L, &nz, xmul ? &xp : nullptr, xmul))) return st;
+    int st = CSC_OK;
     FmLists F;
     if ((st = build_fm_lists(h, K, L, nz, &F))) return st;
     WS(sc, double, WS_SCAL, SC_COUNT);
@@ -1210,6 +1226,100 @@ extern "C" int csc_dict_step(csc_handle h, const csc_images *im, const float *x,
         }
     }
     if (L_d_out) *L_d_out = Ld;
+    return CSC_OK;
+}
+
+extern "C" int csc_dict_step(csc_handle h, const csc_images *im, const float *x, const uint8_t *W, const float *z,
+                             float *d, int K, int m, csc_surrogate *sur, int n_iter, double step, int n_power,
+                             int precision, double *L_d_out) {
+    if (!h) return CSC_EINVAL;
+    int st = check_images(h, im);
+    if (!st) st = check_filters(h, K, m);
+    if (!st) st = check_precision(h, precision);
+    if (st) return st;
+    if (!x || !d || !z) return fail(h, CSC_EINVAL, "null pointer argument");
+    if (n_iter < 0) return fail(h, CSC_EINVAL, "n_iter must be >= 0");
+    if (n_power < 1) return fail(h, CSC_EINVAL, "n_power must be >= 1");
+    if (!std::isfinite(step)) return fail(h, CSC_EINVAL, "step must be finite");
+    if (sur && (!sur->C || !sur->B || sur->t < 0 || !(sur->Ld_sum >= 0.0)))
+        return fail(h, CSC_EINVAL, "surrogate: need C, B, t >= 0 and Ld_sum >= 0");
+    HIPCHK(hipSetDevice(h->device));
+    if ((st = geometry(h, im))) return st;
+    const Geometry &g = h->geo;
+    const bool need_ld = sur || step <= 0.0 || L_d_out;
+    const bool lag_pass = !W && (sur || need_ld);
+    Lists L;
+    unsigned long long nz = 0;
+    const XPair *xp = nullptr;
+    const unsigned xmul = lag_pass ? lag_rows_stride(g, K, m) : 0u;
+    if ((st = build_nonzero_lists(h, K, z, &L, &nz, xmul ? &xp : nullptr, xmul))) return st;
+    return dict_step_lists(h, x, W, L, nz, xp, d, K, m, sur, n_iter, step, n_power, precision, L_d_out);
+}
+
+// Exact-capacity lists (and the lag pass's tagged entries when xmul != 0) from
+// the lists a code step ends with; their capacities sum to cap.  The output
+// takes the code step's other pair and length buffers (free once its last
+// iteration has run) and offsets of its own.
+static int lists_from_code_step(csc_ctx *h, Lists in, int cur, unsigned long long cap, Lists *out,
+                                const XPair **xp_out, unsigned xmul) {
+    const Geometry &g = h->geo;
+    WS(cnt32, unsigned, WS_CNT32, g.n_pix);
+    WS(off, unsigned, WS_COFF, g.n_pix + 1);
+    WS(tmp, unsigned long long, WS_SCANTMP, scan_tmp_elems(g.n_pix));
+    WS(sc, double, WS_SCAL, SC_COUNT);
+    WS(pairs, Pair, cur ? WS_PAIRS0 : WS_PAIRS1, cap + 1);
+    WS(nzc, unsigned short, cur ? WS_NZC0 : WS_NZC1, g.n_pix);
+    XPair *xp = nullptr;
+    if (xmul) {
+        WS(xpb, XPair, WS_XPAIRS, cap + 1);
+        xp = xpb;
+    }
+    PROF(CSC_PK_LISTS);
+    unsigned long long *total = reinterpret_cast<unsigned long long *>(sc + SC_TOTAL);
+    HIPCHK(launch_counts_u32(in.cnt, g.n_pix, cnt32, h->stream));
+    HIPCHK(launch_scan(cnt32, off, g.n_pix, tmp, total, h->stream));
+    HIPCHK(launch_compact_lists(g, in, off, pairs, nzc, xp, xmul, h->stream));
+    *out = Lists{off, nzc, pairs};
+    *xp_out = xp;
+    return CSC_OK;
+}
+
+extern "C" int csc_online_step(csc_handle h, const csc_images *im, const float *x, const uint8_t *W, float *d, int K,
+                               int m, float *z, double lambda, double p, uint64_t seed, uint32_t draw, int n_iter,
+                               double step, int precision, csc_surrogate *sur, int n_dict_iter, int n_power,
+                               csc_code_stats *stats, double *L_d_out) {
+    if (!h) return CSC_EINVAL;
+    if (!sur || !sur->C || !sur->B || sur->t < 0 || !(sur->Ld_sum >= 0.0))
+        return fail(h, CSC_EINVAL, "surrogate: need C, B, t >= 0 and Ld_sum >= 0");
+    if (n_dict_iter < 0) return fail(h, CSC_EINVAL, "n_dict_iter must be >= 0");
+    if (n_power < 1) return fail(h, CSC_EINVAL, "n_power must be >= 1");
+    CodeStepFused fo;
+    fo.want_stats = stats != nullptr;
+    int st = code_step_impl(h, im, x, W, d, K, m, z, lambda, p, seed, draw, n_iter, step, precision, nullptr, false,
+                            &fo);
+    if (st) return st;
+    const Geometry &g = h->geo;
+    const unsigned xmul = W ? 0u : lag_rows_stride(g, K, m);
+    const int cur = n_iter & 1;
+    Lists L;
+    const XPair *xp = nullptr;
+    if ((st = lists_from_code_step(h, fo.lists, cur, fo.nsel, &L, &xp, xmul))) return st;
+    double Ld = 0.0;
+    // the filter step reads the device scalars back once (L_d), which brings the
+    // code statistics along
+    if ((st = dict_step_lists(h, x, W, L, fo.nsel, xp, d, K, m, sur, n_dict_iter, 0.0, n_power, precision, &Ld)))
+        return st;
+    if (L_d_out) *L_d_out = Ld;
+    if (stats) {
+        unsigned long long v, vs;
+        std::memcpy(&v, &h->h_pinned[SC_CNNZ], sizeof(v));
+        std::memcpy(&vs, &h->h_pinned[SC_NNZSUM], sizeof(vs));
+        stats->sampled = (int64_t)fo.nsel;
+        stats->nnz = (int64_t)v;
+        stats->nnz_iter_sum = n_iter > 0 ? (int64_t)(vs - v) : 0;
+        stats->L_z = fo.Lz;
+        stats->step = fo.eta;
+    }
     return CSC_OK;
 }
 

@@ -213,6 +213,37 @@ __global__ __launch_bounds__(TPB) void k_fill_nonzero(const ImgInfo *imgs, int n
     cnt[c.gp] = (unsigned short)nn;
 }
 
+// The list lengths of a code step as 32-bit counts (for the exclusive scan).
+__global__ __launch_bounds__(TPB) void k_counts_u32(const unsigned short *cnt, long long n, unsigned *out) {
+    const long long i = (long long)blockIdx.x * TPB + threadIdx.x;
+    if (i < n) out[i] = cnt[i];
+}
+
+// Exact-capacity lists (offsets = prefix of the lengths) copied from a code
+// step's lists, with the XPair tags of k_fill_nonzero when xp is given.  The
+// entries of a pixel keep their order (ascending k), so the result equals what
+// k_fill_nonzero builds from the dense codes the lists describe.
+__global__ __launch_bounds__(TPB) void k_compact_lists(const ImgInfo *imgs, int n_img, long long n_pix, Lists in,
+                                                       const unsigned *off, Pair *pairs, unsigned short *cnt,
+                                                       XPair *xp, unsigned xmul) {
+    PixelCtx c = flat_ctx(imgs, n_img, n_pix);
+    if (!c.valid) return;
+    const unsigned src = in.off[c.gp], dst = off[c.gp];
+    const int n = in.cnt[c.gp];
+    for (int i0 = 0; i0 < n; i0 += ZB) {
+        Pair e[ZB];
+#pragma unroll
+        for (int u = 0; u < ZB; ++u) e[u] = i0 + u < n ? in.pairs[src + i0 + u] : Pair{0, 0.f};
+#pragma unroll
+        for (int u = 0; u < ZB; ++u) {
+            if (i0 + u >= n) break;
+            pairs[dst + i0 + u] = e[u];
+            if (xp) xp[dst + i0 + u] = XPair{((unsigned)c.x * xmul + (unsigned)e[u].k) * 8u, e[u].v};
+        }
+    }
+    cnt[c.gp] = (unsigned short)n;
+}
+
 __global__ __launch_bounds__(TPB) void k_scatter_dense(const ImgInfo *imgs, int n_img, long long n_pix, int K,
                                                        Lists zl, float *z) {
     PixelCtx c = flat_ctx(imgs, n_img, n_pix);
@@ -945,6 +976,18 @@ hipError_t launch_fill_nonzero(const Geometry &g, int K, const float *z, const u
                                unsigned short *cnt, XPair *xp, unsigned xmul, hipStream_t s) {
     hipLaunchKernelGGL(k_fill_nonzero, dim3(flat_grid(g.n_pix)), dim3(TPB), 0, s, g.d_img, g.n_img, g.n_pix, K, z,
                        off, pairs, cnt, xp, xmul);
+    return hipGetLastError();
+}
+
+hipError_t launch_counts_u32(const unsigned short *cnt, long long n, unsigned *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_counts_u32, dim3((unsigned)((n + TPB - 1) / TPB)), dim3(TPB), 0, s, cnt, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_compact_lists(const Geometry &g, Lists in, const unsigned *off, Pair *pairs, unsigned short *cnt,
+                                XPair *xp, unsigned xmul, hipStream_t s) {
+    hipLaunchKernelGGL(k_compact_lists, dim3(flat_grid(g.n_pix)), dim3(TPB), 0, s, g.d_img, g.n_img, g.n_pix, in, off,
+                       pairs, cnt, xp, xmul);
     return hipGetLastError();
 }
 

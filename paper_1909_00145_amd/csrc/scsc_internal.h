@@ -284,6 +284,12 @@ hipError_t launch_count_nonzero(const Geometry &g, int K, const float *z, unsign
 // xp (may be null): the same entries tagged with their columns for row stride xmul.
 hipError_t launch_fill_nonzero(const Geometry &g, int K, const float *z, const unsigned *off, Pair *pairs,
                                unsigned short *cnt, XPair *xp, unsigned xmul, hipStream_t s);
+// Exact-capacity lists from a code step's lists (lengths in.cnt at offsets in.off):
+// launch_counts_u32 widens the lengths for launch_scan, whose offsets off feed
+// launch_compact_lists (entries, lengths and, with xp, the tags of launch_fill_nonzero).
+hipError_t launch_counts_u32(const unsigned short *cnt, long long n, unsigned *out, hipStream_t s);
+hipError_t launch_compact_lists(const Geometry &g, Lists in, const unsigned *off, Pair *pairs, unsigned short *cnt,
+                                XPair *xp, unsigned xmul, hipStream_t s);
 // Held codes: lists of the non-zero codes of z off the sample (count, then fill),
 // and the scatter of the sample only (the other coordinates of z unchanged).
 hipError_t launch_count_held(const Geometry &g, int K, const unsigned *mask_words, const float *z, unsigned *cnt,

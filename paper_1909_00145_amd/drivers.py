@@ -49,27 +49,26 @@ class OnlineLearner:
     mini-batch from zero, folds it into the surrogates and updates the filters."""
 
     def __init__(self, ctx: Context, im: Images, d, lam: float, p: float, n_code_iter: int = 20, seed: int = 1,
-                 n_dict_iter: int = 1, n_power: int = 20, precision: str = "fp32"):
+                 n_dict_iter: int = 1, n_power: int = 20, precision: str = "fp32", keep_codes: bool = False):
+        """keep_codes: write every mini-batch's codes to ``self.z`` (else they stay on the
+        device as lists only, and ``self.z`` is None)."""
         self.ctx, self.im, self.d = ctx, im, d
         self.K, self.m = int(d.shape[0]), int(d.shape[-1])
         self.lam, self.p, self.T, self.seed = lam, p, n_code_iter, seed
         self.n_dict_iter, self.n_power, self.precision = n_dict_iter, n_power, precision
         self.sur = Surrogate(self.K, self.m, device=d.device)
-        self.z = torch.zeros(self.K * im.n_pix, dtype=torch.float32, device=d.device)
+        self.z = torch.zeros(self.K * im.n_pix, dtype=torch.float32, device=d.device) if keep_codes else None
 
     @property
     def t(self):
         return self.sur.t
 
     def step(self, x, W=None):
-        """Process one mini-batch x (packed like ``im``)."""
+        """Process one mini-batch x (packed like ``im``): one csc_online_step."""
         draw = self.sur.t + 1
-        self.z.zero_()
-        st = self.ctx.code_step(self.im, x, self.d, self.z, self.lam, self.p, self.seed, draw, self.T, W=W,
-                                precision=self.precision, stats=True)
-        Ld = self.ctx.dict_step(self.im, x, self.z, self.d, n_iter=self.n_dict_iter, n_power=self.n_power, W=W,
-                                surrogate=self.sur, precision=self.precision)
-        return st, Ld
+        return self.ctx.online_step(self.im, x, self.d, self.sur, self.lam, self.p, self.seed, draw, self.T,
+                                    z=self.z, W=W, precision=self.precision, n_dict_iter=self.n_dict_iter,
+                                    n_power=self.n_power, stats=True)
 
     def evaluate(self, im: Images, x, n_iter: int = 50, lam: float | None = None, W=None):
         """Objective of eq. (1) on held-out images with codes fitted at p = 1 from zero."""

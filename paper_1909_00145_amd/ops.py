@@ -248,6 +248,30 @@ class Context:
             surrogate.Ld_sum = float(sur.Ld_sum)
         return ld.value
 
+    def online_step(self, im: Images, x, d, surrogate: Surrogate, lam, p, seed, draw, n_iter, z=None, step=0.0,
+                    W=None, precision="fp32", n_dict_iter=1, n_power=20, stats=False):
+        """One step of Alg. 2 (csc_online_step): codes of the mini-batch from zero, then the
+        surrogate and filter update.  z (optional) receives the codes.  Returns
+        (CodeStats or None, L_d of the mini-batch)."""
+        K, m = int(d.shape[0]), int(d.shape[-1])
+        self._sync_stream()
+        _ptr(surrogate.C, torch.float64, "surrogate.C")
+        _ptr(surrogate.B, torch.float64, "surrogate.B", K * m * m)
+        sur = _lib.csc_surrogate(surrogate.C.data_ptr(), surrogate.B.data_ptr(), surrogate.t, surrogate.Ld_sum)
+        st = _lib.csc_code_stats()
+        ld = C.c_double(0.0)
+        rc = self.lib.csc_online_step(
+            self.h, im.cref(), _ptr(x, torch.float32, "x", im.n_pix), _ptr(W, torch.uint8, "W", im.n_pix),
+            _ptr(d, torch.float32, "d", K * m * m), K, m, _ptr(z, torch.float32, "z", K * im.n_pix),
+            float(lam), float(p), int(seed) & (2**64 - 1), int(draw) & (2**32 - 1), int(n_iter), float(step),
+            PRECISIONS[precision], C.byref(sur), int(n_dict_iter), int(n_power), C.byref(st) if stats else None,
+            C.byref(ld))
+        self._check(rc)
+        surrogate.t = int(sur.t)
+        surrogate.Ld_sum = float(sur.Ld_sum)
+        cs = CodeStats(st.sampled, st.nnz, st.L_z, st.step, st.nnz_iter_sum) if stats else None
+        return cs, ld.value
+
     def objective(self, im: Images, x, d, z, lam, W=None):
         K, m = int(d.shape[0]), int(d.shape[-1])
         self._sync_stream()

@@ -1,0 +1,108 @@
+"""csc_online_step, one step of Alg. 2 in one call, against the two calls it
+joins (csc_code_step from zero codes, then csc_dict_step with the
+surrogates), and against the oracle on one case.
+
+The joined call runs the same kernels in the same order on the same lists, so
+the codes, the statistics and B_bar agree exactly.  The lag sums behind C_bar
+and L_d are accumulated with LDS atomics, so those agree to FP64 rounding
+(1e-12 relative) and the filters to 1e-6.  Steps alternate between writing
+the codes out and leaving them on the device; iteration counts of both
+parities take the two list buffers of the code step in turn.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from tests.gpu_helpers import f32, make_problem, packed, rel_err, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1909_00145_amd.ops import Context
+
+    torch.cuda.set_device(0)
+    c = Context(0)
+    yield c
+    c.set_graph(True)
+    c.close()
+
+
+CASES = [
+    # hw, K, m, with_W, precision, lam, p, T, graph
+    ([(30, 26)], 4, 5, False, "fp32", 0.3, 0.3, 7, False),
+    ([(24, 20), (16, 21)], 3, 11, True, "fp32", 0.3, 0.4, 10, False),
+    ([(40, 45), (33, 17)], 20, 11, False, "bf16", 0.5, 0.3, 9, True),
+    ([(23, 31)], 6, 3, False, "fp32", 0.3, 0.5, 0, False),
+    ([(100, 100)] * 4, 100, 11, False, "bf16", 1.0, 0.1, 20, True),
+]
+
+
+@pytest.mark.parametrize("hw,K,m,with_W,precision,lam,p,T,graph", CASES)
+def test_online_step_equals_code_then_dict_step(ctx, hw, K, m, with_W, precision, lam, p, T, graph):
+    from paper_1909_00145_amd.ops import Images, Surrogate
+
+    say("online step", hw, K, m, with_W, precision, "T", T, "graph", graph)
+    ctx.set_graph(graph)
+    im = Images(hw)
+    xs, d, Ws = make_problem(3, hw, K, m, with_W)
+    d = f32(oracle.project_ball(d))
+    xg = packed(im, xs)
+    Wg = packed(im, Ws, torch.uint8) if Ws else None
+    d_ref, d_f = to_dev(d), to_dev(d)
+    sur_ref, sur_f = Surrogate(K, m), Surrogate(K, m)
+    z_ref = torch.zeros(K * im.n_pix, dtype=torch.float32, device="cuda")
+    z_f = torch.full_like(z_ref, 7.0)  # written over where codes are written out
+    for draw in (1, 2, 3):
+        z_ref.zero_()
+        st_ref = ctx.code_step(im, xg, d_ref, z_ref, lam, p, 5, draw, T, W=Wg, precision=precision, stats=True)
+        Ld_ref = ctx.dict_step(im, xg, z_ref, d_ref, W=Wg, surrogate=sur_ref, precision=precision)
+        write = draw != 2
+        st_f, Ld_f = ctx.online_step(im, xg, d_f, sur_f, lam, p, 5, draw, T, z=z_f if write else None, W=Wg,
+                                     precision=precision, stats=True)
+        say("  draw", draw, "nnz", st_f.nnz, st_ref.nnz, "Ld", Ld_f, Ld_ref)
+        assert st_f == st_ref
+        if write:
+            assert torch.equal(z_f, z_ref)
+        assert sur_f.t == sur_ref.t == draw
+        assert abs(Ld_f - Ld_ref) <= 1e-12 * max(Ld_ref, 1e-300)
+        assert abs(sur_f.Ld_sum - sur_ref.Ld_sum) <= 1e-12 * max(sur_ref.Ld_sum, 1e-300)
+        assert torch.equal(sur_f.B, sur_ref.B)
+        assert rel_err(sur_f.C.cpu().numpy(), sur_ref.C.cpu().numpy()) < 1e-12
+        assert rel_err(d_f.cpu().numpy(), d_ref.cpu().numpy()) < 1e-6
+    if T == 0:
+        assert st_f.nnz == 0 and sur_f.Ld_sum == 0.0
+
+
+def test_online_step_against_oracle(ctx):
+    """Codes from the oracle's code step (from zero, step 1 / L_z), surrogates and
+    filters from the oracle's online filter step fed with the oracle's own codes."""
+    from paper_1909_00145_amd.ops import Images, Surrogate
+
+    hw, K, m, lam, p, T = [(30, 26), (17, 22)], 4, 5, 0.3, 0.3, 12
+    say("online step against the oracle", hw, K, m)
+    ctx.set_graph(True)
+    im = Images(hw)
+    xs, d, _ = make_problem(4, hw, K, m)
+    d = f32(oracle.project_ball(d))
+    dg = to_dev(d)
+    sur = Surrogate(K, m)
+    z = torch.zeros(K * im.n_pix, dtype=torch.float32, device="cuda")
+    st = ctx.online_step(im, packed(im, xs), dg, sur, lam, p, 9, 1, T, z=z, stats=True)[0]
+    Lz = oracle.lipschitz_code(d, im.max_side)
+    zr = [oracle.code_step(x, d, np.zeros((K,) + x.shape), lam, p, 9, 1, T, step=1.0 / Lz, image_index=i)[0]
+          for i, x in enumerate(xs)]
+    got = im.unpack(z.cpu().numpy(), K)
+    err = rel_err(np.concatenate([g.ravel() for g in got]), np.concatenate([r.ravel() for r in zr]))
+    say("  codes rel err", err, "L_z", st.L_z, Lz)
+    assert err < 1e-5
+    assert abs(st.L_z - Lz) <= 1e-12 * Lz
+    state = oracle.OnlineState(K, m)
+    dr = oracle.dict_step_online(xs, None, zr, d, state)
+    say("  d rel err", rel_err(dg.cpu().numpy(), dr), "Ld_sum", sur.Ld_sum, state.Ld_sum)
+    assert rel_err(dg.cpu().numpy(), dr) < 1e-4
+    assert rel_err(sur.dense_C(), state.C) < 1e-5
+    assert abs(sur.Ld_sum - state.Ld_sum) <= 1e-5 * state.Ld_sum
