@@ -45,20 +45,16 @@ PEAK_HBM = 8.0e12
 # valid only for the kernel source they were taken on (first 16 hex digits of its SHA-256).
 # Keyed by (kernel class, precision).
 TRAFFIC = {
-    ("synth", "bf16"): ("kernels_mfma.hip", "16ec6e23e6f32e19", 43.33e6, 1.02e6),
-    ("adjoint", "bf16"): ("kernels_code.hip", "82dce5536bf66e1f", 34.15e6, 11.07e6),
-    ("corr", "bf16"): ("kernels_dict.hip", "0bf8d154ab50cc41", 27.00e6, 4.07e6),
-    ("sur_expand", "bf16"): ("kernels_sur.hip", "d1aa18db8753e5f7", 732.62e6, 603.88e6),
+    ("synth", "bf16"): ("kernels_mfma.hip", "16ec6e23e6f32e19", 43.34e6, 1.02e6),
+    ("adjoint", "bf16"): ("kernels_code.hip", "cc5c855ad395c81b", 34.16e6, 11.07e6),
+    ("corr", "bf16"): ("kernels_dict.hip", "0bf8d154ab50cc41", 27.01e6, 4.07e6),
+    ("sur_expand", "bf16"): ("kernels_sur.hip", "d1aa18db8753e5f7", 732.34e6, 603.90e6),
     ("power", "bf16"): ("kernels_sur.hip", "d1aa18db8753e5f7", 18.21e6, 0.69e6),
-    ("gather", "bf16"): ("kernels_code.hip", "82dce5536bf66e1f", 89.16e6, 0.40e6),
-    ("scatter", "bf16"): ("kernels_code.hip", "82dce5536bf66e1f", 17.30e6, 80.05e6),
-    ("synth", "fp32"): ("kernels_code.hip", "82dce5536bf66e1f", 18.08e6, 0.81e6),
-    ("adjoint", "fp32"): ("kernels_code.hip", "82dce5536bf66e1f", 20.94e6, 10.63e6),
+    ("synth", "fp32"): ("kernels_code.hip", "cc5c855ad395c81b", 18.12e6, 0.81e6),
+    ("adjoint", "fp32"): ("kernels_code.hip", "cc5c855ad395c81b", 20.94e6, 10.63e6),
     ("corr", "fp32"): ("kernels_dict.hip", "0bf8d154ab50cc41", 27.01e6, 4.07e6),
-    ("sur_expand", "fp32"): ("kernels_sur.hip", "d1aa18db8753e5f7", 732.71e6, 603.94e6),
+    ("sur_expand", "fp32"): ("kernels_sur.hip", "d1aa18db8753e5f7", 732.38e6, 603.89e6),
     ("power", "fp32"): ("kernels_sur.hip", "d1aa18db8753e5f7", 18.21e6, 0.69e6),
-    ("gather", "fp32"): ("kernels_code.hip", "82dce5536bf66e1f", 89.16e6, 0.40e6),
-    ("scatter", "fp32"): ("kernels_code.hip", "82dce5536bf66e1f", 17.30e6, 80.05e6),
 }
 
 
