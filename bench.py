@@ -100,7 +100,11 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--eager", action="store_true",
-                    help="launch the code step's iterations one by one instead of replaying them from a HIP graph")
+                    help="launch the code step's iterations one by one instead of replaying them from a HIP graph "
+                         "(the default for the online workload)")
+    ap.add_argument("--graph", action="store_true",
+                    help="replay the code step's iterations and the power iteration from HIP graphs (the default "
+                         "for the batch and ragged workloads)")
     ap.add_argument("--tto", action="store_true",
                     help="also measure time-to-objective of online learning, FP32 against BF16 (adds ~1 min)")
     ap.add_argument("--tto-batches", type=int, default=100, help="mini-batches of the time-to-objective run")
@@ -481,7 +485,10 @@ def main():
         r["kernels"] = kernels
         return r
 
-    graph = not args.eager
+    # The joined online step queues a whole mini-batch of launches ahead of the GPU,
+    # so graph replay only adds its launch latency there (4.40 against 4.52 ms per
+    # step measured); the separate calls of the other workloads keep the graphs.
+    graph = args.graph or (not args.eager and args.workload != "online")
     # the headline run (no event timing), then the same steps eagerly with every kernel
     # class timed by HIP events, for the per-kernel figures and the roofline
     res = timed_run(args.precision, graph, False)
