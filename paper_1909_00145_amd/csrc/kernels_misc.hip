@@ -90,8 +90,18 @@ __global__ __launch_bounds__(1024) void k_reduce_pairs(const double *partial, in
     }
 }
 
+// The P roots of unity of the DFT grid: tw[ph] = (cos, sin)(-2 pi ph / P).  Both
+// passes index this table with the phase (u b) mod P.
+__global__ void k_dft_twiddles(int P, double2 *tw) {
+    const int ph = blockIdx.x * blockDim.x + threadIdx.x;
+    if (ph >= P) return;
+    double sn, cs;
+    sincos(-2.0 * M_PI * (double)ph / (double)P, &sn, &cs);
+    tw[ph] = make_double2(cs, sn);
+}
+
 // Row DFT of every filter row, zero padded to P: F1[k][a][u] = sum_b d[k][a][b] e^{-2 pi i u b / P}.
-__global__ void k_dft_rows(const float *d, int K, int m, int P, double2 *F1) {
+__global__ void k_dft_rows(const float *d, int K, int m, int P, const double2 *__restrict__ tw, double2 *F1) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long n = (long long)K * m * P;
     if (i >= n) return;
@@ -100,11 +110,9 @@ __global__ void k_dft_rows(const float *d, int K, int m, int P, double2 *F1) {
     const float *row = d + ka * m;
     double re = 0.0, im = 0.0;
     for (int b = 0; b < m; ++b) {
-        const int ph = (int)(((long long)u * b) % P);
-        double sn, cs;
-        sincos(-2.0 * M_PI * (double)ph / (double)P, &sn, &cs);
-        re += (double)row[b] * cs;
-        im += (double)row[b] * sn;
+        const double2 t = tw[((long long)u * b) % P];
+        re += (double)row[b] * t.x;
+        im += (double)row[b] * t.y;
     }
     F1[i] = make_double2(re, im);
 }
@@ -113,7 +121,8 @@ __global__ void k_dft_rows(const float *d, int K, int m, int P, double2 *F1) {
 // frequency (v, u): part[chunk][v P + u].
 constexpr int DFT_KC = 8;
 
-__global__ __launch_bounds__(256) void k_dft_cols(const double2 *F1, int K, int m, int P, double *part) {
+__global__ __launch_bounds__(256) void k_dft_cols(const double2 *F1, int K, int m, int P,
+                                                   const double2 *__restrict__ tw, double *part) {
     const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
     if (i >= (long long)P * P) return;
     const int u = (int)(i % P), v = (int)(i / P);
@@ -123,8 +132,9 @@ __global__ __launch_bounds__(256) void k_dft_cols(const double2 *F1, int K, int 
         tc[a] = 0.0;
         ts[a] = 0.0;
         if (a < m) {
-            const int ph = (int)(((long long)v * a) % P);
-            sincos(-2.0 * M_PI * (double)ph / (double)P, &ts[a], &tc[a]);
+            const double2 t = tw[((long long)v * a) % P];
+            tc[a] = t.x;
+            ts[a] = t.y;
         }
     }
     const int k0 = blockIdx.y * DFT_KC, k1 = min(K, k0 + DFT_KC);
@@ -187,21 +197,24 @@ hipError_t launch_objective(const Geometry &g, int K, int m, const float *x, con
 }
 
 long long lipschitz_tmp_elems(int K, int m, int P) {
-    return 2LL * K * m * P + (long long)((K + DFT_KC - 1) / DFT_KC) * P * P + 1;
+    return 2LL * K * m * P + (long long)((K + DFT_KC - 1) / DFT_KC) * P * P + 2LL * P + 1;
 }
 
 hipError_t launch_lipschitz_code(const float *d, int K, int m, int P, double *tmp, double *out, hipStream_t s) {
     double2 *F1 = reinterpret_cast<double2 *>(tmp);
     const long long n1 = (long long)K * m * P;
-    hipLaunchKernelGGL(k_dft_rows, dim3((unsigned)((n1 + 255) / 256)), dim3(256), 0, s, d, K, m, P, F1);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    e = hipMemsetAsync(out, 0, sizeof(double), s);
-    if (e != hipSuccess) return e;
     const long long n2 = (long long)P * P;
     const int nch = (K + DFT_KC - 1) / DFT_KC;
     double *part = tmp + 2LL * K * m * P;
-    hipLaunchKernelGGL(k_dft_cols, dim3((unsigned)((n2 + 255) / 256), nch), dim3(256), 0, s, F1, K, m, P, part);
+    double2 *tw = reinterpret_cast<double2 *>(part + (long long)nch * n2);  // 2P doubles, 16-byte aligned
+    hipLaunchKernelGGL(k_dft_twiddles, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, P, tw);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_dft_rows, dim3((unsigned)((n1 + 255) / 256)), dim3(256), 0, s, d, K, m, P, tw, F1);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    e = hipMemsetAsync(out, 0, sizeof(double), s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_dft_cols, dim3((unsigned)((n2 + 255) / 256), nch), dim3(256), 0, s, F1, K, m, P, tw, part);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_dft_max, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, s, part, nch, n2,
                        reinterpret_cast<unsigned long long *>(out));
