@@ -797,12 +797,20 @@ int code_step_impl(csc_ctx *h, const csc_images *im, const float *x, const uint8
     // The work that does not depend on the size of the selection is queued before
     // the read-back, so that the GPU has it in hand when the host waits.
     WS(R, float, WS_R, g.n_pix);
+    // step and threshold as device scalars (from L_z on the device when no step is
+    // given), and the counter of list entries at zero
     unsigned long long *nnzsum = reinterpret_cast<unsigned long long *>(sc + SC_NNZSUM);
-    HIPCHK(hipMemsetAsync(nnzsum, 0, sizeof(unsigned long long), h->stream));
-    // step and threshold as device scalars (from L_z on the device when no step is given)
     float *ethr = reinterpret_cast<float *>(sc + SC_ETHR);
-    if (step > 0.0) HIPCHK(launch_set2(ethr, (float)step, (float)(step * lambda), h->stream));
-    else HIPCHK(launch_set_step(ethr, sc + SC_LZ, lambda, h->stream));
+    HIPCHK(launch_set_step(ethr, sc + SC_LZ, step, lambda, nnzsum, h->stream));
+    unsigned short *nzc[2];
+    {
+        WS(c0, unsigned short, WS_NZC0, g.n_pix);
+        WS(c1, unsigned short, WS_NZC1, g.n_pix);
+        nzc[0] = c0;
+        nzc[1] = c1;
+    }
+    // codes from zero: every list starts empty
+    if (fo) HIPCHK(hipMemsetAsync(nzc[0], 0, sizeof(unsigned short) * g.n_pix, h->stream));
     const float *xi = x, *di = d;
     const uint8_t *Wi = W;
     const bool use_graph = h->graphs && n_iter > 0 &&
@@ -846,21 +854,13 @@ int code_step_impl(csc_ctx *h, const csc_images *im, const float *x, const uint8
     std::memcpy(&nsel, &h->h_pinned[SC_TOTAL], sizeof(nsel));
     if (nsel >= (1ULL << 32)) return fail(h, CSC_EUNSUPPORTED, "more than 2^32 selected coordinates");
     Pair *pairs[2];
-    unsigned short *nzc[2];
     {
         WS(p0, Pair, WS_PAIRS0, nsel + 1);
         WS(p1, Pair, WS_PAIRS1, nsel + 1);
-        WS(c0, unsigned short, WS_NZC0, g.n_pix);
-        WS(c1, unsigned short, WS_NZC1, g.n_pix);
         pairs[0] = p0;
         pairs[1] = p1;
-        nzc[0] = c0;
-        nzc[1] = c1;
     }
-    if (fo) {
-        // codes from zero: every list starts empty
-        HIPCHK(hipMemsetAsync(nzc[0], 0, sizeof(unsigned short) * g.n_pix, h->stream));
-    } else {
+    if (!fo) {
         PROF(CSC_PK_GATHER);
         HIPCHK(launch_gather_selected(g, K, mw, soff, z, pairs[0], nzc[0], nnzsum, h->stream));
     }

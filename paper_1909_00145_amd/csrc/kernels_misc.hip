@@ -92,8 +92,9 @@ __global__ __launch_bounds__(1024) void k_reduce_pairs(const double *partial, in
 
 // The P roots of unity of the DFT grid: tw[ph] = (cos, sin)(-2 pi ph / P).  Both
 // passes index this table with the phase (u b) mod P.
-__global__ void k_dft_twiddles(int P, double2 *tw) {
+__global__ void k_dft_twiddles(int P, double2 *tw, double *maxv) {
     const int ph = blockIdx.x * blockDim.x + threadIdx.x;
+    if (ph == 0) *maxv = 0.0;  // the running maximum of k_dft_max starts from zero
     if (ph >= P) return;
     double sn, cs;
     sincos(-2.0 * M_PI * (double)ph / (double)P, &sn, &cs);
@@ -207,13 +208,11 @@ hipError_t launch_lipschitz_code(const float *d, int K, int m, int P, double *tm
     const int nch = (K + DFT_KC - 1) / DFT_KC;
     double *part = tmp + 2LL * K * m * P;
     double2 *tw = reinterpret_cast<double2 *>(part + (long long)nch * n2);  // 2P doubles, 16-byte aligned
-    hipLaunchKernelGGL(k_dft_twiddles, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, P, tw);
+    hipLaunchKernelGGL(k_dft_twiddles, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, P, tw, out);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_dft_rows, dim3((unsigned)((n1 + 255) / 256)), dim3(256), 0, s, d, K, m, P, tw, F1);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    e = hipMemsetAsync(out, 0, sizeof(double), s);
-    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_dft_cols, dim3((unsigned)((n2 + 255) / 256), nch), dim3(256), 0, s, F1, K, m, P, tw, part);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_dft_max, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, s, part, nch, n2,
@@ -277,18 +276,25 @@ hipError_t launch_set2(float *dst, float a, float b, hipStream_t s) {
     return hipGetLastError();
 }
 
-// dst = {(float)(1 / L), (float)(lambda / L)} from the device scalar L (the FP64
-// operations the host would do with L); {0, 0} when L is not positive.
-__global__ void k_set_step(float *dst, const double *L, double lambda) {
+// The step and threshold of a code step, and its counter of list entries set
+// to zero: dst = {(float)eta, (float)(eta lambda)} with eta = step when step > 0,
+// else eta = 1 / L from the device scalar L (the FP64 operations the host would
+// do; 0 when L is not positive).
+__global__ void k_set_step(float *dst, const double *L, double step, double lambda, unsigned long long *counter) {
     if (threadIdx.x != 0) return;
-    const double Lv = *L;
-    const double eta = Lv > 0.0 ? 1.0 / Lv : 0.0;
+    double eta = step;
+    if (!(step > 0.0)) {
+        const double Lv = *L;
+        eta = Lv > 0.0 ? 1.0 / Lv : 0.0;
+    }
     dst[0] = (float)eta;
     dst[1] = (float)(eta * lambda);
+    *counter = 0ull;
 }
 
-hipError_t launch_set_step(float *dst, const double *L, double lambda, hipStream_t s) {
-    hipLaunchKernelGGL(k_set_step, dim3(1), dim3(64), 0, s, dst, L, lambda);
+hipError_t launch_set_step(float *dst, const double *L, double step, double lambda, unsigned long long *counter,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(k_set_step, dim3(1), dim3(64), 0, s, dst, L, step, lambda, counter);
     return hipGetLastError();
 }
 

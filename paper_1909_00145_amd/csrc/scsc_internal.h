@@ -418,7 +418,8 @@ hipError_t launch_ista_grad_u(long long n, const float *z, const float *g, const
 hipError_t launch_axpby(long long n, float a, const float *x, float b, const float *y, float *out, hipStream_t s);
 // dst[0] = a, dst[1] = b (device scalars written in stream order).
 hipError_t launch_set2(float *dst, float a, float b, hipStream_t s);
-hipError_t launch_set_step(float *dst, const double *L, double lambda, hipStream_t s);
+hipError_t launch_set_step(float *dst, const double *L, double step, double lambda, unsigned long long *counter,
+                           hipStream_t s);
 
 // FP64 objective: out[0] = data term, out[1] = L1 norm.
 hipError_t launch_objective(const Geometry &g, int K, int m, const float *x, const unsigned char *W,
