@@ -204,7 +204,7 @@ int csc_dict_step(csc_handle h, const csc_images *im, const float *x, const uint
  * steps of eq. (9) on the filters (as csc_dict_step with sur).  The result equals those two
  * calls in sequence; joined, the filter step takes the code step's final lists instead of
  * rebuilding them from the dense codes, and the host waits for the GPU twice instead of
- * four times (the selection count, then L_d together with the code statistics).
+ * three times (the selection count, then L_d together with the code statistics).
  *   d : filters, in/out (the code step reads the filters given, the filter step updates them).
  *   z : codes, out, packed [K][pixels] per image; may be NULL (the codes then stay on the
  *       device as lists only and are not written out).
