@@ -106,3 +106,35 @@ def test_online_step_against_oracle(ctx):
     assert rel_err(dg.cpu().numpy(), dr) < 1e-4
     assert rel_err(sur.dense_C(), state.C) < 1e-5
     assert abs(sur.Ld_sum - state.Ld_sum) <= 1e-5 * state.Ld_sum
+
+
+def test_online_step_rejects_bad_arguments(ctx):
+    """Argument errors come back before anything is written."""
+    from paper_1909_00145_amd import CSCError
+    from paper_1909_00145_amd.ops import Images, Surrogate
+
+    hw, K, m = [(20, 18)], 3, 5
+    im = Images(hw)
+    xs, d, _ = make_problem(3, hw, K, m)
+    xg, dg = packed(im, xs), to_dev(d)
+    sur = Surrogate(K, m)
+    z = torch.full((K * im.n_pix,), 7.0, device="cuda")
+    d0, z0 = dg.clone(), z.clone()
+    bad = [
+        dict(n_power=0),
+        dict(n_dict_iter=-1),
+        dict(precision="fp16"),
+    ]
+    for kw in bad:
+        args = dict(z=z, n_power=20, n_dict_iter=1, precision="fp32")
+        args.update(kw)
+        with pytest.raises((CSCError, KeyError)):
+            ctx.online_step(im, xg, dg, sur, 0.3, 0.3, 1, 1, 5, **args)
+    with pytest.raises(CSCError):
+        ctx.online_step(im, xg, dg, sur, -1.0, 0.3, 1, 1, 5, z=z)  # lambda < 0
+    with pytest.raises(CSCError):
+        ctx.online_step(im, xg, dg, sur, 0.3, 1.5, 1, 1, 5, z=z)  # p > 1
+    torch.cuda.synchronize()
+    assert torch.equal(dg, d0) and torch.equal(z, z0)
+    assert sur.t == 0 and sur.Ld_sum == 0.0
+    assert not bool(sur.C.any()) and not bool(sur.B.any())
