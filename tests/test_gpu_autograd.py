@@ -59,7 +59,10 @@ def _unrolled_case(ctx, hw, K, m, p, lam, T, with_W, seed=4):
     xs, d, Ws = make_problem(seed, hw, K, m, with_W)
     im = Images(hw)
     mask = ctx.mask(im, K, p, seed, 1)
-    masks = [a.astype(bool) for a in im.unpack(mask.cpu().numpy(), K)]
+    # the oracle side takes its own sample; the GPU's must equal it bit for bit
+    masks = [oracle.bernoulli_mask(K, int(H), int(W), p, seed, 1, i).astype(bool) for i, (H, W) in enumerate(hw)]
+    got = [a.astype(bool) for a in im.unpack(mask.cpu().numpy(), K)]
+    assert all(np.array_equal(a, b) for a, b in zip(got, masks))
     eta = 1.0 / oracle.lipschitz_code(d, im.max_side)
     rng = np.random.default_rng(seed)
     z0s = [np.where(S, f32(0.05 * rng.standard_normal(S.shape)), 0.0) for S in masks]

@@ -59,4 +59,3 @@ def test_online_step_overcomplete(ctx, K, m, hw):
         assert rel_err(sur.B.cpu().numpy(), Bsum.ravel()) < 1e-12
         assert abs(sur.Ld_sum - Ld_sum) <= 1e-5 * Ld_sum
         assert err < TOL32
-        dr = f32(dg.cpu().numpy())  # continue from the GPU's FP32 filters
