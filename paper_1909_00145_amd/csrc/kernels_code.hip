@@ -20,37 +20,33 @@ namespace {
 
 // ---------------------------------------------------------------------------
 // Selection (eq. 2): one Philox call yields the words of 4 consecutive
-// coordinate indices l = (y W + x) K + k, so a pixel needs about K / 4 calls.
+// coordinate indices l = (y W + x) K + k.  Thread (pixel, word w) draws the 32
+// filters of its mask word (about 8 calls) and adds the word's population to the
+// pixel's count (zeroed before the launch), so a pixel's draws run in parallel.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(TPB) void k_mask_count(const ImgInfo *imgs, int n_img, int K,
                                                     unsigned long long thr, uint2 key, unsigned draw,
                                                     long long n_pix, unsigned *mask_words, unsigned *cnt) {
     PixelCtx c = flat_ctx(imgs, n_img, n_pix);
     if (!c.valid) return;
-    const unsigned long long l0 = (unsigned long long)c.p_img * (unsigned long long)K;
-    const unsigned long long l1 = l0 + (unsigned long long)K;
+    const int kb = (int)blockIdx.y * 32, ke = min(K, kb + 32);
+    const unsigned long long base = (unsigned long long)c.p_img * (unsigned long long)K;
+    const unsigned long long l0 = base + (unsigned long long)kb, l1 = base + (unsigned long long)ke;
     const bool all = thr > 0xFFFFFFFFull;
     unsigned cur = 0;
-    int total = 0;
     for (unsigned long long g4 = l0 >> 2; (g4 << 2) < l1; ++g4) {
         uint4 w = philox4x32_10(make_uint4((unsigned)g4, (unsigned)(g4 >> 32), (unsigned)c.im.index, draw), key);
         unsigned ws[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            unsigned long long l = (g4 << 2) + j;
+            const unsigned long long l = (g4 << 2) + j;
             if (l < l0 || l >= l1) continue;
-            int k = (int)(l - l0);
-            if (all || (unsigned long long)ws[j] < thr) {
-                cur |= 1u << (k & 31);
-                ++total;
-            }
-            if ((k & 31) == 31 || k == K - 1) {
-                mask_words[(long long)(k >> 5) * n_pix + c.gp] = cur;
-                cur = 0;
-            }
+            if (all || (unsigned long long)ws[j] < thr) cur |= 1u << ((int)(l - base) & 31);
         }
     }
-    cnt[c.gp] = (unsigned)total;
+    mask_words[(long long)blockIdx.y * n_pix + c.gp] = cur;
+    const unsigned n = (unsigned)__popc(cur);
+    if (n) atomicAdd(&cnt[c.gp], n);
 }
 
 __global__ __launch_bounds__(TPB) void k_expand_mask(const ImgInfo *imgs, const TileInfo *tiles, int K,
@@ -935,8 +931,10 @@ int filter_chunk() {
 hipError_t launch_mask_count(const Geometry &g, int K, unsigned long long thr, unsigned long long seed,
                              unsigned draw, unsigned *mask_words, unsigned *cnt, hipStream_t s) {
     uint2 key = make_uint2((unsigned)seed, (unsigned)(seed >> 32));
-    hipLaunchKernelGGL(k_mask_count, dim3(flat_grid(g.n_pix)), dim3(TPB), 0, s, g.d_img, g.n_img, K, thr, key, draw,
-                       g.n_pix, mask_words, cnt);
+    hipError_t e = hipMemsetAsync(cnt, 0, sizeof(unsigned) * (size_t)g.n_pix, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_mask_count, dim3(flat_grid(g.n_pix), (unsigned)((K + 31) / 32)), dim3(TPB), 0, s, g.d_img,
+                       g.n_img, K, thr, key, draw, g.n_pix, mask_words, cnt);
     return hipGetLastError();
 }
 
