@@ -45,15 +45,15 @@ PEAK_HBM = 8.0e12
 # valid only for the kernel source they were taken on (first 16 hex digits of its SHA-256).
 # Keyed by (kernel class, precision).
 TRAFFIC = {
-    ("synth", "bf16"): ("kernels_mfma.hip", "16ec6e23e6f32e19", 43.34e6, 1.02e6),
-    ("adjoint", "bf16"): ("kernels_code.hip", "cc5c855ad395c81b", 34.16e6, 11.07e6),
-    ("corr", "bf16"): ("kernels_dict.hip", "0bf8d154ab50cc41", 27.01e6, 4.07e6),
-    ("sur_expand", "bf16"): ("kernels_sur.hip", "d1aa18db8753e5f7", 732.34e6, 603.90e6),
+    ("synth", "bf16"): ("kernels_mfma.hip", "16ec6e23e6f32e19", 43.33e6, 1.02e6),
+    ("adjoint", "bf16"): ("kernels_code.hip", "5513de82161f2941", 34.15e6, 11.07e6),
+    ("corr", "bf16"): ("kernels_dict.hip", "0bf8d154ab50cc41", 27.00e6, 4.07e6),
+    ("sur_expand", "bf16"): ("kernels_sur.hip", "d1aa18db8753e5f7", 732.41e6, 603.92e6),
     ("power", "bf16"): ("kernels_sur.hip", "d1aa18db8753e5f7", 18.21e6, 0.69e6),
-    ("synth", "fp32"): ("kernels_code.hip", "cc5c855ad395c81b", 18.12e6, 0.81e6),
-    ("adjoint", "fp32"): ("kernels_code.hip", "cc5c855ad395c81b", 20.94e6, 10.63e6),
+    ("synth", "fp32"): ("kernels_code.hip", "5513de82161f2941", 18.08e6, 0.80e6),
+    ("adjoint", "fp32"): ("kernels_code.hip", "5513de82161f2941", 20.94e6, 10.64e6),
     ("corr", "fp32"): ("kernels_dict.hip", "0bf8d154ab50cc41", 27.01e6, 4.07e6),
-    ("sur_expand", "fp32"): ("kernels_sur.hip", "d1aa18db8753e5f7", 732.38e6, 603.89e6),
+    ("sur_expand", "fp32"): ("kernels_sur.hip", "d1aa18db8753e5f7", 732.41e6, 603.94e6),
     ("power", "fp32"): ("kernels_sur.hip", "d1aa18db8753e5f7", 18.21e6, 0.69e6),
 }
 
