@@ -60,52 +60,61 @@ def _check_filters(d: np.ndarray) -> int:
     return K
 
 
+def _padded(a: np.ndarray, c: int) -> np.ndarray:
+    """a [..., H, W] embedded in c zero pixels on every side."""
+    H, W = a.shape[-2:]
+    ap = np.zeros(a.shape[:-2] + (H + 2 * c, W + 2 * c))
+    ap[..., c : c + H, c : c + W] = a
+    return ap
+
+
+def _shifted_windows(r: np.ndarray, m: int) -> np.ndarray:
+    """R[s, q] = r[q + s] (zero outside the image) for the m*m taps s in row-major
+    order and the pixels q in row-major order: [m*m, H*W]."""
+    c = m // 2
+    H, W = r.shape
+    rp = _padded(r, c)
+    R = np.empty((m * m, H * W))
+    for sy, sx in _taps(m):
+        R[(sy + c) * m + (sx + c)] = rp[c + sy : c + sy + H, c + sx : c + sx + W].ravel()
+    return R
+
+
 def synthesize(d: np.ndarray, z: np.ndarray) -> np.ndarray:
     """Reconstruction D z = sum_k d_k * z_k of eq. (1) for one image.
 
-    d: [K, m, m]; z: [K, H, W]  ->  [H, W].  Tap by tap, the shifted code maps
-    z_k[p - s] are weighted by d_k[s] and summed over k (a tensordot).
+    d: [K, m, m]; z: [K, H, W]  ->  [H, W].  The sum over filters is one matrix
+    product, Y[s] = sum_k d_k[s] z_k on the zero-padded grid; then
+    y[p] = sum_s Y[s][p - s], tap by tap.
     """
     K = _check_filters(d)
     m = d.shape[1]
     c = m // 2
     _, H, W = z.shape
-    zp = np.zeros((K, H + 2 * c, W + 2 * c))
-    zp[:, c : c + H, c : c + W] = z
+    zp = _padded(z, c)
+    Hp, Wp = zp.shape[1:]
+    Y = (d.reshape(K, m * m).T @ zp.reshape(K, Hp * Wp)).reshape(m * m, Hp, Wp)
     y = np.zeros((H, W))
     for sy, sx in _taps(m):
-        # z_k[p - s] for p in the image: padded rows (p_y - s_y + c)
-        shifted = zp[:, c - sy : c - sy + H, c - sx : c - sx + W]
-        y += np.tensordot(d[:, sy + c, sx + c], shifted, axes=(0, 0))
+        # Y[s] at p - s for p in the image: padded rows (p_y - s_y + c)
+        y += Y[(sy + c) * m + (sx + c), c - sy : c - sy + H, c - sx : c - sx + W]
     return y
 
 
 def adjoint(d: np.ndarray, r: np.ndarray) -> np.ndarray:
-    """D^T r: correlation of the residual with every filter.  [H, W] -> [K, H, W]."""
+    """D^T r: correlation of the residual with every filter, g_k[q] = sum_s d_k[s] r[q + s].
+    [H, W] -> [K, H, W]; one matrix product of the filters with the shifted windows of r."""
     K = _check_filters(d)
     m = d.shape[1]
-    c = m // 2
     H, W = r.shape
-    rp = np.zeros((H + 2 * c, W + 2 * c))
-    rp[c : c + H, c : c + W] = r
-    g = np.zeros((K, H, W))
-    for sy, sx in _taps(m):
-        shifted = rp[c + sy : c + sy + H, c + sx : c + sx + W]  # r[q + s]
-        g += d[:, sy + c, sx + c][:, None, None] * shifted[None, :, :]
-    return g
+    return (d.reshape(K, m * m) @ _shifted_windows(r, m)).reshape(K, H, W)
 
 
 def filter_corr(z: np.ndarray, r: np.ndarray, m: int) -> np.ndarray:
-    """Z^T r for one image: G_k[s] = sum_q z_k[q] r[q + s].  [K,H,W],[H,W] -> [K,m,m]."""
+    """Z^T r for one image: G_k[s] = sum_q z_k[q] r[q + s].  [K,H,W],[H,W] -> [K,m,m];
+    one matrix product of the codes with the shifted windows of r."""
     K, H, W = z.shape
-    c = m // 2
-    rp = np.zeros((H + 2 * c, W + 2 * c))
-    rp[c : c + H, c : c + W] = r
-    G = np.zeros((K, m, m))
-    for sy, sx in _taps(m):
-        shifted = rp[c + sy : c + sy + H, c + sx : c + sx + W]
-        G[:, sy + c, sx + c] = np.tensordot(z, shifted, axes=([1, 2], [0, 1]))
-    return G
+    return (z.reshape(K, H * W) @ _shifted_windows(r, m).T).reshape(K, m, m)
 
 
 def code_matrix(z: np.ndarray, m: int) -> np.ndarray:
@@ -148,11 +157,11 @@ def bernoulli_mask(K: int, H: int, W: int, p: float, seed: int, draw: int, image
     image_index, draw) under key (lo32(seed), hi32(seed)).
     """
     thr = sample_threshold(p)
-    y, x, k = np.meshgrid(np.arange(H), np.arange(W), np.arange(K), indexing="ij")
-    l = ((y.astype(np.uint64) * np.uint64(W) + x.astype(np.uint64)) * np.uint64(K) + k.astype(np.uint64))
-    q = l >> np.uint64(2)
+    n = H * W * K
+    # one Philox call per counter q = l >> 2 gives the words of l = 4q .. 4q + 3
+    q = np.arange((n + 3) // 4, dtype=np.uint64)
     seed = int(seed) & ((1 << 64) - 1)
-    w0, w1, w2, w3 = philox4x32_10(
+    w = philox4x32_10(
         q & np.uint64(0xFFFFFFFF),
         q >> np.uint64(32),
         np.uint64(image_index & 0xFFFFFFFF),
@@ -160,9 +169,9 @@ def bernoulli_mask(K: int, H: int, W: int, p: float, seed: int, draw: int, image
         np.uint64(seed & 0xFFFFFFFF),
         np.uint64(seed >> 32),
     )
-    sel = (l & np.uint64(3)).astype(np.int64)
-    words = np.choose(sel, [w0, w1, w2, w3])
-    sampled = words < np.uint64(thr) if thr < (1 << 32) else np.ones(words.shape, dtype=bool)
+    words = np.stack(w, axis=1).reshape(-1)[:n]  # words[l] = word (l & 3) of counter l >> 2
+    sampled = words < np.uint64(thr) if thr < (1 << 32) else np.ones(n, dtype=bool)
+    sampled = sampled.reshape(H, W, K)  # l = (y W + x) K + k
     # [H, W, K] -> [K, H, W]
     return np.ascontiguousarray(np.transpose(sampled, (2, 0, 1)))
 
