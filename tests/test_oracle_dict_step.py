@@ -7,7 +7,12 @@
   the definition with loops), C d - B = -Z^T W (x - Z d), and the running
   sums divided by t equal the eq. (8) recursion;
 * the online step at t = 1 equals the batch projected-gradient step with the
-  same step size.
+  same step size;
+* past t = 1: single delta codes give a closed form at every t, the t = 2 step
+  equals the batch step on the union of both mini-batches with step
+  1 / (L_1 + L_2), a repeated mini-batch gives the batch step at every t, and
+  each step lowers the eq. (9) surrogate objective built from explicit code
+  matrices.
 """
 
 import numpy as np
@@ -154,3 +159,90 @@ def test_batch_dict_step_decreases_objective(rng):
         assert f1 <= f0 + 1e-12 * f0
         f0 = f1
     assert np.all(np.sqrt((d ** 2).sum(axis=(1, 2))) <= 1 + 1e-14)
+
+
+# ---------------------------------------------------------------------------
+# The online step past its first mini-batch (eq. (8) averaging, eq. (9) step).
+# At t >= 2 the surrogates are C^t = (C_1 + ... + C_t) / t and
+# B^t = (B_1 + ... + B_t) / t, and the step divides by L^t = (L_1 + ... + L_t) / t.
+# Each pin below fails if one of the three averages is dropped or mis-scaled.
+# ---------------------------------------------------------------------------
+
+
+def test_online_delta_codes_closed_form_over_t(rng):
+    """Mini-batch t holds one image x_t with a single code a_t at pixel q_t (K = 1).
+    Then C_t = a_t^2 I, B_t = a_t patch_{q_t}(x_t), L_t = a_t^2, and for any
+    previous filter the step lands on P(sum_i a_i patch_i / sum_i a_i^2)."""
+    m, H, W = 5, 11, 12
+    c = m // 2
+    st = oracle.OnlineState(1, m)
+    d = oracle.project_ball(rng.standard_normal((1, m, m)))
+    num = np.zeros((1, m, m))
+    den = 0.0
+    for t in range(1, 5):
+        x = rng.standard_normal((H, W))
+        a = float(rng.uniform(0.5, 2.0)) * (1 if t % 2 else -1)
+        qy, qx = int(rng.integers(c, H - c)), int(rng.integers(c, W - c))
+        z = np.zeros((1, H, W))
+        z[0, qy, qx] = a
+        num += a * x[qy - c : qy + c + 1, qx - c : qx + c + 1][None]
+        den += a * a
+        d = oracle.dict_step_online([x], None, [z], d, st)
+        assert st.Ld_sum == pytest.approx(den, rel=1e-12)
+        np.testing.assert_allclose(d, oracle.project_ball(num / den), rtol=1e-12, atol=1e-14)
+
+
+def test_online_second_step_is_batch_step_on_both_minibatches(rng):
+    """(C^2 d - B^2) / L^2 = -sum_{both batches} Z^T (x - Z d) / (L_1 + L_2): the
+    t = 2 step equals the batch step of eq. (5) over the union of the two
+    mini-batches with step 1 / (L_1 + L_2)."""
+    K, m = 3, 5
+    mk = lambda: [rng.standard_normal((9, 10)), rng.standard_normal((8, 7))]
+    xa, xb = mk(), mk()
+    za = [rng.standard_normal((K,) + x.shape) * (rng.random((K,) + x.shape) < 0.25) for x in xa]
+    zb = [rng.standard_normal((K,) + x.shape) * (rng.random((K,) + x.shape) < 0.25) for x in xb]
+    d0 = oracle.project_ball(rng.standard_normal((K, m, m)))
+    st = oracle.OnlineState(K, m)
+    d1 = oracle.dict_step_online(xa, None, za, d0, st)
+    d2 = oracle.dict_step_online(xb, None, zb, d1, st)
+    La = oracle.lipschitz_filter(za, None, K, m)
+    Lb = oracle.lipschitz_filter(zb, None, K, m)
+    ref, _ = oracle.dict_step_batch(xa + xb, None, za + zb, d1, step=1.0 / (La + Lb))
+    np.testing.assert_allclose(d2, ref, rtol=1e-11, atol=1e-12)
+    assert not np.allclose(d2, d1)
+
+
+def test_online_repeated_minibatch_is_batch_step(rng):
+    """The same mini-batch fed t times: C^t = C_1, B^t = B_1, L^t = L_1, so every
+    online step equals the batch step from the current filters."""
+    K, m = 2, 3
+    xs = [rng.standard_normal((7, 8))]
+    zs = [rng.standard_normal((K, 7, 8)) * (rng.random((K, 7, 8)) < 0.3)]
+    d = oracle.project_ball(rng.standard_normal((K, m, m)))
+    st = oracle.OnlineState(K, m)
+    for t in range(1, 5):
+        ref, _ = oracle.dict_step_batch(xs, None, zs, d)
+        d = oracle.dict_step_online(xs, None, zs, d, st)
+        np.testing.assert_allclose(d, ref, rtol=1e-11, atol=1e-12)
+
+
+def test_online_step_decreases_surrogate_objective(rng):
+    """For t = 2..4 the projected step does not increase the eq. (9) surrogate
+    objective f_t(d) = 1/2 d^T C^t d - d^T B^t (built here from explicit code
+    matrices), since 1 / L^t is a descent step for C^t."""
+    K, m = 3, 3
+    st = oracle.OnlineState(K, m)
+    Csum = np.zeros((K * m * m,) * 2)
+    Bsum = np.zeros(K * m * m)
+    d = oracle.project_ball(rng.standard_normal((K, m, m)))
+    for t in range(1, 5):
+        x = rng.standard_normal((8, 9))
+        z = rng.standard_normal((K, 8, 9)) * (rng.random((K, 8, 9)) < 0.3)
+        Z = oracle.code_matrix(z, m)
+        Csum += Z.T @ Z
+        Bsum += Z.T @ x.ravel()
+        f = lambda v: 0.5 * v.ravel() @ (Csum / t) @ v.ravel() - v.ravel() @ (Bsum / t)
+        d_new = oracle.dict_step_online([x], None, [z], d, st)
+        if t >= 2:
+            assert f(d_new) <= f(d) + 1e-12 * abs(f(d))
+        d = d_new
