@@ -232,7 +232,8 @@ int csc_objective(csc_handle h, const csc_images *im, const float *x, const uint
 /* y = D z for every image (y packed like x). */
 int csc_synthesize(csc_handle h, const csc_images *im, const float *d, int K, int m,
                    const float *z, float *y, int precision);
-/* g = D^T r at every coordinate (g packed like z). */
+/* g = D^T r at every coordinate (g packed like z).  CSC_BF16: BF16 operands on the
+ * matrix cores, FP32 accumulation. */
 int csc_adjoint(csc_handle h, const csc_images *im, const float *d, int K, int m,
                 const float *r, float *g, int precision);
 /* G = sum_i Z_i^T r_i  ([K][m][m]). */
@@ -292,8 +293,11 @@ int csc_profile_read(csc_handle h, int kernel_class, int64_t *launches, double *
  * fixed selection `mask` (u8, packed like z: 1 = selected), step eta > 0 and
  * threshold eta * lambda:
  *     r = W (x - D z_in),   u = z_in + eta D^T r,   z_out = mask * shrink(u, eta * lambda).
- * Dense packed codes; x, W as in csc_code_step; FP32 (BF16 returns CSC_EUNSUPPORTED).
- * z_out may alias z_in.  Asynchronous apart from list sizing, which synchronises. */
+ * Dense packed codes; x, W as in csc_code_step.  precision CSC_FP32, or CSC_BF16: every
+ * product (D z, D^T r and, in the backward pass, the filter correlations) takes BF16
+ * operands on the matrix cores with FP32 accumulation; codes, residuals and gradients
+ * stay FP32.  z_out may alias z_in.  Asynchronous apart from list sizing, which
+ * synchronises. */
 int csc_ista_forward(csc_handle h, const csc_images *im, const float *x, const uint8_t *W,
                      const float *d, int K, int m, const uint8_t *mask, const float *z_in, float *z_out,
                      double eta, double lambda, int precision);

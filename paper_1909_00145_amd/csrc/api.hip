@@ -1350,6 +1350,25 @@ extern "C" int csc_objective(csc_handle h, const csc_images *im, const float *x,
     return CSC_OK;
 }
 
+namespace {
+// The filters as the BF16 operand of the dense adjoint (written once per layer call).
+int adjoint_operand(csc_ctx *h, int K, int m, const float *d, const __bf16 **dA_out) {
+    WS(dA, __bf16, WS_ADA, adj_prep_elems(K, m));
+    HIPCHK(launch_adj_prep(d, K, m, dA, h->stream));
+    *dA_out = dA;
+    return CSC_OK;
+}
+
+// out = D^T r at every coordinate, FP32 or with BF16 operands (dA from adjoint_operand).
+int adjoint_dense(csc_ctx *h, int K, int m, const float *r, const float *d, const __bf16 *dA, float *out) {
+    PROF(CSC_PK_DENSE);
+    if (dA) HIPCHK(launch_adjoint_dense_mfma(h->geo, K, m, r, dA, out, h->stream));
+    else HIPCHK(launch_adjoint_dense(h->geo, K, m, r, d, out, h->stream));
+    return CSC_OK;
+}
+
+}  // namespace
+
 extern "C" int csc_synthesize(csc_handle h, const csc_images *im, const float *d, int K, int m, const float *z,
                               float *y, int precision) {
     if (!h) return CSC_EINVAL;
@@ -1379,11 +1398,9 @@ extern "C" int csc_adjoint(csc_handle h, const csc_images *im, const float *d, i
     if (!d || !r || !g) return fail(h, CSC_EINVAL, "null pointer argument");
     HIPCHK(hipSetDevice(h->device));
     if ((st = geometry(h, im))) return st;
-    {
-        PROF(CSC_PK_DENSE);
-        HIPCHK(launch_adjoint_dense(h->geo, K, m, r, d, g, h->stream));
-    }
-    return CSC_OK;
+    const __bf16 *dA = nullptr;
+    if (precision == CSC_BF16 && (st = adjoint_operand(h, K, m, d, &dA))) return st;
+    return adjoint_dense(h, K, m, r, d, dA, g);
 }
 
 extern "C" int csc_filter_corr(csc_handle h, const csc_images *im, const float *z, int K, int m, const float *r,
@@ -1416,13 +1433,12 @@ int check_layer_args(csc_ctx *h, const csc_images *im, int K, int m, int precisi
     if (st) return st;
     if (!(eta > 0.0) || !std::isfinite(eta)) return fail(h, CSC_EINVAL, "eta must be finite and > 0");
     if (!(lambda >= 0.0) || !std::isfinite(lambda)) return fail(h, CSC_EINVAL, "lambda must be finite and >= 0");
-    if (precision != CSC_FP32) return fail(h, CSC_EUNSUPPORTED, "BF16 unrolled layers not built yet");
     return CSC_OK;
 }
 
 // r = W (x - D z) into R and g = D^T r (dense) into G.
 int layer_residual_gradient(csc_ctx *h, int K, int m, const float *x, const uint8_t *W, const float *d,
-                            const float *z, float **R_out, float **G_out) {
+                            const __bf16 *dA, const float *z, int precision, float **R_out, float **G_out) {
     const Geometry &g = h->geo;
     Lists L;
     int st = build_nonzero_lists(h, K, z, &L);
@@ -1431,23 +1447,21 @@ int layer_residual_gradient(csc_ctx *h, int K, int m, const float *x, const uint
     WS(G, float, WS_DG, (size_t)K * g.n_pix);
     {
         PROF(CSC_PK_SYNTH);
-        HIPCHK(synth(h, K, m, L, d, x, W, R, SYNTH_RESIDUAL));
+        HIPCHK(synth(h, K, m, L, d, x, W, R, SYNTH_RESIDUAL, true, precision));
     }
-    {
-        PROF(CSC_PK_DENSE);
-        HIPCHK(launch_adjoint_dense(g, K, m, R, d, G, h->stream));
-    }
+    if ((st = adjoint_dense(h, K, m, R, d, dA, G))) return st;
     *R_out = R;
     *G_out = G;
     return CSC_OK;
 }
 
 // G_out = sum_i Z(a)_i^T b_i for dense codes a (lists built here).
-int corr_dense(csc_ctx *h, int K, int m, const float *a, const float *b, float *G_out) {
+int corr_dense(csc_ctx *h, int K, int m, const float *a, const float *b, float *G_out, int precision) {
     Lists L;
     unsigned long long nz = 0;
     int st = build_nonzero_lists(h, K, a, &L, &nz);
     if (st) return st;
+    if (precision == CSC_BF16) return filter_corr_bf16(h, K, m, L, b, G_out);
     FmLists F;
     if ((st = build_fm_lists(h, K, L, nz, &F))) return st;
     return filter_corr_lists(h, K, m, F, b, G_out);
@@ -1464,8 +1478,10 @@ extern "C" int csc_ista_forward(csc_handle h, const csc_images *im, const float 
     HIPCHK(hipSetDevice(h->device));
     if ((st = geometry(h, im))) return st;
     const long long n = (long long)K * h->geo.n_pix;
+    const __bf16 *dA = nullptr;
+    if (precision == CSC_BF16 && (st = adjoint_operand(h, K, m, d, &dA))) return st;
     float *R = nullptr, *G = nullptr;
-    if ((st = layer_residual_gradient(h, K, m, x, W, d, z_in, &R, &G))) return st;
+    if ((st = layer_residual_gradient(h, K, m, x, W, d, dA, z_in, precision, &R, &G))) return st;
     PROF(CSC_PK_UPDATE);
     HIPCHK(launch_ista_update(n, z_in, G, mask, (float)eta, (float)(eta * lambda), z_out, h->stream));
     return CSC_OK;
@@ -1486,8 +1502,10 @@ extern "C" int csc_ista_backward(csc_handle h, const csc_images *im, const float
     const long long n = (long long)K * g.n_pix;
     const float feta = (float)eta;
     // recompute r and u from the layer input, then g_u = g_out on the active selected set
+    const __bf16 *dA = nullptr;
+    if (precision == CSC_BF16 && (st = adjoint_operand(h, K, m, d, &dA))) return st;
     float *R = nullptr, *G = nullptr;
-    if ((st = layer_residual_gradient(h, K, m, x, W, d, z_in, &R, &G))) return st;
+    if ((st = layer_residual_gradient(h, K, m, x, W, d, dA, z_in, precision, &R, &G))) return st;
     WS(GU, float, WS_GU, (size_t)n);
     {
         PROF(CSC_PK_UPDATE);
@@ -1499,23 +1517,20 @@ extern "C" int csc_ista_backward(csc_handle h, const csc_images *im, const float
         Lists Lu;
         if ((st = build_nonzero_lists(h, K, GU, &Lu))) return st;
         PROF(CSC_PK_SYNTH);
-        HIPCHK(synth(h, K, m, Lu, d, nullptr, W, T, SYNTH_WEIGHTED));
+        HIPCHK(synth(h, K, m, Lu, d, nullptr, W, T, SYNTH_WEIGHTED, true, precision));
     }
     // g_d = eta (Z(g_u)^T r - Z(z)^T t)
     WS(G1, float, WS_G, K * M);
     WS(G2, float, WS_W, K * M);
-    if ((st = corr_dense(h, K, m, GU, R, G1))) return st;
-    if ((st = corr_dense(h, K, m, z_in, T, G2))) return st;
+    if ((st = corr_dense(h, K, m, GU, R, G1, precision))) return st;
+    if ((st = corr_dense(h, K, m, z_in, T, G2, precision))) return st;
     {
         PROF(CSC_PK_UPDATE);
         HIPCHK(launch_axpby(K * M, feta, G1, -feta, G2, g_d, h->stream));
         if (g_x) HIPCHK(launch_axpby(g.n_pix, feta, T, 0.f, nullptr, g_x, h->stream));
     }
     // g_z = g_u - eta D^T t  (G is free again)
-    {
-        PROF(CSC_PK_DENSE);
-        HIPCHK(launch_adjoint_dense(g, K, m, T, d, G, h->stream));
-    }
+    if ((st = adjoint_dense(h, K, m, T, d, dA, G))) return st;
     PROF(CSC_PK_UPDATE);
     HIPCHK(launch_axpby(n, 1.f, GU, -feta, G, g_z, h->stream));
     return CSC_OK;

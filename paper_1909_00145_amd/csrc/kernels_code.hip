@@ -907,6 +907,74 @@ __global__ __launch_bounds__(TPB) void k_adjoint_dense(const ImgInfo *imgs, cons
     }
 }
 
+// Dense adjoint g = D^T r at every coordinate with BF16 operands on the matrix
+// cores: the same implicit-im2col GEMM per 16 x 16 tile as the selected-set
+// kernel (M = filters, N = the tile's pixels, K-dim = the m^2 taps padded to 32s,
+// FP32 accumulation), with the accumulators stored straight to out[k][H][W]:
+// lane l holds filters 4 (l / 16) + i of pixel column l % 16, so 16 lanes write
+// 64 contiguous bytes of one filter plane.  Filters come from k_adj_prep_a.
+template <int MM>
+__global__ __launch_bounds__(TPB) void k_adjoint_dense_mfma(const ImgInfo *imgs, const TileInfo *tiles, int n_tiles,
+                                                            int K, const float *__restrict__ r,
+                                                            const __bf16 *__restrict__ dA, float *__restrict__ out) {
+    constexpr int C = MM / 2, RW = TS + 2 * C, M = MM * MM, NKS = (M + 31) / 32, MP = 32 * NKS;
+    __shared__ __bf16 rb[RW * RW];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int fcol = lane & 15, fk = 8 * (lane >> 4);
+    const bf16x8 *dA8 = reinterpret_cast<const bf16x8 *>(dA) + (long long)fcol * (MP / 8) + (lane >> 4);
+    long long first, step, end;
+    xcd_work(n_tiles, first, step, end);
+    for (long long tile = first; tile < end; tile += step) {
+        const TileInfo t = tiles[tile];
+        const ImgInfo im = imgs[t.img];
+        const int oy = t.ty * TS - C, ox = t.tx * TS - C;
+        __syncthreads();  // the previous tile's fragments have been read
+        for (int i = threadIdx.x; i < RW * RW; i += TPB) {
+            const int gy = oy + i / RW, gx = ox + i % RW;
+            float v = 0.f;
+            if (gy >= 0 && gy < im.H && gx >= 0 && gx < im.W) v = r[im.pix_off + (long long)gy * im.W + gx];
+            rb[i] = (__bf16)v;
+        }
+        __syncthreads();
+        bf16x8 bfr[4][NKS];
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct) {
+            const int py = wave * 4 + ct;
+#pragma unroll
+            for (int ks = 0; ks < NKS; ++ks) {
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const int tp = ks * 32 + fk + i;
+                    bfr[ct][ks][i] = tp < M ? rb[(py + tp / MM) * RW + fcol + tp % MM] : (__bf16)0.f;
+                }
+            }
+        }
+        const long long HW = (long long)im.H * im.W;
+        const int gx = t.tx * TS + fcol;
+        float *ob = out + (long long)K * im.pix_off;
+        for (int k0 = 0; k0 < K; k0 += 16) {
+            bf16x8 afr[NKS];
+#pragma unroll
+            for (int ks = 0; ks < NKS; ++ks) afr[ks] = dA8[(long long)k0 * (MP / 8) + ks * 4];
+#pragma unroll
+            for (int ct = 0; ct < 4; ++ct) {
+                f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int ks = 0; ks < NKS; ++ks)
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr[ks], bfr[ct][ks], acc, 0, 0, 0);
+                const int gy = t.ty * TS + wave * 4 + ct;
+                if (gy < im.H && gx < im.W) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int k = k0 + (lane >> 4) * 4 + i;
+                        if (k < K) ob[(long long)k * HW + (long long)gy * im.W + gx] = acc[i];
+                    }
+                }
+            }
+        }
+    }
+}
+
 // Filters per LDS chunk: at most 56 KiB of staged filters, a multiple of 4.
 template <int MM>
 int filter_chunk() {
@@ -1089,6 +1157,15 @@ hipError_t adj_prep_impl(const float *d, int K, __bf16 *dA, hipStream_t s) {
 }
 
 template <int MM>
+hipError_t adjoint_dense_mfma_impl(const Geometry &g, int K, const float *r, const __bf16 *dA, float *out,
+                                   hipStream_t s) {
+    const int grid = persistent_grid(reinterpret_cast<const void *>(&k_adjoint_dense_mfma<MM>), TPB, 0, g.n_tiles);
+    hipLaunchKernelGGL(k_adjoint_dense_mfma<MM>, dim3(grid), dim3(TPB), 0, s, g.d_img, g.d_tiles, g.n_tiles, K, r,
+                       dA, out);
+    return hipGetLastError();
+}
+
+template <int MM>
 hipError_t adjoint_dense_impl(const Geometry &g, int K, const float *r, const float *d, float *out,
                               hipStream_t s) {
     constexpr int M = MM * MM, M4 = (M + 3) / 4 * 4;
@@ -1133,6 +1210,11 @@ hipError_t launch_adjoint_shrink_mfma(const Geometry &g, int K, int m, const uns
 hipError_t launch_adjoint_dense(const Geometry &g, int K, int m, const float *r, const float *d, float *out,
                                 hipStream_t s) {
     SCSC_DISPATCH_M(m, adjoint_dense_impl, g, K, r, d, out, s);
+}
+
+hipError_t launch_adjoint_dense_mfma(const Geometry &g, int K, int m, const float *r, const __bf16 *dA, float *out,
+                                     hipStream_t s) {
+    SCSC_DISPATCH_M(m, adjoint_dense_mfma_impl, g, K, r, dA, out, s);
 }
 
 int persistent_grid(const void *kernel, int block_threads, size_t dyn_lds, long long items) {

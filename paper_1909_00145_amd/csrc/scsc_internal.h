@@ -340,6 +340,10 @@ hipError_t launch_reduce_partials_f64_add(const double *partial, int nblocks, in
 // Dense adjoint D^T r (every coordinate).
 hipError_t launch_adjoint_dense(const Geometry &g, int K, int m, const float *r, const float *d, float *out,
                                 hipStream_t s);
+// The same with BF16 operands on the matrix cores (FP32 accumulation); the filters
+// enter as dA, written by launch_adj_prep (adj_prep_elems(K, m) elements).
+hipError_t launch_adjoint_dense_mfma(const Geometry &g, int K, int m, const float *r, const __bf16 *dA, float *out,
+                                     hipStream_t s);
 
 // Filter updates.
 hipError_t launch_fill(float *v, int n, float val, hipStream_t s);

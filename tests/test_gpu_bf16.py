@@ -191,3 +191,20 @@ def test_synthesis_bf16_variants_bit_identical(ctx):
         ctx.set_autotune(True)
     np.testing.assert_array_equal(outs[1], outs[0])
     np.testing.assert_array_equal(codes[1], codes[0])
+
+
+@pytest.mark.parametrize("hw,K,m", [([(40, 36)], 16, 11), ([(23, 50), (31, 17)], 33, 7), ([(32, 32)] * 2, 256, 11),
+                                    ([(19, 21)], 5, 3)])
+def test_dense_adjoint_matches_bf16_rounded_operands(ctx, hw, K, m):
+    """csc_adjoint with BF16 operands: every coordinate equals D^T r of the BF16-rounded d and r
+    (FP32 accumulation of exact products)."""
+    from paper_1909_00145_amd.ops import Images
+
+    say("bf16 dense adjoint", hw, K, m)
+    xs, d, _ = make_problem(8, hw, K, m)
+    im = Images(hw)
+    g = ctx.adjoint(im, to_dev(d), packed(im, xs), precision="bf16").cpu().numpy()
+    ref = im.pack([oracle.adjoint(bf16_round(d), bf16_round(x)) for x in xs])
+    err = rel_err(g, ref)
+    say("  rel err", err)
+    assert err < 1e-5

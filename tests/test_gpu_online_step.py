@@ -103,7 +103,7 @@ def test_online_step_against_oracle(ctx):
     state = oracle.OnlineState(K, m)
     dr = oracle.dict_step_online(xs, None, zr, d, state)
     say("  d rel err", rel_err(dg.cpu().numpy(), dr), "Ld_sum", sur.Ld_sum, state.Ld_sum)
-    assert rel_err(dg.cpu().numpy(), dr) < 1e-4
+    assert rel_err(dg.cpu().numpy(), dr) < 1e-5
     assert rel_err(sur.dense_C(), state.C) < 1e-5
     assert abs(sur.Ld_sum - state.Ld_sum) <= 1e-5 * state.Ld_sum
 
@@ -138,3 +138,68 @@ def test_online_step_rejects_bad_arguments(ctx):
     assert torch.equal(dg, d0) and torch.equal(z, z0)
     assert sur.t == 0 and sur.Ld_sum == 0.0
     assert not bool(sur.C.any()) and not bool(sur.B.any())
+
+
+# ---------------------------------------------------------------------------
+# The joined call at the full online mini-batch: 20 images 100x100, K = 100
+# filters 11x11, p = 0.1, lambda = 1, 20 iterations, two consecutive
+# mini-batches (t = 1, 2) in the launch configuration the bench times.
+# The oracle's chain runs in FP64 from the same initial filters: its codes
+# from zero at each mini-batch, and its filter steps matrix-free (the dense
+# surrogate would hold 1.5e8 doubles): the t = 1 step is the batch step of
+# eq. (5) with step 1 / L_1, and the t = 2 step is the batch step over both
+# mini-batches with step 1 / (L_1 + L_2) -- both identities are pinned on the
+# oracle's own online step.
+# ---------------------------------------------------------------------------
+
+FULL = dict(N=20, H=100, W=100, K=100, m=11, lam=1.0, p=0.1, T=20, cfg=3, seed=3)
+
+
+@pytest.fixture(scope="module")
+def full_chain():
+    import scsc_inputs as si
+
+    N, H, W, K, m = (FULL[k] for k in ("N", "H", "W", "K", "m"))
+    xs = [[f32(a) for a in si.stream_batch(FULL["cfg"], t, N, H, W)] for t in (1, 2)]
+    d0 = f32(oracle.project_ball(si.filters(FULL["cfg"], K, m)))
+    say("full online chain: oracle codes and filter steps (FP64)")
+    ds, zs, Ls = [d0], [], []
+    for t in (1, 2):
+        d = ds[-1]
+        Lz = oracle.lipschitz_code(d, max(H, W))
+        zt = [oracle.code_step(x, d, np.zeros((K, H, W)), FULL["lam"], FULL["p"], FULL["seed"], t, FULL["T"],
+                               step=1.0 / Lz, image_index=n)[0] for n, x in enumerate(xs[t - 1])]
+        zs.append(zt)
+        Ls.append(oracle.lipschitz_filter(zt, None, K, m))
+        allx = sum(xs[:t], [])
+        allz = sum(zs, [])
+        dn, _ = oracle.dict_step_batch(allx, None, allz, d, step=1.0 / sum(Ls))
+        ds.append(dn)
+        say("  t", t, "L_d", Ls[-1], "nnz", sum(int(np.count_nonzero(z)) for z in zt))
+    return xs, ds, zs, Ls
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-5), ("bf16", 2e-2)])
+def test_online_step_full_size_against_oracle(ctx, full_chain, precision, tol):
+    from paper_1909_00145_amd.ops import Images, Surrogate
+
+    xs, ds, zs, Ls = full_chain
+    N, H, W, K, m = (FULL[k] for k in ("N", "H", "W", "K", "m"))
+    say("joined online step at full size against the oracle,", precision)
+    ctx.set_graph(False)
+    im = Images([(H, W)] * N)
+    dg = to_dev(ds[0])
+    sur = Surrogate(K, m)
+    z = torch.zeros(K * im.n_pix, dtype=torch.float32, device="cuda")
+    for t in (1, 2):
+        st, Ld = ctx.online_step(im, packed(im, xs[t - 1]), dg, sur, FULL["lam"], FULL["p"], FULL["seed"], t,
+                                 FULL["T"], z=z, precision=precision, stats=True)
+        got = im.unpack(z.cpu().numpy(), K)
+        errz = rel_err(np.concatenate([g.ravel() for g in got]), np.concatenate([r.ravel() for r in zs[t - 1]]))
+        errd = rel_err(dg.cpu().numpy(), ds[t])
+        say("  t", t, "codes rel err", errz, "filters rel err", errd, "L_d", Ld, Ls[t - 1])
+        assert errz < tol
+        assert errd < tol
+        if precision == "fp32":
+            assert abs(Ld - Ls[t - 1]) <= 1e-5 * Ls[t - 1]
+    assert sur.t == 2

@@ -57,3 +57,44 @@ def test_gradient_with_all_codes_inactive_is_loss_only(rng):
     np.testing.assert_array_equal(gz, 0.0)
     np.testing.assert_array_equal(gd, 0.0)
     np.testing.assert_array_equal(gx, x)
+
+
+def test_gradients_finite_differences_differentiation_subset():
+    """The differentiation workload's gradient subset: 4 images 32x32 (1/f^2 fields),
+    K = 256 filters 11x11, p = 0.2 (the oracle's Bernoulli sample), lambda = 0.5,
+    10 layers from zero codes.  Central differences with h = 1e-4 along 6 seeded
+    unit directions in d and in x agree with the analytic gradient to 1e-4 of its
+    norm (the soft-threshold's kinks bound how close a finite difference can get)."""
+    import scsc_inputs as si
+
+    K, m, H, W, N, p, lam, T = 256, 11, 32, 32, 4, 0.2, 0.5, 10
+    xs = [si.field(5, n, H, W) for n in range(N)]
+    d = si.filters(5, K, m)
+    S = [oracle.bernoulli_mask(K, H, W, p, 5, 1, n) for n in range(N)]
+    eta = 1.0 / oracle.lipschitz_code(d, H)
+    z0 = np.zeros((K, H, W))
+
+    def L(dd, xx):
+        return sum(unrolled.reconstruction_loss(xx[n], dd, unrolled.unrolled_forward(xx[n], dd, z0, S[n], eta, lam,
+                                                                                      T)[-1]) for n in range(N))
+
+    res = [unrolled.loss_and_grads(xs[n], d, z0, S[n], eta, lam, T) for n in range(N)]
+    gd = sum(r[2] for r in res)
+    gx = [r[3] for r in res]
+    assert abs(sum(r[0] for r in res) - L(d, xs)) <= 1e-12 * L(d, xs)
+    ngd = np.linalg.norm(gd)
+    ngx = np.sqrt(sum(float((g * g).sum()) for g in gx))
+    rng = np.random.default_rng(0)
+    h = 1e-4
+    for _ in range(6):
+        ed = rng.standard_normal(d.shape)
+        ed /= np.linalg.norm(ed)
+        ex = [rng.standard_normal((H, W)) for _ in range(N)]
+        nx = np.sqrt(sum(float((e * e).sum()) for e in ex))
+        ex = [e / nx for e in ex]
+        fd_d = (L(d + h * ed, xs) - L(d - h * ed, xs)) / (2 * h)
+        fd_x = (L(d, [a + h * e for a, e in zip(xs, ex)]) - L(d, [a - h * e for a, e in zip(xs, ex)])) / (2 * h)
+        an_d = float(np.sum(gd * ed))
+        an_x = sum(float(np.sum(g * e)) for g, e in zip(gx, ex))
+        assert abs(fd_d - an_d) <= 1e-4 * ngd, (fd_d, an_d, ngd)
+        assert abs(fd_x - an_x) <= 1e-4 * ngx, (fd_x, an_x, ngx)
