@@ -227,6 +227,28 @@ int csc_objective(csc_handle h, const csc_images *im, const float *x, const uint
                   const float *d, int K, int m, const float *z, double lambda,
                   double *f_out, double *terms_out);
 
+/* Bytes of the library's fixed device scratch array (one copy per GPU, held until the
+ * process ends), used by csc_objective_noalloc. */
+#define CSC_NOALLOC_SCRATCH_BYTES (8u << 20)
+
+/* csc_objective for callers that cannot allocate device memory (code inside HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc).  Same arguments,
+ * results and synchronisation as csc_objective, computed by the same kernels, but the
+ * call allocates nothing: the batch records, the per-tile FP64 partial sums and the two
+ * reduced terms live in the fixed scratch array of CSC_NOALLOC_SCRATCH_BYTES instead of
+ * the handle's workspaces, and the handle's cached batch geometry is left as it was.
+ * Limit: 256*ceil(40n/256) + 256*ceil(16T/256) + 256*ceil(16T/256) + 256 bytes must not
+ * exceed CSC_NOALLOC_SCRATCH_BYTES, where n is the number of images and T the number of
+ * 16x16 tiles, sum_i ceil(H_i/16) ceil(W_i/16) (about 262,000 tiles, 6.7e7 pixels);
+ * a larger batch returns CSC_EINVAL before any work, with nothing written.  Every call on
+ * one GPU shares that GPU's scratch array: calls that overlap on one GPU (from other
+ * handles, streams or threads) race and must be serialised by the caller.  Returns
+ * CSC_EHIP if the scratch array's address could not be obtained when the handle was
+ * created. */
+int csc_objective_noalloc(csc_handle h, const csc_images *im, const float *x, const uint8_t *W,
+                          const float *d, int K, int m, const float *z, double lambda,
+                          double *f_out, double *terms_out);
+
 /* ---- operators and helpers --------------------------------------------------- */
 
 /* y = D z for every image (y packed like x). */

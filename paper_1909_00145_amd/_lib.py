@@ -20,6 +20,7 @@ CSC_EHIP = -3
 CSC_EUNSUPPORTED = -4
 CSC_FP32 = 0
 CSC_BF16 = 1
+CSC_NOALLOC_SCRATCH_BYTES = 8 << 20
 
 STATUS_NAMES = {
     CSC_OK: "CSC_OK",
@@ -68,6 +69,7 @@ SIGNATURES = {
     "csc_online_step": (_i, [_vp, _pimg, _vp, _vp, _vp, _i, _i, _vp, _d, _d, _u64, _u32, _i, _d, _i,
                              C.POINTER(csc_surrogate), _i, _i, C.POINTER(csc_code_stats), C.POINTER(_d)]),
     "csc_objective": (_i, [_vp, _pimg, _vp, _vp, _vp, _i, _i, _vp, _d, C.POINTER(_d), C.POINTER(_d)]),
+    "csc_objective_noalloc": (_i, [_vp, _pimg, _vp, _vp, _vp, _i, _i, _vp, _d, C.POINTER(_d), C.POINTER(_d)]),
     "csc_synthesize": (_i, [_vp, _pimg, _vp, _i, _i, _vp, _vp, _i]),
     "csc_adjoint": (_i, [_vp, _pimg, _vp, _i, _i, _vp, _vp, _i]),
     "csc_filter_corr": (_i, [_vp, _pimg, _vp, _i, _i, _vp, _vp, _i]),

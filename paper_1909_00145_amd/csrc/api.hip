@@ -7,6 +7,7 @@
 #include <cstring>
 #include <functional>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -120,6 +121,9 @@ struct csc_ctx {
     bool autotune = true;
     int force_variant = -1;
     std::map<std::array<int, 5>, int> tuned;
+    // this device's copy of the fixed scratch array (csc_objective_noalloc), or null if
+    // its address could not be obtained when the handle was created
+    unsigned char *scratch = nullptr;
 };
 
 namespace {
@@ -414,41 +418,52 @@ int check_precision(csc_ctx *h, int precision) {
     return CSC_OK;
 }
 
+// Image records (packed offsets, tile counts, sampler index, first global row) and
+// the TS x TS tile records of a batch, in packing order.
+void batch_records(const csc_images *im, std::vector<ImgInfo> &imgs, std::vector<TileInfo> &tiles) {
+    imgs.assign(im->n, ImgInfo{});
+    tiles.clear();
+    long long pix = 0;
+    int ntiles = 0, rows = 0;
+    for (int i = 0; i < im->n; ++i) {
+        ImgInfo &ii = imgs[i];
+        ii.H = im->hw[2 * i];
+        ii.W = im->hw[2 * i + 1];
+        ii.pix_off = pix;
+        ii.tiles_y = (ii.H + TS - 1) / TS;
+        ii.tiles_x = (ii.W + TS - 1) / TS;
+        ii.tile_off = ntiles;
+        ii.index = im->index_base + i;
+        ii.row_off = rows;
+        rows += ii.H;
+        for (int ty = 0; ty < ii.tiles_y; ++ty)
+            for (int tx = 0; tx < ii.tiles_x; ++tx) tiles.push_back(TileInfo{i, ty, tx, 0});
+        ntiles += ii.tiles_y * ii.tiles_x;
+        pix += (long long)ii.H * ii.W;
+    }
+}
+
 // Upload (or reuse) the geometry of a batch.
 int geometry(csc_ctx *h, const csc_images *im) {
     std::vector<int32_t> key(im->hw, im->hw + 2 * im->n);
     key.push_back(im->index_base);
     if (h->geo_valid && key == h->geo_key) return CSC_OK;
     Geometry &g = h->geo;
-    g.h_img.assign(im->n, ImgInfo{});
-    g.h_tiles.clear();
+    batch_records(im, g.h_img, g.h_tiles);
     g.h_tiles_big.clear();
-    long long pix = 0;
-    int tiles = 0, max_side = 0, rows = 0;
+    int max_side = 0, rows = 0;
     std::vector<int> row_img;
     for (int i = 0; i < im->n; ++i) {
-        ImgInfo &ii = g.h_img[i];
-        ii.H = im->hw[2 * i];
-        ii.W = im->hw[2 * i + 1];
-        ii.pix_off = pix;
-        ii.tiles_y = (ii.H + TS - 1) / TS;
-        ii.tiles_x = (ii.W + TS - 1) / TS;
-        ii.tile_off = tiles;
-        ii.index = im->index_base + i;
-        ii.row_off = rows;
+        const ImgInfo &ii = g.h_img[i];
         rows += ii.H;
         row_img.insert(row_img.end(), ii.H, i);
-        for (int ty = 0; ty < ii.tiles_y; ++ty)
-            for (int tx = 0; tx < ii.tiles_x; ++tx) g.h_tiles.push_back(TileInfo{i, ty, tx, 0});
         for (int ty = 0; ty < (ii.H + TS_BIG - 1) / TS_BIG; ++ty)
             for (int tx = 0; tx < (ii.W + TS_BIG - 1) / TS_BIG; ++tx) g.h_tiles_big.push_back(TileInfo{i, ty, tx, 0});
-        tiles += ii.tiles_y * ii.tiles_x;
-        pix += (long long)ii.H * ii.W;
         max_side = std::max(max_side, std::max(ii.H, ii.W));
     }
     g.n_img = im->n;
-    g.n_tiles = tiles;
-    g.n_pix = pix;
+    g.n_tiles = (int)g.h_tiles.size();
+    g.n_pix = im->n ? g.h_img.back().pix_off + (long long)g.h_img.back().H * g.h_img.back().W : 0;
     g.max_side = max_side;
     g.n_rows = rows;
     g.n_tiles_big = (int)g.h_tiles_big.size();
@@ -654,6 +669,41 @@ int power_iteration_lag(csc_ctx *h, int K, int m, const double *Rl, int n_power)
 }  // namespace
 
 // ===========================================================================
+// Fixed device scratch of the allocation-free entry point.  Each GPU holds its
+// own copy of the array until the process ends.  Host code never passes the
+// array's name to a kernel or copy: it uses the per-device address taken once
+// with that device current.
+// ===========================================================================
+
+static __device__ __align__(256) unsigned char scratch[CSC_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::map<int, unsigned char *> g_scratch_addr;  // device -> its copy of `scratch`
+
+// With `device` current: the device address of that device's copy of `scratch`.
+int scratch_address(int device, unsigned char **out) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    auto it = g_scratch_addr.find(device);
+    if (it == g_scratch_addr.end()) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            hipGetLastError();
+            return CSC_EHIP;
+        }
+        it = g_scratch_addr.emplace(device, static_cast<unsigned char *>(p)).first;
+    }
+    *out = it->second;
+    return CSC_OK;
+}
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+}  // namespace
+
+// ===========================================================================
 // Entry points
 // ===========================================================================
 
@@ -676,6 +726,7 @@ extern "C" int csc_create(csc_handle *out, int device, void *stream) {
         delete h;
         return CSC_ENOMEM;
     }
+    if (scratch_address(device, &h->scratch) != CSC_OK) h->scratch = nullptr;  // reported by csc_objective_noalloc
     *out = h;
     return CSC_OK;
 }
@@ -1342,6 +1393,51 @@ extern "C" int csc_objective(csc_handle h, const csc_images *im, const float *x,
     }
     if ((st = read_scalars(h, sc, SC_COUNT))) return st;
     const double data = h->h_pinned[SC_OBJ], l1 = h->h_pinned[SC_OBJ + 1];
+    *f_out = data + lambda * l1;
+    if (terms_out) {
+        terms_out[0] = data;
+        terms_out[1] = l1;
+    }
+    return CSC_OK;
+}
+
+extern "C" int csc_objective_noalloc(csc_handle h, const csc_images *im, const float *x, const uint8_t *W,
+                                     const float *d, int K, int m, const float *z, double lambda, double *f_out,
+                                     double *terms_out) {
+    static_assert(sizeof(ImgInfo) == 40 && sizeof(TileInfo) == 16, "record sizes stated in scsc.h");
+    if (!h) return CSC_EINVAL;
+    int st = check_images(h, im);
+    if (!st) st = check_filters(h, K, m);
+    if (st) return st;
+    if (!x || !d || !z || !f_out) return fail(h, CSC_EINVAL, "null pointer argument");
+    if (!(lambda >= 0.0) || !std::isfinite(lambda)) return fail(h, CSC_EINVAL, "lambda must be finite and >= 0");
+    std::vector<ImgInfo> imgs;
+    std::vector<TileInfo> tiles;
+    batch_records(im, imgs, tiles);
+    const size_t T = tiles.size();
+    const size_t b_img = align256(sizeof(ImgInfo) * imgs.size()), b_tiles = align256(sizeof(TileInfo) * T),
+                 b_part = align256(2 * sizeof(double) * T);
+    const size_t need = b_img + b_tiles + b_part + 256;
+    if (need > CSC_NOALLOC_SCRATCH_BYTES)
+        return fail(h, CSC_EINVAL,
+                    "batch too large for the allocation-free objective: it needs " + std::to_string(need) +
+                        " bytes of scratch, the limit is " + std::to_string(CSC_NOALLOC_SCRATCH_BYTES));
+    if (!h->scratch) return fail(h, CSC_EHIP, "the address of the device scratch array was not available");
+    HIPCHK(hipSetDevice(h->device));
+    unsigned char *base = h->scratch;
+    Geometry g;
+    g.n_img = im->n;
+    g.n_tiles = (int)T;
+    g.d_img = reinterpret_cast<ImgInfo *>(base);
+    g.d_tiles = reinterpret_cast<TileInfo *>(base + b_img);
+    double *part = reinterpret_cast<double *>(base + b_img + b_tiles);
+    double *terms = reinterpret_cast<double *>(base + b_img + b_tiles + b_part);
+    HIPCHK(hipMemcpyAsync(g.d_img, imgs.data(), sizeof(ImgInfo) * imgs.size(), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipMemcpyAsync(g.d_tiles, tiles.data(), sizeof(TileInfo) * T, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(launch_objective(g, K, m, x, W, d, z, part, terms, h->stream));  // no timing events: they are created lazily
+    // the host records stay alive until the stream has drained
+    if ((st = read_scalars(h, terms, 2))) return st;
+    const double data = h->h_pinned[0], l1 = h->h_pinned[1];
     *f_out = data + lambda * l1;
     if (terms_out) {
         terms_out[0] = data;

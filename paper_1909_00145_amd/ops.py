@@ -272,12 +272,15 @@ class Context:
         cs = CodeStats(st.sampled, st.nnz, st.L_z, st.step, st.nnz_iter_sum) if stats else None
         return cs, ld.value
 
-    def objective(self, im: Images, x, d, z, lam, W=None):
+    def objective(self, im: Images, x, d, z, lam, W=None, noalloc=False):
+        """Objective of eq. (1); ``noalloc`` calls the entry point that allocates no
+        device memory (its scratch is a fixed array in the library)."""
         K, m = int(d.shape[0]), int(d.shape[-1])
         self._sync_stream()
         f = C.c_double()
         terms = (C.c_double * 2)()
-        rc = self.lib.csc_objective(
+        fn = self.lib.csc_objective_noalloc if noalloc else self.lib.csc_objective
+        rc = fn(
             self.h, im.cref(), _ptr(x, torch.float32, "x", im.n_pix), _ptr(W, torch.uint8, "W", im.n_pix),
             _ptr(d, torch.float32, "d", K * m * m), K, m, _ptr(z, torch.float32, "z", K * im.n_pix), float(lam),
             C.byref(f), terms)
