@@ -14,11 +14,23 @@ outer iteration instead.
 
 Metric: selected code-coordinate updates per second = sum over the timed
 steps of (iterations x |S|) / wall time, with the inputs resident in HBM.
-Prints one JSON line.  Its ``hold_vs_project`` object compares, on the batch
-workload, the objective against training time with the unselected codes zeroed
-(eq. 4) and held (the randomization paragraph of Sec. 3.1); its ``inpainting``
-object reports the reconstruction PSNR from half of the pixels (Sec. 4) with
-filters learned online.
+Prints one JSON line.  Beside the headline it carries:
+* ``fp32_plain``: the same steps with FP32 operands (the metric's comparison);
+* ``time_to_objective``: online learning over 100 mini-batches in both
+  precisions, with the training time until a held-out objective reaches FP32's
+  final one;
+* ``ragged``: code steps of the 256-image ragged batch (sides in [64, 512]) in
+  both precisions, with per-kernel rooflines;
+* ``unrolled``: forward and backward through 10 unrolled layers on 32 images
+  128 x 128 with K = 256, both precisions, with the dense adjoint's roofline;
+* ``hold_vs_project``: on the batch workload, the objective against training
+  time with the unselected codes zeroed (eq. 4) and held (the randomization
+  paragraph of Sec. 3.1);
+* ``inpainting``: the reconstruction PSNR from half of the pixels (Sec. 4) with
+  filters learned online;
+* ``solver_compare``: ISTA against the paper's ADMM on one mini-batch;
+* ``paper_reference``: the paper's own CPU timings, with their hardware;
+* ``cpu_baseline``: the FP64 oracle's code step on the host cores.
 """
 
 from __future__ import annotations
@@ -55,6 +67,22 @@ TRAFFIC = {
     ("corr", "fp32"): ("kernels_dict.hip", "0bf8d154ab50cc41", 27.01e6, 4.07e6),
     ("sur_expand", "fp32"): ("kernels_sur.hip", "d1aa18db8753e5f7", 732.41e6, 603.94e6),
     ("power", "fp32"): ("kernels_sur.hip", "d1aa18db8753e5f7", 18.21e6, 0.69e6),
+}
+
+
+# The paper's own timings (end-to-end CPU wall times on a Core i7 PC with Matlab built-in
+# functions, ADMM code solver; no GPU figures, no precision stated).  Context, not the target.
+PAPER_REFERENCE = {
+    "hardware": "Core i7 PC, Matlab built-in functions (the mini-batch study single-core)",
+    "sbcsc_fruit": "10 images 100x100, K=100 filters 11x11, p=0.1: 170 s for 14 outer iterations of 10 ADMM "
+                   "iterations each (Heide et al. 2015: 350 s); per outer iteration about 6x faster than the "
+                   "non-subsampled spatial solver and about 2x faster than Fourier-domain ADMM",
+    "socsc_fruit": "the 10 training images, one per iteration: 70 s (Liu et al. 2018: 440 s)",
+    "minibatch": "1000 patches 100x100, K=400: mini-batches of 20 reach a comparable objective about 10x sooner "
+                 "than single images",
+    "derived_updates_per_s": 8.2e5,
+    "derived_note": "not printed in the paper: 1e6 sampled coordinates per outer iteration x 10 ADMM iterations "
+                    "x 14 outer iterations in 170 s, whole pipeline",
 }
 
 
@@ -105,9 +133,20 @@ def parse():
     ap.add_argument("--graph", action="store_true",
                     help="replay the code step's iterations and the power iteration from HIP graphs (the default "
                          "for the batch and ragged workloads)")
-    ap.add_argument("--tto", action="store_true",
-                    help="also measure time-to-objective of online learning, FP32 against BF16 (adds ~1 min)")
+    ap.add_argument("--no-tto", action="store_true",
+                    help="skip the time-to-objective comparison of online learning, FP32 against BF16 "
+                         "(100 mini-batches each; a few seconds)")
     ap.add_argument("--tto-batches", type=int, default=100, help="mini-batches of the time-to-objective run")
+    ap.add_argument("--tto-study", action="store_true",
+                    help="also run the study of the held-out objective during online learning (p = 0.1 and 1 on "
+                         "streams with 2 px, 8 px and no local contrast normalisation; about a minute)")
+    ap.add_argument("--no-ragged", action="store_true",
+                    help="skip the ragged-batch leg (256 images with sides in [64, 512], one code step per timed "
+                         "step in BF16 and FP32 with per-kernel rooflines; about 20 s)")
+    ap.add_argument("--ragged-steps", type=int, default=2, help="timed code steps of the ragged leg per precision")
+    ap.add_argument("--no-unrolled", action="store_true",
+                    help="skip the differentiation leg (10 unrolled layers on 32 images 128x128, K=256, forward "
+                         "and backward in BF16 and FP32; a few seconds)")
     ap.add_argument("--no-hold-compare", action="store_true",
                     help="skip the batch-workload comparison of the objective against training time with the "
                          "unselected codes held (HOLD) and zeroed (PROJECT); about a second on one GPU")
@@ -132,52 +171,81 @@ def parse():
 
 
 def cpu_baseline(w, budget_s, sizes):
-    """Time the FP64 oracle's code step on a bounded sample of the same workload.
+    """Time the FP64 oracle's code step on a bounded sample of the same workload,
+    once with the BLAS pool at its default size and once with one thread.
 
     sizes: (H, W) of the images of one step, in order; image n of the sample is
-    image n of the step."""
+    image n of the step.  Each pass codes images until it has run for budget_s / 2
+    or the step's images are done.  The oracle's filter step is not timed: its
+    dense surrogate and code matrices (about 1 GB per image at this size) take
+    minutes per mini-batch."""
+    import platform
+
     import oracle
     import scsc_inputs as si
 
     try:
-        from threadpoolctl import threadpool_info
-
-        threads = max([int(i.get("num_threads", 1)) for i in threadpool_info()] or [1])
+        from threadpoolctl import threadpool_info, threadpool_limits
     except Exception:  # pragma: no cover
-        threads = 1
+        threadpool_info = threadpool_limits = None
+    blas = max([int(i.get("num_threads", 1)) for i in threadpool_info()] or [1]) if threadpool_info else 1
+    host_cores = len(os.sched_getaffinity(0))
+    model = platform.processor() or "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next(ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
     d = si.filters(w["cfg"], w["K"], w["m"]).astype(np.float32).astype(np.float64)
     Lz = oracle.lipschitz_code(d, int(max(max(hw) for hw in sizes)))
-    t0 = time.perf_counter()
-    updates = 0
-    n = 0
-    while n < len(sizes):
-        H, W = int(sizes[n][0]), int(sizes[n][1])
-        x = si.field(w["cfg"], n, H, W).astype(np.float32).astype(np.float64)
-        z, S = oracle.code_step(x, d, np.zeros((w["K"], H, W)), w["lam"], w["p"], 1, 1, w["T"],
-                                step=1.0 / Lz, image_index=n)
-        updates += int(S.sum()) * w["T"]
-        n += 1
-        if time.perf_counter() - t0 > budget_s:
-            break
-    el = time.perf_counter() - t0
+    xs = [si.field(w["cfg"], n, int(H), int(W)).astype(np.float32).astype(np.float64)
+          for n, (H, W) in enumerate(sizes)]
+
+    def run():
+        t0 = time.perf_counter()
+        updates = n = 0
+        while n < len(sizes):
+            H, W = xs[n].shape
+            z, S = oracle.code_step(xs[n], d, np.zeros((w["K"], H, W)), w["lam"], w["p"], 1, 1, w["T"],
+                                    step=1.0 / Lz, image_index=n)
+            updates += int(S.sum()) * w["T"]
+            n += 1
+            if time.perf_counter() - t0 > budget_s / 2:
+                break
+        el = time.perf_counter() - t0
+        return updates / el, n, el
+
+    v_all, n_all, el_all = run()
+    if threadpool_limits is not None:
+        with threadpool_limits(limits=1):
+            v_one, n_one, el_one = run()
+    else:  # pragma: no cover
+        v_one, n_one, el_one = None, 0, 0.0
     return {
-        "value": updates / el,
+        "value": v_all,
         "unit": "updates/s",
-        "cores": threads,
+        "cores": min(blas, host_cores),
         "kind": "oracle",
-        "sample": "code step (%d ISTA iterations, p=%g) of %d of the %d images of one step, "
-                  "FP64 NumPy, %.1f s; filter step not included" % (w["T"], w["p"], n, len(sizes), el),
+        "sample": "code step (%d ISTA iterations, p=%g) of %d of the %d images of one step, FP64 NumPy, "
+                  "%.1f s with the BLAS pool at %d threads; filter step not included"
+                  % (w["T"], w["p"], n_all, len(sizes), el_all, blas),
+        "value_1thread": v_one,
+        "sample_1thread": "the same code step of %d images with the BLAS pool at 1 thread, %.1f s" % (n_one, el_one),
+        "cpu_model": model,
+        "host_cores": host_cores,
+        "os_cpu_count": os.cpu_count(),
+        "blas_threads": blas,
     }
 
 
-def time_to_objective(ctx, w, n_batches):
-    """Online learning over a stream of n_batches mini-batches in FP32 and in BF16.
-
-    After every mini-batch the held-out objective (eq. 1) is evaluated with the
-    clock stopped: 20 held-out images, codes fitted from zero at p = 1 with 50
-    FP32 iterations.  The target is FP32's final held-out objective F*; each
-    precision reports the training time until its held-out objective first
-    reaches F* (1 + 1e-3)."""
+def online_curve(ctx, w, xs, him, held, precision, p, n_batches, lcn_note="", full=False):
+    """Online learning from the workload's initial filters over the mini-batches xs,
+    with the held-out objective (eq. 1, FP64) after every mini-batch, clock stopped.
+    The held-out codes come from the training's own code update (rate p, w["T"] FP32
+    iterations from zero, one fixed sample: draw 0, which no training step uses).
+    Returns [(training seconds, F)] starting with the initial filters at 0 s, and
+    with full=True also the held-out objective with codes over every coordinate
+    (p = 1, 300 iterations) at the start and the end, and L_z of the final filters."""
     import torch
 
     import scsc_inputs as si
@@ -186,37 +254,110 @@ def time_to_objective(ctx, w, n_batches):
 
     K, m, N, H, W = w["K"], w["m"], w["N"], w["H"], w["W"]
     im = Images.uniform(N, H, W)
-    xs = torch.from_numpy(np.stack([si.stream_batch(w["cfg"], t, N, H, W).astype(np.float32).reshape(-1)
-                                    for t in range(1, n_batches + 1)])).cuda()
-    held = torch.from_numpy(si.batch(33, 20, H, W).astype(np.float32).reshape(-1)).cuda()
+    d = torch.from_numpy(si.filters(w["cfg"], K, m).astype(np.float32)).cuda()
+    learner = OnlineLearner(ctx, im, d, w["lam"], p, n_code_iter=w["T"], precision=precision)
+    extra = [learner.evaluate(him, held, n_iter=300, p=1.0)[0]] if full else []
+    elapsed, curve = 0.0, [(0.0, learner.evaluate(him, held, n_iter=w["T"], p=p)[0])]
+    for t in range(n_batches):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        learner.step(xs[t])
+        torch.cuda.synchronize()
+        elapsed += time.perf_counter() - t0
+        curve.append((elapsed, learner.evaluate(him, held, n_iter=w["T"], p=p)[0]))
+    if full:
+        extra.append(learner.evaluate(him, held, n_iter=300, p=1.0)[0])
+        extra.append(ctx.lipschitz_code(learner.d, max(H, W)))
+    return curve, extra
+
+
+def time_to_objective(ctx, w, n_batches):
+    """Online learning over a stream of n_batches mini-batches in FP32 and in BF16,
+    from the same filters on the same stream.
+
+    The stream has the online workload's shape and settings, with 1/f^2 fields that
+    are only z-scored: on the locally contrast-normalised stream of the headline
+    (2 px windows) the held-out objective falls for one mini-batch and then rises,
+    at any sampling rate, so no time to an objective can be read off it
+    (``--tto-study`` runs both streams).  After every mini-batch the held-out
+    objective (eq. 1, FP64) is evaluated with the clock stopped, on 20 held-out
+    images whose codes come from the code update the learner trains with (p and T
+    of the workload, from zero, FP32, one fixed sample).  The target F* is the
+    lowest held-out objective FP32 reaches; each precision reports the training
+    time until its held-out objective first reaches F* (1 + 1e-3), and the two final
+    objectives are compared (equal within 1e-3 relative)."""
+    import torch
+
+    import scsc_inputs as si
+    from paper_1909_00145_amd.ops import Images
+
+    N, H, W = w["N"], w["H"], w["W"]
+    xs = torch.from_numpy(np.stack([si.stream_batch(w["cfg"], t, N, H, W, lcn_sigma=None).astype(np.float32)
+                                    .reshape(-1) for t in range(1, n_batches + 1)])).cuda()
+    held = torch.from_numpy(si.batch(33, 20, H, W, lcn_sigma=None).astype(np.float32).reshape(-1)).cuda()
     him = Images.uniform(20, H, W)
-    curves = {}
+    curves, full = {}, {}
     for prec in ("fp32", "bf16"):
-        d = torch.from_numpy(si.filters(w["cfg"], K, m).astype(np.float32)).cuda()
-        learner = OnlineLearner(ctx, im, d, w["lam"], w["p"], n_code_iter=w["T"], precision=prec)
-        elapsed, curve = 0.0, []
-        for t in range(n_batches):
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            learner.step(xs[t])
-            torch.cuda.synchronize()
-            elapsed += time.perf_counter() - t0
-            F, _, _ = learner.evaluate(him, held)
-            curve.append((elapsed, F))
-        curves[prec] = curve
-    target = curves["fp32"][-1][1]
-    out = {"target_F": target, "tolerance": 1e-3, "mini_batches": n_batches,
-           "eval": "held-out 20 images 100x100 (cfg 33), codes from zero at p=1, 50 FP32 iterations, lambda=%g"
-                   % w["lam"],
-           "criterion": "first mini-batch whose held-out objective is within 1e-3 (relative) of FP32's final one"}
+        curves[prec], full[prec] = online_curve(ctx, w, xs, him, held, prec, w["p"], n_batches, full=True)
+    best = min(range(1, n_batches + 1), key=lambda i: curves["fp32"][i][1])
+    target = curves["fp32"][best][1]
+    out = {"stream": "%d mini-batches of %d images %dx%d, 1/f^2 fields z-scored without local contrast "
+                     "normalisation (cfg %d); K=%d, p=%g, lambda=%g, %d ISTA iterations"
+                     % (n_batches, N, H, W, w["cfg"], w["K"], w["p"], w["lam"], w["T"]),
+           "target_F": target, "target_mini_batch_fp32": best, "tolerance": 1e-3, "mini_batches": n_batches,
+           "eval": "held-out 20 images 100x100 (cfg 33, same generator): codes from zero by the training's code "
+                   "update (p=%g, %d FP32 iterations, one fixed sample), objective of eq. (1) in FP64, lambda=%g"
+                   % (w["p"], w["T"], w["lam"]),
+           "criterion": "first mini-batch whose held-out objective is <= F* (1 + 1e-3), F* = the lowest one "
+                        "FP32 reaches over the run"}
     ref = [F for _, F in curves["fp32"]]
     for prec, curve in curves.items():
-        hit = next((i for i, (_, F) in enumerate(curve) if abs(F - target) <= 1e-3 * abs(target)), None)
+        hit = next((i for i in range(1, len(curve)) if curve[i][1] <= target * (1.0 + 1e-3)), None)
         out[prec] = {"seconds": curve[hit][0] if hit is not None else None,
-                     "mini_batches": hit + 1 if hit is not None else None,
-                     "final_F": curve[-1][1], "train_seconds": curve[-1][0],
+                     "mini_batches": hit,
+                     "initial_F": curve[0][1], "min_F": min(F for _, F in curve[1:]), "final_F": curve[-1][1],
+                     "train_seconds": curve[-1][0],
+                     "final_rel_diff_from_fp32": abs(curve[-1][1] - ref[-1]) / abs(ref[-1]),
                      "max_rel_dev_from_fp32": max(abs(F - r) / abs(r) for (_, F), r in zip(curve, ref)),
-                     "F_every_10": [round(F, 3) for _, F in curve[9::10]]}
+                     "F_after": {str(t): round(curve[t][1], 3) for t in (1, 2, 5, 10, 20, 50, 100)
+                                 if t < len(curve)},
+                     "heldout_p1_300iters_initial_final": [round(v, 3) for v in full[prec][:2]],
+                     "final_L_z": full[prec][2]}
+    if out["fp32"]["seconds"] and out["bf16"]["seconds"]:
+        out["fp32_over_bf16_time"] = out["fp32"]["seconds"] / out["bf16"]["seconds"]
+    out["fp32_over_bf16_time_per_mini_batch"] = out["fp32"]["train_seconds"] / out["bf16"]["train_seconds"]
+    return out
+
+
+def tto_study(ctx, w, n_batches):
+    """Why the held-out objective of online learning rises on the default stream:
+    FP32 online learning from the same filters for p = 0.1 and p = 1, on streams
+    whose local contrast normalisation uses Gaussian windows of 2 px (the default),
+    8 px, or none.  Reports the held-out objective under the training's code update
+    and with codes over every coordinate (p = 1, 300 iterations), and L_z of the
+    final filters (how coherent the dictionary has become)."""
+    import torch
+
+    import scsc_inputs as si
+    from paper_1909_00145_amd.ops import Images
+
+    N, H, W = w["N"], w["H"], w["W"]
+    him = Images.uniform(20, H, W)
+    out = {"mini_batches": n_batches, "precision": "fp32",
+           "L_z_initial": ctx.lipschitz_code(
+               torch.from_numpy(si.filters(w["cfg"], w["K"], w["m"]).astype(np.float32)).cuda(), max(H, W))}
+    for sig in (2.0, 8.0, None):
+        xs = torch.from_numpy(np.stack([si.stream_batch(w["cfg"], t, N, H, W, lcn_sigma=sig).astype(np.float32)
+                                        .reshape(-1) for t in range(1, n_batches + 1)])).cuda()
+        held = torch.from_numpy(si.batch(33, 20, H, W, lcn_sigma=sig).astype(np.float32).reshape(-1)).cuda()
+        for p in (w["p"], 1.0):
+            curve, full = online_curve(ctx, w, xs, him, held, "fp32", p, n_batches, full=True)
+            progress("study: stream lcn=%s p=%g done" % (sig, p))
+            out["lcn_%s_p%g" % ("none" if sig is None else "%gpx" % sig, p)] = {
+                "F_after": {str(t): round(curve[t][1], 1) for t in (0, 1, 2, 5, 10, 20, 50, 100) if t < len(curve)},
+                "heldout_p1_300iters_initial_final": [round(v, 1) for v in full[:2]],
+                "final_L_z": round(full[2], 1)}
+        del xs, held
     return out
 
 
@@ -400,121 +541,105 @@ def solver_compare(ctx, w):
     return out
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print("bench.py runs on exactly one GPU: the method's hot path is measured on one MI355X; "
-              "--gpus %d is not supported" % args.gpus, file=sys.stderr)
-        return 2
+def progress(msg):
+    """One line per finished leg on stderr (the JSON result goes to stdout at the end)."""
+    print("[bench] %s" % msg, file=sys.stderr, flush=True)
+
+
+def workload_inputs(wname, w, n_steps):
+    """Batch geometry and device-resident inputs of a workload (generated before any timing)."""
+    import torch
+
+    import scsc_inputs as si
+    from paper_1909_00145_amd.ops import Images
+
+    if wname == "ragged":
+        im = Images(si.ragged_sizes(w["cfg"], w["N"], 64, 512))
+    else:
+        im = Images.uniform(w["N"], w["H"], w["W"])
+    if wname == "online":
+        x = torch.from_numpy(np.stack([si.stream_batch(w["cfg"], t, w["N"], w["H"], w["W"]).astype(np.float32)
+                                       .reshape(-1) for t in range(1, n_steps + 1)])).cuda()
+    elif wname == "ragged":
+        x = torch.from_numpy(im.pack([si.field(w["cfg"], n, int(H), int(Wd)).astype(np.float32)
+                                      for n, (H, Wd) in enumerate(im.hw)])).cuda()
+    else:
+        x = torch.from_numpy(si.batch(w["cfg"], w["N"], w["H"], w["W"]).astype(np.float32).reshape(-1)).cuda()
+    return im, x
+
+
+def timed_run(ctx, wname, w, im, x, precision, graph, profile, warmup, steps):
+    """Warm-up and timed steps of a workload in one precision, from the initial filters.
+
+    graph: replay the code step's iterations from a HIP graph; profile: time every
+    kernel class with HIP events on the library's stream (which needs eager launches
+    to attribute the code step's kernels)."""
+    import ctypes as C
+
     import torch
 
     import scsc_inputs as si
     from paper_1909_00145_amd import _lib
     from paper_1909_00145_amd.drivers import BatchLearner, OnlineLearner
-    from paper_1909_00145_amd.ops import Context, Images
 
-    w = dict(WORKLOADS[args.workload])
-    if args.p is not None:
-        w["p"] = args.p
-    torch.cuda.set_device(0)
-    ctx = Context(0)
     K, m = w["K"], w["m"]
-    if args.workload == "ragged":
-        im = Images(si.ragged_sizes(w["cfg"], w["N"], 64, 512))
+    ctx.set_graph(graph)
+    d = torch.from_numpy(si.filters(w["cfg"], K, m).astype(np.float32)).cuda()
+    if wname == "online":
+        learner = OnlineLearner(ctx, im, d, w["lam"], w["p"], n_code_iter=w["T"], precision=precision)
+
+        def step(i):
+            return learner.step(x[i])
+    elif wname == "ragged":
+        z = torch.zeros(K * im.n_pix, dtype=torch.float32, device="cuda")
+
+        def step(i):
+            st = ctx.code_step(im, x, d, z, w["lam"], w["p"], w["cfg"], i + 1, w["T"], precision=precision,
+                               stats=True)
+            return st, None
     else:
-        im = Images.uniform(w["N"], w["H"], w["W"])
-    total_steps = args.warmup + args.steps
-    if args.workload == "online":
-        xs = torch.from_numpy(np.stack([si.stream_batch(w["cfg"], t, w["N"], w["H"], w["W"]).astype(np.float32)
-                                        .reshape(-1) for t in range(1, total_steps + 1)])).cuda()
-    elif args.workload == "ragged":
-        x = torch.from_numpy(im.pack([si.field(w["cfg"], n, int(H), int(Wd)).astype(np.float32)
-                                      for n, (H, Wd) in enumerate(im.hw)])).cuda()
-    else:
-        x = torch.from_numpy(si.batch(w["cfg"], w["N"], w["H"], w["W"]).astype(np.float32).reshape(-1)).cuda()
-    def timed_run(precision, graph, profile):
-        """Warm-up and timed steps of the workload in one precision, from the initial filters.
+        learner = BatchLearner(ctx, im, x, d, w["lam"], w["p"], n_code_iter=w["T"], precision=precision)
 
-        graph: replay the code step's iterations from a HIP graph; profile: time every
-        kernel class with HIP events on the library's stream (which needs eager launches
-        to attribute the code step's kernels)."""
-        ctx.set_graph(graph)
-        d = torch.from_numpy(si.filters(w["cfg"], K, m).astype(np.float32)).cuda()
-        if args.workload == "online":
-            learner = OnlineLearner(ctx, im, d, w["lam"], w["p"], n_code_iter=w["T"], precision=precision)
+        def step(i):
+            return learner.step()
 
-            def step(i):
-                return learner.step(xs[i])
-        elif args.workload == "ragged":
-            z = torch.zeros(K * im.n_pix, dtype=torch.float32, device="cuda")
+    for i in range(warmup):
+        step(i)
+    torch.cuda.synchronize()
+    ctx.lib.csc_profile_enable(ctx.h, 1 if profile else 0)
+    r = {"sampled": 0, "nnz_iter": 0, "nnz_dict": 0}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(warmup, warmup + steps):
+        st, _ = step(i)
+        r["sampled"] += st.sampled
+        r["nnz_iter"] += st.nnz_iter_sum
+        r["nnz_dict"] += st.nnz
+    torch.cuda.synchronize()
+    r["el"] = time.perf_counter() - t0
+    kernels = {}
+    for ci, name in enumerate(_lib.KERNEL_CLASSES):
+        n = C.c_int64()
+        ms = C.c_double()
+        ctx.lib.csc_profile_read(ctx.h, ci, C.byref(n), C.byref(ms))
+        if n.value:
+            kernels[name] = {"launches": int(n.value), "avg_us": 1e3 * ms.value / n.value, "total_ms": ms.value}
+    ctx.lib.csc_profile_enable(ctx.h, 0)
+    r["kernels"] = kernels
+    return r
 
-            def step(i):
-                st = ctx.code_step(im, x, d, z, w["lam"], w["p"], w["cfg"], i + 1, w["T"], precision=precision,
-                                   stats=True)
-                return st, None
-        else:
-            learner = BatchLearner(ctx, im, x, d, w["lam"], w["p"], n_code_iter=w["T"], precision=precision)
 
-            def step(i):
-                return learner.step()
-
-        for i in range(args.warmup):
-            step(i)
-        torch.cuda.synchronize()
-        ctx.lib.csc_profile_enable(ctx.h, 1 if profile else 0)
-        r = {"sampled": 0, "nnz_iter": 0, "nnz_dict": 0}
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for i in range(args.warmup, total_steps):
-            st, _ = step(i)
-            r["sampled"] += st.sampled
-            r["nnz_iter"] += st.nnz_iter_sum
-            r["nnz_dict"] += st.nnz
-        torch.cuda.synchronize()
-        r["el"] = time.perf_counter() - t0
-        kernels = {}
-        import ctypes as C
-
-        for ci, name in enumerate(_lib.KERNEL_CLASSES):
-            n = C.c_int64()
-            ms = C.c_double()
-            ctx.lib.csc_profile_read(ctx.h, ci, C.byref(n), C.byref(ms))
-            if n.value:
-                kernels[name] = {"launches": int(n.value), "avg_us": 1e3 * ms.value / n.value, "total_ms": ms.value}
-        ctx.lib.csc_profile_enable(ctx.h, 0)
-        r["kernels"] = kernels
-        return r
-
-    # The joined online step queues a whole mini-batch of launches ahead of the GPU,
-    # so graph replay only adds its launch latency there (4.40 against 4.52 ms per
-    # step measured); the separate calls of the other workloads keep the graphs.
-    graph = args.graph or (not args.eager and args.workload != "online")
-    # the headline run (no event timing), then the same steps eagerly with every kernel
-    # class timed by HIP events, for the per-kernel figures and the roofline
-    res = timed_run(args.precision, graph, False)
-    el = res["el"]
+def rooflines(wname, w, im, precision, res, kernels, steps):
+    """Roofline object of the dominant modelled kernel class and the fractions of all
+    modelled classes, from the algorithmic work of the timed steps (res) and the
+    per-class event averages (kernels)."""
+    K, m = w["K"], w["m"]
     sampled, nnz_iter, nnz_dict = res["sampled"], res["nnz_iter"], res["nnz_dict"]
-    prof = timed_run(args.precision, False, True)
-    kernels = prof["kernels"]
-    if (prof["sampled"], prof["nnz_iter"], prof["nnz_dict"]) != (sampled, nnz_iter, nnz_dict):
-        raise RuntimeError("the profiled pass did not repeat the headline run's work")
-
-    if args.copy_probe_mb > 0:
-        nb = args.copy_probe_mb << 20
-        src = torch.ones(nb // 4, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-
-    updates = sampled * w["T"]
-    value = updates / el
     M = m * m
     c = m // 2
     L2 = (2 * m - 1) ** 2
     n_power = 20
-    bf16 = args.precision == "bf16"
+    bf16 = precision == "bf16"
     mm_peak = PEAK_BF16_MFMA if bf16 else PEAK_FP32_VECTOR
     mm_bound = "mfma" if bf16 else "alu"
     # Algorithmic work of every timed launch of a kernel class, summed over the timed steps.
@@ -526,19 +651,19 @@ def main():
         # M multiply-adds per non-zero code of one correlation (B_bar = Z^T x, FP32 in both precisions)
         "corr": ("alu", 2 * M * nnz_dict, PEAK_FP32_VECTOR),
         # K^2 M^2 FP64 multiply-adds per product with the lag-sum normal matrix (20 per step)
-        "power": ("alu64", 2.0 * K * K * M * M * n_power * args.steps, PEAK_FP64_VECTOR),
+        "power": ("alu64", 2.0 * K * K * M * M * n_power * steps, PEAK_FP64_VECTOR),
         # one pass over the blocks (k, k2 >= k) of the FP64 lag-layout matrix (the rest is their transpose)
-        "sur_mv": ("hbm", 8.0 * (K * (K + 1) // 2) * M * M * args.steps, PEAK_HBM),
+        "sur_mv": ("hbm", 8.0 * (K * (K + 1) // 2) * M * M * steps, PEAK_HBM),
         # read-modify-write of the stored blocks (k <= k2) of C_bar plus their lag sums and the
         # 4 c^2 (2m - 1) band sums that can be non-zero
         "sur_expand": ("hbm", (K * (K + 1) // 2) * (16.0 * M * M + 8.0 * (L2 + 4 * c * c * (2 * m - 1)))
-                       * args.steps, PEAK_HBM),
+                       * steps, PEAK_HBM),
         # gather: the K planes of z read once (a Bernoulli(p) sample touches nearly every 64-byte
         # sector), the selection words, offsets and counts; the gathered pairs are not counted,
         # so this is a lower bound
-        "gather": ("hbm", (4.0 * K + 4.0 * ((K + 31) // 32) + 6.0) * im.n_pix * args.steps, PEAK_HBM),
+        "gather": ("hbm", (4.0 * K + 4.0 * ((K + 31) // 32) + 6.0) * im.n_pix * steps, PEAK_HBM),
         # scatter: the K planes of z written once, the offsets and counts, and the list entries
-        "scatter": ("hbm", (4.0 * K + 6.0) * im.n_pix * args.steps + 8.0 * nnz_dict, PEAK_HBM),
+        "scatter": ("hbm", (4.0 * K + 6.0) * im.n_pix * steps + 8.0 * nnz_dict, PEAK_HBM),
     }
     # MFMA work the BF16 kernels execute per launch (dense tiles, padded shapes), 16x16x32 = 16384 flop
     executed = {}
@@ -546,10 +671,10 @@ def main():
         tiles = sum(((int(H) + 15) // 16) * ((int(Wd) + 15) // 16) for H, Wd in im.hw)
         executed["synth"] = tiles * ((K + 7) // 8) * ((m + 3) // 4) * (16 + 2 * c) * 16384.0
         executed["adjoint"] = tiles * ((K + 15) // 16) * 16 * ((M + 31) // 32) * 16384.0
-    if args.workload == "ragged":
+    if wname == "ragged":
         # code steps only
         work = {k: work[k] for k in ("adjoint", "synth", "gather", "scatter")}
-    elif args.workload != "online":
+    elif wname != "online":
         # batch filter step: one residual synthesis and one gradient correlation; lag-sum power iteration
         work.pop("sur_mv")
         work.pop("sur_expand")
@@ -570,7 +695,7 @@ def main():
             if bound == "alu64":
                 r["precision"] = "fp64"
         r["frac"] = r["achieved"] / r["peak"]
-        r["traffic"] = traffic_for(k, args.workload, args.precision)
+        r["traffic"] = traffic_for(k, wname, precision)
         r["kernel"] = k
         r["per_launch_work"] = per_launch
         r["avg_launch_us"] = kernels[k]["avg_us"]
@@ -585,8 +710,164 @@ def main():
     others = {}
     for k in modelled:
         r = roof_of(k)
-        others[k] = {key: r[key] for key in ("bound", "frac", "traffic", "executed_mfma_frac") if key in r}
+        others[k] = {key: r[key] for key in ("bound", "achieved", "unit", "frac", "traffic", "executed_mfma_frac")
+                     if key in r}
+    return roof, others
 
+
+def ragged_leg(ctx, steps, warmup):
+    """One code step of the ragged batch (256 images, sides uniform in [64, 512], K = 100,
+    T = 30) per timed step, BF16 and FP32 plain, replayed from HIP graphs; then the same
+    steps with eager launches and every kernel class timed by HIP events, for the
+    per-class roofline fractions."""
+    import torch
+
+    w = WORKLOADS["ragged"]
+    im, x = workload_inputs("ragged", w, 0)
+    out = {"workload": w["name"], "pixels": im.n_pix, "steps": steps, "warmup": warmup, "graph": True}
+    for prec in ("bf16", "fp32"):
+        res = timed_run(ctx, "ragged", w, im, x, prec, True, False, warmup, steps)
+        progress("ragged %s timed" % prec)
+        prof = timed_run(ctx, "ragged", w, im, x, prec, False, True, warmup, steps)
+        roof, others = rooflines("ragged", w, im, prec, prof, prof["kernels"], steps)
+        out[prec] = {"value": res["sampled"] * w["T"] / res["el"], "unit": "updates/s",
+                     "ms_per_step": 1e3 * res["el"] / steps,
+                     "roofline": roof, "roofline_all": others,
+                     "kernels_avg_us": {k: round(v["avg_us"], 1) for k, v in prof["kernels"].items()}}
+        torch.cuda.empty_cache()
+        progress("ragged %s: %.1f ms per step" % (prec, out[prec]["ms_per_step"]))
+    return out
+
+
+def unrolled_leg(ctx, reps=2):
+    """Differentiation workload: 10 unrolled subsampled-ISTA layers (p = 0.2, lambda =
+    0.5, step 1/L_z) on 32 images 128 x 128 with K = 256 filters 11 x 11, loss
+    1/2 sum ||x - D z_10||^2, one forward and backward pass through the torch
+    Functions per timed run, in BF16 and FP32, with a checkpoint at every layer and
+    every 5 layers.  Then a profiled pass for the per-class kernel times; the dense
+    adjoint correlation (the layer's D^T r at every coordinate) is the real dense
+    contraction here, so its roofline is reported on the matrix cores in BF16."""
+    import torch
+
+    import scsc_inputs as si
+    from paper_1909_00145_amd import _lib
+    from paper_1909_00145_amd.autograd import synthesis, unrolled_ista
+    from paper_1909_00145_amd.ops import Images
+
+    N, H, W, K, m, p, lam, T, cfg = 32, 128, 128, 256, 11, 0.2, 0.5, 10, 5
+    im = Images.uniform(N, H, W)
+    x0 = torch.from_numpy(si.batch(cfg, N, H, W).astype(np.float32).reshape(-1)).cuda()
+    d0 = torch.from_numpy(si.filters(cfg, K, m).astype(np.float32)).cuda()
+    mask = ctx.mask(im, K, p, cfg, 1)
+    eta = 1.0 / ctx.lipschitz_code(d0, max(H, W))
+    sampled = int(mask.sum())
+    M, MP = m * m, 32 * ((m * m + 31) // 32)
+    out = {"workload": "%d images %dx%d, K=%d filters %dx%d, p=%g, lambda=%g, %d unrolled layers, loss "
+                       "1/2 sum ||x - D z_T||^2, forward + backward" % (N, H, W, K, m, m, p, lam, T),
+           "sampled": sampled}
+
+    def run(prec, every):
+        x = x0.clone().requires_grad_(True)
+        d = d0.clone().requires_grad_(True)
+        z0 = torch.zeros(K * im.n_pix, dtype=torch.float32, device="cuda")
+        zT = unrolled_ista(ctx, im, x, d, z0, mask, eta, lam, T, checkpoint_every=every, precision=prec)
+        e = x - synthesis(ctx, im, zT, d, precision=prec)
+        loss = 0.5 * (e * e).sum()
+        loss.backward()
+        return float(loss.detach())
+
+    import ctypes as C
+
+    for prec in ("bf16", "fp32"):
+        res = {}
+        for every in (1, 5):
+            run(prec, every)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                loss = run(prec, every)
+            torch.cuda.synchronize()
+            ms = 1e3 * (time.perf_counter() - t0) / reps
+            res["checkpoint_every_%d" % every] = {"ms_fwd_bwd": round(ms, 2), "loss": loss,
+                                                  "layer_updates_per_s": T * sampled / (ms * 1e-3)}
+            torch.cuda.empty_cache()
+        ctx.lib.csc_profile_enable(ctx.h, 1)
+        run(prec, 1)
+        torch.cuda.synchronize()
+        kern = {}
+        for ci, name in enumerate(_lib.KERNEL_CLASSES):
+            n = C.c_int64()
+            t = C.c_double()
+            ctx.lib.csc_profile_read(ctx.h, ci, C.byref(n), C.byref(t))
+            if n.value:
+                kern[name] = {"launches": int(n.value), "avg_us": round(1e3 * t.value / n.value, 1)}
+        ctx.lib.csc_profile_enable(ctx.h, 0)
+        res["kernels"] = kern
+        if "dense" in kern:
+            avg = kern["dense"]["avg_us"] * 1e-6
+            if prec == "bf16":
+                # executed: the GEMM over 32-padded taps and 16-padded filters; algorithmic: 2 M K per pixel
+                ex = 2.0 * (16 * ((K + 15) // 16)) * MP * im.n_pix
+                res["roofline_dense_adjoint"] = {
+                    "bound": "mfma", "achieved": 2.0 * M * K * im.n_pix / avg / 1e12, "peak": PEAK_BF16_MFMA / 1e12,
+                    "unit": "TFLOP/s", "frac": 2.0 * M * K * im.n_pix / avg / PEAK_BF16_MFMA,
+                    "executed_mfma_frac": ex / avg / PEAK_BF16_MFMA, "avg_launch_us": kern["dense"]["avg_us"]}
+            else:
+                res["roofline_dense_adjoint"] = {
+                    "bound": "alu", "achieved": 2.0 * M * K * im.n_pix / avg / 1e12, "peak": PEAK_FP32_VECTOR / 1e12,
+                    "unit": "TFLOP/s", "frac": 2.0 * M * K * im.n_pix / avg / PEAK_FP32_VECTOR,
+                    "avg_launch_us": kern["dense"]["avg_us"]}
+        out[prec] = res
+        progress("unrolled %s: %.1f ms per forward and backward" % (prec, res["checkpoint_every_1"]["ms_fwd_bwd"]))
+    return out
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU: the method's hot path is measured on one MI355X; "
+              "--gpus %d is not supported" % args.gpus, file=sys.stderr)
+        return 2
+    import torch
+
+    from paper_1909_00145_amd.ops import Context
+
+    w = dict(WORKLOADS[args.workload])
+    if args.p is not None:
+        w["p"] = args.p
+    torch.cuda.set_device(0)
+    ctx = Context(0)
+    K, m = w["K"], w["m"]
+    total_steps = args.warmup + args.steps
+    im, x = workload_inputs(args.workload, w, total_steps)
+
+    # The joined online step queues a whole mini-batch of launches ahead of the GPU,
+    # so graph replay only adds its launch latency there (4.40 against 4.52 ms per
+    # step measured); the separate calls of the other workloads keep the graphs.
+    graph = args.graph or (not args.eager and args.workload != "online")
+    # the headline run (no event timing), then the same steps eagerly with every kernel
+    # class timed by HIP events, for the per-kernel figures and the roofline
+    res = timed_run(ctx, args.workload, w, im, x, args.precision, graph, False, args.warmup, args.steps)
+    el = res["el"]
+    progress("headline %s: %.3f ms per step" % (args.precision, 1e3 * el / args.steps))
+    prof = timed_run(ctx, args.workload, w, im, x, args.precision, False, True, args.warmup, args.steps)
+    kernels = prof["kernels"]
+    if (prof["sampled"], prof["nnz_iter"], prof["nnz_dict"]) != (res["sampled"], res["nnz_iter"], res["nnz_dict"]):
+        raise RuntimeError("the profiled pass did not repeat the headline run's work")
+
+    if args.copy_probe_mb > 0:
+        nb = args.copy_probe_mb << 20
+        src = torch.ones(nb // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    updates = res["sampled"] * w["T"]
+    value = updates / el
+    roof, others = rooflines(args.workload, w, im, args.precision, res, kernels, args.steps)
+    bf16 = args.precision == "bf16"
     out = {
         "metric": "sampled code-coord updates/sec",
         "value": value,
@@ -609,28 +890,41 @@ def main():
         "kernels": kernels,
         "kernels_note": "per-class HIP-event averages from an eager pass of the same steps (%.2f ms per step "
                         "with the events)" % (1e3 * prof["el"] / args.steps),
-        "code_density": nnz_dict / (args.steps * K * im.n_pix),
+        "code_density": res["nnz_dict"] / (args.steps * K * im.n_pix),
     }
     if not args.no_compare:
         other = "fp32" if bf16 else "bf16"
-        r2 = timed_run(other, graph, False)
-        p2 = timed_run(other, False, True)
+        r2 = timed_run(ctx, args.workload, w, im, x, other, graph, False, args.warmup, args.steps)
+        p2 = timed_run(ctx, args.workload, w, im, x, other, False, True, args.warmup, args.steps)
         out["fp32_plain" if other == "fp32" else "bf16"] = {
             "value": r2["sampled"] * w["T"] / r2["el"], "unit": "updates/s",
             "ms_per_step": 1e3 * r2["el"] / args.steps,
             "code_density": r2["nnz_dict"] / (args.steps * K * im.n_pix),
             "kernels_avg_us": {k: round(v["avg_us"], 1) for k, v in p2["kernels"].items()}}
-    if args.tto:
+    if not args.no_tto:
         out["time_to_objective"] = time_to_objective(ctx, WORKLOADS["online"], args.tto_batches)
+        progress("time to objective done")
+    if args.tto_study:
+        out["tto_study"] = tto_study(ctx, WORKLOADS["online"], args.tto_batches)
+        progress("time-to-objective study done")
+    if args.workload == "online" and not args.no_ragged:
+        out["ragged"] = ragged_leg(ctx, args.ragged_steps, 1)
+        progress("ragged leg done")
+    if args.workload == "online" and not args.no_unrolled:
+        out["unrolled"] = unrolled_leg(ctx)
     if not args.no_hold_compare:
         out["hold_vs_project"] = hold_vs_project(ctx, WORKLOADS["batch"], args.hold_iters, args.precision)
+        progress("hold/project comparison done")
     if not args.no_inpaint:
         out["inpainting"] = inpainting(ctx, WORKLOADS["online"], args.inpaint_train, args.precision)
+        progress("inpainting done")
     if not args.no_solver_compare:
         out["solver_compare"] = solver_compare(ctx, WORKLOADS["online"])
+        progress("solver comparison done")
     if args.eta_sweep:
         out["eta_sweep"] = eta_sweep(ctx, WORKLOADS["online"], args.sweep_K,
                                      [int(v) for v in args.eta_sweep.split(",")], args.sweep_samples, args.precision)
+    out["paper_reference"] = PAPER_REFERENCE
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds, [tuple(hw) for hw in im.hw])
     print(json.dumps(out), flush=True)

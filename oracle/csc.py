@@ -498,7 +498,8 @@ class OnlineState:
 
 
 def dict_step_online(xs, Ws, zs, d: np.ndarray, state: OnlineState, n_iter: int = 1, n_power: int = 20):
-    """Online filter update (eqs. 7-8) for one mini-batch; mutates ``state``.
+    """Online filter update (surrogates of eq. 8, surrogate problem of eq. 9) for one mini-batch;
+    mutates ``state``.
 
     C_bar += sum Z^T W Z, B_bar += sum Z^T W x, t += 1, Ld_sum += L_d(batch);
     then n_iter steps d <- P(d - (C^t d - B^t) / L^t) with L^t = Ld_sum / t, an

@@ -6,6 +6,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <functional>
+#include <initializer_list>
 #include <map>
 #include <mutex>
 #include <string>
@@ -393,6 +394,18 @@ void *ws(csc_ctx *h, Slot s, size_t bytes, int *status) {
 
 bool supported_m(int m) { return m == 3 || m == 5 || m == 7 || m == 9 || m == 11; }
 
+// Float, int and u16 arrays must be 4-byte aligned, double arrays 8-byte aligned
+// (null pointers are checked separately).
+int check_aligned(csc_ctx *h, std::initializer_list<const void *> p4, std::initializer_list<const void *> p8 = {}) {
+    for (const void *p : p4)
+        if (p && reinterpret_cast<uintptr_t>(p) % 4u)
+            return fail(h, CSC_EINVAL, "array arguments of 4-byte elements must be 4-byte aligned");
+    for (const void *p : p8)
+        if (p && reinterpret_cast<uintptr_t>(p) % 8u)
+            return fail(h, CSC_EINVAL, "surrogate arrays must be 8-byte aligned");
+    return CSC_OK;
+}
+
 int check_filters(csc_ctx *h, int K, int m) {
     if (K < 1 || K > MAX_K) return fail(h, CSC_EINVAL, "K must lie in [1, 1024]");
     if (m < 1 || (m & 1) == 0) return fail(h, CSC_EINVAL, "filter side m must be odd and positive");
@@ -767,6 +780,7 @@ extern "C" int csc_lipschitz_code(csc_handle h, const float *d, int K, int m, in
     int st = check_filters(h, K, m);
     if (st) return st;
     if (!d || !L_out) return fail(h, CSC_EINVAL, "null pointer argument");
+    if ((st = check_aligned(h, {d}))) return st;
     if (max_side < 1 || max_side > (1 << 16)) return fail(h, CSC_EINVAL, "max_side must lie in [1, 65536]");
     HIPCHK(hipSetDevice(h->device));
     return lipschitz(h, d, K, m, max_side, L_out);
@@ -815,6 +829,7 @@ int code_step_impl(csc_ctx *h, const csc_images *im, const float *x, const uint8
     if (!st) st = check_precision(h, precision);
     if (st) return st;
     if (!x || !d || (!z && !fo)) return fail(h, CSC_EINVAL, "null pointer argument");
+    if ((st = check_aligned(h, {x, d, z}))) return st;
     if (fo && hold) return fail(h, CSC_EINVAL, "a fused code step starts from zero codes");
     if (!(lambda >= 0.0) || !std::isfinite(lambda)) return fail(h, CSC_EINVAL, "lambda must be finite and >= 0");
     if (!(p > 0.0 && p <= 1.0)) return fail(h, CSC_EINVAL, "p must lie in (0, 1]");
@@ -1045,6 +1060,7 @@ extern "C" int csc_code_step_admm(csc_handle h, const csc_images *im, const floa
     if (!st) st = check_filters(h, K, m);
     if (st) return st;
     if (!x || !d || !z) return fail(h, CSC_EINVAL, "null pointer argument");
+    if ((st = check_aligned(h, {x, d, z}))) return st;
     if (!(lambda >= 0.0) || !std::isfinite(lambda)) return fail(h, CSC_EINVAL, "lambda must be finite and >= 0");
     if (!(p > 0.0 && p <= 1.0)) return fail(h, CSC_EINVAL, "p must lie in (0, 1]");
     if (n_admm < 0 || n_cg < 0) return fail(h, CSC_EINVAL, "n_admm and n_cg must be >= 0");
@@ -1289,9 +1305,11 @@ extern "C" int csc_dict_step(csc_handle h, const csc_images *im, const float *x,
     if (!st) st = check_precision(h, precision);
     if (st) return st;
     if (!x || !d || !z) return fail(h, CSC_EINVAL, "null pointer argument");
+    if ((st = check_aligned(h, {x, d, z}))) return st;
     if (n_iter < 0) return fail(h, CSC_EINVAL, "n_iter must be >= 0");
     if (n_power < 1) return fail(h, CSC_EINVAL, "n_power must be >= 1");
     if (!std::isfinite(step)) return fail(h, CSC_EINVAL, "step must be finite");
+    if (sur && (st = check_aligned(h, {}, {sur->C, sur->B}))) return st;
     if (sur && (!sur->C || !sur->B || sur->t < 0 || !(sur->Ld_sum >= 0.0)))
         return fail(h, CSC_EINVAL, "surrogate: need C, B, t >= 0 and Ld_sum >= 0");
     HIPCHK(hipSetDevice(h->device));
@@ -1342,6 +1360,7 @@ extern "C" int csc_online_step(csc_handle h, const csc_images *im, const float *
     if (!h) return CSC_EINVAL;
     if (!sur || !sur->C || !sur->B || sur->t < 0 || !(sur->Ld_sum >= 0.0))
         return fail(h, CSC_EINVAL, "surrogate: need C, B, t >= 0 and Ld_sum >= 0");
+    if (int sa = check_aligned(h, {}, {sur->C, sur->B})) return sa;
     if (n_dict_iter < 0) return fail(h, CSC_EINVAL, "n_dict_iter must be >= 0");
     if (n_power < 1) return fail(h, CSC_EINVAL, "n_power must be >= 1");
     CodeStepFused fo;
@@ -1381,6 +1400,7 @@ extern "C" int csc_objective(csc_handle h, const csc_images *im, const float *x,
     if (!st) st = check_filters(h, K, m);
     if (st) return st;
     if (!x || !d || !z || !f_out) return fail(h, CSC_EINVAL, "null pointer argument");
+    if ((st = check_aligned(h, {x, d, z}))) return st;
     if (!(lambda >= 0.0) || !std::isfinite(lambda)) return fail(h, CSC_EINVAL, "lambda must be finite and >= 0");
     HIPCHK(hipSetDevice(h->device));
     if ((st = geometry(h, im))) return st;
@@ -1410,6 +1430,7 @@ extern "C" int csc_objective_noalloc(csc_handle h, const csc_images *im, const f
     if (!st) st = check_filters(h, K, m);
     if (st) return st;
     if (!x || !d || !z || !f_out) return fail(h, CSC_EINVAL, "null pointer argument");
+    if ((st = check_aligned(h, {x, d, z}))) return st;
     if (!(lambda >= 0.0) || !std::isfinite(lambda)) return fail(h, CSC_EINVAL, "lambda must be finite and >= 0");
     std::vector<ImgInfo> imgs;
     std::vector<TileInfo> tiles;
@@ -1473,6 +1494,7 @@ extern "C" int csc_synthesize(csc_handle h, const csc_images *im, const float *d
     if (!st) st = check_precision(h, precision);
     if (st) return st;
     if (!d || !z || !y) return fail(h, CSC_EINVAL, "null pointer argument");
+    if ((st = check_aligned(h, {d, z, y}))) return st;
     HIPCHK(hipSetDevice(h->device));
     if ((st = geometry(h, im))) return st;
     Lists L;
@@ -1492,6 +1514,7 @@ extern "C" int csc_adjoint(csc_handle h, const csc_images *im, const float *d, i
     if (!st) st = check_precision(h, precision);
     if (st) return st;
     if (!d || !r || !g) return fail(h, CSC_EINVAL, "null pointer argument");
+    if ((st = check_aligned(h, {d, r, g}))) return st;
     HIPCHK(hipSetDevice(h->device));
     if ((st = geometry(h, im))) return st;
     const __bf16 *dA = nullptr;
@@ -1507,6 +1530,7 @@ extern "C" int csc_filter_corr(csc_handle h, const csc_images *im, const float *
     if (!st) st = check_precision(h, precision);
     if (st) return st;
     if (!z || !r || !G) return fail(h, CSC_EINVAL, "null pointer argument");
+    if ((st = check_aligned(h, {z, r, G}))) return st;
     HIPCHK(hipSetDevice(h->device));
     if ((st = geometry(h, im))) return st;
     Lists L;
@@ -1571,6 +1595,7 @@ extern "C" int csc_ista_forward(csc_handle h, const csc_images *im, const float 
     int st = check_layer_args(h, im, K, m, precision, eta, lambda);
     if (st) return st;
     if (!x || !d || !mask || !z_in || !z_out) return fail(h, CSC_EINVAL, "null pointer argument");
+    if ((st = check_aligned(h, {x, d, z_in, z_out}))) return st;
     HIPCHK(hipSetDevice(h->device));
     if ((st = geometry(h, im))) return st;
     const long long n = (long long)K * h->geo.n_pix;
@@ -1591,6 +1616,7 @@ extern "C" int csc_ista_backward(csc_handle h, const csc_images *im, const float
     int st = check_layer_args(h, im, K, m, precision, eta, lambda);
     if (st) return st;
     if (!x || !d || !mask || !z_in || !g_out || !g_z || !g_d) return fail(h, CSC_EINVAL, "null pointer argument");
+    if ((st = check_aligned(h, {x, d, z_in, g_out, g_z, g_d}))) return st;
     HIPCHK(hipSetDevice(h->device));
     if ((st = geometry(h, im))) return st;
     const Geometry &g = h->geo;

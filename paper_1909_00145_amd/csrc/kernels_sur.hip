@@ -1,4 +1,5 @@
-// Online surrogate kernels for gfx950 (eqs. 7-8), FP64:
+// Online surrogate kernels for gfx950 (the surrogates of eq. (8) and the
+// gradient of the surrogate problem, eq. (9)), FP64:
 //   C_bar += sum_n Z_n^T W_n Z_n   and   y = C_bar d.
 //
 // Entry ((k, s), (k2, s2)) of Z^T W Z is sum_p W[p] z_k[p - s] z_k2[p - s2], p over
@@ -13,8 +14,11 @@
 //         + E_right(delta, s_x) - E_corners(delta, s),
 // and each side term is a prefix sum over the first (last) c rows (columns) of
 // the image of the lag sums restricted to codes in that row (column).  The lag
-// sums are accumulated by workgroups that own one filter k and 64 lags (lane ->
-// lag, wave -> code), the corner term exactly from the corner ring pixels.
+// sums come from filter-major runs of non-zero codes: a workgroup owns a
+// tap-row offset, a few filters k and a range of image rows, keeps the sums
+// for every column offset and partner filter in LDS, and pairs each of its
+// codes with the contiguous run of partner codes in the row below; the corner
+// term is formed exactly from the corner ring pixels.
 // With an observation mask the masked pixels are excluded as well; that case
 // uses a tiled kernel that enumerates every excluded pixel.
 #include "scsc_internal.h"

@@ -70,11 +70,16 @@ class OnlineLearner:
                                     z=self.z, W=W, precision=self.precision, n_dict_iter=self.n_dict_iter,
                                     n_power=self.n_power, stats=True)
 
-    def evaluate(self, im: Images, x, n_iter: int = 50, lam: float | None = None, W=None):
-        """Objective of eq. (1) on held-out images with codes fitted at p = 1 from zero."""
+    def evaluate(self, im: Images, x, n_iter: int = 50, lam: float | None = None, W=None, p: float = 1.0):
+        """Objective of eq. (1) on held-out images with codes fitted from zero by n_iter
+        FP32 proximal-gradient iterations on a Bernoulli(p) sample.  The sample is draw 0
+        of the learner's seed, which no training step uses, so repeated evaluations of one
+        dictionary see the same coordinates.  p = 1 codes every coordinate; p = the
+        learner's own rate with n_iter = its iteration count evaluates the dictionary
+        under the code update it is trained with."""
         lam = self.lam if lam is None else lam
         z = torch.zeros(self.K * im.n_pix, dtype=torch.float32, device=x.device)
-        self.ctx.code_step(im, x, self.d, z, lam, 1.0, self.seed, 0, n_iter, W=W, precision="fp32")
+        self.ctx.code_step(im, x, self.d, z, lam, p, self.seed, 0, n_iter, W=W, precision="fp32")
         return self.ctx.objective(im, x, self.d, z, lam, W=W)
 
     def state_dict(self):

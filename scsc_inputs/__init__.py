@@ -39,8 +39,11 @@ LCN_SIGMA = 2.0
 LCN_TRUNCATE = 4.0
 
 
-def field(cfg: int, n: int, H: int, W: int) -> np.ndarray:
-    """One synthetic image (float64, shape [H, W]) for config id ``cfg``, index ``n``."""
+def field(cfg: int, n: int, H: int, W: int, lcn_sigma: float | None = LCN_SIGMA) -> np.ndarray:
+    """One synthetic image (float64, shape [H, W]) for config id ``cfg``, index ``n``.
+
+    lcn_sigma: width (px) of the Gaussian windows of the local contrast
+    normalisation; None skips that step (the 1/f^2 field is only z-scored)."""
     rng = np.random.default_rng(np.random.SeedSequence([int(cfg), int(n)]))
     w = rng.standard_normal((H, W))
     fy = np.fft.fftfreq(H)[:, None]
@@ -49,23 +52,27 @@ def field(cfg: int, n: int, H: int, W: int) -> np.ndarray:
     amp = np.zeros_like(f)
     amp[f > 0] = 1.0 / f[f > 0]
     g = np.real(np.fft.ifft2(np.fft.fft2(w) * amp))
-    mu = ndimage.gaussian_filter(g, LCN_SIGMA, mode="reflect", truncate=LCN_TRUNCATE)
-    c = g - mu
-    v = ndimage.gaussian_filter(c * c, LCN_SIGMA, mode="reflect", truncate=LCN_TRUNCATE)
-    y = c / np.sqrt(np.maximum(v, v.mean()))
+    if lcn_sigma is None:
+        y = g
+    else:
+        mu = ndimage.gaussian_filter(g, lcn_sigma, mode="reflect", truncate=LCN_TRUNCATE)
+        c = g - mu
+        v = ndimage.gaussian_filter(c * c, lcn_sigma, mode="reflect", truncate=LCN_TRUNCATE)
+        y = c / np.sqrt(np.maximum(v, v.mean()))
     y = y - y.mean()
     s = y.std()
     return y / s if s > 0 else y
 
 
-def batch(cfg: int, N: int, H: int, W: int, first: int = 0) -> np.ndarray:
+def batch(cfg: int, N: int, H: int, W: int, first: int = 0, lcn_sigma: float | None = LCN_SIGMA) -> np.ndarray:
     """N same-size images [N, H, W] (float64), image indices first..first+N-1."""
-    return np.stack([field(cfg, first + i, H, W) for i in range(N)])
+    return np.stack([field(cfg, first + i, H, W, lcn_sigma) for i in range(N)])
 
 
-def stream_batch(cfg: int, t: int, batch_size: int, H: int, W: int) -> np.ndarray:
+def stream_batch(cfg: int, t: int, batch_size: int, H: int, W: int,
+                 lcn_sigma: float | None = LCN_SIGMA) -> np.ndarray:
     """Mini-batch t (1-based) of an image stream: indices (t-1)*b .. t*b-1."""
-    return batch(cfg, batch_size, H, W, first=(t - 1) * batch_size)
+    return batch(cfg, batch_size, H, W, first=(t - 1) * batch_size, lcn_sigma=lcn_sigma)
 
 
 def filters(cfg: int, K: int, m: int) -> np.ndarray:

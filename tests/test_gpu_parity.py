@@ -212,6 +212,14 @@ def test_code_step_rejects_bad_arguments(ctx):
     with pytest.raises(CSCError) as e:
         ctx.code_step(im, x, torch.zeros(2, 4, 4, device="cuda"), z, 1.0, 0.5, 1, 1, 1, step=1.0)
     assert e.value.status == -1
+    # an image array that is not 4-byte aligned (the buffer holds the whole image after the offset)
+    import ctypes as C
+
+    buf = torch.zeros(64 * 4 + 4, dtype=torch.uint8, device="cuda")
+    rc = ctx.lib.csc_code_step(ctx.h, im.cref(), C.c_void_p(buf.data_ptr() + 2), None, C.c_void_p(d.data_ptr()),
+                               2, 3, C.c_void_p(z.data_ptr()), 1.0, 0.5, 1, 1, 1, 1.0, 0, None)
+    assert rc == -1 and b"aligned" in ctx.lib.csc_last_error(ctx.h)
+    assert torch.all(z == 7.0)
 
 
 def test_code_step_full_size_image(ctx):
@@ -234,7 +242,7 @@ def test_code_step_full_size_image(ctx):
 
 
 # ---------------------------------------------------------------------------
-# filter steps (eq. 5, eqs. 7-8)
+# filter steps (eq. 5; online: eqs. (8)-(9))
 # ---------------------------------------------------------------------------
 def sparse_codes(hw, K, density, seed):
     rng = np.random.default_rng(seed)

@@ -34,3 +34,13 @@ def test_ragged_sizes_range():
     assert s.shape == (256, 2)
     assert s.min() >= 64 and s.max() <= 512
     np.testing.assert_array_equal(s, si.ragged_sizes(4, 256))
+
+
+def test_field_default_is_the_sigma_2_normalisation():
+    a = si.field(5, 1, 40, 30)
+    np.testing.assert_array_equal(a, si.field(5, 1, 40, 30, lcn_sigma=2.0))
+    raw = si.field(5, 1, 40, 30, lcn_sigma=None)
+    assert abs(raw.mean()) < 1e-12 and abs(raw.std() - 1.0) < 1e-12
+    assert not np.allclose(raw, a)
+    np.testing.assert_array_equal(si.stream_batch(5, 2, 3, 40, 30, lcn_sigma=8.0)[1],
+                                  si.field(5, 4, 40, 30, lcn_sigma=8.0))
