@@ -54,7 +54,9 @@ typedef struct csc_ctx *csc_handle;
 typedef enum {
     CSC_OK = 0,
     CSC_EINVAL = -1,       /* invalid argument (nothing written)              */
-    CSC_ENOMEM = -2,       /* device workspace allocation failed              */
+    CSC_ENOMEM = -2,       /* device workspace allocation failed (or would     *
+                            * exceed the limit SCSC_WORKSPACE_LIMIT, in bytes,  *
+                            * that the environment held at csc_create)          */
     CSC_EHIP = -3,         /* a HIP runtime call or kernel launch failed      */
     CSC_EUNSUPPORTED = -4  /* valid but unsupported size / option             */
 } csc_status;

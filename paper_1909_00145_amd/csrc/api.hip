@@ -125,6 +125,9 @@ struct csc_ctx {
     // this device's copy of the fixed scratch array (csc_objective_noalloc), or null if
     // its address could not be obtained when the handle was created
     unsigned char *scratch = nullptr;
+    // cap on the handle's device workspaces in bytes (0: none), from SCSC_WORKSPACE_LIMIT at creation
+    size_t ws_limit = 0;
+    size_t ws_total = 0;
 };
 
 namespace {
@@ -367,13 +370,19 @@ void *ws(csc_ctx *h, Slot s, size_t bytes, int *status) {
     Buffer &b = h->ws[s];
     if (bytes == 0) bytes = 256;
     if (b.bytes >= bytes) return b.p;
+    size_t want = bytes + bytes / 8;
+    if (h->ws_limit && h->ws_total - b.bytes + want > h->ws_limit) {
+        *status = fail(h, CSC_ENOMEM, "device workspace of " + std::to_string(want) + " bytes would exceed the " +
+                                          "handle's limit of " + std::to_string(h->ws_limit) + " bytes");
+        return nullptr;
+    }
     if (b.p) {
         hipStreamSynchronize(h->stream);
         hipFree(b.p);
+        h->ws_total -= b.bytes;
         b.p = nullptr;
         b.bytes = 0;
     }
-    size_t want = bytes + bytes / 8;
     if (hipMalloc(&b.p, want) != hipSuccess) {
         hipGetLastError();
         b.p = nullptr;
@@ -381,6 +390,7 @@ void *ws(csc_ctx *h, Slot s, size_t bytes, int *status) {
         return nullptr;
     }
     b.bytes = want;
+    h->ws_total += want;
     return b.p;
 }
 
@@ -740,6 +750,7 @@ extern "C" int csc_create(csc_handle *out, int device, void *stream) {
         return CSC_ENOMEM;
     }
     if (scratch_address(device, &h->scratch) != CSC_OK) h->scratch = nullptr;  // reported by csc_objective_noalloc
+    if (const char *lim = std::getenv("SCSC_WORKSPACE_LIMIT")) h->ws_limit = std::strtoull(lim, nullptr, 10);
     *out = h;
     return CSC_OK;
 }
