@@ -68,6 +68,8 @@ enum Slot {
     WS_ADOT,
     WS_ASEG,
     WS_COFF,
+    WS_PPART,
+    WS_CPART,
     WS_COUNT
 };
 
@@ -117,6 +119,11 @@ struct csc_ctx {
     std::vector<uintptr_t> graph_key[2];
     hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
     hipStream_t graph_stream = nullptr;  // capture / replay stream when the handle's stream is the null stream
+    // second stream (default priority) for the parts of the online filter step that
+    // do not depend on each other, ordered against the handle's stream with events
+    hipStream_t side = nullptr;
+    hipEvent_t side_ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    bool side_failed = false;
     hipEvent_t graph_ev[2] = {nullptr, nullptr};
     // autotuner: launch variant per (kernel, m, K, log2 pixel count, mode)
     bool autotune = true;
@@ -650,37 +657,44 @@ int power_iteration(csc_ctx *h, int K, int m, Lists L, FmLists F, const unsigned
 
 // Power iteration on the zero-padded normal matrix given by the lag sums Rl
 // (no observation mask); leaves the estimate in the device scalar SC_LAM.
-int power_iteration_lag(csc_ctx *h, int K, int m, const double *Rl, int n_power) {
+// Power iteration on the lag sums, launched on stream `s` (the handle's stream or
+// its side stream); its workspaces are its own, so it may run beside the surrogate
+// kernels.
+int power_iteration_lag(csc_ctx *h, int K, int m, const double *Rl, int n_power, hipStream_t s) {
     const int M = m * m, n = K * M;
     const int nch = lag_matvec_chunks(K), nb = power_reduce_blocks(n);
     WS(wa, float, WS_V, n);
     WS(wb, float, WS_W, n);
-    WS(part, double, WS_PART, (size_t)nch * n);
+    WS(part, double, WS_PPART, (size_t)nch * n);
     WS(np, double, WS_PNORM, 3 * (size_t)nb);
     WS(sc, double, WS_SCAL, SC_COUNT);
     WS(Rf, float, WS_LAGF, surrogate_lag_elems(K, m));
-    HIPCHK(launch_lag_to_f32(K, m, Rl, Rf, h->stream));
+    HIPCHK(launch_lag_to_f32(K, m, Rl, Rf, s));
     // start: v = the normalised ones vector, given as w = 1 with ||w||^2 = n
     double *na = np, *nbp = np + nb, *dp = np + 2 * nb;
-    HIPCHK(launch_fill(wa, n, 1.0f, h->stream));
-    HIPCHK(launch_power_start(na, nb, (double)n, h->stream));
-    HIPCHK(hipMemsetAsync(sc + SC_LAM, 0, sizeof(double), h->stream));
+    HIPCHK(launch_fill(wa, n, 1.0f, s));
+    HIPCHK(launch_power_start(na, nb, (double)n, s));
+    HIPCHK(hipMemsetAsync(sc + SC_LAM, 0, sizeof(double), s));
     // the products only launch kernels (their vectors and norms live on the device),
-    // so the same launches can be replayed as a graph
+    // so the same launches can be replayed as a graph; on the handle's stream they
+    // take h->stream at launch time, which is the capture stream while a graph is
+    // being recorded
+    const bool own = s == h->stream;
     auto products = [&]() -> int {
+        const hipStream_t ls = own ? h->stream : s;
         float *a = wa, *b = wb;
         double *p = na, *q = nbp;
         for (int it = 0; it < n_power; ++it) {
             PROF(CSC_PK_POWER);
-            HIPCHK(launch_lag_matvec(K, m, Rf, a, p, nb, part, h->stream));
-            HIPCHK(launch_power_reduce(part, nch, n, b, a, p, nb, q, dp, h->stream));
+            HIPCHK(launch_lag_matvec(K, m, Rf, a, p, nb, part, ls));
+            HIPCHK(launch_power_reduce(part, nch, n, b, a, p, nb, q, dp, ls));
             std::swap(a, b);
             std::swap(p, q);
         }
-        if (n_power > 0) HIPCHK(launch_power_final(p, dp, nb, sc + SC_LAM, h->stream));
+        if (n_power > 0) HIPCHK(launch_power_final(p, dp, nb, sc + SC_LAM, ls));
         return CSC_OK;
     };
-    if (h->graphs && n_power > 0) {
+    if (h->graphs && n_power > 0 && own) {
         const std::vector<uintptr_t> key = {(uintptr_t)K, (uintptr_t)m, (uintptr_t)n_power, (uintptr_t)Rf,
                                             (uintptr_t)wa, (uintptr_t)wb, (uintptr_t)part, (uintptr_t)np,
                                             (uintptr_t)sc};
@@ -766,6 +780,12 @@ extern "C" int csc_destroy(csc_handle h) {
         hipStreamSynchronize(h->graph_stream);
         hipStreamDestroy(h->graph_stream);
     }
+    if (h->side) {
+        hipStreamSynchronize(h->side);
+        hipStreamDestroy(h->side);
+    }
+    for (auto e : h->side_ev)
+        if (e) hipEventDestroy(e);
     for (auto e : h->graph_ev)
         if (e) hipEventDestroy(e);
     for (auto e : h->ev_pool) hipEventDestroy(e);
@@ -1194,6 +1214,24 @@ extern "C" int csc_code_step_admm(csc_handle h, const csc_images *im, const floa
 // capacities (offsets = prefix of the lengths), nz an upper bound of their
 // total, xp the entries tagged for the lag pass (row stride lag_rows_stride)
 // when that pass runs.  The arguments are checked and the geometry is set.
+// The handle's side stream and its events, created on first use; null (and the
+// caller runs everything in order on the handle's stream) if they cannot be made.
+static hipStream_t side_stream(csc_ctx *h) {
+    if (h->side || h->side_failed) return h->side;
+    bool ok = hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) == hipSuccess;
+    for (auto &e : h->side_ev) ok = ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+        hipGetLastError();
+        if (h->side) hipStreamDestroy(h->side);
+        for (auto &e : h->side_ev)
+            if (e) hipEventDestroy(e);
+        h->side = nullptr;
+        for (auto &e : h->side_ev) e = nullptr;
+        h->side_failed = true;
+    }
+    return h->side;
+}
+
 static int dict_step_lists(csc_ctx *h, const float *x, const uint8_t *W, Lists L, unsigned long long nz, const XPair *xp,
                     float *d, int K, int m, csc_surrogate *sur, int n_iter, double step, int n_power, int precision,
                     double *L_d_out) {
@@ -1205,6 +1243,34 @@ static int dict_step_lists(csc_ctx *h, const float *x, const uint8_t *W, Lists L
     FmLists F;
     if ((st = build_fm_lists(h, K, L, nz, &F))) return st;
     WS(sc, double, WS_SCAL, SC_COUNT);
+    // Online without an observation mask, the increment of B_bar, the corner-ring
+    // products and the power iteration for L_d do not depend on what runs beside
+    // them: on the side stream, B_bar and the corner products run while the lag
+    // sums form, and the power iteration beside the expansion of C_bar.  (In order
+    // on the handle's stream when graphs or per-kernel timing are on.)
+    hipStream_t side = (sur && lag_pass && n_power > 0 && !h->graphs && !h->prof) ? side_stream(h) : nullptr;
+    const int M_ = M;
+    auto b_increment = [&](hipStream_t s) -> int {
+        const int nch = corr_chunks(K);
+        WS(part, double, WS_CPART, (size_t)nch * K * M_);
+        PROF(CSC_PK_CORR);
+        HIPCHK(launch_corr_fm(g, K, m, F.off, F.codes, x, W, true, part, s));
+        HIPCHK(launch_reduce_partials_f64_add(part, nch, K * M_, sur->B, s));
+        return CSC_OK;
+    };
+    // the corner-ring products go into C_bar with atomics, before its expansion
+    auto corner = [&](hipStream_t s) -> int {
+        PROF(CSC_PK_SUR_CORNER);
+        HIPCHK(launch_surrogate_corner(g, K, m, L, sur->C, s));
+        return CSC_OK;
+    };
+    if (side) {
+        HIPCHK(hipEventRecord(h->side_ev[0], h->stream));
+        HIPCHK(hipStreamWaitEvent(side, h->side_ev[0], 0));
+        if ((st = b_increment(side))) return st;
+        if ((st = corner(side))) return st;
+        HIPCHK(hipEventRecord(h->side_ev[3], side));
+    }
     // Without an observation mask the lag sums R of the batch give both the
     // surrogate increment and the zero-padded normal matrix used for L_d.
     double *Rl = nullptr, *Es = nullptr;
@@ -1223,8 +1289,15 @@ static int dict_step_lists(csc_ctx *h, const float *x, const uint8_t *W, Lists L
         HIPCHK(launch_surrogate_lag(g, K, m, L, xp, F.off, F.codes, lpart, Rl, Es, h->stream));
     }
     if (need_ld) {
-        if (W) st = power_iteration(h, K, m, L, F, W, n_power, precision);
-        else st = power_iteration_lag(h, K, m, Rl, n_power);
+        if (W) {
+            st = power_iteration(h, K, m, L, F, W, n_power, precision);
+        } else if (side) {
+            HIPCHK(hipEventRecord(h->side_ev[1], h->stream));  // the lag sums are formed
+            HIPCHK(hipStreamWaitEvent(side, h->side_ev[1], 0));
+            st = power_iteration_lag(h, K, m, Rl, n_power, side);
+        } else {
+            st = power_iteration_lag(h, K, m, Rl, n_power, h->stream);
+        }
         if (st) return st;
     }
     double Ld = 0.0;
@@ -1268,9 +1341,10 @@ static int dict_step_lists(csc_ctx *h, const float *x, const uint8_t *W, Lists L
         } else {
             WS(tab, unsigned short, WS_TAB, (size_t)M * M);
             WS(mvpart, double, WS_PART, surrogate_matvec_partial_elems(K, m));
-            {
-                PROF(CSC_PK_SUR_CORNER);
-                HIPCHK(launch_surrogate_corner(g, K, m, L, sur->C, h->stream));
+            if (side) {
+                HIPCHK(hipStreamWaitEvent(h->stream, h->side_ev[3], 0));  // the corner products are in
+            } else if ((st = corner(h->stream))) {
+                return st;
             }
             {
                 PROF(CSC_PK_SUR_EXPAND);
@@ -1278,12 +1352,11 @@ static int dict_step_lists(csc_ctx *h, const float *x, const uint8_t *W, Lists L
                                                h->stream));
             }
         }
-        {
-            const int nch = corr_chunks(K);
-            WS(part, double, WS_PART, (size_t)nch * K * M);
-            PROF(CSC_PK_CORR);
-            HIPCHK(launch_corr_fm(g, K, m, F.off, F.codes, x, W, true, part, h->stream));
-            HIPCHK(launch_reduce_partials_f64_add(part, nch, K * M, sur->B, h->stream));
+        if (side) {
+            HIPCHK(hipEventRecord(h->side_ev[2], side));  // B_bar and L_d are done
+            HIPCHK(hipStreamWaitEvent(h->stream, h->side_ev[2], 0));
+        } else if ((st = b_increment(h->stream))) {
+            return st;
         }
         if ((st = read_ld())) return st;
         const bool step_d = sur->Ld_sum + Ld > 0.0;
