@@ -52,37 +52,29 @@ PEAK_FP64_VECTOR = 78.6e12
 PEAK_BF16_MFMA = 2.5e15
 PEAK_HBM = 8.0e12
 
-# HBM bytes per launch of each kernel class's main kernel on the online workload, from
-# rocprofv3 FETCH_SIZE / WRITE_SIZE passes scaled by a 512 MiB copy (read x 2.000, write x 1.000),
-# valid only for the kernel source they were taken on (first 16 hex digits of its SHA-256).
-# Keyed by (kernel class, precision).
+# HBM bytes per launch of each kernel class's main kernel, from rocprofv3 FETCH_SIZE / WRITE_SIZE
+# passes scaled by a 512 MiB copy (read x 2.000, write x 1.000), valid only for the kernel source
+# they were taken on (first 16 hex digits of its SHA-256).  Keyed by (workload, kernel class,
+# precision): (source, digest, bytes read, bytes written).
 TRAFFIC = {
-    ("synth", "bf16"): ("kernels_mfma.hip", "16ec6e23e6f32e19", 43.33e6, 1.02e6),
-    ("adjoint", "bf16"): ("kernels_code.hip", "5513de82161f2941", 34.15e6, 11.07e6),
-    ("corr", "bf16"): ("kernels_dict.hip", "0bf8d154ab50cc41", 27.00e6, 4.07e6),
-    ("sur_expand", "bf16"): ("kernels_sur.hip", "d1aa18db8753e5f7", 732.41e6, 603.92e6),
-    ("power", "bf16"): ("kernels_sur.hip", "d1aa18db8753e5f7", 18.21e6, 0.69e6),
-    ("synth", "fp32"): ("kernels_code.hip", "5513de82161f2941", 18.08e6, 0.80e6),
-    ("adjoint", "fp32"): ("kernels_code.hip", "5513de82161f2941", 20.94e6, 10.64e6),
-    ("corr", "fp32"): ("kernels_dict.hip", "0bf8d154ab50cc41", 27.01e6, 4.07e6),
-    ("sur_expand", "fp32"): ("kernels_sur.hip", "d1aa18db8753e5f7", 732.41e6, 603.94e6),
-    ("power", "fp32"): ("kernels_sur.hip", "d1aa18db8753e5f7", 18.21e6, 0.69e6),
-}
-
-
-# The paper's own timings (end-to-end CPU wall times on a Core i7 PC with Matlab built-in
-# functions, ADMM code solver; no GPU figures, no precision stated).  Context, not the target.
-PAPER_REFERENCE = {
-    "hardware": "Core i7 PC, Matlab built-in functions (the mini-batch study single-core)",
-    "sbcsc_fruit": "10 images 100x100, K=100 filters 11x11, p=0.1: 170 s for 14 outer iterations of 10 ADMM "
-                   "iterations each (Heide et al. 2015: 350 s); per outer iteration about 6x faster than the "
-                   "non-subsampled spatial solver and about 2x faster than Fourier-domain ADMM",
-    "socsc_fruit": "the 10 training images, one per iteration: 70 s (Liu et al. 2018: 440 s)",
-    "minibatch": "1000 patches 100x100, K=400: mini-batches of 20 reach a comparable objective about 10x sooner "
-                 "than single images",
-    "derived_updates_per_s": 8.2e5,
-    "derived_note": "not printed in the paper: 1e6 sampled coordinates per outer iteration x 10 ADMM iterations "
-                    "x 14 outer iterations in 170 s, whole pipeline",
+    ("online", "synth", "bf16"): ("kernels_mfma.hip", "16ec6e23e6f32e19", 43.44e6, 1.024e6),
+    ("online", "adjoint", "bf16"): ("kernels_code.hip", "8d3470bde5b9f97f", 34.16e6, 11.07e6),
+    ("online", "corr", "bf16"): ("kernels_dict.hip", "0bf8d154ab50cc41", 27.01e6, 4.067e6),
+    ("online", "sur_expand", "bf16"): ("kernels_sur.hip", "4242b143181c9d61", 732.5e6, 603.9e6),
+    ("online", "power", "bf16"): ("kernels_sur.hip", "4242b143181c9d61", 18.21e6, 0.6944e6),
+    ("online", "synth", "fp32"): ("kernels_code.hip", "8d3470bde5b9f97f", 18.08e6, 0.8023e6),
+    ("online", "adjoint", "fp32"): ("kernels_code.hip", "8d3470bde5b9f97f", 20.94e6, 10.63e6),
+    ("online", "corr", "fp32"): ("kernels_dict.hip", "0bf8d154ab50cc41", 27.01e6, 4.067e6),
+    ("online", "sur_expand", "fp32"): ("kernels_sur.hip", "4242b143181c9d61", 732.7e6, 603.9e6),
+    ("online", "power", "fp32"): ("kernels_sur.hip", "4242b143181c9d61", 18.21e6, 0.6944e6),
+    ("ragged", "synth", "bf16"): ("kernels_mfma.hip", "16ec6e23e6f32e19", 4998e6, 119.9e6),
+    ("ragged", "adjoint", "bf16"): ("kernels_code.hip", "8d3470bde5b9f97f", 3570e6, 1439e6),
+    ("ragged", "gather", "bf16"): ("kernels_code.hip", "8d3470bde5b9f97f", 9798e6, 184.7e6),
+    ("ragged", "scatter", "bf16"): ("kernels_code.hip", "8d3470bde5b9f97f", 1920e6, 8766e6),
+    ("ragged", "synth", "fp32"): ("kernels_code.hip", "8d3470bde5b9f97f", 3534e6, 129.3e6),
+    ("ragged", "adjoint", "fp32"): ("kernels_code.hip", "8d3470bde5b9f97f", 2225e6, 1404e6),
+    ("ragged", "gather", "fp32"): ("kernels_code.hip", "8d3470bde5b9f97f", 9798e6, 184.7e6),
+    ("ragged", "scatter", "fp32"): ("kernels_code.hip", "8d3470bde5b9f97f", 1920e6, 8765e6),
 }
 
 
@@ -90,9 +82,10 @@ def traffic_for(cls, workload, precision):
     """Calibrated HBM bytes per launch, or None when the kernel changed since the counters were taken."""
     import hashlib
 
-    if workload != "online" or (cls, precision) not in TRAFFIC:
+    key = (workload, cls, precision)
+    if key not in TRAFFIC:
         return None
-    src, sha, rd, wr = TRAFFIC[(cls, precision)]
+    src, sha, rd, wr = TRAFFIC[key]
     path = os.path.join(ROOT, "paper_1909_00145_amd", "csrc", src)
     try:
         cur = hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
