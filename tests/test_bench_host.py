@@ -1,0 +1,28 @@
+"""Host-side checks of bench.py (no GPU): the module loads with its tables, the
+traffic table names sources that exist, and more than one GPU is refused."""
+
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_bench_module_tables():
+    sys.path.insert(0, ROOT)
+    import bench
+
+    assert bench.PAPER_REFERENCE["derived_updates_per_s"] > 0
+    for (wl, cls, prec), (src, sha, rd, wr) in bench.TRAFFIC.items():
+        assert wl in bench.WORKLOADS and prec in ("bf16", "fp32")
+        assert os.path.exists(os.path.join(ROOT, "paper_1909_00145_amd", "csrc", src))
+        assert len(sha) == 16 and rd > 0 and wr > 0
+    for name in ("time_to_objective", "tto_study", "ragged_leg", "unrolled_leg", "cpu_baseline", "rooflines"):
+        assert callable(getattr(bench, name))
+
+
+def test_bench_refuses_more_than_one_gpu():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
