@@ -1246,8 +1246,9 @@ static int dict_step_lists(csc_ctx *h, const float *x, const uint8_t *W, Lists L
     // Online without an observation mask, the increment of B_bar, the corner-ring
     // products and the power iteration for L_d do not depend on what runs beside
     // them: on the side stream, B_bar and the corner products run while the lag
-    // sums form, and the power iteration beside the expansion of C_bar.  (In order
-    // on the handle's stream when graphs or per-kernel timing are on.)
+    // sums form, and the power iteration (from R, once formed) beside the band sums
+    // and the expansion of C_bar.  (In order on the handle's stream when graphs or
+    // per-kernel timing are on.)
     hipStream_t side = (sur && lag_pass && n_power > 0 && !h->graphs && !h->prof) ? side_stream(h) : nullptr;
     const int M_ = M;
     auto b_increment = [&](hipStream_t s) -> int {
@@ -1264,13 +1265,7 @@ static int dict_step_lists(csc_ctx *h, const float *x, const uint8_t *W, Lists L
         HIPCHK(launch_surrogate_corner(g, K, m, L, sur->C, s));
         return CSC_OK;
     };
-    if (side) {
-        HIPCHK(hipEventRecord(h->side_ev[0], h->stream));
-        HIPCHK(hipStreamWaitEvent(side, h->side_ev[0], 0));
-        if ((st = b_increment(side))) return st;
-        if ((st = corner(side))) return st;
-        HIPCHK(hipEventRecord(h->side_ev[3], side));
-    }
+    if (side) HIPCHK(hipEventRecord(h->side_ev[0], h->stream));  // the lists are built
     // Without an observation mask the lag sums R of the batch give both the
     // surrogate increment and the zero-padded normal matrix used for L_d.
     double *Rl = nullptr, *Es = nullptr;
@@ -1286,18 +1281,21 @@ static int dict_step_lists(csc_ctx *h, const float *x, const uint8_t *W, Lists L
         }
         WS(lpart, double, WS_LAGPART, surrogate_lag_part_elems(g, K, m));
         PROF(CSC_PK_SUR_LAG);
-        HIPCHK(launch_surrogate_lag(g, K, m, L, xp, F.off, F.codes, lpart, Rl, Es, h->stream));
+        // with the side stream, side_ev[1] marks R formed (before the band sums)
+        HIPCHK(launch_surrogate_lag(g, K, m, L, xp, F.off, F.codes, lpart, Rl, Es, side ? h->side_ev[1] : nullptr,
+                                    h->stream));
     }
-    if (need_ld) {
-        if (W) {
-            st = power_iteration(h, K, m, L, F, W, n_power, precision);
-        } else if (side) {
-            HIPCHK(hipEventRecord(h->side_ev[1], h->stream));  // the lag sums are formed
-            HIPCHK(hipStreamWaitEvent(side, h->side_ev[1], 0));
-            st = power_iteration_lag(h, K, m, Rl, n_power, side);
-        } else {
-            st = power_iteration_lag(h, K, m, Rl, n_power, h->stream);
-        }
+    // The host queues the launches that the handle's stream runs next before the
+    // side stream's run of small power-iteration launches.
+    if (side) {
+        HIPCHK(hipStreamWaitEvent(side, h->side_ev[0], 0));
+        if ((st = b_increment(side))) return st;
+        if ((st = corner(side))) return st;
+        HIPCHK(hipEventRecord(h->side_ev[3], side));
+    }
+    if (need_ld && !side) {
+        if (W) st = power_iteration(h, K, m, L, F, W, n_power, precision);
+        else st = power_iteration_lag(h, K, m, Rl, n_power, h->stream);
         if (st) return st;
     }
     double Ld = 0.0;
@@ -1353,6 +1351,8 @@ static int dict_step_lists(csc_ctx *h, const float *x, const uint8_t *W, Lists L
             }
         }
         if (side) {
+            HIPCHK(hipStreamWaitEvent(side, h->side_ev[1], 0));  // R is formed
+            if ((st = power_iteration_lag(h, K, m, Rl, n_power, side))) return st;
             HIPCHK(hipEventRecord(h->side_ev[2], side));  // B_bar and L_d are done
             HIPCHK(hipStreamWaitEvent(h->stream, h->side_ev[2], 0));
         } else if ((st = b_increment(h->stream))) {

@@ -598,6 +598,16 @@ __global__ __launch_bounds__(LR_THREADS, 8) void k_lag_rows(const ImgInfo *__res
 // RM_KB partner filters); thread (k2, tap row s_y) keeps the m outputs of its row
 // in registers and reads each lag row once per s2_y; the partner filters are then
 // summed in a fixed order.
+// Sum of a[0, n) by the 64 lanes of the first wave: lane l adds a[l], a[l + 64], ...
+// in order, then a fixed butterfly; every lane ends with the same total.
+__device__ __forceinline__ double wave_sum_strided(const double *__restrict__ a, int n) {
+    double t = 0.0;
+    for (int i = threadIdx.x; i < n; i += 64) t += a[i];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+    return t;
+}
+
 constexpr int RM_KB = 16;
 constexpr int RM_LB = 48;  // loads in flight per thread (RM_KB LL / threads for m = 11: one round trip)
 
@@ -612,10 +622,9 @@ __global__ __launch_bounds__(MM *RM_KB) void k_lag_matvec(int K, const float *__
     __shared__ double inv_s;
     const int k = blockIdx.x, ch = blockIdx.y;
     const int k2lo = ch * RM_KB, nk = min(RM_KB, K - k2lo);
-    if (threadIdx.x == 0) {
-        double nn = 0.0;
-        for (int i = 0; i < n_nparts; ++i) nn += nparts[i];
-        inv_s = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
+    if (threadIdx.x < 64) {
+        const double nn = wave_sum_strided(nparts, n_nparts);
+        if (threadIdx.x == 0) inv_s = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
     }
     const float *src = Rf + ((long long)k * K + k2lo) * LL;
     const int nr = nk * LL;
@@ -697,10 +706,9 @@ __global__ __launch_bounds__(PR_THREADS) void k_power_reduce(const double *__res
                                                              double *__restrict__ nparts_out,
                                                              double *__restrict__ dparts_out) {
     __shared__ double inv_s, rn[PR_THREADS], rd[PR_THREADS];
-    if (threadIdx.x == 0) {
-        double nn = 0.0;
-        for (int i = 0; i < n_nparts; ++i) nn += nparts_prev[i];
-        inv_s = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
+    if (threadIdx.x < 64) {
+        const double nn = wave_sum_strided(nparts_prev, n_nparts);
+        if (threadIdx.x == 0) inv_s = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
     }
     __syncthreads();
     const int i = blockIdx.x * PR_THREADS + threadIdx.x;
@@ -749,7 +757,10 @@ __global__ void k_power_final(const double *__restrict__ nparts, const double *_
 
 // C_bar(k, k2) += R - E_top - E_bottom - E_left - E_right for every stored block
 // k <= k2 (one workgroup per block, blockIdx.x = its upper-triangle index).
-// Each workgroup reads and writes its own block with coalesced accesses.
+// Each workgroup reads and writes its own block with coalesced accesses.  C_bar is
+// streamed with non-temporal loads and stores (each entry is touched once per
+// mini-batch), so that it does not evict the lag sums that the power iteration
+// beside it reads 20 times.
 constexpr int EX_THREADS = 512;
 constexpr int EX_BATCH = 16;
 
@@ -843,14 +854,14 @@ __global__ __launch_bounds__(EX_THREADS) void k_sur_expand(int K, const double *
 #pragma unroll
         for (int u = 0; u < EX_BATCH; ++u) {
             const int i = i0 + u * EX_THREADS;
-            old[u] = i < M2 ? blk[i] : 0.0;
+            old[u] = i < M2 ? __builtin_nontemporal_load(&blk[i]) : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < EX_BATCH; ++u) {
             const int i = i0 + u * EX_THREADS;
             if (i >= M2) continue;
             const double nv = old[u] + val[u];
-            blk[i] = nv;
+            __builtin_nontemporal_store(nv, &blk[i]);
             if (d) {
                 // entry (k, s; k2, s2 = s - delta): row k gets C d_k2, row k2 gets C^T d_k
                 atomicAdd(&ya[si[u]], nv * dkb[s2i[u]]);
@@ -1084,7 +1095,7 @@ unsigned lag_rows_impl(const Geometry &g, int K) {
 
 template <int MM>
 hipError_t sur_lag_impl(const Geometry &g, int K, Lists z, const XPair *xp, const unsigned *fm_off,
-                        const FmCode *fm, double *part, double *Rl, double *Es, hipStream_t s) {
+                        const FmCode *fm, double *part, double *Rl, double *Es, hipEvent_t sums_done, hipStream_t s) {
     constexpr int Cc = MM / 2, L = 2 * MM - 1, LL = L * L;
     const LagPlan pl = lag_plan<MM>(g, K);
     const size_t shm = sizeof(double) * (size_t)pl.KC * K;
@@ -1105,6 +1116,7 @@ hipError_t sur_lag_impl(const Geometry &g, int K, Lists z, const XPair *xp, cons
     const unsigned nt = (unsigned)((K + LS_T - 1) / LS_T);
     hipLaunchKernelGGL(k_lag_sum<MM>, dim3(pl.nlag, nt, nt), dim3(256), 0, s, K, nparts, part, Rl);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (sums_done && (e = hipEventRecord(sums_done, s)) != hipSuccess) return e;
     if (Cc > 0 && Es) {
         hipLaunchKernelGGL(k_lag_outer<MM>, dim3(LL, pl.nkc, 4 * Cc), dim3(LO_THREADS), shm, s, g.d_img, g.n_img,
                            (long long)g.n_pix, g.max_side, K, z, 1, pl.KC, Es);
@@ -1185,8 +1197,9 @@ unsigned lag_rows_stride(const Geometry &g, int K, int m) {
 }
 
 hipError_t launch_surrogate_lag(const Geometry &g, int K, int m, Lists z, const XPair *xp, const unsigned *fm_off,
-                                const FmCode *fm, double *part, double *Rl, double *Es, hipStream_t s) {
-    SCSC_DISPATCH_M(m, sur_lag_impl, g, K, z, xp, fm_off, fm, part, Rl, Es, s);
+                                const FmCode *fm, double *part, double *Rl, double *Es, hipEvent_t sums_done,
+                                hipStream_t s) {
+    SCSC_DISPATCH_M(m, sur_lag_impl, g, K, z, xp, fm_off, fm, part, Rl, Es, sums_done, s);
 }
 
 hipError_t launch_surrogate_expand(int K, int m, const double *Rl, const double *Es, unsigned short *tab, double *C,

@@ -365,12 +365,14 @@ hipError_t launch_surrogate_blocks(const Geometry &g, int K, int m, const unsign
 // part: surrogate_lag_part_elems doubles of workspace (per-chunk partial sums).
 // With xp (the entries of z tagged for row stride lag_rows_stride) and the
 // per-filter lists, the lags delta >= 0 are summed by filter-major runs, else by
-// pixel slots.
+// pixel slots.  sums_done (may be null) is recorded on s once R is formed, before
+// the band sums.
 long long surrogate_lag_elems(int K, int m);
 long long surrogate_lag_part_elems(const Geometry &g, int K, int m);
 unsigned lag_rows_stride(const Geometry &g, int K, int m);  // 0: the run pass does not apply
 hipError_t launch_surrogate_lag(const Geometry &g, int K, int m, Lists z, const XPair *xp, const unsigned *fm_off,
-                                const FmCode *fm, double *part, double *Rl, double *Es, hipStream_t s);
+                                const FmCode *fm, double *part, double *Rl, double *Es, hipEvent_t sums_done,
+                                hipStream_t s);
 // Power iteration on the zero-padded normal matrix given by the lag sums.
 // Rf = the lag sums rounded to FP32 (a step-size estimate needs no more), in
 // [k][k2][lag] order (launch_lag_to_f32).  The matvec multiplies v = w / ||w||,
