@@ -848,6 +848,24 @@ struct CodeStepFused {
     double Lz = 0.0, eta = 0.0;     // out
 };
 
+// The handle's side stream and its events, created on first use; null (and the
+// caller runs everything in order on the handle's stream) if they cannot be made.
+static hipStream_t side_stream(csc_ctx *h) {
+    if (h->side || h->side_failed) return h->side;
+    bool ok = hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) == hipSuccess;
+    for (auto &e : h->side_ev) ok = ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+        hipGetLastError();
+        if (h->side) hipStreamDestroy(h->side);
+        for (auto &e : h->side_ev)
+            if (e) hipEventDestroy(e);
+        h->side = nullptr;
+        for (auto &e : h->side_ev) e = nullptr;
+        h->side_failed = true;
+    }
+    return h->side;
+}
+
 // The code update of csc_code_step; hold: the unselected coordinates keep their
 // values (csc_code_step_hold).  Their codes enter every residual through
 // x_eff = x - D z_held, formed once, and only the sample is written back.
@@ -1017,7 +1035,46 @@ int code_step_impl(csc_ctx *h, const csc_images *im, const float *x, const uint8
         }
         return CSC_OK;
     };
-    if (use_graph) {
+    // BF16 with eager launches and a tuned synthesis: the two halves of the batch
+    // (split between images, which the iterations never couple) run on the
+    // handle's stream and its side stream, so that the kernels of one half fill
+    // the CUs that the other half's last workgroups leave idle.  Same kernels and
+    // tiles as one launch over the batch, so the same bits.
+    const auto skey = synth_key(h, K, m, SYNTH_RESIDUAL, precision);
+    hipStream_t hs = (!use_graph && !h->prof && precision == CSC_BF16 && n_iter > 0 && g.n_img >= 2 &&
+                      h->force_variant < 0 && tuned_variant(h, skey) >= 0)
+                         ? side_stream(h)
+                         : nullptr;
+    if (hs) {
+        Geometry half[2];
+        const int split = g.h_img[g.n_img / 2].tile_off;
+        for (Geometry &gh : half) {
+            gh.n_img = g.n_img;
+            gh.n_pix = g.n_pix;
+            gh.max_side = g.max_side;
+            gh.d_img = g.d_img;
+        }
+        half[0].d_tiles = g.d_tiles;
+        half[0].n_tiles = split;
+        half[1].d_tiles = g.d_tiles + split;
+        half[1].n_tiles = g.n_tiles - split;
+        const hipStream_t hstr[2] = {h->stream, hs};
+        const int v = tuned_variant(h, skey);
+        HIPCHK(hipEventRecord(h->side_ev[0], h->stream));
+        HIPCHK(hipStreamWaitEvent(hs, h->side_ev[0], 0));
+        int c = 0;
+        for (int it = 0; it < n_iter; ++it) {
+            for (int i = 0; i < 2; ++i)
+                HIPCHK(launch_synth_mfma(half[i], K, m, Lists{soff, nzc[c], pairs[c]}, sda, xi, Wi, R,
+                                         (int)SYNTH_RESIDUAL, v, hstr[i]));
+            for (int i = 0; i < 2; ++i)
+                HIPCHK(launch_adjoint_shrink_mfma(half[i], K, m, mw, soff, pairs[c], nzc[c], pairs[c ^ 1], nzc[c ^ 1],
+                                                  R, ada, ethr, nnzsum, hstr[i]));
+            c ^= 1;
+        }
+        HIPCHK(hipEventRecord(h->side_ev[3], hs));
+        HIPCHK(hipStreamWaitEvent(h->stream, h->side_ev[3], 0));
+    } else if (use_graph) {
         const std::vector<uintptr_t> key = {
             (uintptr_t)K, (uintptr_t)m, (uintptr_t)precision, (uintptr_t)n_iter, (uintptr_t)g.n_tiles,
             (uintptr_t)g.n_pix, (uintptr_t)(h->force_variant + 1), (uintptr_t)tuned_variant(h, synth_key(h, K, m, SYNTH_RESIDUAL, precision)),
@@ -1214,24 +1271,6 @@ extern "C" int csc_code_step_admm(csc_handle h, const csc_images *im, const floa
 // capacities (offsets = prefix of the lengths), nz an upper bound of their
 // total, xp the entries tagged for the lag pass (row stride lag_rows_stride)
 // when that pass runs.  The arguments are checked and the geometry is set.
-// The handle's side stream and its events, created on first use; null (and the
-// caller runs everything in order on the handle's stream) if they cannot be made.
-static hipStream_t side_stream(csc_ctx *h) {
-    if (h->side || h->side_failed) return h->side;
-    bool ok = hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) == hipSuccess;
-    for (auto &e : h->side_ev) ok = ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
-    if (!ok) {
-        hipGetLastError();
-        if (h->side) hipStreamDestroy(h->side);
-        for (auto &e : h->side_ev)
-            if (e) hipEventDestroy(e);
-        h->side = nullptr;
-        for (auto &e : h->side_ev) e = nullptr;
-        h->side_failed = true;
-    }
-    return h->side;
-}
-
 static int dict_step_lists(csc_ctx *h, const float *x, const uint8_t *W, Lists L, unsigned long long nz, const XPair *xp,
                     float *d, int K, int m, csc_surrogate *sur, int n_iter, double step, int n_power, int precision,
                     double *L_d_out) {
