@@ -51,6 +51,10 @@ PEAK_FP32_VECTOR = 157.3e12
 PEAK_FP64_VECTOR = 78.6e12
 PEAK_BF16_MFMA = 2.5e15
 PEAK_HBM = 8.0e12
+# LDS: 128 bytes per clock per CU (256 CUs, 2.4 GHz); one FP64 product of the lag pass is an
+# 8-byte atomic read-modify-write in LDS (8 bytes read, 8 written), so 8 products per clock per CU
+PEAK_LDS_BYTES = 256 * 2.4e9 * 128
+PEAK_LAG_PRODUCTS = PEAK_LDS_BYTES / 16
 
 # HBM bytes per launch of each kernel class's main kernel, from rocprofv3 FETCH_SIZE / WRITE_SIZE
 # passes scaled by a 512 MiB copy (read x 2.000, write x 1.000), valid only for the kernel source
@@ -638,6 +642,50 @@ def timed_run(ctx, wname, w, im, x, precision, graph, profile, warmup, steps):
     return r
 
 
+def lag_pairs(z, im, K, m):
+    """Products of the lag pass over codes z (packed [K][H][W] per image): every pair of a
+    non-zero code at pixel q and one at q + delta, for the lags delta = (dy, dx) with dy > 0,
+    or dy = 0 and dx >= 0, inside the window (|dx|, dy <= m - 1), both pixels in the image."""
+    import torch
+
+    r = m - 1
+    total = 0.0
+    base = 0
+    for H, Wd in im.hw:
+        H, Wd = int(H), int(Wd)
+        n = (z[base:base + K * H * Wd].view(K, H, Wd) != 0).sum(0).double()
+        base += K * H * Wd
+        for dy in range(0, min(r, H - 1) + 1):
+            for dx in range(-r, r + 1):
+                if (dy == 0 and dx < 0) or abs(dx) >= Wd:
+                    continue
+                xa, xb = max(0, -dx), Wd - max(0, dx)
+                total += float((n[0:H - dy, xa:xb] * n[dy:H, xa + dx:xb + dx]).sum())
+    return total
+
+
+def lag_pair_count(ctx, w, im, x, precision, warmup, steps):
+    """Products of the lag pass summed over the timed steps, from a replay of the same
+    online steps that writes every mini-batch's codes (the FP64 atomics of the surrogate
+    sums may round the filters differently in the last bit, so the count can differ from
+    the timed run's by the few codes that sit at the threshold)."""
+    import torch
+
+    import scsc_inputs as si
+    from paper_1909_00145_amd.drivers import OnlineLearner
+
+    K, m = w["K"], w["m"]
+    ctx.set_graph(False)
+    d = torch.from_numpy(si.filters(w["cfg"], K, m).astype(np.float32)).cuda()
+    learner = OnlineLearner(ctx, im, d, w["lam"], w["p"], n_code_iter=w["T"], precision=precision, keep_codes=True)
+    total = 0.0
+    for i in range(warmup + steps):
+        learner.step(x[i])
+        if i >= warmup:
+            total += lag_pairs(learner.z, im, K, m)
+    return total
+
+
 def rooflines(wname, w, im, precision, res, kernels, steps):
     """Roofline object of the dominant modelled kernel class and the fractions of all
     modelled classes, from the algorithmic work of the timed steps (res) and the
@@ -674,6 +722,10 @@ def rooflines(wname, w, im, precision, res, kernels, steps):
         # scatter: the K planes of z written once, the offsets and counts, and the list entries
         "scatter": ("hbm", (4.0 * K + 6.0) * im.n_pix * steps + 8.0 * nnz_dict, PEAK_HBM),
     }
+    if "lag_pairs" in res:
+        # one FP64 product (an 8-byte LDS atomic read-modify-write) per pair of non-zero codes at
+        # a lag of the half window; the class also holds the tiled sum and the band sums
+        work["sur_lag"] = ("lds", res["lag_pairs"], PEAK_LAG_PRODUCTS)
     # MFMA work the BF16 kernels execute per launch (dense tiles, padded shapes), 16x16x32 = 16384 flop
     executed = {}
     if bf16:
@@ -690,7 +742,9 @@ def rooflines(wname, w, im, precision, res, kernels, steps):
         work["synth"] = (mm_bound, 2 * M * (nnz_iter + nnz_dict), mm_peak)
     dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
     modelled = [k for k in kernels if k in work]
-    pick = dom if dom in work else max(modelled, key=lambda k: kernels[k]["total_ms"])
+    # the headline roofline stays on a kernel with a flop or byte model
+    headline = [k for k in modelled if work[k][0] != "lds"]
+    pick = dom if dom in headline else max(headline, key=lambda k: kernels[k]["total_ms"])
 
     def roof_of(k):
         bound, total_work, peak = work[k]
@@ -698,6 +752,9 @@ def rooflines(wname, w, im, precision, res, kernels, steps):
         per_launch = total_work / kernels[k]["launches"]
         if bound == "hbm":
             r = {"bound": "hbm", "achieved": per_launch / avg_s / 1e9, "peak": peak / 1e9, "unit": "GB/s"}
+        elif bound == "lds":
+            r = {"bound": "lds", "achieved": per_launch / avg_s / 1e9, "peak": peak / 1e9,
+                 "unit": "Gproducts/s"}
         else:
             r = {"bound": "alu" if bound == "alu64" else bound, "achieved": per_launch / avg_s / 1e12,
                  "peak": peak / 1e12, "unit": "TFLOP/s"}
@@ -719,7 +776,8 @@ def rooflines(wname, w, im, precision, res, kernels, steps):
     others = {}
     for k in modelled:
         r = roof_of(k)
-        others[k] = {key: r[key] for key in ("bound", "achieved", "unit", "frac", "traffic", "executed_mfma_frac")
+        others[k] = {key: r[key] for key in ("bound", "achieved", "peak", "unit", "frac", "per_launch_work",
+                                             "traffic", "executed_mfma_frac")
                      if key in r}
     return roof, others
 
@@ -863,6 +921,8 @@ def main():
     kernels = prof["kernels"]
     if (prof["sampled"], prof["nnz_iter"], prof["nnz_dict"]) != (res["sampled"], res["nnz_iter"], res["nnz_dict"]):
         raise RuntimeError("the profiled pass did not repeat the headline run's work")
+    if args.workload == "online":
+        res["lag_pairs"] = lag_pair_count(ctx, w, im, x, args.precision, args.warmup, args.steps)
 
     if args.copy_probe_mb > 0:
         nb = args.copy_probe_mb << 20

@@ -26,3 +26,29 @@ def test_bench_refuses_more_than_one_gpu():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_lag_pair_count_matches_brute_force():
+    """The lag pass's product count, against a loop over every pair of non-zero codes."""
+    sys.path.insert(0, ROOT)
+    import numpy as np
+    import torch
+
+    import bench
+
+    class Im:
+        hw = [(9, 13), (6, 4)]
+
+    K, m = 3, 5
+    rng = np.random.default_rng(4)
+    parts = [(rng.standard_normal((K, H, W)) * (rng.random((K, H, W)) < 0.3)).astype(np.float32) for H, W in Im.hw]
+    z = torch.from_numpy(np.concatenate([p.ravel() for p in parts]))
+    want = 0
+    for p in parts:
+        nz = list(zip(*np.nonzero(p)))
+        for (_, y, x) in nz:
+            for (_, y2, x2) in nz:
+                dy, dx = y2 - y, x2 - x
+                if 0 <= dy <= m - 1 and abs(dx) <= m - 1 and (dy > 0 or dx >= 0):
+                    want += 1
+    assert bench.lag_pairs(z, Im, K, m) == want
