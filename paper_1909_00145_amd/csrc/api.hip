@@ -205,7 +205,7 @@ struct ProfScope {
     } while (0)
 
 // Kernels with several launch variants that compute bit-identical results.
-enum TunedKernel { TK_SYNTH = 0, TK_SYNTH_BF16 = 1 };
+enum TunedKernel { TK_SYNTH = 0, TK_SYNTH_BF16 = 1, TK_SPLIT_BF16 = 2 };
 
 int ilog2(long long v) {
     int r = 0;
@@ -1026,7 +1026,7 @@ int code_step_impl(csc_ctx *h, const csc_images *im, const float *x, const uint8
                 PROF(CSC_PK_ADJOINT);
                 if (precision == CSC_BF16)
                     HIPCHK(launch_adjoint_shrink_mfma(g, K, m, mw, soff, pairs[c], nzc[c], pairs[c ^ 1], nzc[c ^ 1],
-                                                      R, ada, ethr, nnzsum, h->stream));
+                                                      R, ada, ethr, nnzsum, 0, h->stream));
                 else
                     HIPCHK(launch_adjoint_shrink(g, K, m, mw, soff, pairs[c], nzc[c], pairs[c ^ 1], nzc[c ^ 1], R,
                                                  di, ethr, nnzsum, h->stream));
@@ -1039,7 +1039,11 @@ int code_step_impl(csc_ctx *h, const csc_images *im, const float *x, const uint8
     // (split between images, which the iterations never couple) run on the
     // handle's stream and its side stream, so that the kernels of one half fill
     // the CUs that the other half's last workgroups leave idle.  Same kernels and
-    // tiles as one launch over the batch, so the same bits.
+    // tiles as one launch over the batch, so the same bits.  Which synthesis and
+    // adjoint variants run best beside each other is tuned on a whole iteration
+    // (variant index = 2 * synthesis variant + adjoint variant), once the first
+    // split call has run its iterations: the timed iterations repeat the last one
+    // from the same lists without the non-zero count, which rewrites the same bits.
     const auto skey = synth_key(h, K, m, SYNTH_RESIDUAL, precision);
     hipStream_t hs = (!use_graph && !h->prof && precision == CSC_BF16 && n_iter > 0 && g.n_img >= 2 &&
                       h->force_variant < 0 && tuned_variant(h, skey) >= 0)
@@ -1059,21 +1063,41 @@ int code_step_impl(csc_ctx *h, const csc_images *im, const float *x, const uint8
         half[1].d_tiles = g.d_tiles + split;
         half[1].n_tiles = g.n_tiles - split;
         const hipStream_t hstr[2] = {h->stream, hs};
-        const int v = tuned_variant(h, skey);
-        HIPCHK(hipEventRecord(h->side_ev[0], h->stream));
-        HIPCHK(hipStreamWaitEvent(hs, h->side_ev[0], 0));
+        const std::array<int, 5> ikey = {TK_SPLIT_BF16, m, K, ilog2(g.n_pix), 0};
+        // one iteration on both streams from lists c; acc: the non-zero count, or null
+        auto iteration = [&](int vi, int c, unsigned long long *acc) -> hipError_t {
+            hipError_t e = hipSuccess;
+            for (int i = 0; i < 2 && e == hipSuccess; ++i)
+                e = launch_synth_mfma(half[i], K, m, Lists{soff, nzc[c], pairs[c]}, sda, xi, Wi, R,
+                                      (int)SYNTH_RESIDUAL, vi >> 1, hstr[i]);
+            for (int i = 0; i < 2 && e == hipSuccess; ++i)
+                e = launch_adjoint_shrink_mfma(half[i], K, m, mw, soff, pairs[c], nzc[c], pairs[c ^ 1], nzc[c ^ 1], R,
+                                               ada, ethr, acc, vi & 1, hstr[i]);
+            return e;
+        };
+        auto fork = [&]() -> hipError_t {
+            hipError_t e = hipEventRecord(h->side_ev[0], h->stream);
+            return e == hipSuccess ? hipStreamWaitEvent(hs, h->side_ev[0], 0) : e;
+        };
+        auto join = [&]() -> hipError_t {
+            hipError_t e = hipEventRecord(h->side_ev[3], hs);
+            return e == hipSuccess ? hipStreamWaitEvent(h->stream, h->side_ev[3], 0) : e;
+        };
+        const int tuned = tuned_variant(h, ikey);
+        const int vi = tuned >= 0 ? tuned : 2 * tuned_variant(h, skey);
+        HIPCHK(fork());
         int c = 0;
         for (int it = 0; it < n_iter; ++it) {
-            for (int i = 0; i < 2; ++i)
-                HIPCHK(launch_synth_mfma(half[i], K, m, Lists{soff, nzc[c], pairs[c]}, sda, xi, Wi, R,
-                                         (int)SYNTH_RESIDUAL, v, hstr[i]));
-            for (int i = 0; i < 2; ++i)
-                HIPCHK(launch_adjoint_shrink_mfma(half[i], K, m, mw, soff, pairs[c], nzc[c], pairs[c ^ 1], nzc[c ^ 1],
-                                                  R, ada, ethr, nnzsum, hstr[i]));
+            HIPCHK(iteration(vi, c, nnzsum));
             c ^= 1;
         }
-        HIPCHK(hipEventRecord(h->side_ev[3], hs));
-        HIPCHK(hipStreamWaitEvent(h->stream, h->side_ev[3], 0));
+        HIPCHK(join());
+        if (tuned < 0 && h->autotune)
+            HIPCHK(tuned_launch(h, ikey, 4, [&](int v) -> hipError_t {
+                hipError_t e = fork();
+                if (e == hipSuccess) e = iteration(v, c ^ 1, nullptr);
+                return e == hipSuccess ? join() : e;
+            }));
     } else if (use_graph) {
         const std::vector<uintptr_t> key = {
             (uintptr_t)K, (uintptr_t)m, (uintptr_t)precision, (uintptr_t)n_iter, (uintptr_t)g.n_tiles,

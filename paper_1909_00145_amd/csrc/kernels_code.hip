@@ -710,7 +710,10 @@ __global__ __launch_bounds__(TPB) void k_adjoint_shrink(const ImgInfo *imgs, con
 // epilogue as the FP32 kernel (u = z + eta g, shrink, new lists) reads it there.
 // The filters come prepared as dA[k][32 ceil(m^2 / 32)] (BF16, taps zero padded,
 // rows padded to a multiple of 32 with zeros), so every lane loads its operand
-// fragments directly, one chunk ahead.
+// fragments directly.  Two variants with the same arithmetic: PF loads the next
+// chunk's operand fragments during the current chunk (204 registers, two
+// workgroups per CU); without PF they load at the chunk's start (168 registers,
+// three workgroups per CU), which runs better beside other kernels.
 // Fragment layout of the 16x16x32 instruction (lane l, element i):
 //   A: row l % 16, k 8 (l / 16) + i;  B: k 8 (l / 16) + i, column l % 16;
 //   D: row 4 (l / 16) + i, column l % 16.
@@ -728,8 +731,8 @@ __global__ void k_adj_prep_a(const float *__restrict__ d, int K, int Kp, __bf16 
     }
 }
 
-template <int MM>
-__global__ __launch_bounds__(TPB) void k_adjoint_shrink_mfma(const ImgInfo *imgs, const TileInfo *tiles, int K,
+template <int MM, bool PF>
+__global__ __launch_bounds__(TPB, PF ? 1 : 3) void k_adjoint_shrink_mfma(const ImgInfo *imgs, const TileInfo *tiles, int K,
                                                              long long n_pix, const unsigned *__restrict__ mask_words,
                                                              const unsigned *__restrict__ soff,
                                                              const Pair *__restrict__ oldp,
@@ -791,22 +794,31 @@ __global__ __launch_bounds__(TPB) void k_adjoint_shrink_mfma(const ImgInfo *imgs
     // operand A of a chunk: rows k0 + 16 rt + fcol, K-dim 32 ks + 8 (lane / 16)
     const bf16x8 *dA8 = reinterpret_cast<const bf16x8 *>(dA) + (long long)fcol * (MP / 8) + (lane >> 4);
     bf16x8 afr[2][NKS], afn[2][NKS];
-#pragma unroll
-    for (int rt = 0; rt < 2; ++rt)
-#pragma unroll
-        for (int ks = 0; ks < NKS; ++ks) afn[rt][ks] = dA8[(long long)(rt * 16) * (MP / 8) + ks * 4];
-    for (int k0 = 0; k0 < K; k0 += MF_KB) {
-        const int nk = min(MF_KB, K - k0);
+    if constexpr (PF) {
 #pragma unroll
         for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
-            for (int ks = 0; ks < NKS; ++ks) afr[rt][ks] = afn[rt][ks];
-        if (k0 + MF_KB < K)  // the next chunk's operands load during this chunk
+            for (int ks = 0; ks < NKS; ++ks) afn[rt][ks] = dA8[(long long)(rt * 16) * (MP / 8) + ks * 4];
+    }
+    for (int k0 = 0; k0 < K; k0 += MF_KB) {
+        const int nk = min(MF_KB, K - k0);
+        if constexpr (PF) {
 #pragma unroll
             for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
-                for (int ks = 0; ks < NKS; ++ks)
-                    afn[rt][ks] = dA8[(long long)(k0 + MF_KB + rt * 16) * (MP / 8) + ks * 4];
+                for (int ks = 0; ks < NKS; ++ks) afr[rt][ks] = afn[rt][ks];
+            if (k0 + MF_KB < K)  // the next chunk's operands load during this chunk
+#pragma unroll
+                for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+                    for (int ks = 0; ks < NKS; ++ks)
+                        afn[rt][ks] = dA8[(long long)(k0 + MF_KB + rt * 16) * (MP / 8) + ks * 4];
+        } else {
+#pragma unroll
+            for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+                for (int ks = 0; ks < NKS; ++ks) afr[rt][ks] = dA8[(long long)(k0 + rt * 16) * (MP / 8) + ks * 4];
+        }
         __syncthreads();  // the previous chunk's epilogue is done with gc
 #pragma unroll
         for (int rt = 0; rt < 2; ++rt) {
@@ -1141,9 +1153,13 @@ template <int MM>
 hipError_t adjoint_shrink_mfma_impl(const Geometry &g, int K, const unsigned *mw, const unsigned *soff,
                                     const Pair *oldp, const unsigned short *oldc, Pair *newp, unsigned short *newc,
                                     const float *r, const __bf16 *dA, const float *ethr,
-                                    unsigned long long *nnz_acc, hipStream_t s) {
-    hipLaunchKernelGGL(k_adjoint_shrink_mfma<MM>, dim3(g.n_tiles), dim3(TPB), 0, s, g.d_img, g.d_tiles, K, g.n_pix,
-                       mw, soff, oldp, oldc, newp, newc, r, dA, ethr, nnz_acc);
+                                    unsigned long long *nnz_acc, int variant, hipStream_t s) {
+    if (variant == 0)
+        hipLaunchKernelGGL((k_adjoint_shrink_mfma<MM, true>), dim3(g.n_tiles), dim3(TPB), 0, s, g.d_img, g.d_tiles, K,
+                           g.n_pix, mw, soff, oldp, oldc, newp, newc, r, dA, ethr, nnz_acc);
+    else
+        hipLaunchKernelGGL((k_adjoint_shrink_mfma<MM, false>), dim3(g.n_tiles), dim3(TPB), 0, s, g.d_img, g.d_tiles,
+                           K, g.n_pix, mw, soff, oldp, oldc, newp, newc, r, dA, ethr, nnz_acc);
     return hipGetLastError();
 }
 
@@ -1202,9 +1218,9 @@ hipError_t launch_adj_prep(const float *d, int K, int m, __bf16 *dA, hipStream_t
 hipError_t launch_adjoint_shrink_mfma(const Geometry &g, int K, int m, const unsigned *mask_words,
                                       const unsigned *soff, const Pair *old_pairs, const unsigned short *old_cnt,
                                       Pair *new_pairs, unsigned short *new_cnt, const float *r, const __bf16 *dA,
-                                      const float *ethr, unsigned long long *nnz_acc, hipStream_t s) {
+                                      const float *ethr, unsigned long long *nnz_acc, int variant, hipStream_t s) {
     SCSC_DISPATCH_M(m, adjoint_shrink_mfma_impl, g, K, mask_words, soff, old_pairs, old_cnt, new_pairs, new_cnt, r,
-                    dA, ethr, nnz_acc, s);
+                    dA, ethr, nnz_acc, variant, s);
 }
 
 hipError_t launch_adjoint_dense(const Geometry &g, int K, int m, const float *r, const float *d, float *out,

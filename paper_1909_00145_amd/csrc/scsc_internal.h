@@ -269,10 +269,13 @@ hipError_t launch_synth(const Geometry &g, int K, int m, Lists z, const float *d
 // The filters enter as dA, written by launch_adj_prep (adj_prep_elems(K, m) elements).
 size_t adj_prep_elems(int K, int m);
 hipError_t launch_adj_prep(const float *d, int K, int m, __bf16 *dA, hipStream_t s);
+// variant 0: the next chunk's operands load during the current chunk (two
+// workgroups per CU); 1: at the chunk's start (three per CU).  Same bits.
+// nnz_acc may be null (the count of non-zeros is then not added).
 hipError_t launch_adjoint_shrink_mfma(const Geometry &g, int K, int m, const unsigned *mask_words,
                                       const unsigned *soff, const Pair *old_pairs, const unsigned short *old_cnt,
                                       Pair *new_pairs, unsigned short *new_cnt, const float *r, const __bf16 *dA,
-                                      const float *ethr, unsigned long long *nnz_acc, hipStream_t s);
+                                      const float *ethr, unsigned long long *nnz_acc, int variant, hipStream_t s);
 hipError_t launch_adjoint_shrink(const Geometry &g, int K, int m, const unsigned *mask_words,
                                  const unsigned *soff, const Pair *old_pairs, const unsigned short *old_cnt,
                                  Pair *new_pairs, unsigned short *new_cnt, const float *r, const float *d,
