@@ -1,5 +1,6 @@
 // C ABI of the gfx950 stochastic-CSC library: handle, workspaces, argument
 // validation, batch geometry, and the entry points declared in scsc.h.
+#include <algorithm>
 #include <array>
 #include <cmath>
 #include <cstdio>
@@ -129,6 +130,15 @@ struct csc_ctx {
     bool autotune = true;
     int force_variant = -1;
     std::map<std::array<int, 5>, int> tuned;
+    // the split code step's variants: the two best of a screening, confirmed on the
+    // next two whole split calls (their iteration loops timed with split_ev)
+    struct SplitTune {
+        int cand[2] = {-1, -1};
+        float ms[2] = {-1.f, -1.f};
+        int pending = -1;  // candidate whose call's events have not been read yet
+    };
+    std::map<std::array<int, 5>, SplitTune> split_tune;
+    hipEvent_t split_ev[2] = {nullptr, nullptr};
     // this device's copy of the fixed scratch array (csc_objective_noalloc), or null if
     // its address could not be obtained when the handle was created
     unsigned char *scratch = nullptr;
@@ -309,7 +319,7 @@ hipError_t synth(csc_ctx *h, int K, int m, Lists L, const float *d, const float 
             dA = buf;
         }
         return tuned_launch(
-            h, synth_key(h, K, m, mode, precision), 2,
+            h, synth_key(h, K, m, mode, precision), SYNTH_MFMA_VARIANTS,
             [&](int v) { return launch_synth_mfma(g, K, m, L, dA, x, W, out, (int)mode, v, h->stream); },
             representative);
     }
@@ -786,6 +796,8 @@ extern "C" int csc_destroy(csc_handle h) {
     }
     for (auto e : h->side_ev)
         if (e) hipEventDestroy(e);
+    for (auto e : h->split_ev)
+        if (e) hipEventDestroy(e);
     for (auto e : h->graph_ev)
         if (e) hipEventDestroy(e);
     for (auto e : h->ev_pool) hipEventDestroy(e);
@@ -1014,6 +1026,9 @@ int code_step_impl(csc_ctx *h, const csc_images *im, const float *x, const uint8
     }
     // The n_iter iterations only launch kernels; their step and threshold are
     // read from device scalars, so the same launches can be replayed as a graph.
+    // one stream: the adjoint that loads a chunk ahead, unless a variant is forced
+    // (the forced variant's low bit picks the adjoint, so tests reach both)
+    const int adj_variant = h->force_variant >= 0 ? (h->force_variant & 1) : 0;
     auto iterations = [&]() -> int {
         int c = 0;
         for (int it = 0; it < n_iter; ++it) {
@@ -1026,7 +1041,7 @@ int code_step_impl(csc_ctx *h, const csc_images *im, const float *x, const uint8
                 PROF(CSC_PK_ADJOINT);
                 if (precision == CSC_BF16)
                     HIPCHK(launch_adjoint_shrink_mfma(g, K, m, mw, soff, pairs[c], nzc[c], pairs[c ^ 1], nzc[c ^ 1],
-                                                      R, ada, ethr, nnzsum, 0, h->stream));
+                                                      R, ada, ethr, nnzsum, adj_variant, h->stream));
                 else
                     HIPCHK(launch_adjoint_shrink(g, K, m, mw, soff, pairs[c], nzc[c], pairs[c ^ 1], nzc[c ^ 1], R,
                                                  di, ethr, nnzsum, h->stream));
@@ -1039,11 +1054,13 @@ int code_step_impl(csc_ctx *h, const csc_images *im, const float *x, const uint8
     // (split between images, which the iterations never couple) run on the
     // handle's stream and its side stream, so that the kernels of one half fill
     // the CUs that the other half's last workgroups leave idle.  Same kernels and
-    // tiles as one launch over the batch, so the same bits.  Which synthesis and
-    // adjoint variants run best beside each other is tuned on a whole iteration
-    // (variant index = 2 * synthesis variant + adjoint variant), once the first
-    // split call has run its iterations: the timed iterations repeat the last one
-    // from the same lists without the non-zero count, which rewrites the same bits.
+    // tiles as one launch over the batch, so the same bits.  The synthesis and
+    // adjoint variants that run best beside each other (variant index = 2 *
+    // synthesis variant + adjoint variant) are chosen in two stages: after the
+    // first split call's iterations, every pair is timed on its last iteration,
+    // repeated five times back to back from the same lists without the non-zero
+    // count (which rewrites the same bits); the two fastest then run the next two
+    // split calls, whose iteration loops are timed, and the faster is kept.
     const auto skey = synth_key(h, K, m, SYNTH_RESIDUAL, precision);
     hipStream_t hs = (!use_graph && !h->prof && precision == CSC_BF16 && n_iter > 0 && g.n_img >= 2 &&
                       h->force_variant < 0 && tuned_variant(h, skey) >= 0)
@@ -1083,8 +1100,43 @@ int code_step_impl(csc_ctx *h, const csc_images *im, const float *x, const uint8
             hipError_t e = hipEventRecord(h->side_ev[3], hs);
             return e == hipSuccess ? hipStreamWaitEvent(h->stream, h->side_ev[3], 0) : e;
         };
-        const int tuned = tuned_variant(h, ikey);
-        const int vi = tuned >= 0 ? tuned : 2 * tuned_variant(h, skey);
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        const bool can_tune = h->autotune && hipStreamIsCapturing(h->stream, &cs) == hipSuccess &&
+                              cs == hipStreamCaptureStatusNone;
+        hipGetLastError();
+        int vi = tuned_variant(h, ikey);
+        const bool settled = vi >= 0;
+        int confirm = -1;  // the candidate this call confirms
+        auto stt = h->split_tune.find(ikey);
+        if (!settled) {
+            vi = 2 * tuned_variant(h, skey);
+            if (stt != h->split_tune.end() && can_tune) {
+                csc_ctx::SplitTune &t = stt->second;
+                if (t.pending >= 0) {
+                    float ms = 0.f;
+                    HIPCHK(hipEventSynchronize(h->split_ev[1]));
+                    HIPCHK(hipEventElapsedTime(&ms, h->split_ev[0], h->split_ev[1]));
+                    t.ms[t.pending] = ms;
+                    t.pending = -1;
+                }
+                if (t.ms[0] >= 0.f && t.ms[1] >= 0.f) {
+                    vi = t.ms[1] < t.ms[0] ? t.cand[1] : t.cand[0];
+                    if (std::getenv("SCSC_TUNE_LOG"))
+                        std::fprintf(stderr, "[scsc tune] split m %d K %d: variant %d %.3f ms, variant %d %.3f ms\n", m,
+                                     K, t.cand[0], t.ms[0], t.cand[1], t.ms[1]);
+                    h->tuned[ikey] = vi;
+                    h->split_tune.erase(stt);
+                } else {
+                    confirm = t.ms[0] < 0.f ? 0 : 1;
+                    vi = t.cand[confirm];
+                }
+            }
+        }
+        if (confirm >= 0) {
+            for (auto &e : h->split_ev)
+                if (!e) HIPCHK(hipEventCreate(&e));
+            HIPCHK(hipEventRecord(h->split_ev[0], h->stream));
+        }
         HIPCHK(fork());
         int c = 0;
         for (int it = 0; it < n_iter; ++it) {
@@ -1092,12 +1144,39 @@ int code_step_impl(csc_ctx *h, const csc_images *im, const float *x, const uint8
             c ^= 1;
         }
         HIPCHK(join());
-        if (tuned < 0 && h->autotune)
-            HIPCHK(tuned_launch(h, ikey, 4, [&](int v) -> hipError_t {
-                hipError_t e = fork();
-                if (e == hipSuccess) e = iteration(v, c ^ 1, nullptr);
-                return e == hipSuccess ? join() : e;
-            }));
+        if (confirm >= 0) {
+            HIPCHK(hipEventRecord(h->split_ev[1], h->stream));
+            h->split_tune[ikey].pending = confirm;
+        }
+        if (!settled && can_tune && h->split_tune.find(ikey) == h->split_tune.end() && h->tuned.count(ikey) == 0) {
+            // screening: every pair on the last iteration, five times back to back
+            for (auto &e : h->split_ev)
+                if (!e) HIPCHK(hipEventCreate(&e));
+            std::vector<std::pair<float, int>> rank;
+            for (int v = 0; v < 2 * SYNTH_MFMA_VARIANTS; ++v) {
+                float best = 0.f;
+                for (int rep = 0; rep < 3; ++rep) {  // the first run warms up
+                    HIPCHK(hipEventRecord(h->split_ev[0], h->stream));
+                    HIPCHK(fork());
+                    for (int r5 = 0; r5 < 5; ++r5) HIPCHK(iteration(v, c ^ 1, nullptr));
+                    HIPCHK(join());
+                    HIPCHK(hipEventRecord(h->split_ev[1], h->stream));
+                    HIPCHK(hipEventSynchronize(h->split_ev[1]));
+                    float ms = 0.f;
+                    HIPCHK(hipEventElapsedTime(&ms, h->split_ev[0], h->split_ev[1]));
+                    if (rep == 1 || (rep > 1 && ms < best)) best = ms;
+                }
+                if (std::getenv("SCSC_TUNE_LOG"))
+                    std::fprintf(stderr, "[scsc tune] split m %d K %d screening: variant %d %.1f us\n", m, K, v,
+                                 1e3 * best);
+                rank.push_back({best, v});
+            }
+            std::sort(rank.begin(), rank.end());
+            csc_ctx::SplitTune t;
+            t.cand[0] = rank[0].second;
+            t.cand[1] = rank[1].second;
+            h->split_tune[ikey] = t;
+        }
     } else if (use_graph) {
         const std::vector<uintptr_t> key = {
             (uintptr_t)K, (uintptr_t)m, (uintptr_t)precision, (uintptr_t)n_iter, (uintptr_t)g.n_tiles,

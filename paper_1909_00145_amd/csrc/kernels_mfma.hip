@@ -174,7 +174,7 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int *excl, int *wsum)
 }
 
 template <int MM, int FG>
-__global__ __launch_bounds__(TPB) void k_synth_mfma(const ImgInfo *imgs, const TileInfo *tiles, int K, Lists zl,
+__global__ __launch_bounds__(TPB, FG == 1 ? 4 : 1) void k_synth_mfma(const ImgInfo *imgs, const TileInfo *tiles, int K, Lists zl,
                                                     const __bf16 *__restrict__ dA, const float *__restrict__ x,
                                                     const unsigned char *__restrict__ W, float *__restrict__ out,
                                                     int mode) {
@@ -361,8 +361,11 @@ hipError_t synth_mfma_impl(const Geometry &g, int K, Lists z, const __bf16 *dA, 
     if (variant == 0)
         hipLaunchKernelGGL((k_synth_mfma<MM, 2>), dim3(g.n_tiles), dim3(TPB), 0, s, g.d_img, g.d_tiles, K, z, dA, x, W,
                            out, mode);
-    else
+    else if (variant == 1)
         hipLaunchKernelGGL((k_synth_mfma<MM, 4>), dim3(g.n_tiles), dim3(TPB), 0, s, g.d_img, g.d_tiles, K, z, dA, x, W,
+                           out, mode);
+    else
+        hipLaunchKernelGGL((k_synth_mfma<MM, 1>), dim3(g.n_tiles), dim3(TPB), 0, s, g.d_img, g.d_tiles, K, z, dA, x, W,
                            out, mode);
     return hipGetLastError();
 }

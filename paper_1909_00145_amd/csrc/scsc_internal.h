@@ -411,7 +411,8 @@ int corr_mfma_blocks(const Geometry &g, int K);
 // written by launch_synth_mfma_prep (synth_mfma_prep_elems(K) elements).
 size_t synth_mfma_prep_elems(int K);
 hipError_t launch_synth_mfma_prep(const float *d, int K, int m, __bf16 *dA, hipStream_t s);
-// variant 0: 16 filters per LDS chunk, 1: 32.
+// variant 0: 16 filters per LDS chunk, 1: 32, 2: 8 (four workgroups per CU).  Same bits.
+constexpr int SYNTH_MFMA_VARIANTS = 3;
 hipError_t launch_synth_mfma(const Geometry &g, int K, int m, Lists z, const __bf16 *dA, const float *x,
                              const unsigned char *W, float *out, int mode, int variant, hipStream_t s);
 hipError_t launch_corr_mfma(const Geometry &g, int K, int m, Lists z, const float *r, float *part, float *G,
