@@ -59,28 +59,29 @@ PEAK_LAG_PRODUCTS = PEAK_LDS_BYTES / 16
 # HBM bytes per launch of each kernel class's main kernel, from rocprofv3 FETCH_SIZE / WRITE_SIZE
 # passes scaled by a 512 MiB copy (read x 2.000, write x 1.000), valid only for the kernel source
 # they were taken on (first 16 hex digits of its SHA-256).  Keyed by (workload, kernel class,
-# precision): (source, digest, bytes read, bytes written).  The online BF16 synthesis and adjoint
-# are taken on their full-batch launches (the per-kernel timing pass launches those; the eager
-# headline splits the batch over two streams).
+# precision): (source, digest, bytes read, bytes written), taken on the launch variant with the
+# most dispatches (the tuned one, which the timing pass runs; named after each entry).  The online
+# BF16 synthesis and adjoint are taken on their full-batch launches (the per-kernel timing pass
+# launches those; the eager headline splits the batch over two streams).
 TRAFFIC = {
-    ("online", "synth", "bf16"): ("kernels_mfma.hip", "16ec6e23e6f32e19", 43.36e6, 1.024e6),
-    ("online", "adjoint", "bf16"): ("kernels_code.hip", "8d3470bde5b9f97f", 34.16e6, 11.07e6),
-    ("online", "corr", "bf16"): ("kernels_dict.hip", "0bf8d154ab50cc41", 27.01e6, 4.067e6),
-    ("online", "sur_expand", "bf16"): ("kernels_sur.hip", "99875288c5777629", 767.5e6, 653.6e6),
-    ("online", "power", "bf16"): ("kernels_sur.hip", "99875288c5777629", 18.22e6, 0.6944e6),
-    ("online", "synth", "fp32"): ("kernels_code.hip", "8d3470bde5b9f97f", 18.11e6, 0.8021e6),
-    ("online", "adjoint", "fp32"): ("kernels_code.hip", "8d3470bde5b9f97f", 20.94e6, 10.63e6),
-    ("online", "corr", "fp32"): ("kernels_dict.hip", "0bf8d154ab50cc41", 27.01e6, 4.067e6),
-    ("online", "sur_expand", "fp32"): ("kernels_sur.hip", "99875288c5777629", 767.6e6, 653.6e6),
-    ("online", "power", "fp32"): ("kernels_sur.hip", "99875288c5777629", 18.22e6, 0.6944e6),
-    ("ragged", "synth", "bf16"): ("kernels_mfma.hip", "16ec6e23e6f32e19", 4043e6, 96.97e6),
-    ("ragged", "adjoint", "bf16"): ("kernels_code.hip", "8d3470bde5b9f97f", 2856e6, 1152e6),
-    ("ragged", "gather", "bf16"): ("kernels_code.hip", "8d3470bde5b9f97f", 9798e6, 184.7e6),
-    ("ragged", "scatter", "bf16"): ("kernels_code.hip", "8d3470bde5b9f97f", 1921e6, 8764e6),
-    ("ragged", "synth", "fp32"): ("kernels_code.hip", "8d3470bde5b9f97f", 3530e6, 129.5e6),
-    ("ragged", "adjoint", "fp32"): ("kernels_code.hip", "8d3470bde5b9f97f", 2225e6, 1408e6),
-    ("ragged", "gather", "fp32"): ("kernels_code.hip", "8d3470bde5b9f97f", 9798e6, 184.7e6),
-    ("ragged", "scatter", "fp32"): ("kernels_code.hip", "8d3470bde5b9f97f", 1921e6, 8763e6),
+    ("online", "synth", "bf16"): ("kernels_mfma.hip", "fd4ac6be865cdead", 44.19e6, 1.024e6),  # k_synth_mfma<11, 1> (full batch)
+    ("online", "adjoint", "bf16"): ("kernels_code.hip", "1249f574aaaf1c72", 34.16e6, 11.07e6),  # k_adjoint_shrink_mfma<11, true> (full batch)
+    ("online", "corr", "bf16"): ("kernels_dict.hip", "0bf8d154ab50cc41", 27.01e6, 4.067e6),  # k_corr_fm<11>
+    ("online", "sur_expand", "bf16"): ("kernels_sur.hip", "99875288c5777629", 767.5e6, 653.5e6),  # k_sur_expand<11>
+    ("online", "power", "bf16"): ("kernels_sur.hip", "99875288c5777629", 18.22e6, 0.6944e6),  # k_lag_matvec<11>
+    ("online", "synth", "fp32"): ("kernels_code.hip", "1249f574aaaf1c72", 18.08e6, 0.802e6),  # k_synth<11, true, 16, 8, 2>
+    ("online", "adjoint", "fp32"): ("kernels_code.hip", "1249f574aaaf1c72", 20.94e6, 10.63e6),  # k_adjoint_shrink<11>
+    ("online", "corr", "fp32"): ("kernels_dict.hip", "0bf8d154ab50cc41", 27.01e6, 4.067e6),  # k_corr_fm<11>
+    ("online", "sur_expand", "fp32"): ("kernels_sur.hip", "99875288c5777629", 767.4e6, 653.5e6),  # k_sur_expand<11>
+    ("online", "power", "fp32"): ("kernels_sur.hip", "99875288c5777629", 18.22e6, 0.6944e6),  # k_lag_matvec<11>
+    ("ragged", "synth", "bf16"): ("kernels_mfma.hip", "fd4ac6be865cdead", 3513e6, 80.85e6),  # k_synth_mfma<11, 1>
+    ("ragged", "adjoint", "bf16"): ("kernels_code.hip", "1249f574aaaf1c72", 2461e6, 967.2e6),  # k_adjoint_shrink_mfma<11, true>
+    ("ragged", "gather", "bf16"): ("kernels_code.hip", "1249f574aaaf1c72", 9798e6, 185.8e6),  # k_gather_selected
+    ("ragged", "scatter", "bf16"): ("kernels_code.hip", "1249f574aaaf1c72", 1921e6, 8765e6),  # k_scatter_dense
+    ("ragged", "synth", "fp32"): ("kernels_code.hip", "1249f574aaaf1c72", 3460e6, 130.2e6),  # k_synth<11, true, 16, 8, 4>
+    ("ragged", "adjoint", "fp32"): ("kernels_code.hip", "1249f574aaaf1c72", 2225e6, 1405e6),  # k_adjoint_shrink<11>
+    ("ragged", "gather", "fp32"): ("kernels_code.hip", "1249f574aaaf1c72", 9798e6, 184.7e6),  # k_gather_selected
+    ("ragged", "scatter", "fp32"): ("kernels_code.hip", "1249f574aaaf1c72", 1921e6, 8767e6),  # k_scatter_dense
 }
 
 
