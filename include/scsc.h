@@ -15,12 +15,13 @@
  * Stream.  Work is enqueued on the handle's HIP stream.  Calls that return
  *   host values (objective, statistics, L_d, the surrogate count) synchronise
  *   that stream before returning; the others are asynchronous.  With eager
- *   launches some work of a call runs on a second stream that the handle owns
- *   (same device, default priority): half of a BF16 code step's images, and in
- *   the online filter step the B_bar increment, the corner products and the
- *   power iteration.  It is forked from and joined back to the handle's stream
- *   with events inside the call, so stream order is as if all ran on the
- *   handle's stream.  Graph replay and per-kernel timing keep one stream.
+ *   launches some work of a call runs on two further streams that the handle
+ *   owns (same device, default priority): two of three parts of a BF16 code
+ *   step's images (one of two for two images), and in the online filter step the
+ *   B_bar increment, the corner products and the power iteration.  They are
+ *   forked from and joined back to the handle's stream with events inside the
+ *   call, so stream order is as if all ran on the handle's stream.  Graph
+ *   replay and per-kernel timing keep one stream.
  * Errors.  Every int-returning function returns CSC_OK (0) or a negative
  *   csc_status.  Arguments are validated before any work is enqueued: on
  *   CSC_EINVAL / CSC_EUNSUPPORTED no output has been written.  The message of

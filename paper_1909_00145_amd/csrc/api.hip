@@ -125,6 +125,9 @@ struct csc_ctx {
     hipStream_t side = nullptr;
     hipEvent_t side_ev[4] = {nullptr, nullptr, nullptr, nullptr};
     bool side_failed = false;
+    // a third stream for the third part of a split BF16 code step, with its join event
+    hipStream_t side2 = nullptr;
+    hipEvent_t side2_ev = nullptr;
     hipEvent_t graph_ev[2] = {nullptr, nullptr};
     // autotuner: launch variant per (kernel, m, K, log2 pixel count, mode)
     bool autotune = true;
@@ -794,6 +797,11 @@ extern "C" int csc_destroy(csc_handle h) {
         hipStreamSynchronize(h->side);
         hipStreamDestroy(h->side);
     }
+    if (h->side2) {
+        hipStreamSynchronize(h->side2);
+        hipStreamDestroy(h->side2);
+    }
+    if (h->side2_ev) hipEventDestroy(h->side2_ev);
     for (auto e : h->side_ev)
         if (e) hipEventDestroy(e);
     for (auto e : h->split_ev)
@@ -860,19 +868,25 @@ struct CodeStepFused {
     double Lz = 0.0, eta = 0.0;     // out
 };
 
-// The handle's side stream and its events, created on first use; null (and the
-// caller runs everything in order on the handle's stream) if they cannot be made.
+// The handle's side streams (a second and a third, default priority) and their
+// events, created on first use; null (and the caller runs everything in order on
+// the handle's stream) if they cannot be made.
 static hipStream_t side_stream(csc_ctx *h) {
     if (h->side || h->side_failed) return h->side;
     bool ok = hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) == hipSuccess;
     for (auto &e : h->side_ev) ok = ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
+    ok = ok && hipStreamCreateWithFlags(&h->side2, hipStreamNonBlocking) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&h->side2_ev, hipEventDisableTiming) == hipSuccess;
     if (!ok) {
         hipGetLastError();
         if (h->side) hipStreamDestroy(h->side);
+        if (h->side2) hipStreamDestroy(h->side2);
         for (auto &e : h->side_ev)
             if (e) hipEventDestroy(e);
-        h->side = nullptr;
+        if (h->side2_ev) hipEventDestroy(h->side2_ev);
+        h->side = h->side2 = nullptr;
         for (auto &e : h->side_ev) e = nullptr;
+        h->side2_ev = nullptr;
         h->side_failed = true;
     }
     return h->side;
@@ -1050,11 +1064,11 @@ int code_step_impl(csc_ctx *h, const csc_images *im, const float *x, const uint8
         }
         return CSC_OK;
     };
-    // BF16 with eager launches and a tuned synthesis: the two halves of the batch
-    // (split between images, which the iterations never couple) run on the
-    // handle's stream and its side stream, so that the kernels of one half fill
-    // the CUs that the other half's last workgroups leave idle.  Same kernels and
-    // tiles as one launch over the batch, so the same bits.  The synthesis and
+    // BF16 with eager launches and a tuned synthesis: three parts of the batch (two
+    // for two images; split between images, which the iterations never couple)
+    // run on the handle's stream and its side streams, so that the kernels of one
+    // part fill the CUs that another part's last workgroups leave idle.  Same
+    // kernels and tiles as one launch over the batch, so the same bits.  The synthesis and
     // adjoint variants that run best beside each other (variant index = 2 *
     // synthesis variant + adjoint variant) are chosen in two stages: after the
     // first split call's iterations, every pair is timed on its last iteration,
@@ -1067,38 +1081,45 @@ int code_step_impl(csc_ctx *h, const csc_images *im, const float *x, const uint8
                          ? side_stream(h)
                          : nullptr;
     if (hs) {
-        Geometry half[2];
-        const int split = g.h_img[g.n_img / 2].tile_off;
-        for (Geometry &gh : half) {
-            gh.n_img = g.n_img;
-            gh.n_pix = g.n_pix;
-            gh.max_side = g.max_side;
-            gh.d_img = g.d_img;
+        // three parts when the batch has three images or more
+        const int NPART = g.n_img >= 3 ? 3 : 2;
+        Geometry part[3];
+        for (int i = 0; i < NPART; ++i) {
+            const int t0 = g.h_img[g.n_img * i / NPART].tile_off;
+            const int t1 = i + 1 < NPART ? g.h_img[g.n_img * (i + 1) / NPART].tile_off : g.n_tiles;
+            part[i].n_img = g.n_img;
+            part[i].n_pix = g.n_pix;
+            part[i].max_side = g.max_side;
+            part[i].d_img = g.d_img;
+            part[i].d_tiles = g.d_tiles + t0;
+            part[i].n_tiles = t1 - t0;
         }
-        half[0].d_tiles = g.d_tiles;
-        half[0].n_tiles = split;
-        half[1].d_tiles = g.d_tiles + split;
-        half[1].n_tiles = g.n_tiles - split;
-        const hipStream_t hstr[2] = {h->stream, hs};
+        const hipStream_t pstr[3] = {h->stream, hs, h->side2};
         const std::array<int, 5> ikey = {TK_SPLIT_BF16, m, K, ilog2(g.n_pix), 0};
-        // one iteration on both streams from lists c; acc: the non-zero count, or null
+        // one iteration on every part's stream from lists c; acc: the non-zero count, or null
         auto iteration = [&](int vi, int c, unsigned long long *acc) -> hipError_t {
             hipError_t e = hipSuccess;
-            for (int i = 0; i < 2 && e == hipSuccess; ++i)
-                e = launch_synth_mfma(half[i], K, m, Lists{soff, nzc[c], pairs[c]}, sda, xi, Wi, R,
-                                      (int)SYNTH_RESIDUAL, vi >> 1, hstr[i]);
-            for (int i = 0; i < 2 && e == hipSuccess; ++i)
-                e = launch_adjoint_shrink_mfma(half[i], K, m, mw, soff, pairs[c], nzc[c], pairs[c ^ 1], nzc[c ^ 1], R,
-                                               ada, ethr, acc, vi & 1, hstr[i]);
+            for (int i = 0; i < NPART && e == hipSuccess; ++i)
+                e = launch_synth_mfma(part[i], K, m, Lists{soff, nzc[c], pairs[c]}, sda, xi, Wi, R,
+                                      (int)SYNTH_RESIDUAL, vi >> 1, pstr[i]);
+            for (int i = 0; i < NPART && e == hipSuccess; ++i)
+                e = launch_adjoint_shrink_mfma(part[i], K, m, mw, soff, pairs[c], nzc[c], pairs[c ^ 1], nzc[c ^ 1], R,
+                                               ada, ethr, acc, vi & 1, pstr[i]);
             return e;
         };
         auto fork = [&]() -> hipError_t {
             hipError_t e = hipEventRecord(h->side_ev[0], h->stream);
-            return e == hipSuccess ? hipStreamWaitEvent(hs, h->side_ev[0], 0) : e;
+            for (int i = 1; i < NPART && e == hipSuccess; ++i) e = hipStreamWaitEvent(pstr[i], h->side_ev[0], 0);
+            return e;
         };
         auto join = [&]() -> hipError_t {
-            hipError_t e = hipEventRecord(h->side_ev[3], hs);
-            return e == hipSuccess ? hipStreamWaitEvent(h->stream, h->side_ev[3], 0) : e;
+            hipEvent_t ev[3] = {nullptr, h->side_ev[3], h->side2_ev};
+            hipError_t e = hipSuccess;
+            for (int i = 1; i < NPART && e == hipSuccess; ++i) {
+                e = hipEventRecord(ev[i], pstr[i]);
+                if (e == hipSuccess) e = hipStreamWaitEvent(h->stream, ev[i], 0);
+            }
+            return e;
         };
         hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
         const bool can_tune = h->autotune && hipStreamIsCapturing(h->stream, &cs) == hipSuccess &&

@@ -1,7 +1,8 @@
-"""The BF16 code step with eager launches runs the two halves of a batch (split
-between images) on the handle's stream and its side stream.  It gives the same
-bits as the same step run in order on one stream, which the library does while
-per-kernel timing is on."""
+"""The BF16 code step with eager launches runs three parts of a batch (two for two
+images; split between images) on the handle's stream and its side streams, with
+its synthesis and adjoint variants tuned on the first calls.  Every call gives the
+same bits as the same step run in order on one stream, which the library does
+while per-kernel timing is on."""
 
 import numpy as np
 import pytest
@@ -24,7 +25,7 @@ def test_split_code_step_matches_one_stream(hw):
     single.lib.csc_profile_enable(single.h, 1)
     im = Images(hw)
     try:
-        for call in range(3):
+        for call in range(5):
             xs = [f32(si.field(12, 10 * call + i, H, Wd)) for i, (H, Wd) in enumerate(hw)]
             d = f32(si.filters(12 + call, K, m))
             x = packed(im, xs)
