@@ -16,8 +16,8 @@
  *   host values (objective, statistics, L_d, the surrogate count) synchronise
  *   that stream before returning; the others are asynchronous.  With eager
  *   launches some work of a call runs on two further streams that the handle
- *   owns (same device, default priority): two of three parts of a BF16 code
- *   step's images (one of two for two images), and in the online filter step the
+ *   owns (same device, default priority): two of three parts of a code step's
+ *   images (one of two for two images), and in the online filter step the
  *   B_bar increment, the corner products and the power iteration.  They are
  *   forked from and joined back to the handle's stream with events inside the
  *   call, so stream order is as if all ran on the handle's stream.  Graph

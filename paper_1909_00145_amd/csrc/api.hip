@@ -134,11 +134,12 @@ struct csc_ctx {
     int force_variant = -1;
     std::map<std::array<int, 5>, int> tuned;
     // the split code step's variants: the two best of a screening, confirmed on the
-    // next two whole split calls (their iteration loops timed with split_ev)
+    // next four whole split calls, in turn (their iteration loops timed with split_ev)
     struct SplitTune {
         int cand[2] = {-1, -1};
-        float ms[2] = {-1.f, -1.f};
-        int pending = -1;  // candidate whose call's events have not been read yet
+        float ms[2] = {-1.f, -1.f};  // the faster of each candidate's timed calls
+        int runs = 0;                // confirmation calls made (alternating candidates)
+        int pending = -1;            // candidate whose call's events have not been read yet
     };
     std::map<std::array<int, 5>, SplitTune> split_tune;
     hipEvent_t split_ev[2] = {nullptr, nullptr};
@@ -218,7 +219,8 @@ struct ProfScope {
     } while (0)
 
 // Kernels with several launch variants that compute bit-identical results.
-enum TunedKernel { TK_SYNTH = 0, TK_SYNTH_BF16 = 1, TK_SPLIT_BF16 = 2 };
+enum TunedKernel { TK_SYNTH = 0, TK_SYNTH_BF16 = 1, TK_SPLIT_BF16 = 2, TK_SPLIT_FP32 = 3 };
+constexpr int SYNTH_FP32_VARIANTS = 4;
 
 int ilog2(long long v) {
     int r = 0;
@@ -327,7 +329,7 @@ hipError_t synth(csc_ctx *h, int K, int m, Lists L, const float *d, const float 
             representative);
     }
     return tuned_launch(
-        h, synth_key(h, K, m, mode), 4,
+        h, synth_key(h, K, m, mode), SYNTH_FP32_VARIANTS,
         [&](int v) { return launch_synth(g, K, m, L, d, x, W, out, mode, v, h->stream); }, representative);
 }
 
@@ -1064,20 +1066,22 @@ int code_step_impl(csc_ctx *h, const csc_images *im, const float *x, const uint8
         }
         return CSC_OK;
     };
-    // BF16 with eager launches and a tuned synthesis: three parts of the batch (two
-    // for two images; split between images, which the iterations never couple)
-    // run on the handle's stream and its side streams, so that the kernels of one
-    // part fill the CUs that another part's last workgroups leave idle.  Same
-    // kernels and tiles as one launch over the batch, so the same bits.  The synthesis and
-    // adjoint variants that run best beside each other (variant index = 2 *
-    // synthesis variant + adjoint variant) are chosen in two stages: after the
-    // first split call's iterations, every pair is timed on its last iteration,
-    // repeated five times back to back from the same lists without the non-zero
-    // count (which rewrites the same bits); the two fastest then run the next two
-    // split calls, whose iteration loops are timed, and the faster is kept.
+    // With eager launches and a tuned synthesis, three parts of the batch (two for
+    // two images; split between images, which the iterations never couple) run on
+    // the handle's stream and its side streams, so that the kernels of one part
+    // fill the CUs that another part's last workgroups leave idle.  Same kernels
+    // and tiles as one launch over the batch, so the same bits.  The synthesis and
+    // adjoint variants that run best beside each other (variant index =
+    // synthesis variant * adjoint variants + adjoint variant; the FP32 adjoint has
+    // one) are chosen in two stages: after the first split call's iterations,
+    // every pair is timed on its last iteration, repeated five times back to back
+    // from the same lists without the non-zero count (which rewrites the same
+    // bits); the two fastest then run the next four split calls in turn, whose
+    // iteration loops are timed, and the one with the faster call is kept.
+    const bool bf16 = precision == CSC_BF16;
     const auto skey = synth_key(h, K, m, SYNTH_RESIDUAL, precision);
-    hipStream_t hs = (!use_graph && !h->prof && precision == CSC_BF16 && n_iter > 0 && g.n_img >= 2 &&
-                      h->force_variant < 0 && tuned_variant(h, skey) >= 0)
+    hipStream_t hs = (!use_graph && !h->prof && n_iter > 0 && g.n_img >= 2 && h->force_variant < 0 &&
+                      tuned_variant(h, skey) >= 0)
                          ? side_stream(h)
                          : nullptr;
     if (hs) {
@@ -1095,16 +1099,22 @@ int code_step_impl(csc_ctx *h, const csc_images *im, const float *x, const uint8
             part[i].n_tiles = t1 - t0;
         }
         const hipStream_t pstr[3] = {h->stream, hs, h->side2};
-        const std::array<int, 5> ikey = {TK_SPLIT_BF16, m, K, ilog2(g.n_pix), 0};
+        const int n_av = bf16 ? 2 : 1;
+        const int n_vi = (bf16 ? SYNTH_MFMA_VARIANTS : SYNTH_FP32_VARIANTS) * n_av;
+        const std::array<int, 5> ikey = {bf16 ? TK_SPLIT_BF16 : TK_SPLIT_FP32, m, K, ilog2(g.n_pix), 0};
         // one iteration on every part's stream from lists c; acc: the non-zero count, or null
         auto iteration = [&](int vi, int c, unsigned long long *acc) -> hipError_t {
+            const int sv = vi / n_av, av = vi % n_av;
+            const Lists Lc{soff, nzc[c], pairs[c]};
             hipError_t e = hipSuccess;
             for (int i = 0; i < NPART && e == hipSuccess; ++i)
-                e = launch_synth_mfma(part[i], K, m, Lists{soff, nzc[c], pairs[c]}, sda, xi, Wi, R,
-                                      (int)SYNTH_RESIDUAL, vi >> 1, pstr[i]);
+                e = bf16 ? launch_synth_mfma(part[i], K, m, Lc, sda, xi, Wi, R, (int)SYNTH_RESIDUAL, sv, pstr[i])
+                         : launch_synth(part[i], K, m, Lc, di, xi, Wi, R, SYNTH_RESIDUAL, sv, pstr[i]);
             for (int i = 0; i < NPART && e == hipSuccess; ++i)
-                e = launch_adjoint_shrink_mfma(part[i], K, m, mw, soff, pairs[c], nzc[c], pairs[c ^ 1], nzc[c ^ 1], R,
-                                               ada, ethr, acc, vi & 1, pstr[i]);
+                e = bf16 ? launch_adjoint_shrink_mfma(part[i], K, m, mw, soff, pairs[c], nzc[c], pairs[c ^ 1],
+                                                      nzc[c ^ 1], R, ada, ethr, acc, av, pstr[i])
+                         : launch_adjoint_shrink(part[i], K, m, mw, soff, pairs[c], nzc[c], pairs[c ^ 1], nzc[c ^ 1],
+                                                 R, di, ethr, acc, pstr[i]);
             return e;
         };
         auto fork = [&]() -> hipError_t {
@@ -1130,17 +1140,17 @@ int code_step_impl(csc_ctx *h, const csc_images *im, const float *x, const uint8
         int confirm = -1;  // the candidate this call confirms
         auto stt = h->split_tune.find(ikey);
         if (!settled) {
-            vi = 2 * tuned_variant(h, skey);
+            vi = n_av * tuned_variant(h, skey);
             if (stt != h->split_tune.end() && can_tune) {
                 csc_ctx::SplitTune &t = stt->second;
                 if (t.pending >= 0) {
                     float ms = 0.f;
                     HIPCHK(hipEventSynchronize(h->split_ev[1]));
                     HIPCHK(hipEventElapsedTime(&ms, h->split_ev[0], h->split_ev[1]));
-                    t.ms[t.pending] = ms;
+                    if (t.ms[t.pending] < 0.f || ms < t.ms[t.pending]) t.ms[t.pending] = ms;
                     t.pending = -1;
                 }
-                if (t.ms[0] >= 0.f && t.ms[1] >= 0.f) {
+                if (t.runs >= 4) {
                     vi = t.ms[1] < t.ms[0] ? t.cand[1] : t.cand[0];
                     if (std::getenv("SCSC_TUNE_LOG"))
                         std::fprintf(stderr, "[scsc tune] split m %d K %d: variant %d %.3f ms, variant %d %.3f ms\n", m,
@@ -1148,7 +1158,8 @@ int code_step_impl(csc_ctx *h, const csc_images *im, const float *x, const uint8
                     h->tuned[ikey] = vi;
                     h->split_tune.erase(stt);
                 } else {
-                    confirm = t.ms[0] < 0.f ? 0 : 1;
+                    confirm = t.runs & 1;
+                    ++t.runs;
                     vi = t.cand[confirm];
                 }
             }
@@ -1174,7 +1185,7 @@ int code_step_impl(csc_ctx *h, const csc_images *im, const float *x, const uint8
             for (auto &e : h->split_ev)
                 if (!e) HIPCHK(hipEventCreate(&e));
             std::vector<std::pair<float, int>> rank;
-            for (int v = 0; v < 2 * SYNTH_MFMA_VARIANTS; ++v) {
+            for (int v = 0; v < n_vi; ++v) {
                 float best = 0.f;
                 for (int rep = 0; rep < 3; ++rep) {  // the first run warms up
                     HIPCHK(hipEventRecord(h->split_ev[0], h->stream));
