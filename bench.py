@@ -64,6 +64,7 @@ PEAK_LAG_PRODUCTS = PEAK_LDS_BYTES / 16
 # BF16 synthesis and adjoint are taken on their full-batch launches (the per-kernel timing pass
 # launches those; the eager headline splits the batch over two streams).
 TRAFFIC = {
+    ("online", "synth", "bf16"): ("kernels_mfma.hip", "fd4ac6be865cdead", 44.04e6, 1.024e6),  # k_synth_mfma<11, 1> (full batch)
     ("online", "adjoint", "bf16"): ("kernels_code.hip", "1249f574aaaf1c72", 34.16e6, 11.07e6),  # k_adjoint_shrink_mfma<11, true> (full batch)
     ("online", "corr", "bf16"): ("kernels_dict.hip", "0bf8d154ab50cc41", 27.01e6, 4.067e6),  # k_corr_fm<11>
     ("online", "sur_expand", "bf16"): ("kernels_sur.hip", "99875288c5777629", 767.5e6, 653.6e6),  # k_sur_expand<11>
