@@ -17,6 +17,10 @@ def test_bench_module_tables():
         assert wl in bench.WORKLOADS and prec in ("bf16", "fp32")
         assert os.path.exists(os.path.join(ROOT, "paper_1909_00145_amd", "csrc", src))
         assert len(sha) == 16 and rd > 0 and wr > 0
+    for wl in ("online", "ragged"):
+        for prec in ("bf16", "fp32"):
+            for cls in ("synth", "adjoint"):
+                assert (wl, cls, prec) in bench.TRAFFIC
     for name in ("time_to_objective", "tto_study", "ragged_leg", "unrolled_leg", "cpu_baseline", "rooflines"):
         assert callable(getattr(bench, name))
 
