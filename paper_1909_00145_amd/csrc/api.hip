@@ -134,11 +134,11 @@ struct csc_ctx {
     int force_variant = -1;
     std::map<std::array<int, 5>, int> tuned;
     // the split code step's variants: the two best of a screening, confirmed on the
-    // next four whole split calls, in turn (their iteration loops timed with split_ev)
+    // next two whole split calls (their iteration loops timed with split_ev)
     struct SplitTune {
         int cand[2] = {-1, -1};
-        float ms[2] = {-1.f, -1.f};  // the faster of each candidate's timed calls
-        int runs = 0;                // confirmation calls made (alternating candidates)
+        float ms[2] = {-1.f, -1.f};  // each candidate's timed call
+        int runs = 0;                // confirmation calls made (one per candidate)
         int pending = -1;            // candidate whose call's events have not been read yet
     };
     std::map<std::array<int, 5>, SplitTune> split_tune;
@@ -1076,8 +1076,9 @@ int code_step_impl(csc_ctx *h, const csc_images *im, const float *x, const uint8
     // one) are chosen in two stages: after the first split call's iterations,
     // every pair is timed on its last iteration, repeated five times back to back
     // from the same lists without the non-zero count (which rewrites the same
-    // bits); the two fastest then run the next four split calls in turn, whose
-    // iteration loops are timed, and the one with the faster call is kept.
+    // bits); the two fastest then run the next two split calls, whose iteration
+    // loops are timed, and the faster is kept (so that a caller's first five calls
+    // settle the choice).
     const bool bf16 = precision == CSC_BF16;
     const auto skey = synth_key(h, K, m, SYNTH_RESIDUAL, precision);
     hipStream_t hs = (!use_graph && !h->prof && n_iter > 0 && g.n_img >= 2 && h->force_variant < 0 &&
@@ -1150,7 +1151,7 @@ int code_step_impl(csc_ctx *h, const csc_images *im, const float *x, const uint8
                     if (t.ms[t.pending] < 0.f || ms < t.ms[t.pending]) t.ms[t.pending] = ms;
                     t.pending = -1;
                 }
-                if (t.runs >= 4) {
+                if (t.runs >= 2) {
                     vi = t.ms[1] < t.ms[0] ? t.cand[1] : t.cand[0];
                     if (std::getenv("SCSC_TUNE_LOG"))
                         std::fprintf(stderr, "[scsc tune] split m %d K %d: variant %d %.3f ms, variant %d %.3f ms\n", m,
