@@ -144,11 +144,10 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--eager", action="store_true",
-                    help="launch the code step's iterations one by one instead of replaying them from a HIP graph "
-                         "(the default for the online workload)")
+                    help="launch the code step's iterations one by one (the default): the library then splits "
+                         "them over three streams")
     ap.add_argument("--graph", action="store_true",
-                    help="replay the code step's iterations and the power iteration from HIP graphs (the default "
-                         "for the batch and ragged workloads)")
+                    help="replay the code step's iterations and the power iteration from HIP graphs, on one stream")
     ap.add_argument("--no-tto", action="store_true",
                     help="skip the time-to-objective comparison of online learning, FP32 against BF16 "
                          "(100 mini-batches each; a few seconds)")
@@ -801,18 +800,19 @@ def rooflines(wname, w, im, precision, res, kernels, steps):
 
 def ragged_leg(ctx, steps, warmup):
     """One code step of the ragged batch (256 images, sides uniform in [64, 512], K = 100,
-    T = 30) per timed step, BF16 and FP32 plain, replayed from HIP graphs; then the same
-    steps with eager launches and every kernel class timed by HIP events, for the
-    per-class roofline fractions."""
+    T = 30) per timed step, BF16 and FP32 plain, with eager launches (the code step split
+    over three streams; the warm-up covers the tuning of the split); then the same steps
+    on one stream with every kernel class timed by HIP events, for the per-class roofline
+    fractions."""
     import torch
 
     w = WORKLOADS["ragged"]
     im, x = workload_inputs("ragged", w, 0)
-    out = {"workload": w["name"], "pixels": im.n_pix, "steps": steps, "warmup": warmup, "graph": True}
+    out = {"workload": w["name"], "pixels": im.n_pix, "steps": steps, "warmup": warmup, "graph": False}
     for prec in ("bf16", "fp32"):
-        res = timed_run(ctx, "ragged", w, im, x, prec, True, False, warmup, steps)
+        res = timed_run(ctx, "ragged", w, im, x, prec, False, False, warmup, steps)
         progress("ragged %s timed" % prec)
-        prof = timed_run(ctx, "ragged", w, im, x, prec, False, True, warmup, steps)
+        prof = timed_run(ctx, "ragged", w, im, x, prec, False, True, 1, steps)
         roof, others = rooflines("ragged", w, im, prec, prof, prof["kernels"], steps)
         out[prec] = {"value": res["sampled"] * w["T"] / res["el"], "unit": "updates/s",
                      "ms_per_step": 1e3 * res["el"] / steps,
@@ -925,10 +925,10 @@ def main():
     total_steps = args.warmup + args.steps
     im, x = workload_inputs(args.workload, w, total_steps)
 
-    # The joined online step queues a whole mini-batch of launches ahead of the GPU,
-    # so graph replay only adds its launch latency there (4.40 against 4.52 ms per
-    # step measured); the separate calls of the other workloads keep the graphs.
-    graph = args.graph or (not args.eager and args.workload != "online")
+    # Eager launches by default: they let the library split the code step over three
+    # streams, which beats graph replay on one stream for every workload (online 3.55
+    # against 4.24 ms, batch 2.49 against 2.57 ms, ragged 196 against 225 ms per step).
+    graph = args.graph and not args.eager
     # the headline run (no event timing), then the same steps eagerly with every kernel
     # class timed by HIP events, for the per-kernel figures and the roofline
     res = timed_run(ctx, args.workload, w, im, x, args.precision, graph, False, args.warmup, args.steps)
@@ -994,7 +994,7 @@ def main():
         out["tto_study"] = tto_study(ctx, WORKLOADS["online"], args.tto_batches)
         progress("time-to-objective study done")
     if args.workload == "online" and not args.no_ragged:
-        out["ragged"] = ragged_leg(ctx, args.ragged_steps, 1)
+        out["ragged"] = ragged_leg(ctx, args.ragged_steps, 4)
         progress("ragged leg done")
     if args.workload == "online" and not args.no_unrolled:
         out["unrolled"] = unrolled_leg(ctx)

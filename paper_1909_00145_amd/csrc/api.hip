@@ -133,13 +133,13 @@ struct csc_ctx {
     bool autotune = true;
     int force_variant = -1;
     std::map<std::array<int, 5>, int> tuned;
-    // the split code step's variants: the two best of a screening, confirmed on the
-    // next two whole split calls (their iteration loops timed with split_ev)
+    // the split code step's variants: the two best of a screening and the unsplit
+    // loop, confirmed on the next three calls (their iteration loops timed with split_ev)
     struct SplitTune {
-        int cand[2] = {-1, -1};
-        float ms[2] = {-1.f, -1.f};  // each candidate's timed call
-        int runs = 0;                // confirmation calls made (one per candidate)
-        int pending = -1;            // candidate whose call's events have not been read yet
+        int cand[3] = {-1, -1, -1};      // the two best split pairs, and the loop on one stream
+        float ms[3] = {-1.f, -1.f, -1.f};  // each candidate's timed call
+        int runs = 0;                    // confirmation calls made (one per candidate)
+        int pending = -1;                // candidate whose call's events have not been read yet
     };
     std::map<std::array<int, 5>, SplitTune> split_tune;
     hipEvent_t split_ev[2] = {nullptr, nullptr};
@@ -1076,9 +1076,9 @@ int code_step_impl(csc_ctx *h, const csc_images *im, const float *x, const uint8
     // one) are chosen in two stages: after the first split call's iterations,
     // every pair is timed on its last iteration, repeated five times back to back
     // from the same lists without the non-zero count (which rewrites the same
-    // bits); the two fastest then run the next two split calls, whose iteration
-    // loops are timed, and the faster is kept (so that a caller's first five calls
-    // settle the choice).
+    // bits); the two fastest, and the loop on one stream without a split, then run
+    // the next three calls, whose iteration loops are timed, and the fastest is
+    // kept (a caller's sixth call runs the choice).
     const bool bf16 = precision == CSC_BF16;
     const auto skey = synth_key(h, K, m, SYNTH_RESIDUAL, precision);
     hipStream_t hs = (!use_graph && !h->prof && n_iter > 0 && g.n_img >= 2 && h->force_variant < 0 &&
@@ -1151,16 +1151,20 @@ int code_step_impl(csc_ctx *h, const csc_images *im, const float *x, const uint8
                     if (t.ms[t.pending] < 0.f || ms < t.ms[t.pending]) t.ms[t.pending] = ms;
                     t.pending = -1;
                 }
-                if (t.runs >= 2) {
-                    vi = t.ms[1] < t.ms[0] ? t.cand[1] : t.cand[0];
+                if (t.runs >= 3) {
+                    int b = 0;
+                    for (int i = 1; i < 3; ++i)
+                        if (t.ms[i] < t.ms[b]) b = i;
+                    vi = t.cand[b];
                     if (std::getenv("SCSC_TUNE_LOG"))
-                        std::fprintf(stderr, "[scsc tune] split m %d K %d: variant %d %.3f ms, variant %d %.3f ms\n", m,
-                                     K, t.cand[0], t.ms[0], t.cand[1], t.ms[1]);
+                        std::fprintf(stderr,
+                                     "[scsc tune] split m %d K %d: variant %d %.3f ms, variant %d %.3f ms, "
+                                     "one stream %.3f ms\n",
+                                     m, K, t.cand[0], t.ms[0], t.cand[1], t.ms[1], t.ms[2]);
                     h->tuned[ikey] = vi;
                     h->split_tune.erase(stt);
                 } else {
-                    confirm = t.runs & 1;
-                    ++t.runs;
+                    confirm = t.runs++;
                     vi = t.cand[confirm];
                 }
             }
@@ -1170,13 +1174,18 @@ int code_step_impl(csc_ctx *h, const csc_images *im, const float *x, const uint8
                 if (!e) HIPCHK(hipEventCreate(&e));
             HIPCHK(hipEventRecord(h->split_ev[0], h->stream));
         }
-        HIPCHK(fork());
-        int c = 0;
-        for (int it = 0; it < n_iter; ++it) {
-            HIPCHK(iteration(vi, c, nnzsum));
-            c ^= 1;
+        int c = n_iter & 1;
+        if (vi == n_vi) {  // the loop on the handle's stream
+            if ((st = iterations())) return st;
+        } else {
+            HIPCHK(fork());
+            c = 0;
+            for (int it = 0; it < n_iter; ++it) {
+                HIPCHK(iteration(vi, c, nnzsum));
+                c ^= 1;
+            }
+            HIPCHK(join());
         }
-        HIPCHK(join());
         if (confirm >= 0) {
             HIPCHK(hipEventRecord(h->split_ev[1], h->stream));
             h->split_tune[ikey].pending = confirm;
@@ -1208,6 +1217,7 @@ int code_step_impl(csc_ctx *h, const csc_images *im, const float *x, const uint8
             csc_ctx::SplitTune t;
             t.cand[0] = rank[0].second;
             t.cand[1] = rank[1].second;
+            t.cand[2] = n_vi;  // no split
             h->split_tune[ikey] = t;
         }
     } else if (use_graph) {
