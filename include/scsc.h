@@ -312,11 +312,15 @@ typedef enum {
     CSC_PK_COUNT = 18
 } csc_kernel_class;
 
-/* enable != 0: record a pair of HIP events on the handle's stream around every
- * kernel launch from now on, clearing previous records; enable == 0: stop. */
+/* enable != 0: time every kernel class from now on, clearing previous records;
+ * enable == 0: stop.  Each timed scope of a class is measured with two HIP events
+ * that its kernels record themselves (hipExtLaunchKernel): the first kernel's start
+ * and the last kernel's end, on the handle's stream.  A graph replay
+ * (CSC_PK_GRAPH) is timed with an event pair recorded on the stream around it.
+ * While profiling is on, a code step runs on the handle's stream only. */
 int csc_profile_enable(csc_handle h, int enable);
-/* Launch count and summed event time (milliseconds) of one kernel class since
- * profiling was enabled.  Host outputs.  Synchronises the stream. */
+/* Number of timed scopes and their summed time (milliseconds) of one kernel class
+ * since profiling was enabled.  Host outputs.  Synchronises the stream. */
 int csc_profile_read(csc_handle h, int kernel_class, int64_t *launches, double *total_ms);
 
 /* ---- Unrolled proximal-gradient layers (differentiable code updates) ----------

@@ -15,6 +15,10 @@
 
 #include "scsc_internal.h"
 
+namespace scsc {
+thread_local KernelTiming *kernel_timing = nullptr;
+}
+
 using namespace scsc;
 
 namespace {
@@ -189,28 +193,56 @@ void fold_records(csc_ctx *h) {
     h->recs.clear();
 }
 
-// Records an event pair around the launches of its scope when profiling is on.
+// Times the launches of its scope when profiling is on: from the first kernel's start to
+// the last kernel's end, with events that the kernels record themselves (SCSC_LAUNCH).
+// A scope that launches no kernel of this library (a graph replay) is timed with an
+// event pair recorded on the handle's stream around it instead.
 struct ProfScope {
     csc_ctx *h;
     int cls;
-    hipEvent_t a = nullptr;
-    ProfScope(csc_ctx *h_, int cls_) : h(h_), cls(cls_) {
-        if (h->prof && !h->capturing) {
+    hipEvent_t a = nullptr;  // marker-pair timing only
+    KernelTiming kt;
+    KernelTiming *outer = nullptr;
+    bool hooked = false;
+    ProfScope(csc_ctx *h_, int cls_, bool markers = false) : h(h_), cls(cls_) {
+        if (!h->prof || h->capturing) return;
+        if (markers) {
             a = take_event(h);
             if (a) hipEventRecord(a, h->stream);
+            return;
+        }
+        kt.start = take_event(h);
+        kt.stop = take_event(h);
+        if (kt.start && kt.stop) {
+            outer = kernel_timing;
+            kernel_timing = &kt;
+            hooked = true;
+        } else {
+            if (kt.start) h->ev_pool.push_back(kt.start);
+            if (kt.stop) h->ev_pool.push_back(kt.stop);
         }
     }
     ~ProfScope() {
-        if (!a) return;
-        hipEvent_t b = take_event(h);
-        if (!b) return;
-        hipEventRecord(b, h->stream);
-        h->recs.push_back(csc_ctx::Rec{cls, a, b});
+        if (hooked) {
+            kernel_timing = outer;
+            if (kt.used) {
+                h->recs.push_back(csc_ctx::Rec{cls, kt.start, kt.stop});
+            } else {
+                h->ev_pool.push_back(kt.start);
+                h->ev_pool.push_back(kt.stop);
+            }
+        } else if (a) {
+            hipEvent_t b = take_event(h);
+            if (!b) return;
+            hipEventRecord(b, h->stream);
+            h->recs.push_back(csc_ctx::Rec{cls, a, b});
+        }
         if (h->recs.size() > 100000) fold_records(h);
     }
 };
 
 #define PROF(cls) ProfScope prof_scope_(h, cls)
+#define PROF_MARKERS(cls) ProfScope prof_scope_(h, cls, true)
 
 #define HIPCHK(expr)                                                                              \
     do {                                                                                          \
@@ -373,7 +405,7 @@ int graph_replay(csc_ctx *h, int slot, const std::vector<uintptr_t> &key, const 
         HIPCHK(ie);
         h->graph_key[slot] = key;
     }
-    PROF(CSC_PK_GRAPH);
+    PROF_MARKERS(CSC_PK_GRAPH);
     if (gs != h->stream) {
         HIPCHK(hipEventRecord(h->graph_ev[0], h->stream));
         HIPCHK(hipStreamWaitEvent(gs, h->graph_ev[0], 0));

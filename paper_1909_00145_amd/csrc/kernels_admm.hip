@@ -157,65 +157,65 @@ inline unsigned vec_grid(long long n) {
 
 hipError_t launch_sel_list(const Geometry &g, int K, const unsigned *mask_words, const unsigned *soff, const float *z,
                            Pair *pairs, unsigned short *cnt, hipStream_t s) {
-    hipLaunchKernelGGL(k_sel_list, dim3(flat_grid(g.n_pix)), dim3(TPB), 0, s, g.d_img, g.n_img, g.n_pix, K,
-                       mask_words, soff, z, pairs, cnt);
+    SCSC_LAUNCH(k_sel_list, dim3(flat_grid(g.n_pix)), dim3(TPB), 0, s, g.d_img, g.n_img, g.n_pix, K,
+                mask_words, soff, z, pairs, cnt);
     return hipGetLastError();
 }
 
 hipError_t launch_pack(const Pair *sel, const float *val, Pair *pairs, long long n, hipStream_t s) {
-    hipLaunchKernelGGL(k_pack, dim3(vec_grid(n)), dim3(256), 0, s, sel, val, pairs, n);
+    SCSC_LAUNCH(k_pack, dim3(vec_grid(n)), dim3(256), 0, s, sel, val, pairs, n);
     return hipGetLastError();
 }
 
 hipError_t launch_unpack(const Geometry &g, const unsigned *soff, const Pair *sel, const Pair *cl,
                          const unsigned short *ccnt, float *out, hipStream_t s) {
-    hipLaunchKernelGGL(k_unpack, dim3(flat_grid(g.n_pix)), dim3(TPB), 0, s, g.d_img, g.n_img, g.n_pix, soff, sel, cl,
-                       ccnt, out);
+    SCSC_LAUNCH(k_unpack, dim3(flat_grid(g.n_pix)), dim3(TPB), 0, s, g.d_img, g.n_img, g.n_pix, soff, sel, cl,
+                ccnt, out);
     return hipGetLastError();
 }
 
 long long admm_dot_elems(int n_img) { return (long long)AD_BLOCKS * n_img; }
 
 hipError_t launch_seg(const Geometry &g, const unsigned *soff, unsigned *seg, hipStream_t s) {
-    hipLaunchKernelGGL(k_seg, dim3((g.n_img + 256) / 256), dim3(256), 0, s, g.d_img, g.n_img, g.n_pix, soff, seg);
+    SCSC_LAUNCH(k_seg, dim3((g.n_img + 256) / 256), dim3(256), 0, s, g.d_img, g.n_img, g.n_pix, soff, seg);
     return hipGetLastError();
 }
 
 hipError_t launch_cg_dot(const Geometry &g, const float *a, const float *b, const unsigned *seg, double *part,
                          int mode, double *scs, hipStream_t s) {
-    hipLaunchKernelGGL(k_dot_part, dim3(AD_BLOCKS, g.n_img), dim3(256), 0, s, a, b, seg, part);
+    SCSC_LAUNCH(k_dot_part, dim3(AD_BLOCKS, g.n_img), dim3(256), 0, s, a, b, seg, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_cg_scalar, dim3((g.n_img + 63) / 64), dim3(64), 0, s, part, AD_BLOCKS, g.n_img, mode, scs);
+    SCSC_LAUNCH(k_cg_scalar, dim3((g.n_img + 63) / 64), dim3(64), 0, s, part, AD_BLOCKS, g.n_img, mode, scs);
     return hipGetLastError();
 }
 
 hipError_t launch_axpy_alpha(const Geometry &g, float *y, const float *x, const double *scs, const unsigned *seg,
                              float sgn, hipStream_t s) {
-    hipLaunchKernelGGL(k_axpy_alpha, dim3(AD_BLOCKS, g.n_img), dim3(256), 0, s, y, x, scs, seg, sgn);
+    SCSC_LAUNCH(k_axpy_alpha, dim3(AD_BLOCKS, g.n_img), dim3(256), 0, s, y, x, scs, seg, sgn);
     return hipGetLastError();
 }
 
 hipError_t launch_cg_dir(const Geometry &g, float *q, const float *r, const double *scs, const unsigned *seg,
                          hipStream_t s) {
-    hipLaunchKernelGGL(k_cg_dir, dim3(AD_BLOCKS, g.n_img), dim3(256), 0, s, q, r, scs, seg);
+    SCSC_LAUNCH(k_cg_dir, dim3(AD_BLOCKS, g.n_img), dim3(256), 0, s, q, r, scs, seg);
     return hipGetLastError();
 }
 
 hipError_t launch_add_scaled(float *Aq, const float *q, float rho, long long n, hipStream_t s) {
-    hipLaunchKernelGGL(k_add_scaled, dim3(vec_grid(n)), dim3(256), 0, s, Aq, q, rho, n);
+    SCSC_LAUNCH(k_add_scaled, dim3(vec_grid(n)), dim3(256), 0, s, Aq, q, rho, n);
     return hipGetLastError();
 }
 
 hipError_t launch_cg_init(float *r, float *q, const float *b0, const float *v, const float *u, const float *Aq,
                           float rho, long long n, hipStream_t s) {
-    hipLaunchKernelGGL(k_cg_init, dim3(vec_grid(n)), dim3(256), 0, s, r, q, b0, v, u, Aq, rho, n);
+    SCSC_LAUNCH(k_cg_init, dim3(vec_grid(n)), dim3(256), 0, s, r, q, b0, v, u, Aq, rho, n);
     return hipGetLastError();
 }
 
 hipError_t launch_admm_update(const float *zt, float *v, float *u, float alpha, float thr, long long n,
                               hipStream_t s) {
-    hipLaunchKernelGGL(k_admm_update, dim3(vec_grid(n)), dim3(256), 0, s, zt, v, u, alpha, thr, n);
+    SCSC_LAUNCH(k_admm_update, dim3(vec_grid(n)), dim3(256), 0, s, zt, v, u, alpha, thr, n);
     return hipGetLastError();
 }
 
@@ -239,7 +239,7 @@ __global__ __launch_bounds__(256) void k_count_nz(const float *v, long long n, u
 }  // namespace
 
 hipError_t launch_count_nz(const float *v, long long n, unsigned long long *out, hipStream_t s) {
-    hipLaunchKernelGGL(k_count_nz, dim3(vec_grid(n)), dim3(256), 0, s, v, n, out);
+    SCSC_LAUNCH(k_count_nz, dim3(vec_grid(n)), dim3(256), 0, s, v, n, out);
     return hipGetLastError();
 }
 }  // namespace scsc

@@ -751,7 +751,7 @@ __global__ __launch_bounds__(TPB, PF ? 1 : 3) void k_adjoint_shrink_mfma(const I
     __shared__ int bsum;
 
     const float eta = ethr[0], thr = ethr[1];
-    PixelCtx c = pixel_ctx(imgs, tiles);
+    PixelCtx c = pixel_ctx(imgs, tiles, xcd_tile((int)blockIdx.x, (int)gridDim.x));
     const int oy = c.t.ty * TS - C, ox = c.t.tx * TS - C;
     for (int i = threadIdx.x; i < RW * RW; i += TPB) {
         const int gy = oy + i / RW, gx = ox + i % RW;
@@ -1013,15 +1013,15 @@ hipError_t launch_mask_count(const Geometry &g, int K, unsigned long long thr, u
     uint2 key = make_uint2((unsigned)seed, (unsigned)(seed >> 32));
     hipError_t e = hipMemsetAsync(cnt, 0, sizeof(unsigned) * (size_t)g.n_pix, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_mask_count, dim3(flat_grid(g.n_pix), (unsigned)((K + 31) / 32)), dim3(TPB), 0, s, g.d_img,
-                       g.n_img, K, thr, key, draw, g.n_pix, mask_words, cnt);
+    SCSC_LAUNCH(k_mask_count, dim3(flat_grid(g.n_pix), (unsigned)((K + 31) / 32)), dim3(TPB), 0, s, g.d_img,
+                g.n_img, K, thr, key, draw, g.n_pix, mask_words, cnt);
     return hipGetLastError();
 }
 
 hipError_t launch_expand_mask(const Geometry &g, int K, const unsigned *mask_words, unsigned char *mask,
                               hipStream_t s) {
-    hipLaunchKernelGGL(k_expand_mask, dim3(g.n_tiles), dim3(TPB), 0, s, g.d_img, g.d_tiles, K, g.n_pix,
-                       mask_words, mask);
+    SCSC_LAUNCH(k_expand_mask, dim3(g.n_tiles), dim3(TPB), 0, s, g.d_img, g.d_tiles, K, g.n_pix,
+                mask_words, mask);
     return hipGetLastError();
 }
 
@@ -1030,69 +1030,69 @@ long long scan_tmp_elems(long long n) { return (n + SCAN_BLOCK - 1) / SCAN_BLOCK
 hipError_t launch_scan(const unsigned *cnt, unsigned *off, long long n, unsigned long long *tmp,
                        unsigned long long *total64, hipStream_t s) {
     const long long nb = (n + SCAN_BLOCK - 1) / SCAN_BLOCK;
-    if (nb > 0) hipLaunchKernelGGL(k_scan_local, dim3((unsigned)nb), dim3(TPB), 0, s, cnt, off, n, tmp);
-    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(TPB), 0, s, tmp, nb, off, n, total64);
-    if (n > 0) hipLaunchKernelGGL(k_scan_add, dim3((unsigned)((n + TPB - 1) / TPB)), dim3(TPB), 0, s, off, n, tmp);
+    if (nb > 0) SCSC_LAUNCH(k_scan_local, dim3((unsigned)nb), dim3(TPB), 0, s, cnt, off, n, tmp);
+    SCSC_LAUNCH(k_scan_blocks, dim3(1), dim3(TPB), 0, s, tmp, nb, off, n, total64);
+    if (n > 0) SCSC_LAUNCH(k_scan_add, dim3((unsigned)((n + TPB - 1) / TPB)), dim3(TPB), 0, s, off, n, tmp);
     return hipGetLastError();
 }
 
 hipError_t launch_gather_selected(const Geometry &g, int K, const unsigned *mask_words, const unsigned *soff,
                                   const float *z, Pair *pairs, unsigned short *cnt, unsigned long long *nnz_acc,
                                   hipStream_t s) {
-    hipLaunchKernelGGL(k_gather_selected, dim3(flat_grid(g.n_pix)), dim3(TPB), 0, s, g.d_img, g.n_img, K, g.n_pix,
-                       mask_words, soff, z, pairs, cnt, nnz_acc);
+    SCSC_LAUNCH(k_gather_selected, dim3(flat_grid(g.n_pix)), dim3(TPB), 0, s, g.d_img, g.n_img, K, g.n_pix,
+                mask_words, soff, z, pairs, cnt, nnz_acc);
     return hipGetLastError();
 }
 
 hipError_t launch_count_nonzero(const Geometry &g, int K, const float *z, unsigned *cnt, hipStream_t s) {
-    hipLaunchKernelGGL(k_count_nonzero, dim3(flat_grid(g.n_pix)), dim3(TPB), 0, s, g.d_img, g.n_img, g.n_pix, K, z,
-                       cnt);
+    SCSC_LAUNCH(k_count_nonzero, dim3(flat_grid(g.n_pix)), dim3(TPB), 0, s, g.d_img, g.n_img, g.n_pix, K, z,
+                cnt);
     return hipGetLastError();
 }
 
 hipError_t launch_fill_nonzero(const Geometry &g, int K, const float *z, const unsigned *off, Pair *pairs,
                                unsigned short *cnt, XPair *xp, unsigned xmul, hipStream_t s) {
-    hipLaunchKernelGGL(k_fill_nonzero, dim3(flat_grid(g.n_pix)), dim3(TPB), 0, s, g.d_img, g.n_img, g.n_pix, K, z,
-                       off, pairs, cnt, xp, xmul);
+    SCSC_LAUNCH(k_fill_nonzero, dim3(flat_grid(g.n_pix)), dim3(TPB), 0, s, g.d_img, g.n_img, g.n_pix, K, z,
+                off, pairs, cnt, xp, xmul);
     return hipGetLastError();
 }
 
 hipError_t launch_counts_u32(const unsigned short *cnt, long long n, unsigned *out, hipStream_t s) {
-    hipLaunchKernelGGL(k_counts_u32, dim3((unsigned)((n + TPB - 1) / TPB)), dim3(TPB), 0, s, cnt, n, out);
+    SCSC_LAUNCH(k_counts_u32, dim3((unsigned)((n + TPB - 1) / TPB)), dim3(TPB), 0, s, cnt, n, out);
     return hipGetLastError();
 }
 
 hipError_t launch_compact_lists(const Geometry &g, Lists in, const unsigned *off, Pair *pairs, unsigned short *cnt,
                                 XPair *xp, unsigned xmul, hipStream_t s) {
-    hipLaunchKernelGGL(k_compact_lists, dim3(flat_grid(g.n_pix)), dim3(TPB), 0, s, g.d_img, g.n_img, g.n_pix, in, off,
-                       pairs, cnt, xp, xmul);
+    SCSC_LAUNCH(k_compact_lists, dim3(flat_grid(g.n_pix)), dim3(TPB), 0, s, g.d_img, g.n_img, g.n_pix, in, off,
+                pairs, cnt, xp, xmul);
     return hipGetLastError();
 }
 
 hipError_t launch_scatter_dense(const Geometry &g, int K, Lists z, float *zout, hipStream_t s) {
-    hipLaunchKernelGGL(k_scatter_dense, dim3(flat_grid(g.n_pix)), dim3(TPB), 0, s, g.d_img, g.n_img, g.n_pix, K, z,
-                       zout);
+    SCSC_LAUNCH(k_scatter_dense, dim3(flat_grid(g.n_pix)), dim3(TPB), 0, s, g.d_img, g.n_img, g.n_pix, K, z,
+                zout);
     return hipGetLastError();
 }
 
 hipError_t launch_count_held(const Geometry &g, int K, const unsigned *mask_words, const float *z, unsigned *cnt,
                              hipStream_t s) {
-    hipLaunchKernelGGL(k_count_held, dim3(flat_grid(g.n_pix)), dim3(TPB), 0, s, g.d_img, g.n_img, g.n_pix, K,
-                       mask_words, z, cnt);
+    SCSC_LAUNCH(k_count_held, dim3(flat_grid(g.n_pix)), dim3(TPB), 0, s, g.d_img, g.n_img, g.n_pix, K,
+                mask_words, z, cnt);
     return hipGetLastError();
 }
 
 hipError_t launch_fill_held(const Geometry &g, int K, const unsigned *mask_words, const float *z, const unsigned *off,
                             Pair *pairs, unsigned short *cnt, hipStream_t s) {
-    hipLaunchKernelGGL(k_fill_held, dim3(flat_grid(g.n_pix)), dim3(TPB), 0, s, g.d_img, g.n_img, g.n_pix, K,
-                       mask_words, z, off, pairs, cnt);
+    SCSC_LAUNCH(k_fill_held, dim3(flat_grid(g.n_pix)), dim3(TPB), 0, s, g.d_img, g.n_img, g.n_pix, K,
+                mask_words, z, off, pairs, cnt);
     return hipGetLastError();
 }
 
 hipError_t launch_scatter_selected(const Geometry &g, int K, const unsigned *mask_words, Lists zl, float *z,
                                    hipStream_t s) {
-    hipLaunchKernelGGL(k_scatter_selected, dim3(flat_grid(g.n_pix)), dim3(TPB), 0, s, g.d_img, g.n_img, g.n_pix, K,
-                       mask_words, zl, z);
+    SCSC_LAUNCH(k_scatter_selected, dim3(flat_grid(g.n_pix)), dim3(TPB), 0, s, g.d_img, g.n_img, g.n_pix, K,
+                mask_words, zl, z);
     return hipGetLastError();
 }
 
@@ -1100,7 +1100,7 @@ hipError_t launch_sum_counts(const unsigned short *cnt, long long n, unsigned lo
     long long nb = (n + TPB - 1) / TPB;
     if (nb > 1024) nb = 1024;
     if (nb < 1) nb = 1;
-    hipLaunchKernelGGL(k_sum_counts, dim3((unsigned)nb), dim3(TPB), 0, s, cnt, n, out);
+    SCSC_LAUNCH(k_sum_counts, dim3((unsigned)nb), dim3(TPB), 0, s, cnt, n, out);
     return hipGetLastError();
 }
 
@@ -1111,8 +1111,8 @@ hipError_t synth_launch(const Geometry &g, int K, Lists z, const float *d, const
     const void *kfn = reinterpret_cast<const void *>(&k_synth<MM, DLDS, TS, TY, SP>);
     const int block = TS * TY * SP;
     const int grid = persistent_grid(kfn, block, 0, (long long)g.n_tiles * (TS / TY));
-    hipLaunchKernelGGL((k_synth<MM, DLDS, TS, TY, SP>), dim3(grid), dim3(block), 0, s, g.d_img, g.d_tiles, g.n_tiles,
-                       K, z, d, x, W, out, (int)mode);
+    SCSC_LAUNCH((k_synth<MM, DLDS, TS, TY, SP>), dim3(grid), dim3(block), 0, s, g.d_img, g.d_tiles, g.n_tiles,
+                K, z, d, x, W, out, (int)mode);
     return hipGetLastError();
 }
 
@@ -1144,8 +1144,8 @@ hipError_t adjoint_shrink_impl(const Geometry &g, int K, const unsigned *mw, con
     const int kc = K < KC ? K : KC;
     const size_t shm = (size_t)kc * M4 * sizeof(float);
     const int grid = persistent_grid(reinterpret_cast<const void *>(&k_adjoint_shrink<MM>), TPB, shm, g.n_tiles);
-    hipLaunchKernelGGL(k_adjoint_shrink<MM>, dim3(grid), dim3(TPB), shm, s, g.d_img, g.d_tiles, g.n_tiles, K,
-                       g.n_pix, mw, soff, oldp, oldc, newp, newc, r, d, ethr, KC, nnz_acc);
+    SCSC_LAUNCH(k_adjoint_shrink<MM>, dim3(grid), dim3(TPB), shm, s, g.d_img, g.d_tiles, g.n_tiles, K,
+                g.n_pix, mw, soff, oldp, oldc, newp, newc, r, d, ethr, KC, nnz_acc);
     return hipGetLastError();
 }
 
@@ -1155,11 +1155,11 @@ hipError_t adjoint_shrink_mfma_impl(const Geometry &g, int K, const unsigned *mw
                                     const float *r, const __bf16 *dA, const float *ethr,
                                     unsigned long long *nnz_acc, int variant, hipStream_t s) {
     if (variant == 0)
-        hipLaunchKernelGGL((k_adjoint_shrink_mfma<MM, true>), dim3(g.n_tiles), dim3(TPB), 0, s, g.d_img, g.d_tiles, K,
-                           g.n_pix, mw, soff, oldp, oldc, newp, newc, r, dA, ethr, nnz_acc);
+        SCSC_LAUNCH((k_adjoint_shrink_mfma<MM, true>), dim3(g.n_tiles), dim3(TPB), 0, s, g.d_img, g.d_tiles, K,
+                    g.n_pix, mw, soff, oldp, oldc, newp, newc, r, dA, ethr, nnz_acc);
     else
-        hipLaunchKernelGGL((k_adjoint_shrink_mfma<MM, false>), dim3(g.n_tiles), dim3(TPB), 0, s, g.d_img, g.d_tiles,
-                           K, g.n_pix, mw, soff, oldp, oldc, newp, newc, r, dA, ethr, nnz_acc);
+        SCSC_LAUNCH((k_adjoint_shrink_mfma<MM, false>), dim3(g.n_tiles), dim3(TPB), 0, s, g.d_img, g.d_tiles,
+                    K, g.n_pix, mw, soff, oldp, oldc, newp, newc, r, dA, ethr, nnz_acc);
     return hipGetLastError();
 }
 
@@ -1168,7 +1168,7 @@ hipError_t adj_prep_impl(const float *d, int K, __bf16 *dA, hipStream_t s) {
     constexpr int M = MM * MM, MP = 32 * ((M + 31) / 32);
     const int Kp = (K + MF_KB - 1) / MF_KB * MF_KB;
     const long long n = (long long)Kp * MP;
-    hipLaunchKernelGGL(k_adj_prep_a<MM>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, d, K, Kp, dA);
+    SCSC_LAUNCH(k_adj_prep_a<MM>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, d, K, Kp, dA);
     return hipGetLastError();
 }
 
@@ -1176,8 +1176,8 @@ template <int MM>
 hipError_t adjoint_dense_mfma_impl(const Geometry &g, int K, const float *r, const __bf16 *dA, float *out,
                                    hipStream_t s) {
     const int grid = persistent_grid(reinterpret_cast<const void *>(&k_adjoint_dense_mfma<MM>), TPB, 0, g.n_tiles);
-    hipLaunchKernelGGL(k_adjoint_dense_mfma<MM>, dim3(grid), dim3(TPB), 0, s, g.d_img, g.d_tiles, g.n_tiles, K, r,
-                       dA, out);
+    SCSC_LAUNCH(k_adjoint_dense_mfma<MM>, dim3(grid), dim3(TPB), 0, s, g.d_img, g.d_tiles, g.n_tiles, K, r,
+                dA, out);
     return hipGetLastError();
 }
 
@@ -1188,8 +1188,8 @@ hipError_t adjoint_dense_impl(const Geometry &g, int K, const float *r, const fl
     const int KC = filter_chunk<MM>();
     const int kc = K < KC ? K : KC;
     const size_t shm = (size_t)kc * M4 * sizeof(float);
-    hipLaunchKernelGGL(k_adjoint_dense<MM>, dim3(g.n_tiles), dim3(TPB), shm, s, g.d_img, g.d_tiles, K, r, d, out,
-                       KC);
+    SCSC_LAUNCH(k_adjoint_dense<MM>, dim3(g.n_tiles), dim3(TPB), shm, s, g.d_img, g.d_tiles, K, r, d, out,
+                KC);
     return hipGetLastError();
 }
 }  // namespace

@@ -162,8 +162,8 @@ __host__ __device__ __forceinline__ int lag_prefix(int a, int m) {
 template <int MM>
 hipError_t corr_fm_impl(const Geometry &g, int K, const unsigned *fm_off, const FmCode *fm, const float *r,
                         const unsigned char *W, bool weight_rhs, double *partial, hipStream_t s) {
-    hipLaunchKernelGGL(k_corr_fm<MM>, dim3(corr_chunks(K), K), dim3(128), 0, s, g.d_img, K, g.n_rows, fm_off, fm, r, W,
-                       weight_rhs ? 1 : 0, partial);
+    SCSC_LAUNCH(k_corr_fm<MM>, dim3(corr_chunks(K), K), dim3(128), 0, s, g.d_img, K, g.n_rows, fm_off, fm, r, W,
+                weight_rhs ? 1 : 0, partial);
     return hipGetLastError();
 }
 
@@ -201,34 +201,34 @@ __global__ __launch_bounds__(256) void k_reduce_f64_to_f32(const double *__restr
 }  // namespace
 
 hipError_t launch_reduce_partials_f64_to_f32(const double *partial, int nblocks, int n, float *out, hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce_f64_to_f32, dim3((n + 255) / 256), dim3(256), 0, s, partial, nblocks, n, out);
+    SCSC_LAUNCH(k_reduce_f64_to_f32, dim3((n + 255) / 256), dim3(256), 0, s, partial, nblocks, n, out);
     return hipGetLastError();
 }
 
 hipError_t launch_reduce_partials_f64_add(const double *partial, int nblocks, int n, double *inout, hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce_partials<double>, dim3((n + 15) / 16), dim3(256), 0, s, partial, nblocks, n, inout,
-                       1);
+    SCSC_LAUNCH(k_reduce_partials<double>, dim3((n + 15) / 16), dim3(256), 0, s, partial, nblocks, n, inout,
+                1);
     return hipGetLastError();
 }
 
 hipError_t launch_fill(float *v, int n, float val, hipStream_t s) {
-    hipLaunchKernelGGL(k_fill, dim3((n + 255) / 256), dim3(256), 0, s, v, n, val);
+    SCSC_LAUNCH(k_fill, dim3((n + 255) / 256), dim3(256), 0, s, v, n, val);
     return hipGetLastError();
 }
 
 hipError_t launch_power_update(float *v, const float *w, int n, double *lam, hipStream_t s) {
-    hipLaunchKernelGGL(k_power_update, dim3(1), dim3(1024), 0, s, v, w, n, lam);
+    SCSC_LAUNCH(k_power_update, dim3(1), dim3(1024), 0, s, v, w, n, lam);
     return hipGetLastError();
 }
 
 hipError_t launch_batch_update(float *d, const float *G, const double *lam, int K, int M, hipStream_t s) {
-    hipLaunchKernelGGL(k_batch_update, dim3(K), dim3(128), 0, s, d, G, lam, M);
+    SCSC_LAUNCH(k_batch_update, dim3(K), dim3(128), 0, s, d, G, lam, M);
     return hipGetLastError();
 }
 
 hipError_t launch_online_update(float *d, const double *y, const double *B, double Ld_sum, int K, int M,
                                 hipStream_t s) {
-    hipLaunchKernelGGL(k_online_update, dim3(K), dim3(128), 0, s, d, y, B, Ld_sum, M);
+    SCSC_LAUNCH(k_online_update, dim3(K), dim3(128), 0, s, d, y, B, Ld_sum, M);
     return hipGetLastError();
 }
 

@@ -109,12 +109,12 @@ template <int MM>
 hipError_t corr_mfma_impl(const Geometry &g, int K, Lists z, const float *r, float *part, int nblk, float *G,
                           hipStream_t s) {
     const int ngroups = (K + CM_FG - 1) / CM_FG;
-    hipLaunchKernelGGL(k_corr_mfma<MM>, dim3(nblk, ngroups), dim3(TPB), 0, s, g.d_img, g.d_tiles, g.n_tiles, K, z,
-                       r, part);
+    SCSC_LAUNCH(k_corr_mfma<MM>, dim3(nblk, ngroups), dim3(TPB), 0, s, g.d_img, g.d_tiles, g.n_tiles, K, z,
+                r, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int n = K * MM * MM;
-    hipLaunchKernelGGL(k_reduce_f32_partials_f64, dim3((n + 255) / 256), dim3(256), 0, s, part, nblk, n, G);
+    SCSC_LAUNCH(k_reduce_f32_partials_f64, dim3((n + 255) / 256), dim3(256), 0, s, part, nblk, n, G);
     return hipGetLastError();
 }
 
@@ -195,7 +195,7 @@ __global__ __launch_bounds__(TPB, FG == 1 ? 4 : 1) void k_synth_mfma(const ImgIn
     unsigned *skey = reinterpret_cast<unsigned *>(reinterpret_cast<char *>(lds8) + ZB);  // k << 10 | region pixel
     __bf16 *sval = reinterpret_cast<__bf16 *>(skey + SM_CAP);
 
-    const PixelCtx c = pixel_ctx(imgs, tiles);
+    const PixelCtx c = pixel_ctx(imgs, tiles, xcd_tile((int)blockIdx.x, (int)gridDim.x));
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int fcol = lane & 15, kg = lane >> 4;
     const int oy = c.t.ty * TS - C, ox = c.t.tx * TS - C;
@@ -351,7 +351,7 @@ __global__ __launch_bounds__(TPB, FG == 1 ? 4 : 1) void k_synth_mfma(const ImgIn
 template <int MM>
 hipError_t synth_mfma_prep_impl(const float *d, int K, __bf16 *dA, hipStream_t s) {
     const long long n = 16LL * ((K + 7) / 8) * 4 * sm_steps<MM>() * 8;
-    hipLaunchKernelGGL(k_synth_prep_a<MM>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, d, K, dA);
+    SCSC_LAUNCH(k_synth_prep_a<MM>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, d, K, dA);
     return hipGetLastError();
 }
 
@@ -359,14 +359,14 @@ template <int MM>
 hipError_t synth_mfma_impl(const Geometry &g, int K, Lists z, const __bf16 *dA, const float *x,
                            const unsigned char *W, float *out, int mode, int variant, hipStream_t s) {
     if (variant == 0)
-        hipLaunchKernelGGL((k_synth_mfma<MM, 2>), dim3(g.n_tiles), dim3(TPB), 0, s, g.d_img, g.d_tiles, K, z, dA, x, W,
-                           out, mode);
+        SCSC_LAUNCH((k_synth_mfma<MM, 2>), dim3(g.n_tiles), dim3(TPB), 0, s, g.d_img, g.d_tiles, K, z, dA, x, W,
+                    out, mode);
     else if (variant == 1)
-        hipLaunchKernelGGL((k_synth_mfma<MM, 4>), dim3(g.n_tiles), dim3(TPB), 0, s, g.d_img, g.d_tiles, K, z, dA, x, W,
-                           out, mode);
+        SCSC_LAUNCH((k_synth_mfma<MM, 4>), dim3(g.n_tiles), dim3(TPB), 0, s, g.d_img, g.d_tiles, K, z, dA, x, W,
+                    out, mode);
     else
-        hipLaunchKernelGGL((k_synth_mfma<MM, 1>), dim3(g.n_tiles), dim3(TPB), 0, s, g.d_img, g.d_tiles, K, z, dA, x, W,
-                           out, mode);
+        SCSC_LAUNCH((k_synth_mfma<MM, 1>), dim3(g.n_tiles), dim3(TPB), 0, s, g.d_img, g.d_tiles, K, z, dA, x, W,
+                    out, mode);
     return hipGetLastError();
 }
 

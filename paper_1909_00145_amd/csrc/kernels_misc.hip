@@ -176,10 +176,10 @@ __global__ __launch_bounds__(256) void k_dft_max(const double *part, int nch, lo
 template <int MM>
 hipError_t objective_impl(const Geometry &g, int K, const float *x, const unsigned char *W, const float *d,
                           const float *z, double *partial, double *out, hipStream_t s) {
-    hipLaunchKernelGGL(k_objective<MM>, dim3(g.n_tiles), dim3(TPB), 0, s, g.d_img, g.d_tiles, K, x, W, d, z, partial);
+    SCSC_LAUNCH(k_objective<MM>, dim3(g.n_tiles), dim3(TPB), 0, s, g.d_img, g.d_tiles, K, x, W, d, z, partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_reduce_pairs, dim3(1), dim3(1024), 0, s, partial, g.n_tiles, out);
+    SCSC_LAUNCH(k_reduce_pairs, dim3(1), dim3(1024), 0, s, partial, g.n_tiles, out);
     return hipGetLastError();
 }
 
@@ -208,15 +208,15 @@ hipError_t launch_lipschitz_code(const float *d, int K, int m, int P, double *tm
     const int nch = (K + DFT_KC - 1) / DFT_KC;
     double *part = tmp + 2LL * K * m * P;
     double2 *tw = reinterpret_cast<double2 *>(part + (long long)nch * n2);  // 2P doubles, 16-byte aligned
-    hipLaunchKernelGGL(k_dft_twiddles, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, P, tw, out);
+    SCSC_LAUNCH(k_dft_twiddles, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, P, tw, out);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_dft_rows, dim3((unsigned)((n1 + 255) / 256)), dim3(256), 0, s, d, K, m, P, tw, F1);
+    SCSC_LAUNCH(k_dft_rows, dim3((unsigned)((n1 + 255) / 256)), dim3(256), 0, s, d, K, m, P, tw, F1);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_dft_cols, dim3((unsigned)((n2 + 255) / 256), nch), dim3(256), 0, s, F1, K, m, P, tw, part);
+    SCSC_LAUNCH(k_dft_cols, dim3((unsigned)((n2 + 255) / 256), nch), dim3(256), 0, s, F1, K, m, P, tw, part);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_dft_max, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, s, part, nch, n2,
-                       reinterpret_cast<unsigned long long *>(out));
+    SCSC_LAUNCH(k_dft_max, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, s, part, nch, n2,
+                reinterpret_cast<unsigned long long *>(out));
     return hipGetLastError();
 }
 
@@ -261,18 +261,18 @@ unsigned ew_blocks(long long n) {
 
 hipError_t launch_ista_update(long long n, const float *z, const float *g, const unsigned char *mask, float eta,
                               float thr, float *out, hipStream_t s) {
-    hipLaunchKernelGGL(k_ista_update, dim3(ew_blocks(n)), dim3(256), 0, s, n, z, g, mask, eta, thr, out);
+    SCSC_LAUNCH(k_ista_update, dim3(ew_blocks(n)), dim3(256), 0, s, n, z, g, mask, eta, thr, out);
     return hipGetLastError();
 }
 
 hipError_t launch_ista_grad_u(long long n, const float *z, const float *g, const unsigned char *mask,
                               const float *gout, float eta, float thr, float *gu, hipStream_t s) {
-    hipLaunchKernelGGL(k_ista_grad_u, dim3(ew_blocks(n)), dim3(256), 0, s, n, z, g, mask, gout, eta, thr, gu);
+    SCSC_LAUNCH(k_ista_grad_u, dim3(ew_blocks(n)), dim3(256), 0, s, n, z, g, mask, gout, eta, thr, gu);
     return hipGetLastError();
 }
 
 hipError_t launch_set2(float *dst, float a, float b, hipStream_t s) {
-    hipLaunchKernelGGL(k_set2, dim3(1), dim3(64), 0, s, dst, a, b);
+    SCSC_LAUNCH(k_set2, dim3(1), dim3(64), 0, s, dst, a, b);
     return hipGetLastError();
 }
 
@@ -294,12 +294,12 @@ __global__ void k_set_step(float *dst, const double *L, double step, double lamb
 
 hipError_t launch_set_step(float *dst, const double *L, double step, double lambda, unsigned long long *counter,
                            hipStream_t s) {
-    hipLaunchKernelGGL(k_set_step, dim3(1), dim3(64), 0, s, dst, L, step, lambda, counter);
+    SCSC_LAUNCH(k_set_step, dim3(1), dim3(64), 0, s, dst, L, step, lambda, counter);
     return hipGetLastError();
 }
 
 hipError_t launch_axpby(long long n, float a, const float *x, float b, const float *y, float *out, hipStream_t s) {
-    hipLaunchKernelGGL(k_axpby, dim3(ew_blocks(n)), dim3(256), 0, s, n, a, x, b, y, out);
+    SCSC_LAUNCH(k_axpby, dim3(ew_blocks(n)), dim3(256), 0, s, n, a, x, b, y, out);
     return hipGetLastError();
 }
 

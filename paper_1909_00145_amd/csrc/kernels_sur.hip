@@ -996,16 +996,16 @@ __global__ void k_sur_matvec_reduce(int K, int M, const double *__restrict__ par
 template <int MM>
 hipError_t sur_block_impl(const Geometry &g, int K, int R, const unsigned *fm_off, const FmCode *fm,
                           const unsigned char *W, double *C, hipStream_t s) {
-    hipLaunchKernelGGL(k_sur_block<MM>, dim3(K, K), dim3(SB_THREADS), 0, s, g.d_img, g.n_img, K, R, fm_off, fm, W, C);
+    SCSC_LAUNCH(k_sur_block<MM>, dim3(K, K), dim3(SB_THREADS), 0, s, g.d_img, g.n_img, K, R, fm_off, fm, W, C);
     return hipGetLastError();
 }
 
 template <int MM>
 hipError_t sur_mv_impl(int K, const double *C, const float *d, double *part, double *y, hipStream_t s) {
-    hipLaunchKernelGGL(k_sur_matvec<MM>, dim3(K, K), dim3(MV_THREADS), 0, s, K, C, d, part);
+    SCSC_LAUNCH(k_sur_matvec<MM>, dim3(K, K), dim3(MV_THREADS), 0, s, K, C, d, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_sur_matvec_reduce, dim3(K), dim3(128), 0, s, K, MM * MM, part, y);
+    SCSC_LAUNCH(k_sur_matvec_reduce, dim3(K), dim3(128), 0, s, K, MM * MM, part, y);
     return hipGetLastError();
 }
 
@@ -1014,8 +1014,8 @@ hipError_t sur_mv_impl(int K, const double *C, const float *d, double *part, dou
 hipError_t launch_fm_lists(const Geometry &g, int K, Lists z, unsigned *fm_cnt, unsigned *fm_off, FmCode *fm,
                            unsigned long long *scan_tmp, unsigned long long *total64, hipStream_t s) {
     const int R = g.n_rows;
-    hipLaunchKernelGGL(k_fm_count, dim3(R), dim3(256), sizeof(unsigned) * (size_t)K, s, g.d_img, g.d_row_img, z, R,
-                       K, fm_cnt);
+    SCSC_LAUNCH(k_fm_count, dim3(R), dim3(256), sizeof(unsigned) * (size_t)K, s, g.d_img, g.d_row_img, z, R,
+                K, fm_cnt);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if ((e = launch_scan(fm_cnt, fm_off, (long long)K * R, scan_tmp, total64, s)) != hipSuccess) return e;
@@ -1023,8 +1023,8 @@ hipError_t launch_fm_lists(const Geometry &g, int K, Lists z, unsigned *fm_cnt, 
     const int nww = (g.max_side + 63) / 64;
     const size_t bm_bytes = sizeof(unsigned long long) * (size_t)K * nww;
     const bool use_bm = bm_bytes <= (size_t)FM_BM_BYTES;
-    hipLaunchKernelGGL(k_fm_fill, dim3(R), dim3(256), use_bm ? bm_bytes : 0, s, g.d_img, g.d_row_img, z, R, K,
-                       use_bm ? nww : 0, fm_off, fm);
+    SCSC_LAUNCH(k_fm_fill, dim3(R), dim3(256), use_bm ? bm_bytes : 0, s, g.d_img, g.d_row_img, z, R, K,
+                use_bm ? nww : 0, fm_off, fm);
     return hipGetLastError();
 }
 
@@ -1104,22 +1104,22 @@ hipError_t sur_lag_impl(const Geometry &g, int K, Lists z, const XPair *xp, cons
         const size_t shr = sizeof(double) * (size_t)L * pl.KR * K + sizeof(RunDesc) * LR_NB +
                            sizeof(unsigned) * (2 * (size_t)LR_SEG + 1);
         const unsigned nb = (unsigned)((long long)pl.PR * pl.nkr * (Cc * 2 + 1));
-        hipLaunchKernelGGL(k_lag_rows<MM>, dim3(nb), dim3(LR_THREADS), shr, s, g.d_img, g.n_rows, K, pl.KR, pl.nkr,
-                           pl.PR, fm_off, fm, z.off, xp, part);
+        SCSC_LAUNCH(k_lag_rows<MM>, dim3(nb), dim3(LR_THREADS), shr, s, g.d_img, g.n_rows, K, pl.KR, pl.nkr,
+                    pl.PR, fm_off, fm, z.off, xp, part);
         nparts = pl.PR;
     } else {
-        hipLaunchKernelGGL(k_lag_outer<MM>, dim3(pl.nlag, pl.nkc, (unsigned)pl.P), dim3(LO_THREADS), shm, s, g.d_img,
-                           g.n_img, (long long)g.n_pix, g.max_side, K, z, 0, pl.KC, part);
+        SCSC_LAUNCH(k_lag_outer<MM>, dim3(pl.nlag, pl.nkc, (unsigned)pl.P), dim3(LO_THREADS), shm, s, g.d_img,
+                    g.n_img, (long long)g.n_pix, g.max_side, K, z, 0, pl.KC, part);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const unsigned nt = (unsigned)((K + LS_T - 1) / LS_T);
-    hipLaunchKernelGGL(k_lag_sum<MM>, dim3(pl.nlag, nt, nt), dim3(256), 0, s, K, nparts, part, Rl);
+    SCSC_LAUNCH(k_lag_sum<MM>, dim3(pl.nlag, nt, nt), dim3(256), 0, s, K, nparts, part, Rl);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (sums_done && (e = hipEventRecord(sums_done, s)) != hipSuccess) return e;
     if (Cc > 0 && Es) {
-        hipLaunchKernelGGL(k_lag_outer<MM>, dim3(LL, pl.nkc, 4 * Cc), dim3(LO_THREADS), shm, s, g.d_img, g.n_img,
-                           (long long)g.n_pix, g.max_side, K, z, 1, pl.KC, Es);
+        SCSC_LAUNCH(k_lag_outer<MM>, dim3(LL, pl.nkc, 4 * Cc), dim3(LO_THREADS), shm, s, g.d_img, g.n_img,
+                    (long long)g.n_pix, g.max_side, K, z, 1, pl.KC, Es);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     return hipSuccess;
@@ -1135,14 +1135,14 @@ template <int MM>
 hipError_t sur_expand_impl(int K, const double *Rl, const double *Es, unsigned short *tab, double *C, const float *d,
                            double *part, double *y, hipStream_t s) {
     constexpr int L = 2 * MM - 1, LL = L * L;
-    hipLaunchKernelGGL(k_lag_table<MM>, dim3((LL + 63) / 64), dim3(64), 0, s, tab);
+    SCSC_LAUNCH(k_lag_table<MM>, dim3((LL + 63) / 64), dim3(64), 0, s, tab);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_sur_expand<MM>, dim3(xcd_grid(tri_block(K, K, K))), dim3(EX_THREADS), 0, s, K, Rl, Es, tab,
-                       C, d, part);
+    SCSC_LAUNCH(k_sur_expand<MM>, dim3(xcd_grid(tri_block(K, K, K))), dim3(EX_THREADS), 0, s, K, Rl, Es, tab,
+                C, d, part);
     if (d) {
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_sur_matvec_reduce, dim3(K), dim3(128), 0, s, K, MM * MM, part, y);
+        SCSC_LAUNCH(k_sur_matvec_reduce, dim3(K), dim3(128), 0, s, K, MM * MM, part, y);
     }
     return hipGetLastError();
 }
@@ -1150,15 +1150,15 @@ hipError_t sur_expand_impl(int K, const double *Rl, const double *Es, unsigned s
 template <int MM>
 hipError_t lag_matvec_impl(int K, const float *Rf, const float *w, const double *nparts, int n_nparts, double *part,
                            hipStream_t s) {
-    hipLaunchKernelGGL(k_lag_matvec<MM>, dim3(K, (K + RM_KB - 1) / RM_KB), dim3(MM * RM_KB), 0, s, K, Rf, w, nparts,
-                       n_nparts, part);
+    SCSC_LAUNCH(k_lag_matvec<MM>, dim3(K, (K + RM_KB - 1) / RM_KB), dim3(MM * RM_KB), 0, s, K, Rf, w, nparts,
+                n_nparts, part);
     return hipGetLastError();
 }
 
 template <int MM>
 hipError_t lag_to_f32_impl(int K, const double *Rl, float *Rf, hipStream_t s) {
     constexpr int L = 2 * MM - 1, LL = L * L;
-    hipLaunchKernelGGL(k_lag_to_f32_t<MM>, dim3(K, (K + 31) / 32, (LL + 31) / 32), dim3(256), 0, s, K, Rl, Rf);
+    SCSC_LAUNCH(k_lag_to_f32_t<MM>, dim3(K, (K + 31) / 32, (LL + 31) / 32), dim3(256), 0, s, K, Rl, Rf);
     return hipGetLastError();
 }
 
@@ -1166,7 +1166,7 @@ template <int MM>
 hipError_t sur_corner_impl(const Geometry &g, int K, Lists z, double *C, hipStream_t s) {
     constexpr int Cc = MM / 2;
     if (Cc == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_sur_corner<MM>, dim3(g.n_img, 4, Cc * Cc), dim3(256), 0, s, g.d_img, K, z, C);
+    SCSC_LAUNCH(k_sur_corner<MM>, dim3(g.n_img, 4, Cc * Cc), dim3(256), 0, s, g.d_img, K, z, C);
     return hipGetLastError();
 }
 }  // namespace
@@ -1228,18 +1228,18 @@ int power_reduce_blocks(int n) { return (n + PR_THREADS - 1) / PR_THREADS; }
 hipError_t launch_power_reduce(const double *part, int nch, int n, float *w_out, const float *w_prev,
                                const double *nparts_prev, int n_nparts, double *nparts_out, double *dparts_out,
                                hipStream_t s) {
-    hipLaunchKernelGGL(k_power_reduce, dim3(power_reduce_blocks(n)), dim3(PR_THREADS), 0, s, part, nch, n, w_out,
-                       w_prev, nparts_prev, n_nparts, nparts_out, dparts_out);
+    SCSC_LAUNCH(k_power_reduce, dim3(power_reduce_blocks(n)), dim3(PR_THREADS), 0, s, part, nch, n, w_out,
+                w_prev, nparts_prev, n_nparts, nparts_out, dparts_out);
     return hipGetLastError();
 }
 
 hipError_t launch_power_start(double *nparts, int nb, double nn0, hipStream_t s) {
-    hipLaunchKernelGGL(k_power_start, dim3(1), dim3(256), 0, s, nparts, nb, nn0);
+    SCSC_LAUNCH(k_power_start, dim3(1), dim3(256), 0, s, nparts, nb, nn0);
     return hipGetLastError();
 }
 
 hipError_t launch_power_final(const double *nparts, const double *dparts, int nb, double *lam, hipStream_t s) {
-    hipLaunchKernelGGL(k_power_final, dim3(1), dim3(64), 0, s, nparts, dparts, nb, lam);
+    SCSC_LAUNCH(k_power_final, dim3(1), dim3(64), 0, s, nparts, dparts, nb, lam);
     return hipGetLastError();
 }
 

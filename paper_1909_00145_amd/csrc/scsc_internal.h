@@ -2,6 +2,7 @@
 // the compact per-pixel code lists, device helpers and kernel launchers.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -11,6 +12,29 @@
 #include "scsc.h"
 
 namespace scsc {
+
+// Kernel-level timing of one profiled launch scope.  While such a scope is open on
+// this thread, SCSC_LAUNCH has each kernel record its own start (the scope's first
+// kernel only) and end (every kernel, so the last one's end is kept) in these events
+// on the launch's stream: the scope's time is then the kernels' execution from the
+// first one's start to the last one's end, without the dispatch gaps around them.
+struct KernelTiming {
+    hipEvent_t start = nullptr;
+    hipEvent_t stop = nullptr;
+    bool used = false;
+};
+extern thread_local KernelTiming *kernel_timing;
+
+#define SCSC_LAUNCH(kernel, grid, block, shm, stream, ...)                                            \
+    do {                                                                                              \
+        if (::scsc::KernelTiming *kt_ = ::scsc::kernel_timing) {                                      \
+            hipExtLaunchKernelGGL(kernel, grid, block, shm, stream, kt_->used ? nullptr : kt_->start, \
+                                  kt_->stop, 0u, __VA_ARGS__);                                        \
+            kt_->used = true;                                                                         \
+        } else {                                                                                      \
+            hipLaunchKernelGGL(kernel, grid, block, shm, stream, __VA_ARGS__);                        \
+        }                                                                                             \
+    } while (0)
 
 // Every per-pixel kernel works on square output tiles of TS x TS pixels, one
 // workgroup of TS*TS threads (4 wave64s) per tile, thread (ty, tx) <-> pixel.
@@ -175,6 +199,14 @@ __device__ __forceinline__ long long xcd_item(long long n) {
     const long long per = gridDim.x / N_XCD;
     const long long item = (long long)(blockIdx.x % N_XCD) * per + blockIdx.x / N_XCD;
     return item < n ? item : -1;
+}
+// Tile of a launch with one workgroup per tile over n tiles (any n): XCD x takes the
+// x-th of eight runs of consecutive tiles (q + 1 tiles for x < n mod 8, else q, with
+// q = n / 8), so the halo data that neighbouring tiles share is fetched into one L2.
+// A bijection on [0, n): workgroup 8 i + x is tile start(x) + i.
+__device__ __forceinline__ int xcd_tile(int b, int n) {
+    const int x = b % N_XCD, i = b / N_XCD, q = n / N_XCD, r = n % N_XCD;
+    return x * q + min(x, r) + i;
 }
 __device__ __forceinline__ void xcd_work(long long total, long long &first, long long &step, long long &end) {
     const int G = gridDim.x;
