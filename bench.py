@@ -437,7 +437,8 @@ def inpainting(ctx, w, n_train, precision):
     and 5 observation masks, for the filters after n_train mini-batches of online
     learning (the online workload's stream and settings), for the initial filters,
     and for filling the unobserved pixels with zeros.  The reconstruction time is the
-    median over the timed reconstructions, after six untimed ones that settle the
+    median over the timed reconstructions (and per filter set: the code sparsity, and
+    so the work, differs between them), after six untimed ones that settle the
     launch-variant tuning of the 256 x 256 batch."""
     import torch
 
@@ -459,7 +460,7 @@ def inpainting(ctx, w, n_train, precision):
     im = Images.uniform(NT, HT, WT)
     x = torch.from_numpy(si.batch(33, NT, HT, WT).astype(np.float32).reshape(-1)).cuda()
     res = {"learned": [], "initial": [], "zero_fill": []}
-    times = []
+    times, by = [], {"learned": [], "initial": []}
     # the first five code steps of this shape tune its launch variants: untimed
     W0 = torch.from_numpy(np.stack([si.observation_mask(50, n, HT, WT) for n in range(NT)]).reshape(-1)).cuda()
     for _ in range(6):
@@ -474,12 +475,14 @@ def inpainting(ctx, w, n_train, precision):
             xh, _ = inpaint(ctx, im, x, Wm, d, lam, iters, precision=precision)
             torch.cuda.synchronize()
             times.append(time.perf_counter() - t0)
+            by[name].append(times[-1])
             res[name] += psnr(im, xh, x)
     return {"images": "%d held-out synthetic %dx%d fields (1/f^2)" % (NT, HT, WT), "observed": 0.5,
             "lambda": lam, "iterations": iters, "trials": trials, "precision": precision,
             "train": "%d online mini-batches (%.2f s)" % (n_train, train_s),
             "psnr_db": {k: round(float(np.mean(v)), 3) for k, v in res.items()},
-            "ms_per_reconstruction": round(1e3 * float(np.median(times)), 1)}
+            "ms_per_reconstruction": round(1e3 * float(np.median(times)), 1),
+            "ms_per_reconstruction_by_filters": {k: round(1e3 * float(np.median(v)), 1) for k, v in by.items()}}
 
 
 def eta_sweep(ctx, w, K, etas, n_samples, precision):
