@@ -1018,6 +1018,10 @@ def main():
         progress("hold/project comparison done")
     if not args.no_inpaint:
         out["inpainting"] = inpainting(ctx, WORKLOADS["online"], args.inpaint_train, args.precision)
+        other = "fp32" if args.precision == "bf16" else "bf16"
+        ip2 = inpainting(ctx, WORKLOADS["online"], args.inpaint_train, other)
+        out["inpainting"]["other_precision"] = {k: ip2[k] for k in ("precision", "psnr_db", "ms_per_reconstruction",
+                                                                    "ms_per_reconstruction_by_filters")}
         progress("inpainting done")
     if not args.no_solver_compare:
         out["solver_compare"] = solver_compare(ctx, WORKLOADS["online"])
