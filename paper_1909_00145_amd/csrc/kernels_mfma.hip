@@ -96,13 +96,26 @@ __global__ __launch_bounds__(TPB) void k_corr_mfma(const ImgInfo *imgs, const Ti
     }
 }
 
+// out[i] = sum_b part[b][i] in FP64: blocks of 16 elements x 16 slices; slice j adds
+// the partials b = j, j + 16, ... in order and the 16 slice sums are then added in
+// order, so the result is deterministic with 16 times the parallelism of one thread
+// per element (one workgroup per tile leaves hundreds of partials).
 __global__ __launch_bounds__(256) void k_reduce_f32_partials_f64(const float *__restrict__ part, int nblocks, int n,
                                                                  float *__restrict__ out) {
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= n) return;
+    __shared__ double red[16][17];
+    const int e = threadIdx.x & 15, slice = threadIdx.x >> 4;
+    const int i = blockIdx.x * 16 + e;
     double s = 0.0;
-    for (int b = 0; b < nblocks; ++b) s += (double)part[(long long)b * n + i];
-    out[i] = (float)s;
+    if (i < n)
+#pragma unroll 4
+        for (int b = slice; b < nblocks; b += 16) s += (double)part[(long long)b * n + i];
+    red[slice][e] = s;
+    __syncthreads();
+    if (slice == 0 && i < n) {
+        double t = 0.0;
+        for (int j = 0; j < 16; ++j) t += red[j][e];
+        out[i] = (float)t;
+    }
 }
 
 template <int MM>
@@ -114,7 +127,7 @@ hipError_t corr_mfma_impl(const Geometry &g, int K, Lists z, const float *r, flo
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int n = K * MM * MM;
-    SCSC_LAUNCH(k_reduce_f32_partials_f64, dim3((n + 255) / 256), dim3(256), 0, s, part, nblk, n, G);
+    SCSC_LAUNCH(k_reduce_f32_partials_f64, dim3((n + 15) / 16), dim3(256), 0, s, part, nblk, n, G);
     return hipGetLastError();
 }
 
