@@ -1857,6 +1857,28 @@ int check_layer_args(csc_ctx *h, const csc_images *im, int K, int m, int precisi
     return CSC_OK;
 }
 
+// Whether a layer's synthesis over the lists just built may tune its launch variant:
+// only when they hold a non-zero code (a stack of layers starts from zero codes, on
+// which every variant takes the same time, so a choice made there is noise).  The
+// count is read back only while the key is still untuned.
+int layer_synth_representative(csc_ctx *h, int K, int m, SynthMode mode, int precision, bool *rep) {
+    *rep = true;
+    if (!h->autotune || h->force_variant >= 0 || h->tuned.count(synth_key(h, K, m, mode, precision))) return CSC_OK;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(h->stream, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) {
+        hipGetLastError();
+        *rep = false;
+        return CSC_OK;
+    }
+    WS(sc, double, WS_SCAL, SC_COUNT);
+    int st = read_scalars(h, sc, SC_COUNT);
+    if (st) return st;
+    unsigned long long nz = 0;
+    std::memcpy(&nz, &h->h_pinned[SC_TOTAL], sizeof(nz));
+    *rep = nz > 0;
+    return CSC_OK;
+}
+
 // r = W (x - D z) into R and g = D^T r (dense) into G.
 int layer_residual_gradient(csc_ctx *h, int K, int m, const float *x, const uint8_t *W, const float *d,
                             const __bf16 *dA, const float *z, int precision, float **R_out, float **G_out) {
@@ -1864,11 +1886,13 @@ int layer_residual_gradient(csc_ctx *h, int K, int m, const float *x, const uint
     Lists L;
     int st = build_nonzero_lists(h, K, z, &L);
     if (st) return st;
+    bool rep = true;
+    if ((st = layer_synth_representative(h, K, m, SYNTH_RESIDUAL, precision, &rep))) return st;
     WS(R, float, WS_R, g.n_pix);
     WS(G, float, WS_DG, (size_t)K * g.n_pix);
     {
         PROF(CSC_PK_SYNTH);
-        HIPCHK(synth(h, K, m, L, d, x, W, R, SYNTH_RESIDUAL, true, precision));
+        HIPCHK(synth(h, K, m, L, d, x, W, R, SYNTH_RESIDUAL, rep, precision));
     }
     if ((st = adjoint_dense(h, K, m, R, d, dA, G))) return st;
     *R_out = R;
@@ -1939,8 +1963,10 @@ extern "C" int csc_ista_backward(csc_handle h, const csc_images *im, const float
     {
         Lists Lu;
         if ((st = build_nonzero_lists(h, K, GU, &Lu))) return st;
+        bool rep = true;
+        if ((st = layer_synth_representative(h, K, m, SYNTH_WEIGHTED, precision, &rep))) return st;
         PROF(CSC_PK_SYNTH);
-        HIPCHK(synth(h, K, m, Lu, d, nullptr, W, T, SYNTH_WEIGHTED, true, precision));
+        HIPCHK(synth(h, K, m, Lu, d, nullptr, W, T, SYNTH_WEIGHTED, rep, precision));
     }
     // g_d = eta (Z(g_u)^T r - Z(z)^T t)
     WS(G1, float, WS_G, K * M);
