@@ -772,8 +772,13 @@ __global__ __launch_bounds__(EX_THREADS) void k_sur_expand(int K, const double *
                                                            double *__restrict__ part) {
     constexpr int C = MM / 2, M = MM * MM, M2 = M * M, L = 2 * MM - 1, LL = L * L;
     constexpr int NC = C > 0 ? C : 1;
+    // Band prefix sums ec[side][a][b] = sum_{j <= a} E_side,j(delta) over the lags delta at
+    // which a band sum can be non-zero: |dy| < c for the top and bottom bands (b = (dy +
+    // c - 1) L + dx + 2c), |dx| < c for the left and right ones (b = (dy + 2c)(2c - 1) +
+    // dx + c - 1); at every other lag all of them are 0.
+    constexpr int NB = (C > 0 ? 2 * C - 1 : 1) * L;
     __shared__ double r[LL];
-    __shared__ double ec[4][NC][LL];  // band prefix sums: ec[side][a][delta] = sum_{j <= a} E_side,j(delta)
+    __shared__ double ec[4][NC][NB];
     __shared__ double ya[M], yb[M], dka[M], dkb[M];
     // decode the upper-triangle block index into (k, k2); neighbouring blocks
     // (which read neighbouring lag and band sums) share an XCD
@@ -785,7 +790,7 @@ __global__ __launch_bounds__(EX_THREADS) void k_sur_expand(int K, const double *
     for (int i = threadIdx.x; i < LL; i += EX_THREADS) r[i] = Rl[((long long)i * K + k) * K + k2];
     // band sums: all loads of the block issued EX_BATCH at a time, then the
     // prefix over the band rows j in LDS
-    constexpr int NE = 4 * NC * LL;
+    constexpr int NE = 4 * NC * NB;
     for (int i0 = threadIdx.x; i0 < NE && C > 0; i0 += EX_THREADS * EX_BATCH) {
         double ev[EX_BATCH];
 #pragma unroll
@@ -793,9 +798,11 @@ __global__ __launch_bounds__(EX_THREADS) void k_sur_expand(int K, const double *
             const int i = i0 + u * EX_THREADS;
             ev[u] = 0.0;
             if (i >= NE) continue;
-            const int cls = i / LL, di = i % LL;  // cls = side * c + j
+            const int cls = i / NB, b = i % NB;  // cls = side * c + j
             const int sd = cls / NC, j = cls % NC;
-            const int dy = di / L - 2 * C, dx = di % L - 2 * C;
+            const int dy = sd < 2 ? b / L - (C - 1) : b / (2 * C - 1) - 2 * C;
+            const int dx = sd < 2 ? b % L - 2 * C : b % (2 * C - 1) - (C - 1);
+            const int di = (dy + 2 * C) * L + dx + 2 * C;
             const int dlt = sd == 0 ? -dy : sd == 1 ? dy : sd == 2 ? -dx : dx;
             // band rows j >= min(c, c + dlt) are never read for this lag, and for dlt > j
             // the partner pixel lies outside every image (the sum is 0); neither was formed
@@ -808,12 +815,12 @@ __global__ __launch_bounds__(EX_THREADS) void k_sur_expand(int K, const double *
         }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < 4 * LL && C > 0; i += EX_THREADS) {
-        const int sd = i / LL, di = i % LL;
+    for (int i = threadIdx.x; i < 4 * NB && C > 0; i += EX_THREADS) {
+        const int sd = i / NB, b = i % NB;
         double acc = 0.0;
         for (int j = 0; j < NC; ++j) {
-            acc += ec[sd][j][di];
-            ec[sd][j][di] = acc;
+            acc += ec[sd][j][b];
+            ec[sd][j][b] = acc;
         }
     }
     if (d)  // the product C_bar d of the updated block (first filter iteration), fused
@@ -843,10 +850,12 @@ __global__ __launch_bounds__(EX_THREADS) void k_sur_expand(int K, const double *
             // R minus the codes whose partner window is cut by the image border:
             // the first -s_y rows (top), last s_y rows (bottom), likewise columns
             double v = r[di];
-            if (sy < 0) v -= ec[0][-sy - 1][di];
-            if (sy > 0) v -= ec[1][sy - 1][di];
-            if (sx < 0) v -= ec[2][-sx - 1][di];
-            if (sx > 0) v -= ec[3][sx - 1][di];
+            const bool by = dy > -C && dy < C, bx = dx > -C && dx < C;  // else the band sums are 0
+            const int iy = (dy + C - 1) * L + dx + 2 * C, ix = (dy + 2 * C) * (2 * C - 1) + dx + C - 1;
+            if (sy < 0 && by) v -= ec[0][-sy - 1][iy];
+            if (sy > 0 && by) v -= ec[1][sy - 1][iy];
+            if (sx < 0 && bx) v -= ec[2][-sx - 1][ix];
+            if (sx > 0 && bx) v -= ec[3][sx - 1][ix];
             val[u] = v;
             si[u] = (sy + C) * MM + sx + C;
             s2i[u] = (sy - dy + C) * MM + sx - dx + C;
