@@ -325,7 +325,19 @@ __global__ __launch_bounds__(LO_THREADS, 8) void k_lag_outer(const ImgInfo *imgs
     constexpr int C = MM / 2, L = 2 * MM - 1, LL = L * L;
     constexpr int NC = C > 0 ? C : 1;
     extern __shared__ double Rd[];  // [KC][K]
-    const int di = band ? (int)blockIdx.x : (LL - 1) / 2 + (int)blockIdx.x;
+    // band: blockIdx.x = t L + e takes the t-th of the c offsets dlt in (j - c, j] across
+    // the band (the only ones whose band row j is read and can be non-zero) and the
+    // e-th along it
+    int di;
+    if (band) {
+        const int sd = (int)blockIdx.z / NC, jj = (int)blockIdx.z % NC;
+        const int t = (int)blockIdx.x / L, e = (int)blockIdx.x % L - 2 * C;
+        const int dl = jj - C + 1 + t;
+        const int dyb = sd == 0 ? -dl : sd == 1 ? dl : e, dxb = sd == 2 ? -dl : sd == 3 ? dl : e;
+        di = (dyb + 2 * C) * L + dxb + 2 * C;
+    } else {
+        di = (LL - 1) / 2 + (int)blockIdx.x;
+    }
     const int dy = di / L - 2 * C, dx = di % L - 2 * C;
     if (band) {
         // The expansion uses band row j of a side only where it lies inside the
@@ -1127,7 +1139,7 @@ hipError_t sur_lag_impl(const Geometry &g, int K, Lists z, const XPair *xp, cons
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (sums_done && (e = hipEventRecord(sums_done, s)) != hipSuccess) return e;
     if (Cc > 0 && Es) {
-        SCSC_LAUNCH(k_lag_outer<MM>, dim3(LL, pl.nkc, 4 * Cc), dim3(LO_THREADS), shm, s, g.d_img, g.n_img,
+        SCSC_LAUNCH(k_lag_outer<MM>, dim3(Cc * L, pl.nkc, 4 * Cc), dim3(LO_THREADS), shm, s, g.d_img, g.n_img,
                     (long long)g.n_pix, g.max_side, K, z, 1, pl.KC, Es);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
