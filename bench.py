@@ -64,32 +64,32 @@ PEAK_LAG_PRODUCTS = PEAK_LDS_BYTES / 16
 # BF16 synthesis and adjoint are taken on their full-batch launches (the per-class timing pass
 # launches those; the eager headline splits the batch over three streams).
 TRAFFIC = {
-    ("online", "synth", "bf16"): ("kernels_mfma.hip", "a5c6d6ec6d723eb8", 18.15e6, 0.8036e6),  # k_synth_mfma<11, 1> (full batch)
-    ("online", "adjoint", "bf16"): ("kernels_code.hip", "0bb0489ac2ba911a", 20.98e6, 10.64e6),  # k_adjoint_shrink_mfma<11, true> (full batch)
+    ("online", "synth", "bf16"): ("kernels_mfma.hip", "a5c6d6ec6d723eb8", 18.56e6, 0.8036e6),  # k_synth_mfma<11, 1> (full batch)
+    ("online", "adjoint", "bf16"): ("kernels_code.hip", "41c438702764e40d", 20.98e6, 10.64e6),  # k_adjoint_shrink_mfma<11, true> (full batch)
     ("online", "corr", "bf16"): ("kernels_dict.hip", "5dba40135f457554", 27.01e6, 4.067e6),  # k_corr_fm<11>
-    ("online", "sur_expand", "bf16"): ("kernels_sur.hip", "d57f51a0e58c130e", 772.6e6, 653.3e6),  # k_sur_expand<11>
+    ("online", "sur_expand", "bf16"): ("kernels_sur.hip", "d57f51a0e58c130e", 772.5e6, 653.2e6),  # k_sur_expand<11>
     ("online", "power", "bf16"): ("kernels_sur.hip", "d57f51a0e58c130e", 18.22e6, 0.6944e6),  # k_lag_matvec<11>
-    ("online", "synth", "fp32"): ("kernels_code.hip", "0bb0489ac2ba911a", 18.47e6, 0.807e6),  # k_synth<11, true, 16, 8, 4>
-    ("online", "adjoint", "fp32"): ("kernels_code.hip", "0bb0489ac2ba911a", 20.93e6, 10.63e6),  # k_adjoint_shrink<11>
+    ("online", "synth", "fp32"): ("kernels_code.hip", "41c438702764e40d", 18.07e6, 0.802e6),  # k_synth<11, true, 16, 8, 4>
+    ("online", "adjoint", "fp32"): ("kernels_code.hip", "41c438702764e40d", 20.93e6, 10.63e6),  # k_adjoint_shrink<11>
     ("online", "corr", "fp32"): ("kernels_dict.hip", "5dba40135f457554", 27.01e6, 4.067e6),  # k_corr_fm<11>
-    ("online", "sur_expand", "fp32"): ("kernels_sur.hip", "d57f51a0e58c130e", 772.6e6, 653.4e6),  # k_sur_expand<11>
+    ("online", "sur_expand", "fp32"): ("kernels_sur.hip", "d57f51a0e58c130e", 772.5e6, 653.2e6),  # k_sur_expand<11>
     ("online", "power", "fp32"): ("kernels_sur.hip", "d57f51a0e58c130e", 18.22e6, 0.6944e6),  # k_lag_matvec<11>
-    ("batch", "synth", "bf16"): ("kernels_mfma.hip", "a5c6d6ec6d723eb8", 9.972e6, 0.4036e6),  # k_synth_mfma<11, 4> (full batch)
-    ("batch", "adjoint", "bf16"): ("kernels_code.hip", "0bb0489ac2ba911a", 10.91e6, 5.289e6),  # k_adjoint_shrink_mfma<11, true> (full batch)
+    ("batch", "synth", "bf16"): ("kernels_mfma.hip", "a5c6d6ec6d723eb8", 9.634e6, 0.4036e6),  # k_synth_mfma<11, 2> (full batch)
+    ("batch", "adjoint", "bf16"): ("kernels_code.hip", "41c438702764e40d", 10.91e6, 5.289e6),  # k_adjoint_shrink_mfma<11, true> (full batch)
     ("batch", "power", "bf16"): ("kernels_sur.hip", "d57f51a0e58c130e", 18.22e6, 0.6944e6),  # k_lag_matvec<11>
-    ("batch", "corr", "bf16"): ("kernels_mfma.hip", "a5c6d6ec6d723eb8", 7.659e6, 23.73e6),  # k_corr_mfma<11>
-    ("batch", "synth", "fp32"): ("kernels_code.hip", "0bb0489ac2ba911a", 9.525e6, 0.4031e6),  # k_synth<11, true, 16, 8, 4>
-    ("batch", "adjoint", "fp32"): ("kernels_code.hip", "0bb0489ac2ba911a", 10.91e6, 5.289e6),  # k_adjoint_shrink<11>
+    ("batch", "corr", "bf16"): ("kernels_mfma.hip", "a5c6d6ec6d723eb8", 7.659e6, 23.72e6),  # k_corr_mfma<11>
+    ("batch", "synth", "fp32"): ("kernels_code.hip", "41c438702764e40d", 9.881e6, 0.4031e6),  # k_synth<11, true, 16, 8, 4>
+    ("batch", "adjoint", "fp32"): ("kernels_code.hip", "41c438702764e40d", 10.91e6, 5.289e6),  # k_adjoint_shrink<11>
     ("batch", "power", "fp32"): ("kernels_sur.hip", "d57f51a0e58c130e", 18.22e6, 0.6944e6),  # k_lag_matvec<11>
     ("batch", "corr", "fp32"): ("kernels_dict.hip", "5dba40135f457554", 13.77e6, 4.067e6),  # k_corr_fm<11>
-    ("ragged", "synth", "bf16"): ("kernels_mfma.hip", "a5c6d6ec6d723eb8", 1845e6, 85.06e6),  # k_synth_mfma<11, 1> (full batch)
-    ("ragged", "adjoint", "bf16"): ("kernels_code.hip", "0bb0489ac2ba911a", 2170e6, 1350e6),  # k_adjoint_shrink_mfma<11, true> (full batch)
-    ("ragged", "gather", "bf16"): ("kernels_code.hip", "0bb0489ac2ba911a", 9798e6, 184.7e6),  # k_gather_selected
-    ("ragged", "scatter", "bf16"): ("kernels_code.hip", "0bb0489ac2ba911a", 1920e6, 8767e6),  # k_scatter_dense
-    ("ragged", "synth", "fp32"): ("kernels_code.hip", "0bb0489ac2ba911a", 3476e6, 129.6e6),  # k_synth<11, true, 16, 8, 4>
-    ("ragged", "adjoint", "fp32"): ("kernels_code.hip", "0bb0489ac2ba911a", 2224e6, 1405e6),  # k_adjoint_shrink<11>
-    ("ragged", "gather", "fp32"): ("kernels_code.hip", "0bb0489ac2ba911a", 9798e6, 184.7e6),  # k_gather_selected
-    ("ragged", "scatter", "fp32"): ("kernels_code.hip", "0bb0489ac2ba911a", 1921e6, 8764e6),  # k_scatter_dense
+    ("ragged", "synth", "bf16"): ("kernels_mfma.hip", "a5c6d6ec6d723eb8", 1845e6, 85.04e6),  # k_synth_mfma<11, 1> (full batch)
+    ("ragged", "adjoint", "bf16"): ("kernels_code.hip", "41c438702764e40d", 2170e6, 1349e6),  # k_adjoint_shrink_mfma<11, true> (full batch)
+    ("ragged", "gather", "bf16"): ("kernels_code.hip", "41c438702764e40d", 9798e6, 184.7e6),  # k_gather_selected
+    ("ragged", "scatter", "bf16"): ("kernels_code.hip", "41c438702764e40d", 1920e6, 8765e6),  # k_scatter_dense
+    ("ragged", "synth", "fp32"): ("kernels_code.hip", "41c438702764e40d", 3462e6, 129.1e6),  # k_synth<11, true, 16, 8, 4>
+    ("ragged", "adjoint", "fp32"): ("kernels_code.hip", "41c438702764e40d", 2224e6, 1404e6),  # k_adjoint_shrink<11>
+    ("ragged", "gather", "fp32"): ("kernels_code.hip", "41c438702764e40d", 9798e6, 184.7e6),  # k_gather_selected
+    ("ragged", "scatter", "fp32"): ("kernels_code.hip", "41c438702764e40d", 1921e6, 8766e6),  # k_scatter_dense
 }
 
 

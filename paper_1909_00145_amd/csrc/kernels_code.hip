@@ -819,7 +819,13 @@ __global__ __launch_bounds__(TPB, PF ? 1 : 3) void k_adjoint_shrink_mfma(const I
 #pragma unroll
                 for (int ks = 0; ks < NKS; ++ks) afr[rt][ks] = dA8[(long long)(k0 + rt * 16) * (MP / 8) + ks * 4];
         }
-        __syncthreads();  // the previous chunk's epilogue is done with gc
+        // gc is wave-private: wave w writes G for the tile pixels 64w .. 64w + 63 (its
+        // four pixel rows) and only its own threads read them in the epilogue.  The LDS
+        // performs one wave's accesses in issue order, so a wavefront-scope fence (which
+        // keeps the compiler from moving them) replaces the workgroup barriers here, and
+        // the waves of a tile no longer wait for each other between chunks
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
 #pragma unroll
         for (int rt = 0; rt < 2; ++rt) {
             if (rt * 16 < nk) {  // (a guard, not a break: the loop stays unrolled)
@@ -835,7 +841,8 @@ __global__ __launch_bounds__(TPB, PF ? 1 : 3) void k_adjoint_shrink_mfma(const I
                 }
             }
         }
-        __syncthreads();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
         if (!c.valid) continue;
         const int k1 = k0 + nk;
         for (int w = k0 >> 5; w <= (k1 - 1) >> 5; ++w) {
